@@ -1,0 +1,6 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU path.
+
+This package holds input generation only (meshes, grids, fields, seeds);
+none of the transfer arithmetic lives here.
+"""
+from .gen import *  # noqa: F401,F403
