@@ -1,0 +1,248 @@
+/*
+ * ibvt — L2-projection transfer between a staggered rectilinear fluid grid
+ * and a P1 tetrahedral solid mesh, on AMD MI355X (gfx950).
+ *
+ * The operations are those of Section 2.3 of Nestola et al., "An immersed
+ * boundary method for fluid-structure interaction based on overlapping
+ * domain decomposition" (arXiv 1810.13046), paragraph "Variational Transfer:
+ * the L2-Projection Approach":
+ *
+ *   - the auxiliary Q1 space on the finite-difference grid (one node lattice
+ *     per velocity component of the staggered grid of Section 2.2);
+ *   - the mortar integrals  B_ij = ∫ N_f,j N_fsi,i dV  (solid rows i, fluid
+ *     columns j) and S_ij = ∫ N_s,j N_fsi,i dV, with the standard multiplier
+ *     space equal to the P1 solid space, so S is the P1 mass matrix of
+ *     Section 2.1 (consistent) or its row-sum lumping;
+ *   - velocity transfer  w_s = S^{-1} B v_f  (Step 1 of the FSI algorithm,
+ *     Section 3);
+ *   - force transfer with the transpose (Step 4 of Section 3).
+ *
+ * Conventions common to every call
+ *   - All field and mesh buffers are device memory owned by the caller.
+ *     Solid nodal fields are (3, n_vert) row-major (component-major).
+ *     Fluid fields are one array per component d, laid out (n_z, n_y, n_x)
+ *     with x fastest, over component d's lattice (see ibvt_lattice_coords).
+ *   - Fluid and solid fields are double for IBVT_FP64 couplings and float
+ *     for IBVT_FP32_MIXED couplings.  Coordinates X and the gradient g_X are
+ *     always double.
+ *   - Work is enqueued on `stream` in order.  Calls that size device
+ *     buffers (assembly) synchronize the stream once or twice to read
+ *     counts; transfers synchronize only for the consistent-mass solve's
+ *     convergence checks and when `info` is requested.
+ *   - Every call returns an ibvt status; nothing throws across the ABI.
+ *     ibvt_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef IBVT_H
+#define IBVT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define IBVT_OK 0
+#define IBVT_E_INVALID 1        /* null pointer, bad size or enum, non-finite
+                                   coordinate, non-increasing faces */
+#define IBVT_E_OUT_OF_GRID 2    /* a tet's bounding box leaves a velocity
+                                   lattice's node hull */
+#define IBVT_E_HIP 3            /* a HIP runtime call failed */
+#define IBVT_E_NOMEM 4          /* device allocation failed */
+#define IBVT_E_NOT_CONVERGED 5  /* CG reached maxit; results are written */
+#define IBVT_E_CAPACITY 6       /* an internal fixed capacity was exceeded
+                                   (clipped-piece vertices, vertex valence,
+                                   index range); the coupling is unusable */
+#define IBVT_E_UNSUPPORTED 7    /* valid but unsupported combination */
+
+/* Precision of a coupling. */
+#define IBVT_FP64 0             /* everything in double */
+#define IBVT_FP32_MIXED 1       /* double coordinates, plane distances and
+                                   cut points; float quadrature, float B
+                                   values and float transfers; CG with float
+                                   inner iterations and a double residual */
+
+/* Mass matrix used for S. */
+#define IBVT_LUMPED 0           /* S = diag(m), m_i = ∫ λ_i = Σ_{T∋i} |T|/4 */
+#define IBVT_CONSISTENT 1       /* S = M, M_il = ∫ λ_i λ_l, Jacobi-PCG solve */
+
+/* assemble_coupling flags. */
+#define IBVT_BUILD_CONSISTENT_M 1u  /* also build the consistent mass matrix */
+
+/* transfer_force flags. */
+#define IBVT_FORCE_IS_LOAD 1u   /* f_s is a load vector: apply S^{-1}
+                                   (consistent) before B^T, i.e. the literal
+                                   transpose of the velocity transfer
+                                   operator T = S^{-1} B */
+
+typedef struct ibvt_coupling ibvt_coupling;
+
+/* Rectilinear fluid grid: n_cells[e] cells along axis e, with n_cells[e]+1
+ * strictly increasing face coordinates faces[e] (HOST pointers, read during
+ * the call only).  Velocity component d lives on the faces normal to axis d
+ * and at face midpoints along the other two axes (staggered grid, Section
+ * 2.2), so its lattice has n_cells[d]+1 nodes along axis d and n_cells[e]
+ * along e != d. */
+typedef struct {
+  int32_t n_cells[3];
+  const double* faces[3];
+} ibvt_grid;
+
+/* P1 tetrahedral mesh in its current configuration (Section 2.1, the
+ * transfer uses the current configuration, Section 2.3).  X: device,
+ * (n_vert, 3) double, row-major.  tets: device, (n_tet, 4) int32 vertex
+ * indices, either orientation.  Both are read during the call (the
+ * coupling keeps its own copies). */
+typedef struct {
+  int64_t n_vert;
+  int64_t n_tet;
+  const double* X;
+  const int32_t* tets;
+} ibvt_mesh;
+
+/* Per-component outcome of a consistent-mass solve. */
+typedef struct {
+  int32_t iterations[3];
+  double rel_residual[3];   /* ||b - M x||_2 / ||b||_2, recomputed in double */
+} ibvt_solve_info;
+
+/* Counters of a coupling (coupling_info). */
+typedef struct {
+  int32_t precision;
+  int32_t has_consistent_mass;
+  int64_t n_vert, n_tet;
+  int64_t lattice[3][3];     /* nodes per axis e of component d: [d][e] */
+  int64_t n_fluid[3];        /* lattice nodes of component d */
+  int64_t pairs;             /* candidate (tet, component, cell) pairs */
+  int64_t pieces;            /* non-empty pieces kept (vol > 1e-14 |T|) */
+  int64_t dropped;           /* non-empty pieces with vol <= 1e-14 |T| */
+  int64_t zero_tets;         /* tets of zero volume (skipped) */
+  int64_t nnz[3];            /* nonzeros of B^d (and of B^dT) */
+  int64_t touched[3];        /* fluid nodes of component d with a nonzero
+                                column in B^d (rows of B^dT) */
+  int64_t nnz_mass;          /* nonzeros of the consistent mass matrix */
+  int64_t device_bytes;      /* device memory held by the coupling */
+  int64_t assemblies;        /* assemblies done on this handle */
+} ibvt_info;
+
+/*
+ * assemble_coupling — build B^d (d = 0, 1, 2) for the mesh and grid.
+ *   Section 2.3, assembly steps (I)-(IV): overlap detection (here: index
+ *   ranges on the rectilinear lattices instead of a tree search), exact
+ *   integration of λ_i N_j on every tet ∩ cell piece (axis-plane clipping
+ *   in double, then quadrature exact for the degree-4 integrand), and global
+ *   assembly.  Also builds B^dT (over the touched fluid nodes), the lumped
+ *   mass and, with IBVT_BUILD_CONSISTENT_M, the consistent mass matrix.
+ *   precision: IBVT_FP64 or IBVT_FP32_MIXED.
+ *   out: receives a new handle owned by the library (free with
+ *   coupling_free).  On failure *out is set to NULL.
+ *   Errors: IBVT_E_INVALID, IBVT_E_OUT_OF_GRID, IBVT_E_CAPACITY,
+ *   IBVT_E_NOMEM, IBVT_E_HIP.
+ */
+int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precision,
+                      uint32_t flags, hipStream_t stream, ibvt_coupling** out);
+
+/*
+ * reassemble_coupling — rebuild the same coupling for moved vertices X
+ * (same topology, same grid, same precision and flags): the transfer must
+ * follow the current configuration of the solid (Section 2.3), so a moving
+ * solid reassembles every step.  Reuses the handle's device buffers
+ * (grows them when needed).  X: device (n_vert, 3) double.
+ *   Errors: as assemble_coupling; on error the handle must be freed.
+ */
+int reassemble_coupling(ibvt_coupling* c, const double* X, hipStream_t stream);
+
+/*
+ * transfer_velocity — w_s = S^{-1} B v_f (Section 2.3; Step 1 of Section 3).
+ *   u_f[d]: component d's fluid values on its lattice (read).
+ *   u_s: (3, n_vert) output, overwritten.
+ *   mass: IBVT_LUMPED or IBVT_CONSISTENT (needs IBVT_BUILD_CONSISTENT_M).
+ *   cg_rtol, cg_maxit: stop when ||b - M x|| <= cg_rtol ||b|| per component
+ *   (ignored for IBVT_LUMPED).  info: nullable.
+ *   Errors: IBVT_E_INVALID, IBVT_E_NOT_CONVERGED (u_s holds the last
+ *   iterate), IBVT_E_HIP.
+ */
+int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int mass,
+                      double cg_rtol, int cg_maxit, hipStream_t stream, ibvt_solve_info* info);
+
+/*
+ * transfer_force — f_f[d] += alpha · B^dT f_s[d] at the touched fluid nodes
+ *   (force transfer with the transpose, Section 2.3; Step 4 of Section 3,
+ *   where alpha is the nondimensional scale L_ref / (rho_f U_ref^2)).
+ *   f_s: (3, n_vert), the P1 nodal coefficients of the force density (read).
+ *   With IBVT_FORCE_IS_LOAD f_s is a load vector and S^{-1} (consistent,
+ *   cg_rtol 1e-12 for FP64 couplings, 1e-6 for FP32 couplings) is applied
+ *   first.  f_f[d]: fluid arrays of component d, accumulated.
+ *   Errors: IBVT_E_INVALID, IBVT_E_NOT_CONVERGED, IBVT_E_HIP.
+ */
+int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double alpha,
+                   uint32_t flags, hipStream_t stream);
+
+/*
+ * transfer_velocity_vjp — reverse mode of u_s = S^{-1} B(X) u_f.
+ *   With z = S^{-1} g_us:
+ *     g_uf[d] += B^dT z_d                       (force-spreading transpose)
+ *     g_X     += Σ_d [ z_d^T (∂B^d/∂X) u_f,d − z_d^T (∂S/∂X) u_s,d ]
+ *   where ∂B_ij/∂X_{a,k} = Σ_{T∋a} ∫_T (λ_a λ_i ∂_k N_j + ∂_k λ_a λ_i N_j)
+ *   (the P1 hats move with the vertices, the Q1 hats stay on the grid) and
+ *   ∂|T|/∂X_a = |T| ∇λ_a for the mass.  The derivation is ours; the paper
+ *   defines only the forward operators.
+ *   g_us, u_s: (3, n_vert) (read); u_f: as in transfer_velocity (read).
+ *   g_uf: nullable array of 3 fluid arrays (accumulated); g_X: nullable
+ *   (n_vert, 3) double (accumulated).
+ *   Errors: IBVT_E_INVALID, IBVT_E_NOT_CONVERGED, IBVT_E_HIP.
+ */
+int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
+                          const void* u_s, int mass, double cg_rtol, int cg_maxit,
+                          void* const g_uf[3], double* g_X, hipStream_t stream);
+
+/*
+ * transfer_force_vjp — reverse mode of f_f = f_f0 + alpha · B(X)^T f_s
+ *   (flags 0 only):  g_fs += alpha · B g_ff,
+ *   g_X += alpha · Σ_d f_s,d^T (∂B^d/∂X) g_ff,d.
+ *   g_ff: 3 fluid arrays (read); f_s: (3, n_vert) (read); g_fs: nullable
+ *   (3, n_vert) (accumulated); g_X: nullable (n_vert, 3) double (accumulated).
+ *   Errors: IBVT_E_INVALID, IBVT_E_HIP.
+ */
+int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s,
+                       double alpha, void* g_fs, double* g_X, hipStream_t stream);
+
+/* coupling_info — fill *info (host).  Errors: IBVT_E_INVALID. */
+int coupling_info(const ibvt_coupling* c, ibvt_info* info);
+
+/*
+ * coupling_export_csr — copy B^d (transposed = 0: rows = solid vertices) or
+ *   B^dT (transposed = 1: rows = touched fluid nodes, row_map[r] = global
+ *   fluid index of row r) to HOST buffers, values as double.  Call first
+ *   with row_ptr = col = val = row_map = NULL to get *n_rows and *nnz; then
+ *   with buffers of n_rows+1, nnz, nnz and n_rows entries (row_map may stay
+ *   NULL).  Synchronizes the device.  Errors: IBVT_E_INVALID, IBVT_E_HIP.
+ */
+int coupling_export_csr(const ibvt_coupling* c, int comp, int transposed, int64_t* n_rows,
+                        int64_t* nnz, int32_t* row_ptr, int32_t* col, double* val,
+                        int32_t* row_map);
+
+/* coupling_free — release the handle and its device memory (synchronizes
+ * the device).  NULL is a no-op. */
+void coupling_free(ibvt_coupling* c);
+
+/* ibvt_status_string — static text for a status code. */
+const char* ibvt_status_string(int status);
+
+/* ibvt_last_error — thread-local detail message of the last failing call. */
+const char* ibvt_last_error(void);
+
+/*
+ * ibvt_lattice_coords — node coordinates of component comp's lattice along
+ *   axis (HOST output, n entries; pass out = NULL to get *n).  Component d
+ *   uses the face coordinates along axis d and the face midpoints elsewhere
+ *   (staggered grid, Section 2.2).  Errors: IBVT_E_INVALID.
+ */
+int ibvt_lattice_coords(const ibvt_grid* grid, int comp, int axis, double* out, int64_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBVT_H */

@@ -1,0 +1,398 @@
+// C-ABI entry points of libibvt (declared in include/ibvt.h).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace ibvt {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int set_error(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return IBVT_OK;
+  if (e == hipErrorOutOfMemory)
+    return set_error(IBVT_E_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
+  return set_error(IBVT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (b.p && b.cap >= bytes) return IBVT_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    c->device_bytes -= int64_t(b.cap);
+    b.p = nullptr;
+    b.cap = 0;
+    if (e != hipSuccess) return hip_check(e, "hipFree");
+  }
+  // grow with headroom so a moving mesh does not reallocate every step
+  const size_t want = bytes + bytes / 8 + 256;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return hip_check(e, "hipMalloc");
+  }
+  b.cap = want;
+  c->device_bytes += int64_t(want);
+  return IBVT_OK;
+}
+
+void release(ibvt_coupling* c, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    c->device_bytes -= int64_t(b.cap);
+  }
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+namespace {
+
+void release_csr(ibvt_coupling* c, Csr& m) {
+  release(c, m.rowptr);
+  release(c, m.col);
+  release(c, m.val);
+  release(c, m.rowmap);
+}
+
+void release_all(ibvt_coupling* c) {
+  DevBuf* bufs[] = {&c->lat, &c->X, &c->tets, &c->vt_ptr, &c->vt_tet, &c->tetvol, &c->rng,
+                    &c->cnt, &c->pair_off, &c->owner, &c->pval, &c->keep, &c->rownnz, &c->mark,
+                    &c->cidx, &c->tcount, &c->mlump, &c->minv, &c->Mval32, &c->Mdiag_inv,
+                    &c->flags_dev, &c->counters, &c->scan_tmp, &c->work, &c->work2, &c->zbuf};
+  for (DevBuf* b : bufs) release(c, *b);
+  for (int d = 0; d < 3; ++d) {
+    release_csr(c, c->B[d]);
+    release_csr(c, c->Bt[d]);
+  }
+  release_csr(c, c->M);
+}
+
+int validate_grid(const ibvt_grid* g) {
+  if (!g) return set_error(IBVT_E_INVALID, "grid is NULL");
+  for (int e = 0; e < 3; ++e) {
+    if (g->n_cells[e] < 2)
+      return set_error(IBVT_E_INVALID, "each axis needs at least 2 cells (cell-centre lattices)");
+    if (!g->faces[e]) return set_error(IBVT_E_INVALID, "grid faces pointer is NULL");
+    for (int k = 0; k <= g->n_cells[e]; ++k)
+      if (!std::isfinite(g->faces[e][k]))
+        return set_error(IBVT_E_INVALID, "non-finite face coordinate");
+    for (int k = 0; k < g->n_cells[e]; ++k)
+      if (!(g->faces[e][k + 1] > g->faces[e][k]))
+        return set_error(IBVT_E_INVALID, "face coordinates must be strictly increasing");
+  }
+  int64_t n = 1;
+  for (int e = 0; e < 3; ++e) n *= int64_t(g->n_cells[e]) + 1;
+  if (n >= (int64_t(1) << 31))
+    return set_error(IBVT_E_CAPACITY, "lattice has 2^31 nodes or more (int32 column indices)");
+  return IBVT_OK;
+}
+
+// Lattice of component d along axis e: faces along d, midpoints elsewhere.
+std::vector<double> lattice_axis(const ibvt_grid* g, int d, int e) {
+  std::vector<double> out;
+  const int n = g->n_cells[e];
+  if (e == d) {
+    out.assign(g->faces[e], g->faces[e] + n + 1);
+  } else {
+    out.resize(n);
+    for (int k = 0; k < n; ++k) out[k] = 0.5 * (g->faces[e][k] + g->faces[e][k + 1]);
+  }
+  return out;
+}
+
+int setup_lattices(ibvt_coupling* c, const ibvt_grid* g, hipStream_t s) {
+  int32_t off = 0;
+  for (int d = 0; d < 3; ++d) {
+    int64_t nf = 1;
+    for (int e = 0; e < 3; ++e) {
+      c->lat_host[3 * d + e] = lattice_axis(g, d, e);
+      c->ld.off[3 * d + e] = off;
+      c->ld.n[3 * d + e] = int32_t(c->lat_host[3 * d + e].size());
+      off += c->ld.n[3 * d + e];
+      nf *= c->ld.n[3 * d + e];
+    }
+    c->n_fluid[d] = nf;
+  }
+  int st = ensure(c, c->lat, size_t(off) * sizeof(double));
+  if (st) return st;
+  std::vector<double> flat;
+  flat.reserve(off);
+  for (int k = 0; k < 9; ++k) flat.insert(flat.end(), c->lat_host[k].begin(), c->lat_host[k].end());
+  st = hip_check(hipMemcpyAsync(c->lat.p, flat.data(), flat.size() * sizeof(double),
+                                hipMemcpyHostToDevice, s),
+                 "lattice copy");
+  if (st) return st;
+  return hip_check(hipStreamSynchronize(s), "lattice sync");
+}
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+}  // namespace
+}  // namespace ibvt
+
+using namespace ibvt;
+
+extern "C" {
+
+const char* ibvt_status_string(int status) {
+  switch (status) {
+    case IBVT_OK: return "ok";
+    case IBVT_E_INVALID: return "invalid argument";
+    case IBVT_E_OUT_OF_GRID: return "solid outside the fluid lattice";
+    case IBVT_E_HIP: return "HIP runtime error";
+    case IBVT_E_NOMEM: return "out of device memory";
+    case IBVT_E_NOT_CONVERGED: return "CG did not converge";
+    case IBVT_E_CAPACITY: return "internal capacity exceeded";
+    case IBVT_E_UNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+  }
+}
+
+const char* ibvt_last_error(void) { return g_last_error.c_str(); }
+
+int ibvt_lattice_coords(const ibvt_grid* grid, int comp, int axis, double* out, int64_t* n) {
+  int st = validate_grid(grid);
+  if (st) return st;
+  if (comp < 0 || comp > 2 || axis < 0 || axis > 2 || !n)
+    return set_error(IBVT_E_INVALID, "bad comp/axis or NULL n");
+  std::vector<double> v = lattice_axis(grid, comp, axis);
+  *n = int64_t(v.size());
+  if (out) std::memcpy(out, v.data(), v.size() * sizeof(double));
+  return IBVT_OK;
+}
+
+int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precision,
+                      uint32_t flags, hipStream_t stream, ibvt_coupling** out) {
+  if (!out) return set_error(IBVT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int st = validate_grid(grid);
+  if (st) return st;
+  if (!mesh) return set_error(IBVT_E_INVALID, "mesh is NULL");
+  if (mesh->n_vert < 1 || mesh->n_tet < 0)
+    return set_error(IBVT_E_INVALID, "mesh needs n_vert >= 1 and n_tet >= 0");
+  if (mesh->n_vert >= (int64_t(1) << 31) || mesh->n_tet >= (int64_t(1) << 31) / 3)
+    return set_error(IBVT_E_CAPACITY, "mesh too large for int32 indices");
+  if (bad_ptr(mesh->X) || (mesh->n_tet > 0 && bad_ptr(mesh->tets)))
+    return set_error(IBVT_E_INVALID, "mesh X or tets is NULL");
+  if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
+    return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
+  if (flags & ~IBVT_BUILD_CONSISTENT_M) return set_error(IBVT_E_INVALID, "unknown flags");
+  ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
+  if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
+  c->precision = precision;
+  c->flags = flags;
+  c->n_vert = mesh->n_vert;
+  c->n_tet = mesh->n_tet;
+  c->has_M = (flags & IBVT_BUILD_CONSISTENT_M) != 0;
+  for (int e = 0; e < 3; ++e) c->n_cells[e] = grid->n_cells[e];
+  st = setup_lattices(c, grid, stream);
+  if (!st) st = ensure(c, c->X, size_t(3 * c->n_vert) * sizeof(double));
+  if (!st) st = ensure(c, c->tets, size_t(4 * c->n_tet + 4) * sizeof(int32_t));
+  if (!st)
+    st = hip_check(hipMemcpyAsync(c->X.p, mesh->X, size_t(3 * c->n_vert) * sizeof(double),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "copy X");
+  if (!st && c->n_tet > 0)
+    st = hip_check(hipMemcpyAsync(c->tets.p, mesh->tets, size_t(4 * c->n_tet) * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "copy tets");
+  if (!st) st = build_topology(c, stream);
+  if (!st) st = assemble_all(c, stream);
+  if (st) {
+    std::string keep_msg = g_last_error;
+    (void)hipStreamSynchronize(stream);
+    release_all(c);
+    delete c;
+    g_last_error = keep_msg;
+    return st;
+  }
+  *out = c;
+  return IBVT_OK;
+}
+
+int reassemble_coupling(ibvt_coupling* c, const double* X, hipStream_t stream) {
+  if (!c || !X) return set_error(IBVT_E_INVALID, "NULL coupling or X");
+  int st = hip_check(hipMemcpyAsync(c->X.p, X, size_t(3 * c->n_vert) * sizeof(double),
+                                    hipMemcpyDeviceToDevice, stream),
+                     "copy X");
+  if (st) return st;
+  return assemble_all(c, stream);
+}
+
+int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int mass,
+                      double cg_rtol, int cg_maxit, hipStream_t stream, ibvt_solve_info* info) {
+  if (!c || !u_f || !u_s) return set_error(IBVT_E_INVALID, "NULL argument");
+  for (int d = 0; d < 3; ++d)
+    if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
+  if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
+    return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (mass == IBVT_LUMPED) return apply_B(c, u_f, u_s, true, stream);
+  if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
+  if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad CG rtol/maxit");
+  // rhs = B u_f into the scratch, start from the lumped solution in u_s
+  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+  int st = ensure(c, c->work2, size_t(3 * c->n_vert) * tsize);
+  if (st) return st;
+  if ((st = apply_B(c, u_f, c->work2.p, false, stream))) return st;
+  if ((st = lumped_solve(c, c->work2.p, u_s, stream))) return st;
+  return mass_solve(c, c->work2.p, u_s, cg_rtol, cg_maxit, stream, info, true);
+}
+
+int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double alpha,
+                   uint32_t flags, hipStream_t stream) {
+  if (!c || !f_s || !f_f) return set_error(IBVT_E_INVALID, "NULL argument");
+  for (int d = 0; d < 3; ++d)
+    if (!f_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
+  if (flags & ~IBVT_FORCE_IS_LOAD) return set_error(IBVT_E_INVALID, "unknown flags");
+  if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
+  if (flags & IBVT_FORCE_IS_LOAD) {
+    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
+    const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+    int st = ensure(c, c->work2, size_t(3 * c->n_vert) * tsize);
+    if (st) return st;
+    const double rtol = c->precision == IBVT_FP32_MIXED ? 1e-6 : 1e-12;
+    if ((st = mass_solve(c, f_s, c->work2.p, rtol, 500, stream, nullptr, false))) return st;
+    return apply_Bt(c, c->work2.p, f_f, alpha, stream);
+  }
+  return apply_Bt(c, f_s, f_f, alpha, stream);
+}
+
+int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
+                          const void* u_s, int mass, double cg_rtol, int cg_maxit,
+                          void* const g_uf[3], double* g_X, hipStream_t stream) {
+  if (!c || !g_us) return set_error(IBVT_E_INVALID, "NULL argument");
+  if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
+    return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
+  if (g_X && (!u_f || !u_s)) return set_error(IBVT_E_INVALID, "g_X needs u_f and u_s");
+  if (g_X)
+    for (int d = 0; d < 3; ++d)
+      if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
+  if (g_uf)
+    for (int d = 0; d < 3; ++d)
+      if (!g_uf[d]) return set_error(IBVT_E_INVALID, "NULL g_uf component");
+  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+  // z = S^{-1} g_us lives in its own buffer (the shape kernel reuses work2)
+  int st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize);
+  if (st) return st;
+  void* z = c->zbuf.p;
+  if (mass == IBVT_LUMPED) {
+    if ((st = lumped_solve(c, g_us, z, stream))) return st;
+  } else {
+    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
+    if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad CG rtol/maxit");
+    if ((st = mass_solve(c, g_us, z, cg_rtol, cg_maxit, stream, nullptr, false))) return st;
+  }
+  if (g_uf && (st = apply_Bt(c, z, g_uf, 1.0, stream))) return st;
+  if (g_X && (st = shape_gradient(c, z, u_f, u_s, mass == IBVT_CONSISTENT ? 1 : 0, 1.0, g_X, stream)))
+    return st;
+  return IBVT_OK;
+}
+
+int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s,
+                       double alpha, void* g_fs, double* g_X, hipStream_t stream) {
+  if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
+  for (int d = 0; d < 3; ++d)
+    if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
+  if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
+  if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
+  int st;
+  if (g_fs) {
+    // g_fs += alpha B g_ff: B into scratch, then accumulate
+    const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+    if ((st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize))) return st;
+    if ((st = apply_B(c, g_ff, c->zbuf.p, false, stream))) return st;
+    if ((st = axpy_solid(c, alpha, c->zbuf.p, g_fs, stream))) return st;
+  }
+  if (g_X && (st = shape_gradient(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream))) return st;
+  return IBVT_OK;
+}
+
+int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
+  if (!c || !info) return set_error(IBVT_E_INVALID, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->precision = c->precision;
+  info->has_consistent_mass = c->has_M ? 1 : 0;
+  info->n_vert = c->n_vert;
+  info->n_tet = c->n_tet;
+  for (int d = 0; d < 3; ++d) {
+    for (int e = 0; e < 3; ++e) info->lattice[d][e] = c->ld.n[3 * d + e];
+    info->n_fluid[d] = c->n_fluid[d];
+    info->nnz[d] = c->B[d].nnz;
+    info->touched[d] = c->Bt[d].nrows;
+  }
+  info->pairs = c->stats.pairs;
+  info->pieces = c->stats.pieces;
+  info->dropped = c->stats.dropped;
+  info->zero_tets = c->stats.zero_tets;
+  info->nnz_mass = c->has_M ? c->M.nnz : 0;
+  info->device_bytes = c->device_bytes;
+  info->assemblies = c->stats.assemblies;
+  return IBVT_OK;
+}
+
+int coupling_export_csr(const ibvt_coupling* c, int comp, int transposed, int64_t* n_rows,
+                        int64_t* nnz, int32_t* row_ptr, int32_t* col, double* val,
+                        int32_t* row_map) {
+  if (!c || comp < 0 || comp > 2 || !n_rows || !nnz)
+    return set_error(IBVT_E_INVALID, "bad argument");
+  const Csr& m = transposed ? c->Bt[comp] : c->B[comp];
+  *n_rows = m.nrows;
+  *nnz = m.nnz;
+  if (!row_ptr && !col && !val && !row_map) return IBVT_OK;
+  int st = hip_check(hipDeviceSynchronize(), "sync");
+  if (st) return st;
+  if (row_ptr) {
+    std::vector<int64_t> rp(size_t(m.nrows + 1));
+    if ((st = hip_check(hipMemcpy(rp.data(), m.rowptr.p, rp.size() * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost),
+                        "copy")))
+      return st;
+    if (m.nnz >= (int64_t(1) << 31)) return set_error(IBVT_E_CAPACITY, "nnz exceeds int32");
+    for (size_t k = 0; k < rp.size(); ++k) row_ptr[k] = int32_t(rp[k]);
+  }
+  if (col && m.nnz)
+    if ((st = hip_check(hipMemcpy(col, m.col.p, size_t(m.nnz) * sizeof(int32_t), hipMemcpyDeviceToHost),
+                        "copy")))
+      return st;
+  if (val && m.nnz) {
+    if (c->precision == IBVT_FP32_MIXED) {
+      std::vector<float> v(size_t(m.nnz));
+      if ((st = hip_check(hipMemcpy(v.data(), m.val.p, v.size() * sizeof(float), hipMemcpyDeviceToHost),
+                          "copy")))
+        return st;
+      for (size_t k = 0; k < v.size(); ++k) val[k] = double(v[k]);
+    } else if ((st = hip_check(hipMemcpy(val, m.val.p, size_t(m.nnz) * sizeof(double),
+                                         hipMemcpyDeviceToHost),
+                               "copy"))) {
+      return st;
+    }
+  }
+  if (row_map && transposed && m.nrows)
+    if ((st = hip_check(hipMemcpy(row_map, m.rowmap.p, size_t(m.nrows) * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost),
+                        "copy")))
+      return st;
+  return IBVT_OK;
+}
+
+void coupling_free(ibvt_coupling* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  release_all(c);
+  delete c;
+}
+
+}  // extern "C"

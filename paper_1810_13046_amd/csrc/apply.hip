@@ -1,0 +1,592 @@
+// Transfer applies (Section 2.3): velocity  w_s = S^{-1} B v_f  and force
+// f_f += alpha B^T f_s, plus the consistent-mass solve.
+//
+// SpMV: CSR with a group of G lanes per row (rows of B hold a few tens of
+// entries); the group strides through the row so each wave reads
+// contiguous runs of values and column indices, reduces with lane shuffles
+// and writes one result per row.  The three velocity components run in one
+// launch (grid.y).  B^T rows are the touched fluid nodes; their results are
+// scattered to the caller's full fluid arrays through the row map (each
+// fluid node appears once, so no atomics).
+//
+// Consistent mass: Jacobi-preconditioned CG on M for the three components
+// at once (one pass over M serves all three right-hand sides), with
+// per-component scalars and stopping tests.  Reductions are two-stage
+// (per-block partials, then one block in fixed order), so results do not
+// depend on timing.  In the mixed-precision path an outer loop recomputes
+// the residual b - M x in double with double M values and solves the
+// correction with a float CG (iterative refinement).
+#include "internal.hpp"
+
+#include <cmath>
+
+namespace ibvt {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+struct SpmvArgs {
+  const int64_t* rowptr[3];
+  const int32_t* col[3];
+  const T* val[3];
+  int64_t nrows[3];
+  const T* x[3];
+  T* y[3];
+  const int32_t* rowmap[3];
+  const T* scale;   // per-row factor (lumped inverse mass) or null
+  T alpha;
+  int accumulate;
+};
+
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs<T> a) {
+  const int d = blockIdx.y;
+  const int64_t row = int64_t(blockIdx.x) * (kThreads / G) + threadIdx.x / G;
+  const int g = threadIdx.x % G;
+  T s = T(0);
+  const bool active = row < a.nrows[d];
+  if (active) {
+    const int64_t b = a.rowptr[d][row], e = a.rowptr[d][row + 1];
+    const int32_t* __restrict__ col = a.col[d];
+    const T* __restrict__ val = a.val[d];
+    const T* __restrict__ x = a.x[d];
+    for (int64_t k = b + g; k < e; k += G) s += val[k] * x[col[k]];
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+  if (active && g == 0) {
+    T v = a.alpha * s;
+    if (a.scale) v *= a.scale[row];
+    const int64_t dst = a.rowmap[d] ? int64_t(a.rowmap[d][row]) : row;
+    if (a.accumulate) a.y[d][dst] += v;
+    else a.y[d][dst] = v;
+  }
+}
+
+template <typename T, int G>
+int launch_spmv(const SpmvArgs<T>& a, hipStream_t s) {
+  int64_t mx = std::max(a.nrows[0], std::max(a.nrows[1], a.nrows[2]));
+  if (mx <= 0) return IBVT_OK;
+  dim3 grid(unsigned(ceil_div(mx, kThreads / G)), 3);
+  k_spmv<T, G><<<grid, kThreads, 0, s>>>(a);
+  return hip_check(hipGetLastError(), "spmv launch");
+}
+
+// ---------------------------------------------------------------------------
+// consistent-mass CG
+// ---------------------------------------------------------------------------
+
+struct CgScalars {
+  double rz[3], bb[3], rr[3], pq[3];
+  double alpha[3], beta[3];
+  int conv[3];
+  int iters[3];
+  int all;
+};
+
+// q = M p for the three components (values V, vectors T), plus per-block
+// partials of p·q.
+template <typename T, typename V>
+__global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const V* __restrict__ val,
+                                                       const T* __restrict__ p, T* __restrict__ q,
+                                                       double* __restrict__ part,
+                                                       const CgScalars* sc) {
+  __shared__ double red[3][kThreads / kWave];
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  double loc[3] = {0, 0, 0};
+  if (!sc || !sc->all) {
+    if (i < n) {
+      T s0 = 0, s1 = 0, s2 = 0;
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int64_t j = col[k];
+        const T m = T(val[k]);
+        s0 += m * p[j];
+        s1 += m * p[n + j];
+        s2 += m * p[2 * n + j];
+      }
+      q[i] = s0;
+      q[n + i] = s1;
+      q[2 * n + i] = s2;
+      loc[0] = double(p[i]) * double(s0);
+      loc[1] = double(p[n + i]) * double(s1);
+      loc[2] = double(p[2 * n + i]) * double(s2);
+    }
+  }
+  if (!part) return;
+  for (int d = 0; d < 3; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
+    part[int64_t(blockIdx.x) * 3 + threadIdx.x] = t;
+  }
+}
+
+// Sum per-block partials (nb x 3) in fixed order into out[0..2].
+__global__ __launch_bounds__(kThreads) void k_reduce3(const double* __restrict__ part, int64_t nb,
+                                                     double* __restrict__ out) {
+  __shared__ double red[3][kThreads / kWave];
+  double loc[3] = {0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nb; b += kThreads)
+    for (int d = 0; d < 3; ++d) loc[d] += part[b * 3 + d];
+  for (int d = 0; d < 3; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
+    out[threadIdx.x] = t;
+  }
+}
+
+// Elementwise steps with block partials of up to two dot products.
+//  mode 0 (init):  r = b - q; z = Dinv r; p = z;  partials (r·z, b·b)
+//  mode 1 (update): x += α p; r -= α q; z = Dinv r; partials (r·z, r·r)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_vec(int mode, int64_t n, const T* __restrict__ b,
+                                                    const T* __restrict__ q, T* __restrict__ x,
+                                                    T* __restrict__ r, T* __restrict__ z,
+                                                    T* __restrict__ p, const double* __restrict__ dinv,
+                                                    double* __restrict__ part, const CgScalars* sc) {
+  __shared__ double red[6][kThreads / kWave];
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  double loc[6] = {0, 0, 0, 0, 0, 0};
+  if (i < n && !(mode == 1 && sc->all)) {
+    const double di = dinv[i];
+    for (int d = 0; d < 3; ++d) {
+      const int64_t k = int64_t(d) * n + i;
+      if (mode == 0) {
+        const T rv = b[k] - q[k];
+        const T zv = T(di * double(rv));
+        r[k] = rv;
+        z[k] = zv;
+        p[k] = zv;
+        loc[d] = double(rv) * double(zv);
+        loc[3 + d] = double(b[k]) * double(b[k]);
+      } else {
+        if (sc->conv[d]) continue;
+        const T al = T(sc->alpha[d]);
+        x[k] += al * p[k];
+        const T rv = r[k] - al * q[k];
+        const T zv = T(di * double(rv));
+        r[k] = rv;
+        z[k] = zv;
+        loc[d] = double(rv) * double(zv);
+        loc[3 + d] = double(rv) * double(rv);
+      }
+    }
+  }
+  for (int d = 0; d < 6; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
+    part[int64_t(blockIdx.x) * 6 + threadIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce6(const double* __restrict__ part, int64_t nb,
+                                                     double* __restrict__ out) {
+  __shared__ double red[6][kThreads / kWave];
+  double loc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nb; b += kThreads)
+    for (int d = 0; d < 6; ++d) loc[d] += part[b * 6 + d];
+  for (int d = 0; d < 6; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
+    out[threadIdx.x] = t;
+  }
+}
+
+// Scalar steps (one thread).
+//  step 0: after init reduce (rz, bb) in tmp[0..5]
+//  step 1: after pq reduce in tmp[0..2]: alpha
+//  step 2: after update reduce (rz_new, rr) in tmp[0..5]: beta, convergence
+__global__ void k_cg_scalar(int step, CgScalars* sc, const double* __restrict__ tmp, double rtol2) {
+  if (threadIdx.x != 0) return;
+  if (step == 0) {
+    sc->all = 1;
+    for (int d = 0; d < 3; ++d) {
+      sc->rz[d] = tmp[d];
+      sc->bb[d] = tmp[3 + d];
+      sc->rr[d] = 0;
+      sc->iters[d] = 0;
+      // stop when the preconditioned start already meets the tolerance is
+      // decided after the first true residual norm: use r·z > 0 as "work left"
+      sc->conv[d] = (sc->bb[d] == 0.0) ? 1 : 0;
+      if (!sc->conv[d]) sc->all = 0;
+    }
+  } else if (step == 1) {
+    for (int d = 0; d < 3; ++d) {
+      sc->pq[d] = tmp[d];
+      sc->alpha[d] = (!sc->conv[d] && tmp[d] != 0.0) ? sc->rz[d] / tmp[d] : 0.0;
+    }
+  } else {
+    sc->all = 1;
+    for (int d = 0; d < 3; ++d) {
+      if (sc->conv[d]) continue;
+      const double rzn = tmp[d];
+      sc->rr[d] = tmp[3 + d];
+      sc->beta[d] = (sc->rz[d] != 0.0) ? rzn / sc->rz[d] : 0.0;
+      sc->rz[d] = rzn;
+      sc->iters[d] += 1;
+      if (sc->rr[d] <= rtol2 * sc->bb[d]) sc->conv[d] = 1;
+      else sc->all = 0;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_p(int64_t n, const T* __restrict__ z,
+                                                  T* __restrict__ p, const CgScalars* sc) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= n || sc->all) return;
+  for (int d = 0; d < 3; ++d) {
+    if (sc->conv[d]) continue;
+    const int64_t k = int64_t(d) * n + i;
+    p[k] = z[k] + T(sc->beta[d]) * p[k];
+  }
+}
+
+// residual in double: res = b - M x  (b, x of type T; M double)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_residual64(int64_t n, const int64_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const T* __restrict__ b,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ res,
+                                                        double* __restrict__ part) {
+  __shared__ double red[6][kThreads / kWave];
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  double loc[6] = {0, 0, 0, 0, 0, 0};
+  if (i < n) {
+    double s[3] = {0, 0, 0};
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int64_t j = col[k];
+      for (int d = 0; d < 3; ++d) s[d] += val[k] * x[int64_t(d) * n + j];
+    }
+    for (int d = 0; d < 3; ++d) {
+      const double bv = double(b[int64_t(d) * n + i]);
+      const double rv = bv - s[d];
+      res[int64_t(d) * n + i] = rv;
+      loc[d] = rv * rv;
+      loc[3 + d] = bv * bv;
+    }
+  }
+  for (int d = 0; d < 6; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
+    part[int64_t(blockIdx.x) * 6 + threadIdx.x] = t;
+  }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(int64_t n, const Tin* __restrict__ a, Tout* __restrict__ b) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) b[i] = Tout(a[i]);
+}
+
+template <typename T>
+__global__ void k_lumped_apply(int64_t n, const T* __restrict__ rhs, const T* __restrict__ minv,
+                               T* __restrict__ x) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n)
+    for (int d = 0; d < 3; ++d) x[int64_t(d) * n + i] = rhs[int64_t(d) * n + i] * minv[i];
+}
+
+template <typename T>
+__global__ void k_axpy(int64_t n, T alpha, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) y[i] += alpha * x[i];
+}
+
+__global__ void k_add_correction(int64_t n3, const float* __restrict__ e, double* __restrict__ x) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n3) x[i] += double(e[i]);
+}
+
+inline unsigned nblk(int64_t n) { return unsigned(ceil_div(n > 0 ? n : 1, kThreads)); }
+
+// Workspace layout for the CG (bytes): scalars, partials, 6 vectors of T
+// (b copy not needed: rhs is read), plus double x/res for refinement.
+struct CgWork {
+  CgScalars* sc;
+  double* part;
+  double* tmp;
+  void* vec;
+  double* x64;
+  double* res64;
+};
+
+int cg_workspace(ibvt_coupling* c, size_t tsize, CgWork& w) {
+  const int64_t n = c->n_vert;
+  const int64_t nb = nblk(n);
+  const size_t off_part = 256;
+  const size_t off_tmp = off_part + size_t(nb) * 6 * sizeof(double);
+  const size_t off_vec = (off_tmp + 16 * sizeof(double) + 255) & ~size_t(255);
+  const size_t off_x64 = (off_vec + size_t(6 * 3 * n) * tsize + 255) & ~size_t(255);
+  const size_t off_res = (off_x64 + size_t(3 * n) * sizeof(double) + 255) & ~size_t(255);
+  const size_t total = off_res + size_t(3 * n) * sizeof(double) + 256;
+  int st = ensure(c, c->work, total);
+  if (st) return st;
+  char* base = c->work.as<char>();
+  w.sc = reinterpret_cast<CgScalars*>(base);
+  w.part = reinterpret_cast<double*>(base + off_part);
+  w.tmp = reinterpret_cast<double*>(base + off_tmp);
+  w.vec = base + off_vec;
+  w.x64 = reinterpret_cast<double*>(base + off_x64);
+  w.res64 = reinterpret_cast<double*>(base + off_res);
+  return IBVT_OK;
+}
+
+// Plain CG on M (values V) for three right-hand sides b (type T), x in/out.
+// Returns iterations in info-like arrays through the scalars; checks
+// convergence on the host every `check` iterations.
+template <typename T, typename V>
+int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int maxit,
+            const CgWork& w, hipStream_t s, int* iters_out, bool* converged) {
+  const int64_t n = c->n_vert;
+  const unsigned nb = nblk(n);
+  T* q = static_cast<T*>(w.vec);
+  T* r = q + 3 * n;
+  T* z = r + 3 * n;
+  T* p = z + 3 * n;
+  const int64_t* rp = c->M.rowptr.as<int64_t>();
+  const int32_t* col = c->M.col.as<int32_t>();
+  const double* dinv = c->Mdiag_inv.as<double>();
+  const double rtol2 = rtol * rtol;
+  // q = M x ; r = b - q ; z = D^-1 r ; p = z
+  k_mass_spmv<T, V><<<nb, kThreads, 0, s>>>(n, rp, col, mval, x, q, nullptr, nullptr);
+  k_cg_vec<T><<<nb, kThreads, 0, s>>>(0, n, b, q, x, r, z, p, dinv, w.part, w.sc);
+  k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
+  k_cg_scalar<<<1, 64, 0, s>>>(0, w.sc, w.tmp, rtol2);
+  int st = hip_check(hipGetLastError(), "cg init launch");
+  if (st) return st;
+  const int check = 8;
+  int it = 0;
+  CgScalars host{};
+  *converged = false;
+  while (it < maxit) {
+    const int chunk = std::min(check, maxit - it);
+    for (int k = 0; k < chunk; ++k) {
+      k_mass_spmv<T, V><<<nb, kThreads, 0, s>>>(n, rp, col, mval, p, q, w.part, w.sc);
+      k_reduce3<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
+      k_cg_scalar<<<1, 64, 0, s>>>(1, w.sc, w.tmp, rtol2);
+      k_cg_vec<T><<<nb, kThreads, 0, s>>>(1, n, b, q, x, r, z, p, dinv, w.part, w.sc);
+      k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
+      k_cg_scalar<<<1, 64, 0, s>>>(2, w.sc, w.tmp, rtol2);
+      k_cg_p<T><<<nb, kThreads, 0, s>>>(n, z, p, w.sc);
+    }
+    it += chunk;
+    if ((st = hip_check(hipGetLastError(), "cg launch"))) return st;
+    if ((st = hip_check(hipMemcpyAsync(&host, w.sc, sizeof(host), hipMemcpyDeviceToHost, s),
+                        "cg read")))
+      return st;
+    if ((st = hip_check(hipStreamSynchronize(s), "cg sync"))) return st;
+    if (host.all) {
+      *converged = true;
+      break;
+    }
+  }
+  if (it == 0) {
+    if ((st = hip_check(hipMemcpyAsync(&host, w.sc, sizeof(host), hipMemcpyDeviceToHost, s),
+                        "cg read")))
+      return st;
+    if ((st = hip_check(hipStreamSynchronize(s), "cg sync"))) return st;
+    *converged = host.all != 0;
+  }
+  for (int d = 0; d < 3; ++d) iters_out[d] += host.iters[d];
+  return IBVT_OK;
+}
+
+// True residual norms ||b - M x|| / ||b|| in double (x as double).
+template <typename T>
+int true_residual(ibvt_coupling* c, const T* b, const double* x, const CgWork& w, hipStream_t s,
+                  double rel[3]) {
+  const int64_t n = c->n_vert;
+  const unsigned nb = nblk(n);
+  k_residual64<T><<<nb, kThreads, 0, s>>>(n, c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>(),
+                                          c->M.val.as<double>(), b, x, w.res64, w.part);
+  k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
+  double h[6];
+  int st = hip_check(hipMemcpyAsync(h, w.tmp, sizeof(h), hipMemcpyDeviceToHost, s), "res read");
+  if (st) return st;
+  if ((st = hip_check(hipStreamSynchronize(s), "res sync"))) return st;
+  for (int d = 0; d < 3; ++d) rel[d] = (h[3 + d] > 0) ? std::sqrt(h[d] / h[3 + d]) : 0.0;
+  return IBVT_OK;
+}
+
+}  // namespace
+
+int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s) {
+  const int64_t n = c->n_vert;
+  if (c->precision == IBVT_FP32_MIXED) {
+    SpmvArgs<float> a{};
+    for (int d = 0; d < 3; ++d) {
+      a.rowptr[d] = c->B[d].rowptr.as<int64_t>();
+      a.col[d] = c->B[d].col.as<int32_t>();
+      a.val[d] = c->B[d].val.as<float>();
+      a.nrows[d] = n;
+      a.x[d] = static_cast<const float*>(x[d]);
+      a.y[d] = static_cast<float*>(y) + d * n;
+    }
+    a.scale = lumped_scale ? c->minv.as<float>() : nullptr;
+    a.alpha = 1.0f;
+    return launch_spmv<float, 16>(a, s);
+  }
+  SpmvArgs<double> a{};
+  for (int d = 0; d < 3; ++d) {
+    a.rowptr[d] = c->B[d].rowptr.as<int64_t>();
+    a.col[d] = c->B[d].col.as<int32_t>();
+    a.val[d] = c->B[d].val.as<double>();
+    a.nrows[d] = n;
+    a.x[d] = static_cast<const double*>(x[d]);
+    a.y[d] = static_cast<double*>(y) + d * n;
+  }
+  a.scale = lumped_scale ? c->minv.as<double>() : nullptr;
+  a.alpha = 1.0;
+  return launch_spmv<double, 16>(a, s);
+}
+
+// out[d][rowmap[r]] += alpha * (B^dT ys_d)[r]
+int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha, hipStream_t s) {
+  const int64_t n = c->n_vert;
+  if (c->precision == IBVT_FP32_MIXED) {
+    SpmvArgs<float> a{};
+    for (int d = 0; d < 3; ++d) {
+      a.rowptr[d] = c->Bt[d].rowptr.as<int64_t>();
+      a.col[d] = c->Bt[d].col.as<int32_t>();
+      a.val[d] = c->Bt[d].val.as<float>();
+      a.nrows[d] = c->Bt[d].nrows;
+      a.x[d] = static_cast<const float*>(ys) + d * n;
+      a.y[d] = static_cast<float*>(out[d]);
+      a.rowmap[d] = c->Bt[d].rowmap.as<int32_t>();
+    }
+    a.alpha = float(alpha);
+    a.accumulate = 1;
+    return launch_spmv<float, 16>(a, s);
+  }
+  SpmvArgs<double> a{};
+  for (int d = 0; d < 3; ++d) {
+    a.rowptr[d] = c->Bt[d].rowptr.as<int64_t>();
+    a.col[d] = c->Bt[d].col.as<int32_t>();
+    a.val[d] = c->Bt[d].val.as<double>();
+    a.nrows[d] = c->Bt[d].nrows;
+    a.x[d] = static_cast<const double*>(ys) + d * n;
+    a.y[d] = static_cast<double*>(out[d]);
+    a.rowmap[d] = c->Bt[d].rowmap.as<int32_t>();
+  }
+  a.alpha = alpha;
+  a.accumulate = 1;
+  return launch_spmv<double, 16>(a, s);
+}
+
+int lumped_solve(ibvt_coupling* c, const void* rhs, void* x, hipStream_t s) {
+  const int64_t n = c->n_vert;
+  if (c->precision == IBVT_FP32_MIXED)
+    k_lumped_apply<float><<<nblk(n), kThreads, 0, s>>>(n, static_cast<const float*>(rhs),
+                                                       c->minv.as<float>(), static_cast<float*>(x));
+  else
+    k_lumped_apply<double><<<nblk(n), kThreads, 0, s>>>(n, static_cast<const double*>(rhs),
+                                                        c->minv.as<double>(),
+                                                        static_cast<double*>(x));
+  return hip_check(hipGetLastError(), "lumped launch");
+}
+
+int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream_t s) {
+  const int64_t n3 = 3 * c->n_vert;
+  if (c->precision == IBVT_FP32_MIXED)
+    k_axpy<float><<<nblk(n3), kThreads, 0, s>>>(n3, float(alpha), static_cast<const float*>(x),
+                                                static_cast<float*>(y));
+  else
+    k_axpy<double><<<nblk(n3), kThreads, 0, s>>>(n3, alpha, static_cast<const double*>(x),
+                                                 static_cast<double*>(y));
+  return hip_check(hipGetLastError(), "axpy launch");
+}
+
+// x = M^{-1} rhs (three components).  x holds the start (lumped solution)
+// when x_has_guess.
+int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxit, hipStream_t s,
+               ibvt_solve_info* info, bool x_has_guess) {
+  if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built (flags)");
+  const int64_t n = c->n_vert;
+  int st;
+  if (!x_has_guess && (st = lumped_solve(c, rhs, x, s))) return st;
+  int iters[3] = {0, 0, 0};
+  bool conv = false;
+  double rel[3] = {0, 0, 0};
+  if (c->precision == IBVT_FP64) {
+    CgWork w;
+    if ((st = cg_workspace(c, sizeof(double), w))) return st;
+    if ((st = cg_core<double, double>(c, c->M.val.as<double>(), static_cast<const double*>(rhs),
+                                      static_cast<double*>(x), rtol, maxit, w, s, iters, &conv)))
+      return st;
+    if (info || !conv) {
+      if ((st = true_residual<double>(c, static_cast<const double*>(rhs),
+                                      static_cast<const double*>(x), w, s, rel)))
+        return st;
+    }
+  } else {
+    // iterative refinement: double residual, float correction solves
+    CgWork w;
+    if ((st = cg_workspace(c, sizeof(float), w))) return st;
+    const float* b = static_cast<const float*>(rhs);
+    float* xf = static_cast<float*>(x);
+    k_convert<float, double><<<nblk(3 * n), kThreads, 0, s>>>(3 * n, xf, w.x64);
+    float* e = static_cast<float*>(w.vec) + 4 * 3 * n;   // vectors 4 and 5 of the workspace
+    float* rf = e + 3 * n;
+    const double inner = std::max(1e-5, rtol);
+    int outer = 0;
+    for (; outer < 8; ++outer) {
+      if ((st = true_residual<float>(c, b, w.x64, w, s, rel))) return st;
+      if (rel[0] <= rtol && rel[1] <= rtol && rel[2] <= rtol) {
+        conv = true;
+        break;
+      }
+      k_convert<double, float><<<nblk(3 * n), kThreads, 0, s>>>(3 * n, w.res64, rf);
+      if ((st = hip_check(hipMemsetAsync(e, 0, size_t(3 * n) * sizeof(float), s), "memset")))
+        return st;
+      bool c2 = false;
+      if ((st = cg_core<float, float>(c, c->Mval32.as<float>(), rf, e, inner, maxit, w, s, iters,
+                                      &c2)))
+        return st;
+      k_add_correction<<<nblk(3 * n), kThreads, 0, s>>>(3 * n, e, w.x64);
+      if (iters[0] + iters[1] + iters[2] >= 3 * maxit) break;
+    }
+    k_convert<double, float><<<nblk(3 * n), kThreads, 0, s>>>(3 * n, w.x64, xf);
+    if ((st = hip_check(hipGetLastError(), "refinement launch"))) return st;
+  }
+  if (info) {
+    for (int d = 0; d < 3; ++d) {
+      info->iterations[d] = iters[d];
+      info->rel_residual[d] = rel[d];
+    }
+  }
+  if (!conv) return set_error(IBVT_E_NOT_CONVERGED, "consistent-mass CG reached maxit");
+  return IBVT_OK;
+}
+
+}  // namespace ibvt

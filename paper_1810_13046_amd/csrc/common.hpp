@@ -1,0 +1,61 @@
+// Shared host/device helpers for the ibvt HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibvt {
+
+constexpr int kWave = 64;
+
+// Device-side status bits (OR-ed into a flag word by kernels).
+constexpr unsigned kFlagOutOfGrid = 1u;
+constexpr unsigned kFlagCapacity = 2u;
+constexpr unsigned kFlagNonFinite = 4u;
+constexpr unsigned kFlagValence = 8u;
+
+// Counter slots (unsigned long long) written by the assembly kernels.
+enum Counter : int {
+  kCntPieces = 0,
+  kCntDropped = 1,
+  kCntZeroTets = 2,
+  kCntSlots = 8,
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// Lanes below this one in a wave64 mask.
+__device__ __forceinline__ int rank_below(uint64_t m) {
+  return __popcll(m & ((1ull << __lane_id()) - 1ull));
+}
+
+__host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Per-tet cell range for one velocity component: first cell index and
+// cell count along each axis (packed 6 x int32).
+struct CellRange {
+  int32_t lo[3];
+  int32_t n[3];
+};
+
+}  // namespace ibvt

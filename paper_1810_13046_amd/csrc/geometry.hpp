@@ -1,0 +1,442 @@
+// Tet ∩ cell clipping and exact integration of the mortar products on the
+// pieces (Section 2.3, assembly steps (II) and (III): quadrature points in
+// the intersection of a solid element with a fluid cell, then the local
+// contributions ∫ λ_i N_j).
+//
+// Clipping keeps the piece as a vertex graph (every vertex has exactly three
+// neighbours, listed counter-clockwise seen from outside), the
+// representation of Powell & Abel's r3d ("An exact general remeshing scheme
+// applied to physically conservative voxelization", J. Comput. Phys. 2015).
+// A tet cut by the six planes of a box has at most 10 faces, hence at most
+// 2·10 − 4 = 16 vertices; cut points reuse the slots of vertices that leave,
+// so 16 slots always suffice.  Signed distances and cut points are double;
+// a cut point's coordinate on its plane is set to the plane value, and a
+// vertex with distance >= 0 is inside.
+//
+// Integration: the piece is fanned into sub-tetrahedra from its lowest
+// vertex (faces through that vertex are skipped); on each, λ_i N_j is a
+// degree-4 polynomial and a symmetric 14-point degree-5 rule integrates it
+// exactly.  Coordinates are cell-local (ξ = (x − x0)/h ∈ [0, 1]^3), so the
+// Q1 hats are ξ or 1 − ξ per axis and float arithmetic keeps its relative
+// precision in the mixed-precision path.
+//
+// Everything here is __host__ __device__: the storage of the vertex graph
+// is a strided view (stride 64 = one slot per lane in LDS on the GPU).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibvt {
+
+#include "quadrature.inc"
+
+constexpr int kMaxV = 16;
+constexpr uint32_t kAllSlots = (1u << kMaxV) - 1u;
+
+__host__ __device__ __forceinline__ int ctz32(uint32_t m) { return __builtin_ctz(m); }
+__host__ __device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
+
+__host__ __device__ __forceinline__ int nb_get(uint32_t w, int k) { return (w >> (8 * k)) & 0xff; }
+__host__ __device__ __forceinline__ uint32_t nb_set(uint32_t w, int k, int v) {
+  return (w & ~(0xffu << (8 * k))) | (uint32_t(v) << (8 * k));
+}
+__host__ __device__ __forceinline__ uint32_t nb_pack(int a, int b, int c) {
+  return uint32_t(a) | (uint32_t(b) << 8) | (uint32_t(c) << 16);
+}
+__host__ __device__ __forceinline__ int nb_find(uint32_t w, int v) {
+  return nb_get(w, 0) == v ? 0 : (nb_get(w, 1) == v ? 1 : 2);
+}
+
+// Strided view of one piece's vertex graph.
+struct PolyView {
+  double* px;
+  double* py;
+  double* pz;
+  uint32_t* pnb;
+  int S;
+  __host__ __device__ double& co(int v, int a) const {
+    return (a == 0 ? px : (a == 1 ? py : pz))[v * S];
+  }
+  __host__ __device__ double& x(int v) const { return px[v * S]; }
+  __host__ __device__ double& y(int v) const { return py[v * S]; }
+  __host__ __device__ double& z(int v) const { return pz[v * S]; }
+  __host__ __device__ uint32_t& nb(int v) const { return pnb[v * S]; }
+};
+
+// Load a tetrahedron (vertices V, any orientation); `flip` swaps vertices 2
+// and 3 so that the stored one is positively oriented.
+__host__ __device__ inline uint32_t poly_init_tet(const PolyView& P, const double V[4][3],
+                                                  bool flip) {
+  const int ord[4] = {0, 1, flip ? 3 : 2, flip ? 2 : 3};
+  for (int v = 0; v < 4; ++v) {
+    P.x(v) = V[ord[v]][0];
+    P.y(v) = V[ord[v]][1];
+    P.z(v) = V[ord[v]][2];
+  }
+  P.nb(0) = nb_pack(1, 3, 2);
+  P.nb(1) = nb_pack(2, 3, 0);
+  P.nb(2) = nb_pack(0, 3, 1);
+  P.nb(3) = nb_pack(1, 2, 0);
+  return 0xFu;
+}
+
+// Keep the half-space sgn·(x_a − c) >= 0.  `live` is the mask of used
+// slots.  Returns false if the fixed capacity or a walk bound is exceeded.
+__host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int a, double c,
+                                          double sgn) {
+  uint32_t out = 0;
+  for (uint32_t m = live; m; m &= m - 1) {
+    const int v = ctz32(m);
+    if (sgn * (P.co(v, a) - c) < 0.0) out |= 1u << v;
+  }
+  if (!out) return true;
+  if (out == live) {
+    live = 0;
+    return true;
+  }
+  const uint32_t in = live & ~out;
+  uint32_t adj = 0;  // vertices adjacent to an inside vertex
+  for (uint32_t m = in; m; m &= m - 1) {
+    const uint32_t w = P.nb(ctz32(m));
+    adj |= (1u << nb_get(w, 0)) | (1u << nb_get(w, 1)) | (1u << nb_get(w, 2));
+  }
+  // free slots: never used, or outside with no inside neighbour
+  uint32_t freem = (~live & kAllSlots) | (out & ~adj);
+  uint32_t newm = 0;
+  for (uint32_t m = out & adj; m; m &= m - 1) {
+    const int u = ctz32(m);
+    const double ux = P.x(u), uy = P.y(u), uz = P.z(u);
+    const double su = sgn * (P.co(u, a) - c);
+    const uint32_t unb = P.nb(u);
+    bool first = true;
+    for (int k = 0; k < 3; ++k) {
+      const int v = nb_get(unb, k);
+      if (!((in >> v) & 1u)) continue;
+      const double vx = P.x(v), vy = P.y(v), vz = P.z(v);
+      const double sv = sgn * (P.co(v, a) - c);
+      const double t = sv / (sv - su);
+      int w;
+      if (first) {
+        w = u;  // v's neighbour entry already names u
+        first = false;
+      } else {
+        if (!freem) return false;
+        w = ctz32(freem);
+        freem &= freem - 1;
+        const uint32_t vw = P.nb(v);
+        P.nb(v) = nb_set(vw, nb_find(vw, u), w);
+      }
+      P.x(w) = vx + t * (ux - vx);
+      P.y(w) = vy + t * (uy - vy);
+      P.z(w) = vz + t * (uz - vz);
+      P.co(w, a) = c;
+      P.nb(w) = nb_pack(v, v, v);
+      newm |= 1u << w;
+    }
+  }
+  // Close the cap: from each new vertex walk around the face on its left
+  // until the next new vertex.
+  for (uint32_t m = newm; m; m &= m - 1) {
+    const int w = ctz32(m);
+    int vcur = w;
+    int vnext = nb_get(P.nb(w), 0);
+    int guard = 0;
+    do {
+      const uint32_t nw = P.nb(vnext);
+      const int np = nb_find(nw, vcur);
+      vcur = vnext;
+      vnext = nb_get(nw, (np + 1) % 3);
+      if (++guard > 3 * kMaxV) return false;
+    } while (!((newm >> vcur) & 1u));
+    P.nb(w) = nb_set(P.nb(w), 2, vcur);
+    P.nb(vcur) = nb_set(P.nb(vcur), 1, w);
+  }
+  live = in | newm;
+  return true;
+}
+
+// Clip by the six planes of the box [lo, hi].
+__host__ __device__ inline bool poly_clip_box(const PolyView& P, uint32_t& live, const double lo[3],
+                                              const double hi[3]) {
+  for (int a = 0; a < 3 && live; ++a) {
+    if (!poly_clip(P, live, a, lo[a], 1.0)) return false;
+    if (live && !poly_clip(P, live, a, hi[a], -1.0)) return false;
+  }
+  return true;
+}
+
+// Call fn(apex, f0, f1, f2) for every sub-tetrahedron of the fan
+// decomposition.  Faces are walked with the same rule as the cap closure,
+// which traverses every face clockwise seen from outside, so each
+// sub-tetrahedron (apex, f0, f1, f2) has a non-positive determinant.
+template <typename F>
+__host__ __device__ inline bool poly_fan(const PolyView& P, uint32_t live, F&& fn) {
+  if (!live) return true;
+  const int apex = ctz32(live);
+  uint64_t seen = 0;
+  for (uint32_t m = live; m; m &= m - 1) {
+    const int v = ctz32(m);
+    const uint32_t vw = P.nb(v);
+    for (int k = 0; k < 3; ++k) {
+      if ((seen >> (3 * v + k)) & 1ull) continue;
+      // pass 1: mark the face's directed edges, look for the apex
+      bool has_apex = (v == apex);
+      int prev = v, cur = nb_get(vw, k);
+      seen |= 1ull << (3 * v + k);
+      int guard = 0;
+      while (cur != v) {
+        has_apex |= (cur == apex);
+        const uint32_t cw = P.nb(cur);
+        const int nk = (nb_find(cw, prev) + 1) % 3;
+        seen |= 1ull << (3 * cur + nk);
+        prev = cur;
+        cur = nb_get(cw, nk);
+        if (++guard > 3 * kMaxV) return false;
+      }
+      if (has_apex) continue;
+      // pass 2: fan from v
+      int f1 = nb_get(vw, k);
+      prev = v;
+      guard = 0;
+      for (;;) {
+        const uint32_t cw = P.nb(f1);
+        const int f2 = nb_get(cw, (nb_find(cw, prev) + 1) % 3);
+        if (f2 == v) break;
+        fn(apex, v, f1, f2);
+        prev = f1;
+        f1 = f2;
+        if (++guard > 3 * kMaxV) return false;
+      }
+    }
+  }
+  return true;
+}
+
+// Integrate λ_i N_j (i = 0..3 tet vertices, j = corner a + 2b + 4c of the
+// cell) over one sub-tetrahedron with vertices y (cell-local coordinates)
+// and weight scale wscale (its determinant).  λ_i(ξ) = LA[i] + LG[i]·ξ.
+// Adds the unscaled sums into acc[i*8 + j]; the caller multiplies by
+// (cell volume / 6) and the orientation sign.
+template <typename T>
+__host__ __device__ __forceinline__ void quad_point(T px, T py, T pz, T w, const T LA[4],
+                                                    const T LG[4][3], T acc[32]) {
+  const T hx1 = px, hx0 = T(1) - px;
+  const T hy1 = py, hy0 = T(1) - py;
+  const T hz1 = pz, hz0 = T(1) - pz;
+  const T n00 = hx0 * hy0, n10 = hx1 * hy0, n01 = hx0 * hy1, n11 = hx1 * hy1;
+  const T N[8] = {n00 * hz0, n10 * hz0, n01 * hz0, n11 * hz0,
+                  n00 * hz1, n10 * hz1, n01 * hz1, n11 * hz1};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T wl = w * (LA[i] + LG[i][0] * px + LG[i][1] * py + LG[i][2] * pz);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i * 8 + j] += wl * N[j];
+  }
+}
+
+template <typename T>
+__host__ __device__ inline void subtet_integrate(const T y[4][3], T wscale, const T LA[4],
+                                                 const T LG[4][3], T acc[32]) {
+  T S[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) S[e] = y[0][e] + y[1][e] + y[2][e] + y[3][e];
+  const T a1 = T(kQA1), c1 = T(1.0 - 4.0 * kQA1), w1 = T(kQW1) * wscale;
+  const T a2 = T(kQA2), c2 = T(1.0 - 4.0 * kQA2), w2 = T(kQW2) * wscale;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    quad_point<T>(a1 * S[0] + c1 * y[k][0], a1 * S[1] + c1 * y[k][1], a1 * S[2] + c1 * y[k][2],
+                  w1, LA, LG, acc);
+    quad_point<T>(a2 * S[0] + c2 * y[k][0], a2 * S[1] + c2 * y[k][1], a2 * S[2] + c2 * y[k][2],
+                  w2, LA, LG, acc);
+  }
+  // S22 orbit: b on a pair of vertices, 1/2 − b on the complementary pair
+  const T pb = T(2.0 * kQB - 0.5), ps = T(0.5 - kQB), w3 = T(kQW3) * wscale;
+  const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int k = pk[q], l = pl[q];
+    quad_point<T>(pb * (y[k][0] + y[l][0]) + ps * S[0], pb * (y[k][1] + y[l][1]) + ps * S[1],
+                  pb * (y[k][2] + y[l][2]) + ps * S[2], w3, LA, LG, acc);
+  }
+}
+
+// Shape-derivative integrand on one sub-tetrahedron.  With w = Σ_i z_i λ_i
+// (z at the tet's vertices) and U = Σ_j u_j N_j (u at the cell's corners):
+//   A[a*3+k] += ∫ λ_a w ∂U/∂ξ_k,   Bs += ∫ w U      (unscaled, cell-local)
+template <typename T>
+__host__ __device__ __forceinline__ void grad_point(T px, T py, T pz, T wq, const T LA[4],
+                                                    const T LG[4][3], const T zl[4],
+                                                    const T ul[8], T A[12], T& Bs) {
+  T lam[4];
+  T w = T(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    lam[i] = LA[i] + LG[i][0] * px + LG[i][1] * py + LG[i][2] * pz;
+    w += zl[i] * lam[i];
+  }
+  const T hx1 = px, hx0 = T(1) - px, hy1 = py, hy0 = T(1) - py, hz1 = pz, hz0 = T(1) - pz;
+  // differences along each axis of the corner values (corner = a + 2b + 4c)
+  const T dx00 = ul[1] - ul[0], dx10 = ul[3] - ul[2], dx01 = ul[5] - ul[4], dx11 = ul[7] - ul[6];
+  const T dy00 = ul[2] - ul[0], dy10 = ul[3] - ul[1], dy01 = ul[6] - ul[4], dy11 = ul[7] - ul[5];
+  const T dz00 = ul[4] - ul[0], dz10 = ul[5] - ul[1], dz01 = ul[6] - ul[2], dz11 = ul[7] - ul[3];
+  const T gx = (dx00 * hy0 + dx10 * hy1) * hz0 + (dx01 * hy0 + dx11 * hy1) * hz1;
+  const T gy = (dy00 * hx0 + dy10 * hx1) * hz0 + (dy01 * hx0 + dy11 * hx1) * hz1;
+  const T gz = (dz00 * hx0 + dz10 * hx1) * hy0 + (dz01 * hx0 + dz11 * hx1) * hy1;
+  const T u00 = ul[0] + px * dx00, u10 = ul[2] + px * dx10;
+  const T u01 = ul[4] + px * dx01, u11 = ul[6] + px * dx11;
+  const T U = (u00 * hy0 + u10 * hy1) * hz0 + (u01 * hy0 + u11 * hy1) * hz1;
+  const T ww = wq * w;
+  Bs += ww * U;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const T t = ww * lam[a];
+    A[a * 3 + 0] += t * gx;
+    A[a * 3 + 1] += t * gy;
+    A[a * 3 + 2] += t * gz;
+  }
+}
+
+template <typename T>
+__host__ __device__ inline void subtet_grad(const T y[4][3], T wscale, const T LA[4],
+                                            const T LG[4][3], const T zl[4], const T ul[8],
+                                            T A[12], T& Bs) {
+  T S[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) S[e] = y[0][e] + y[1][e] + y[2][e] + y[3][e];
+  const T a1 = T(kQA1), c1 = T(1.0 - 4.0 * kQA1), w1 = T(kQW1) * wscale;
+  const T a2 = T(kQA2), c2 = T(1.0 - 4.0 * kQA2), w2 = T(kQW2) * wscale;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    grad_point<T>(a1 * S[0] + c1 * y[k][0], a1 * S[1] + c1 * y[k][1], a1 * S[2] + c1 * y[k][2],
+                  w1, LA, LG, zl, ul, A, Bs);
+    grad_point<T>(a2 * S[0] + c2 * y[k][0], a2 * S[1] + c2 * y[k][1], a2 * S[2] + c2 * y[k][2],
+                  w2, LA, LG, zl, ul, A, Bs);
+  }
+  const T pb = T(2.0 * kQB - 0.5), ps = T(0.5 - kQB), w3 = T(kQW3) * wscale;
+  const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int k = pk[q], l = pl[q];
+    grad_point<T>(pb * (y[k][0] + y[l][0]) + ps * S[0], pb * (y[k][1] + y[l][1]) + ps * S[1],
+                  pb * (y[k][2] + y[l][2]) + ps * S[2], w3, LA, LG, zl, ul, A, Bs);
+  }
+}
+
+// Tet data shared by the clip kernels: vertices, orientation, volume and
+// barycentric gradients.
+struct TetGeom {
+  double V[4][3];
+  double det;      // e1 · (e2 × e3), e_k = V_k − V_0
+  double g[4][3];  // ∇λ_i
+};
+
+__host__ __device__ inline void tet_geom(TetGeom& G) {
+  double e[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 3; ++a) e[k][a] = G.V[k + 1][a] - G.V[0][a];
+  // cofactor rows: ∇λ_1 = (e2 × e3)/det, ∇λ_2 = (e3 × e1)/det, ∇λ_3 = (e1 × e2)/det
+  double c[3][3];
+  for (int k = 0; k < 3; ++k) {
+    const double* p = e[(k + 1) % 3];
+    const double* q = e[(k + 2) % 3];
+    c[k][0] = p[1] * q[2] - p[2] * q[1];
+    c[k][1] = p[2] * q[0] - p[0] * q[2];
+    c[k][2] = p[0] * q[1] - p[1] * q[0];
+  }
+  G.det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+  const double inv = (G.det != 0.0) ? 1.0 / G.det : 0.0;
+  for (int a = 0; a < 3; ++a) {
+    G.g[1][a] = c[0][a] * inv;
+    G.g[2][a] = c[1][a] * inv;
+    G.g[3][a] = c[2][a] * inv;
+    G.g[0][a] = -(G.g[1][a] + G.g[2][a] + G.g[3][a]);
+  }
+}
+
+// Clip tet ∩ box and integrate.  Returns false on a capacity/walk failure.
+// vol6 receives 6·|piece| in cell-local units (times the cell volume gives
+// 6|piece|), acc the 32 unscaled sums (caller scales by cellvol/6·(−1)).
+template <typename T>
+__host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom& G,
+                                               const double lo[3], const double hi[3],
+                                               double& vol6, T acc[32]) {
+  for (int k = 0; k < 32; ++k) acc[k] = T(0);
+  vol6 = 0.0;
+  uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
+  if (!poly_clip_box(P, live, lo, hi)) return false;
+  if (!live) return true;
+  const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
+  const double h[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+  // λ_i in cell-local coordinates: λ_i(ξ) = λ_i(lo) + (∇λ_i ∘ h)·ξ
+  T LA[4], LG[4][3];
+  for (int i = 0; i < 4; ++i) {
+    double a0 = (i == 0) ? 1.0 : 0.0;
+    for (int e = 0; e < 3; ++e) a0 += G.g[i][e] * (lo[e] - G.V[0][e]);
+    LA[i] = T(a0);
+    for (int e = 0; e < 3; ++e) LG[i][e] = T(G.g[i][e] * h[e]);
+  }
+  double vsum = 0.0;
+  const bool ok = poly_fan(P, live, [&](int q0, int q1, int q2, int q3) {
+    const int qs[4] = {q0, q1, q2, q3};
+    double yd[4][3];
+    for (int v = 0; v < 4; ++v)
+      for (int e = 0; e < 3; ++e) yd[v][e] = (P.co(qs[v], e) - lo[e]) * ih[e];
+    double d[3][3];
+    for (int v = 0; v < 3; ++v)
+      for (int e = 0; e < 3; ++e) d[v][e] = yd[v + 1][e] - yd[0][e];
+    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+    vsum += det;
+    T y[4][3];
+    for (int v = 0; v < 4; ++v)
+      for (int e = 0; e < 3; ++e) y[v][e] = T(yd[v][e]);
+    subtet_integrate<T>(y, T(det), LA, LG, acc);
+  });
+  vol6 = -vsum;
+  return ok;
+}
+
+// Clip tet ∩ box and call sub(y, det) for every sub-tetrahedron (cell-local
+// coordinates as T, determinant as double).  Also returns the λ
+// coefficients in cell-local coordinates and 6|piece| (cell-local units).
+template <typename T, typename F>
+__host__ __device__ inline bool clip_fan_local(const PolyView& P, const TetGeom& G,
+                                               const double lo[3], const double hi[3], T LA[4],
+                                               T LG[4][3], double& vol6, F&& sub) {
+  vol6 = 0.0;
+  uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
+  if (!poly_clip_box(P, live, lo, hi)) return false;
+  const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
+  const double h[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+  for (int i = 0; i < 4; ++i) {
+    double a0 = (i == 0) ? 1.0 : 0.0;
+    for (int e = 0; e < 3; ++e) a0 += G.g[i][e] * (lo[e] - G.V[0][e]);
+    LA[i] = T(a0);
+    for (int e = 0; e < 3; ++e) LG[i][e] = T(G.g[i][e] * h[e]);
+  }
+  if (!live) return true;
+  double vsum = 0.0;
+  const bool ok = poly_fan(P, live, [&](int q0, int q1, int q2, int q3) {
+    const int qs[4] = {q0, q1, q2, q3};
+    double yd[4][3];
+    for (int v = 0; v < 4; ++v)
+      for (int e = 0; e < 3; ++e) yd[v][e] = (P.co(qs[v], e) - lo[e]) * ih[e];
+    double d[3][3];
+    for (int v = 0; v < 3; ++v)
+      for (int e = 0; e < 3; ++e) d[v][e] = yd[v + 1][e] - yd[0][e];
+    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+    vsum += det;
+    T y[4][3];
+    for (int v = 0; v < 4; ++v)
+      for (int e = 0; e < 3; ++e) y[v][e] = T(yd[v][e]);
+    sub(y, det);
+  });
+  vol6 = -vsum;
+  return ok;
+}
+
+}  // namespace ibvt

@@ -1,0 +1,186 @@
+// Shape derivative of the transfers with respect to the solid vertex
+// positions X (reverse mode).
+//
+// B_ij(X) = Σ_T ∫_T λ_i N_j: the P1 hats λ_i move with the vertices while the
+// Q1 hats N_j stay on the grid.  Moving vertex a of T along e_k moves the
+// points of T by λ_a e_k, so
+//   ∂B_ij/∂X_{a,k} = Σ_{T∋a} ∫_T (λ_a λ_i ∂_k N_j + ∂_k λ_a λ_i N_j)
+// and, contracted with z (solid) and u (fluid), with w = Σ z_i λ_i and
+// U = Σ u_j N_j (the Q1 interpolant):
+//   z^T (∂B/∂X_{a,k}) u = Σ_{T∋a} [ ∫ λ_a w ∂_k U + ∂_k λ_a ∫ w U ].
+// The kernel below computes the bracket per (tet, component, cell) pair by
+// re-clipping the piece; k_grad_gather sums it per vertex in a fixed order
+// and subtracts the mass term  z^T (∂S/∂X) u_s, with ∂|T|/∂X_a = |T| ∇λ_a
+// (S consistent: |T|(1+δ_il)/20 per tet; lumped: |T|/4 on the diagonal).
+#include "geometry.hpp"
+#include "internal.hpp"
+
+namespace ibvt {
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_shape_pairs(
+    int64_t n_pairs, int64_t n_t, int64_t n_v, const int32_t* __restrict__ owner,
+    const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
+    const uint8_t* __restrict__ keep, const double* __restrict__ X,
+    const int32_t* __restrict__ tets, const double* __restrict__ lat, LatDesc ld,
+    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, T* __restrict__ pg,
+    unsigned* flags) {
+  __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
+  __shared__ uint32_t snb[kMaxV * kWave];
+  const int lane = threadIdx.x;
+  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave};
+  bool fail = false;
+  for (int64_t p = int64_t(blockIdx.x) * kWave + lane; p < n_pairs;
+       p += int64_t(gridDim.x) * kWave) {
+    T* out = pg + p * 12;
+    if (!keep[p]) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) out[k] = T(0);
+      continue;
+    }
+    const int64_t tc = owner[p];
+    const int d = int(tc / n_t);
+    const int64_t t = tc - int64_t(d) * n_t;
+    const CellRange r = rng[tc];
+    const int64_t q = p - pair_off[tc];
+    const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
+                       r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+    TetGeom G;
+    T zl[4];
+    for (int k = 0; k < 4; ++k) {
+      const int64_t v = tets[4 * t + k];
+      G.V[k][0] = X[3 * v + 0];
+      G.V[k][1] = X[3 * v + 1];
+      G.V[k][2] = X[3 * v + 2];
+      zl[k] = z[int64_t(d) * n_v + v];
+    }
+    tet_geom(G);
+    double lo[3], hi[3];
+    for (int e = 0; e < 3; ++e) {
+      const double* L = lat + ld.off[3 * d + e];
+      lo[e] = L[ci[e]];
+      hi[e] = L[ci[e] + 1];
+    }
+    const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
+    const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
+    T ul[8];
+    for (int c = 0; c < 2; ++c)
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a)
+          ul[a + 2 * b + 4 * c] = u[(ci[0] + a) + NX * ((ci[1] + b) + NY * int64_t(ci[2] + c))];
+    T LA[4], LG[4][3], A[12], Bs = T(0);
+    for (int k = 0; k < 12; ++k) A[k] = T(0);
+    double vol6;
+    const bool ok = clip_fan_local<T>(P, G, lo, hi, LA, LG, vol6, [&](const T (&y)[4][3], double det) {
+      subtet_grad<T>(y, T(det), LA, LG, zl, ul, A, Bs);
+    });
+    if (!ok) {
+      fail = true;
+      for (int k = 0; k < 12; ++k) out[k] = T(0);
+      continue;
+    }
+    const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+    const double sc = -cv / 6.0;
+    for (int a = 0; a < 4; ++a)
+      for (int k = 0; k < 3; ++k)
+        out[a * 3 + k] = T(sc * (double(A[a * 3 + k]) / (hi[k] - lo[k]) + G.g[a][k] * double(Bs)));
+  }
+  const uint64_t fm = ballot64(fail);
+  if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
+}
+
+// One wavefront per vertex a: lanes take (incident tet, component) items,
+// sum the pair terms and the mass term, then a fixed-order wave reduction.
+// mass: 0 lumped, 1 consistent, -1 none.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_gather(
+    int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
+    const int64_t* __restrict__ pair_off, const T* __restrict__ pg, const double* __restrict__ X,
+    const T* __restrict__ z, const T* __restrict__ us, int mass, double alpha,
+    double* __restrict__ gX) {
+  const int64_t a = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  if (a >= n_v) return;
+  const int64_t beg = vt_ptr[a], end = vt_ptr[a + 1];
+  double g[3] = {0, 0, 0};
+  for (int64_t it = beg * 3 + lane; it < end * 3; it += kWave) {
+    const int64_t k = it / 3;
+    const int d = int(it - k * 3);
+    const int64_t t = vt_tet[k];
+    int la = 0;
+    int32_t vv[4];
+    for (int q = 0; q < 4; ++q) {
+      vv[q] = tets[4 * t + q];
+      if (vv[q] == int32_t(a)) la = q;
+    }
+    const int64_t tc = int64_t(d) * n_t + t;
+    for (int64_t p = pair_off[tc]; p < pair_off[tc + 1]; ++p)
+      for (int e = 0; e < 3; ++e) g[e] += double(pg[p * 12 + la * 3 + e]);
+    if (mass >= 0) {
+      TetGeom G;
+      for (int q = 0; q < 4; ++q)
+        for (int e = 0; e < 3; ++e) G.V[q][e] = X[3 * int64_t(vv[q]) + e];
+      tet_geom(G);
+      const double vol = fabs(G.det) / 6.0;
+      double zl[4], ul[4], zs = 0, uss = 0, zu = 0;
+      for (int q = 0; q < 4; ++q) {
+        zl[q] = double(z[int64_t(d) * n_v + vv[q]]);
+        ul[q] = double(us[int64_t(d) * n_v + vv[q]]);
+        zs += zl[q];
+        uss += ul[q];
+        zu += zl[q] * ul[q];
+      }
+      const double s = (mass == 1) ? (zu + zs * uss) / 20.0 : zu / 4.0;
+      for (int e = 0; e < 3; ++e) g[e] -= vol * s * G.g[la][e];
+    }
+  }
+  for (int e = 0; e < 3; ++e) g[e] = wave_sum(g[e]);
+  if (lane == 0)
+    for (int e = 0; e < 3; ++e) gX[3 * a + e] += alpha * g[e];
+}
+
+template <typename T>
+int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const void* us, int mass,
+                double alpha, double* gX, hipStream_t s) {
+  int st = ensure(c, c->work2, size_t(c->n_pairs + 1) * 12 * sizeof(T));
+  if (st) return st;
+  T* pg = c->work2.as<T>();
+  unsigned* flags = c->flags_dev.as<unsigned>();
+  if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
+  if (c->n_pairs > 0) {
+    const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
+    k_shape_pairs<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
+        c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
+        c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->X.as<double>(), c->tets.as<int32_t>(),
+        c->lat.as<double>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
+        static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg, flags);
+  }
+  if ((st = hip_check(hipGetLastError(), "shape launch"))) return st;
+  const unsigned blocks = unsigned(ceil_div(c->n_vert * kWave, 256));
+  if (c->n_vert > 0)
+    k_grad_gather<T><<<blocks, 256, 0, s>>>(c->n_vert, c->n_tet, c->vt_ptr.as<int64_t>(),
+                                            c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+                                            c->pair_off.as<int64_t>(), pg, c->X.as<double>(),
+                                            static_cast<const T*>(z), static_cast<const T*>(us),
+                                            mass, alpha, gX);
+  if ((st = hip_check(hipGetLastError(), "gather launch"))) return st;
+  unsigned f = 0;
+  if ((st = hip_check(hipMemcpyAsync(&f, flags, sizeof(f), hipMemcpyDeviceToHost, s), "read")))
+    return st;
+  if ((st = hip_check(hipStreamSynchronize(s), "sync"))) return st;
+  if (f & kFlagCapacity) return set_error(IBVT_E_CAPACITY, "clipped piece exceeded capacity");
+  return IBVT_OK;
+}
+
+}  // namespace
+
+int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
+                   int mass, double alpha, double* gX, hipStream_t s) {
+  if (c->precision == IBVT_FP32_MIXED) return shape_typed<float>(c, z, u, us, mass, alpha, gX, s);
+  return shape_typed<double>(c, z, u, us, mass, alpha, gX, s);
+}
+
+}  // namespace ibvt

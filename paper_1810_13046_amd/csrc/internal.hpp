@@ -1,0 +1,115 @@
+// Internal (non-ABI) declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ibvt.h"
+#include "common.hpp"
+
+namespace ibvt {
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct Csr {
+  int64_t nrows = 0;
+  int64_t nnz = 0;
+  DevBuf rowptr;  // int64 (nrows + 1)
+  DevBuf col;     // int32 (nnz)
+  DevBuf val;     // double or float (nnz)
+  DevBuf rowmap;  // int32 (nrows), transposed matrices only
+};
+
+// Lattice description passed by value to kernels: 9 coordinate arrays
+// (component d, axis e) concatenated in one device buffer.
+struct LatDesc {
+  int32_t off[9];
+  int32_t n[9];
+};
+
+struct AsmStats {
+  int64_t pairs = 0, pieces = 0, dropped = 0, zero_tets = 0;
+  int64_t assemblies = 0;
+};
+
+}  // namespace ibvt
+
+struct ibvt_coupling {
+  int precision = IBVT_FP64;
+  uint32_t flags = 0;
+  int64_t n_vert = 0, n_tet = 0;
+  int32_t n_cells[3] = {0, 0, 0};
+  std::vector<double> lat_host[9];
+  ibvt::LatDesc ld{};
+  int64_t n_fluid[3] = {0, 0, 0};
+  ibvt::DevBuf lat;          // double, concatenated lattices
+  ibvt::DevBuf X, tets;      // own copies
+  ibvt::DevBuf vt_ptr, vt_tet;  // vertex -> incident tets (int64 ptr, int32 ids)
+  ibvt::DevBuf tetvol;       // double n_tet
+  ibvt::DevBuf rng;          // CellRange 3*n_tet
+  ibvt::DevBuf cnt;          // int64 3*n_tet
+  ibvt::DevBuf pair_off;     // int64 3*n_tet + 1
+  int64_t n_pairs = 0;
+  ibvt::DevBuf owner;        // int32 n_pairs
+  ibvt::DevBuf pval;         // T n_pairs*32
+  ibvt::DevBuf keep;         // uint8 n_pairs
+  ibvt::DevBuf rownnz;       // int64 3*n_vert
+  ibvt::Csr B[3], Bt[3];
+  ibvt::DevBuf mark;         // int32 max n_fluid (+1)
+  ibvt::DevBuf cidx;         // int64 max n_fluid + 1
+  ibvt::DevBuf tcount;       // int64 max touched + 1 (counts / cursors)
+  ibvt::DevBuf mlump;        // double n_vert
+  ibvt::DevBuf minv;         // T n_vert
+  bool has_M = false;
+  ibvt::Csr M;               // consistent mass (double values)
+  ibvt::DevBuf Mval32;       // float copy of M values (mixed precision)
+  ibvt::DevBuf Mdiag_inv;    // double n_vert
+  ibvt::DevBuf flags_dev;    // unsigned
+  ibvt::DevBuf counters;     // unsigned long long kCntSlots
+  ibvt::DevBuf scan_tmp;     // scan scratch
+  ibvt::DevBuf work;         // transfer scratch (CG vectors etc.)
+  ibvt::DevBuf work2;        // shape-gradient per-pair scratch / CG right-hand side
+  ibvt::DevBuf zbuf;         // solid-sized scratch of the reverse-mode calls
+  ibvt::DevBuf host_pinned;  // small pinned host buffer for read-backs
+  ibvt::AsmStats stats;
+  int64_t device_bytes = 0;
+};
+
+namespace ibvt {
+
+// status helpers (api.hip)
+int set_error(int status, const std::string& msg);
+int hip_check(hipError_t e, const char* what);
+int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes);
+void release(ibvt_coupling* c, DevBuf& b);
+
+// scan.hip: exclusive prefix sum; out has n+1 entries, out[n] = total.
+int scan_i64(ibvt_coupling* c, const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+int scan_i32_to_i64(ibvt_coupling* c, const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+
+// assemble.hip
+int build_topology(ibvt_coupling* c, hipStream_t s);
+int assemble_all(ibvt_coupling* c, hipStream_t s);
+
+// apply.hip
+int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s);
+int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha, hipStream_t s);
+int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxit,
+               hipStream_t s, ibvt_solve_info* info, bool x_has_guess);
+int lumped_solve(ibvt_coupling* c, const void* rhs, void* x, hipStream_t s);
+int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream_t s);
+
+// grad.hip
+int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
+                   int mass, double alpha, double* gX, hipStream_t s);
+
+}  // namespace ibvt

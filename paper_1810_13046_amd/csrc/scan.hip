@@ -1,0 +1,120 @@
+// Exclusive prefix sums (int64 totals) for counts, offsets and index maps.
+// Three passes: per-block totals, one block scanning the totals, per-block
+// scan plus offset.  Deterministic (integer) and independent of timing.
+#include "internal.hpp"
+
+namespace ibvt {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename Tin>
+__global__ __launch_bounds__(kScanThreads) void k_block_sums(const Tin* __restrict__ in, int64_t n,
+                                                            int64_t* __restrict__ bsum) {
+  __shared__ int64_t red[kScanThreads / kWave];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + int64_t(k) * kScanThreads + threadIdx.x;
+    if (i < n) s += int64_t(in[i]);
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) t += red[w];
+    bsum[blockIdx.x] = t;
+  }
+}
+
+// Inclusive scan of one value per thread across the block; returns the
+// exclusive prefix and writes the block total to *total.
+__device__ int64_t block_exclusive(int64_t v, int64_t* sh, int64_t* total) {
+  // wave-level inclusive scan
+  int64_t x = v;
+  const int l = lane_id();
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, kWave);
+    if (l >= o) x += y;
+  }
+  const int w = threadIdx.x / kWave;
+  if (l == kWave - 1) sh[w] = x;
+  __syncthreads();
+  int64_t pre = 0, tot = 0;
+  for (int k = 0; k < int(blockDim.x) / kWave; ++k) {
+    if (k < w) pre += sh[k];
+    tot += sh[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t* __restrict__ bsum, int64_t nb,
+                                                           int64_t* __restrict__ total_out) {
+  __shared__ int64_t sh[kScanThreads / kWave];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = (i < nb) ? bsum[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive(v, sh, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const Tin* __restrict__ in, int64_t n,
+                                                            const int64_t* __restrict__ bsum,
+                                                            int64_t* __restrict__ out) {
+  __shared__ int64_t sh[kScanThreads / kWave];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    v[k] = (i < n) ? int64_t(in[i]) : 0;
+    s += v[k];
+  }
+  int64_t tot;
+  int64_t pre = block_exclusive(s, sh, &tot) + bsum[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    if (i < n) out[i] = pre;
+    pre += v[k];
+  }
+}
+
+template <typename Tin>
+int scan_impl(ibvt_coupling* c, const Tin* in, int64_t* out, int64_t n, hipStream_t s) {
+  const int64_t nb = ceil_div(n > 0 ? n : 1, kScanTile);
+  int st = ensure(c, c->scan_tmp, size_t(nb) * sizeof(int64_t));
+  if (st) return st;
+  int64_t* bsum = c->scan_tmp.as<int64_t>();
+  if (n > 0) k_block_sums<Tin><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(in, n, bsum);
+  else {
+    st = hip_check(hipMemsetAsync(bsum, 0, sizeof(int64_t), s), "memset");
+    if (st) return st;
+  }
+  k_scan_sums<<<1, kScanThreads, 0, s>>>(bsum, n > 0 ? nb : 0, out + n);
+  if (n > 0) k_scan_tiles<Tin><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(in, n, bsum, out);
+  return hip_check(hipGetLastError(), "scan launch");
+}
+
+}  // namespace
+
+int scan_i64(ibvt_coupling* c, const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  return scan_impl<int64_t>(c, in, out, n, s);
+}
+
+int scan_i32_to_i64(ibvt_coupling* c, const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  return scan_impl<int32_t>(c, in, out, n, s);
+}
+
+}  // namespace ibvt

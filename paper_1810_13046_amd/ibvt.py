@@ -1,0 +1,304 @@
+"""Python binding of libibvt (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module only checks
+shapes and dtypes of torch tensors and passes device pointers and the
+current HIP stream through the C ABI declared in include/ibvt.h.  There is
+no CPU fallback: if the library is missing or no GPU is present, calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibvt.so")
+
+IBVT_OK = 0
+STATUS_NAMES = {
+    0: "IBVT_OK", 1: "IBVT_E_INVALID", 2: "IBVT_E_OUT_OF_GRID", 3: "IBVT_E_HIP",
+    4: "IBVT_E_NOMEM", 5: "IBVT_E_NOT_CONVERGED", 6: "IBVT_E_CAPACITY", 7: "IBVT_E_UNSUPPORTED",
+}
+FP64, FP32_MIXED = 0, 1
+LUMPED, CONSISTENT = 0, 1
+BUILD_CONSISTENT_M = 1
+FORCE_IS_LOAD = 1
+
+EXPORTED = [
+    "assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
+    "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info", "coupling_export_csr",
+    "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
+]
+
+
+class IbvtError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {self.name}: {detail}")
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32 * 3), ("faces", ctypes.c_void_p * 3)]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_vert", ctypes.c_int64), ("n_tet", ctypes.c_int64),
+                ("X", ctypes.c_void_p), ("tets", ctypes.c_void_p)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32 * 3), ("rel_residual", ctypes.c_double * 3)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("has_consistent_mass", ctypes.c_int32),
+                ("n_vert", ctypes.c_int64), ("n_tet", ctypes.c_int64),
+                ("lattice", (ctypes.c_int64 * 3) * 3), ("n_fluid", ctypes.c_int64 * 3),
+                ("pairs", ctypes.c_int64), ("pieces", ctypes.c_int64),
+                ("dropped", ctypes.c_int64), ("zero_tets", ctypes.c_int64),
+                ("nnz", ctypes.c_int64 * 3), ("touched", ctypes.c_int64 * 3),
+                ("nnz_mass", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("assemblies", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libibvt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_1810_13046_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+    P = ctypes.POINTER
+    lib.assemble_coupling.argtypes = [P(_Grid), P(_Mesh), ctypes.c_int, u32, vp, P(vp)]
+    lib.reassemble_coupling.argtypes = [vp, vp, vp]
+    lib.transfer_velocity.argtypes = [vp, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int, vp, P(_SolveInfo)]
+    lib.transfer_force.argtypes = [vp, vp, P(vp), dbl, u32, vp]
+    lib.transfer_velocity_vjp.argtypes = [vp, vp, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int, P(vp), vp, vp]
+    lib.transfer_force_vjp.argtypes = [vp, P(vp), vp, dbl, vp, vp, vp]
+    lib.coupling_info.argtypes = [vp, P(_Info)]
+    lib.coupling_export_csr.argtypes = [vp, ctypes.c_int, ctypes.c_int, P(i64), P(i64), vp, vp, vp, vp]
+    lib.coupling_free.argtypes = [vp]
+    lib.coupling_free.restype = None
+    lib.ibvt_status_string.argtypes = [ctypes.c_int]
+    lib.ibvt_status_string.restype = ctypes.c_char_p
+    lib.ibvt_last_error.argtypes = []
+    lib.ibvt_last_error.restype = ctypes.c_char_p
+    lib.ibvt_lattice_coords.argtypes = [P(_Grid), ctypes.c_int, ctypes.c_int, vp, P(i64)]
+    for name in EXPORTED:
+        if getattr(lib, name).restype is ctypes.c_int and name not in ("coupling_free",):
+            pass
+    for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
+                 "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
+                 "coupling_export_csr", "ibvt_lattice_coords"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str):
+    if st != IBVT_OK:
+        detail = _lib.ibvt_last_error().decode(errors="replace") if _lib else ""
+        raise IbvtError(st, where, detail)
+
+
+def _grid_struct(faces):
+    faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
+    g = _Grid()
+    for e in range(3):
+        g.n_cells[e] = faces[e].size - 1
+        g.faces[e] = faces[e].ctypes.data
+    return g, faces
+
+
+def lattice_coords(faces, comp: int):
+    """Node coordinates of component `comp`'s lattice along x, y, z (host)."""
+    lib = load_library()
+    g, keep = _grid_struct(faces)
+    out = []
+    for e in range(3):
+        n = ctypes.c_int64()
+        _check(lib.ibvt_lattice_coords(ctypes.byref(g), comp, e, None, ctypes.byref(n)), "lattice")
+        a = np.empty(n.value)
+        _check(lib.ibvt_lattice_coords(ctypes.byref(g), comp, e, a.ctypes.data, ctypes.byref(n)),
+               "lattice")
+        out.append(a)
+    del keep
+    return out
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, numel, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what}: expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveInfo:
+    iterations: tuple
+    rel_residual: tuple
+
+
+class Coupling:
+    """A coupling handle: B^d, B^dT, masses for one grid and mesh."""
+
+    def __init__(self, faces, X, tets, precision: str = "fp64", consistent: bool = True,
+                 stream=None):
+        import torch
+        lib = load_library()
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("precision must be 'fp64' or 'fp32' (mixed)")
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
+        self.n_vert = int(X.shape[0])
+        self.n_tet = int(tets.shape[0])
+        if X.ndim != 2 or X.shape[1] != 3:
+            raise ValueError("X must be (n_vert, 3)")
+        if tets.ndim != 2 or tets.shape[1] != 4:
+            raise ValueError("tets must be (n_tet, 4)")
+        g, keep = _grid_struct(self.faces)
+        m = _Mesh()
+        m.n_vert = self.n_vert
+        m.n_tet = self.n_tet
+        m.X = _dev(X, torch.float64, 3 * self.n_vert, "X")
+        m.tets = _dev(tets, torch.int32, 4 * self.n_tet, "tets") if self.n_tet else None
+        h = ctypes.c_void_p()
+        flags = BUILD_CONSISTENT_M if consistent else 0
+        _check(lib.assemble_coupling(ctypes.byref(g), ctypes.byref(m),
+                                     FP64 if precision == "fp64" else FP32_MIXED, flags,
+                                     _stream(stream), ctypes.byref(h)), "assemble_coupling")
+        self._h = h
+        self.consistent = consistent
+        del keep
+        self.lattice_shapes = [tuple(len(a) for a in lattice_coords(self.faces, d))
+                               for d in range(3)]
+        self.n_fluid = [int(np.prod(s)) for s in self.lattice_shapes]
+
+    # -- lifetime ---------------------------------------------------------
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.coupling_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("coupling was freed")
+        return self._h
+
+    def reassemble(self, X, stream=None):
+        import torch
+        _check(_lib.reassemble_coupling(self.handle, _dev(X, torch.float64, 3 * self.n_vert, "X"),
+                                        _stream(stream)), "reassemble_coupling")
+
+    # -- operations ---------------------------------------------------------
+    def _fluid_ptrs(self, u, what):
+        if len(u) != 3:
+            raise ValueError(f"{what}: need 3 fluid components")
+        arr = (ctypes.c_void_p * 3)()
+        for d in range(3):
+            arr[d] = _dev(u[d], self.dtype, self.n_fluid[d], f"{what}[{d}]")
+        return arr
+
+    def velocity(self, u_f, mass: str = "lumped", rtol: float = 1e-10, maxit: int = 500,
+                 out=None, stream=None, with_info: bool = False):
+        """u_s = S^{-1} B u_f, returns (3, n_vert)."""
+        import torch
+        uf = self._fluid_ptrs(u_f, "u_f")
+        if out is None:
+            out = torch.empty((3, self.n_vert), dtype=self.dtype, device=u_f[0].device)
+        info = _SolveInfo()
+        st = _lib.transfer_velocity(self.handle, uf, _dev(out, self.dtype, 3 * self.n_vert, "u_s"),
+                                    LUMPED if mass == "lumped" else CONSISTENT, float(rtol),
+                                    int(maxit), _stream(stream),
+                                    ctypes.byref(info) if with_info else None)
+        _check(st, "transfer_velocity")
+        if with_info:
+            return out, SolveInfo(tuple(info.iterations), tuple(info.rel_residual))
+        return out
+
+    def force(self, f_s, f_f, alpha: float = 1.0, load: bool = False, stream=None):
+        """f_f[d] += alpha B^dT f_s[d] (in place), returns f_f."""
+        ff = self._fluid_ptrs(f_f, "f_f")
+        _check(_lib.transfer_force(self.handle, _dev(f_s, self.dtype, 3 * self.n_vert, "f_s"), ff,
+                                   float(alpha), FORCE_IS_LOAD if load else 0, _stream(stream)),
+               "transfer_force")
+        return f_f
+
+    def velocity_vjp(self, g_us, u_f=None, u_s=None, mass: str = "lumped", g_uf=None, g_X=None,
+                     rtol: float = 1e-12, maxit: int = 500, stream=None):
+        """Accumulates g_uf (3 fluid arrays) and g_X ((n_vert, 3) float64)."""
+        import torch
+        uf = self._fluid_ptrs(u_f, "u_f") if u_f is not None else None
+        guf = self._fluid_ptrs(g_uf, "g_uf") if g_uf is not None else None
+        _check(_lib.transfer_velocity_vjp(
+            self.handle, _dev(g_us, self.dtype, 3 * self.n_vert, "g_us"), uf,
+            _dev(u_s, self.dtype, 3 * self.n_vert, "u_s") if u_s is not None else None,
+            LUMPED if mass == "lumped" else CONSISTENT, float(rtol), int(maxit), guf,
+            _dev(g_X, torch.float64, 3 * self.n_vert, "g_X") if g_X is not None else None,
+            _stream(stream)), "transfer_velocity_vjp")
+
+    def force_vjp(self, g_ff, f_s=None, alpha: float = 1.0, g_fs=None, g_X=None, stream=None):
+        import torch
+        gff = self._fluid_ptrs(g_ff, "g_ff")
+        _check(_lib.transfer_force_vjp(
+            self.handle, gff, _dev(f_s, self.dtype, 3 * self.n_vert, "f_s") if f_s is not None else None,
+            float(alpha), _dev(g_fs, self.dtype, 3 * self.n_vert, "g_fs") if g_fs is not None else None,
+            _dev(g_X, torch.float64, 3 * self.n_vert, "g_X") if g_X is not None else None,
+            _stream(stream)), "transfer_force_vjp")
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(_lib.coupling_info(self.handle, ctypes.byref(i)), "coupling_info")
+        return dict(precision=i.precision, has_consistent_mass=bool(i.has_consistent_mass),
+                    n_vert=i.n_vert, n_tet=i.n_tet,
+                    lattice=[[i.lattice[d][e] for e in range(3)] for d in range(3)],
+                    n_fluid=list(i.n_fluid), pairs=i.pairs, pieces=i.pieces, dropped=i.dropped,
+                    zero_tets=i.zero_tets, nnz=list(i.nnz), touched=list(i.touched),
+                    nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies)
+
+    def export_csr(self, comp: int, transposed: bool = False):
+        """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""
+        nr, nz = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.coupling_export_csr(self.handle, comp, int(transposed), ctypes.byref(nr),
+                                        ctypes.byref(nz), None, None, None, None), "export")
+        rp = np.empty(nr.value + 1, dtype=np.int32)
+        col = np.empty(max(nz.value, 1), dtype=np.int32)
+        val = np.empty(max(nz.value, 1), dtype=np.float64)
+        rm = np.empty(max(nr.value, 1), dtype=np.int32)
+        _check(_lib.coupling_export_csr(self.handle, comp, int(transposed), ctypes.byref(nr),
+                                        ctypes.byref(nz), rp.ctypes.data, col.ctypes.data,
+                                        val.ctypes.data, rm.ctypes.data if transposed else None),
+               "export")
+        col, val = col[:nz.value], val[:nz.value]
+        if transposed:
+            return rp, col, val, rm[:nr.value]
+        return rp, col, val
