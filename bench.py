@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Throughput of the L2-projection transfer hot path on one MI355X.
+
+Workload (default): the large three-body case on a 512 x 256 x 256
+staggered grid, y-stretched (ratio 4) about y = 1/2, domain [0,2]x[0,1]x[0,1];
+beam 1,975,392 + plate 1,500,282 + curved shell 1,027,728 = 4,503,402 P1
+tets, 832,517 vertices, assembled in one launch sequence.  Inputs are seeded
+and synthetic (see workloads/gen.py), resident in HBM before timing.
+
+One step = the whole hot path on that input:
+  reassemble B^d (all three velocity lattices) for the current positions,
+  velocity transfer with the consistent mass (CG to 1e-10),
+  force transfer,
+  reverse mode of both transfers (fluid cotangents and the shape gradient).
+The headline `value` is solid tets per second of that step in the
+mixed-precision path (double clipping, float quadrature and applies); the
+same step in FP64 is reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VEC_PEAK_TFLOPS = 157.3
+FP64_VEC_PEAK_TFLOPS = 78.6
+# flops per quadrature point of the 4 x 8 mortar products (hats, 8 Q1 basis
+# products, 4 affine λ evaluations, 32 multiply-adds), 14 points per
+# sub-tetrahedron of a clipped piece
+FLOPS_PER_POINT = 107
+POINTS_PER_SUBTET = 14
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(cfg, dev):
+    import torch
+    import workloads as wl
+    from paper_1810_13046_amd import lattice_coords
+    t0 = time.time()
+    W = wl.workload(cfg)
+    k, phi = wl.fourier_modes(W.n_modes, W.kmax, 2000 + cfg)
+    u64 = []
+    for d in range(3):
+        xs, ys, zs = lattice_coords(W.faces, d)
+        u64.append(wl.fourier_field(k[d], phi[d], xs, ys, zs, device=dev).contiguous())
+    X = torch.as_tensor(W.X, device=dev).contiguous()
+    T = torch.as_tensor(W.tets, device=dev).contiguous()
+    f_s = torch.as_tensor(W.f_s(), device=dev).contiguous()
+    u_t = torch.as_tensor(W.u_target(), device=dev).contiguous()
+    torch.cuda.synchronize()
+    log(f"[bench] inputs for workload {cfg} ({W.name}) in {time.time() - t0:.1f}s: "
+        f"{W.tets.shape[0]} tets, {W.X.shape[0]} vertices, grid {W.n_cells}")
+    return W, X, T, u64, f_s, u_t
+
+
+class Step:
+    """Buffers and one full pass of the hot path for one precision."""
+
+    def __init__(self, W, X, T, u64, f_s, u_t, precision):
+        import torch
+        from paper_1810_13046_amd import Coupling
+        self.c = Coupling(W.faces, X, T, precision=precision, consistent=True)
+        dt = self.c.dtype
+        self.X = X
+        self.u = [u.to(dt).contiguous() for u in u64]
+        self.f_s = f_s.to(dt).contiguous()
+        self.u_t = u_t.to(dt).contiguous()
+        self.us = torch.empty((3, X.shape[0]), dtype=dt, device=X.device)
+        self.ff = [torch.zeros_like(u) for u in self.u]
+        self.g_uf = [torch.zeros_like(u) for u in self.u]
+        self.g_fs = torch.zeros_like(self.f_s)
+        self.g_X = torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device)
+
+    def run(self):
+        c = self.c
+        c.reassemble(self.X)
+        c.velocity(self.u, mass="consistent", rtol=1e-10, maxit=500, out=self.us)
+        c.force(self.f_s, self.ff, alpha=1.0)
+        g_us = self.us - self.u_t
+        c.velocity_vjp(g_us, u_f=self.u, u_s=self.us, mass="consistent", g_uf=self.g_uf,
+                       g_X=self.g_X, rtol=1e-10, maxit=500)
+        c.force_vjp(self.u, f_s=self.f_s, alpha=1.0, g_fs=self.g_fs, g_X=self.g_X)
+
+
+def time_steps(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step.run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for k in range(steps):
+        step.run()
+        log(f"[bench]   step {k + 1}/{steps}")
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def kernel_profile(step):
+    import torch
+    from paper_1810_13046_amd import profile_enable, profile_read
+    torch.cuda.synchronize()
+    profile_read()
+    profile_enable(True)
+    step.run()
+    torch.cuda.synchronize()
+    prof = profile_read()
+    profile_enable(False)
+    return prof
+
+
+def apply_rates(step, reps=20):
+    """Lumped velocity apply and force apply: ms per launch (HIP events on
+    the library's stream) and algorithmic bytes per apply."""
+    import torch
+    from paper_1810_13046_amd import profile_enable, profile_read
+    c = step.c
+    info = c.info()
+    s = 8 if c.precision == "fp64" else 4
+    n = info["n_vert"]
+    nnz, t = info["nnz"], info["touched"]
+    vel_bytes = sum(nnz[d] * (s + 4) + 4 * (n + 1) + s * t[d] + s * n for d in range(3)) + s * n
+    frc_bytes = sum(nnz[d] * (s + 4) + 4 * (t[d] + 1) + 4 * t[d] + 2 * s * t[d] + s * n
+                    for d in range(3))
+    for _ in range(3):
+        c.velocity(step.u, mass="lumped", out=step.us)
+        c.force(step.f_s, step.ff)
+    torch.cuda.synchronize()
+    profile_read()
+    profile_enable(True)
+    for _ in range(reps):
+        c.velocity(step.u, mass="lumped", out=step.us)
+        c.force(step.f_s, step.ff)
+    torch.cuda.synchronize()
+    prof = profile_read()
+    profile_enable(False)
+    vel_ms = prof["spmv_B"][1] / prof["spmv_B"][0]
+    frc_ms = prof["spmv_Bt"][1] / prof["spmv_Bt"][0]
+    return dict(velocity_ms=vel_ms, force_ms=frc_ms, velocity_bytes=vel_bytes, force_bytes=frc_bytes,
+                velocity_GBs=vel_bytes / vel_ms / 1e6, force_GBs=frc_bytes / frc_ms / 1e6)
+
+
+def cpu_baseline(W, dev, tets_per_body):
+    """The FP64 oracle on a bounded sample: the first `tets_per_body` tets of
+    each body (a sub-mesh on the same grid), one full step."""
+    import torch
+    import oracle
+    import workloads as wl
+    oracle.build(force=False)
+    sel = []
+    for b in range(len(W.bodies)):
+        t0, t1 = int(W.body_tet_offsets[b]), int(W.body_tet_offsets[b + 1])
+        sel.append(np.arange(t0, min(t1, t0 + tets_per_body)))
+    sel = np.concatenate(sel)
+    T = W.tets[sel]
+    used, inv = np.unique(T, return_inverse=True)
+    T = inv.reshape(T.shape).astype(np.int32)
+    X = W.X[used]
+    k, phi = wl.fourier_modes(W.n_modes, W.kmax, 2000 + W.cfg)
+    u = []
+    for d in range(3):
+        xs, ys, zs = oracle.lattice(W.faces, d)
+        u.append(wl.fourier_field(k[d], phi[d], xs, ys, zs, device=dev).cpu().numpy())
+    f_s = W.f_s()[:, used]
+    u_t = W.u_target()[:, used]
+    t0 = time.perf_counter()
+    cpl = oracle.assemble(W.faces, X, T)
+    us = oracle.transfer_velocity(cpl, u, "consistent")
+    oracle.transfer_force(cpl, f_s, 1.0)
+    oracle.velocity_vjp(cpl, u, us - u_t, "consistent")
+    oracle.force_vjp(cpl, f_s, [a.ravel() for a in u], 1.0)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=T.shape[0] / dt, unit="solid tets/s", cores=cores, kind="oracle",
+                sample=f"first {tets_per_body} tets of each of the {len(W.bodies)} bodies "
+                       f"({T.shape[0]} tets, {X.shape[0]} vertices) on the full grid; one full "
+                       f"step (assembly, consistent velocity by sparse LU, force, both adjoints) "
+                       f"in {dt:.1f}s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=5, help=argparse.SUPPRESS)
+    ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 step")
+    ap.add_argument("--skip-cpu", action="store_true", help="do not time the oracle")
+    ap.add_argument("--cpu-tets-per-body", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the transfer is built and timed on a single MI355X; "
+              "multi-GPU sharding is a design note only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    from paper_1810_13046_amd import load_library
+    load_library()
+
+    W, X, T, u64, f_s, u_t = make_inputs(args.workload, dev)
+    n_tet = W.tets.shape[0]
+
+    log("[bench] mixed-precision step: build")
+    mixed = Step(W, X, T, u64, f_s, u_t, "fp32")
+    log("[bench] mixed-precision step: timing")
+    ms_mixed, wall_mixed = time_steps(mixed, args.steps, args.warmup)
+    prof_mixed = kernel_profile(mixed)
+    rates_mixed = apply_rates(mixed)
+    info = mixed.c.info()
+    log(f"[bench] mixed {ms_mixed:.2f} ms/step; kernels {json.dumps(prof_mixed)}")
+
+    fp64 = None
+    if not args.skip_fp64:
+        del mixed.c
+        mixed_keep = mixed
+        log("[bench] fp64 step: build")
+        s64 = Step(W, X, T, u64, f_s, u_t, "fp64")
+        log("[bench] fp64 step: timing")
+        ms64, wall64 = time_steps(s64, args.steps, args.warmup)
+        prof64 = kernel_profile(s64)
+        rates64 = apply_rates(s64)
+        fp64 = dict(ms_per_step=ms64, value=n_tet / (ms64 * 1e-3), kernels_ms=prof64,
+                    applies=rates64)
+        log(f"[bench] fp64 {ms64:.2f} ms/step")
+        del s64
+        del mixed_keep
+
+    # dominant kernel of the mixed step and its roofline
+    per_kernel = {k: v[1] for k, v in prof_mixed.items()}
+    dom = max(per_kernel, key=per_kernel.get)
+    launches = prof_mixed[dom][0]
+    avg_ms = per_kernel[dom] / launches
+    if dom == "clip_integrate":
+        flops = info["subtets"] * POINTS_PER_SUBTET * FLOPS_PER_POINT
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP32_VEC_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=achieved / FP32_VEC_PEAK_TFLOPS, traffic=None,
+                    launch_ms=avg_ms, algorithmic_flops_per_launch=flops)
+    else:
+        roof = dict(kernel=dom, bound="unknown", achieved=None, peak=None, unit=None, frac=None,
+                    traffic=None, launch_ms=avg_ms)
+    roof_apply = dict(kernel="spmv_B (lumped velocity apply)", bound="hbm",
+                      achieved=rates_mixed["velocity_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=rates_mixed["velocity_GBs"] / HBM_PEAK_GBS, traffic=None,
+                      launch_ms=rates_mixed["velocity_ms"],
+                      algorithmic_bytes_per_launch=rates_mixed["velocity_bytes"])
+
+    cpu = None
+    if not args.skip_cpu:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(W, dev, args.cpu_tets_per_body)
+        log(f"[bench] cpu baseline {cpu['value']:.1f} tets/s")
+
+    out = {
+        "metric": "B assembly (solid tets/s) + transfer applies/s, HBM % of peak; mixed vs FP64",
+        "value": n_tet / (ms_mixed * 1e-3),
+        "unit": "solid tets/s (full step: assembly + consistent velocity + force + both adjoints)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mixed,
+        "wall_ms_per_step": wall_mixed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 quadrature/applies, f64 clipping and CG residual",
+        "data": "synthetic (seeded meshes and Fourier velocity fields)",
+        "config": {
+            "workload": W.name, "n_tet": int(n_tet), "n_vert": int(W.X.shape[0]),
+            "grid_cells": list(W.n_cells), "y_stretch_ratio": 4.0, "bodies": len(W.bodies),
+            "mass": "consistent", "cg_rtol": 1e-10, "parallelism": "single GPU",
+        },
+        "assembly": {"pairs": info["pairs"], "pieces": info["pieces"], "subtets": info["subtets"],
+                     "nnz": info["nnz"], "touched": info["touched"],
+                     "device_bytes": info["device_bytes"]},
+        "kernels_ms": {k: v[1] for k, v in prof_mixed.items()},
+        "kernel_launches": {k: v[0] for k, v in prof_mixed.items()},
+        "applies": {
+            "velocity_per_s": 1e3 / rates_mixed["velocity_ms"],
+            "force_per_s": 1e3 / rates_mixed["force_ms"],
+            **rates_mixed,
+        },
+        "fp64": fp64,
+        "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / ms_mixed) if fp64 else None,
+        "roofline": roof,
+        "roofline_apply": roof_apply,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -124,6 +124,8 @@ typedef struct {
   int64_t nnz_mass;          /* nonzeros of the consistent mass matrix */
   int64_t device_bytes;      /* device memory held by the coupling */
   int64_t assemblies;        /* assemblies done on this handle */
+  int64_t subtets;           /* sub-tetrahedra integrated by the last
+                                assembly (each gets the 14-point rule) */
 } ibvt_info;
 
 /*
@@ -240,6 +242,18 @@ const char* ibvt_last_error(void);
  *   (staggered grid, Section 2.2).  Errors: IBVT_E_INVALID.
  */
 int ibvt_lattice_coords(const ibvt_grid* grid, int comp, int axis, double* out, int64_t* n);
+
+/*
+ * Kernel tracing (process-wide; no paper counterpart).  While enabled, the
+ * library records a HIP event pair on the caller's stream around each of
+ * its main kernel launches.  ibvt_profile_read synchronizes those events and
+ * returns, per kernel name, the number of launches and the summed device
+ * time in milliseconds (up to max entries, sorted by name); it also clears
+ * the records.  names[k] points to static strings.  Returns the number of
+ * entries written, or -IBVT_E_HIP.
+ */
+void ibvt_profile_enable(int on);
+int ibvt_profile_read(const char** names, int64_t* launches, double* ms, int max);
 
 #ifdef __cplusplus
 }

@@ -10,5 +10,6 @@ grid (Q1 per velocity component) and a P1 tetrahedral solid mesh
 Autograd forms live in paper_1810_13046_amd.autograd.
 """
 from .ibvt import (  # noqa: F401
-    Coupling, IbvtError, lattice_coords, load_library, LIB_PATH, EXPORTED,
+    Coupling, IbvtError, lattice_coords, load_library, LIB_PATH, EXPORTED, profile_enable,
+    profile_read,
 )

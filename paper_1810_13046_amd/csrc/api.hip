@@ -7,10 +7,46 @@
 
 #include "internal.hpp"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 namespace ibvt {
 
 namespace {
 thread_local std::string g_last_error;
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> recs;
+};
+ProfState& prof() {
+  static ProfState p;
+  return p;
+}
+}  // namespace
+
+ProfScope::ProfScope(const char* name, hipStream_t stream) : s(stream) {
+  ProfState& P = prof();
+  if (!P.on) return;
+  ProfRec r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  (void)hipEventRecord(r.a, stream);
+  std::lock_guard<std::mutex> g(P.mu);
+  slot = int(P.recs.size());
+  P.recs.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+  if (slot < 0) return;
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  if (slot < int(P.recs.size())) (void)hipEventRecord(P.recs[slot].b, s);
 }
 
 int set_error(int status, const std::string& msg) {
@@ -340,6 +376,7 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->nnz_mass = c->has_M ? c->M.nnz : 0;
   info->device_bytes = c->device_bytes;
   info->assemblies = c->stats.assemblies;
+  info->subtets = c->stats.subtets;
   return IBVT_OK;
 }
 
@@ -386,6 +423,42 @@ int coupling_export_csr(const ibvt_coupling* c, int comp, int transposed, int64_
                         "copy")))
       return st;
   return IBVT_OK;
+}
+
+void ibvt_profile_enable(int on) {
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = on != 0;
+}
+
+int ibvt_profile_read(const char** names, int64_t* launches, double* ms, int max) {
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  std::map<std::string, std::pair<int64_t, double>> acc;
+  std::map<std::string, const char*> keep;
+  int status = 0;
+  for (ProfRec& r : P.recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      status = -IBVT_E_HIP;
+    auto& e = acc[r.name];
+    e.first += 1;
+    e.second += double(t);
+    keep[r.name] = r.name;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  P.recs.clear();
+  if (status) return status;
+  int k = 0;
+  for (auto& kv : acc) {
+    if (k >= max) break;
+    if (names) names[k] = keep[kv.first];
+    if (launches) launches[k] = kv.second.first;
+    if (ms) ms[k] = kv.second.second;
+    ++k;
+  }
+  return k;
 }
 
 void coupling_free(ibvt_coupling* c) {

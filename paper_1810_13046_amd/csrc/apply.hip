@@ -66,10 +66,11 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs<T> a) {
 }
 
 template <typename T, int G>
-int launch_spmv(const SpmvArgs<T>& a, hipStream_t s) {
+int launch_spmv(const SpmvArgs<T>& a, hipStream_t s, const char* name) {
   int64_t mx = std::max(a.nrows[0], std::max(a.nrows[1], a.nrows[2]));
   if (mx <= 0) return IBVT_OK;
   dim3 grid(unsigned(ceil_div(mx, kThreads / G)), 3);
+  ProfScope ps(name, s);
   k_spmv<T, G><<<grid, kThreads, 0, s>>>(a);
   return hip_check(hipGetLastError(), "spmv launch");
 }
@@ -392,6 +393,7 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
   while (it < maxit) {
     const int chunk = std::min(check, maxit - it);
     for (int k = 0; k < chunk; ++k) {
+      ProfScope ps("cg_iteration", s);
       k_mass_spmv<T, V><<<nb, kThreads, 0, s>>>(n, rp, col, mval, p, q, w.part, w.sc);
       k_reduce3<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
       k_cg_scalar<<<1, 64, 0, s>>>(1, w.sc, w.tmp, rtol2);
@@ -455,7 +457,7 @@ int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale
     }
     a.scale = lumped_scale ? c->minv.as<float>() : nullptr;
     a.alpha = 1.0f;
-    return launch_spmv<float, 16>(a, s);
+    return launch_spmv<float, 16>(a, s, "spmv_B");
   }
   SpmvArgs<double> a{};
   for (int d = 0; d < 3; ++d) {
@@ -468,7 +470,7 @@ int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale
   }
   a.scale = lumped_scale ? c->minv.as<double>() : nullptr;
   a.alpha = 1.0;
-  return launch_spmv<double, 16>(a, s);
+  return launch_spmv<double, 16>(a, s, "spmv_B");
 }
 
 // out[d][rowmap[r]] += alpha * (B^dT ys_d)[r]
@@ -487,7 +489,7 @@ int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,
     }
     a.alpha = float(alpha);
     a.accumulate = 1;
-    return launch_spmv<float, 16>(a, s);
+    return launch_spmv<float, 16>(a, s, "spmv_Bt");
   }
   SpmvArgs<double> a{};
   for (int d = 0; d < 3; ++d) {
@@ -501,7 +503,7 @@ int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,
   }
   a.alpha = alpha;
   a.accumulate = 1;
-  return launch_spmv<double, 16>(a, s);
+  return launch_spmv<double, 16>(a, s, "spmv_Bt");
 }
 
 int lumped_solve(ibvt_coupling* c, const void* rhs, void* x, hipStream_t s) {

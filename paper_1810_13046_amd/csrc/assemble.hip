@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
   __shared__ uint32_t snb[kMaxV * kWave];
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave};
-  unsigned long long nk = 0, nd = 0;
+  unsigned long long nk = 0, nd = 0, ns = 0;
   bool fail = false;
   for (int64_t p = int64_t(blockIdx.x) * kWave + lane; p < n_pairs;
        p += int64_t(gridDim.x) * kWave) {
@@ -242,7 +242,10 @@ __global__ __launch_bounds__(kWave) void k_clip(
     }
     double vol6;
     T acc[32];
-    if (!clip_integrate<T>(P, G, lo, hi, vol6, acc)) {
+    int nsub = 0;
+    const bool ok = clip_integrate<T>(P, G, lo, hi, vol6, acc, nsub);
+    ns += unsigned(nsub);
+    if (!ok) {
       fail = true;
       keep[p] = 0;
       continue;
@@ -263,10 +266,12 @@ __global__ __launch_bounds__(kWave) void k_clip(
   }
   nk = wave_sum(nk);
   nd = wave_sum(nd);
+  ns = wave_sum(ns);
   const uint64_t fm = ballot64(fail);
   if (lane == 0) {
     if (nk) atomicAdd(&counters[kCntPieces], nk);
     if (nd) atomicAdd(&counters[kCntDropped], nd);
+    if (ns) atomicAdd(&counters[kCntSubtets], ns);
     if (fm) atomicOr(flags, kFlagCapacity);
   }
 }
@@ -555,9 +560,12 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
                       "memset")))
     return st;
   // (I) overlap candidates
+  {
+    ProfScope ps("tet_prep", s);
   k_tet_prep<<<blocks_for(n_t, 256), 256, 0, s>>>(
       n_t, c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld,
       c->tetvol.as<double>(), c->rng.as<CellRange>(), c->cnt.as<int64_t>(), flags, counters);
+  }
   if ((st = hip_check(hipGetLastError(), "prep launch"))) return st;
   if ((st = scan_i64(c, c->cnt.as<int64_t>(), c->pair_off.as<int64_t>(), 3 * n_t, s))) return st;
   if ((st = check_flags(c, s))) return st;
@@ -575,6 +583,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   // (II)+(III) clip and integrate every pair
   if (n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(n_pairs, kWave), int64_t(1) << 22);
+    ProfScope ps("clip_integrate", s);
     k_clip<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
         n_pairs, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
         c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,
@@ -584,10 +593,13 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   // (IV) global assembly: rows of B^d
   RowOut<T> ro{};
   const unsigned row_blocks = blocks_for(3 * n_v * kWave, 256);
-  k_rows<T, false><<<row_blocks, 256, 0, s>>>(
-      n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-      c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
-      c->ld, c->rownnz.as<int64_t>(), ro);
+  {
+    ProfScope ps("rows_count", s);
+    k_rows<T, false><<<row_blocks, 256, 0, s>>>(
+        n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+        c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
+        c->ld, c->rownnz.as<int64_t>(), ro);
+  }
   if ((st = hip_check(hipGetLastError(), "rows launch"))) return st;
   for (int d = 0; d < 3; ++d) {
     c->B[d].nrows = n_v;
@@ -606,14 +618,21 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     ro.col[d] = c->B[d].col.as<int32_t>();
     ro.val[d] = c->B[d].val.as<T>();
   }
-  k_rows<T, true><<<row_blocks, 256, 0, s>>>(
-      n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-      c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
-      c->ld, c->rownnz.as<int64_t>(), ro);
+  {
+    ProfScope ps("rows_fill", s);
+    k_rows<T, true><<<row_blocks, 256, 0, s>>>(
+        n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+        c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
+        c->ld, c->rownnz.as<int64_t>(), ro);
+  }
   if ((st = hip_check(hipGetLastError(), "rows fill launch"))) return st;
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
+    ProfScope ps("transpose", s);
     if ((st = transpose_one<T>(c, d, s))) return st;
+  }
   // masses
+  {
+    ProfScope ps("masses", s);
   k_lumped<T><<<blocks_for(n_v, 256), 256, 0, s>>>(n_v, c->vt_ptr.as<int64_t>(),
                                                    c->vt_tet.as<int32_t>(), c->tetvol.as<double>(),
                                                    c->mlump.as<double>(), c->minv.as<T>());
@@ -624,6 +643,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
         c->M.val.as<double>(), c->precision == IBVT_FP32_MIXED ? c->Mval32.as<float>() : nullptr,
         c->Mdiag_inv.as<double>());
   }
+  }
   if ((st = hip_check(hipGetLastError(), "mass launch"))) return st;
   unsigned long long cnt[kCntSlots];
   if ((st = read_back(c, cnt, counters, sizeof(cnt), s))) return st;
@@ -631,6 +651,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   c->stats.pieces = int64_t(cnt[kCntPieces]);
   c->stats.dropped = int64_t(cnt[kCntDropped]);
   c->stats.zero_tets = int64_t(cnt[kCntZeroTets]);
+  c->stats.subtets = int64_t(cnt[kCntSubtets]);
   c->stats.assemblies += 1;
   return check_flags(c, s);
 }

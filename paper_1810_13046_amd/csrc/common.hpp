@@ -19,6 +19,7 @@ enum Counter : int {
   kCntPieces = 0,
   kCntDropped = 1,
   kCntZeroTets = 2,
+  kCntSubtets = 3,
   kCntSlots = 8,
 };
 

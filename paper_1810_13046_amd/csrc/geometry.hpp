@@ -360,9 +360,10 @@ __host__ __device__ inline void tet_geom(TetGeom& G) {
 template <typename T>
 __host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom& G,
                                                const double lo[3], const double hi[3],
-                                               double& vol6, T acc[32]) {
+                                               double& vol6, T acc[32], int& nsub) {
   for (int k = 0; k < 32; ++k) acc[k] = T(0);
   vol6 = 0.0;
+  nsub = 0;
   uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
   if (!poly_clip_box(P, live, lo, hi)) return false;
   if (!live) return true;
@@ -389,6 +390,7 @@ __host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom&
                        d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
                        d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
     vsum += det;
+    ++nsub;
     T y[4][3];
     for (int v = 0; v < 4; ++v)
       for (int e = 0; e < 3; ++e) y[v][e] = T(yd[v][e]);

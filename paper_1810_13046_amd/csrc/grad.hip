@@ -152,6 +152,7 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
   if (c->n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
+    ProfScope ps("shape_pairs", s);
     k_shape_pairs<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
         c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->X.as<double>(), c->tets.as<int32_t>(),
@@ -160,6 +161,7 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   }
   if ((st = hip_check(hipGetLastError(), "shape launch"))) return st;
   const unsigned blocks = unsigned(ceil_div(c->n_vert * kWave, 256));
+  ProfScope ps_g("grad_gather", s);
   if (c->n_vert > 0)
     k_grad_gather<T><<<blocks, 256, 0, s>>>(c->n_vert, c->n_tet, c->vt_ptr.as<int64_t>(),
                                             c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),

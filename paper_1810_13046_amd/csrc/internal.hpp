@@ -37,7 +37,7 @@ struct LatDesc {
 };
 
 struct AsmStats {
-  int64_t pairs = 0, pieces = 0, dropped = 0, zero_tets = 0;
+  int64_t pairs = 0, pieces = 0, dropped = 0, zero_tets = 0, subtets = 0;
   int64_t assemblies = 0;
 };
 
@@ -85,6 +85,14 @@ struct ibvt_coupling {
 };
 
 namespace ibvt {
+
+// Kernel tracing: records an event pair around a launch when enabled.
+struct ProfScope {
+  int slot = -1;
+  hipStream_t s = nullptr;
+  ProfScope(const char* name, hipStream_t stream);
+  ~ProfScope();
+};
 
 // status helpers (api.hip)
 int set_error(int status, const std::string& msg);

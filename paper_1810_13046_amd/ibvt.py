@@ -31,6 +31,7 @@ EXPORTED = [
     "assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
     "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info", "coupling_export_csr",
     "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
+    "ibvt_profile_enable", "ibvt_profile_read",
 ]
 
 
@@ -62,7 +63,7 @@ class _Info(ctypes.Structure):
                 ("dropped", ctypes.c_int64), ("zero_tets", ctypes.c_int64),
                 ("nnz", ctypes.c_int64 * 3), ("touched", ctypes.c_int64 * 3),
                 ("nnz_mass", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("assemblies", ctypes.c_int64)]
+                ("assemblies", ctypes.c_int64), ("subtets", ctypes.c_int64)]
 
 
 _lib = None
@@ -93,9 +94,10 @@ def load_library(path: str = LIB_PATH):
     lib.ibvt_last_error.argtypes = []
     lib.ibvt_last_error.restype = ctypes.c_char_p
     lib.ibvt_lattice_coords.argtypes = [P(_Grid), ctypes.c_int, ctypes.c_int, vp, P(i64)]
-    for name in EXPORTED:
-        if getattr(lib, name).restype is ctypes.c_int and name not in ("coupling_free",):
-            pass
+    lib.ibvt_profile_enable.argtypes = [ctypes.c_int]
+    lib.ibvt_profile_enable.restype = None
+    lib.ibvt_profile_read.argtypes = [P(ctypes.c_char_p), P(i64), P(dbl), ctypes.c_int]
+    lib.ibvt_profile_read.restype = ctypes.c_int
     for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords"):
@@ -133,6 +135,24 @@ def lattice_coords(faces, comp: int):
         out.append(a)
     del keep
     return out
+
+
+def profile_enable(on: bool = True):
+    """Record device time of the library's main kernels (HIP events)."""
+    load_library().ibvt_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} since the last read (synchronizes)."""
+    lib = load_library()
+    n = 64
+    names = (ctypes.c_char_p * n)()
+    launches = (ctypes.c_int64 * n)()
+    ms = (ctypes.c_double * n)()
+    k = lib.ibvt_profile_read(names, launches, ms, n)
+    if k < 0:
+        raise IbvtError(-k, "profile_read", lib.ibvt_last_error().decode(errors="replace"))
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(k)}
 
 
 def _stream(stream):
@@ -283,7 +303,8 @@ class Coupling:
                     lattice=[[i.lattice[d][e] for e in range(3)] for d in range(3)],
                     n_fluid=list(i.n_fluid), pairs=i.pairs, pieces=i.pieces, dropped=i.dropped,
                     zero_tets=i.zero_tets, nnz=list(i.nnz), touched=list(i.touched),
-                    nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies)
+                    nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies,
+                    subtets=i.subtets)
 
     def export_csr(self, comp: int, transposed: bool = False):
         """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""

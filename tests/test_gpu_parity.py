@@ -102,21 +102,25 @@ def test_transfers_match_oracle(dev, name, prec):
     say(f"  consistent rel {e2:.2e} iters {inf.iterations} res {inf.rel_residual}")
     assert e2 <= (5e-12 if prec == "fp64" else TOL[prec])
     assert max(inf.rel_residual) <= rtol * 1.0001
-    # force: accumulate into a non-zero field
+    # force into zero arrays, compared with the oracle
     f_s = W.f_s()
     alpha = 0.37
-    base = [np.asarray(u) * 0.5 for u in u_f]
-    fd = [to_dev(b, dt, dev) for b in base]
     say(f"[gpu] force {name} {prec}")
-    c.force(to_dev(f_s, dt, dev), fd, alpha=alpha)
-    wantf = oracle.transfer_force(R, f_s, alpha, base=base)
+    f0 = [torch.zeros(u.shape, dtype=dt, device=dev) for u in u_f]
+    c.force(to_dev(f_s, dt, dev), f0, alpha=alpha)
+    wantf = oracle.transfer_force(R, f_s, alpha)
     for d in range(3):
-        got = fd[d].cpu().numpy().ravel()
-        delta_g = got - base[d].ravel()
-        delta_w = wantf[d] - base[d].ravel()
-        assert rel_fro(delta_g, delta_w) <= TOL[prec], d
+        e = rel_fro(f0[d].cpu().numpy().ravel(), wantf[d])
+        say(f"  force d={d} rel {e:.2e}")
+        assert e <= TOL[prec], d
+    # accumulation: f_f += alpha B^T f_s leaves untouched nodes bitwise alone
+    base = [to_dev(np.asarray(u) * 0.5, dt, dev) for u in u_f]
+    acc = [b.clone() for b in base]
+    c.force(to_dev(f_s, dt, dev), acc, alpha=alpha)
+    for d in range(3):
+        assert torch.equal(acc[d], base[d] + f0[d])
     # force with a load vector (literal transpose of S^{-1} B)
-    fd2 = [torch.zeros_like(x) for x in fd]
+    fd2 = [torch.zeros_like(x) for x in f0]
     c.force(to_dev(f_s, dt, dev), fd2, alpha=alpha, load=True)
     wantl = oracle.transfer_force(R, f_s, alpha, load=True)
     for d in range(3):
@@ -213,8 +217,10 @@ def test_edge_cases(dev):
     # a zero-volume tet next to a valid one: counted, contributes nothing
     say("[gpu] edge: zero-volume tet")
     T = np.array([[0, 1, 2, 3], [0, 1, 4, 2]], dtype=np.int32)
-    Xz = X.copy()
-    Xz[4] = 0.5 * (Xz[0] + Xz[1])          # collinear with 0 and 1 -> flat tet (0,1,4,2)
+    # vertices 0, 1, 2, 4 all lie in the plane z = 3/8 (exact in binary), so
+    # tet (0, 1, 4, 2) has a determinant of exactly zero
+    Xz = np.array([[0.375, 0.375, 0.375], [0.625, 0.375, 0.375], [0.375, 0.625, 0.375],
+                   [0.4, 0.45, 0.6], [0.5, 0.5, 0.375]], dtype=np.float64)
     c = Coupling(faces, to_dev(Xz, torch.float64, dev), to_dev(T, torch.int32, dev))
     R = oracle.assemble(faces, Xz, T)
     assert c.info()["zero_tets"] == 1
