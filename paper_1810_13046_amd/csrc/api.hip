@@ -105,8 +105,10 @@ void release_csr(ibvt_coupling* c, Csr& m) {
 void release_all(ibvt_coupling* c) {
   DevBuf* bufs[] = {&c->lat, &c->X, &c->tets, &c->vt_ptr, &c->vt_tet, &c->tetvol, &c->rng,
                     &c->cnt, &c->pair_off, &c->owner, &c->pval, &c->keep, &c->rownnz, &c->mark,
-                    &c->cidx, &c->tcount, &c->mlump, &c->minv, &c->Mval32, &c->Mdiag_inv,
-                    &c->flags_dev, &c->counters, &c->scan_tmp, &c->work, &c->work2, &c->zbuf};
+                    &c->cidx, &c->tbuf, &c->mlump, &c->minv, &c->Mval32, &c->Mdiag_inv,
+                    &c->flags_dev, &c->counters, &c->scan_tmp, &c->work, &c->work2, &c->zbuf,
+                    &c->pool, &c->sub_begin, &c->sub_cnt, &c->rowbox, &c->rowcap,
+                    &c->rowtmpoff, &c->rowtmpcol, &c->rowtmpval};
   for (DevBuf* b : bufs) release(c, *b);
   for (int d = 0; d < 3; ++d) {
     release_csr(c, c->B[d]);
@@ -224,7 +226,8 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
     return set_error(IBVT_E_INVALID, "mesh X or tets is NULL");
   if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
     return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
-  if (flags & ~IBVT_BUILD_CONSISTENT_M) return set_error(IBVT_E_INVALID, "unknown flags");
+  if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE))
+    return set_error(IBVT_E_INVALID, "unknown flags");
   ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
   c->precision = precision;
@@ -232,6 +235,7 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
   c->n_vert = mesh->n_vert;
   c->n_tet = mesh->n_tet;
   c->has_M = (flags & IBVT_BUILD_CONSISTENT_M) != 0;
+  c->store_pieces = (flags & IBVT_NO_PIECE_STORE) == 0;
   for (int e = 0; e < 3; ++e) c->n_cells[e] = grid->n_cells[e];
   st = setup_lattices(c, grid, stream);
   if (!st) st = ensure(c, c->X, size_t(3 * c->n_vert) * sizeof(double));
@@ -377,6 +381,7 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->device_bytes = c->device_bytes;
   info->assemblies = c->stats.assemblies;
   info->subtets = c->stats.subtets;
+  info->piece_store = c->pool_valid ? 1 : 0;
   return IBVT_OK;
 }
 

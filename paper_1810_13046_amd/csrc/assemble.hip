@@ -210,58 +210,98 @@ __global__ __launch_bounds__(kWave) void k_clip(
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
     const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
     LatDesc ld, double drop_rel, T* __restrict__ pval, uint8_t* __restrict__ keep,
-    unsigned* flags, unsigned long long* counters) {
+    T* __restrict__ pool, int64_t pool_cap, int64_t* __restrict__ sub_begin,
+    uint8_t* __restrict__ sub_cnt, unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
   __shared__ uint32_t snb[kMaxV * kWave];
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave};
   unsigned long long nk = 0, nd = 0, ns = 0;
   bool fail = false;
-  for (int64_t p = int64_t(blockIdx.x) * kWave + lane; p < n_pairs;
-       p += int64_t(gridDim.x) * kWave) {
-    const int64_t tc = owner[p];
-    const int d = int(tc / n_t);
-    const int64_t t = tc - int64_t(d) * n_t;
-    const CellRange r = rng[tc];
-    const int64_t q = p - pair_off[tc];
-    const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
-                       r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+  for (int64_t p0 = int64_t(blockIdx.x) * kWave; p0 < n_pairs; p0 += int64_t(gridDim.x) * kWave) {
+    const int64_t p = p0 + lane;
+    const bool active = p < n_pairs;
     TetGeom G;
-    for (int k = 0; k < 4; ++k) {
-      const int64_t v = tets[4 * t + k];
-      G.V[k][0] = X[3 * v + 0];
-      G.V[k][1] = X[3 * v + 1];
-      G.V[k][2] = X[3 * v + 2];
-    }
-    tet_geom(G);
     double lo[3], hi[3];
-    for (int e = 0; e < 3; ++e) {
-      const double* L = lat + ld.off[3 * d + e];
-      lo[e] = L[ci[e]];
-      hi[e] = L[ci[e] + 1];
+    uint32_t live = 0;
+    int want = 0;
+    bool ok = true;
+    if (active) {
+      const int64_t tc = owner[p];
+      const int d = int(tc / n_t);
+      const int64_t t = tc - int64_t(d) * n_t;
+      const CellRange r = rng[tc];
+      const int64_t q = p - pair_off[tc];
+      const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
+                         r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+      for (int k = 0; k < 4; ++k) {
+        const int64_t v = tets[4 * t + k];
+        G.V[k][0] = X[3 * v + 0];
+        G.V[k][1] = X[3 * v + 1];
+        G.V[k][2] = X[3 * v + 2];
+      }
+      tet_geom(G);
+      for (int e = 0; e < 3; ++e) {
+        const double* L = lat + ld.off[3 * d + e];
+        lo[e] = L[ci[e]];
+        hi[e] = L[ci[e] + 1];
+      }
+      live = poly_init_tet(P, G.V, G.det < 0.0);
+      ok = poly_clip_box(P, live, lo, hi, G.mn, G.mx);
+      if (ok && pool) {
+        want = poly_fan_count(P, live);
+        if (want < 0) {
+          ok = false;
+          want = 0;
+        }
+      }
     }
-    double vol6;
-    T acc[32];
-    int nsub = 0;
-    const bool ok = clip_integrate<T>(P, G, lo, hi, vol6, acc, nsub);
-    ns += unsigned(nsub);
-    if (!ok) {
-      fail = true;
-      keep[p] = 0;
-      continue;
+    // one reservation per wave in the piece store
+    int incl = want;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
     }
-    const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
-    const double vol = vol6 * cv / 6.0;
-    const bool kp = vol > drop_rel * (fabs(G.det) / 6.0);
-    keep[p] = kp ? 1 : 0;
-    if (kp) {
-      ++nk;
-      const T sc = T(-cv / 6.0);
-      T* out = pval + p * 32;
+    const int wave_total = __shfl(incl, kWave - 1, kWave);
+    unsigned long long wbase = 0;
+    if (pool && wave_total > 0) {
+      if (lane == 0) wbase = atomicAdd(&counters[kCntPool], (unsigned long long)wave_total);
+      wbase = __shfl(wbase, 0, kWave);
+    }
+    if (active) {
+      const int64_t my = int64_t(wbase) + (incl - want);
+      const bool fits = pool && want > 0 && my + want <= pool_cap;
+      double vol6 = 0.0;
+      T acc[32];
+      int nsub = 0;
+      if (ok)
+        ok = integrate_piece<T>(P, live, G, lo, hi, vol6, acc, nsub,
+                                fits ? pool + my * kRecord : nullptr, want);
+      if (ok && fits && nsub != want) ok = false;
+      ns += unsigned(nsub);
+      if (!ok) {
+        fail = true;
+        keep[p] = 0;
+        if (pool) sub_cnt[p] = 0;
+      } else {
+        const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+        const double vol = vol6 * cv / 6.0;
+        const bool kp = vol > drop_rel * (fabs(G.det) / 6.0);
+        keep[p] = kp ? 1 : 0;
+        if (pool) {
+          sub_begin[p] = my;
+          sub_cnt[p] = (kp && fits) ? uint8_t(nsub) : 0;
+        }
+        if (kp) {
+          ++nk;
+          const T sc = T(-cv / 6.0);
+          T* out = pval + p * 32;
 #pragma unroll
-      for (int k = 0; k < 32; ++k) out[k] = acc[k] * sc;
-    } else if (vol > 0.0) {
-      ++nd;
+          for (int k = 0; k < 32; ++k) out[k] = acc[k] * sc;
+        } else if (vol > 0.0) {
+          ++nd;
+        }
+      }
     }
   }
   nk = wave_sum(nk);
@@ -280,28 +320,22 @@ __global__ __launch_bounds__(kWave) void k_clip(
 // row gather: one wavefront per (vertex, component)
 // ---------------------------------------------------------------------------
 
-template <typename T>
-struct RowOut {
-  const int64_t* rowptr[3];
-  int32_t* col[3];
-  T* val[3];
+// Node box of row (vertex i, component d): the union of the cell ranges of
+// the incident tets, as lo[3] and extent[3] (nodes); its size bounds the row.
+struct RowBox {
+  int32_t lo[3];
+  int32_t n[3];
 };
 
-template <typename T, bool FILL>
-__global__ __launch_bounds__(256) void k_rows(
-    int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
-    const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
-    const CellRange* __restrict__ rng, const int64_t* __restrict__ pair_off,
-    const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
-    int64_t* __restrict__ rownnz, RowOut<T> out) {
-  const int64_t wid = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const int lane = lane_id();
-  if (wid >= 3 * n_v) return;
-  const int d = int(wid / n_v);
-  const int64_t i = wid - int64_t(d) * n_v;
-  const int64_t beg = vt_ptr[i], end = vt_ptr[i + 1];
+__global__ void k_row_box(int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
+                          const int32_t* __restrict__ vt_tet, const CellRange* __restrict__ rng,
+                          RowBox* __restrict__ box, int64_t* __restrict__ cap) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= 3 * n_v) return;
+  const int d = int(w / n_v);
+  const int64_t i = w - int64_t(d) * n_v;
   int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
-  for (int64_t k = beg + lane; k < end; k += kWave) {
+  for (int64_t k = vt_ptr[i]; k < vt_ptr[i + 1]; ++k) {
     const CellRange r = rng[int64_t(d) * n_t + vt_tet[k]];
     if (int64_t(r.n[0]) * r.n[1] * r.n[2] == 0) continue;
     for (int e = 0; e < 3; ++e) {
@@ -309,19 +343,56 @@ __global__ __launch_bounds__(256) void k_rows(
       bmax[e] = max(bmax[e], r.lo[e] + r.n[e]);
     }
   }
+  RowBox b;
+  int64_t sz = 1;
   for (int e = 0; e < 3; ++e) {
-    bmin[e] = wave_min(bmin[e]);
-    bmax[e] = wave_max(bmax[e]);
+    b.lo[e] = bmin[e] <= bmax[e] ? bmin[e] : 0;
+    b.n[e] = bmin[e] <= bmax[e] ? bmax[e] - bmin[e] + 1 : 0;
+    sz *= b.n[e];
   }
-  if (bmin[0] > bmax[0]) {
-    if (!FILL && lane == 0) rownnz[wid] = 0;
-    return;
-  }
-  const int sx = bmax[0] - bmin[0] + 1, sy = bmax[1] - bmin[1] + 1, sz = bmax[2] - bmin[2] + 1;
-  const int64_t total = int64_t(sx) * sy * sz;
+  box[w] = b;
+  cap[w] = sz;
+}
+
+template <typename T>
+__device__ __forceinline__ T readlane_t(T v, int l);
+template <>
+__device__ __forceinline__ float readlane_t<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ double readlane_t<double>(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+  return __longlong_as_double((long long)((unsigned long long)(unsigned)lo |
+                                          ((unsigned long long)(unsigned)hi << 32)));
+}
+
+// Gather the pieces of the incident tets into the row's node box (kRowSlots
+// nodes per lane per pass, in a fixed order: incident tets ascending, then
+// cells), and write the touched nodes, column-sorted, at tmp_off[w].
+// Each incident tet's pairs are fetched across lanes in one step and
+// broadcast with readlane.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows(
+    int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
+    const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
+    const CellRange* __restrict__ rng, const int64_t* __restrict__ pair_off,
+    const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
+    const RowBox* __restrict__ box, const int64_t* __restrict__ tmp_off,
+    int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz) {
+  const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  if (w >= 3 * n_v) return;
+  const int d = int(w / n_v);
+  const int64_t i = w - int64_t(d) * n_v;
+  const RowBox b = box[w];
+  const int64_t total = int64_t(b.n[0]) * b.n[1] * b.n[2];
+  int64_t outpos = tmp_off[w];
+  const int64_t start = outpos;
   const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
-  int64_t outpos = FILL ? out.rowptr[d][i] : 0;
-  int64_t count = 0;
+  const int64_t beg = vt_ptr[i], end = vt_ptr[i + 1];
   for (int64_t c0 = 0; c0 < total; c0 += int64_t(kWave) * kRowSlots) {
     T acc[kRowSlots];
     int nx[kRowSlots], ny[kRowSlots], nz[kRowSlots];
@@ -331,11 +402,10 @@ __global__ __launch_bounds__(256) void k_rows(
       acc[rr] = T(0);
       const int64_t lin = c0 + int64_t(rr) * kWave + lane;
       if (lin < total) valid |= 1u << rr;
-      nx[rr] = bmin[0] + int(lin % sx);
-      ny[rr] = bmin[1] + int((lin / sx) % sy);
-      nz[rr] = bmin[2] + int(lin / (int64_t(sx) * sy));
+      nx[rr] = b.lo[0] + int(lin % b.n[0]);
+      ny[rr] = b.lo[1] + int((lin / b.n[0]) % b.n[1]);
+      nz[rr] = b.lo[2] + int(lin / (int64_t(b.n[0]) * b.n[1]));
     }
-    const int active = int(min<int64_t>(kRowSlots, ceil_div(total - c0, kWave)));
     for (int64_t k = beg; k < end; ++k) {
       const int64_t t = vt_tet[k];
       const int64_t tc = int64_t(d) * n_t + t;
@@ -346,20 +416,42 @@ __global__ __launch_bounds__(256) void k_rows(
       for (int q = 1; q < 4; ++q)
         if (tets[4 * t + q] == int32_t(i)) li = q;
       const int64_t base = pair_off[tc];
-      for (int q = 0; q < ncell; ++q) {
-        if (!keep[base + q]) continue;
-        const int cx = r.lo[0] + q % r.n[0];
-        const int cy = r.lo[1] + (q / r.n[0]) % r.n[1];
-        const int cz = r.lo[2] + q / (r.n[0] * r.n[1]);
-        const T* pv = pval + (base + q) * 32 + li * 8;
+      for (int q0 = 0; q0 < ncell; q0 += kWave) {
+        // lane l fetches pair q0 + l: keep flag and the 8 values of row li
+        const int ql = q0 + lane;
+        int kp = 0;
+        T v8[8];
+        if (ql < ncell) {
+          kp = keep[base + ql];
+          if (kp) {
+            const T* pv = pval + (base + ql) * 32 + li * 8;
 #pragma unroll
-        for (int rr = 0; rr < kRowSlots; ++rr) {
-          if (rr >= active) break;
-          const unsigned dx = unsigned(nx[rr] - cx), dy = unsigned(ny[rr] - cy),
-                         dz = unsigned(nz[rr] - cz);
-          if (((valid >> rr) & 1u) && dx <= 1u && dy <= 1u && dz <= 1u) {
-            touched |= 1u << rr;
-            if (FILL) acc[rr] += pv[dx + 2 * dy + 4 * dz];
+            for (int j = 0; j < 8; ++j) v8[j] = pv[j];
+          }
+        }
+        const uint64_t km = ballot64(kp != 0);
+        const int qn = min(kWave, ncell - q0);
+        for (int l = 0; l < qn; ++l) {
+          if (!((km >> l) & 1ull)) continue;
+          const int q = q0 + l;
+          const int cx = r.lo[0] + q % r.n[0];
+          const int cy = r.lo[1] + (q / r.n[0]) % r.n[1];
+          const int cz = r.lo[2] + q / (r.n[0] * r.n[1]);
+          T vb[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) vb[j] = readlane_t<T>(v8[j], l);
+#pragma unroll
+          for (int rr = 0; rr < kRowSlots; ++rr) {
+            const unsigned dx = unsigned(nx[rr] - cx), dy = unsigned(ny[rr] - cy),
+                           dz = unsigned(nz[rr] - cz);
+            if (((valid >> rr) & 1u) && dx <= 1u && dy <= 1u && dz <= 1u) {
+              touched |= 1u << rr;
+              const int corner = int(dx + 2 * dy + 4 * dz);
+              T v = vb[0];
+#pragma unroll
+              for (int j = 1; j < 8; ++j) v = (corner == j) ? vb[j] : v;
+              acc[rr] += v;
+            }
           }
         }
       }
@@ -368,75 +460,37 @@ __global__ __launch_bounds__(256) void k_rows(
     for (int rr = 0; rr < kRowSlots; ++rr) {
       const bool tch = (touched >> rr) & 1u;
       const uint64_t m = ballot64(tch);
-      if (FILL) {
-        if (tch) {
-          const int64_t pos = outpos + rank_below(m);
-          out.col[d][pos] = int32_t(nx[rr] + NX * (ny[rr] + NY * int64_t(nz[rr])));
-          out.val[d][pos] = acc[rr];
-        }
-        outpos += popc64(m);
-      } else {
-        count += popc64(m);
+      if (tch) {
+        const int64_t pos = outpos + rank_below(m);
+        tmp_col[pos] = int32_t(nx[rr] + NX * (ny[rr] + NY * int64_t(nz[rr])));
+        tmp_val[pos] = acc[rr];
       }
+      outpos += popc64(m);
     }
   }
-  if (!FILL && lane == 0) rownnz[wid] = count;
+  if (lane == 0) rownnz[w] = outpos - start;
 }
 
-// ---------------------------------------------------------------------------
-// transpose
-// ---------------------------------------------------------------------------
-
-__global__ void k_mark(int64_t nnz, const int32_t* __restrict__ col, int32_t* __restrict__ mark) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k < nnz) mark[col[k]] = 1;
-}
-
-__global__ void k_compact(int64_t n, const int32_t* __restrict__ mark,
-                          const int64_t* __restrict__ cidx, int32_t* __restrict__ rowmap) {
-  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j < n && mark[j]) rowmap[cidx[j]] = int32_t(j);
-}
-
-__global__ void k_tcount(int64_t nnz, const int32_t* __restrict__ col,
-                         const int64_t* __restrict__ cidx, unsigned long long* __restrict__ cnt) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k < nnz) atomicAdd(&cnt[cidx[col[k]]], 1ull);
-}
-
+// Copy each row from the box-capacity scratch into the CSR arrays.
 template <typename T>
-__global__ void k_tfill(int64_t n_rows, const int64_t* __restrict__ rowptr,
-                        const int32_t* __restrict__ col, const T* __restrict__ val,
-                        const int64_t* __restrict__ cidx, const int64_t* __restrict__ trowptr,
-                        unsigned long long* __restrict__ cur, int32_t* __restrict__ tcol,
-                        T* __restrict__ tval) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n_rows) return;
-  for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const int64_t r = cidx[col[k]];
-    const int64_t pos = trowptr[r] + int64_t(atomicAdd(&cur[r], 1ull));
-    tcol[pos] = int32_t(i);
-    tval[pos] = val[k];
-  }
-}
-
-template <typename T>
-__global__ void k_tsort(int64_t n_rows, const int64_t* __restrict__ ptr, int32_t* __restrict__ key,
-                        T* __restrict__ val) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n_rows) return;
-  const int64_t b = ptr[i], e = ptr[i + 1];
-  for (int64_t k = b + 1; k < e; ++k) {
-    const int32_t x = key[k];
-    const T v = val[k];
-    int64_t j = k - 1;
-    while (j >= b && key[j] > x) {
-      key[j + 1] = key[j];
-      val[j + 1] = val[j];
-      --j;
-    }
-    key[j + 1] = x;
-    val[j + 1] = v;
+__global__ __launch_bounds__(256) void k_rows_compact(
+    int64_t n_v, const int64_t* __restrict__ tmp_off, const int32_t* __restrict__ tmp_col,
+    const T* __restrict__ tmp_val, const int64_t* __restrict__ rp0,
+    const int64_t* __restrict__ rp1, const int64_t* __restrict__ rp2, int32_t* __restrict__ c0,
+    int32_t* __restrict__ c1, int32_t* __restrict__ c2, T* __restrict__ v0, T* __restrict__ v1,
+    T* __restrict__ v2) {
+  const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  if (w >= 3 * n_v) return;
+  const int d = int(w / n_v);
+  const int64_t i = w - int64_t(d) * n_v;
+  const int64_t* rp = d == 0 ? rp0 : (d == 1 ? rp1 : rp2);
+  int32_t* col = d == 0 ? c0 : (d == 1 ? c1 : c2);
+  T* val = d == 0 ? v0 : (d == 1 ? v1 : v2);
+  const int64_t src = tmp_off[w], dst = rp[i], n = rp[i + 1] - rp[i];
+  for (int64_t k = lane; k < n; k += kWave) {
+    col[dst + k] = tmp_col[src + k];
+    val[dst + k] = tmp_val[src + k];
   }
 }
 
@@ -511,45 +565,6 @@ int check_flags(ibvt_coupling* c, hipStream_t s) {
 }
 
 template <typename T>
-int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
-  const int64_t nf = c->n_fluid[d];
-  const ibvt::Csr& B = c->B[d];
-  ibvt::Csr& Bt = c->Bt[d];
-  int st;
-  if ((st = hip_check(hipMemsetAsync(c->mark.p, 0, size_t(nf) * sizeof(int32_t), s), "memset")))
-    return st;
-  if (B.nnz)
-    k_mark<<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, B.col.as<int32_t>(), c->mark.as<int32_t>());
-  if ((st = scan_i32_to_i64(c, c->mark.as<int32_t>(), c->cidx.as<int64_t>(), nf, s))) return st;
-  int64_t touched = 0;
-  if ((st = read_back(c, &touched, c->cidx.as<int64_t>() + nf, sizeof(int64_t), s))) return st;
-  Bt.nrows = touched;
-  Bt.nnz = B.nnz;
-  if ((st = ensure(c, Bt.rowptr, size_t(touched + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, Bt.rowmap, size_t(touched + 1) * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, Bt.col, size_t(B.nnz + 1) * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, Bt.val, size_t(B.nnz + 1) * sizeof(T)))) return st;
-  if ((st = ensure(c, c->tcount, size_t(touched + 1) * sizeof(int64_t)))) return st;
-  k_compact<<<blocks_for(nf, 256), 256, 0, s>>>(nf, c->mark.as<int32_t>(), c->cidx.as<int64_t>(),
-                                                Bt.rowmap.as<int32_t>());
-  auto* cnt = c->tcount.as<unsigned long long>();
-  if ((st = hip_check(hipMemsetAsync(cnt, 0, size_t(touched + 1) * sizeof(int64_t), s), "memset")))
-    return st;
-  if (B.nnz)
-    k_tcount<<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, B.col.as<int32_t>(),
-                                                    c->cidx.as<int64_t>(), cnt);
-  if ((st = scan_i64(c, c->tcount.as<int64_t>(), Bt.rowptr.as<int64_t>(), touched, s))) return st;
-  if ((st = hip_check(hipMemsetAsync(cnt, 0, size_t(touched + 1) * sizeof(int64_t), s), "memset")))
-    return st;
-  k_tfill<T><<<blocks_for(c->n_vert, 256), 256, 0, s>>>(
-      c->n_vert, B.rowptr.as<int64_t>(), B.col.as<int32_t>(), B.val.as<T>(), c->cidx.as<int64_t>(),
-      Bt.rowptr.as<int64_t>(), cnt, Bt.col.as<int32_t>(), Bt.val.as<T>());
-  k_tsort<T><<<blocks_for(touched, 256), 256, 0, s>>>(touched, Bt.rowptr.as<int64_t>(),
-                                                      Bt.col.as<int32_t>(), Bt.val.as<T>());
-  return hip_check(hipGetLastError(), "transpose launch");
-}
-
-template <typename T>
 int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
   int st;
@@ -580,6 +595,19 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 32 * sizeof(T)))) return st;
   k_owner<<<blocks_for(3 * n_t, 256), 256, 0, s>>>(3 * n_t, c->pair_off.as<int64_t>(),
                                                    c->owner.as<int32_t>());
+  // piece store: sub-tetrahedra of every kept piece, for the reverse mode
+  T* pool = nullptr;
+  if (c->store_pieces) {
+    const int64_t want = std::max<int64_t>(int64_t(3.0 * double(n_pairs)) + 1024,
+                                           c->pool_needed + c->pool_needed / 32 + 1024);
+    if (int64_t(c->pool.cap / (kRecord * sizeof(T))) < want &&
+        (st = ensure(c, c->pool, size_t(want) * kRecord * sizeof(T))))
+      return st;
+    if ((st = ensure(c, c->sub_begin, size_t(n_pairs + 1) * sizeof(int64_t)))) return st;
+    if ((st = ensure(c, c->sub_cnt, size_t(n_pairs + 1)))) return st;
+    c->pool_cap = int64_t(c->pool.cap / (kRecord * sizeof(T)));
+    pool = c->pool.as<T>();
+  }
   // (II)+(III) clip and integrate every pair
   if (n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(n_pairs, kWave), int64_t(1) << 22);
@@ -587,18 +615,35 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     k_clip<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
         n_pairs, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
         c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,
-        c->pval.as<T>(), c->keep.as<uint8_t>(), flags, counters);
+        c->pval.as<T>(), c->keep.as<uint8_t>(), pool, c->pool_cap,
+        pool ? c->sub_begin.as<int64_t>() : nullptr, pool ? c->sub_cnt.as<uint8_t>() : nullptr,
+        flags, counters);
   }
   if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
   // (IV) global assembly: rows of B^d
-  RowOut<T> ro{};
+  if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
+  if ((st = ensure(c, c->rowcap, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->rowtmpoff, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
+  {
+    ProfScope ps("rows_box", s);
+    k_row_box<<<blocks_for(3 * n_v, 256), 256, 0, s>>>(
+        n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->rng.as<CellRange>(),
+        c->rowbox.as<RowBox>(), c->rowcap.as<int64_t>());
+  }
+  if ((st = scan_i64(c, c->rowcap.as<int64_t>(), c->rowtmpoff.as<int64_t>(), 3 * n_v, s))) return st;
+  int64_t tmp_total = 0;
+  if ((st = read_back(c, &tmp_total, c->rowtmpoff.as<int64_t>() + 3 * n_v, sizeof(int64_t), s)))
+    return st;
+  if ((st = ensure(c, c->rowtmpcol, size_t(tmp_total + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->rowtmpval, size_t(tmp_total + 1) * sizeof(T)))) return st;
   const unsigned row_blocks = blocks_for(3 * n_v * kWave, 256);
   {
-    ProfScope ps("rows_count", s);
-    k_rows<T, false><<<row_blocks, 256, 0, s>>>(
+    ProfScope ps("rows_gather", s);
+    k_rows<T><<<row_blocks, 256, 0, s>>>(
         n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
         c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
-        c->ld, c->rownnz.as<int64_t>(), ro);
+        c->ld, c->rowbox.as<RowBox>(), c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(),
+        c->rowtmpval.as<T>(), c->rownnz.as<int64_t>());
   }
   if ((st = hip_check(hipGetLastError(), "rows launch"))) return st;
   for (int d = 0; d < 3; ++d) {
@@ -612,20 +657,20 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     if ((st = read_back(c, &nnz, c->B[d].rowptr.as<int64_t>() + n_v, sizeof(int64_t), s)))
       return st;
     c->B[d].nnz = nnz;
+    if (nnz >= (int64_t(1) << 31) - 1)
+      return set_error(IBVT_E_CAPACITY, "more than 2^31 nonzeros in one component of B");
     if ((st = ensure(c, c->B[d].col, size_t(nnz + 1) * sizeof(int32_t)))) return st;
     if ((st = ensure(c, c->B[d].val, size_t(nnz + 1) * sizeof(T)))) return st;
-    ro.rowptr[d] = c->B[d].rowptr.as<int64_t>();
-    ro.col[d] = c->B[d].col.as<int32_t>();
-    ro.val[d] = c->B[d].val.as<T>();
   }
   {
-    ProfScope ps("rows_fill", s);
-    k_rows<T, true><<<row_blocks, 256, 0, s>>>(
-        n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-        c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
-        c->ld, c->rownnz.as<int64_t>(), ro);
+    ProfScope ps("rows_compact", s);
+    k_rows_compact<T><<<row_blocks, 256, 0, s>>>(
+        n_v, c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(), c->rowtmpval.as<T>(),
+        c->B[0].rowptr.as<int64_t>(), c->B[1].rowptr.as<int64_t>(), c->B[2].rowptr.as<int64_t>(),
+        c->B[0].col.as<int32_t>(), c->B[1].col.as<int32_t>(), c->B[2].col.as<int32_t>(),
+        c->B[0].val.as<T>(), c->B[1].val.as<T>(), c->B[2].val.as<T>());
   }
-  if ((st = hip_check(hipGetLastError(), "rows fill launch"))) return st;
+  if ((st = hip_check(hipGetLastError(), "rows compact launch"))) return st;
   for (int d = 0; d < 3; ++d) {
     ProfScope ps("transpose", s);
     if ((st = transpose_one<T>(c, d, s))) return st;
@@ -652,6 +697,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   c->stats.dropped = int64_t(cnt[kCntDropped]);
   c->stats.zero_tets = int64_t(cnt[kCntZeroTets]);
   c->stats.subtets = int64_t(cnt[kCntSubtets]);
+  c->pool_needed = int64_t(cnt[kCntPool]);
+  c->pool_valid = c->store_pieces && c->pool_needed <= c->pool_cap;
   c->stats.assemblies += 1;
   return check_flags(c, s);
 }

@@ -20,6 +20,7 @@ enum Counter : int {
   kCntDropped = 1,
   kCntZeroTets = 2,
   kCntSubtets = 3,
+  kCntPool = 4,
   kCntSlots = 8,
 };
 

@@ -68,12 +68,17 @@ struct PolyView {
 // and 3 so that the stored one is positively oriented.
 __host__ __device__ inline uint32_t poly_init_tet(const PolyView& P, const double V[4][3],
                                                   bool flip) {
-  const int ord[4] = {0, 1, flip ? 3 : 2, flip ? 2 : 3};
-  for (int v = 0; v < 4; ++v) {
-    P.x(v) = V[ord[v]][0];
-    P.y(v) = V[ord[v]][1];
-    P.z(v) = V[ord[v]][2];
+  for (int v = 0; v < 2; ++v) {
+    P.x(v) = V[v][0];
+    P.y(v) = V[v][1];
+    P.z(v) = V[v][2];
   }
+  P.x(2) = flip ? V[3][0] : V[2][0];
+  P.y(2) = flip ? V[3][1] : V[2][1];
+  P.z(2) = flip ? V[3][2] : V[2][2];
+  P.x(3) = flip ? V[2][0] : V[3][0];
+  P.y(3) = flip ? V[2][1] : V[3][1];
+  P.z(3) = flip ? V[2][2] : V[3][2];
   P.nb(0) = nb_pack(1, 3, 2);
   P.nb(1) = nb_pack(2, 3, 0);
   P.nb(2) = nb_pack(0, 3, 1);
@@ -156,14 +161,46 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
   return true;
 }
 
-// Clip by the six planes of the box [lo, hi].
+// Clip by the six planes of the box [lo, hi].  mn/mx bound the original
+// tet: the piece never leaves them, so a plane the tet does not straddle is
+// skipped, and a box the tet only touches gives an empty piece.
 __host__ __device__ inline bool poly_clip_box(const PolyView& P, uint32_t& live, const double lo[3],
-                                              const double hi[3]) {
-  for (int a = 0; a < 3 && live; ++a) {
-    if (!poly_clip(P, live, a, lo[a], 1.0)) return false;
-    if (live && !poly_clip(P, live, a, hi[a], -1.0)) return false;
+                                              const double hi[3], const double mn[3],
+                                              const double mx[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (mx[a] <= lo[a] || mn[a] >= hi[a]) {
+      live = 0;
+      return true;
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (live && mn[a] < lo[a] && !poly_clip(P, live, a, lo[a], 1.0)) return false;
+    if (live && mx[a] > hi[a] && !poly_clip(P, live, a, hi[a], -1.0)) return false;
   }
   return true;
+}
+
+// Number of sub-tetrahedra poly_fan will emit: a 3-regular polyhedral graph
+// with V vertices has Σ_faces (deg − 2) = 2V − 4; faces through the apex
+// are skipped.  Returns -1 if a walk exceeds its bound.
+__host__ __device__ inline int poly_fan_count(const PolyView& P, uint32_t live) {
+  if (!live) return 0;
+  const int apex = ctz32(live);
+  int total = 2 * __builtin_popcount(live) - 4;
+  const uint32_t aw = P.nb(apex);
+  for (int k = 0; k < 3; ++k) {
+    int prev = apex, cur = nb_get(aw, k), deg = 1, guard = 0;
+    while (cur != apex) {
+      const uint32_t cw = P.nb(cur);
+      const int nxt = nb_get(cw, (nb_find(cw, prev) + 1) % 3);
+      prev = cur;
+      cur = nxt;
+      ++deg;
+      if (++guard > 3 * kMaxV) return -1;
+    }
+    total -= deg - 2;
+  }
+  return total;
 }
 
 // Call fn(apex, f0, f1, f2) for every sub-tetrahedron of the fan
@@ -329,9 +366,14 @@ struct TetGeom {
   double V[4][3];
   double det;      // e1 · (e2 × e3), e_k = V_k − V_0
   double g[4][3];  // ∇λ_i
+  double mn[3], mx[3];  // bounding box
 };
 
 __host__ __device__ inline void tet_geom(TetGeom& G) {
+  for (int a = 0; a < 3; ++a) {
+    G.mn[a] = fmin(fmin(G.V[0][a], G.V[1][a]), fmin(G.V[2][a], G.V[3][a]));
+    G.mx[a] = fmax(fmax(G.V[0][a], G.V[1][a]), fmax(G.V[2][a], G.V[3][a]));
+  }
   double e[3][3];
   for (int k = 0; k < 3; ++k)
     for (int a = 0; a < 3; ++a) e[k][a] = G.V[k + 1][a] - G.V[0][a];
@@ -354,29 +396,39 @@ __host__ __device__ inline void tet_geom(TetGeom& G) {
   }
 }
 
-// Clip tet ∩ box and integrate.  Returns false on a capacity/walk failure.
-// vol6 receives 6·|piece| in cell-local units (times the cell volume gives
-// 6|piece|), acc the 32 unscaled sums (caller scales by cellvol/6·(−1)).
+// λ_i in cell-local coordinates: λ_i(ξ) = λ_i(lo) + (∇λ_i ∘ h)·ξ.
 template <typename T>
-__host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom& G,
-                                               const double lo[3], const double hi[3],
-                                               double& vol6, T acc[32], int& nsub) {
-  for (int k = 0; k < 32; ++k) acc[k] = T(0);
-  vol6 = 0.0;
-  nsub = 0;
-  uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
-  if (!poly_clip_box(P, live, lo, hi)) return false;
-  if (!live) return true;
-  const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
-  const double h[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
-  // λ_i in cell-local coordinates: λ_i(ξ) = λ_i(lo) + (∇λ_i ∘ h)·ξ
-  T LA[4], LG[4][3];
+__host__ __device__ inline void cell_lambda(const TetGeom& G, const double lo[3], const double hi[3],
+                                            T LA[4], T LG[4][3]) {
   for (int i = 0; i < 4; ++i) {
     double a0 = (i == 0) ? 1.0 : 0.0;
     for (int e = 0; e < 3; ++e) a0 += G.g[i][e] * (lo[e] - G.V[0][e]);
     LA[i] = T(a0);
-    for (int e = 0; e < 3; ++e) LG[i][e] = T(G.g[i][e] * h[e]);
+    for (int e = 0; e < 3; ++e) LG[i][e] = T(G.g[i][e] * (hi[e] - lo[e]));
   }
+}
+
+// Sub-tetrahedron record of the piece store: 4 vertices (cell-local) and
+// the determinant, kRecord values of type T.
+constexpr int kRecord = 13;
+
+// Clip tet ∩ box and integrate.  Returns false on a capacity/walk failure.
+// vol6 receives 6·|piece| in cell-local units (times the cell volume gives
+// 6|piece|), acc the 32 unscaled sums (caller scales by cellvol/6·(−1)).
+// The piece must already be clipped (live = its vertex mask).  With rec
+// non-null, the first `cap` sub-tetrahedra are also written there.
+template <typename T>
+__host__ __device__ inline bool integrate_piece(const PolyView& P, uint32_t live, const TetGeom& G,
+                                                const double lo[3], const double hi[3],
+                                                double& vol6, T acc[32], int& nsub, T* rec,
+                                                int cap) {
+  for (int k = 0; k < 32; ++k) acc[k] = T(0);
+  vol6 = 0.0;
+  nsub = 0;
+  if (!live) return true;
+  const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
+  T LA[4], LG[4][3];
+  cell_lambda<T>(G, lo, hi, LA, LG);
   double vsum = 0.0;
   const bool ok = poly_fan(P, live, [&](int q0, int q1, int q2, int q3) {
     const int qs[4] = {q0, q1, q2, q3};
@@ -390,14 +442,33 @@ __host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom&
                        d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
                        d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
     vsum += det;
-    ++nsub;
     T y[4][3];
     for (int v = 0; v < 4; ++v)
       for (int e = 0; e < 3; ++e) y[v][e] = T(yd[v][e]);
+    if (rec && nsub < cap) {
+      T* r = rec + nsub * kRecord;
+      for (int v = 0; v < 4; ++v)
+        for (int e = 0; e < 3; ++e) r[v * 3 + e] = y[v][e];
+      r[12] = T(det);
+    }
+    ++nsub;
     subtet_integrate<T>(y, T(det), LA, LG, acc);
   });
   vol6 = -vsum;
   return ok;
+}
+
+template <typename T>
+__host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom& G,
+                                               const double lo[3], const double hi[3],
+                                               double& vol6, T acc[32], int& nsub) {
+  uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
+  if (!poly_clip_box(P, live, lo, hi, G.mn, G.mx)) {
+    vol6 = 0.0;
+    nsub = 0;
+    return false;
+  }
+  return integrate_piece<T>(P, live, G, lo, hi, vol6, acc, nsub, nullptr, 0);
 }
 
 // Clip tet ∩ box and call sub(y, det) for every sub-tetrahedron (cell-local
@@ -409,15 +480,9 @@ __host__ __device__ inline bool clip_fan_local(const PolyView& P, const TetGeom&
                                                T LG[4][3], double& vol6, F&& sub) {
   vol6 = 0.0;
   uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
-  if (!poly_clip_box(P, live, lo, hi)) return false;
+  if (!poly_clip_box(P, live, lo, hi, G.mn, G.mx)) return false;
   const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
-  const double h[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
-  for (int i = 0; i < 4; ++i) {
-    double a0 = (i == 0) ? 1.0 : 0.0;
-    for (int e = 0; e < 3; ++e) a0 += G.g[i][e] * (lo[e] - G.V[0][e]);
-    LA[i] = T(a0);
-    for (int e = 0; e < 3; ++e) LG[i][e] = T(G.g[i][e] * h[e]);
-  }
+  cell_lambda<T>(G, lo, hi, LA, LG);
   if (!live) return true;
   double vsum = 0.0;
   const bool ok = poly_fan(P, live, [&](int q0, int q1, int q2, int q3) {

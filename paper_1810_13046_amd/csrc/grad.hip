@@ -91,6 +91,73 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
 
+// Same terms from the piece store: the sub-tetrahedra written by the
+// assembly are integrated again with the new weights, no clipping.
+template <typename T>
+__global__ __launch_bounds__(256) void k_shape_pool(
+    int64_t n_pairs, int64_t n_t, int64_t n_v, const int32_t* __restrict__ owner,
+    const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
+    const uint8_t* __restrict__ keep, const T* __restrict__ pool,
+    const int64_t* __restrict__ sub_begin, const uint8_t* __restrict__ sub_cnt,
+    const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
+    LatDesc ld, const T* __restrict__ z, const T* u0, const T* u1, const T* u2,
+    T* __restrict__ pg) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  T* out = pg + p * 12;
+  const int cnt = keep[p] ? int(sub_cnt[p]) : 0;
+  if (cnt == 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[k] = T(0);
+    return;
+  }
+  const int64_t tc = owner[p];
+  const int d = int(tc / n_t);
+  const int64_t t = tc - int64_t(d) * n_t;
+  const CellRange r = rng[tc];
+  const int64_t q = p - pair_off[tc];
+  const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
+                     r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+  TetGeom G;
+  T zl[4];
+  for (int k = 0; k < 4; ++k) {
+    const int64_t v = tets[4 * t + k];
+    G.V[k][0] = X[3 * v + 0];
+    G.V[k][1] = X[3 * v + 1];
+    G.V[k][2] = X[3 * v + 2];
+    zl[k] = z[int64_t(d) * n_v + v];
+  }
+  tet_geom(G);
+  double lo[3], hi[3];
+  for (int e = 0; e < 3; ++e) {
+    const double* L = lat + ld.off[3 * d + e];
+    lo[e] = L[ci[e]];
+    hi[e] = L[ci[e] + 1];
+  }
+  const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
+  const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
+  T ul[8];
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a)
+        ul[a + 2 * b + 4 * c] = u[(ci[0] + a) + NX * ((ci[1] + b) + NY * int64_t(ci[2] + c))];
+  T LA[4], LG[4][3], A[12], Bs = T(0);
+  cell_lambda<T>(G, lo, hi, LA, LG);
+  for (int k = 0; k < 12; ++k) A[k] = T(0);
+  const T* rec = pool + sub_begin[p] * kRecord;
+  for (int sI = 0; sI < cnt; ++sI, rec += kRecord) {
+    T y[4][3];
+    for (int v = 0; v < 4; ++v)
+      for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
+    subtet_grad<T>(y, rec[12], LA, LG, zl, ul, A, Bs);
+  }
+  const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+  const double sc = -cv / 6.0;
+  for (int a = 0; a < 4; ++a)
+    for (int k = 0; k < 3; ++k)
+      out[a * 3 + k] = T(sc * (double(A[a * 3 + k]) / (hi[k] - lo[k]) + G.g[a][k] * double(Bs)));
+}
+
 // One wavefront per vertex a: lanes take (incident tet, component) items,
 // sum the pair terms and the mass term, then a fixed-order wave reduction.
 // mass: 0 lumped, 1 consistent, -1 none.
@@ -134,7 +201,11 @@ __global__ __launch_bounds__(256) void k_grad_gather(
         zu += zl[q] * ul[q];
       }
       const double s = (mass == 1) ? (zu + zs * uss) / 20.0 : zu / 4.0;
-      for (int e = 0; e < 3; ++e) g[e] -= vol * s * G.g[la][e];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const double ga = la == 0 ? G.g[0][e] : (la == 1 ? G.g[1][e] : (la == 2 ? G.g[2][e] : G.g[3][e]));
+        g[e] -= vol * s * ga;
+      }
     }
   }
   for (int e = 0; e < 3; ++e) g[e] = wave_sum(g[e]);
@@ -150,7 +221,15 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   T* pg = c->work2.as<T>();
   unsigned* flags = c->flags_dev.as<unsigned>();
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
-  if (c->n_pairs > 0) {
+  if (c->n_pairs > 0 && c->pool_valid) {
+    ProfScope ps("shape_pool", s);
+    k_shape_pool<T><<<unsigned(ceil_div(c->n_pairs, 256)), 256, 0, s>>>(
+        c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
+        c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pool.as<T>(),
+        c->sub_begin.as<int64_t>(), c->sub_cnt.as<uint8_t>(), c->X.as<double>(),
+        c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, static_cast<const T*>(z),
+        static_cast<const T*>(u[0]), static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg);
+  } else if (c->n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
     ProfScope ps("shape_pairs", s);
     k_shape_pairs<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(

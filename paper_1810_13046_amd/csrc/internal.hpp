@@ -62,11 +62,23 @@ struct ibvt_coupling {
   ibvt::DevBuf owner;        // int32 n_pairs
   ibvt::DevBuf pval;         // T n_pairs*32
   ibvt::DevBuf keep;         // uint8 n_pairs
+  bool store_pieces = true;  // keep the sub-tetrahedra of every piece
+  ibvt::DevBuf pool;         // T records of kRecord values
+  int64_t pool_cap = 0;      // records
+  int64_t pool_needed = 0;   // records the last assembly asked for
+  bool pool_valid = false;   // every kept piece of the last assembly is stored
+  ibvt::DevBuf sub_begin;    // int64 n_pairs: first record of the pair
+  ibvt::DevBuf sub_cnt;      // uint8 n_pairs: records of the pair
   ibvt::DevBuf rownnz;       // int64 3*n_vert
+  ibvt::DevBuf rowbox;       // node box per (vertex, component)
+  ibvt::DevBuf rowcap;       // int64 box size per row
+  ibvt::DevBuf rowtmpoff;    // int64 offsets into the row scratch
+  ibvt::DevBuf rowtmpcol;    // int32 row scratch columns
+  ibvt::DevBuf rowtmpval;    // T row scratch values
   ibvt::Csr B[3], Bt[3];
   ibvt::DevBuf mark;         // int32 max n_fluid (+1)
   ibvt::DevBuf cidx;         // int64 max n_fluid + 1
-  ibvt::DevBuf tcount;       // int64 max touched + 1 (counts / cursors)
+  ibvt::DevBuf tbuf;         // transpose sort scratch
   ibvt::DevBuf mlump;        // double n_vert
   ibvt::DevBuf minv;         // T n_vert
   bool has_M = false;
@@ -107,6 +119,10 @@ int scan_i32_to_i64(ibvt_coupling* c, const int32_t* in, int64_t* out, int64_t n
 // assemble.hip
 int build_topology(ibvt_coupling* c, hipStream_t s);
 int assemble_all(ibvt_coupling* c, hipStream_t s);
+
+// transpose.hip
+template <typename T>
+int transpose_one(ibvt_coupling* c, int d, hipStream_t s);
 
 // apply.hip
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s);

@@ -1,0 +1,133 @@
+// B^dT over the touched fluid nodes (the force transfer's operator).
+//
+// The touched fluid nodes are compacted with a prefix sum over the lattice;
+// the nonzeros of B^d, taken in their CSR order (row i ascending, then
+// column), are sorted by compacted column with a stable LSD radix sort, so
+// each row of B^dT lists its vertices in ascending order.  No value is
+// reduced and no position depends on timing: the result is deterministic.
+#include <hipcub/hipcub.hpp>
+
+#include "internal.hpp"
+
+namespace ibvt {
+
+namespace {
+
+__global__ void k_mark(int64_t nnz, const int32_t* __restrict__ col, int32_t* __restrict__ mark) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < nnz) mark[col[k]] = 1;
+}
+
+__global__ void k_compact(int64_t n, const int32_t* __restrict__ mark,
+                          const int64_t* __restrict__ cidx, int32_t* __restrict__ rowmap) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n && mark[j]) rowmap[cidx[j]] = int32_t(j);
+}
+
+// keys[k] = compacted column of nonzero k; idx[k] = k; row[k] = its row.
+__global__ void k_keys(int64_t n_rows, const int64_t* __restrict__ rowptr,
+                       const int32_t* __restrict__ col, const int64_t* __restrict__ cidx,
+                       int32_t* __restrict__ keys, int32_t* __restrict__ idx,
+                       int32_t* __restrict__ row) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    keys[k] = int32_t(cidx[col[k]]);
+    idx[k] = int32_t(k);
+    row[k] = int32_t(i);
+  }
+}
+
+template <typename T>
+__global__ void k_tgather(int64_t nnz, const int32_t* __restrict__ skeys,
+                          const int32_t* __restrict__ perm, const int32_t* __restrict__ row,
+                          const T* __restrict__ val, int32_t* __restrict__ tcol,
+                          T* __restrict__ tval, int64_t* __restrict__ trowptr) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t k = perm[p];
+  tcol[p] = row[k];
+  tval[p] = val[k];
+  // every compacted row has at least one entry, so a row starts where the
+  // sorted key changes
+  if (p == 0 || skeys[p] != skeys[p - 1]) trowptr[skeys[p]] = p;
+  if (p == nnz - 1) trowptr[int64_t(skeys[p]) + 1] = nnz;
+}
+
+inline unsigned blocks_for(int64_t n, int threads) {
+  return unsigned(ceil_div(n > 0 ? n : 1, threads));
+}
+
+int end_bit_for(int64_t n) {
+  int b = 1;
+  while ((int64_t(1) << b) < n + 1) ++b;
+  return b;
+}
+
+}  // namespace
+
+template <typename T>
+int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
+  const int64_t nf = c->n_fluid[d];
+  const Csr& B = c->B[d];
+  Csr& Bt = c->Bt[d];
+  int st;
+  if ((st = hip_check(hipMemsetAsync(c->mark.p, 0, size_t(nf) * sizeof(int32_t), s), "memset")))
+    return st;
+  if (B.nnz)
+    k_mark<<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, B.col.as<int32_t>(), c->mark.as<int32_t>());
+  if ((st = scan_i32_to_i64(c, c->mark.as<int32_t>(), c->cidx.as<int64_t>(), nf, s))) return st;
+  int64_t touched = 0;
+  if ((st = hip_check(hipMemcpyAsync(&touched, c->cidx.as<int64_t>() + nf, sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, s),
+                      "read touched")))
+    return st;
+  if ((st = hip_check(hipStreamSynchronize(s), "sync"))) return st;
+  Bt.nrows = touched;
+  Bt.nnz = B.nnz;
+  if ((st = ensure(c, Bt.rowptr, size_t(touched + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, Bt.rowmap, size_t(touched + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, Bt.col, size_t(B.nnz + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, Bt.val, size_t(B.nnz + 1) * sizeof(T)))) return st;
+  k_compact<<<blocks_for(nf, 256), 256, 0, s>>>(nf, c->mark.as<int32_t>(), c->cidx.as<int64_t>(),
+                                                Bt.rowmap.as<int32_t>());
+  if (B.nnz == 0) {
+    int64_t z = 0;
+    return hip_check(hipMemcpyAsync(Bt.rowptr.p, &z, sizeof(z), hipMemcpyHostToDevice, s),
+                     "rowptr");
+  }
+  // sort scratch: keys in/out, index in/out, row of each nonzero, cub temp
+  const int end_bit = end_bit_for(touched);
+  size_t temp_bytes = 0;
+  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(
+                          nullptr, temp_bytes, static_cast<const int32_t*>(nullptr),
+                          static_cast<int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                          static_cast<int32_t*>(nullptr), int(B.nnz), 0, end_bit, s),
+                      "sort size")))
+    return st;
+  const size_t n4 = (size_t(B.nnz) * sizeof(int32_t) + 255) & ~size_t(255);
+  if ((st = ensure(c, c->tbuf, 5 * n4 + temp_bytes + 256))) return st;
+  char* base = c->tbuf.as<char>();
+  int32_t* keys = reinterpret_cast<int32_t*>(base);
+  int32_t* skeys = reinterpret_cast<int32_t*>(base + n4);
+  int32_t* idx = reinterpret_cast<int32_t*>(base + 2 * n4);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + 3 * n4);
+  int32_t* row = reinterpret_cast<int32_t*>(base + 4 * n4);
+  void* temp = base + 5 * n4;
+  k_keys<<<blocks_for(c->n_vert, 256), 256, 0, s>>>(c->n_vert, B.rowptr.as<int64_t>(),
+                                                    B.col.as<int32_t>(), c->cidx.as<int64_t>(),
+                                                    keys, idx, row);
+  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx, perm,
+                                                         int(B.nnz), 0, end_bit, s),
+                      "radix sort")))
+    return st;
+  k_tgather<T><<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, skeys, perm, row, B.val.as<T>(),
+                                                      Bt.col.as<int32_t>(), Bt.val.as<T>(),
+                                                      Bt.rowptr.as<int64_t>());
+  return hip_check(hipGetLastError(), "transpose launch");
+}
+
+template int transpose_one<float>(ibvt_coupling*, int, hipStream_t);
+template int transpose_one<double>(ibvt_coupling*, int, hipStream_t);
+
+}  // namespace ibvt

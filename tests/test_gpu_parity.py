@@ -33,13 +33,13 @@ def ref(name):
     return _cache[name]
 
 
-def make(name, prec, dev, consistent=True):
+def make(name, prec, dev, consistent=True, store_pieces=True):
     import torch
     from paper_1810_13046_amd import Coupling
     W, _ = ref(name)
-    say(f"[gpu] assemble {name} {prec} n_tet={W.tets.shape[0]}")
+    say(f"[gpu] assemble {name} {prec} n_tet={W.tets.shape[0]} store={store_pieces}")
     c = Coupling(W.faces, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
-                 precision=prec, consistent=consistent)
+                 precision=prec, consistent=consistent, store_pieces=store_pieces)
     torch.cuda.synchronize()
     return c
 
@@ -128,13 +128,15 @@ def test_transfers_match_oracle(dev, name, prec):
     c.free()
 
 
+@pytest.mark.parametrize("store", [True, False])
 @pytest.mark.parametrize("mass", ["lumped", "consistent"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_velocity_vjp_matches_oracle(dev, mass, prec):
+def test_velocity_vjp_matches_oracle(dev, mass, prec, store):
     import torch
     name = "plate4320_grid256s_tilted" if prec == "fp64" else "beam144_grid32"
     W, R = ref(name)
-    c = make(name, prec, dev)
+    c = make(name, prec, dev, store_pieces=store)
+    assert c.info()["piece_store"] == store
     dt = c.dtype
     u_f = fluid_fields(W)
     ud = [to_dev(u, dt, dev) for u in u_f]
