@@ -205,7 +205,11 @@ def main():
     ap.add_argument("--workload", type=int, default=5, help=argparse.SUPPRESS)
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 step")
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the oracle")
-    ap.add_argument("--cpu-tets-per-body", type=int, default=1000)
+    ap.add_argument("--cpu-tets-per-body", type=int, default=8000)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="one mixed-precision step and the applies only (for rocprofv3)")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the transfer is built and timed on a single MI355X; "
@@ -216,8 +220,20 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * (1 << 30) / 8)
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}))
+        return
     from paper_1810_13046_amd import load_library
     load_library()
+    if args.profile_run:
+        args.skip_fp64 = True
+        args.skip_cpu = True
 
     W, X, T, u64, f_s, u_t = make_inputs(args.workload, dev)
     n_tet = W.tets.shape[0]

@@ -204,14 +204,47 @@ __global__ void k_owner(int64_t n_tc, const int64_t* __restrict__ off, int32_t* 
 // clip + integrate, one lane per (tet, component, cell) pair
 // ---------------------------------------------------------------------------
 
+// Pair geometry shared by the clip and integration kernels.
+__device__ __forceinline__ void pair_geometry(int64_t p, int64_t n_t, const int32_t* owner,
+                                              const int64_t* pair_off, const CellRange* rng,
+                                              const double* X, const int32_t* tets,
+                                              const double* lat, const LatDesc& ld, int& d,
+                                              int64_t& t, int ci[3], TetGeom& G, double lo[3],
+                                              double hi[3]) {
+  const int64_t tc = owner[p];
+  d = int(tc / n_t);
+  t = tc - int64_t(d) * n_t;
+  const CellRange r = rng[tc];
+  const int64_t q = p - pair_off[tc];
+  ci[0] = r.lo[0] + int(q % r.n[0]);
+  ci[1] = r.lo[1] + int((q / r.n[0]) % r.n[1]);
+  ci[2] = r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]));
+  for (int k = 0; k < 4; ++k) {
+    const int64_t v = tets[4 * t + k];
+    G.V[k][0] = X[3 * v + 0];
+    G.V[k][1] = X[3 * v + 1];
+    G.V[k][2] = X[3 * v + 2];
+  }
+  tet_geom(G);
+  for (int e = 0; e < 3; ++e) {
+    const double* L = lat + ld.off[3 * d + e];
+    lo[e] = L[ci[e]];
+    hi[e] = L[ci[e] + 1];
+  }
+}
+
+// Clip every (tet, component, cell) pair in double, one lane per pair, and
+// store the fan sub-tetrahedra of the piece.  A wave reserves one
+// contiguous block of the store, so the records of the 64 pairs of a wave
+// are contiguous and in pair order.
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_clip(
     int64_t n_pairs, int64_t n_t, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
     const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
-    LatDesc ld, double drop_rel, T* __restrict__ pval, uint8_t* __restrict__ keep,
-    T* __restrict__ pool, int64_t pool_cap, int64_t* __restrict__ sub_begin,
-    uint8_t* __restrict__ sub_cnt, unsigned* flags, unsigned long long* counters) {
+    LatDesc ld, double drop_rel, uint8_t* __restrict__ keep, T* __restrict__ pool,
+    int64_t pool_cap, int64_t* __restrict__ sub_begin, uint8_t* __restrict__ sub_cnt,
+    unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
   __shared__ uint32_t snb[kMaxV * kWave];
   const int lane = threadIdx.x;
@@ -227,28 +260,12 @@ __global__ __launch_bounds__(kWave) void k_clip(
     int want = 0;
     bool ok = true;
     if (active) {
-      const int64_t tc = owner[p];
-      const int d = int(tc / n_t);
-      const int64_t t = tc - int64_t(d) * n_t;
-      const CellRange r = rng[tc];
-      const int64_t q = p - pair_off[tc];
-      const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
-                         r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
-      for (int k = 0; k < 4; ++k) {
-        const int64_t v = tets[4 * t + k];
-        G.V[k][0] = X[3 * v + 0];
-        G.V[k][1] = X[3 * v + 1];
-        G.V[k][2] = X[3 * v + 2];
-      }
-      tet_geom(G);
-      for (int e = 0; e < 3; ++e) {
-        const double* L = lat + ld.off[3 * d + e];
-        lo[e] = L[ci[e]];
-        hi[e] = L[ci[e] + 1];
-      }
+      int d, ci[3];
+      int64_t t;
+      pair_geometry(p, n_t, owner, pair_off, rng, X, tets, lat, ld, d, t, ci, G, lo, hi);
       live = poly_init_tet(P, G.V, G.det < 0.0);
       ok = poly_clip_box(P, live, lo, hi, G.mn, G.mx);
-      if (ok && pool) {
+      if (ok) {
         want = poly_fan_count(P, live);
         if (want < 0) {
           ok = false;
@@ -256,7 +273,6 @@ __global__ __launch_bounds__(kWave) void k_clip(
         }
       }
     }
-    // one reservation per wave in the piece store
     int incl = want;
     for (int o = 1; o < kWave; o <<= 1) {
       const int y = __shfl_up(incl, o, kWave);
@@ -264,43 +280,33 @@ __global__ __launch_bounds__(kWave) void k_clip(
     }
     const int wave_total = __shfl(incl, kWave - 1, kWave);
     unsigned long long wbase = 0;
-    if (pool && wave_total > 0) {
+    if (wave_total > 0) {
       if (lane == 0) wbase = atomicAdd(&counters[kCntPool], (unsigned long long)wave_total);
       wbase = __shfl(wbase, 0, kWave);
     }
     if (active) {
       const int64_t my = int64_t(wbase) + (incl - want);
-      const bool fits = pool && want > 0 && my + want <= pool_cap;
+      const bool fits = my + want <= pool_cap;
       double vol6 = 0.0;
-      T acc[32];
       int nsub = 0;
-      if (ok)
-        ok = integrate_piece<T>(P, live, G, lo, hi, vol6, acc, nsub,
-                                fits ? pool + my * kRecord : nullptr, want);
-      if (ok && fits && nsub != want) ok = false;
+      if (ok && want > 0)
+        ok = emit_subtets<T>(P, live, lo, hi, fits ? pool + my * kRecord : nullptr, want, vol6,
+                             nsub);
+      if (ok && nsub != want) ok = false;
       ns += unsigned(nsub);
       if (!ok) {
         fail = true;
         keep[p] = 0;
-        if (pool) sub_cnt[p] = 0;
+        sub_cnt[p] = 0;
       } else {
         const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
         const double vol = vol6 * cv / 6.0;
         const bool kp = vol > drop_rel * (fabs(G.det) / 6.0);
         keep[p] = kp ? 1 : 0;
-        if (pool) {
-          sub_begin[p] = my;
-          sub_cnt[p] = (kp && fits) ? uint8_t(nsub) : 0;
-        }
-        if (kp) {
-          ++nk;
-          const T sc = T(-cv / 6.0);
-          T* out = pval + p * 32;
-#pragma unroll
-          for (int k = 0; k < 32; ++k) out[k] = acc[k] * sc;
-        } else if (vol > 0.0) {
-          ++nd;
-        }
+        sub_begin[p] = my;
+        sub_cnt[p] = kp ? uint8_t(nsub) : 0;
+        if (kp) ++nk;
+        else if (vol > 0.0) ++nd;
       }
     }
   }
@@ -313,6 +319,103 @@ __global__ __launch_bounds__(kWave) void k_clip(
     if (nd) atomicAdd(&counters[kCntDropped], nd);
     if (ns) atomicAdd(&counters[kCntSubtets], ns);
     if (fm) atomicOr(flags, kFlagCapacity);
+  }
+}
+
+// One wave per group of 64 consecutive pairs, whose records are contiguous:
+// records are taken one per lane (balanced whatever the count per pair) and
+// summed per pair in record order through LDS (deterministic).  Returns,
+// for the group's dense record index s, the owning lane (largest j with
+// excl_j <= s, excl = exclusive prefix of the per-pair counts).
+__device__ __forceinline__ int owner_lane(int excl, int s) {
+  int lo = 0, hi = kWave - 1;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int e = __shfl(excl, mid, kWave);
+    if (e <= s) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// (III) integrate λ_i N_j on every stored sub-tetrahedron and sum per pair
+// into pval[i][pair][j] (local-vertex major: each vertex row of a pair is 8
+// contiguous values).
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_integrate(
+    int64_t n_pairs, int64_t n_t, const int32_t* __restrict__ owner,
+    const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
+    const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
+    LatDesc ld, const uint8_t* __restrict__ keep, const T* __restrict__ pool,
+    const int64_t* __restrict__ sub_begin, const uint8_t* __restrict__ sub_cnt,
+    T* __restrict__ pval) {
+  __shared__ T red[kWave][33];
+  __shared__ int rown[kWave];
+  __shared__ int rlast[kWave];
+  const int lane = threadIdx.x;
+  const int64_t g0 = int64_t(blockIdx.x) * kWave;
+  const int64_t pj = g0 + lane;
+  int cnt = 0;
+  int64_t beg = 0;
+  if (pj < n_pairs && keep[pj]) {
+    cnt = sub_cnt[pj];
+    beg = sub_begin[pj];
+  }
+  int incl = cnt;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const int excl = incl - cnt;
+  const int total = __shfl(incl, kWave - 1, kWave);
+  T run = T(0);
+  const int64_t plane = n_pairs * 8;
+  for (int s0 = 0; s0 < total; s0 += kWave) {
+    const int s = s0 + lane;
+    const int j = owner_lane(excl, s);
+    const int ex_j = __shfl(excl, j, kWave);
+    const int in_j = __shfl(incl, j, kWave);
+    const long long bj = __shfl((long long)beg, j, kWave);
+    T acc[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[k] = T(0);
+    if (s < total) {
+      int d, ci[3];
+      int64_t t;
+      TetGeom G;
+      double lo[3], hi[3];
+      pair_geometry(g0 + j, n_t, owner, pair_off, rng, X, tets, lat, ld, d, t, ci, G, lo, hi);
+      T LA[4], LG[4][3];
+      cell_lambda<T>(G, lo, hi, LA, LG);
+      const T* rec = pool + (int64_t(bj) + (s - ex_j)) * kRecord;
+      T y[4][3];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
+      subtet_integrate<T>(y, rec[12], LA, LG, acc);
+      const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
+#pragma unroll
+      for (int k = 0; k < 32; ++k) acc[k] *= sc;
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) red[lane][k] = acc[k];
+    rown[lane] = j;
+    rlast[lane] = (s < total) && (s + 1 == in_j);
+    __syncthreads();
+    if (lane < 32) {
+      const int rows = min(kWave, total - s0);
+      const int64_t vbase = int64_t(lane >> 3) * plane + (lane & 7);
+      for (int r = 0; r < rows; ++r) {
+        run += red[r][lane];
+        if (rlast[r]) {
+          pval[vbase + (g0 + rown[r]) * 8] = run;
+          run = T(0);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -376,7 +479,7 @@ __device__ __forceinline__ double readlane_t<double>(double v, int l) {
 // broadcast with readlane.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
-    int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
+    int64_t n_v, int64_t n_t, int64_t n_pairs, const int64_t* __restrict__ vt_ptr,
     const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
     const CellRange* __restrict__ rng, const int64_t* __restrict__ pair_off,
     const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
@@ -424,7 +527,7 @@ __global__ __launch_bounds__(256) void k_rows(
         if (ql < ncell) {
           kp = keep[base + ql];
           if (kp) {
-            const T* pv = pval + (base + ql) * 32 + li * 8;
+            const T* pv = pval + int64_t(li) * n_pairs * 8 + (base + ql) * 8;
 #pragma unroll
             for (int j = 0; j < 8; ++j) v8[j] = pv[j];
           }
@@ -595,31 +698,50 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 32 * sizeof(T)))) return st;
   k_owner<<<blocks_for(3 * n_t, 256), 256, 0, s>>>(3 * n_t, c->pair_off.as<int64_t>(),
                                                    c->owner.as<int32_t>());
-  // piece store: sub-tetrahedra of every kept piece, for the reverse mode
-  T* pool = nullptr;
-  if (c->store_pieces) {
+  // piece store: the fan sub-tetrahedra of every kept piece (integrated
+  // below, and again by the reverse mode)
+  if ((st = ensure(c, c->sub_begin, size_t(n_pairs + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->sub_cnt, size_t(n_pairs + 1)))) return st;
+  for (int attempt = 0; attempt < 2; ++attempt) {
     const int64_t want = std::max<int64_t>(int64_t(3.0 * double(n_pairs)) + 1024,
                                            c->pool_needed + c->pool_needed / 32 + 1024);
     if (int64_t(c->pool.cap / (kRecord * sizeof(T))) < want &&
         (st = ensure(c, c->pool, size_t(want) * kRecord * sizeof(T))))
       return st;
-    if ((st = ensure(c, c->sub_begin, size_t(n_pairs + 1) * sizeof(int64_t)))) return st;
-    if ((st = ensure(c, c->sub_cnt, size_t(n_pairs + 1)))) return st;
     c->pool_cap = int64_t(c->pool.cap / (kRecord * sizeof(T)));
-    pool = c->pool.as<T>();
+    // clear pieces/dropped and subtets/store counters (zero-tet count stays)
+    if ((st = hip_check(hipMemsetAsync(counters + kCntPieces, 0, 2 * sizeof(unsigned long long), s),
+                        "memset")) ||
+        (st = hip_check(hipMemsetAsync(counters + kCntSubtets, 0, 2 * sizeof(unsigned long long), s),
+                        "memset")))
+      return st;
+    // (II) clip every pair
+    if (n_pairs > 0) {
+      const int64_t nb = std::min<int64_t>(ceil_div(n_pairs, kWave), int64_t(1) << 22);
+      ProfScope ps("clip", s);
+      k_clip<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
+          n_pairs, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
+          c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,
+          c->keep.as<uint8_t>(), c->pool.as<T>(), c->pool_cap, c->sub_begin.as<int64_t>(),
+          c->sub_cnt.as<uint8_t>(), flags, counters);
+    }
+    if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
+    unsigned long long used = 0;
+    if ((st = read_back(c, &used, counters + kCntPool, sizeof(used), s))) return st;
+    c->pool_needed = int64_t(used);
+    if (c->pool_needed <= c->pool_cap) break;
+    if (attempt == 1) return set_error(IBVT_E_CAPACITY, "piece store could not be sized");
   }
-  // (II)+(III) clip and integrate every pair
+  // (III) integrate every stored sub-tetrahedron, summed per pair
   if (n_pairs > 0) {
-    const int64_t nb = std::min<int64_t>(ceil_div(n_pairs, kWave), int64_t(1) << 22);
-    ProfScope ps("clip_integrate", s);
-    k_clip<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
+    ProfScope ps("integrate", s);
+    k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
         n_pairs, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
-        c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,
-        c->pval.as<T>(), c->keep.as<uint8_t>(), pool, c->pool_cap,
-        pool ? c->sub_begin.as<int64_t>() : nullptr, pool ? c->sub_cnt.as<uint8_t>() : nullptr,
-        flags, counters);
+        c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld,
+        c->keep.as<uint8_t>(), c->pool.as<T>(), c->sub_begin.as<int64_t>(),
+        c->sub_cnt.as<uint8_t>(), c->pval.as<T>());
   }
-  if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
+  if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
   // (IV) global assembly: rows of B^d
   if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
   if ((st = ensure(c, c->rowcap, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
@@ -640,7 +762,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   {
     ProfScope ps("rows_gather", s);
     k_rows<T><<<row_blocks, 256, 0, s>>>(
-        n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+        n_v, n_t, n_pairs, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
         c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
         c->ld, c->rowbox.as<RowBox>(), c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(),
         c->rowtmpval.as<T>(), c->rownnz.as<int64_t>());
@@ -697,8 +819,13 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   c->stats.dropped = int64_t(cnt[kCntDropped]);
   c->stats.zero_tets = int64_t(cnt[kCntZeroTets]);
   c->stats.subtets = int64_t(cnt[kCntSubtets]);
-  c->pool_needed = int64_t(cnt[kCntPool]);
   c->pool_valid = c->store_pieces && c->pool_needed <= c->pool_cap;
+  if (!c->store_pieces) {
+    // memory-saving mode: the reverse mode clips again
+    if ((st = hip_check(hipStreamSynchronize(s), "sync"))) return st;
+    release(c, c->pool);
+    c->pool_cap = 0;
+  }
   c->stats.assemblies += 1;
   return check_flags(c, s);
 }

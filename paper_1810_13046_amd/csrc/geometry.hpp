@@ -458,6 +458,42 @@ __host__ __device__ inline bool integrate_piece(const PolyView& P, uint32_t live
   return ok;
 }
 
+// Write the fan's sub-tetrahedra of a clipped piece as records (cell-local
+// coordinates and determinant, rounded to T) at rec (up to cap of them);
+// vol6 receives the piece's 6·volume in cell-local units (double).
+template <typename T>
+__host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, const double lo[3],
+                                             const double hi[3], T* rec, int cap, double& vol6,
+                                             int& nsub) {
+  vol6 = 0.0;
+  nsub = 0;
+  if (!live) return true;
+  const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
+  double vsum = 0.0;
+  const bool ok = poly_fan(P, live, [&](int q0, int q1, int q2, int q3) {
+    const int qs[4] = {q0, q1, q2, q3};
+    double yd[4][3];
+    for (int v = 0; v < 4; ++v)
+      for (int e = 0; e < 3; ++e) yd[v][e] = (P.co(qs[v], e) - lo[e]) * ih[e];
+    double d[3][3];
+    for (int v = 0; v < 3; ++v)
+      for (int e = 0; e < 3; ++e) d[v][e] = yd[v + 1][e] - yd[0][e];
+    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+    vsum += det;
+    if (rec && nsub < cap) {
+      T* r = rec + nsub * kRecord;
+      for (int v = 0; v < 4; ++v)
+        for (int e = 0; e < 3; ++e) r[v * 3 + e] = T(yd[v][e]);
+      r[12] = T(det);
+    }
+    ++nsub;
+  });
+  vol6 = -vsum;
+  return ok;
+}
+
 template <typename T>
 __host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom& G,
                                                const double lo[3], const double hi[3],

@@ -92,9 +92,23 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
 }
 
 // Same terms from the piece store: the sub-tetrahedra written by the
-// assembly are integrated again with the new weights, no clipping.
+// assembly are integrated again with the new weights, without clipping.
+// One wave per group of 64 consecutive pairs (their records are
+// contiguous); one record per lane, per-pair sums in record order (LDS).
+__device__ __forceinline__ int owner_lane_g(int excl, int s) {
+  int lo = 0, hi = kWave - 1;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int e = __shfl(excl, mid, kWave);
+    if (e <= s) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_shape_pool(
+__global__ __launch_bounds__(kWave) void k_shape_pool(
     int64_t n_pairs, int64_t n_t, int64_t n_v, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
     const uint8_t* __restrict__ keep, const T* __restrict__ pool,
@@ -102,60 +116,107 @@ __global__ __launch_bounds__(256) void k_shape_pool(
     const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
     LatDesc ld, const T* __restrict__ z, const T* u0, const T* u1, const T* u2,
     T* __restrict__ pg) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  T* out = pg + p * 12;
-  const int cnt = keep[p] ? int(sub_cnt[p]) : 0;
-  if (cnt == 0) {
+  __shared__ T red[kWave][13];
+  __shared__ int rown[kWave];
+  __shared__ int rlast[kWave];
+  const int lane = threadIdx.x;
+  const int64_t g0 = int64_t(blockIdx.x) * kWave;
+  const int64_t pj = g0 + lane;
+  int cnt = 0;
+  int64_t beg = 0;
+  if (pj < n_pairs) {
+    if (keep[pj]) {
+      cnt = sub_cnt[pj];
+      beg = sub_begin[pj];
+    }
+    if (cnt == 0)
+      for (int k = 0; k < 12; ++k) pg[pj * 12 + k] = T(0);
+  }
+  int incl = cnt;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const int excl = incl - cnt;
+  const int total = __shfl(incl, kWave - 1, kWave);
+  T run = T(0);
+  for (int s0 = 0; s0 < total; s0 += kWave) {
+    const int s = s0 + lane;
+    const int j = owner_lane_g(excl, s);
+    const int ex_j = __shfl(excl, j, kWave);
+    const int in_j = __shfl(incl, j, kWave);
+    const long long bj = __shfl((long long)beg, j, kWave);
+    T out[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) out[k] = T(0);
-    return;
+    if (s < total) {
+      const int64_t p = g0 + j;
+      const int64_t tc = owner[p];
+      const int d = int(tc / n_t);
+      const int64_t t = tc - int64_t(d) * n_t;
+      const CellRange r = rng[tc];
+      const int64_t q = p - pair_off[tc];
+      const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
+                         r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+      TetGeom G;
+      T zl[4];
+      for (int k = 0; k < 4; ++k) {
+        const int64_t v = tets[4 * t + k];
+        G.V[k][0] = X[3 * v + 0];
+        G.V[k][1] = X[3 * v + 1];
+        G.V[k][2] = X[3 * v + 2];
+        zl[k] = z[int64_t(d) * n_v + v];
+      }
+      tet_geom(G);
+      double lo[3], hi[3];
+      for (int e = 0; e < 3; ++e) {
+        const double* L = lat + ld.off[3 * d + e];
+        lo[e] = L[ci[e]];
+        hi[e] = L[ci[e] + 1];
+      }
+      const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
+      const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
+      T ul[8];
+      for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+          for (int a = 0; a < 2; ++a)
+            ul[a + 2 * b + 4 * c] = u[(ci[0] + a) + NX * ((ci[1] + b) + NY * int64_t(ci[2] + c))];
+      T LA[4], LG[4][3], A[12], Bs = T(0);
+      cell_lambda<T>(G, lo, hi, LA, LG);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) A[k] = T(0);
+      const T* rec = pool + (int64_t(bj) + (s - ex_j)) * kRecord;
+      T y[4][3];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
+      subtet_grad<T>(y, rec[12], LA, LG, zl, ul, A, Bs);
+      const double sc = -(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          out[a * 3 + k] =
+              T(sc * (double(A[a * 3 + k]) / (hi[k] - lo[k]) + G.g[a][k] * double(Bs)));
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[lane][k] = out[k];
+    rown[lane] = j;
+    rlast[lane] = (s < total) && (s + 1 == in_j);
+    __syncthreads();
+    if (lane < 12) {
+      const int rows = min(kWave, total - s0);
+      for (int rr = 0; rr < rows; ++rr) {
+        run += red[rr][lane];
+        if (rlast[rr]) {
+          pg[(g0 + rown[rr]) * 12 + lane] = run;
+          run = T(0);
+        }
+      }
+    }
+    __syncthreads();
   }
-  const int64_t tc = owner[p];
-  const int d = int(tc / n_t);
-  const int64_t t = tc - int64_t(d) * n_t;
-  const CellRange r = rng[tc];
-  const int64_t q = p - pair_off[tc];
-  const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
-                     r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
-  TetGeom G;
-  T zl[4];
-  for (int k = 0; k < 4; ++k) {
-    const int64_t v = tets[4 * t + k];
-    G.V[k][0] = X[3 * v + 0];
-    G.V[k][1] = X[3 * v + 1];
-    G.V[k][2] = X[3 * v + 2];
-    zl[k] = z[int64_t(d) * n_v + v];
-  }
-  tet_geom(G);
-  double lo[3], hi[3];
-  for (int e = 0; e < 3; ++e) {
-    const double* L = lat + ld.off[3 * d + e];
-    lo[e] = L[ci[e]];
-    hi[e] = L[ci[e] + 1];
-  }
-  const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
-  const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
-  T ul[8];
-  for (int c = 0; c < 2; ++c)
-    for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < 2; ++a)
-        ul[a + 2 * b + 4 * c] = u[(ci[0] + a) + NX * ((ci[1] + b) + NY * int64_t(ci[2] + c))];
-  T LA[4], LG[4][3], A[12], Bs = T(0);
-  cell_lambda<T>(G, lo, hi, LA, LG);
-  for (int k = 0; k < 12; ++k) A[k] = T(0);
-  const T* rec = pool + sub_begin[p] * kRecord;
-  for (int sI = 0; sI < cnt; ++sI, rec += kRecord) {
-    T y[4][3];
-    for (int v = 0; v < 4; ++v)
-      for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
-    subtet_grad<T>(y, rec[12], LA, LG, zl, ul, A, Bs);
-  }
-  const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
-  const double sc = -cv / 6.0;
-  for (int a = 0; a < 4; ++a)
-    for (int k = 0; k < 3; ++k)
-      out[a * 3 + k] = T(sc * (double(A[a * 3 + k]) / (hi[k] - lo[k]) + G.g[a][k] * double(Bs)));
 }
 
 // One wavefront per vertex a: lanes take (incident tet, component) items,
@@ -223,7 +284,7 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
   if (c->n_pairs > 0 && c->pool_valid) {
     ProfScope ps("shape_pool", s);
-    k_shape_pool<T><<<unsigned(ceil_div(c->n_pairs, 256)), 256, 0, s>>>(
+    k_shape_pool<T><<<unsigned(ceil_div(c->n_pairs, kWave)), kWave, 0, s>>>(
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
         c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pool.as<T>(),
         c->sub_begin.as<int64_t>(), c->sub_cnt.as<uint8_t>(), c->X.as<double>(),
