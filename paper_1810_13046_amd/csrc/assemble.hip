@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
     const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
     LatDesc ld, double drop_rel, uint8_t* __restrict__ keep, T* __restrict__ pool,
     int64_t pool_cap, int64_t* __restrict__ sub_begin, uint8_t* __restrict__ sub_cnt,
-    unsigned* flags, unsigned long long* counters) {
+    T* __restrict__ coef, unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
   __shared__ uint32_t snb[kMaxV * kWave];
   const int lane = threadIdx.x;
@@ -305,8 +305,23 @@ __global__ __launch_bounds__(kWave) void k_clip(
         keep[p] = kp ? 1 : 0;
         sub_begin[p] = my;
         sub_cnt[p] = kp ? uint8_t(nsub) : 0;
-        if (kp) ++nk;
-        else if (vol > 0.0) ++nd;
+        if (kp) {
+          ++nk;
+          T LA[4], LG[4][3];
+          cell_lambda<T>(G, lo, hi, LA, LG);
+          T* cf = coef + p * kCoef;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            cf[i] = LA[i];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) cf[4 + 3 * i + e] = LG[i][e];
+          }
+#pragma unroll
+          for (int e = 0; e < 3; ++e) cf[16 + e] = T(hi[e] - lo[e]);
+          cf[19] = T(-cv / 6.0);
+        } else if (vol > 0.0) {
+          ++nd;
+        }
       }
     }
   }
@@ -344,12 +359,9 @@ __device__ __forceinline__ int owner_lane(int excl, int s) {
 // contiguous values).
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_integrate(
-    int64_t n_pairs, int64_t n_t, const int32_t* __restrict__ owner,
-    const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-    const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
-    LatDesc ld, const uint8_t* __restrict__ keep, const T* __restrict__ pool,
+    int64_t n_pairs, const uint8_t* __restrict__ keep, const T* __restrict__ pool,
     const int64_t* __restrict__ sub_begin, const uint8_t* __restrict__ sub_cnt,
-    T* __restrict__ pval) {
+    const T* __restrict__ coef, T* __restrict__ pval) {
   __shared__ T red[kWave][33];
   __shared__ int rown[kWave];
   __shared__ int rlast[kWave];
@@ -381,13 +393,14 @@ __global__ __launch_bounds__(kWave) void k_integrate(
 #pragma unroll
     for (int k = 0; k < 32; ++k) acc[k] = T(0);
     if (s < total) {
-      int d, ci[3];
-      int64_t t;
-      TetGeom G;
-      double lo[3], hi[3];
-      pair_geometry(g0 + j, n_t, owner, pair_off, rng, X, tets, lat, ld, d, t, ci, G, lo, hi);
+      const T* cf = coef + (g0 + j) * kCoef;
       T LA[4], LG[4][3];
-      cell_lambda<T>(G, lo, hi, LA, LG);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        LA[i] = cf[i];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
+      }
       const T* rec = pool + (int64_t(bj) + (s - ex_j)) * kRecord;
       T y[4][3];
 #pragma unroll
@@ -395,7 +408,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(
 #pragma unroll
         for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
       subtet_integrate<T>(y, rec[12], LA, LG, acc);
-      const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
+      const T sc = cf[19];
 #pragma unroll
       for (int k = 0; k < 32; ++k) acc[k] *= sc;
     }
@@ -457,26 +470,12 @@ __global__ void k_row_box(int64_t n_v, int64_t n_t, const int64_t* __restrict__ 
   cap[w] = sz;
 }
 
-template <typename T>
-__device__ __forceinline__ T readlane_t(T v, int l);
-template <>
-__device__ __forceinline__ float readlane_t<float>(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-template <>
-__device__ __forceinline__ double readlane_t<double>(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane(int(b >> 32), l);
-  return __longlong_as_double((long long)((unsigned long long)(unsigned)lo |
-                                          ((unsigned long long)(unsigned)hi << 32)));
-}
-
 // Gather the pieces of the incident tets into the row's node box (kRowSlots
 // nodes per lane per pass, in a fixed order: incident tets ascending, then
 // cells), and write the touched nodes, column-sorted, at tmp_off[w].
-// Each incident tet's pairs are fetched across lanes in one step and
-// broadcast with readlane.
+// Pair rows are fetched 8 pairs at a time, one value per lane (lane =
+// 8·pair + corner), and each node lane pulls its corner with one lane
+// permute.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
     int64_t n_v, int64_t n_t, int64_t n_pairs, const int64_t* __restrict__ vt_ptr,
@@ -496,7 +495,9 @@ __global__ __launch_bounds__(256) void k_rows(
   const int64_t start = outpos;
   const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
   const int64_t beg = vt_ptr[i], end = vt_ptr[i + 1];
+  const int qq = lane >> 3, jj = lane & 7;
   for (int64_t c0 = 0; c0 < total; c0 += int64_t(kWave) * kRowSlots) {
+    const int nslots = int(min<int64_t>(kRowSlots, ceil_div(total - c0, kWave)));
     T acc[kRowSlots];
     int nx[kRowSlots], ny[kRowSlots], nz[kRowSlots];
     uint32_t valid = 0, touched = 0;
@@ -519,41 +520,41 @@ __global__ __launch_bounds__(256) void k_rows(
       for (int q = 1; q < 4; ++q)
         if (tets[4 * t + q] == int32_t(i)) li = q;
       const int64_t base = pair_off[tc];
-      for (int q0 = 0; q0 < ncell; q0 += kWave) {
-        // lane l fetches pair q0 + l: keep flag and the 8 values of row li
-        const int ql = q0 + lane;
+      const T* rowv = pval + int64_t(li) * n_pairs * 8;
+      int ix = 0, iy = 0, iz = 0;  // cell of pair q, x fastest
+      for (int q0 = 0; q0 < ncell; q0 += 8) {
+        const int ql = q0 + qq;
+        T val = T(0);
         int kp = 0;
-        T v8[8];
         if (ql < ncell) {
           kp = keep[base + ql];
-          if (kp) {
-            const T* pv = pval + int64_t(li) * n_pairs * 8 + (base + ql) * 8;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v8[j] = pv[j];
-          }
+          if (kp) val = rowv[(base + ql) * 8 + jj];
         }
-        const uint64_t km = ballot64(kp != 0);
-        const int qn = min(kWave, ncell - q0);
-        for (int l = 0; l < qn; ++l) {
-          if (!((km >> l) & 1ull)) continue;
-          const int q = q0 + l;
-          const int cx = r.lo[0] + q % r.n[0];
-          const int cy = r.lo[1] + (q / r.n[0]) % r.n[1];
-          const int cz = r.lo[2] + q / (r.n[0] * r.n[1]);
-          T vb[8];
+        const uint64_t km = ballot64(kp != 0 && jj == 0);
+        const int nq = min(8, ncell - q0);
+        for (int u = 0; u < nq; ++u) {
+          if ((km >> (8 * u)) & 1ull) {
+            const int cx = r.lo[0] + ix, cy = r.lo[1] + iy, cz = r.lo[2] + iz;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) vb[j] = readlane_t<T>(v8[j], l);
-#pragma unroll
-          for (int rr = 0; rr < kRowSlots; ++rr) {
-            const unsigned dx = unsigned(nx[rr] - cx), dy = unsigned(ny[rr] - cy),
-                           dz = unsigned(nz[rr] - cz);
-            if (((valid >> rr) & 1u) && dx <= 1u && dy <= 1u && dz <= 1u) {
-              touched |= 1u << rr;
-              const int corner = int(dx + 2 * dy + 4 * dz);
-              T v = vb[0];
-#pragma unroll
-              for (int j = 1; j < 8; ++j) v = (corner == j) ? vb[j] : v;
-              acc[rr] += v;
+            for (int rr = 0; rr < kRowSlots; ++rr) {
+              if (rr < nslots) {
+                const unsigned dx = unsigned(nx[rr] - cx), dy = unsigned(ny[rr] - cy),
+                               dz = unsigned(nz[rr] - cz);
+                const bool adj = ((valid >> rr) & 1u) && dx <= 1u && dy <= 1u && dz <= 1u;
+                const int corner = adj ? int(dx + 2 * dy + 4 * dz) : 0;
+                const T v = __shfl(val, 8 * u + corner, kWave);
+                if (adj) {
+                  acc[rr] += v;
+                  touched |= 1u << rr;
+                }
+              }
+            }
+          }
+          if (++ix == r.n[0]) {
+            ix = 0;
+            if (++iy == r.n[1]) {
+              iy = 0;
+              ++iz;
             }
           }
         }
@@ -702,6 +703,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   // below, and again by the reverse mode)
   if ((st = ensure(c, c->sub_begin, size_t(n_pairs + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->sub_cnt, size_t(n_pairs + 1)))) return st;
+  if ((st = ensure(c, c->paircoef, size_t(n_pairs + 1) * kCoef * sizeof(T)))) return st;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int64_t want = std::max<int64_t>(int64_t(3.0 * double(n_pairs)) + 1024,
                                            c->pool_needed + c->pool_needed / 32 + 1024);
@@ -723,7 +725,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
           n_pairs, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
           c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,
           c->keep.as<uint8_t>(), c->pool.as<T>(), c->pool_cap, c->sub_begin.as<int64_t>(),
-          c->sub_cnt.as<uint8_t>(), flags, counters);
+          c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), flags, counters);
     }
     if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
     unsigned long long used = 0;
@@ -736,10 +738,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if (n_pairs > 0) {
     ProfScope ps("integrate", s);
     k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
-        n_pairs, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
-        c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld,
-        c->keep.as<uint8_t>(), c->pool.as<T>(), c->sub_begin.as<int64_t>(),
-        c->sub_cnt.as<uint8_t>(), c->pval.as<T>());
+        n_pairs, c->keep.as<uint8_t>(), c->pool.as<T>(), c->sub_begin.as<int64_t>(),
+        c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), c->pval.as<T>());
   }
   if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
   // (IV) global assembly: rows of B^d

@@ -412,6 +412,11 @@ __host__ __device__ inline void cell_lambda(const TetGeom& G, const double lo[3]
 // the determinant, kRecord values of type T.
 constexpr int kRecord = 13;
 
+// Per-pair coefficients kept by the clip kernel for the integration
+// kernels: λ offsets (4), cell-local λ gradients (12), cell size (3) and
+// the scale −|cell|/6 (1).
+constexpr int kCoef = 20;
+
 // Clip tet ∩ box and integrate.  Returns false on a capacity/walk failure.
 // vol6 receives 6·|piece| in cell-local units (times the cell volume gives
 // 6|piece|), acc the 32 unscaled sums (caller scales by cellvol/6·(−1)).

@@ -113,9 +113,8 @@ __global__ __launch_bounds__(kWave) void k_shape_pool(
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
     const uint8_t* __restrict__ keep, const T* __restrict__ pool,
     const int64_t* __restrict__ sub_begin, const uint8_t* __restrict__ sub_cnt,
-    const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
-    LatDesc ld, const T* __restrict__ z, const T* u0, const T* u1, const T* u2,
-    T* __restrict__ pg) {
+    const T* __restrict__ coef, const int32_t* __restrict__ tets, LatDesc ld,
+    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, T* __restrict__ pg) {
   __shared__ T red[kWave][13];
   __shared__ int rown[kWave];
   __shared__ int rlast[kWave];
@@ -158,22 +157,8 @@ __global__ __launch_bounds__(kWave) void k_shape_pool(
       const int64_t q = p - pair_off[tc];
       const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
                          r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
-      TetGeom G;
       T zl[4];
-      for (int k = 0; k < 4; ++k) {
-        const int64_t v = tets[4 * t + k];
-        G.V[k][0] = X[3 * v + 0];
-        G.V[k][1] = X[3 * v + 1];
-        G.V[k][2] = X[3 * v + 2];
-        zl[k] = z[int64_t(d) * n_v + v];
-      }
-      tet_geom(G);
-      double lo[3], hi[3];
-      for (int e = 0; e < 3; ++e) {
-        const double* L = lat + ld.off[3 * d + e];
-        lo[e] = L[ci[e]];
-        hi[e] = L[ci[e] + 1];
-      }
+      for (int k = 0; k < 4; ++k) zl[k] = z[int64_t(d) * n_v + tets[4 * t + k]];
       const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
       const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
       T ul[8];
@@ -181,8 +166,14 @@ __global__ __launch_bounds__(kWave) void k_shape_pool(
         for (int b = 0; b < 2; ++b)
           for (int a = 0; a < 2; ++a)
             ul[a + 2 * b + 4 * c] = u[(ci[0] + a) + NX * ((ci[1] + b) + NY * int64_t(ci[2] + c))];
+      const T* cf = coef + p * kCoef;
       T LA[4], LG[4][3], A[12], Bs = T(0);
-      cell_lambda<T>(G, lo, hi, LA, LG);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        LA[i] = cf[i];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
+      }
 #pragma unroll
       for (int k = 0; k < 12; ++k) A[k] = T(0);
       const T* rec = pool + (int64_t(bj) + (s - ex_j)) * kRecord;
@@ -192,13 +183,14 @@ __global__ __launch_bounds__(kWave) void k_shape_pool(
 #pragma unroll
         for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
       subtet_grad<T>(y, rec[12], LA, LG, zl, ul, A, Bs);
-      const double sc = -(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0;
+      // ∂/∂x_k = (1/h_k) ∂/∂ξ_k; ∇λ_a = (cell-local gradient)/h
+      const T sc = cf[19];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int k = 0; k < 3; ++k) {
+        const T ih = T(1) / cf[16 + k];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          out[a * 3 + k] =
-              T(sc * (double(A[a * 3 + k]) / (hi[k] - lo[k]) + G.g[a][k] * double(Bs)));
+        for (int a = 0; a < 4; ++a) out[a * 3 + k] = sc * ih * (A[a * 3 + k] + LG[a][k] * Bs);
+      }
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) red[lane][k] = out[k];
@@ -287,8 +279,8 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
     k_shape_pool<T><<<unsigned(ceil_div(c->n_pairs, kWave)), kWave, 0, s>>>(
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
         c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pool.as<T>(),
-        c->sub_begin.as<int64_t>(), c->sub_cnt.as<uint8_t>(), c->X.as<double>(),
-        c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, static_cast<const T*>(z),
+        c->sub_begin.as<int64_t>(), c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(),
+        c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z),
         static_cast<const T*>(u[0]), static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg);
   } else if (c->n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
