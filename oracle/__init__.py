@@ -310,7 +310,13 @@ def vertex_star(tets, vertices):
     return np.nonzero(mask)[0]
 
 
-def tets_touching_node(faces, X, tets, d, node_ijk):
+def tet_bounds(X, tets):
+    """Per-tet bounding boxes (mn, mx), each (n_t, 3)."""
+    P = np.asarray(X)[tets]
+    return P.min(axis=1), P.max(axis=1)
+
+
+def tets_touching_node(faces, X, tets, d, node_ijk, bounds=None):
     """Tets whose bounding box meets the support of fluid node (i,j,k) of
     component d (a superset of those contributing to that column)."""
     lat = lattice(faces, d)
@@ -320,8 +326,7 @@ def tets_touching_node(faces, X, tets, d, node_ijk):
         k = node_ijk[e]
         lo[e] = lat[e][max(k - 1, 0)]
         hi[e] = lat[e][min(k + 1, lat[e].size - 1)]
-    P = np.asarray(X)[tets]
-    mn, mx = P.min(axis=1), P.max(axis=1)
+    mn, mx = tet_bounds(X, tets) if bounds is None else bounds
     ok = np.all((mx >= lo) & (mn <= hi), axis=1)
     return np.nonzero(ok)[0]
 

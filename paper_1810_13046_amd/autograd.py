@@ -1,0 +1,119 @@
+"""torch.autograd forms of the two transfers (hand-written backward).
+
+TransferVelocity:  u_s = S^{-1} B(X) u_f
+    backward: z = S^{-1} g_us;  g_uf = B^T z;  g_X = shape derivative
+TransferForce:     f_f = alpha B(X)^T f_s          (a new fluid field)
+    backward: g_fs = alpha B g_ff;  g_X = alpha * shape derivative
+
+Both call the C ABI (transfer_velocity / transfer_force and their
+_vjp entry points); no numerical step runs in Python.  With
+recompute_B=True the coupling is freed after the forward pass and
+assembled again from the saved X in the backward pass, so B and the piece
+store are not held between the two passes.
+"""
+from __future__ import annotations
+
+import torch
+
+from .ibvt import Coupling
+
+
+class _Ctx:
+    def __init__(self, faces, tets, precision, mass, rtol, maxit):
+        self.faces, self.tets, self.precision = faces, tets, precision
+        self.mass, self.rtol, self.maxit = mass, rtol, maxit
+
+
+def _coupling(meta, X, existing):
+    if existing is not None:
+        return existing
+    return Coupling(meta.faces, X.detach().contiguous(), meta.tets, precision=meta.precision,
+                    consistent=(meta.mass == "consistent"))
+
+
+class TransferVelocity(torch.autograd.Function):
+    """u_s = TransferVelocity.apply(u_f0, u_f1, u_f2, X, faces, tets, precision,
+    mass, rtol, maxit, coupling, recompute_B) -> (3, n_vert)."""
+
+    @staticmethod
+    def forward(ctx, u0, u1, u2, X, faces, tets, precision="fp64", mass="lumped", rtol=1e-12,
+                maxit=500, coupling=None, recompute_B=False):
+        meta = _Ctx(faces, tets, precision, mass, rtol, maxit)
+        c = _coupling(meta, X, coupling)
+        u = [u0.contiguous(), u1.contiguous(), u2.contiguous()]
+        us = c.velocity(u, mass=mass, rtol=rtol, maxit=maxit)
+        ctx.meta = meta
+        ctx.recompute = recompute_B and coupling is None
+        ctx.coupling = None if ctx.recompute else c
+        ctx.save_for_backward(u[0], u[1], u[2], X, us)
+        if ctx.recompute:
+            c.free()
+        return us
+
+    @staticmethod
+    def backward(ctx, g_us):
+        u0, u1, u2, X, us = ctx.saved_tensors
+        meta = ctx.meta
+        c = ctx.coupling if ctx.coupling is not None else _coupling(meta, X, None)
+        u = [u0, u1, u2]
+        need_u = any(ctx.needs_input_grad[:3])
+        need_X = ctx.needs_input_grad[3]
+        g_uf = [torch.zeros_like(v) for v in u] if need_u else None
+        g_X = torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device) if need_X else None
+        c.velocity_vjp(g_us.contiguous().to(us.dtype), u_f=u, u_s=us, mass=meta.mass, g_uf=g_uf,
+                       g_X=g_X, rtol=meta.rtol, maxit=meta.maxit)
+        if ctx.coupling is None:
+            c.free()
+        gu = g_uf if need_u else [None, None, None]
+        return (gu[0], gu[1], gu[2], g_X.to(X.dtype) if need_X else None,
+                None, None, None, None, None, None, None, None)
+
+
+class TransferForce(torch.autograd.Function):
+    """f_f = TransferForce.apply(f_s, X, faces, tets, precision, alpha,
+    coupling, recompute_B) -> tuple of 3 fluid arrays."""
+
+    @staticmethod
+    def forward(ctx, f_s, X, faces, tets, precision="fp64", alpha=1.0, coupling=None,
+                recompute_B=False):
+        meta = _Ctx(faces, tets, precision, "lumped", 1e-12, 500)
+        c = _coupling(meta, X, coupling)
+        out = [torch.zeros(s, dtype=c.dtype, device=f_s.device) for s in
+               [tuple(reversed(ls)) for ls in c.lattice_shapes]]
+        c.force(f_s.contiguous(), out, alpha=alpha)
+        ctx.meta = meta
+        ctx.alpha = alpha
+        ctx.recompute = recompute_B and coupling is None
+        ctx.coupling = None if ctx.recompute else c
+        ctx.save_for_backward(f_s, X)
+        if ctx.recompute:
+            c.free()
+        return tuple(out)
+
+    @staticmethod
+    def backward(ctx, g0, g1, g2):
+        f_s, X = ctx.saved_tensors
+        c = ctx.coupling if ctx.coupling is not None else _coupling(ctx.meta, X, None)
+        g_ff = []
+        for g, s in zip((g0, g1, g2), c.lattice_shapes):
+            g_ff.append(torch.zeros(tuple(reversed(s)), dtype=c.dtype, device=X.device)
+                        if g is None else g.contiguous().to(c.dtype))
+        g_fs = torch.zeros_like(f_s) if ctx.needs_input_grad[0] else None
+        g_X = (torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device)
+               if ctx.needs_input_grad[1] else None)
+        c.force_vjp(g_ff, f_s=f_s.contiguous(), alpha=ctx.alpha, g_fs=g_fs, g_X=g_X)
+        if ctx.coupling is None:
+            c.free()
+        return (g_fs, g_X.to(X.dtype) if g_X is not None else None,
+                None, None, None, None, None, None)
+
+
+def transfer_velocity(u_f, X, faces, tets, precision="fp64", mass="lumped", rtol=1e-12,
+                      maxit=500, coupling=None, recompute_B=False):
+    return TransferVelocity.apply(u_f[0], u_f[1], u_f[2], X, faces, tets, precision, mass, rtol,
+                                  maxit, coupling, recompute_B)
+
+
+def transfer_force(f_s, X, faces, tets, precision="fp64", alpha=1.0, coupling=None,
+                   recompute_B=False):
+    return TransferForce.apply(f_s, X, faces, tets, precision, alpha, coupling, recompute_B)
