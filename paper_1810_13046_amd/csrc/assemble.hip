@@ -18,6 +18,8 @@
 //  masses          lumped m_i = Σ_{T∋i} |T|/4 and the consistent P1 mass
 //                  matrix |T|(1+δ_il)/20 (Section 2.1), per vertex in
 //                  incident-tet order.
+#include <hipcub/hipcub.hpp>
+
 #include "geometry.hpp"
 #include "internal.hpp"
 
@@ -233,30 +235,76 @@ __device__ __forceinline__ void pair_geometry(int64_t p, int64_t n_t, const int3
   }
 }
 
+// Which of the six cell planes a pair's tet straddles, from indices alone:
+// the low plane of cell ci cuts the tet iff ci > first cell of the tet's
+// range, the high plane iff ci < last.  Sort key = class · 64 + pattern,
+// class 0: <= 3 cuts, 1: 4, 2: >= 5 (classes need 10, 12, 16 vertex
+// slots); sorting by the key gives every wave the same sequence of clips.
+__global__ void k_pair_key(int64_t n_pairs, const int32_t* __restrict__ owner,
+                           const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
+                           uint8_t* __restrict__ key, int32_t* __restrict__ idx) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n_pairs) {
+    const int64_t tc = owner[p];
+    const CellRange r = rng[tc];
+    const int64_t q = p - pair_off[tc];
+    const int c[3] = {int(q % r.n[0]), int((q / r.n[0]) % r.n[1]),
+                      int(q / (int64_t(r.n[0]) * r.n[1]))};
+    int pattern = 0;
+    for (int e = 0; e < 3; ++e) {
+      if (c[e] > 0) pattern |= 1 << (2 * e);
+      if (c[e] < r.n[e] - 1) pattern |= 2 << (2 * e);
+    }
+    const int cuts = __popc(pattern);
+    const int cls = cuts <= 3 ? 0 : (cuts == 4 ? 1 : 2);
+    key[p] = uint8_t(cls * 64 + pattern);
+    idx[p] = int32_t(p);
+  }
+}
+
+// Class sizes from the sorted keys: first index with key >= 64·k.
+__global__ void k_class_bounds(int64_t n, const uint8_t* __restrict__ skeys,
+                               unsigned long long* __restrict__ out) {
+  const int k = threadIdx.x;
+  __shared__ int64_t first[4];
+  if (k < 4) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (int(skeys[mid]) < 64 * k) lo = mid + 1;
+      else hi = mid;
+    }
+    first[k] = (k == 3) ? n : lo;
+  }
+  __syncthreads();
+  if (k < 3) out[k] = (unsigned long long)(first[k + 1] - first[k]);
+}
+
 // Clip every (tet, component, cell) pair in double, one lane per pair, and
 // store the fan sub-tetrahedra of the piece.  A wave reserves one
 // contiguous block of the store, so the records of the 64 pairs of a wave
 // are contiguous and in pair order.
-template <typename T>
+template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_clip(
-    int64_t n_pairs, int64_t n_t, const int32_t* __restrict__ owner,
+    int64_t n_list, const int32_t* __restrict__ order, int64_t n_t, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
     const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
     LatDesc ld, double drop_rel, uint8_t* __restrict__ keep, T* __restrict__ pool,
     int64_t pool_cap, int64_t* __restrict__ sub_begin, uint8_t* __restrict__ sub_cnt,
     T* __restrict__ coef, unsigned* flags, unsigned long long* counters) {
-  __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
-  __shared__ uint32_t snb[kMaxV * kWave];
+  __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
+  __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
-  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave};
+  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   unsigned long long nk = 0, nd = 0, ns = 0;
   bool fail = false;
-  for (int64_t p0 = int64_t(blockIdx.x) * kWave; p0 < n_pairs; p0 += int64_t(gridDim.x) * kWave) {
-    const int64_t p = p0 + lane;
-    const bool active = p < n_pairs;
+  for (int64_t p0 = int64_t(blockIdx.x) * kWave; p0 < n_list; p0 += int64_t(gridDim.x) * kWave) {
+    const bool active = p0 + lane < n_list;
+    const int64_t p = active ? int64_t(order[p0 + lane]) : 0;
     TetGeom G;
     double lo[3], hi[3];
     uint32_t live = 0;
+    uint64_t seen = 0;
     int want = 0;
     bool ok = true;
     if (active) {
@@ -266,7 +314,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
       live = poly_init_tet(P, G.V, G.det < 0.0);
       ok = poly_clip_box(P, live, lo, hi, G.mn, G.mx);
       if (ok) {
-        want = poly_fan_count(P, live);
+        want = poly_fan_prepare(P, live, seen);
         if (want < 0) {
           ok = false;
           want = 0;
@@ -290,8 +338,8 @@ __global__ __launch_bounds__(kWave) void k_clip(
       double vol6 = 0.0;
       int nsub = 0;
       if (ok && want > 0)
-        ok = emit_subtets<T>(P, live, lo, hi, fits ? pool + my * kRecord : nullptr, want, vol6,
-                             nsub);
+        ok = emit_subtets<T>(P, live, seen, lo, hi, fits ? pool + my * kRecord : nullptr, want,
+                             vol6, nsub);
       if (ok && nsub != want) ok = false;
       ns += unsigned(nsub);
       if (!ok) {
@@ -510,54 +558,95 @@ __global__ __launch_bounds__(256) void k_rows(
       ny[rr] = b.lo[1] + int((lin / b.n[0]) % b.n[1]);
       nz[rr] = b.lo[2] + int(lin / (int64_t(b.n[0]) * b.n[1]));
     }
-    for (int64_t k = beg; k < end; ++k) {
-      const int64_t t = vt_tet[k];
-      const int64_t tc = int64_t(d) * n_t + t;
-      const CellRange r = rng[tc];
-      const int ncell = r.n[0] * r.n[1] * r.n[2];
-      if (!ncell) continue;
-      int li = 0;
-      for (int q = 1; q < 4; ++q)
-        if (tets[4 * t + q] == int32_t(i)) li = q;
-      const int64_t base = pair_off[tc];
-      const T* rowv = pval + int64_t(li) * n_pairs * 8;
-      int ix = 0, iy = 0, iz = 0;  // cell of pair q, x fastest
-      for (int q0 = 0; q0 < ncell; q0 += 8) {
+    // incident tets in batches of 64: lane k holds tet k's metadata, so the
+    // metadata of a whole batch is fetched in one step
+    for (int64_t kb = beg; kb < end; kb += kWave) {
+      const int nk = int(min<int64_t>(kWave, end - kb));
+      int m_lo0 = 0, m_lo1 = 0, m_lo2 = 0, m_n0 = 0, m_n1 = 0, m_n2 = 0, m_li = 0;
+      int m_base_lo = 0, m_base_hi = 0;
+      if (lane < nk) {
+        const int64_t t = vt_tet[kb + lane];
+        const int64_t tc = int64_t(d) * n_t + t;
+        const CellRange r = rng[tc];
+        m_lo0 = r.lo[0];
+        m_lo1 = r.lo[1];
+        m_lo2 = r.lo[2];
+        m_n0 = r.n[0];
+        m_n1 = r.n[1];
+        m_n2 = r.n[2];
+        const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
+        m_li = (tv.y == int32_t(i)) ? 1 : (tv.z == int32_t(i)) ? 2 : (tv.w == int32_t(i)) ? 3 : 0;
+        const int64_t base = pair_off[tc];
+        m_base_lo = int(base & 0xffffffffll);
+        m_base_hi = int(base >> 32);
+      }
+      // chunk fetch of tet k (pairs q0..q0+7): lane = 8·pair + corner
+      auto fetch = [&](int k, int q0, T& val, int& kp) {
+        const int n0 = __builtin_amdgcn_readlane(m_n0, k), n1 = __builtin_amdgcn_readlane(m_n1, k),
+                  n2 = __builtin_amdgcn_readlane(m_n2, k);
+        const int ncell = n0 * n1 * n2;
+        const int64_t base =
+            int64_t((unsigned long long)(unsigned)__builtin_amdgcn_readlane(m_base_lo, k) |
+                    ((unsigned long long)(unsigned)__builtin_amdgcn_readlane(m_base_hi, k) << 32));
+        const int li = __builtin_amdgcn_readlane(m_li, k);
         const int ql = q0 + qq;
-        T val = T(0);
-        int kp = 0;
+        val = T(0);
+        kp = 0;
         if (ql < ncell) {
           kp = keep[base + ql];
-          if (kp) val = rowv[(base + ql) * 8 + jj];
+          if (kp) val = pval[int64_t(li) * n_pairs * 8 + (base + ql) * 8 + jj];
         }
-        const uint64_t km = ballot64(kp != 0 && jj == 0);
-        const int nq = min(8, ncell - q0);
-        for (int u = 0; u < nq; ++u) {
-          if ((km >> (8 * u)) & 1ull) {
-            const int cx = r.lo[0] + ix, cy = r.lo[1] + iy, cz = r.lo[2] + iz;
+      };
+      T cur_val, nxt_val = T(0);
+      int cur_kp, nxt_kp = 0;
+      fetch(0, 0, cur_val, cur_kp);
+      for (int k = 0; k < nk; ++k) {
+        if (k + 1 < nk) fetch(k + 1, 0, nxt_val, nxt_kp);   // next tet, in flight
+        const int lo0 = __builtin_amdgcn_readlane(m_lo0, k), lo1 = __builtin_amdgcn_readlane(m_lo1, k),
+                  lo2 = __builtin_amdgcn_readlane(m_lo2, k);
+        const int n0 = __builtin_amdgcn_readlane(m_n0, k), n1 = __builtin_amdgcn_readlane(m_n1, k);
+        const int ncell = n0 * n1 * __builtin_amdgcn_readlane(m_n2, k);
+        int ix = 0, iy = 0, iz = 0;  // cell of pair q, x fastest
+        for (int q0 = 0; q0 < ncell; q0 += 8) {
+          T val;
+          int kp;
+          if (q0 == 0) {
+            val = cur_val;
+            kp = cur_kp;
+          } else {
+            fetch(k, q0, val, kp);
+          }
+          const uint64_t km = ballot64(kp != 0 && jj == 0);
+          const int nq = min(8, ncell - q0);
+          for (int u = 0; u < nq; ++u) {
+            if ((km >> (8 * u)) & 1ull) {
+              const int cx = lo0 + ix, cy = lo1 + iy, cz = lo2 + iz;
 #pragma unroll
-            for (int rr = 0; rr < kRowSlots; ++rr) {
-              if (rr < nslots) {
-                const unsigned dx = unsigned(nx[rr] - cx), dy = unsigned(ny[rr] - cy),
-                               dz = unsigned(nz[rr] - cz);
-                const bool adj = ((valid >> rr) & 1u) && dx <= 1u && dy <= 1u && dz <= 1u;
-                const int corner = adj ? int(dx + 2 * dy + 4 * dz) : 0;
-                const T v = __shfl(val, 8 * u + corner, kWave);
-                if (adj) {
-                  acc[rr] += v;
-                  touched |= 1u << rr;
+              for (int rr = 0; rr < kRowSlots; ++rr) {
+                if (rr < nslots) {
+                  const unsigned dx = unsigned(nx[rr] - cx), dy = unsigned(ny[rr] - cy),
+                                 dz = unsigned(nz[rr] - cz);
+                  const bool adj = ((valid >> rr) & 1u) && dx <= 1u && dy <= 1u && dz <= 1u;
+                  const int corner = adj ? int(dx + 2 * dy + 4 * dz) : 0;
+                  const T v = __shfl(val, 8 * u + corner, kWave);
+                  if (adj) {
+                    acc[rr] += v;
+                    touched |= 1u << rr;
+                  }
                 }
               }
             }
-          }
-          if (++ix == r.n[0]) {
-            ix = 0;
-            if (++iy == r.n[1]) {
-              iy = 0;
-              ++iz;
+            if (++ix == n0) {
+              ix = 0;
+              if (++iy == n1) {
+                iy = 0;
+                ++iz;
+              }
             }
           }
         }
+        cur_val = nxt_val;
+        cur_kp = nxt_kp;
       }
     }
 #pragma unroll
@@ -704,6 +793,41 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->sub_begin, size_t(n_pairs + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->sub_cnt, size_t(n_pairs + 1)))) return st;
   if ((st = ensure(c, c->paircoef, size_t(n_pairs + 1) * kCoef * sizeof(T)))) return st;
+  // pair lists ordered by (cut class, straddled-plane pattern)
+  if (n_pairs >= (int64_t(1) << 31) - 1)
+    return set_error(IBVT_E_CAPACITY, "2^31 or more (tet, cell) pairs");
+  if ((st = ensure(c, c->order, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
+  int64_t class_count[3] = {0, 0, 0};
+  if (n_pairs > 0) {
+    ProfScope ps("pair_order", s);
+    size_t temp_bytes = 0;
+    if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(
+                            nullptr, temp_bytes, static_cast<const uint8_t*>(nullptr),
+                            static_cast<uint8_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                            static_cast<int32_t*>(nullptr), int(n_pairs), 0, 8, s),
+                        "sort size")))
+      return st;
+    const size_t kb = (size_t(n_pairs + 1) + 255) & ~size_t(255);
+    const size_t ib = (size_t(n_pairs + 1) * sizeof(int32_t) + 255) & ~size_t(255);
+    if ((st = ensure(c, c->pscan, 2 * kb + ib + temp_bytes + 256))) return st;
+    uint8_t* keys = c->pscan.as<uint8_t>();
+    uint8_t* skeys = keys + kb;
+    int32_t* idx = reinterpret_cast<int32_t*>(c->pscan.as<char>() + 2 * kb);
+    void* temp = c->pscan.as<char>() + 2 * kb + ib;
+    auto* cc = counters + kCntClass;
+    k_pair_key<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
+        n_pairs, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), keys,
+        idx);
+    if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx,
+                                                           c->order.as<int32_t>(), int(n_pairs), 0,
+                                                           8, s),
+                        "pair sort")))
+      return st;
+    k_class_bounds<<<1, 64, 0, s>>>(n_pairs, skeys, cc);
+    unsigned long long h[3];
+    if ((st = read_back(c, h, cc, sizeof(h), s))) return st;
+    for (int k = 0; k < 3; ++k) class_count[k] = int64_t(h[k]);
+  }
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int64_t want = std::max<int64_t>(int64_t(3.0 * double(n_pairs)) + 1024,
                                            c->pool_needed + c->pool_needed / 32 + 1024);
@@ -717,15 +841,28 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
         (st = hip_check(hipMemsetAsync(counters + kCntSubtets, 0, 2 * sizeof(unsigned long long), s),
                         "memset")))
       return st;
-    // (II) clip every pair
-    if (n_pairs > 0) {
-      const int64_t nb = std::min<int64_t>(ceil_div(n_pairs, kWave), int64_t(1) << 22);
+    // (II) clip every pair, grouped by the number of planes it can be cut by
+    // (fewer vertex slots per lane, more resident waves)
+    {
       ProfScope ps("clip", s);
-      k_clip<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
-          n_pairs, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
-          c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,
-          c->keep.as<uint8_t>(), c->pool.as<T>(), c->pool_cap, c->sub_begin.as<int64_t>(),
-          c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), flags, counters);
+      int64_t first = 0;
+      for (int k = 0; k < 3; ++k) {
+        const int64_t n_k = class_count[k];
+        if (n_k > 0) {
+          const int64_t nb = std::min<int64_t>(ceil_div(n_k, kWave), int64_t(1) << 22);
+          const int32_t* ord = c->order.as<int32_t>() + first;
+#define IBVT_CLIP_ARGS                                                                          \
+  n_k, ord, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),     \
+      c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,              \
+      c->keep.as<uint8_t>(), c->pool.as<T>(), c->pool_cap, c->sub_begin.as<int64_t>(),          \
+      c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), flags, counters
+          if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+          else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+          else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+#undef IBVT_CLIP_ARGS
+        }
+        first += n_k;
+      }
     }
     if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
     unsigned long long used = 0;

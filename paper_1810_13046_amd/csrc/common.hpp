@@ -21,6 +21,7 @@ enum Counter : int {
   kCntZeroTets = 2,
   kCntSubtets = 3,
   kCntPool = 4,
+  kCntClass = 5,  // 5, 6, 7: pairs per cut class
   kCntSlots = 8,
 };
 

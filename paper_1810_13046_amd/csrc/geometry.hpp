@@ -48,13 +48,16 @@ __host__ __device__ __forceinline__ int nb_find(uint32_t w, int v) {
   return nb_get(w, 0) == v ? 0 : (nb_get(w, 1) == v ? 1 : 2);
 }
 
-// Strided view of one piece's vertex graph.
+// Strided view of one piece's vertex graph (`all` = its usable slots: a
+// tet cut by c planes has at most 4 + c faces, hence at most 2(4 + c) − 4
+// vertices, and slot reuse never needs more than that).
 struct PolyView {
   double* px;
   double* py;
   double* pz;
   uint32_t* pnb;
   int S;
+  uint32_t all = kAllSlots;  // mask of the slots this view may use
   __host__ __device__ double& co(int v, int a) const {
     return (a == 0 ? px : (a == 1 ? py : pz))[v * S];
   }
@@ -107,7 +110,7 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
     adj |= (1u << nb_get(w, 0)) | (1u << nb_get(w, 1)) | (1u << nb_get(w, 2));
   }
   // free slots: never used, or outside with no inside neighbour
-  uint32_t freem = (~live & kAllSlots) | (out & ~adj);
+  uint32_t freem = (~live & P.all) | (out & ~adj);
   uint32_t newm = 0;
   for (uint32_t m = out & adj; m; m &= m - 1) {
     const int u = ctz32(m);
@@ -463,19 +466,77 @@ __host__ __device__ inline bool integrate_piece(const PolyView& P, uint32_t live
   return ok;
 }
 
+// Walk the three faces through the apex (the lowest live vertex) once:
+// their directed edges are marked in `seen` (they give no sub-tetrahedra),
+// and the number of sub-tetrahedra of the fan is returned:
+// Σ_faces (deg − 2) = 2V − 4 for a 3-regular polyhedral graph, minus the
+// apex faces.  Returns -1 if a walk exceeds its bound.
+__host__ __device__ inline int poly_fan_prepare(const PolyView& P, uint32_t live, uint64_t& seen) {
+  seen = 0;
+  if (!live) return 0;
+  const int apex = ctz32(live);
+  int total = 2 * __builtin_popcount(live) - 4;
+  const uint32_t aw = P.nb(apex);
+  for (int k = 0; k < 3; ++k) {
+    seen |= 1ull << (3 * apex + k);
+    int prev = apex, cur = nb_get(aw, k), deg = 1, guard = 0;
+    while (cur != apex) {
+      const uint32_t cw = P.nb(cur);
+      const int nk = (nb_find(cw, prev) + 1) % 3;
+      seen |= 1ull << (3 * cur + nk);
+      prev = cur;
+      cur = nb_get(cw, nk);
+      ++deg;
+      if (++guard > 3 * kMaxV) return -1;
+    }
+    total -= deg - 2;
+  }
+  return total;
+}
+
+// Emit the fan sub-tetrahedra (apex, f0, f_i, f_{i+1}) of every face not
+// marked in `seen`, one pass per face.
+template <typename F>
+__host__ __device__ inline bool poly_fan_emit(const PolyView& P, uint32_t live, uint64_t seen,
+                                              F&& fn) {
+  if (!live) return true;
+  const int apex = ctz32(live);
+  for (uint32_t m = live; m; m &= m - 1) {
+    const int v = ctz32(m);
+    const uint32_t vw = P.nb(v);
+    for (int k = 0; k < 3; ++k) {
+      if ((seen >> (3 * v + k)) & 1ull) continue;
+      seen |= 1ull << (3 * v + k);
+      int prev = v, f1 = nb_get(vw, k), guard = 0;
+      for (;;) {
+        const uint32_t cw = P.nb(f1);
+        const int nk = (nb_find(cw, prev) + 1) % 3;
+        seen |= 1ull << (3 * f1 + nk);
+        const int f2 = nb_get(cw, nk);
+        if (f2 == v) break;
+        fn(apex, v, f1, f2);
+        prev = f1;
+        f1 = f2;
+        if (++guard > 3 * kMaxV) return false;
+      }
+    }
+  }
+  return true;
+}
+
 // Write the fan's sub-tetrahedra of a clipped piece as records (cell-local
 // coordinates and determinant, rounded to T) at rec (up to cap of them);
 // vol6 receives the piece's 6·volume in cell-local units (double).
 template <typename T>
-__host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, const double lo[3],
-                                             const double hi[3], T* rec, int cap, double& vol6,
-                                             int& nsub) {
+__host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, uint64_t seen,
+                                             const double lo[3], const double hi[3], T* rec,
+                                             int cap, double& vol6, int& nsub) {
   vol6 = 0.0;
   nsub = 0;
   if (!live) return true;
   const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
   double vsum = 0.0;
-  const bool ok = poly_fan(P, live, [&](int q0, int q1, int q2, int q3) {
+  const bool ok = poly_fan_emit(P, live, seen, [&](int q0, int q1, int q2, int q3) {
     const int qs[4] = {q0, q1, q2, q3};
     double yd[4][3];
     for (int v = 0; v < 4; ++v)

@@ -70,6 +70,8 @@ struct ibvt_coupling {
   ibvt::DevBuf sub_begin;    // int64 n_pairs: first record of the pair
   ibvt::DevBuf sub_cnt;      // uint8 n_pairs: records of the pair
   ibvt::DevBuf paircoef;     // T n_pairs*kCoef: per-pair λ coefficients
+  ibvt::DevBuf order;        // int32 n_pairs: pairs sorted by cut pattern
+  ibvt::DevBuf pscan;        // sort keys and scratch
   ibvt::DevBuf rownnz;       // int64 3*n_vert
   ibvt::DevBuf rowbox;       // node box per (vertex, component)
   ibvt::DevBuf rowcap;       // int64 box size per row
