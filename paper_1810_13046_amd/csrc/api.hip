@@ -103,7 +103,7 @@ void release_csr(ibvt_coupling* c, Csr& m) {
 }
 
 void release_all(ibvt_coupling* c) {
-  DevBuf* bufs[] = {&c->lat, &c->X, &c->tets, &c->vt_ptr, &c->vt_tet, &c->tetvol, &c->rng,
+  DevBuf* bufs[] = {&c->lat, &c->X, &c->tets, &c->vt_ptr, &c->vt_tet, &c->tetvol, &c->tetgeo, &c->rng,
                     &c->cnt, &c->pair_off, &c->owner, &c->pval, &c->keep, &c->rownnz, &c->mark,
                     &c->cidx, &c->tbuf, &c->mlump, &c->minv, &c->Mval32, &c->Mdiag_inv,
                     &c->flags_dev, &c->counters, &c->scan_tmp, &c->work, &c->work2, &c->zbuf,

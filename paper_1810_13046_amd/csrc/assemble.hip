@@ -136,7 +136,7 @@ __global__ void k_mass_pattern(int64_t n_v, const int64_t* __restrict__ vt_ptr,
 __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
                            const int32_t* __restrict__ tets, const double* __restrict__ lat,
                            LatDesc ld, double* __restrict__ tetvol, CellRange* __restrict__ rng,
-                           int64_t* __restrict__ cnt, unsigned* flags,
+                           int64_t* __restrict__ cnt, double* __restrict__ tetgeo, unsigned* flags,
                            unsigned long long* counters) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   bool zero = false;
@@ -165,6 +165,13 @@ __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
                        a[2] * (b[0] * c[1] - b[1] * c[0]);
     const double vol = fabs(det) / 6.0;
     tetvol[t] = finite ? vol : 0.0;
+    {
+      TetGeom G;
+      for (int k = 0; k < 4; ++k)
+        for (int e = 0; e < 3; ++e) G.V[k][e] = P[k][e];
+      tet_geom(G);
+      store_tet_geom(G, tetgeo + t * kTetGeo);
+    }
     zero = finite && (vol == 0.0);
     if (!finite) atomicOr(flags, kFlagNonFinite);
     for (int d = 0; d < 3; ++d) {
@@ -206,13 +213,13 @@ __global__ void k_owner(int64_t n_tc, const int64_t* __restrict__ off, int32_t* 
 // clip + integrate, one lane per (tet, component, cell) pair
 // ---------------------------------------------------------------------------
 
-// Pair geometry shared by the clip and integration kernels.
+// Pair geometry shared by the clip kernels: cell of the pair and the
+// precomputed tet geometry.
 __device__ __forceinline__ void pair_geometry(int64_t p, int64_t n_t, const int32_t* owner,
                                               const int64_t* pair_off, const CellRange* rng,
-                                              const double* X, const int32_t* tets,
-                                              const double* lat, const LatDesc& ld, int& d,
-                                              int64_t& t, int ci[3], TetGeom& G, double lo[3],
-                                              double hi[3]) {
+                                              const double* tetgeo, const double* lat,
+                                              const LatDesc& ld, int& d, int64_t& t, int ci[3],
+                                              TetGeom& G, double lo[3], double hi[3]) {
   const int64_t tc = owner[p];
   d = int(tc / n_t);
   t = tc - int64_t(d) * n_t;
@@ -221,13 +228,7 @@ __device__ __forceinline__ void pair_geometry(int64_t p, int64_t n_t, const int3
   ci[0] = r.lo[0] + int(q % r.n[0]);
   ci[1] = r.lo[1] + int((q / r.n[0]) % r.n[1]);
   ci[2] = r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]));
-  for (int k = 0; k < 4; ++k) {
-    const int64_t v = tets[4 * t + k];
-    G.V[k][0] = X[3 * v + 0];
-    G.V[k][1] = X[3 * v + 1];
-    G.V[k][2] = X[3 * v + 2];
-  }
-  tet_geom(G);
+  load_tet_geom(G, tetgeo + t * kTetGeo);
   for (int e = 0; e < 3; ++e) {
     const double* L = lat + ld.off[3 * d + e];
     lo[e] = L[ci[e]];
@@ -281,22 +282,27 @@ __global__ void k_class_bounds(int64_t n, const uint8_t* __restrict__ skeys,
 }
 
 // Clip every (tet, component, cell) pair in double, one lane per pair, and
-// store the fan sub-tetrahedra of the piece.  A wave reserves one
-// contiguous block of the store, so the records of the 64 pairs of a wave
-// are contiguous and in pair order.
+// store the fan sub-tetrahedra of the piece.  The grid is sized to the
+// resident waves and each wave loops over batches of 64 pairs.  A wave takes
+// store space in chunks of `chunk` records (one atomic per chunk, not per
+// batch: same-address atomics serialise device-wide) and hands each batch a
+// contiguous block of its chunk, so every pair's records are contiguous and
+// in fan order; the unused tail of a chunk is left empty.  The counters are
+// summed per wave and added once at the end.
 template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_clip(
     int64_t n_list, const int32_t* __restrict__ order, int64_t n_t, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-    const double* __restrict__ X, const int32_t* __restrict__ tets, const double* __restrict__ lat,
-    LatDesc ld, double drop_rel, uint8_t* __restrict__ keep, T* __restrict__ pool,
-    int64_t pool_cap, int64_t* __restrict__ sub_begin, uint8_t* __restrict__ sub_cnt,
-    T* __restrict__ coef, unsigned* flags, unsigned long long* counters) {
+    const double* __restrict__ tetgeo, const double* __restrict__ lat, LatDesc ld,
+    double drop_rel, uint8_t* __restrict__ keep, T* __restrict__ pool, int64_t pool_cap, int64_t* __restrict__ sub_begin, uint8_t* __restrict__ sub_cnt,
+    T* __restrict__ coef, int chunk, unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
   __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   unsigned long long nk = 0, nd = 0, ns = 0;
+  unsigned long long cbase = 0;  // next free record of the wave's chunk
+  int cleft = 0;                 // records left in it
   bool fail = false;
   for (int64_t p0 = int64_t(blockIdx.x) * kWave; p0 < n_list; p0 += int64_t(gridDim.x) * kWave) {
     const bool active = p0 + lane < n_list;
@@ -310,7 +316,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
     if (active) {
       int d, ci[3];
       int64_t t;
-      pair_geometry(p, n_t, owner, pair_off, rng, X, tets, lat, ld, d, t, ci, G, lo, hi);
+      pair_geometry(p, n_t, owner, pair_off, rng, tetgeo, lat, ld, d, t, ci, G, lo, hi);
       live = poly_init_tet(P, G.V, G.det < 0.0);
       ok = poly_clip_box(P, live, lo, hi, G.mn, G.mx);
       if (ok) {
@@ -327,11 +333,16 @@ __global__ __launch_bounds__(kWave) void k_clip(
       if (lane >= o) incl += y;
     }
     const int wave_total = __shfl(incl, kWave - 1, kWave);
-    unsigned long long wbase = 0;
-    if (wave_total > 0) {
-      if (lane == 0) wbase = atomicAdd(&counters[kCntPool], (unsigned long long)wave_total);
-      wbase = __shfl(wbase, 0, kWave);
+    if (wave_total > cleft) {
+      const int take = wave_total > chunk ? wave_total : chunk;
+      unsigned long long b = 0;
+      if (lane == 0) b = atomicAdd(&counters[kCntPool], (unsigned long long)take);
+      cbase = __shfl(b, 0, kWave);
+      cleft = take;
     }
+    const unsigned long long wbase = cbase;
+    cbase += unsigned(wave_total);
+    cleft -= wave_total;
     if (active) {
       const int64_t my = int64_t(wbase) + (incl - want);
       const bool fits = my + want <= pool_cap;
@@ -738,6 +749,21 @@ inline unsigned blocks_for(int64_t n, int threads) {
   return unsigned(ceil_div(n > 0 ? n : 1, threads));
 }
 
+// Blocks of one wave each that the device keeps resident for kernel f
+// (grid of a persistent launch).
+template <typename F>
+int resident_blocks(F f) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kWave, 0) != hipSuccess ||
+      cus <= 0 || per_cu <= 0) {
+    (void)hipGetLastError();  // a failed query must not read as a launch error
+    return 1 << 16;
+  }
+  return cus * per_cu;
+}
+
 int read_back(ibvt_coupling* c, void* host, const void* dev, size_t bytes, hipStream_t s) {
   int st = hip_check(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s), "read back");
   if (st) return st;
@@ -772,7 +798,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     ProfScope ps("tet_prep", s);
   k_tet_prep<<<blocks_for(n_t, 256), 256, 0, s>>>(
       n_t, c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld,
-      c->tetvol.as<double>(), c->rng.as<CellRange>(), c->cnt.as<int64_t>(), flags, counters);
+      c->tetvol.as<double>(), c->rng.as<CellRange>(), c->cnt.as<int64_t>(), c->tetgeo.as<double>(),
+      flags, counters);
   }
   if ((st = hip_check(hipGetLastError(), "prep launch"))) return st;
   if ((st = scan_i64(c, c->cnt.as<int64_t>(), c->pair_off.as<int64_t>(), 3 * n_t, s))) return st;
@@ -829,7 +856,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     for (int k = 0; k < 3; ++k) class_count[k] = int64_t(h[k]);
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
-    const int64_t want = std::max<int64_t>(int64_t(3.0 * double(n_pairs)) + 1024,
+    const int64_t want = std::max<int64_t>(int64_t(3.25 * double(n_pairs)) + 1024,
                                            c->pool_needed + c->pool_needed / 32 + 1024);
     if (int64_t(c->pool.cap / (kRecord * sizeof(T))) < want &&
         (st = ensure(c, c->pool, size_t(want) * kRecord * sizeof(T))))
@@ -849,13 +876,20 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
       for (int k = 0; k < 3; ++k) {
         const int64_t n_k = class_count[k];
         if (n_k > 0) {
-          const int64_t nb = std::min<int64_t>(ceil_div(n_k, kWave), int64_t(1) << 22);
+          const int resident =
+              k == 0 ? resident_blocks(k_clip<T, 10>)
+                     : (k == 1 ? resident_blocks(k_clip<T, 12>) : resident_blocks(k_clip<T, kMaxV>));
+          const int64_t nb = std::min<int64_t>(ceil_div(n_k, kWave), resident);
           const int32_t* ord = c->order.as<int32_t>() + first;
+          // chunk ~ 1/8 of a wave's expected records (about 3 per pair),
+          // so the unused chunk tails stay a few percent of the store
+          const int chunk =
+              int(std::min<int64_t>(2048, (3 * n_k) / (8 * nb)));
 #define IBVT_CLIP_ARGS                                                                          \
   n_k, ord, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),     \
-      c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, 1e-14,              \
+      c->tetgeo.as<double>(), c->lat.as<double>(), c->ld, 1e-14,                                \
       c->keep.as<uint8_t>(), c->pool.as<T>(), c->pool_cap, c->sub_begin.as<int64_t>(),          \
-      c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), flags, counters
+      c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), chunk, flags, counters
           if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
           else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
           else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
@@ -1019,6 +1053,7 @@ int assemble_all(ibvt_coupling* c, hipStream_t s) {
   int st;
   int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));
   if ((st = ensure(c, c->tetvol, size_t(n_t + 1) * sizeof(double)))) return st;
+  if ((st = ensure(c, c->tetgeo, size_t(n_t + 1) * kTetGeo * sizeof(double)))) return st;
   if ((st = ensure(c, c->rng, size_t(3 * n_t + 1) * sizeof(CellRange)))) return st;
   if ((st = ensure(c, c->cnt, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->pair_off, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;

@@ -399,6 +399,37 @@ __host__ __device__ inline void tet_geom(TetGeom& G) {
   }
 }
 
+// Per-tet geometry record (vertices, determinant, gradients, box), written
+// once per assembly and read by every pair of the tet.
+constexpr int kTetGeo = 32;
+
+__host__ __device__ inline void store_tet_geom(const TetGeom& G, double* r) {
+  for (int k = 0; k < 4; ++k)
+    for (int e = 0; e < 3; ++e) {
+      r[3 * k + e] = G.V[k][e];
+      r[12 + 3 * k + e] = G.g[k][e];
+    }
+  r[24] = G.det;
+  for (int e = 0; e < 3; ++e) {
+    r[25 + e] = G.mn[e];
+    r[28 + e] = G.mx[e];
+  }
+  r[31] = 0.0;
+}
+
+__host__ __device__ inline void load_tet_geom(TetGeom& G, const double* r) {
+  for (int k = 0; k < 4; ++k)
+    for (int e = 0; e < 3; ++e) {
+      G.V[k][e] = r[3 * k + e];
+      G.g[k][e] = r[12 + 3 * k + e];
+    }
+  G.det = r[24];
+  for (int e = 0; e < 3; ++e) {
+    G.mn[e] = r[25 + e];
+    G.mx[e] = r[28 + e];
+  }
+}
+
 // λ_i in cell-local coordinates: λ_i(ξ) = λ_i(lo) + (∇λ_i ∘ h)·ξ.
 template <typename T>
 __host__ __device__ inline void cell_lambda(const TetGeom& G, const double lo[3], const double hi[3],

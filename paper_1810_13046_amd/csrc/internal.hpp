@@ -55,6 +55,7 @@ struct ibvt_coupling {
   ibvt::DevBuf X, tets;      // own copies
   ibvt::DevBuf vt_ptr, vt_tet;  // vertex -> incident tets (int64 ptr, int32 ids)
   ibvt::DevBuf tetvol;       // double n_tet
+  ibvt::DevBuf tetgeo;       // double n_tet*kTetGeo: per-tet geometry record
   ibvt::DevBuf rng;          // CellRange 3*n_tet
   ibvt::DevBuf cnt;          // int64 3*n_tet
   ibvt::DevBuf pair_off;     // int64 3*n_tet + 1
