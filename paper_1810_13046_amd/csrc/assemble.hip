@@ -29,7 +29,7 @@ namespace ibvt {
 
 namespace {
 
-constexpr int kRowSlots = 4;  // box nodes per lane per pass in k_rows
+constexpr int kRowNodes = 512;  // LDS box nodes per wave per pass in k_rows
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
   int lo = 0, hi = n;  // first index with L[idx] > x
@@ -529,12 +529,21 @@ __global__ void k_row_box(int64_t n_v, int64_t n_t, const int64_t* __restrict__ 
   cap[w] = sz;
 }
 
-// Gather the pieces of the incident tets into the row's node box (kRowSlots
-// nodes per lane per pass, in a fixed order: incident tets ascending, then
-// cells), and write the touched nodes, column-sorted, at tmp_off[w].
-// Pair rows are fetched 8 pairs at a time, one value per lane (lane =
-// 8·pair + corner), and each node lane pulls its corner with one lane
-// permute.
+// Orders the LDS accesses of one wave around this point (the wave's LDS
+// operations execute in issue order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Gather the pieces of the incident tets into the row's node box, kept in
+// LDS kRowNodes nodes at a time.  The row's pairs (incident tets ascending,
+// then cells) are taken 8 per step, one value per lane (lane = 8·pair +
+// corner); the 8 pairs are added to the box one after another, and the 8
+// corners of one pair are distinct nodes, so every node sums its
+// contributions in pair order (deterministic).  Touched nodes are written
+// column-sorted at tmp_off[w].
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
     int64_t n_v, int64_t n_t, int64_t n_pairs, const int64_t* __restrict__ vt_ptr,
@@ -543,9 +552,17 @@ __global__ __launch_bounds__(256) void k_rows(
     const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
     const RowBox* __restrict__ box, const int64_t* __restrict__ tmp_off,
     int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz) {
+  __shared__ T s_acc[4][kRowNodes];
+  __shared__ uint8_t s_flag[4][kRowNodes];
+  __shared__ int4 s_m0[4][kWave], s_m1[4][kWave];
+  const int wib = threadIdx.x / kWave;
   const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = lane_id();
   if (w >= 3 * n_v) return;
+  T* acc = s_acc[wib];
+  uint8_t* flg = s_flag[wib];
+  int4* M0 = s_m0[wib];
+  int4* M1 = s_m1[wib];
   const int d = int(w / n_v);
   const int64_t i = w - int64_t(d) * n_v;
   const RowBox b = box[w];
@@ -555,122 +572,90 @@ __global__ __launch_bounds__(256) void k_rows(
   const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
   const int64_t beg = vt_ptr[i], end = vt_ptr[i + 1];
   const int qq = lane >> 3, jj = lane & 7;
-  for (int64_t c0 = 0; c0 < total; c0 += int64_t(kWave) * kRowSlots) {
-    const int nslots = int(min<int64_t>(kRowSlots, ceil_div(total - c0, kWave)));
-    T acc[kRowSlots];
-    int nx[kRowSlots], ny[kRowSlots], nz[kRowSlots];
-    uint32_t valid = 0, touched = 0;
-#pragma unroll
-    for (int rr = 0; rr < kRowSlots; ++rr) {
-      acc[rr] = T(0);
-      const int64_t lin = c0 + int64_t(rr) * kWave + lane;
-      if (lin < total) valid |= 1u << rr;
-      nx[rr] = b.lo[0] + int(lin % b.n[0]);
-      ny[rr] = b.lo[1] + int((lin / b.n[0]) % b.n[1]);
-      nz[rr] = b.lo[2] + int(lin / (int64_t(b.n[0]) * b.n[1]));
+  const int dx = jj & 1, dy = (jj >> 1) & 1, dz = jj >> 2;
+  const int64_t vplane = n_pairs * 8;
+  for (int64_t c0 = 0; c0 < total; c0 += kRowNodes) {
+    const int span = int(min<int64_t>(kRowNodes, total - c0));
+    for (int k = lane; k < span; k += kWave) {
+      acc[k] = T(0);
+      flg[k] = 0;
     }
-    // incident tets in batches of 64: lane k holds tet k's metadata, so the
-    // metadata of a whole batch is fetched in one step
     for (int64_t kb = beg; kb < end; kb += kWave) {
       const int nk = int(min<int64_t>(kWave, end - kb));
-      int m_lo0 = 0, m_lo1 = 0, m_lo2 = 0, m_n0 = 0, m_n1 = 0, m_n2 = 0, m_li = 0;
-      int m_base_lo = 0, m_base_hi = 0;
+      int cnt = 0;
+      wave_lds_sync();
       if (lane < nk) {
         const int64_t t = vt_tet[kb + lane];
         const int64_t tc = int64_t(d) * n_t + t;
         const CellRange r = rng[tc];
-        m_lo0 = r.lo[0];
-        m_lo1 = r.lo[1];
-        m_lo2 = r.lo[2];
-        m_n0 = r.n[0];
-        m_n1 = r.n[1];
-        m_n2 = r.n[2];
         const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
-        m_li = (tv.y == int32_t(i)) ? 1 : (tv.z == int32_t(i)) ? 2 : (tv.w == int32_t(i)) ? 3 : 0;
+        const int li =
+            (tv.y == int32_t(i)) ? 1 : (tv.z == int32_t(i)) ? 2 : (tv.w == int32_t(i)) ? 3 : 0;
         const int64_t base = pair_off[tc];
-        m_base_lo = int(base & 0xffffffffll);
-        m_base_hi = int(base >> 32);
+        M0[lane] = make_int4(r.lo[0], r.lo[1], r.lo[2], li);
+        M1[lane] = make_int4(r.n[0], r.n[1], int(base & 0xffffffffll), int(base >> 32));
+        cnt = r.n[0] * r.n[1] * r.n[2];
       }
-      // chunk fetch of tet k (pairs q0..q0+7): lane = 8·pair + corner
-      auto fetch = [&](int k, int q0, T& val, int& kp) {
-        const int n0 = __builtin_amdgcn_readlane(m_n0, k), n1 = __builtin_amdgcn_readlane(m_n1, k),
-                  n2 = __builtin_amdgcn_readlane(m_n2, k);
-        const int ncell = n0 * n1 * n2;
-        const int64_t base =
-            int64_t((unsigned long long)(unsigned)__builtin_amdgcn_readlane(m_base_lo, k) |
-                    ((unsigned long long)(unsigned)__builtin_amdgcn_readlane(m_base_hi, k) << 32));
-        const int li = __builtin_amdgcn_readlane(m_li, k);
-        const int ql = q0 + qq;
-        val = T(0);
-        kp = 0;
-        if (ql < ncell) {
-          kp = keep[base + ql];
-          if (kp) val = pval[int64_t(li) * n_pairs * 8 + (base + ql) * 8 + jj];
-        }
-      };
-      T cur_val, nxt_val = T(0);
-      int cur_kp, nxt_kp = 0;
-      fetch(0, 0, cur_val, cur_kp);
-      for (int k = 0; k < nk; ++k) {
-        if (k + 1 < nk) fetch(k + 1, 0, nxt_val, nxt_kp);   // next tet, in flight
-        const int lo0 = __builtin_amdgcn_readlane(m_lo0, k), lo1 = __builtin_amdgcn_readlane(m_lo1, k),
-                  lo2 = __builtin_amdgcn_readlane(m_lo2, k);
-        const int n0 = __builtin_amdgcn_readlane(m_n0, k), n1 = __builtin_amdgcn_readlane(m_n1, k);
-        const int ncell = n0 * n1 * __builtin_amdgcn_readlane(m_n2, k);
-        int ix = 0, iy = 0, iz = 0;  // cell of pair q, x fastest
-        for (int q0 = 0; q0 < ncell; q0 += 8) {
-          T val;
-          int kp;
-          if (q0 == 0) {
-            val = cur_val;
-            kp = cur_kp;
-          } else {
-            fetch(k, q0, val, kp);
+      int incl = cnt;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+      }
+      const int excl = incl - cnt;
+      const int tot = __shfl(incl, kWave - 1, kWave);
+      wave_lds_sync();
+      for (int s0 = 0; s0 < tot; s0 += 8) {
+        const int sl = s0 + qq;
+        const int k = owner_lane(excl, sl);
+        const int exk = __shfl(excl, k, kWave);
+        bool add = false;
+        int loc = 0;
+        T val = T(0);
+        if (sl < tot) {
+          const int4 m0 = M0[k], m1 = M1[k];
+          const unsigned q = unsigned(sl - exk);
+          const int64_t pr = int64_t((unsigned long long)(unsigned)m1.z |
+                                     ((unsigned long long)(unsigned)m1.w << 32)) + q;
+          if (keep[pr]) {
+            val = pval[int64_t(m0.w) * vplane + pr * 8 + jj];
+            const unsigned n0 = unsigned(m1.x), n1 = unsigned(m1.y);
+            const unsigned qy = q / n0;
+            const int ix = int(q - qy * n0);
+            const int iz = int(qy / n1);
+            const int iy = int(qy - unsigned(iz) * n1);
+            const int gx = m0.x + ix + dx - b.lo[0], gy = m0.y + iy + dy - b.lo[1],
+                      gz = m0.z + iz + dz - b.lo[2];
+            const int64_t lin = gx + int64_t(b.n[0]) * (gy + int64_t(b.n[1]) * gz) - c0;
+            add = lin >= 0 && lin < span;
+            loc = int(lin);
           }
-          const uint64_t km = ballot64(kp != 0 && jj == 0);
-          const int nq = min(8, ncell - q0);
-          for (int u = 0; u < nq; ++u) {
-            if ((km >> (8 * u)) & 1ull) {
-              const int cx = lo0 + ix, cy = lo1 + iy, cz = lo2 + iz;
+        }
+        if (add) flg[loc] = 1;
 #pragma unroll
-              for (int rr = 0; rr < kRowSlots; ++rr) {
-                if (rr < nslots) {
-                  const unsigned dx = unsigned(nx[rr] - cx), dy = unsigned(ny[rr] - cy),
-                                 dz = unsigned(nz[rr] - cz);
-                  const bool adj = ((valid >> rr) & 1u) && dx <= 1u && dy <= 1u && dz <= 1u;
-                  const int corner = adj ? int(dx + 2 * dy + 4 * dz) : 0;
-                  const T v = __shfl(val, 8 * u + corner, kWave);
-                  if (adj) {
-                    acc[rr] += v;
-                    touched |= 1u << rr;
-                  }
-                }
-              }
-            }
-            if (++ix == n0) {
-              ix = 0;
-              if (++iy == n1) {
-                iy = 0;
-                ++iz;
-              }
-            }
-          }
+        for (int u = 0; u < 8; ++u) {
+          wave_lds_sync();
+          if (add && qq == u)
+            __hip_atomic_fetch_add(&acc[loc], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
-        cur_val = nxt_val;
-        cur_kp = nxt_kp;
       }
     }
-#pragma unroll
-    for (int rr = 0; rr < kRowSlots; ++rr) {
-      const bool tch = (touched >> rr) & 1u;
+    wave_lds_sync();
+    for (int k0 = 0; k0 < span; k0 += kWave) {
+      const int k = k0 + lane;
+      const bool tch = k < span && flg[k] != 0;
       const uint64_t m = ballot64(tch);
       if (tch) {
+        const int64_t lin = c0 + k;
+        const int64_t gx = b.lo[0] + lin % b.n[0];
+        const int64_t gy = b.lo[1] + (lin / b.n[0]) % b.n[1];
+        const int64_t gz = b.lo[2] + lin / (int64_t(b.n[0]) * b.n[1]);
         const int64_t pos = outpos + rank_below(m);
-        tmp_col[pos] = int32_t(nx[rr] + NX * (ny[rr] + NY * int64_t(nz[rr])));
-        tmp_val[pos] = acc[rr];
+        tmp_col[pos] = int32_t(gx + NX * (gy + NY * gz));
+        tmp_val[pos] = acc[k];
       }
       outpos += popc64(m);
     }
+    wave_lds_sync();
   }
   if (lane == 0) rownnz[w] = outpos - start;
 }
