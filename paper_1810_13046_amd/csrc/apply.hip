@@ -88,7 +88,11 @@ struct CgScalars {
 };
 
 // q = M p for the three components (values V, vectors T), plus per-block
-// partials of p·q.
+// partials of p·q.  kMG lanes per row stride through it (coalesced reads of
+// the row's columns and values) and reduce with lane shuffles in a fixed
+// order.
+constexpr int kMG = 8;
+
 template <typename T, typename V>
 __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t* __restrict__ rp,
                                                        const int32_t* __restrict__ col,
@@ -97,18 +101,27 @@ __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t
                                                        double* __restrict__ part,
                                                        const CgScalars* sc) {
   __shared__ double red[3][kThreads / kWave];
-  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
+  const int g = threadIdx.x % kMG;
   double loc[3] = {0, 0, 0};
   if (!sc || !sc->all) {
+    T s0 = 0, s1 = 0, s2 = 0;
     if (i < n) {
-      T s0 = 0, s1 = 0, s2 = 0;
-      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
         const int64_t j = col[k];
         const T m = T(val[k]);
         s0 += m * p[j];
         s1 += m * p[n + j];
         s2 += m * p[2 * n + j];
       }
+    }
+#pragma unroll
+    for (int o = kMG / 2; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o, kWave);
+      s1 += __shfl_xor(s1, o, kWave);
+      s2 += __shfl_xor(s2, o, kWave);
+    }
+    if (i < n && g == 0) {
       q[i] = s0;
       q[n + i] = s1;
       q[2 * n + i] = s2;
@@ -266,7 +279,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_p(int64_t n, const T* __restric
   }
 }
 
-// residual in double: res = b - M x  (b, x of type T; M double)
+// residual in double: res = b - M x  (b, x of type T; M double), kMG
+// lanes per row as in k_mass_spmv.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_residual64(int64_t n, const int64_t* __restrict__ rp,
                                                         const int32_t* __restrict__ col,
@@ -276,14 +290,20 @@ __global__ __launch_bounds__(kThreads) void k_residual64(int64_t n, const int64_
                                                         double* __restrict__ res,
                                                         double* __restrict__ part) {
   __shared__ double red[6][kThreads / kWave];
-  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
+  const int g = threadIdx.x % kMG;
   double loc[6] = {0, 0, 0, 0, 0, 0};
+  double s[3] = {0, 0, 0};
   if (i < n) {
-    double s[3] = {0, 0, 0};
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+    for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
       const int64_t j = col[k];
       for (int d = 0; d < 3; ++d) s[d] += val[k] * x[int64_t(d) * n + j];
     }
+  }
+#pragma unroll
+  for (int o = kMG / 2; o > 0; o >>= 1)
+    for (int d = 0; d < 3; ++d) s[d] += __shfl_xor(s[d], o, kWave);
+  if (i < n && g == 0) {
     for (int d = 0; d < 3; ++d) {
       const double bv = double(b[int64_t(d) * n + i]);
       const double rv = bv - s[d];
@@ -330,6 +350,10 @@ __global__ void k_add_correction(int64_t n3, const float* __restrict__ e, double
 }
 
 inline unsigned nblk(int64_t n) { return unsigned(ceil_div(n > 0 ? n : 1, kThreads)); }
+// blocks of the row-group kernels (kThreads / kMG rows per block)
+inline unsigned nblk_rows(int64_t n) {
+  return unsigned(ceil_div(n > 0 ? n : 1, kThreads / kMG));
+}
 
 // Workspace layout for the CG (bytes): scalars, partials, 6 vectors of T
 // (b copy not needed: rhs is read), plus double x/res for refinement.
@@ -344,7 +368,7 @@ struct CgWork {
 
 int cg_workspace(ibvt_coupling* c, size_t tsize, CgWork& w) {
   const int64_t n = c->n_vert;
-  const int64_t nb = nblk(n);
+  const int64_t nb = nblk_rows(n);  // >= nblk(n): partials of every kernel fit
   const size_t off_part = 256;
   const size_t off_tmp = off_part + size_t(nb) * 6 * sizeof(double);
   const size_t off_vec = (off_tmp + 16 * sizeof(double) + 255) & ~size_t(255);
@@ -371,6 +395,7 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
             const CgWork& w, hipStream_t s, int* iters_out, bool* converged) {
   const int64_t n = c->n_vert;
   const unsigned nb = nblk(n);
+  const unsigned nbm = nblk_rows(n);
   T* q = static_cast<T*>(w.vec);
   T* r = q + 3 * n;
   T* z = r + 3 * n;
@@ -380,7 +405,7 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
   const double* dinv = c->Mdiag_inv.as<double>();
   const double rtol2 = rtol * rtol;
   // q = M x ; r = b - q ; z = D^-1 r ; p = z
-  k_mass_spmv<T, V><<<nb, kThreads, 0, s>>>(n, rp, col, mval, x, q, nullptr, nullptr);
+  k_mass_spmv<T, V><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, x, q, nullptr, nullptr);
   k_cg_vec<T><<<nb, kThreads, 0, s>>>(0, n, b, q, x, r, z, p, dinv, w.part, w.sc);
   k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
   k_cg_scalar<<<1, 64, 0, s>>>(0, w.sc, w.tmp, rtol2);
@@ -394,8 +419,8 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
     const int chunk = std::min(check, maxit - it);
     for (int k = 0; k < chunk; ++k) {
       ProfScope ps("cg_iteration", s);
-      k_mass_spmv<T, V><<<nb, kThreads, 0, s>>>(n, rp, col, mval, p, q, w.part, w.sc);
-      k_reduce3<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
+      k_mass_spmv<T, V><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, p, q, w.part, w.sc);
+      k_reduce3<<<1, kThreads, 0, s>>>(w.part, nbm, w.tmp);
       k_cg_scalar<<<1, 64, 0, s>>>(1, w.sc, w.tmp, rtol2);
       k_cg_vec<T><<<nb, kThreads, 0, s>>>(1, n, b, q, x, r, z, p, dinv, w.part, w.sc);
       k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
@@ -429,7 +454,7 @@ template <typename T>
 int true_residual(ibvt_coupling* c, const T* b, const double* x, const CgWork& w, hipStream_t s,
                   double rel[3]) {
   const int64_t n = c->n_vert;
-  const unsigned nb = nblk(n);
+  const unsigned nb = nblk_rows(n);
   k_residual64<T><<<nb, kThreads, 0, s>>>(n, c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>(),
                                           c->M.val.as<double>(), b, x, w.res64, w.part);
   k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);

@@ -30,6 +30,7 @@ namespace ibvt {
 namespace {
 
 constexpr int kRowNodes = 512;  // LDS box nodes per wave per pass in k_rows
+constexpr int kRowChunks = 1;   // 8-pair steps whose loads k_rows keeps in flight
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
   int lo = 0, hi = n;  // first index with L[idx] > x
@@ -502,22 +503,39 @@ struct RowBox {
   int32_t n[3];
 };
 
-__global__ void k_row_box(int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
-                          const int32_t* __restrict__ vt_tet, const CellRange* __restrict__ rng,
-                          RowBox* __restrict__ box, int64_t* __restrict__ cap) {
-  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (w >= 3 * n_v) return;
-  const int d = int(w / n_v);
-  const int64_t i = w - int64_t(d) * n_v;
+// kBoxG lanes per row: each takes every kBoxG-th incident tet, then the
+// group reduces its bounds with lane shuffles.
+constexpr int kBoxG = 16;
+
+__global__ __launch_bounds__(256) void k_row_box(int64_t n_v, int64_t n_t,
+                                                 const int64_t* __restrict__ vt_ptr,
+                                                 const int32_t* __restrict__ vt_tet,
+                                                 const CellRange* __restrict__ rng,
+                                                 RowBox* __restrict__ box,
+                                                 int64_t* __restrict__ cap) {
+  const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kBoxG;
+  const int g = threadIdx.x % kBoxG;
+  const bool active = w < 3 * n_v;
   int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
-  for (int64_t k = vt_ptr[i]; k < vt_ptr[i + 1]; ++k) {
-    const CellRange r = rng[int64_t(d) * n_t + vt_tet[k]];
-    if (int64_t(r.n[0]) * r.n[1] * r.n[2] == 0) continue;
-    for (int e = 0; e < 3; ++e) {
-      bmin[e] = min(bmin[e], r.lo[e]);
-      bmax[e] = max(bmax[e], r.lo[e] + r.n[e]);
+  if (active) {
+    const int d = int(w / n_v);
+    const int64_t i = w - int64_t(d) * n_v;
+    for (int64_t k = vt_ptr[i] + g; k < vt_ptr[i + 1]; k += kBoxG) {
+      const CellRange r = rng[int64_t(d) * n_t + vt_tet[k]];
+      if (int64_t(r.n[0]) * r.n[1] * r.n[2] == 0) continue;
+      for (int e = 0; e < 3; ++e) {
+        bmin[e] = min(bmin[e], r.lo[e]);
+        bmax[e] = max(bmax[e], r.lo[e] + r.n[e]);
+      }
     }
   }
+#pragma unroll
+  for (int o = kBoxG / 2; o > 0; o >>= 1)
+    for (int e = 0; e < 3; ++e) {
+      bmin[e] = min(bmin[e], __shfl_xor(bmin[e], o, kWave));
+      bmax[e] = max(bmax[e], __shfl_xor(bmax[e], o, kWave));
+    }
+  if (!active || g != 0) return;
   RowBox b;
   int64_t sz = 1;
   for (int e = 0; e < 3; ++e) {
@@ -604,20 +622,23 @@ __global__ __launch_bounds__(256) void k_rows(
       const int excl = incl - cnt;
       const int tot = __shfl(incl, kWave - 1, kWave);
       wave_lds_sync();
-      for (int s0 = 0; s0 < tot; s0 += 8) {
-        const int sl = s0 + qq;
-        const int k = owner_lane(excl, sl);
-        const int exk = __shfl(excl, k, kWave);
-        bool add = false;
-        int loc = 0;
-        T val = T(0);
-        if (sl < tot) {
-          const int4 m0 = M0[k], m1 = M1[k];
-          const unsigned q = unsigned(sl - exk);
-          const int64_t pr = int64_t((unsigned long long)(unsigned)m1.z |
-                                     ((unsigned long long)(unsigned)m1.w << 32)) + q;
-          if (keep[pr]) {
-            val = pval[int64_t(m0.w) * vplane + pr * 8 + jj];
+      // kRowChunks steps of 8 pairs at a time: all their loads in flight
+      // together (keep and value are read side by side), then the adds
+      for (int s0 = 0; s0 < tot; s0 += 8 * kRowChunks) {
+        bool add[kRowChunks];
+        int loc[kRowChunks];
+        T val[kRowChunks];
+#pragma unroll
+        for (int ch = 0; ch < kRowChunks; ++ch) {
+          const int sl = s0 + 8 * ch + qq;
+          const int k = owner_lane(excl, sl);
+          const int exk = __shfl(excl, k, kWave);
+          add[ch] = false;
+          loc[ch] = 0;
+          val[ch] = T(0);
+          if (sl < tot) {
+            const int4 m0 = M0[k], m1 = M1[k];
+            const unsigned q = unsigned(sl - exk);
             const unsigned n0 = unsigned(m1.x), n1 = unsigned(m1.y);
             const unsigned qy = q / n0;
             const int ix = int(q - qy * n0);
@@ -626,16 +647,27 @@ __global__ __launch_bounds__(256) void k_rows(
             const int gx = m0.x + ix + dx - b.lo[0], gy = m0.y + iy + dy - b.lo[1],
                       gz = m0.z + iz + dz - b.lo[2];
             const int64_t lin = gx + int64_t(b.n[0]) * (gy + int64_t(b.n[1]) * gz) - c0;
-            add = lin >= 0 && lin < span;
-            loc = int(lin);
+            if (lin >= 0 && lin < span) {
+              const int64_t pr = int64_t((unsigned long long)(unsigned)m1.z |
+                                         ((unsigned long long)(unsigned)m1.w << 32)) + q;
+              const uint8_t kp = keep[pr];
+              const T v = pval[int64_t(m0.w) * vplane + pr * 8 + jj];
+              add[ch] = kp != 0;
+              val[ch] = v;
+              loc[ch] = int(lin);
+            }
           }
         }
-        if (add) flg[loc] = 1;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          wave_lds_sync();
-          if (add && qq == u)
-            __hip_atomic_fetch_add(&acc[loc], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        for (int ch = 0; ch < kRowChunks; ++ch) {
+          if (add[ch]) flg[loc[ch]] = 1;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            wave_lds_sync();
+            if (add[ch] && qq == u)
+              __hip_atomic_fetch_add(&acc[loc[ch]], val[ch], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WAVEFRONT);
+          }
         }
       }
     }
@@ -700,34 +732,48 @@ __global__ void k_lumped(int64_t n_v, const int64_t* __restrict__ vt_ptr,
   minv[i] = (s > 0.0) ? T(1.0 / s) : T(0);
 }
 
-__global__ void k_mass_values(int64_t n_v, const int64_t* __restrict__ vt_ptr,
-                              const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
-                              const double* __restrict__ tetvol, const int64_t* __restrict__ rowptr,
-                              const int32_t* __restrict__ col, double* __restrict__ val,
-                              float* __restrict__ val32, double* __restrict__ dinv) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// Consistent mass rows M_il = Σ_{T ∋ i, l} |T|(1 + δ_il)/20, one wave per
+// vertex: lane k holds column k of the row, and the incident tets are
+// broadcast one at a time (sum order = incident-tet order).
+__global__ __launch_bounds__(256) void k_mass_values(
+    int64_t n_v, const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_tet,
+    const int32_t* __restrict__ tets, const double* __restrict__ tetvol,
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    double* __restrict__ val, float* __restrict__ val32, double* __restrict__ dinv) {
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = lane_id();
   if (i >= n_v) return;
   const int64_t rb = rowptr[i], re = rowptr[i + 1];
-  for (int64_t k = rb; k < re; ++k) val[k] = 0.0;
-  for (int64_t k = vt_ptr[i]; k < vt_ptr[i + 1]; ++k) {
-    const int64_t t = vt_tet[k];
-    const double w = tetvol[t] / 20.0;
-    for (int q = 0; q < 4; ++q) {
-      const int l = tets[4 * t + q];
-      int64_t lo = rb, hi = re;  // binary search for column l
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (col[mid] < l) lo = mid + 1; else hi = mid;
+  const int64_t tb = vt_ptr[i], te = vt_ptr[i + 1];
+  double diag = 0.0;
+  for (int64_t c0 = rb; c0 < re; c0 += kWave) {
+    const bool has = c0 + lane < re;
+    const int l = has ? col[c0 + lane] : -1;
+    double a = 0.0;
+    for (int64_t k0 = tb; k0 < te; k0 += kWave) {
+      const int nk = int(min<int64_t>(kWave, te - k0));
+      int4 tv = make_int4(-1, -1, -1, -1);
+      double w = 0.0;
+      if (lane < nk) {
+        const int64_t t = vt_tet[k0 + lane];
+        tv = *reinterpret_cast<const int4*>(tets + 4 * t);
+        w = tetvol[t] / 20.0;
       }
-      val[lo] += (int64_t(l) == i) ? 2.0 * w : w;
+      for (int k = 0; k < nk; ++k) {
+        const int v0 = __builtin_amdgcn_readlane(tv.x, k), v1 = __builtin_amdgcn_readlane(tv.y, k),
+                  v2 = __builtin_amdgcn_readlane(tv.z, k), v3 = __builtin_amdgcn_readlane(tv.w, k);
+        const double wk = __shfl(w, k, kWave);
+        if (l == v0 || l == v1 || l == v2 || l == v3) a += (int64_t(l) == i) ? 2.0 * wk : wk;
+      }
+    }
+    if (has) {
+      val[c0 + lane] = a;
+      if (val32) val32[c0 + lane] = float(a);
+      if (int64_t(l) == i) diag = a;
     }
   }
-  double diag = 0.0;
-  for (int64_t k = rb; k < re; ++k) {
-    if (int64_t(col[k]) == i) diag = val[k];
-    if (val32) val32[k] = float(val[k]);
-  }
-  dinv[i] = (diag > 0.0) ? 1.0 / diag : 0.0;
+  diag = wave_sum(diag);
+  if (lane == 0) dinv[i] = (diag > 0.0) ? 1.0 / diag : 0.0;
 }
 
 inline unsigned blocks_for(int64_t n, int threads) {
@@ -904,7 +950,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->rowtmpoff, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
   {
     ProfScope ps("rows_box", s);
-    k_row_box<<<blocks_for(3 * n_v, 256), 256, 0, s>>>(
+    k_row_box<<<blocks_for(3 * n_v * kBoxG, 256), 256, 0, s>>>(
         n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->rng.as<CellRange>(),
         c->rowbox.as<RowBox>(), c->rowcap.as<int64_t>());
   }
@@ -960,7 +1006,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
                                                    c->vt_tet.as<int32_t>(), c->tetvol.as<double>(),
                                                    c->mlump.as<double>(), c->minv.as<T>());
   if (c->has_M) {
-    k_mass_values<<<blocks_for(n_v, 256), 256, 0, s>>>(
+    k_mass_values<<<blocks_for(n_v * kWave, 256), 256, 0, s>>>(
         n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
         c->tetvol.as<double>(), c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>(),
         c->M.val.as<double>(), c->precision == IBVT_FP32_MIXED ? c->Mval32.as<float>() : nullptr,

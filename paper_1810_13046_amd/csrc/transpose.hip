@@ -25,13 +25,16 @@ __global__ void k_compact(int64_t n, const int32_t* __restrict__ mark,
 }
 
 // keys[k] = compacted column of nonzero k; idx[k] = k; row[k] = its row.
-__global__ void k_keys(int64_t n_rows, const int64_t* __restrict__ rowptr,
-                       const int32_t* __restrict__ col, const int64_t* __restrict__ cidx,
-                       int32_t* __restrict__ keys, int32_t* __restrict__ idx,
-                       int32_t* __restrict__ row) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// One wave per row (coalesced writes).
+__global__ __launch_bounds__(256) void k_keys(int64_t n_rows, const int64_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col,
+                                              const int64_t* __restrict__ cidx,
+                                              int32_t* __restrict__ keys, int32_t* __restrict__ idx,
+                                              int32_t* __restrict__ row) {
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = lane_id();
   if (i >= n_rows) return;
-  for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+  for (int64_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += kWave) {
     keys[k] = int32_t(cidx[col[k]]);
     idx[k] = int32_t(k);
     row[k] = int32_t(i);
@@ -114,7 +117,7 @@ int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
   int32_t* perm = reinterpret_cast<int32_t*>(base + 3 * n4);
   int32_t* row = reinterpret_cast<int32_t*>(base + 4 * n4);
   void* temp = base + 5 * n4;
-  k_keys<<<blocks_for(c->n_vert, 256), 256, 0, s>>>(c->n_vert, B.rowptr.as<int64_t>(),
+  k_keys<<<blocks_for(c->n_vert * kWave, 256), 256, 0, s>>>(c->n_vert, B.rowptr.as<int64_t>(),
                                                     B.col.as<int32_t>(), c->cidx.as<int64_t>(),
                                                     keys, idx, row);
   if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx, perm,
