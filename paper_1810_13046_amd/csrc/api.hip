@@ -103,13 +103,14 @@ void release_csr(ibvt_coupling* c, Csr& m) {
 }
 
 void release_all(ibvt_coupling* c) {
-  DevBuf* bufs[] = {&c->lat, &c->X, &c->tets, &c->vt_ptr, &c->vt_tet, &c->tetvol, &c->tetgeo, &c->rng,
-                    &c->cnt, &c->pair_off, &c->owner, &c->pval, &c->keep, &c->rownnz, &c->mark,
-                    &c->cidx, &c->tbuf, &c->mlump, &c->minv, &c->Mval32, &c->Mdiag_inv,
-                    &c->flags_dev, &c->counters, &c->scan_tmp, &c->work, &c->work2, &c->zbuf,
-                    &c->pool, &c->sub_begin, &c->sub_cnt, &c->paircoef, &c->order,
-                    &c->pscan, &c->rowbox, &c->rowcap,
-                    &c->rowtmpoff, &c->rowtmpcol, &c->rowtmpval};
+  DevBuf* bufs[] = {&c->lat,      &c->X,         &c->tets,      &c->vt_ptr,    &c->vt_tet,
+                    &c->tetvol,   &c->tetgeo,    &c->rng,       &c->pmom,      &c->cnt,
+                    &c->pair_off, &c->owner,     &c->pval,      &c->keep,      &c->rownnz,
+                    &c->mark,     &c->cidx,      &c->tbuf,      &c->mlump,     &c->minv,
+                    &c->Mval32,   &c->Mdiag_inv, &c->flags_dev, &c->counters,  &c->scan_tmp,
+                    &c->work,     &c->work2,     &c->zbuf,      &c->pool,      &c->sub_begin,
+                    &c->sub_cnt,  &c->paircoef,  &c->order,     &c->pscan,     &c->rowbox,
+                    &c->rowcap,   &c->rowtmpoff, &c->rowtmpcol, &c->rowtmpval};
   for (DevBuf* b : bufs) release(c, *b);
   for (int d = 0; d < 3; ++d) {
     release_csr(c, c->B[d]);
@@ -382,7 +383,7 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->device_bytes = c->device_bytes;
   info->assemblies = c->stats.assemblies;
   info->subtets = c->stats.subtets;
-  info->piece_store = c->pool_valid ? 1 : 0;
+  info->piece_store = c->mom_valid ? 1 : 0;
   return IBVT_OK;
 }
 

@@ -414,15 +414,18 @@ __device__ __forceinline__ int owner_lane(int excl, int s) {
   return lo;
 }
 
-// (III) integrate λ_i N_j on every stored sub-tetrahedron and sum per pair
-// into pval[i][pair][j] (local-vertex major: each vertex row of a pair is 8
+// (III) integrate every stored sub-tetrahedron: its 35 moments (cell-local,
+// centred) with the 14-point rule, summed per pair in record order through
+// LDS (deterministic) into pmom[pair][m] (rows of kMomPad).  Then each lane
+// turns its pair's moments into the 4 x 8 values ∫ λ_i N_j, written to
+// pval[i][pair][j] (local-vertex major: each vertex row of a pair is 8
 // contiguous values).
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_integrate(
     int64_t n_pairs, const uint8_t* __restrict__ keep, const T* __restrict__ pool,
     const int64_t* __restrict__ sub_begin, const uint8_t* __restrict__ sub_cnt,
-    const T* __restrict__ coef, T* __restrict__ pval) {
-  __shared__ T red[kWave][33];
+    const T* __restrict__ coef, T* __restrict__ pval, T* __restrict__ pmom) {
+  __shared__ T red[kWave][kMom];
   __shared__ int rown[kWave];
   __shared__ int rlast[kWave];
   const int lane = threadIdx.x;
@@ -442,53 +445,59 @@ __global__ __launch_bounds__(kWave) void k_integrate(
   const int excl = incl - cnt;
   const int total = __shfl(incl, kWave - 1, kWave);
   T run = T(0);
-  const int64_t plane = n_pairs * 8;
   for (int s0 = 0; s0 < total; s0 += kWave) {
     const int s = s0 + lane;
     const int j = owner_lane(excl, s);
     const int ex_j = __shfl(excl, j, kWave);
     const int in_j = __shfl(incl, j, kWave);
     const long long bj = __shfl((long long)beg, j, kWave);
-    T acc[32];
+    T M[kMom];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) acc[k] = T(0);
+    for (int k = 0; k < kMom; ++k) M[k] = T(0);
     if (s < total) {
-      const T* cf = coef + (g0 + j) * kCoef;
-      T LA[4], LG[4][3];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        LA[i] = cf[i];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
-      }
       const T* rec = pool + (int64_t(bj) + (s - ex_j)) * kRecord;
       T y[4][3];
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
-      subtet_integrate<T>(y, rec[12], LA, LG, acc);
-      const T sc = cf[19];
-#pragma unroll
-      for (int k = 0; k < 32; ++k) acc[k] *= sc;
+      subtet_moments<T>(y, rec[12], M);
     }
 #pragma unroll
-    for (int k = 0; k < 32; ++k) red[lane][k] = acc[k];
+    for (int k = 0; k < kMom; ++k) red[lane][k] = M[k];
     rown[lane] = j;
     rlast[lane] = (s < total) && (s + 1 == in_j);
     __syncthreads();
-    if (lane < 32) {
+    if (lane < kMom) {
       const int rows = min(kWave, total - s0);
-      const int64_t vbase = int64_t(lane >> 3) * plane + (lane & 7);
       for (int r = 0; r < rows; ++r) {
         run += red[r][lane];
         if (rlast[r]) {
-          pval[vbase + (g0 + rown[r]) * 8] = run;
+          pmom[(g0 + rown[r]) * kMomPad + lane] = run;
           run = T(0);
         }
       }
     }
     __syncthreads();
+  }
+  // the block barrier above orders these reads after the other lanes' writes
+  if (cnt > 0) {
+    T M[kMomPad];
+    load_row<kMomPad>(pmom + pj * kMomPad, M);
+    const T* cf = coef + pj * kCoef;
+    T LA[4], LG[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      LA[i] = cf[i];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
+    }
+    const T sc = cf[19];
+    const int64_t plane = n_pairs * 8;
+    T b[4][8];
+    mom_to_b<T>(M, LA, LG, [&](int i, int jj, T v) { b[i][jj] = sc * v; });
+#pragma unroll
+    for (int i = 0; i < 4; ++i) store_row<8>(pval + i * plane + pj * 8, b[i]);
   }
 }
 
@@ -844,6 +853,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
   if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 32 * sizeof(T)))) return st;
+  c->mom_valid = false;
+  if ((st = ensure(c, c->pmom, size_t(n_pairs + 1) * kMomPad * sizeof(T)))) return st;
   k_owner<<<blocks_for(3 * n_t, 256), 256, 0, s>>>(3 * n_t, c->pair_off.as<int64_t>(),
                                                    c->owner.as<int32_t>());
   // piece store: the fan sub-tetrahedra of every kept piece (integrated
@@ -941,7 +952,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     ProfScope ps("integrate", s);
     k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
         n_pairs, c->keep.as<uint8_t>(), c->pool.as<T>(), c->sub_begin.as<int64_t>(),
-        c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), c->pval.as<T>());
+        c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), c->pval.as<T>(), c->pmom.as<T>());
   }
   if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
   // (IV) global assembly: rows of B^d
@@ -1021,11 +1032,12 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   c->stats.dropped = int64_t(cnt[kCntDropped]);
   c->stats.zero_tets = int64_t(cnt[kCntZeroTets]);
   c->stats.subtets = int64_t(cnt[kCntSubtets]);
-  c->pool_valid = c->store_pieces && c->pool_needed <= c->pool_cap;
+  c->mom_valid = c->store_pieces;
   if (!c->store_pieces) {
-    // memory-saving mode: the reverse mode clips again
+    // memory-saving mode: no piece store kept; the reverse mode clips again
     if ((st = hip_check(hipStreamSynchronize(s), "sync"))) return st;
     release(c, c->pool);
+    release(c, c->pmom);
     c->pool_cap = 0;
   }
   c->stats.assemblies += 1;

@@ -61,4 +61,35 @@ struct CellRange {
   int32_t n[3];
 };
 
+// Copies n values (n a multiple of 16 bytes' worth) between a 16-byte
+// aligned row in memory and registers with 16-byte accesses.
+template <int N, typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ src, T (&dst)[N]) {
+  static_assert((N * sizeof(T)) % 16 == 0, "row of whole 16-byte words");
+  constexpr int W = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(W)));
+  const V* s = reinterpret_cast<const V*>(src);
+#pragma unroll
+  for (int k = 0; k < N / W; ++k) {
+    const V v = s[k];
+#pragma unroll
+    for (int e = 0; e < W; ++e) dst[k * W + e] = v[e];
+  }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void store_row(T* __restrict__ dst, const T (&src)[N]) {
+  static_assert((N * sizeof(T)) % 16 == 0, "row of whole 16-byte words");
+  constexpr int W = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(W)));
+  V* d = reinterpret_cast<V*>(dst);
+#pragma unroll
+  for (int k = 0; k < N / W; ++k) {
+    V v;
+#pragma unroll
+    for (int e = 0; e < W; ++e) v[e] = src[k * W + e];
+    d[k] = v;
+  }
+}
+
 }  // namespace ibvt

@@ -363,6 +363,206 @@ __host__ __device__ inline void subtet_grad(const T y[4][3], T wscale, const T L
   }
 }
 
+// ---------------------------------------------------------------------------
+// Piece moments.  Every integrand of the transfer and of its shape
+// derivative is a polynomial of degree <= 4 on a piece (λ_i N_j, λ_a w ∂_k U,
+// w U with w, λ linear and N_j, U trilinear), so the 35 moments
+//   M_α = ∫_piece s^α,  s = ξ − (½, ½, ½),  |α| <= 4
+// (cell-local coordinates centred in the cell, which keeps the
+// recombination well conditioned) determine all of them.  Moments are summed
+// per sub-tetrahedron with the 14-point rule (exact to degree 5) and per
+// piece over its fan.
+// ---------------------------------------------------------------------------
+constexpr int kMom = 35;
+constexpr int kMomPad = 36;  // per-pair stride of the moment store (16-byte rows)
+
+struct MomTable {
+  int idx[5][5][5];
+  constexpr MomTable() : idx{} {
+    for (int x = 0; x < 5; ++x)
+      for (int y = 0; y < 5; ++y)
+        for (int z = 0; z < 5; ++z) idx[x][y][z] = -1;
+    int n = 0;
+    for (int x = 0; x <= 4; ++x)
+      for (int y = 0; y <= 4 - x; ++y)
+        for (int z = 0; z <= 4 - x - y; ++z) idx[x][y][z] = n++;
+  }
+};
+constexpr MomTable kMomTable{};
+// position of s_x^a s_y^b s_z^c (a + b + c <= 4) in the moment vector
+__host__ __device__ constexpr int mom_idx(int a, int b, int c) { return kMomTable.idx[a][b][c]; }
+
+// M += w · s^α for every α (the moment order is a, then b, then c ascending)
+template <typename T>
+__host__ __device__ __forceinline__ void mom_point(T sx, T sy, T sz, T w, T M[kMom]) {
+  const T x2 = sx * sx, y2 = sy * sy, z2 = sz * sz;
+  const T px[5] = {T(1), sx, x2, x2 * sx, x2 * x2};
+  const T py[5] = {T(1), sy, y2, y2 * sy, y2 * y2};
+  const T pz[5] = {T(1), sz, z2, z2 * sz, z2 * z2};
+  int k = 0;
+#pragma unroll
+  for (int a = 0; a <= 4; ++a) {
+    const T wa = w * px[a];
+#pragma unroll
+    for (int b = 0; b <= 4 - a; ++b) {
+      const T wab = wa * py[b];
+#pragma unroll
+      for (int c = 0; c <= 4 - a - b; ++c) M[k++] += wab * pz[c];
+    }
+  }
+}
+
+// Adds the unscaled moments of one sub-tetrahedron (vertices y in cell-local
+// coordinates, weight scale = its determinant) to M.
+template <typename T>
+__host__ __device__ inline void subtet_moments(const T y[4][3], T wscale, T M[kMom]) {
+  T yc[4][3], S[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) yc[v][e] = y[v][e] - T(0.5);
+    S[e] = yc[0][e] + yc[1][e] + yc[2][e] + yc[3][e];
+  }
+  const T a1 = T(kQA1), c1 = T(1.0 - 4.0 * kQA1), w1 = T(kQW1) * wscale;
+  const T a2 = T(kQA2), c2 = T(1.0 - 4.0 * kQA2), w2 = T(kQW2) * wscale;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    mom_point<T>(a1 * S[0] + c1 * yc[k][0], a1 * S[1] + c1 * yc[k][1], a1 * S[2] + c1 * yc[k][2],
+                 w1, M);
+    mom_point<T>(a2 * S[0] + c2 * yc[k][0], a2 * S[1] + c2 * yc[k][1], a2 * S[2] + c2 * yc[k][2],
+                 w2, M);
+  }
+  const T pb = T(2.0 * kQB - 0.5), ps = T(0.5 - kQB), w3 = T(kQW3) * wscale;
+  const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int k = pk[q], l = pl[q];
+    mom_point<T>(pb * (yc[k][0] + yc[l][0]) + ps * S[0], pb * (yc[k][1] + yc[l][1]) + ps * S[1],
+                 pb * (yc[k][2] + yc[l][2]) + ps * S[2], w3, M);
+  }
+}
+
+// Q1 hats in centred coordinates: h_0 = ½ − s, h_1 = ½ + s.  Turns the 8
+// values G[a + 2b + 4c] = ∫ s_x^a s_y^b s_z^c f into ∫ h_a h_b h_c f
+// (one axis at a time: ∫ h_0 g = ½∫g − ∫ s g, ∫ h_1 g = ½∫g + ∫ s g).
+template <typename T>
+__host__ __device__ __forceinline__ void hat_butterfly(T G[8]) {
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int st = 1 << e;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j & st) continue;
+      const T g0 = G[j], g1 = G[j + st];
+      G[j] = T(0.5) * g0 - g1;
+      G[j + st] = T(0.5) * g0 + g1;
+    }
+  }
+}
+
+// ∫ λ_i N_j (i = tet vertex, j = cell corner a + 2b + 4c) from the piece's
+// moments M (any memory), with λ_i(ξ) = LA[i] + LG[i]·ξ: calls
+// put(i, j, value) with the value unscaled like M.
+template <typename T, typename F>
+__host__ __device__ inline void mom_to_b(const T* M, const T LA[4], const T LG[4][3], F&& put) {
+  T Fv[4][8];  // Fv[0][j] = ∫ N_j, Fv[1 + e][j] = ∫ s_e N_j
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      Fv[f][j] = M[mom_idx((j & 1) + (f == 1), ((j >> 1) & 1) + (f == 2), (j >> 2) + (f == 3))];
+    hat_butterfly<T>(Fv[f]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T lac = LA[i] + T(0.5) * (LG[i][0] + LG[i][1] + LG[i][2]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      put(i, j, lac * Fv[0][j] + LG[i][0] * Fv[1][j] + LG[i][1] * Fv[2][j] + LG[i][2] * Fv[3][j]);
+  }
+}
+
+// Shape-derivative integrands of one piece from its moments: with
+// w = Σ_i z_i λ_i and U = Σ_j u_j N_j (u at the cell's corners),
+//   A[a*3 + k] = ∫ λ_a w ∂U/∂ξ_k,   Bs = ∫ w U      (unscaled like M).
+template <typename T>
+__host__ __device__ inline void mom_shape(const T M[kMom], const T LA[4], const T LG[4][3],
+                                          const T zl[4], const T ul[8], T A[12], T& Bs) {
+  T lac[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) lac[i] = LA[i] + T(0.5) * (LG[i][0] + LG[i][1] + LG[i][2]);
+  // w = W0 + WG·s
+  T W0 = T(0), WG[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    W0 += zl[i] * lac[i];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) WG[e] += zl[i] * LG[i][e];
+  }
+  // U = Σ_α Uc[α] s^α over α in {0,1}^3 (u_0 h_0 + u_1 h_1 = ½(u_0 + u_1) + (u_1 − u_0) s)
+  T Uc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) Uc[j] = ul[j];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int st = 1 << e;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j & st) continue;
+      const T u0 = Uc[j], u1 = Uc[j + st];
+      Uc[j] = T(0.5) * (u0 + u1);
+      Uc[j + st] = u1 - u0;
+    }
+  }
+  Bs = T(0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int a = j & 1, b = (j >> 1) & 1, c = j >> 2;
+    Bs += Uc[j] * (W0 * M[mom_idx(a, b, c)] + WG[0] * M[mom_idx(a + 1, b, c)] +
+                   WG[1] * M[mom_idx(a, b + 1, c)] + WG[2] * M[mom_idx(a, b, c + 1)]);
+  }
+  // quadratic monomials β: 1, s_x, s_y, s_z, s_x², s_y², s_z², s_x s_y, s_x s_z, s_y s_z
+  constexpr int bx[10] = {0, 1, 0, 0, 2, 0, 0, 1, 1, 0};
+  constexpr int by[10] = {0, 0, 1, 0, 0, 2, 0, 1, 0, 1};
+  constexpr int bz[10] = {0, 0, 0, 1, 0, 0, 2, 0, 1, 1};
+  // E_k[β] = Σ_{α: α_k = 1} Uc[α] M[β + α − e_k]  (= ∫ s^β ∂U/∂s_k)
+  T E[3][10];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (!((j >> k) & 1)) continue;
+        const int a = (j & 1) - (k == 0), b = ((j >> 1) & 1) - (k == 1), c = (j >> 2) - (k == 2);
+        acc += Uc[j] * M[mom_idx(bx[q] + a, by[q] + b, bz[q] + c)];
+      }
+      E[k][q] = acc;
+    }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    // λ_a w = Σ_β q_β s^β
+    T qv[10];
+    qv[0] = lac[a] * W0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      qv[1 + e] = lac[a] * WG[e] + LG[a][e] * W0;
+      qv[4 + e] = LG[a][e] * WG[e];
+    }
+    qv[7] = LG[a][0] * WG[1] + LG[a][1] * WG[0];
+    qv[8] = LG[a][0] * WG[2] + LG[a][2] * WG[0];
+    qv[9] = LG[a][1] * WG[2] + LG[a][2] * WG[1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int q = 0; q < 10; ++q) acc += qv[q] * E[k][q];
+      A[a * 3 + k] = acc;
+    }
+  }
+}
+
 // Tet data shared by the clip kernels: vertices, orientation, volume and
 // barycentric gradients.
 struct TetGeom {

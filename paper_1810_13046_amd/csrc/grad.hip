@@ -8,8 +8,10 @@
 // and, contracted with z (solid) and u (fluid), with w = Σ z_i λ_i and
 // U = Σ u_j N_j (the Q1 interpolant):
 //   z^T (∂B/∂X_{a,k}) u = Σ_{T∋a} [ ∫ λ_a w ∂_k U + ∂_k λ_a ∫ w U ].
-// The kernel below computes the bracket per (tet, component, cell) pair by
-// re-clipping the piece; k_grad_gather sums it per vertex in a fixed order
+// The bracket is a polynomial integral of degree <= 4 on each (tet,
+// component, cell) piece: k_shape_mom takes it from the piece moments kept
+// by the assembly, k_shape_pairs (when no moments are kept) clips the piece
+// again and integrates it; k_grad_gather sums it per vertex in a fixed order
 // and subtracts the mass term  z^T (∂S/∂X) u_s, with ∂|T|/∂X_a = |T| ∇λ_a
 // (S consistent: |T|(1+δ_il)/20 per tet; lumped: |T|/4 on the diagonal).
 #include "geometry.hpp"
@@ -91,124 +93,61 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
 
-// Same terms from the piece store: the sub-tetrahedra written by the
-// assembly are integrated again with the new weights, without clipping.
-// One wave per group of 64 consecutive pairs (their records are
-// contiguous); one record per lane, per-pair sums in record order (LDS).
-__device__ __forceinline__ int owner_lane_g(int excl, int s) {
-  int lo = 0, hi = kWave - 1;
-#pragma unroll
-  for (int it = 0; it < 6; ++it) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int e = __shfl(excl, mid, kWave);
-    if (e <= s) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
+// Pair terms from the stored piece moments (no clipping, no quadrature): one
+// lane per pair.
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_shape_pool(
+__global__ __launch_bounds__(256) void k_shape_mom(
     int64_t n_pairs, int64_t n_t, int64_t n_v, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-    const uint8_t* __restrict__ keep, const T* __restrict__ pool,
-    const int64_t* __restrict__ sub_begin, const uint8_t* __restrict__ sub_cnt,
-    const T* __restrict__ coef, const int32_t* __restrict__ tets, LatDesc ld,
-    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, T* __restrict__ pg) {
-  __shared__ T red[kWave][13];
-  __shared__ int rown[kWave];
-  __shared__ int rlast[kWave];
-  const int lane = threadIdx.x;
-  const int64_t g0 = int64_t(blockIdx.x) * kWave;
-  const int64_t pj = g0 + lane;
-  int cnt = 0;
-  int64_t beg = 0;
-  if (pj < n_pairs) {
-    if (keep[pj]) {
-      cnt = sub_cnt[pj];
-      beg = sub_begin[pj];
+    const uint8_t* __restrict__ keep, const T* __restrict__ pmom, const T* __restrict__ coef,
+    const int32_t* __restrict__ tets, LatDesc ld, const T* __restrict__ z, const T* u0,
+    const T* u1, const T* u2, T* __restrict__ pg) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  T out[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[k] = T(0);
+  if (keep[p]) {
+    const int64_t tc = owner[p];
+    const int d = int(tc / n_t);
+    const int64_t t = tc - int64_t(d) * n_t;
+    const CellRange r = rng[tc];
+    const int64_t q = p - pair_off[tc];
+    const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
+                       r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+    const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
+    const T* zd = z + int64_t(d) * n_v;
+    const T zl[4] = {zd[tv.x], zd[tv.y], zd[tv.z], zd[tv.w]};
+    const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
+    const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
+    const int64_t n000 = ci[0] + NX * (ci[1] + NY * int64_t(ci[2]));
+    T ul[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      ul[j] = u[n000 + (j & 1) + NX * (((j >> 1) & 1) + NY * (j >> 2))];
+    const T* cf = coef + p * kCoef;
+    T LA[4], LG[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      LA[i] = cf[i];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
     }
-    if (cnt == 0)
-      for (int k = 0; k < 12; ++k) pg[pj * 12 + k] = T(0);
-  }
-  int incl = cnt;
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int y = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += y;
-  }
-  const int excl = incl - cnt;
-  const int total = __shfl(incl, kWave - 1, kWave);
-  T run = T(0);
-  for (int s0 = 0; s0 < total; s0 += kWave) {
-    const int s = s0 + lane;
-    const int j = owner_lane_g(excl, s);
-    const int ex_j = __shfl(excl, j, kWave);
-    const int in_j = __shfl(incl, j, kWave);
-    const long long bj = __shfl((long long)beg, j, kWave);
-    T out[12];
+    T M[kMomPad];
+    load_row<kMomPad>(pmom + p * kMomPad, M);
+    T A[12], Bs;
+    mom_shape<T>(M, LA, LG, zl, ul, A, Bs);
+    // ∂/∂x_k = (1/h_k) ∂/∂ξ_k; ∇λ_a = (cell-local gradient)/h
+    const T sc = cf[19];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) out[k] = T(0);
-    if (s < total) {
-      const int64_t p = g0 + j;
-      const int64_t tc = owner[p];
-      const int d = int(tc / n_t);
-      const int64_t t = tc - int64_t(d) * n_t;
-      const CellRange r = rng[tc];
-      const int64_t q = p - pair_off[tc];
-      const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
-                         r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
-      T zl[4];
-      for (int k = 0; k < 4; ++k) zl[k] = z[int64_t(d) * n_v + tets[4 * t + k]];
-      const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
-      const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
-      T ul[8];
-      for (int c = 0; c < 2; ++c)
-        for (int b = 0; b < 2; ++b)
-          for (int a = 0; a < 2; ++a)
-            ul[a + 2 * b + 4 * c] = u[(ci[0] + a) + NX * ((ci[1] + b) + NY * int64_t(ci[2] + c))];
-      const T* cf = coef + p * kCoef;
-      T LA[4], LG[4][3], A[12], Bs = T(0);
+    for (int k = 0; k < 3; ++k) {
+      const T ih = T(1) / cf[16 + k];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        LA[i] = cf[i];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
-      }
-#pragma unroll
-      for (int k = 0; k < 12; ++k) A[k] = T(0);
-      const T* rec = pool + (int64_t(bj) + (s - ex_j)) * kRecord;
-      T y[4][3];
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
-      subtet_grad<T>(y, rec[12], LA, LG, zl, ul, A, Bs);
-      // ∂/∂x_k = (1/h_k) ∂/∂ξ_k; ∇λ_a = (cell-local gradient)/h
-      const T sc = cf[19];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const T ih = T(1) / cf[16 + k];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) out[a * 3 + k] = sc * ih * (A[a * 3 + k] + LG[a][k] * Bs);
-      }
+      for (int a = 0; a < 4; ++a) out[a * 3 + k] = sc * ih * (A[a * 3 + k] + LG[a][k] * Bs);
     }
-#pragma unroll
-    for (int k = 0; k < 12; ++k) red[lane][k] = out[k];
-    rown[lane] = j;
-    rlast[lane] = (s < total) && (s + 1 == in_j);
-    __syncthreads();
-    if (lane < 12) {
-      const int rows = min(kWave, total - s0);
-      for (int rr = 0; rr < rows; ++rr) {
-        run += red[rr][lane];
-        if (rlast[rr]) {
-          pg[(g0 + rown[rr]) * 12 + lane] = run;
-          run = T(0);
-        }
-      }
-    }
-    __syncthreads();
   }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) pg[p * 12 + k] = out[k];
 }
 
 // One wavefront per vertex a: lanes take (incident tet, component) items,
@@ -274,14 +213,13 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   T* pg = c->work2.as<T>();
   unsigned* flags = c->flags_dev.as<unsigned>();
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
-  if (c->n_pairs > 0 && c->pool_valid) {
-    ProfScope ps("shape_pool", s);
-    k_shape_pool<T><<<unsigned(ceil_div(c->n_pairs, kWave)), kWave, 0, s>>>(
+  if (c->n_pairs > 0 && c->mom_valid) {
+    ProfScope ps("shape_moments", s);
+    k_shape_mom<T><<<unsigned(ceil_div(c->n_pairs, 256)), 256, 0, s>>>(
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
-        c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pool.as<T>(),
-        c->sub_begin.as<int64_t>(), c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(),
-        c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z),
-        static_cast<const T*>(u[0]), static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg);
+        c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pmom.as<T>(), c->paircoef.as<T>(),
+        c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
+        static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg);
   } else if (c->n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
     ProfScope ps("shape_pairs", s);

@@ -62,12 +62,13 @@ struct ibvt_coupling {
   int64_t n_pairs = 0;
   ibvt::DevBuf owner;        // int32 n_pairs
   ibvt::DevBuf pval;         // T n_pairs*32
+  ibvt::DevBuf pmom;         // T n_pairs*kMomPad: per-pair piece moments (reverse mode)
   ibvt::DevBuf keep;         // uint8 n_pairs
-  bool store_pieces = true;  // keep the sub-tetrahedra of every piece
+  bool store_pieces = true;  // keep the moments of every piece (reverse mode)
   ibvt::DevBuf pool;         // T records of kRecord values
   int64_t pool_cap = 0;      // records
   int64_t pool_needed = 0;   // records the last assembly asked for
-  bool pool_valid = false;   // every kept piece of the last assembly is stored
+  bool mom_valid = false;    // pmom holds the moments of every kept piece of the last assembly
   ibvt::DevBuf sub_begin;    // int64 n_pairs: first record of the pair
   ibvt::DevBuf sub_cnt;      // uint8 n_pairs: records of the pair
   ibvt::DevBuf paircoef;     // T n_pairs*kCoef: per-pair λ coefficients
