@@ -36,11 +36,40 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP32_VEC_PEAK_TFLOPS = 157.3
 FP64_VEC_PEAK_TFLOPS = 78.6
-# flops per quadrature point of the 4 x 8 mortar products (hats, 8 Q1 basis
-# products, 4 affine λ evaluations, 32 multiply-adds), 14 points per
-# sub-tetrahedron of a clipped piece
-FLOPS_PER_POINT = 107
+
+# Algorithmic FP64 flops of the clip step (double arithmetic only; the
+# vertex graph bookkeeping is integer work and not counted):
+#   signed distance of a vertex to a plane       2  (subtract, sign)
+#   cut point on an edge                        11  (t = s_v/(s_v - s_u): 2;
+#                                                    p = v + t(u - v): 3 x 3)
+#   sub-tetrahedron record                      47  (12 cell-local coordinates
+#                                                    x 2, determinant 23)
+#   pair set-up                                 50  (cell box, λ in cell-local
+#                                                    coordinates, drop test)
+CLIP_FLOPS = dict(dist=2, cut=11, subtet=47, pair=50)
+# flops per quadrature point of the 35 piece moments: point 6, powers 9,
+# partial products 14, 35 multiply-adds 70
+MOM_FLOPS_PER_POINT = 99
 POINTS_PER_SUBTET = 14
+
+# HBM traffic of the clip step (both slot-class launches of one assembly) on
+# the three-body workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter
+# passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
+# summary and its commands are in profiles/.  Reported only while the clip
+# sources are the ones the counters were taken on.
+CLIP_TRAFFIC = dict(sources_sha256="149bbb65d5cd590c601ca7b33e46571c92bad0d2a78d039cff461352e5ff343c",
+                    bytes_mixed=55812873344)
+CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
+                "paper_1810_13046_amd/csrc/common.hpp"]
+
+
+def sources_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -197,6 +226,34 @@ def cpu_baseline(W, dev, tets_per_body):
                        f"in {dt:.1f}s")
 
 
+def roofline(name, prof, info, precision):
+    """Roofline object of one profiled step of kernel `name`: algorithmic
+    work per launch (see the constants above) over its average launch time
+    (HIP events on the library's stream)."""
+    launches, total_ms = prof
+    ms = total_ms / launches
+    out = dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None,
+               traffic=None, launch_ms=ms)
+    if name == "clip":
+        flops = (CLIP_FLOPS["dist"] * info["dist_evals"] + CLIP_FLOPS["cut"] * info["cut_points"] +
+                 CLIP_FLOPS["subtet"] * info["subtets"] + CLIP_FLOPS["pair"] * info["pairs"])
+        achieved = flops / (ms * 1e-3) / 1e12
+        traffic = None
+        if (precision == "fp32" and CLIP_TRAFFIC["bytes_mixed"] is not None and
+                CLIP_TRAFFIC["sources_sha256"] == sources_sha256(CLIP_SOURCES)):
+            traffic = CLIP_TRAFFIC["bytes_mixed"]
+        out.update(bound="alu", achieved=achieved, peak=FP64_VEC_PEAK_TFLOPS, unit="TFLOP/s",
+                   frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=traffic,
+                   algorithmic_flops_per_launch=flops, precision="fp64 (clipping is double)")
+    elif name == "integrate":
+        flops = info["subtets"] * POINTS_PER_SUBTET * MOM_FLOPS_PER_POINT
+        peak = FP32_VEC_PEAK_TFLOPS if precision == "fp32" else FP64_VEC_PEAK_TFLOPS
+        achieved = flops / (ms * 1e-3) / 1e12
+        out.update(bound="alu", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                   algorithmic_flops_per_launch=flops)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,17 +323,7 @@ def main():
     # dominant kernel of the mixed step and its roofline
     per_kernel = {k: v[1] for k, v in prof_mixed.items()}
     dom = max(per_kernel, key=per_kernel.get)
-    launches = prof_mixed[dom][0]
-    avg_ms = per_kernel[dom] / launches
-    if dom == "clip_integrate":
-        flops = info["subtets"] * POINTS_PER_SUBTET * FLOPS_PER_POINT
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP32_VEC_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=achieved / FP32_VEC_PEAK_TFLOPS, traffic=None,
-                    launch_ms=avg_ms, algorithmic_flops_per_launch=flops)
-    else:
-        roof = dict(kernel=dom, bound="unknown", achieved=None, peak=None, unit=None, frac=None,
-                    traffic=None, launch_ms=avg_ms)
+    roof = roofline(dom, prof_mixed[dom], info, "fp32")
     roof_apply = dict(kernel="spmv_B (lumped velocity apply)", bound="hbm",
                       achieved=rates_mixed["velocity_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=rates_mixed["velocity_GBs"] / HBM_PEAK_GBS, traffic=None,

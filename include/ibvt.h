@@ -69,9 +69,9 @@ extern "C" {
 
 /* assemble_coupling flags. */
 #define IBVT_BUILD_CONSISTENT_M 1u  /* also build the consistent mass matrix */
-#define IBVT_NO_PIECE_STORE 2u      /* do not keep the clipped pieces'
-                                       sub-tetrahedra; the reverse-mode calls
-                                       then clip again (less device memory) */
+#define IBVT_NO_PIECE_STORE 2u      /* do not keep the pieces' moments; the
+                                       reverse-mode calls then clip again
+                                       (less device memory) */
 
 /* transfer_force flags. */
 #define IBVT_FORCE_IS_LOAD 1u   /* f_s is a load vector: apply S^{-1}
@@ -129,8 +129,11 @@ typedef struct {
   int64_t assemblies;        /* assemblies done on this handle */
   int64_t subtets;           /* sub-tetrahedra integrated by the last
                                 assembly (each gets the 14-point rule) */
-  int64_t piece_store;       /* 1 if every kept piece's sub-tetrahedra are
-                                stored for the reverse mode */
+  int64_t piece_store;       /* 1 if every kept piece's moments are stored
+                                for the reverse mode */
+  int64_t dist_evals;        /* plane distances evaluated by the last
+                                assembly's clipping (vertices x planes) */
+  int64_t cut_points;        /* edge-plane intersection points it made */
 } ibvt_info;
 
 /*
@@ -141,9 +144,9 @@ typedef struct {
  *   in double, then quadrature exact for the degree-4 integrand), and global
  *   assembly.  Also builds B^dT (over the touched fluid nodes), the lumped
  *   mass and, with IBVT_BUILD_CONSISTENT_M, the consistent mass matrix.
- *   Unless IBVT_NO_PIECE_STORE is set, the sub-tetrahedra of every clipped
- *   piece are kept (about 3 per candidate pair, 13 values each) so that the
- *   reverse-mode calls integrate without clipping again.
+ *   Unless IBVT_NO_PIECE_STORE is set, the 35 moments of every piece
+ *   (monomials of degree <= 4 in cell-local coordinates) are kept, so that
+ *   the reverse-mode calls neither clip nor integrate again.
  *   precision: IBVT_FP64 or IBVT_FP32_MIXED.
  *   out: receives a new handle owned by the library (free with
  *   coupling_free).  On failure *out is set to NULL.

@@ -384,6 +384,8 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->assemblies = c->stats.assemblies;
   info->subtets = c->stats.subtets;
   info->piece_store = c->mom_valid ? 1 : 0;
+  info->dist_evals = c->stats.dist_evals;
+  info->cut_points = c->stats.cut_points;
   return IBVT_OK;
 }
 

@@ -101,33 +101,36 @@ __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t
                                                        double* __restrict__ part,
                                                        const CgScalars* sc) {
   __shared__ double red[3][kThreads / kWave];
-  const int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
   const int g = threadIdx.x % kMG;
   double loc[3] = {0, 0, 0};
   if (!sc || !sc->all) {
-    T s0 = 0, s1 = 0, s2 = 0;
-    if (i < n) {
-      for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
-        const int64_t j = col[k];
-        const T m = T(val[k]);
-        s0 += m * p[j];
-        s1 += m * p[n + j];
-        s2 += m * p[2 * n + j];
+    // grid-stride over groups of kThreads / kMG rows (few blocks: few partials)
+    for (int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
+         i - threadIdx.x / kMG < n; i += int64_t(gridDim.x) * (kThreads / kMG)) {
+      T s0 = 0, s1 = 0, s2 = 0;
+      if (i < n) {
+        for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
+          const int64_t j = col[k];
+          const T m = T(val[k]);
+          s0 += m * p[j];
+          s1 += m * p[n + j];
+          s2 += m * p[2 * n + j];
+        }
       }
-    }
 #pragma unroll
-    for (int o = kMG / 2; o > 0; o >>= 1) {
-      s0 += __shfl_xor(s0, o, kWave);
-      s1 += __shfl_xor(s1, o, kWave);
-      s2 += __shfl_xor(s2, o, kWave);
-    }
-    if (i < n && g == 0) {
-      q[i] = s0;
-      q[n + i] = s1;
-      q[2 * n + i] = s2;
-      loc[0] = double(p[i]) * double(s0);
-      loc[1] = double(p[n + i]) * double(s1);
-      loc[2] = double(p[2 * n + i]) * double(s2);
+      for (int o = kMG / 2; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o, kWave);
+        s1 += __shfl_xor(s1, o, kWave);
+        s2 += __shfl_xor(s2, o, kWave);
+      }
+      if (i < n && g == 0) {
+        q[i] = s0;
+        q[n + i] = s1;
+        q[2 * n + i] = s2;
+        loc[0] += double(p[i]) * double(s0);
+        loc[1] += double(p[n + i]) * double(s1);
+        loc[2] += double(p[2 * n + i]) * double(s2);
+      }
     }
   }
   if (!part) return;
@@ -290,26 +293,28 @@ __global__ __launch_bounds__(kThreads) void k_residual64(int64_t n, const int64_
                                                         double* __restrict__ res,
                                                         double* __restrict__ part) {
   __shared__ double red[6][kThreads / kWave];
-  const int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
   const int g = threadIdx.x % kMG;
   double loc[6] = {0, 0, 0, 0, 0, 0};
-  double s[3] = {0, 0, 0};
-  if (i < n) {
-    for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
-      const int64_t j = col[k];
-      for (int d = 0; d < 3; ++d) s[d] += val[k] * x[int64_t(d) * n + j];
+  for (int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
+       i - threadIdx.x / kMG < n; i += int64_t(gridDim.x) * (kThreads / kMG)) {
+    double s[3] = {0, 0, 0};
+    if (i < n) {
+      for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
+        const int64_t j = col[k];
+        for (int d = 0; d < 3; ++d) s[d] += val[k] * x[int64_t(d) * n + j];
+      }
     }
-  }
 #pragma unroll
-  for (int o = kMG / 2; o > 0; o >>= 1)
-    for (int d = 0; d < 3; ++d) s[d] += __shfl_xor(s[d], o, kWave);
-  if (i < n && g == 0) {
-    for (int d = 0; d < 3; ++d) {
-      const double bv = double(b[int64_t(d) * n + i]);
-      const double rv = bv - s[d];
-      res[int64_t(d) * n + i] = rv;
-      loc[d] = rv * rv;
-      loc[3 + d] = bv * bv;
+    for (int o = kMG / 2; o > 0; o >>= 1)
+      for (int d = 0; d < 3; ++d) s[d] += __shfl_xor(s[d], o, kWave);
+    if (i < n && g == 0) {
+      for (int d = 0; d < 3; ++d) {
+        const double bv = double(b[int64_t(d) * n + i]);
+        const double rv = bv - s[d];
+        res[int64_t(d) * n + i] = rv;
+        loc[d] += rv * rv;
+        loc[3 + d] += bv * bv;
+      }
     }
   }
   for (int d = 0; d < 6; ++d) {
@@ -350,9 +355,10 @@ __global__ void k_add_correction(int64_t n3, const float* __restrict__ e, double
 }
 
 inline unsigned nblk(int64_t n) { return unsigned(ceil_div(n > 0 ? n : 1, kThreads)); }
-// blocks of the row-group kernels (kThreads / kMG rows per block)
+// blocks of the row-group kernels (grid-stride over groups of kThreads / kMG
+// rows; capped so that their per-block partials stay few)
 inline unsigned nblk_rows(int64_t n) {
-  return unsigned(ceil_div(n > 0 ? n : 1, kThreads / kMG));
+  return unsigned(std::min<int64_t>(ceil_div(n > 0 ? n : 1, kThreads / kMG), 2048));
 }
 
 // Workspace layout for the CG (bytes): scalars, partials, 6 vectors of T
@@ -368,7 +374,8 @@ struct CgWork {
 
 int cg_workspace(ibvt_coupling* c, size_t tsize, CgWork& w) {
   const int64_t n = c->n_vert;
-  const int64_t nb = nblk_rows(n);  // >= nblk(n): partials of every kernel fit
+  // per-block partials of every CG kernel fit
+  const int64_t nb = std::max<int64_t>(nblk(n), nblk_rows(n));
   const size_t off_part = 256;
   const size_t off_tmp = off_part + size_t(nb) * 6 * sizeof(double);
   const size_t off_vec = (off_tmp + 16 * sizeof(double) + 255) & ~size_t(255);

@@ -302,6 +302,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   unsigned long long nk = 0, nd = 0, ns = 0;
+  ClipCount cc;
   unsigned long long cbase = 0;  // next free record of the wave's chunk
   int cleft = 0;                 // records left in it
   bool fail = false;
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
       int64_t t;
       pair_geometry(p, n_t, owner, pair_off, rng, tetgeo, lat, ld, d, t, ci, G, lo, hi);
       live = poly_init_tet(P, G.V, G.det < 0.0);
-      ok = poly_clip_box(P, live, lo, hi, G.mn, G.mx);
+      ok = poly_clip_box(P, live, lo, hi, G.mn, G.mx, &cc);
       if (ok) {
         want = poly_fan_prepare(P, live, seen);
         if (want < 0) {
@@ -388,11 +389,15 @@ __global__ __launch_bounds__(kWave) void k_clip(
   nk = wave_sum(nk);
   nd = wave_sum(nd);
   ns = wave_sum(ns);
+  const unsigned long long ndist = wave_sum((unsigned long long)cc.dist);
+  const unsigned long long ncut = wave_sum((unsigned long long)cc.cuts);
   const uint64_t fm = ballot64(fail);
   if (lane == 0) {
     if (nk) atomicAdd(&counters[kCntPieces], nk);
     if (nd) atomicAdd(&counters[kCntDropped], nd);
     if (ns) atomicAdd(&counters[kCntSubtets], ns);
+    if (ndist) atomicAdd(&counters[kCntDist], ndist);
+    if (ncut) atomicAdd(&counters[kCntCutPts], ncut);
     if (fm) atomicOr(flags, kFlagCapacity);
   }
 }
@@ -1032,6 +1037,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   c->stats.dropped = int64_t(cnt[kCntDropped]);
   c->stats.zero_tets = int64_t(cnt[kCntZeroTets]);
   c->stats.subtets = int64_t(cnt[kCntSubtets]);
+  c->stats.dist_evals = int64_t(cnt[kCntDist]);
+  c->stats.cut_points = int64_t(cnt[kCntCutPts]);
   c->mom_valid = c->store_pieces;
   if (!c->store_pieces) {
     // memory-saving mode: no piece store kept; the reverse mode clips again

@@ -22,7 +22,9 @@ enum Counter : int {
   kCntSubtets = 3,
   kCntPool = 4,
   kCntClass = 5,  // 5, 6, 7: pairs per cut class
-  kCntSlots = 8,
+  kCntDist = 8,   // signed distances evaluated by the clip
+  kCntCutPts = 9, // cut points made by the clip
+  kCntSlots = 10,
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -89,10 +89,18 @@ __host__ __device__ inline uint32_t poly_init_tet(const PolyView& P, const doubl
   return 0xFu;
 }
 
+// Work counts of the clip (for throughput figures): signed distances
+// evaluated and cut points made.
+struct ClipCount {
+  uint32_t dist = 0;
+  uint32_t cuts = 0;
+};
+
 // Keep the half-space sgn·(x_a − c) >= 0.  `live` is the mask of used
 // slots.  Returns false if the fixed capacity or a walk bound is exceeded.
 __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int a, double c,
-                                          double sgn) {
+                                          double sgn, ClipCount* cc = nullptr) {
+  if (cc) cc->dist += uint32_t(__builtin_popcount(live));
   uint32_t out = 0;
   for (uint32_t m = live; m; m &= m - 1) {
     const int v = ctz32(m);
@@ -161,6 +169,7 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
     P.nb(vcur) = nb_set(P.nb(vcur), 1, w);
   }
   live = in | newm;
+  if (cc) cc->cuts += uint32_t(__builtin_popcount(newm));
   return true;
 }
 
@@ -169,7 +178,7 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
 // skipped, and a box the tet only touches gives an empty piece.
 __host__ __device__ inline bool poly_clip_box(const PolyView& P, uint32_t& live, const double lo[3],
                                               const double hi[3], const double mn[3],
-                                              const double mx[3]) {
+                                              const double mx[3], ClipCount* cc = nullptr) {
   for (int a = 0; a < 3; ++a)
     if (mx[a] <= lo[a] || mn[a] >= hi[a]) {
       live = 0;
@@ -177,8 +186,8 @@ __host__ __device__ inline bool poly_clip_box(const PolyView& P, uint32_t& live,
     }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (live && mn[a] < lo[a] && !poly_clip(P, live, a, lo[a], 1.0)) return false;
-    if (live && mx[a] > hi[a] && !poly_clip(P, live, a, hi[a], -1.0)) return false;
+    if (live && mn[a] < lo[a] && !poly_clip(P, live, a, lo[a], 1.0, cc)) return false;
+    if (live && mx[a] > hi[a] && !poly_clip(P, live, a, hi[a], -1.0, cc)) return false;
   }
   return true;
 }

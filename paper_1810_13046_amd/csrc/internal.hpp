@@ -38,6 +38,7 @@ struct LatDesc {
 
 struct AsmStats {
   int64_t pairs = 0, pieces = 0, dropped = 0, zero_tets = 0, subtets = 0;
+  int64_t dist_evals = 0, cut_points = 0;  // clip work of the last assembly
   int64_t assemblies = 0;
 };
 

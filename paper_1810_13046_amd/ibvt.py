@@ -65,7 +65,8 @@ class _Info(ctypes.Structure):
                 ("nnz", ctypes.c_int64 * 3), ("touched", ctypes.c_int64 * 3),
                 ("nnz_mass", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("assemblies", ctypes.c_int64), ("subtets", ctypes.c_int64),
-                ("piece_store", ctypes.c_int64)]
+                ("piece_store", ctypes.c_int64), ("dist_evals", ctypes.c_int64),
+                ("cut_points", ctypes.c_int64)]
 
 
 _lib = None
@@ -306,7 +307,8 @@ class Coupling:
                     n_fluid=list(i.n_fluid), pairs=i.pairs, pieces=i.pieces, dropped=i.dropped,
                     zero_tets=i.zero_tets, nnz=list(i.nnz), touched=list(i.touched),
                     nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies,
-                    subtets=i.subtets, piece_store=bool(i.piece_store))
+                    subtets=i.subtets, piece_store=bool(i.piece_store),
+                    dist_evals=i.dist_evals, cut_points=i.cut_points)
 
     def export_csr(self, comp: int, transposed: bool = False):
         """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""
