@@ -104,13 +104,13 @@ void release_csr(ibvt_coupling* c, Csr& m) {
 
 void release_all(ibvt_coupling* c) {
   DevBuf* bufs[] = {&c->lat,      &c->X,         &c->tets,      &c->vt_ptr,    &c->vt_tet,
-                    &c->tetvol,   &c->tetgeo,    &c->rng,       &c->pmom,      &c->cnt,
+                    &c->tetvol,   &c->tetrec,    &c->rng,       &c->pmom,      &c->cnt,
                     &c->pair_off, &c->owner,     &c->pval,      &c->keep,      &c->rownnz,
                     &c->mark,     &c->cidx,      &c->tbuf,      &c->mlump,     &c->minv,
                     &c->Mval32,   &c->Mdiag_inv, &c->flags_dev, &c->counters,  &c->scan_tmp,
-                    &c->work,     &c->work2,     &c->zbuf,      &c->pool,      &c->sub_begin,
-                    &c->sub_cnt,  &c->paircoef,  &c->order,     &c->pscan,     &c->rowbox,
-                    &c->rowcap,   &c->rowtmpoff, &c->rowtmpcol, &c->rowtmpval};
+                    &c->work,     &c->work2,     &c->zbuf,      &c->pool,      &c->pinfo,
+                    &c->order,    &c->pscan,     &c->rowbox,    &c->rowcap,    &c->rowtmpoff,
+                    &c->rowtmpcol, &c->rowtmpval};
   for (DevBuf* b : bufs) release(c, *b);
   for (int d = 0; d < 3; ++d) {
     release_csr(c, c->B[d]);

@@ -137,7 +137,7 @@ __global__ void k_mass_pattern(int64_t n_v, const int64_t* __restrict__ vt_ptr,
 __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
                            const int32_t* __restrict__ tets, const double* __restrict__ lat,
                            LatDesc ld, double* __restrict__ tetvol, CellRange* __restrict__ rng,
-                           int64_t* __restrict__ cnt, double* __restrict__ tetgeo, unsigned* flags,
+                           int64_t* __restrict__ cnt, double* __restrict__ tetrec, unsigned* flags,
                            unsigned long long* counters) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   bool zero = false;
@@ -171,7 +171,9 @@ __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
       for (int k = 0; k < 4; ++k)
         for (int e = 0; e < 3; ++e) G.V[k][e] = P[k][e];
       tet_geom(G);
-      store_tet_geom(G, tetgeo + t * kTetGeo);
+      double r[kTetRec];
+      store_tet_rec(G, r);
+      store_row<kTetRec>(tetrec + t * kTetRec, r);
     }
     zero = finite && (vol == 0.0);
     if (!finite) atomicOr(flags, kFlagNonFinite);
@@ -214,27 +216,16 @@ __global__ void k_owner(int64_t n_tc, const int64_t* __restrict__ off, int32_t* 
 // clip + integrate, one lane per (tet, component, cell) pair
 // ---------------------------------------------------------------------------
 
-// Pair geometry shared by the clip kernels: cell of the pair and the
-// precomputed tet geometry.
+// Pair geometry for the clip: cell box of the pair, tet vertices and box.
 __device__ __forceinline__ void pair_geometry(int64_t p, int64_t n_t, const int32_t* owner,
                                               const int64_t* pair_off, const CellRange* rng,
-                                              const double* tetgeo, const double* lat,
+                                              const double* tetrec, const double* lat,
                                               const LatDesc& ld, int& d, int64_t& t, int ci[3],
                                               TetGeom& G, double lo[3], double hi[3]) {
-  const int64_t tc = owner[p];
-  d = int(tc / n_t);
-  t = tc - int64_t(d) * n_t;
-  const CellRange r = rng[tc];
-  const int64_t q = p - pair_off[tc];
-  ci[0] = r.lo[0] + int(q % r.n[0]);
-  ci[1] = r.lo[1] + int((q / r.n[0]) % r.n[1]);
-  ci[2] = r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]));
-  load_tet_geom(G, tetgeo + t * kTetGeo);
-  for (int e = 0; e < 3; ++e) {
-    const double* L = lat + ld.off[3 * d + e];
-    lo[e] = L[ci[e]];
-    hi[e] = L[ci[e] + 1];
-  }
+  pair_cell(p, n_t, owner, pair_off, rng, lat, ld, d, t, ci, lo, hi);
+  double r[kTetRec];
+  load_row<kTetRec>(tetrec + t * kTetRec, r);
+  load_tet_box(G, r);
 }
 
 // Which of the six cell planes a pair's tet straddles, from indices alone:
@@ -249,9 +240,10 @@ __global__ void k_pair_key(int64_t n_pairs, const int32_t* __restrict__ owner,
   if (p < n_pairs) {
     const int64_t tc = owner[p];
     const CellRange r = rng[tc];
-    const int64_t q = p - pair_off[tc];
-    const int c[3] = {int(q % r.n[0]), int((q / r.n[0]) % r.n[1]),
-                      int(q / (int64_t(r.n[0]) * r.n[1]))};
+    const uint32_t q = uint32_t(p - pair_off[tc]);
+    const uint32_t n0 = uint32_t(r.n[0]), n1 = uint32_t(r.n[1]);
+    const uint32_t qy = q / n0, qz = qy / n1;
+    const int c[3] = {int(q - qy * n0), int(qy - qz * n1), int(qz)};
     int pattern = 0;
     for (int e = 0; e < 3; ++e) {
       if (c[e] > 0) pattern |= 1 << (2 * e);
@@ -294,9 +286,9 @@ template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_clip(
     int64_t n_list, const int32_t* __restrict__ order, int64_t n_t, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-    const double* __restrict__ tetgeo, const double* __restrict__ lat, LatDesc ld,
-    double drop_rel, uint8_t* __restrict__ keep, T* __restrict__ pool, int64_t pool_cap, int64_t* __restrict__ sub_begin, uint8_t* __restrict__ sub_cnt,
-    T* __restrict__ coef, int chunk, unsigned* flags, unsigned long long* counters) {
+    const double* __restrict__ tetrec, const double* __restrict__ lat, LatDesc ld,
+    double drop_rel, T* __restrict__ pool, int64_t pool_cap, uint64_t* __restrict__ pinfo,
+    int chunk, unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
   __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
@@ -318,9 +310,9 @@ __global__ __launch_bounds__(kWave) void k_clip(
     if (active) {
       int d, ci[3];
       int64_t t;
-      pair_geometry(p, n_t, owner, pair_off, rng, tetgeo, lat, ld, d, t, ci, G, lo, hi);
+      pair_geometry(p, n_t, owner, pair_off, rng, tetrec, lat, ld, d, t, ci, G, lo, hi);
       live = poly_init_tet(P, G.V, G.det < 0.0);
-      ok = poly_clip_box(P, live, lo, hi, G.mn, G.mx, &cc);
+      ok = poly_clip_box<MAXV>(P, live, lo, hi, G.mn, G.mx, &cc);
       if (ok) {
         want = poly_fan_prepare(P, live, seen);
         if (want < 0) {
@@ -357,32 +349,14 @@ __global__ __launch_bounds__(kWave) void k_clip(
       ns += unsigned(nsub);
       if (!ok) {
         fail = true;
-        keep[p] = 0;
-        sub_cnt[p] = 0;
+        pinfo[p] = 0;
       } else {
         const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
         const double vol = vol6 * cv / 6.0;
         const bool kp = vol > drop_rel * (fabs(G.det) / 6.0);
-        keep[p] = kp ? 1 : 0;
-        sub_begin[p] = my;
-        sub_cnt[p] = kp ? uint8_t(nsub) : 0;
-        if (kp) {
-          ++nk;
-          T LA[4], LG[4][3];
-          cell_lambda<T>(G, lo, hi, LA, LG);
-          T* cf = coef + p * kCoef;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            cf[i] = LA[i];
-#pragma unroll
-            for (int e = 0; e < 3; ++e) cf[4 + 3 * i + e] = LG[i][e];
-          }
-#pragma unroll
-          for (int e = 0; e < 3; ++e) cf[16 + e] = T(hi[e] - lo[e]);
-          cf[19] = T(-cv / 6.0);
-        } else if (vol > 0.0) {
-          ++nd;
-        }
+        pinfo[p] = kp ? ((uint64_t(my) << 8) | uint64_t(nsub)) : 0;
+        if (kp) ++nk;
+        else if (vol > 0.0) ++nd;
       }
     }
   }
@@ -427,9 +401,11 @@ __device__ __forceinline__ int owner_lane(int excl, int s) {
 // contiguous values).
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_integrate(
-    int64_t n_pairs, const uint8_t* __restrict__ keep, const T* __restrict__ pool,
-    const int64_t* __restrict__ sub_begin, const uint8_t* __restrict__ sub_cnt,
-    const T* __restrict__ coef, T* __restrict__ pval, T* __restrict__ pmom) {
+    int64_t n_pairs, int64_t n_t, const uint64_t* __restrict__ pinfo, const T* __restrict__ pool,
+    const int32_t* __restrict__ owner, const int64_t* __restrict__ pair_off,
+    const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
+    const double* __restrict__ lat, LatDesc ld, uint8_t* __restrict__ keep,
+    T* __restrict__ pval, T* __restrict__ pmom) {
   __shared__ T red[kWave][kMom];
   __shared__ int rown[kWave];
   __shared__ int rlast[kWave];
@@ -438,9 +414,11 @@ __global__ __launch_bounds__(kWave) void k_integrate(
   const int64_t pj = g0 + lane;
   int cnt = 0;
   int64_t beg = 0;
-  if (pj < n_pairs && keep[pj]) {
-    cnt = sub_cnt[pj];
-    beg = sub_begin[pj];
+  if (pj < n_pairs) {
+    const uint64_t pi = pinfo[pj];
+    cnt = int(pi & 0xff);
+    beg = int64_t(pi >> 8);
+    keep[pj] = cnt > 0 ? 1 : 0;
   }
   int incl = cnt;
   for (int o = 1; o < kWave; o <<= 1) {
@@ -489,15 +467,15 @@ __global__ __launch_bounds__(kWave) void k_integrate(
   if (cnt > 0) {
     T M[kMomPad];
     load_row<kMomPad>(pmom + pj * kMomPad, M);
-    const T* cf = coef + pj * kCoef;
+    int d, ci[3];
+    int64_t t;
+    double lo[3], hi[3];
+    pair_cell(pj, n_t, owner, pair_off, rng, lat, ld, d, t, ci, lo, hi);
+    double rec[kTetRec];
+    load_row<kTetRec>(tetrec + t * kTetRec, rec);
     T LA[4], LG[4][3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      LA[i] = cf[i];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
-    }
-    const T sc = cf[19];
+    rec_cell_lambda<T>(rec, lo, hi, LA, LG);
+    const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
     const int64_t plane = n_pairs * 8;
     T b[4][8];
     mom_to_b<T>(M, LA, LG, [&](int i, int jj, T v) { b[i][jj] = sc * v; });
@@ -843,7 +821,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     ProfScope ps("tet_prep", s);
   k_tet_prep<<<blocks_for(n_t, 256), 256, 0, s>>>(
       n_t, c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld,
-      c->tetvol.as<double>(), c->rng.as<CellRange>(), c->cnt.as<int64_t>(), c->tetgeo.as<double>(),
+      c->tetvol.as<double>(), c->rng.as<CellRange>(), c->cnt.as<int64_t>(), c->tetrec.as<double>(),
       flags, counters);
   }
   if ((st = hip_check(hipGetLastError(), "prep launch"))) return st;
@@ -864,9 +842,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
                                                    c->owner.as<int32_t>());
   // piece store: the fan sub-tetrahedra of every kept piece (integrated
   // below, and again by the reverse mode)
-  if ((st = ensure(c, c->sub_begin, size_t(n_pairs + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, c->sub_cnt, size_t(n_pairs + 1)))) return st;
-  if ((st = ensure(c, c->paircoef, size_t(n_pairs + 1) * kCoef * sizeof(T)))) return st;
+  if ((st = ensure(c, c->pinfo, size_t(n_pairs + 1) * sizeof(uint64_t)))) return st;
   // pair lists ordered by (cut class, straddled-plane pattern)
   if (n_pairs >= (int64_t(1) << 31) - 1)
     return set_error(IBVT_E_CAPACITY, "2^31 or more (tet, cell) pairs");
@@ -934,9 +910,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
               int(std::min<int64_t>(2048, (3 * n_k) / (8 * nb)));
 #define IBVT_CLIP_ARGS                                                                          \
   n_k, ord, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),     \
-      c->tetgeo.as<double>(), c->lat.as<double>(), c->ld, 1e-14,                                \
-      c->keep.as<uint8_t>(), c->pool.as<T>(), c->pool_cap, c->sub_begin.as<int64_t>(),          \
-      c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), chunk, flags, counters
+      c->tetrec.as<double>(), c->lat.as<double>(), c->ld, 1e-14, c->pool.as<T>(), c->pool_cap,   \
+      c->pinfo.as<uint64_t>(), chunk, flags, counters
           if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
           else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
           else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
@@ -956,8 +931,9 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if (n_pairs > 0) {
     ProfScope ps("integrate", s);
     k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
-        n_pairs, c->keep.as<uint8_t>(), c->pool.as<T>(), c->sub_begin.as<int64_t>(),
-        c->sub_cnt.as<uint8_t>(), c->paircoef.as<T>(), c->pval.as<T>(), c->pmom.as<T>());
+        n_pairs, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(), c->owner.as<int32_t>(),
+        c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), c->tetrec.as<double>(),
+        c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>());
   }
   if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
   // (IV) global assembly: rows of B^d
@@ -1103,7 +1079,7 @@ int assemble_all(ibvt_coupling* c, hipStream_t s) {
   int st;
   int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));
   if ((st = ensure(c, c->tetvol, size_t(n_t + 1) * sizeof(double)))) return st;
-  if ((st = ensure(c, c->tetgeo, size_t(n_t + 1) * kTetGeo * sizeof(double)))) return st;
+  if ((st = ensure(c, c->tetrec, size_t(n_t + 1) * kTetRec * sizeof(double)))) return st;
   if ((st = ensure(c, c->rng, size_t(3 * n_t + 1) * sizeof(CellRange)))) return st;
   if ((st = ensure(c, c->cnt, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->pair_off, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;

@@ -97,14 +97,18 @@ struct ClipCount {
 };
 
 // Keep the half-space sgn·(x_a − c) >= 0.  `live` is the mask of used
-// slots.  Returns false if the fixed capacity or a walk bound is exceeded.
+// slots, all below NS.  Returns false if the fixed capacity or a walk bound
+// is exceeded.  The distance and adjacency passes run over all NS slots
+// (unused ones masked), so their reads are independent of each other.
+template <int NS = kMaxV>
 __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int a, double c,
                                           double sgn, ClipCount* cc = nullptr) {
   if (cc) cc->dist += uint32_t(__builtin_popcount(live));
   uint32_t out = 0;
-  for (uint32_t m = live; m; m &= m - 1) {
-    const int v = ctz32(m);
-    if (sgn * (P.co(v, a) - c) < 0.0) out |= 1u << v;
+#pragma unroll
+  for (int v = 0; v < NS; ++v) {
+    const double s = sgn * (P.co(v, a) - c);
+    if (((live >> v) & 1u) && s < 0.0) out |= 1u << v;
   }
   if (!out) return true;
   if (out == live) {
@@ -113,9 +117,10 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
   }
   const uint32_t in = live & ~out;
   uint32_t adj = 0;  // vertices adjacent to an inside vertex
-  for (uint32_t m = in; m; m &= m - 1) {
-    const uint32_t w = P.nb(ctz32(m));
-    adj |= (1u << nb_get(w, 0)) | (1u << nb_get(w, 1)) | (1u << nb_get(w, 2));
+#pragma unroll
+  for (int v = 0; v < NS; ++v) {
+    const uint32_t w = P.nb(v);
+    if ((in >> v) & 1u) adj |= (1u << nb_get(w, 0)) | (1u << nb_get(w, 1)) | (1u << nb_get(w, 2));
   }
   // free slots: never used, or outside with no inside neighbour
   uint32_t freem = (~live & P.all) | (out & ~adj);
@@ -176,6 +181,7 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
 // Clip by the six planes of the box [lo, hi].  mn/mx bound the original
 // tet: the piece never leaves them, so a plane the tet does not straddle is
 // skipped, and a box the tet only touches gives an empty piece.
+template <int NS = kMaxV>
 __host__ __device__ inline bool poly_clip_box(const PolyView& P, uint32_t& live, const double lo[3],
                                               const double hi[3], const double mn[3],
                                               const double mx[3], ClipCount* cc = nullptr) {
@@ -186,8 +192,8 @@ __host__ __device__ inline bool poly_clip_box(const PolyView& P, uint32_t& live,
     }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (live && mn[a] < lo[a] && !poly_clip(P, live, a, lo[a], 1.0, cc)) return false;
-    if (live && mx[a] > hi[a] && !poly_clip(P, live, a, hi[a], -1.0, cc)) return false;
+    if (live && mn[a] < lo[a] && !poly_clip<NS>(P, live, a, lo[a], 1.0, cc)) return false;
+    if (live && mx[a] > hi[a] && !poly_clip<NS>(P, live, a, hi[a], -1.0, cc)) return false;
   }
   return true;
 }
@@ -608,34 +614,25 @@ __host__ __device__ inline void tet_geom(TetGeom& G) {
   }
 }
 
-// Per-tet geometry record (vertices, determinant, gradients, box), written
-// once per assembly and read by every pair of the tet.
-constexpr int kTetGeo = 32;
+// Per-tet record read by every pair of the tet: the four vertices and the
+// determinant e1·(e2 × e3) (16 doubles, one 128-byte line).
+constexpr int kTetRec = 16;
 
-__host__ __device__ inline void store_tet_geom(const TetGeom& G, double* r) {
+__host__ __device__ inline void store_tet_rec(const TetGeom& G, double* r) {
   for (int k = 0; k < 4; ++k)
-    for (int e = 0; e < 3; ++e) {
-      r[3 * k + e] = G.V[k][e];
-      r[12 + 3 * k + e] = G.g[k][e];
-    }
-  r[24] = G.det;
-  for (int e = 0; e < 3; ++e) {
-    r[25 + e] = G.mn[e];
-    r[28 + e] = G.mx[e];
-  }
-  r[31] = 0.0;
+    for (int e = 0; e < 3; ++e) r[3 * k + e] = G.V[k][e];
+  r[12] = G.det;
+  r[13] = r[14] = r[15] = 0.0;
 }
 
-__host__ __device__ inline void load_tet_geom(TetGeom& G, const double* r) {
+// Vertices, determinant and bounding box from a tet record (gradients unset).
+__host__ __device__ inline void load_tet_box(TetGeom& G, const double r[kTetRec]) {
   for (int k = 0; k < 4; ++k)
-    for (int e = 0; e < 3; ++e) {
-      G.V[k][e] = r[3 * k + e];
-      G.g[k][e] = r[12 + 3 * k + e];
-    }
-  G.det = r[24];
-  for (int e = 0; e < 3; ++e) {
-    G.mn[e] = r[25 + e];
-    G.mx[e] = r[28 + e];
+    for (int e = 0; e < 3; ++e) G.V[k][e] = r[3 * k + e];
+  G.det = r[12];
+  for (int a = 0; a < 3; ++a) {
+    G.mn[a] = fmin(fmin(G.V[0][a], G.V[1][a]), fmin(G.V[2][a], G.V[3][a]));
+    G.mx[a] = fmax(fmax(G.V[0][a], G.V[1][a]), fmax(G.V[2][a], G.V[3][a]));
   }
 }
 
@@ -651,14 +648,21 @@ __host__ __device__ inline void cell_lambda(const TetGeom& G, const double lo[3]
   }
 }
 
+// λ of the tet of record r in the cell-local coordinates of [lo, hi]
+// (gradients recomputed from the vertices).
+template <typename T>
+__host__ __device__ inline void rec_cell_lambda(const double r[kTetRec], const double lo[3],
+                                                const double hi[3], T LA[4], T LG[4][3]) {
+  TetGeom G;
+  for (int k = 0; k < 4; ++k)
+    for (int e = 0; e < 3; ++e) G.V[k][e] = r[3 * k + e];
+  tet_geom(G);
+  cell_lambda<T>(G, lo, hi, LA, LG);
+}
+
 // Sub-tetrahedron record of the piece store: 4 vertices (cell-local) and
 // the determinant, kRecord values of type T.
 constexpr int kRecord = 13;
-
-// Per-pair coefficients kept by the clip kernel for the integration
-// kernels: λ offsets (4), cell-local λ gradients (12), cell size (3) and
-// the scale −|cell|/6 (1).
-constexpr int kCoef = 20;
 
 // Clip tet ∩ box and integrate.  Returns false on a capacity/walk failure.
 // vol6 receives 6·|piece| in cell-local units (times the cell volume gives
@@ -734,39 +738,12 @@ __host__ __device__ inline int poly_fan_prepare(const PolyView& P, uint32_t live
   return total;
 }
 
-// Emit the fan sub-tetrahedra (apex, f0, f_i, f_{i+1}) of every face not
-// marked in `seen`, one pass per face.
-template <typename F>
-__host__ __device__ inline bool poly_fan_emit(const PolyView& P, uint32_t live, uint64_t seen,
-                                              F&& fn) {
-  if (!live) return true;
-  const int apex = ctz32(live);
-  for (uint32_t m = live; m; m &= m - 1) {
-    const int v = ctz32(m);
-    const uint32_t vw = P.nb(v);
-    for (int k = 0; k < 3; ++k) {
-      if ((seen >> (3 * v + k)) & 1ull) continue;
-      seen |= 1ull << (3 * v + k);
-      int prev = v, f1 = nb_get(vw, k), guard = 0;
-      for (;;) {
-        const uint32_t cw = P.nb(f1);
-        const int nk = (nb_find(cw, prev) + 1) % 3;
-        seen |= 1ull << (3 * f1 + nk);
-        const int f2 = nb_get(cw, nk);
-        if (f2 == v) break;
-        fn(apex, v, f1, f2);
-        prev = f1;
-        f1 = f2;
-        if (++guard > 3 * kMaxV) return false;
-      }
-    }
-  }
-  return true;
-}
-
 // Write the fan's sub-tetrahedra of a clipped piece as records (cell-local
 // coordinates and determinant, rounded to T) at rec (up to cap of them);
-// vol6 receives the piece's 6·volume in cell-local units (double).
+// vol6 receives the piece's 6·volume in cell-local units (double).  The faces
+// not marked in `seen` are walked once each; the apex, the face's first
+// vertex and the previous vertex stay in registers, so each sub-tetrahedron
+// reads one new vertex.
 template <typename T>
 __host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, uint64_t seen,
                                              const double lo[3], const double hi[3], T* rec,
@@ -775,29 +752,64 @@ __host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, u
   nsub = 0;
   if (!live) return true;
   const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
+  auto local = [&](int v, double y[3]) {
+    y[0] = (P.x(v) - lo[0]) * ih[0];
+    y[1] = (P.y(v) - lo[1]) * ih[1];
+    y[2] = (P.z(v) - lo[2]) * ih[2];
+  };
+  const int apex = ctz32(live);
+  double ya[3];
+  local(apex, ya);
   double vsum = 0.0;
-  const bool ok = poly_fan_emit(P, live, seen, [&](int q0, int q1, int q2, int q3) {
-    const int qs[4] = {q0, q1, q2, q3};
-    double yd[4][3];
-    for (int v = 0; v < 4; ++v)
-      for (int e = 0; e < 3; ++e) yd[v][e] = (P.co(qs[v], e) - lo[e]) * ih[e];
-    double d[3][3];
-    for (int v = 0; v < 3; ++v)
-      for (int e = 0; e < 3; ++e) d[v][e] = yd[v + 1][e] - yd[0][e];
-    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
-                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
-                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
-    vsum += det;
-    if (rec && nsub < cap) {
-      T* r = rec + nsub * kRecord;
-      for (int v = 0; v < 4; ++v)
-        for (int e = 0; e < 3; ++e) r[v * 3 + e] = T(yd[v][e]);
-      r[12] = T(det);
+  for (uint32_t m = live; m; m &= m - 1) {
+    const int v = ctz32(m);
+    if (((seen >> (3 * v)) & 7ull) == 7ull) continue;  // all three faces done
+    const uint32_t vw = P.nb(v);
+    double yv[3];
+    local(v, yv);
+    const double d0[3] = {yv[0] - ya[0], yv[1] - ya[1], yv[2] - ya[2]};
+    for (int k = 0; k < 3; ++k) {
+      if ((seen >> (3 * v + k)) & 1ull) continue;
+      seen |= 1ull << (3 * v + k);
+      int prev = v, f1 = nb_get(vw, k), guard = 0;
+      double y1[3];
+      local(f1, y1);
+      for (;;) {
+        const uint32_t cw = P.nb(f1);
+        const int nk = (nb_find(cw, prev) + 1) % 3;
+        seen |= 1ull << (3 * f1 + nk);
+        const int f2 = nb_get(cw, nk);
+        if (f2 == v) break;
+        double y2[3];
+        local(f2, y2);
+        const double d1[3] = {y1[0] - ya[0], y1[1] - ya[1], y1[2] - ya[2]};
+        const double d2[3] = {y2[0] - ya[0], y2[1] - ya[1], y2[2] - ya[2]};
+        const double det = d0[0] * (d1[1] * d2[2] - d1[2] * d2[1]) -
+                           d0[1] * (d1[0] * d2[2] - d1[2] * d2[0]) +
+                           d0[2] * (d1[0] * d2[1] - d1[1] * d2[0]);
+        vsum += det;
+        if (rec && nsub < cap) {
+          T* r = rec + nsub * kRecord;
+          for (int e = 0; e < 3; ++e) {
+            r[e] = T(ya[e]);
+            r[3 + e] = T(yv[e]);
+            r[6 + e] = T(y1[e]);
+            r[9 + e] = T(y2[e]);
+          }
+          r[12] = T(det);
+        }
+        ++nsub;
+        prev = f1;
+        f1 = f2;
+        y1[0] = y2[0];
+        y1[1] = y2[1];
+        y1[2] = y2[2];
+        if (++guard > 3 * kMaxV) return false;
+      }
     }
-    ++nsub;
-  });
+  }
   vol6 = -vsum;
-  return ok;
+  return true;
 }
 
 template <typename T>

@@ -99,7 +99,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_shape_mom(
     int64_t n_pairs, int64_t n_t, int64_t n_v, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-    const uint8_t* __restrict__ keep, const T* __restrict__ pmom, const T* __restrict__ coef,
+    const uint8_t* __restrict__ keep, const T* __restrict__ pmom,
+    const double* __restrict__ tetrec, const double* __restrict__ lat,
     const int32_t* __restrict__ tets, LatDesc ld, const T* __restrict__ z, const T* u0,
     const T* u1, const T* u2, T* __restrict__ pg) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -108,13 +109,10 @@ __global__ __launch_bounds__(256) void k_shape_mom(
 #pragma unroll
   for (int k = 0; k < 12; ++k) out[k] = T(0);
   if (keep[p]) {
-    const int64_t tc = owner[p];
-    const int d = int(tc / n_t);
-    const int64_t t = tc - int64_t(d) * n_t;
-    const CellRange r = rng[tc];
-    const int64_t q = p - pair_off[tc];
-    const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
-                       r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+    int d, ci[3];
+    int64_t t;
+    double lo[3], hi[3];
+    pair_cell(p, n_t, owner, pair_off, rng, lat, ld, d, t, ci, lo, hi);
     const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
     const T* zd = z + int64_t(d) * n_v;
     const T zl[4] = {zd[tv.x], zd[tv.y], zd[tv.z], zd[tv.w]};
@@ -125,23 +123,19 @@ __global__ __launch_bounds__(256) void k_shape_mom(
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       ul[j] = u[n000 + (j & 1) + NX * (((j >> 1) & 1) + NY * (j >> 2))];
-    const T* cf = coef + p * kCoef;
+    double rec[kTetRec];
+    load_row<kTetRec>(tetrec + t * kTetRec, rec);
     T LA[4], LG[4][3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      LA[i] = cf[i];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) LG[i][e] = cf[4 + 3 * i + e];
-    }
+    rec_cell_lambda<T>(rec, lo, hi, LA, LG);
     T M[kMomPad];
     load_row<kMomPad>(pmom + p * kMomPad, M);
     T A[12], Bs;
     mom_shape<T>(M, LA, LG, zl, ul, A, Bs);
     // ∂/∂x_k = (1/h_k) ∂/∂ξ_k; ∇λ_a = (cell-local gradient)/h
-    const T sc = cf[19];
+    const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const T ih = T(1) / cf[16 + k];
+      const T ih = T(1.0 / (hi[k] - lo[k]));
 #pragma unroll
       for (int a = 0; a < 4; ++a) out[a * 3 + k] = sc * ih * (A[a * 3 + k] + LG[a][k] * Bs);
     }
@@ -217,8 +211,8 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
     ProfScope ps("shape_moments", s);
     k_shape_mom<T><<<unsigned(ceil_div(c->n_pairs, 256)), 256, 0, s>>>(
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
-        c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pmom.as<T>(), c->paircoef.as<T>(),
-        c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
+        c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(),
+        c->lat.as<double>(), c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
         static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg);
   } else if (c->n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);

@@ -36,6 +36,30 @@ struct LatDesc {
   int32_t n[9];
 };
 
+// Cell of pair p (component d, tet t, cell index ci) and its box [lo, hi].
+__device__ __forceinline__ void pair_cell(int64_t p, int64_t n_t, const int32_t* owner,
+                                          const int64_t* pair_off, const CellRange* rng,
+                                          const double* lat, const LatDesc& ld, int& d,
+                                          int64_t& t, int ci[3], double lo[3], double hi[3]) {
+  const int64_t tc = owner[p];
+  d = (tc >= n_t) + (tc >= 2 * n_t);
+  t = tc - int64_t(d) * n_t;
+  const CellRange r = rng[tc];
+  // cell counts per tet are small: 32-bit index arithmetic
+  const uint32_t q = uint32_t(p - pair_off[tc]);
+  const uint32_t n0 = uint32_t(r.n[0]), n1 = uint32_t(r.n[1]);
+  const uint32_t qy = q / n0;
+  ci[0] = r.lo[0] + int(q - qy * n0);
+  const uint32_t qz = qy / n1;
+  ci[1] = r.lo[1] + int(qy - qz * n1);
+  ci[2] = r.lo[2] + int(qz);
+  for (int e = 0; e < 3; ++e) {
+    const double* L = lat + ld.off[3 * d + e];
+    lo[e] = L[ci[e]];
+    hi[e] = L[ci[e] + 1];
+  }
+}
+
 struct AsmStats {
   int64_t pairs = 0, pieces = 0, dropped = 0, zero_tets = 0, subtets = 0;
   int64_t dist_evals = 0, cut_points = 0;  // clip work of the last assembly
@@ -56,7 +80,7 @@ struct ibvt_coupling {
   ibvt::DevBuf X, tets;      // own copies
   ibvt::DevBuf vt_ptr, vt_tet;  // vertex -> incident tets (int64 ptr, int32 ids)
   ibvt::DevBuf tetvol;       // double n_tet
-  ibvt::DevBuf tetgeo;       // double n_tet*kTetGeo: per-tet geometry record
+  ibvt::DevBuf tetrec;       // double n_tet*16: per-tet record (vertices, determinant)
   ibvt::DevBuf rng;          // CellRange 3*n_tet
   ibvt::DevBuf cnt;          // int64 3*n_tet
   ibvt::DevBuf pair_off;     // int64 3*n_tet + 1
@@ -70,9 +94,7 @@ struct ibvt_coupling {
   int64_t pool_cap = 0;      // records
   int64_t pool_needed = 0;   // records the last assembly asked for
   bool mom_valid = false;    // pmom holds the moments of every kept piece of the last assembly
-  ibvt::DevBuf sub_begin;    // int64 n_pairs: first record of the pair
-  ibvt::DevBuf sub_cnt;      // uint8 n_pairs: records of the pair
-  ibvt::DevBuf paircoef;     // T n_pairs*kCoef: per-pair λ coefficients
+  ibvt::DevBuf pinfo;        // uint64 n_pairs: first record << 8 | records (0: dropped)
   ibvt::DevBuf order;        // int32 n_pairs: pairs sorted by cut pattern
   ibvt::DevBuf pscan;        // sort keys and scratch
   ibvt::DevBuf rownnz;       // int64 3*n_vert
