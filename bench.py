@@ -48,9 +48,10 @@ FP64_VEC_PEAK_TFLOPS = 78.6
 #                                                    coordinates, drop test)
 CLIP_FLOPS = dict(dist=2, cut=11, subtet=47, pair=50)
 # flops per quadrature point of the 35 piece moments: point 6, powers 9,
-# partial products 14, 35 multiply-adds 70
+# partial products 14, 35 multiply-adds 70; 11 points (degree 4) per
+# sub-tetrahedron
 MOM_FLOPS_PER_POINT = 99
-POINTS_PER_SUBTET = 14
+POINTS_PER_SUBTET = 11
 
 # HBM traffic of the clip step (both slot-class launches of one assembly) on
 # the three-body workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter

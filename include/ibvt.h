@@ -128,7 +128,7 @@ typedef struct {
   int64_t device_bytes;      /* device memory held by the coupling */
   int64_t assemblies;        /* assemblies done on this handle */
   int64_t subtets;           /* sub-tetrahedra integrated by the last
-                                assembly (each gets the 14-point rule) */
+                                assembly (11 quadrature points each) */
   int64_t piece_store;       /* 1 if every kept piece's moments are stored
                                 for the reverse mode */
   int64_t dist_evals;        /* plane distances evaluated by the last

@@ -385,8 +385,8 @@ __host__ __device__ inline void subtet_grad(const T y[4][3], T wscale, const T L
 //   M_α = ∫_piece s^α,  s = ξ − (½, ½, ½),  |α| <= 4
 // (cell-local coordinates centred in the cell, which keeps the
 // recombination well conditioned) determine all of them.  Moments are summed
-// per sub-tetrahedron with the 14-point rule (exact to degree 5) and per
-// piece over its fan.
+// per sub-tetrahedron with the 11-point degree-4 rule and per piece over its
+// fan.
 // ---------------------------------------------------------------------------
 constexpr int kMom = 35;
 constexpr int kMomPad = 36;  // per-pair stride of the moment store (16-byte rows)
@@ -428,7 +428,8 @@ __host__ __device__ __forceinline__ void mom_point(T sx, T sy, T sz, T w, T M[kM
 }
 
 // Adds the unscaled moments of one sub-tetrahedron (vertices y in cell-local
-// coordinates, weight scale = its determinant) to M.
+// coordinates, weight scale = its determinant) to M, with the 11-point
+// degree-4 rule (exact for the moments, which are of degree <= 4).
 template <typename T>
 __host__ __device__ inline void subtet_moments(const T y[4][3], T wscale, T M[kMom]) {
   T yc[4][3], S[3];
@@ -438,22 +439,19 @@ __host__ __device__ inline void subtet_moments(const T y[4][3], T wscale, T M[kM
     for (int v = 0; v < 4; ++v) yc[v][e] = y[v][e] - T(0.5);
     S[e] = yc[0][e] + yc[1][e] + yc[2][e] + yc[3][e];
   }
-  const T a1 = T(kQA1), c1 = T(1.0 - 4.0 * kQA1), w1 = T(kQW1) * wscale;
-  const T a2 = T(kQA2), c2 = T(1.0 - 4.0 * kQA2), w2 = T(kQW2) * wscale;
+  mom_point<T>(T(0.25) * S[0], T(0.25) * S[1], T(0.25) * S[2], T(kQ4W0) * wscale, M);
+  const T a = T(kQ4A), ca = T(1.0 - 4.0 * kQ4A), wa = T(kQ4WA) * wscale;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    mom_point<T>(a1 * S[0] + c1 * yc[k][0], a1 * S[1] + c1 * yc[k][1], a1 * S[2] + c1 * yc[k][2],
-                 w1, M);
-    mom_point<T>(a2 * S[0] + c2 * yc[k][0], a2 * S[1] + c2 * yc[k][1], a2 * S[2] + c2 * yc[k][2],
-                 w2, M);
-  }
-  const T pb = T(2.0 * kQB - 0.5), ps = T(0.5 - kQB), w3 = T(kQW3) * wscale;
+  for (int k = 0; k < 4; ++k)
+    mom_point<T>(a * S[0] + ca * yc[k][0], a * S[1] + ca * yc[k][1], a * S[2] + ca * yc[k][2],
+                 wa, M);
+  const T pb = T(2.0 * kQ4B - 0.5), ps = T(0.5 - kQ4B), wb = T(kQ4WB) * wscale;
   const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int k = pk[q], l = pl[q];
     mom_point<T>(pb * (yc[k][0] + yc[l][0]) + ps * S[0], pb * (yc[k][1] + yc[l][1]) + ps * S[1],
-                 pb * (yc[k][2] + yc[l][2]) + ps * S[2], w3, M);
+                 pb * (yc[k][2] + yc[l][2]) + ps * S[2], wb, M);
   }
 }
 
