@@ -30,7 +30,7 @@ namespace ibvt {
 namespace {
 
 constexpr int kRowNodes = 512;  // LDS box nodes per wave per pass in k_rows
-constexpr int kRowChunks = 1;   // 8-pair steps whose loads k_rows keeps in flight
+constexpr int kRowMap = 512;    // slots of the slot → tet map of k_rows (one window)
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
   int lo = 0, hi = n;  // first index with L[idx] > x
@@ -200,6 +200,7 @@ __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
       if (!ok) r.n[0] = r.n[1] = r.n[2] = 0;
       rng[d * n_t + t] = r;
       cnt[d * n_t + t] = int64_t(r.n[0]) * r.n[1] * r.n[2];
+      if (int64_t(r.n[0]) * r.n[1] * r.n[2] > kMaxTetCells) atomicOr(flags, kFlagTetSpan);
     }
   }
   const uint64_t zm = ballot64(zero);
@@ -547,13 +548,25 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Exact floor(q / n) for q < 2^16 and 1 <= n < 2^16 as a multiply-high by
+// m = ceil(2^32 / n): with m n = 2^32 + e, 0 <= e < n, the error term q e / 2^32
+// stays below 1.  n = 1 (m = 2^32) is coded as m = 0.
+__device__ __forceinline__ uint32_t magic_div(uint32_t n) {
+  return n <= 1u ? 0u : 0xFFFFFFFFu / n + 1u;
+}
+__device__ __forceinline__ uint32_t div_magic(uint32_t q, uint32_t m) {
+  return m ? __umulhi(q, m) : q;
+}
+
 // Gather the pieces of the incident tets into the row's node box, kept in
 // LDS kRowNodes nodes at a time.  The row's pairs (incident tets ascending,
 // then cells) are taken 8 per step, one value per lane (lane = 8·pair +
 // corner); the 8 pairs are added to the box one after another, and the 8
 // corners of one pair are distinct nodes, so every node sums its
-// contributions in pair order (deterministic).  Touched nodes are written
-// column-sorted at tmp_off[w].
+// contributions in pair order (deterministic).  Per batch of 64 incident
+// tets, each tet's offsets are set up once in LDS and a slot → tet map
+// replaces a search per step.  Touched nodes are written column-sorted at
+// tmp_off[w].
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
     int64_t n_v, int64_t n_t, int64_t n_pairs, const int64_t* __restrict__ vt_ptr,
@@ -565,6 +578,8 @@ __global__ __launch_bounds__(256) void k_rows(
   __shared__ T s_acc[4][kRowNodes];
   __shared__ uint8_t s_flag[4][kRowNodes];
   __shared__ int4 s_m0[4][kWave], s_m1[4][kWave];
+  __shared__ int s_ex[4][kWave];
+  __shared__ uint8_t s_map[4][kRowMap];
   const int wib = threadIdx.x / kWave;
   const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = lane_id();
@@ -573,16 +588,20 @@ __global__ __launch_bounds__(256) void k_rows(
   uint8_t* flg = s_flag[wib];
   int4* M0 = s_m0[wib];
   int4* M1 = s_m1[wib];
+  int* EX = s_ex[wib];
+  uint8_t* smap = s_map[wib];
   const int d = int(w / n_v);
   const int64_t i = w - int64_t(d) * n_v;
   const RowBox b = box[w];
-  const int64_t total = int64_t(b.n[0]) * b.n[1] * b.n[2];
+  const int bn0 = b.n[0], bn1 = b.n[1];
+  const int64_t total = int64_t(bn0) * bn1 * b.n[2];
   int64_t outpos = tmp_off[w];
   const int64_t start = outpos;
   const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
   const int64_t beg = vt_ptr[i], end = vt_ptr[i + 1];
   const int qq = lane >> 3, jj = lane & 7;
-  const int dx = jj & 1, dy = (jj >> 1) & 1, dz = jj >> 2;
+  // box-linear offset of this lane's corner
+  const int coff = (jj & 1) + bn0 * (((jj >> 1) & 1) + bn1 * (jj >> 2));
   const int64_t vplane = n_pairs * 8;
   for (int64_t c0 = 0; c0 < total; c0 += kRowNodes) {
     const int span = int(min<int64_t>(kRowNodes, total - c0));
@@ -601,10 +620,19 @@ __global__ __launch_bounds__(256) void k_rows(
         const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
         const int li =
             (tv.y == int32_t(i)) ? 1 : (tv.z == int32_t(i)) ? 2 : (tv.w == int32_t(i)) ? 3 : 0;
-        const int64_t base = pair_off[tc];
-        M0[lane] = make_int4(r.lo[0], r.lo[1], r.lo[2], li);
-        M1[lane] = make_int4(r.n[0], r.n[1], int(base & 0xffffffffll), int(base >> 32));
+        const int64_t kbase = pair_off[tc];                     // pair of cell 0
+        const int64_t pbase = int64_t(li) * vplane + kbase * 8;  // its pval row
+        // box-linear offset of the tet's first cell in this pass
+        const int off0 = int(int64_t(r.lo[0] - b.lo[0]) +
+                             int64_t(bn0) * ((r.lo[1] - b.lo[1]) +
+                                             int64_t(bn1) * (r.lo[2] - b.lo[2])) -
+                             c0);
         cnt = r.n[0] * r.n[1] * r.n[2];
+        M0[lane] = make_int4(int(pbase & 0xffffffffll), int(pbase >> 32),
+                             int(kbase & 0xffffffffll), int(kbase >> 32));
+        M1[lane] = make_int4(r.n[0] | (r.n[1] << 16), off0,
+                             int(magic_div(uint32_t(max(r.n[0], 1)))),
+                             int(magic_div(uint32_t(max(r.n[1], 1)))));
       }
       int incl = cnt;
       for (int o = 1; o < kWave; o <<= 1) {
@@ -612,53 +640,51 @@ __global__ __launch_bounds__(256) void k_rows(
         if (lane >= o) incl += y;
       }
       const int excl = incl - cnt;
+      EX[lane] = excl;
       const int tot = __shfl(incl, kWave - 1, kWave);
-      wave_lds_sync();
-      // kRowChunks steps of 8 pairs at a time: all their loads in flight
-      // together (keep and value are read side by side), then the adds
-      for (int s0 = 0; s0 < tot; s0 += 8 * kRowChunks) {
-        bool add[kRowChunks];
-        int loc[kRowChunks];
-        T val[kRowChunks];
-#pragma unroll
-        for (int ch = 0; ch < kRowChunks; ++ch) {
-          const int sl = s0 + 8 * ch + qq;
-          const int k = owner_lane(excl, sl);
-          const int exk = __shfl(excl, k, kWave);
-          add[ch] = false;
-          loc[ch] = 0;
-          val[ch] = T(0);
-          if (sl < tot) {
-            const int4 m0 = M0[k], m1 = M1[k];
-            const unsigned q = unsigned(sl - exk);
-            const unsigned n0 = unsigned(m1.x), n1 = unsigned(m1.y);
-            const unsigned qy = q / n0;
+      // slots in windows of kRowMap: the map names each slot's tet
+      for (int w0 = 0; w0 < tot; w0 += kRowMap) {
+        wave_lds_sync();
+        {
+          const int a = max(excl, w0), e = min(incl, w0 + kRowMap);
+          for (int sl = a; sl < e; ++sl) smap[sl - w0] = uint8_t(lane);
+        }
+        wave_lds_sync();
+        const int wend = min(tot, w0 + kRowMap);
+        for (int s0 = w0; s0 < wend; s0 += 8) {
+          const int sl = s0 + qq;
+          bool add = false;
+          int loc = 0;
+          T val = T(0);
+          if (sl < wend) {
+            const int k = smap[sl - w0];
+            const int4 m1 = M1[k];
+            const uint32_t q = uint32_t(sl - EX[k]);
+            const uint32_t n0 = uint32_t(m1.x) & 0xffffu, n1 = uint32_t(m1.x) >> 16;
+            const uint32_t qy = div_magic(q, uint32_t(m1.z));
             const int ix = int(q - qy * n0);
-            const int iz = int(qy / n1);
-            const int iy = int(qy - unsigned(iz) * n1);
-            const int gx = m0.x + ix + dx - b.lo[0], gy = m0.y + iy + dy - b.lo[1],
-                      gz = m0.z + iz + dz - b.lo[2];
-            const int64_t lin = gx + int64_t(b.n[0]) * (gy + int64_t(b.n[1]) * gz) - c0;
+            const uint32_t iz = div_magic(qy, uint32_t(m1.w));
+            const int iy = int(qy - iz * n1);
+            const int lin = m1.y + ix + bn0 * (iy + bn1 * int(iz)) + coff;
             if (lin >= 0 && lin < span) {
-              const int64_t pr = int64_t((unsigned long long)(unsigned)m1.z |
-                                         ((unsigned long long)(unsigned)m1.w << 32)) + q;
-              const uint8_t kp = keep[pr];
-              const T v = pval[int64_t(m0.w) * vplane + pr * 8 + jj];
-              add[ch] = kp != 0;
-              val[ch] = v;
-              loc[ch] = int(lin);
+              const int4 m0 = M0[k];
+              const int64_t pb = int64_t((unsigned long long)(unsigned)m0.x |
+                                         ((unsigned long long)(unsigned)m0.y << 32));
+              const int64_t kb = int64_t((unsigned long long)(unsigned)m0.z |
+                                         ((unsigned long long)(unsigned)m0.w << 32));
+              const uint8_t kp = keep[kb + q];
+              const T v = pval[pb + int64_t(q) * 8 + jj];
+              add = kp != 0;
+              val = v;
+              loc = lin;
             }
           }
-        }
-#pragma unroll
-        for (int ch = 0; ch < kRowChunks; ++ch) {
-          if (add[ch]) flg[loc[ch]] = 1;
+          if (add) flg[loc] = 1;
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             wave_lds_sync();
-            if (add[ch] && qq == u)
-              __hip_atomic_fetch_add(&acc[loc[ch]], val[ch], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WAVEFRONT);
+            if (add && qq == u)
+              __hip_atomic_fetch_add(&acc[loc], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
           }
         }
       }
@@ -670,9 +696,9 @@ __global__ __launch_bounds__(256) void k_rows(
       const uint64_t m = ballot64(tch);
       if (tch) {
         const int64_t lin = c0 + k;
-        const int64_t gx = b.lo[0] + lin % b.n[0];
-        const int64_t gy = b.lo[1] + (lin / b.n[0]) % b.n[1];
-        const int64_t gz = b.lo[2] + lin / (int64_t(b.n[0]) * b.n[1]);
+        const int64_t gx = b.lo[0] + lin % bn0;
+        const int64_t gy = b.lo[1] + (lin / bn0) % bn1;
+        const int64_t gz = b.lo[2] + lin / (int64_t(bn0) * bn1);
         const int64_t pos = outpos + rank_below(m);
         tmp_col[pos] = int32_t(gx + NX * (gy + NY * gz));
         tmp_val[pos] = acc[k];
@@ -803,6 +829,8 @@ int check_flags(ibvt_coupling* c, hipStream_t s) {
     return set_error(IBVT_E_OUT_OF_GRID, "a tet's bounding box leaves a velocity lattice's node hull");
   if (f & kFlagCapacity)
     return set_error(IBVT_E_CAPACITY, "clipped piece exceeded the 16-vertex capacity");
+  if (f & kFlagTetSpan)
+    return set_error(IBVT_E_CAPACITY, "a tet spans more than 65535 cells of one lattice");
   return IBVT_OK;
 }
 

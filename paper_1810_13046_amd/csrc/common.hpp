@@ -13,6 +13,8 @@ constexpr unsigned kFlagOutOfGrid = 1u;
 constexpr unsigned kFlagCapacity = 2u;
 constexpr unsigned kFlagNonFinite = 4u;
 constexpr unsigned kFlagValence = 8u;
+constexpr unsigned kFlagTetSpan = 16u;  // a tet spans more than kMaxTetCells cells
+constexpr int kMaxTetCells = 65535;     // cells of one lattice a tet may span
 
 // Counter slots (unsigned long long) written by the assembly kernels.
 enum Counter : int {
