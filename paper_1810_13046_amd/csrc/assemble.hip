@@ -137,7 +137,8 @@ __global__ void k_mass_pattern(int64_t n_v, const int64_t* __restrict__ vt_ptr,
 __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
                            const int32_t* __restrict__ tets, const double* __restrict__ lat,
                            LatDesc ld, double* __restrict__ tetvol, CellRange* __restrict__ rng,
-                           int64_t* __restrict__ cnt, double* __restrict__ tetrec, unsigned* flags,
+                           int64_t* __restrict__ cnt, double* __restrict__ tetrec,
+                           double* __restrict__ tetgrad, unsigned* flags,
                            unsigned long long* counters) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   bool zero = false;
@@ -174,6 +175,10 @@ __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
       double r[kTetRec];
       store_tet_rec(G, r);
       store_row<kTetRec>(tetrec + t * kTetRec, r);
+      double g[12];
+      for (int k = 0; k < 4; ++k)
+        for (int e = 0; e < 3; ++e) g[3 * k + e] = G.g[k][e];
+      store_row<12>(tetgrad + t * 12, g);
     }
     zero = finite && (vol == 0.0);
     if (!finite) atomicOr(flags, kFlagNonFinite);
@@ -575,7 +580,7 @@ __global__ __launch_bounds__(256) void k_rows(
     const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
     const RowBox* __restrict__ box, const int64_t* __restrict__ tmp_off,
     int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz) {
-  __shared__ T s_acc[4][kRowNodes];
+  __shared__ double s_acc[4][kRowNodes];  // summed in double in both precisions
   __shared__ uint8_t s_flag[4][kRowNodes];
   __shared__ int4 s_m0[4][kWave], s_m1[4][kWave];
   __shared__ int s_ex[4][kWave];
@@ -584,7 +589,7 @@ __global__ __launch_bounds__(256) void k_rows(
   const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = lane_id();
   if (w >= 3 * n_v) return;
-  T* acc = s_acc[wib];
+  double* acc = s_acc[wib];
   uint8_t* flg = s_flag[wib];
   int4* M0 = s_m0[wib];
   int4* M1 = s_m1[wib];
@@ -606,7 +611,7 @@ __global__ __launch_bounds__(256) void k_rows(
   for (int64_t c0 = 0; c0 < total; c0 += kRowNodes) {
     const int span = int(min<int64_t>(kRowNodes, total - c0));
     for (int k = lane; k < span; k += kWave) {
-      acc[k] = T(0);
+      acc[k] = 0.0;
       flg[k] = 0;
     }
     for (int64_t kb = beg; kb < end; kb += kWave) {
@@ -655,7 +660,7 @@ __global__ __launch_bounds__(256) void k_rows(
           const int sl = s0 + qq;
           bool add = false;
           int loc = 0;
-          T val = T(0);
+          double val = 0.0;
           if (sl < wend) {
             const int k = smap[sl - w0];
             const int4 m1 = M1[k];
@@ -675,7 +680,7 @@ __global__ __launch_bounds__(256) void k_rows(
               const uint8_t kp = keep[kb + q];
               const T v = pval[pb + int64_t(q) * 8 + jj];
               add = kp != 0;
-              val = v;
+              val = double(v);
               loc = lin;
             }
           }
@@ -701,7 +706,7 @@ __global__ __launch_bounds__(256) void k_rows(
         const int64_t gz = b.lo[2] + lin / (int64_t(bn0) * bn1);
         const int64_t pos = outpos + rank_below(m);
         tmp_col[pos] = int32_t(gx + NX * (gy + NY * gz));
-        tmp_val[pos] = acc[k];
+        tmp_val[pos] = T(acc[k]);
       }
       outpos += popc64(m);
     }
@@ -850,6 +855,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   k_tet_prep<<<blocks_for(n_t, 256), 256, 0, s>>>(
       n_t, c->X.as<double>(), c->tets.as<int32_t>(), c->lat.as<double>(), c->ld,
       c->tetvol.as<double>(), c->rng.as<CellRange>(), c->cnt.as<int64_t>(), c->tetrec.as<double>(),
+      c->tetgrad.as<double>(),
       flags, counters);
   }
   if ((st = hip_check(hipGetLastError(), "prep launch"))) return st;
@@ -1108,6 +1114,7 @@ int assemble_all(ibvt_coupling* c, hipStream_t s) {
   int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));
   if ((st = ensure(c, c->tetvol, size_t(n_t + 1) * sizeof(double)))) return st;
   if ((st = ensure(c, c->tetrec, size_t(n_t + 1) * kTetRec * sizeof(double)))) return st;
+  if ((st = ensure(c, c->tetgrad, size_t(n_t + 1) * 12 * sizeof(double)))) return st;
   if ((st = ensure(c, c->rng, size_t(3 * n_t + 1) * sizeof(CellRange)))) return st;
   if ((st = ensure(c, c->cnt, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->pair_off, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;

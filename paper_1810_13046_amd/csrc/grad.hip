@@ -144,15 +144,42 @@ __global__ __launch_bounds__(256) void k_shape_mom(
   for (int k = 0; k < 12; ++k) pg[p * 12 + k] = out[k];
 }
 
+// Mass term coefficient per (component d, tet t): |T| · z_T^T S_T u_s,T with
+// S_T = (1 + δ_il)/20 (consistent) or δ_il/4 (lumped) — the derivative of
+// z^T S u_s with respect to vertex a of T is this times ∇λ_a.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass_coef(int64_t n_t, int64_t n_v,
+                                                   const int32_t* __restrict__ tets,
+                                                   const double* __restrict__ tetvol,
+                                                   const T* __restrict__ z, const T* __restrict__ us,
+                                                   int mass, double* __restrict__ out) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= 3 * n_t) return;
+  const int d = int(w / n_t);
+  const int64_t t = w - int64_t(d) * n_t;
+  const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
+  const int32_t vv[4] = {tv.x, tv.y, tv.z, tv.w};
+  double zs = 0, uss = 0, zu = 0;
+  for (int q = 0; q < 4; ++q) {
+    const double zq = double(z[int64_t(d) * n_v + vv[q]]);
+    const double uq = double(us[int64_t(d) * n_v + vv[q]]);
+    zs += zq;
+    uss += uq;
+    zu += zq * uq;
+  }
+  const double sT = (mass == 1) ? (zu + zs * uss) / 20.0 : zu / 4.0;
+  out[w] = tetvol[t] * sT;
+}
+
 // One wavefront per vertex a: lanes take (incident tet, component) items,
 // sum the pair terms and the mass term, then a fixed-order wave reduction.
-// mass: 0 lumped, 1 consistent, -1 none.
+// mcoef: per (component, tet) mass coefficients, or null for no mass term.
 template <typename T>
 __global__ __launch_bounds__(256) void k_grad_gather(
     int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
     const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
-    const int64_t* __restrict__ pair_off, const T* __restrict__ pg, const double* __restrict__ X,
-    const T* __restrict__ z, const T* __restrict__ us, int mass, double alpha,
+    const int64_t* __restrict__ pair_off, const T* __restrict__ pg,
+    const double* __restrict__ tetgrad, const double* __restrict__ mcoef, double alpha,
     double* __restrict__ gX) {
   const int64_t a = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = lane_id();
@@ -163,35 +190,16 @@ __global__ __launch_bounds__(256) void k_grad_gather(
     const int64_t k = it / 3;
     const int d = int(it - k * 3);
     const int64_t t = vt_tet[k];
-    int la = 0;
-    int32_t vv[4];
-    for (int q = 0; q < 4; ++q) {
-      vv[q] = tets[4 * t + q];
-      if (vv[q] == int32_t(a)) la = q;
-    }
+    const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
+    const int la = (tv.y == int32_t(a)) ? 1 : (tv.z == int32_t(a)) ? 2 : (tv.w == int32_t(a)) ? 3 : 0;
     const int64_t tc = int64_t(d) * n_t + t;
     for (int64_t p = pair_off[tc]; p < pair_off[tc + 1]; ++p)
       for (int e = 0; e < 3; ++e) g[e] += double(pg[p * 12 + la * 3 + e]);
-    if (mass >= 0) {
-      TetGeom G;
-      for (int q = 0; q < 4; ++q)
-        for (int e = 0; e < 3; ++e) G.V[q][e] = X[3 * int64_t(vv[q]) + e];
-      tet_geom(G);
-      const double vol = fabs(G.det) / 6.0;
-      double zl[4], ul[4], zs = 0, uss = 0, zu = 0;
-      for (int q = 0; q < 4; ++q) {
-        zl[q] = double(z[int64_t(d) * n_v + vv[q]]);
-        ul[q] = double(us[int64_t(d) * n_v + vv[q]]);
-        zs += zl[q];
-        uss += ul[q];
-        zu += zl[q] * ul[q];
-      }
-      const double s = (mass == 1) ? (zu + zs * uss) / 20.0 : zu / 4.0;
+    if (mcoef) {
+      const double m = mcoef[tc];
+      const double* ga = tetgrad + t * 12 + la * 3;
 #pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const double ga = la == 0 ? G.g[0][e] : (la == 1 ? G.g[1][e] : (la == 2 ? G.g[2][e] : G.g[3][e]));
-        g[e] -= vol * s * ga;
-      }
+      for (int e = 0; e < 3; ++e) g[e] -= m * ga[e];
     }
   }
   for (int e = 0; e < 3; ++e) g[e] = wave_sum(g[e]);
@@ -224,14 +232,21 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
         static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg, flags);
   }
   if ((st = hip_check(hipGetLastError(), "shape launch"))) return st;
+  double* mcoef = nullptr;
+  if (mass >= 0 && c->n_tet > 0) {
+    if ((st = ensure(c, c->mcoef, size_t(3 * c->n_tet + 1) * sizeof(double)))) return st;
+    mcoef = c->mcoef.as<double>();
+    k_mass_coef<T><<<unsigned(ceil_div(3 * c->n_tet, 256)), 256, 0, s>>>(
+        c->n_tet, c->n_vert, c->tets.as<int32_t>(), c->tetvol.as<double>(),
+        static_cast<const T*>(z), static_cast<const T*>(us), mass, mcoef);
+  }
   const unsigned blocks = unsigned(ceil_div(c->n_vert * kWave, 256));
   ProfScope ps_g("grad_gather", s);
   if (c->n_vert > 0)
     k_grad_gather<T><<<blocks, 256, 0, s>>>(c->n_vert, c->n_tet, c->vt_ptr.as<int64_t>(),
                                             c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-                                            c->pair_off.as<int64_t>(), pg, c->X.as<double>(),
-                                            static_cast<const T*>(z), static_cast<const T*>(us),
-                                            mass, alpha, gX);
+                                            c->pair_off.as<int64_t>(), pg, c->tetgrad.as<double>(),
+                                            mcoef, alpha, gX);
   if ((st = hip_check(hipGetLastError(), "gather launch"))) return st;
   unsigned f = 0;
   if ((st = hip_check(hipMemcpyAsync(&f, flags, sizeof(f), hipMemcpyDeviceToHost, s), "read")))

@@ -81,6 +81,8 @@ struct ibvt_coupling {
   ibvt::DevBuf vt_ptr, vt_tet;  // vertex -> incident tets (int64 ptr, int32 ids)
   ibvt::DevBuf tetvol;       // double n_tet
   ibvt::DevBuf tetrec;       // double n_tet*16: per-tet record (vertices, determinant)
+  ibvt::DevBuf tetgrad;      // double n_tet*12: ∇λ_i of every tet
+  ibvt::DevBuf mcoef;        // double 3*n_tet: mass-term coefficients (reverse mode)
   ibvt::DevBuf rng;          // CellRange 3*n_tet
   ibvt::DevBuf cnt;          // int64 3*n_tet
   ibvt::DevBuf pair_off;     // int64 3*n_tet + 1
