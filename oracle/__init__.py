@@ -14,7 +14,11 @@ L2-Projection Approach") directly:
   Section 2.1 (Spatial Discretization);
 * velocity transfer  w_s = S^{-1} B v_f  (S lumped or consistent), solved
   here with a sparse direct factorisation (never CG);
-* force transfer with the transpose.
+* force transfer with the transpose;
+* the dual ("pseudo" L2) variant (eq. biorth): multipliers ψ_i biorthogonal
+  to the P1 hats, here the element-local ψ_i = 5λ_i − 1 on each tet
+  (∫_T λ_j ψ_i = δ_ij |T|/4), so S = diag(∫ψ_i) = the lumped P1 mass and
+  B_ij = ∫ ψ_i N_j.
 
 Readings where the paper is silent are listed in the design doc; the main ones:
 lattice of component d = face coordinates along axis d and face midpoints
@@ -69,7 +73,7 @@ def _load():
         lib.o1_pair_counts.restype = ctypes.c_int
         lib.o1_pairs.argtypes = [P(dp), i64p, dp, ctypes.c_int64, i32p, i64p, ctypes.c_int64, i32p,
                                  i64p, ctypes.c_double, ctypes.c_int, dp, dp,
-                                 P(ctypes.c_uint8), i32p, dp, P(dp), dp, i64p]
+                                 P(ctypes.c_uint8), i32p, dp, P(dp), dp, i64p, ctypes.c_int]
         lib.o1_pairs.restype = ctypes.c_int
         lib.o1_int4.argtypes = [dp] * 5
         lib.o1_int4.restype = ctypes.c_double
@@ -216,7 +220,8 @@ def _lat_arrays(faces):
     return flat, ptrs, nlat
 
 
-def pairs(faces, X, tets, subset=None, drop_rel=DROP_REL, nthreads=0, z=None, u_f=None):
+def pairs(faces, X, tets, subset=None, drop_rel=DROP_REL, nthreads=0, z=None, u_f=None,
+          dual=False):
     """Integrate every (tet, component, cell) pair of the selected tets."""
     lib = _load()
     X = np.ascontiguousarray(X, dtype=np.float64)
@@ -256,7 +261,7 @@ def pairs(faces, X, tets, subset=None, drop_rel=DROP_REL, nthreads=0, z=None, u_
     lib.o1_pairs(ptrs, _i64p(nlat), _dp(X), X.shape[0], _i32p(tets), _i64p(subset), n_sub,
                  _i32p(ranges), _i64p(offsets), float(drop_rel), int(nthreads), _dp(vals),
                  _dp(vols), keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _i32p(cell),
-                 zp, up, Gp, _i64p(zt))
+                 zp, up, Gp, _i64p(zt), int(bool(dual)))
     dt = time.perf_counter() - t0
     return Pairs(subset, counts, offsets, ranges, vals, vols, keep.astype(bool), cell, G,
                  int(zt[0]), dt)
@@ -271,18 +276,26 @@ class Coupling:
     B: list
     pairs: Pairs
     stats: dict = field(default_factory=dict)
+    dual: bool = False
 
     @property
     def n_vert(self):
         return self.X.shape[0]
 
 
-def assemble(faces, X, tets, subset=None, drop_rel=DROP_REL, nthreads=0) -> Coupling:
+def assemble(faces, X, tets, subset=None, drop_rel=DROP_REL, nthreads=0, dual=False) -> Coupling:
     """Mortar matrices B^d_ij = ∫ λ_i N^d_j over the selected tets (all tets
-    by default).  Rows of vertices not touched by the subset are zero."""
+    by default); with dual=True, B^d_ij = ∫ ψ_i N^d_j with the dual
+    multipliers ψ_i = 5λ_i − 1 = Σ_k (5δ_ik − 1) λ_k of each tet, so a
+    piece's values are 5·b_i − Σ_k b_k of its λ products b.  Rows of
+    vertices not touched by the subset are zero."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     tets = np.ascontiguousarray(tets, dtype=np.int32)
     P = pairs(faces, X, tets, subset, drop_rel, nthreads)
+    pvals = P.vals
+    if dual:
+        b = P.vals.reshape(-1, 4, 8)
+        pvals = (5.0 * b - b.sum(axis=1, keepdims=True)).reshape(-1, 32)
     s_idx, comp = P.owner()
     t_idx = P.subset[s_idx]
     B = []
@@ -296,12 +309,12 @@ def assemble(faces, X, tets, subset=None, drop_rel=DROP_REL, nthreads=0) -> Coup
         a, b, cc = corner & 1, (corner >> 1) & 1, (corner >> 2) & 1
         node = ((c[:, 0:1] + a) + nx * ((c[:, 1:2] + b) + ny * (c[:, 2:3] + cc)))  # (k, 8)
         cols = np.tile(node, (1, 4)).reshape(-1)
-        vals = P.vals[sel].reshape(-1)
+        vals = pvals[sel].reshape(-1)
         B.append(sp.csr_matrix((vals, (rows, cols)), shape=(X.shape[0], nx * ny * nz)))
     stats = dict(pairs=int(P.offsets[-1]), pieces=int(P.keep.sum()),
                  dropped=int(((P.vols > 0) & ~P.keep).sum()), zero_tets=P.zero_tets,
                  seconds=P.seconds)
-    return Coupling(list(faces), X, tets, B, P, stats)
+    return Coupling(list(faces), X, tets, B, P, stats, dual)
 
 
 def vertex_star(tets, vertices):
@@ -347,11 +360,20 @@ def mass_solve(X, tets, rhs, mass: str):
     raise ValueError(mass)
 
 
+def _mass_of(cpl: Coupling, mass: str) -> str:
+    """The dual multipliers make S the lumped (diagonal) mass."""
+    if cpl.dual:
+        if mass == "consistent":
+            raise ValueError("the dual basis has a diagonal S: use mass='lumped'")
+        return "lumped"
+    return mass
+
+
 def transfer_velocity(cpl: Coupling, u_f, mass: str = "lumped"):
     """w_s = S^{-1} B v_f per component; u_f: 3 arrays of lattice shape
     (n_z, n_y, n_x).  Returns (3, n_vert)."""
     rhs = np.stack([cpl.B[d] @ np.asarray(u_f[d], dtype=np.float64).ravel() for d in range(3)])
-    return mass_solve(cpl.X, cpl.tets, rhs, mass)
+    return mass_solve(cpl.X, cpl.tets, rhs, _mass_of(cpl, mass))
 
 
 def transfer_force(cpl: Coupling, f_s, alpha: float = 1.0, load: bool = False, base=None):
@@ -360,7 +382,7 @@ def transfer_force(cpl: Coupling, f_s, alpha: float = 1.0, load: bool = False, b
     vector: alpha B^T S^{-1} f_s (consistent S).  Returns 3 flat arrays."""
     f_s = np.asarray(f_s, dtype=np.float64)
     if load:
-        f_s = mass_solve(cpl.X, cpl.tets, f_s, "consistent")
+        f_s = mass_solve(cpl.X, cpl.tets, f_s, "lumped" if cpl.dual else "consistent")
     out = []
     for d in range(3):
         r = alpha * (cpl.B[d].T @ f_s[d])
@@ -370,10 +392,10 @@ def transfer_force(cpl: Coupling, f_s, alpha: float = 1.0, load: bool = False, b
     return out
 
 
-def _shape_pair_terms(faces, X, tets, z, u_f, nthreads=0):
+def _shape_pair_terms(faces, X, tets, z, u_f, nthreads=0, dual=False):
     """Σ over pairs of the B shape-derivative terms, contracted with z (3,n_v)
     and u_f: returns (n_vert, 3)."""
-    P = pairs(faces, X, tets, None, DROP_REL, nthreads, z=z, u_f=u_f)
+    P = pairs(faces, X, tets, None, DROP_REL, nthreads, z=z, u_f=u_f, dual=dual)
     s_idx, _ = P.owner()
     t_idx = P.subset[s_idx]
     g = np.zeros((X.shape[0], 3))
@@ -406,10 +428,11 @@ def velocity_vjp(cpl: Coupling, u_f, g_us, mass: str = "lumped", nthreads=0):
     g_X: (n_vert, 3)).  z = S^{-1} g; g_uf = B^T z; g_X from the shape
     derivative of B (moving P1 hats over the fixed Q1 hats) minus that of S."""
     g_us = np.asarray(g_us, dtype=np.float64)
+    mass = _mass_of(cpl, mass)
     z = mass_solve(cpl.X, cpl.tets, g_us, mass)
     u_s = transfer_velocity(cpl, u_f, mass)
     g_uf = [cpl.B[d].T @ z[d] for d in range(3)]
-    gX = _shape_pair_terms(cpl.faces, cpl.X, cpl.tets, z, u_f, nthreads)
+    gX = _shape_pair_terms(cpl.faces, cpl.X, cpl.tets, z, u_f, nthreads, cpl.dual)
     gX -= _mass_shape_term(cpl.X, cpl.tets, z, u_s, mass)
     return g_uf, gX
 
@@ -418,13 +441,13 @@ def force_vjp(cpl: Coupling, f_s, g_ff, alpha: float = 1.0, nthreads=0):
     """Reverse mode of f_f = alpha B^T f_s.  Returns (g_fs (3, n_vert), g_X)."""
     f_s = np.asarray(f_s, dtype=np.float64)
     g_fs = np.stack([alpha * (cpl.B[d] @ np.asarray(g_ff[d]).ravel()) for d in range(3)])
-    gX = alpha * _shape_pair_terms(cpl.faces, cpl.X, cpl.tets, f_s, g_ff, nthreads)
+    gX = alpha * _shape_pair_terms(cpl.faces, cpl.X, cpl.tets, f_s, g_ff, nthreads, cpl.dual)
     return g_fs, gX
 
 
-def velocity_loss(faces, X, tets, u_f, u_target, mass="lumped"):
+def velocity_loss(faces, X, tets, u_f, u_target, mass="lumped", dual=False):
     """L = 1/2 ||u_s - u_target||^2 with u_s = S^{-1} B u_f (reassembled at X)."""
-    cpl = assemble(faces, X, tets)
+    cpl = assemble(faces, X, tets, dual=dual)
     u_s = transfer_velocity(cpl, u_f, mass)
     r = u_s - u_target
     return 0.5 * float(np.sum(r * r))

@@ -334,13 +334,16 @@ int o1_pair_counts(const double* const* lat, const int64_t* nlat, const double* 
  *   (volume > drop_rel·|T|), cellidx[p*3 + e] (cell index per axis).
  * With z (3 x n_vert, row-major by component), u (3 fluid arrays, x fastest,
  * lattice sizes from nlat) and G non-NULL, also G[p*12 + a*3 + k], the
- * shape-derivative terms of the pair.  zero_tets counts degenerate tets
- * (they produce no pieces).  Returns 0. */
+ * shape-derivative terms of the pair, with w = Σ_i z_i λ_i — or, with dual
+ * set, w = Σ_i z_i ψ_i for the dual multipliers ψ_i = 5λ_i − 1 of the tet
+ * (Section 2.3, eq. biorth), i.e. the same terms with z_i replaced by
+ * 5 z_i − Σ_k z_k.  zero_tets counts degenerate tets (they produce no
+ * pieces).  Returns 0. */
 int o1_pairs(const double* const* lat, const int64_t* nlat, const double* X, int64_t n_vert,
              const int32_t* tets, const int64_t* subset, int64_t n_sub, const int32_t* ranges,
              const int64_t* offsets, double drop_rel, int nthreads, double* vals, double* vols,
              uint8_t* keep, int32_t* cellidx, const double* z, const double* const* u, double* G,
-             int64_t* zero_tets) {
+             int64_t* zero_tets, int dual) {
   init_weights();
   int64_t nz = 0;
 #ifdef _OPENMP
@@ -362,6 +365,10 @@ int o1_pairs(const double* const* lat, const int64_t* nlat, const double* X, int
     if (degenerate && d == 0) nz += 1;
     double zl[4] = {0, 0, 0, 0};
     if (z) for (int v = 0; v < 4; ++v) zl[v] = z[(int64_t)d * n_vert + tets[4 * t + v]];
+    if (z && dual) {
+      double zsum = zl[0] + zl[1] + zl[2] + zl[3];
+      for (int v = 0; v < 4; ++v) zl[v] = 5.0 * zl[v] - zsum;
+    }
     for (int64_t q = 0; q < ncell; ++q) {
       int64_t p = base + q;
       int ci[3] = {r[0] + (int)(q % r[3]), r[1] + (int)((q / r[3]) % r[4]),

@@ -404,3 +404,74 @@ def test_force_gradient_fd(oracle_mod):
     ff = oracle_mod.transfer_force(c, f_s, alpha)
     assert abs(sum(float(np.dot(ff[d], g_ff[d])) for d in range(3)) - float(np.sum(g_fs * f_s))) \
         <= 1e-12 * max(1.0, abs(float(np.sum(g_fs * f_s))))
+
+
+# ---------------------------------------------------------------------------
+# dual ("pseudo" L2) multipliers, Section 2.3 eq. biorth
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cfg1_dual(oracle_mod):
+    W = wl.workload(1)
+    return W, oracle_mod.assemble(W.faces, W.X, W.tets, dual=True)
+
+
+@pytest.fixture(scope="module")
+def cfg3s_dual(oracle_mod):
+    W = wl.workload(3, small=True)
+    return W, oracle_mod.assemble(W.faces, W.X, W.tets, dual=True)
+
+
+def test_dual_affine_reproduction(oracle_mod, cfg1_dual, cfg3s_dual):
+    """Biorthogonality (∫ λ_j ψ_i = δ_ij ∫ ψ_i) makes the transfer with the
+    diagonal S reproduce affine fields exactly at the nodes: ∫ ψ_i p =
+    Σ_j p(x_j) ∫ ψ_i λ_j = p(x_i) m_i, and the Q1 interpolant of p is p."""
+    for W, c in (cfg1_dual, cfg3s_dual):
+        co = np.array([-0.4, 0.9, -1.7, 1.3])
+        p = lambda x, y, z: co[0] + co[1] * x + co[2] * y + co[3] * z
+        u_f = [_lattice_field(oracle_mod, W.faces, d, p) for d in range(3)]
+        us = oracle_mod.transfer_velocity(c, u_f, "lumped")
+        want = p(W.X[:, 0], W.X[:, 1], W.X[:, 2])
+        assert np.max(np.abs(us - want[None, :])) <= 1e-11
+    with pytest.raises(ValueError):
+        oracle_mod.transfer_velocity(cfg1_dual[1], u_f, "consistent")
+
+
+def test_dual_row_sums_are_lumped_mass(oracle_mod, cfg1_dual, cfg3s_dual):
+    """Σ_j B_ij = ∫ ψ_i = m_i: the dual multipliers integrate like the hats.
+    (5 b_i − Σ_k b_k scales the rounding of the λ products by up to 9, hence
+    1e-12 where the standard rows are held to 1e-13.)"""
+    for W, c in (cfg1_dual, cfg3s_dual):
+        m = oracle_mod.lumped_mass(W.X, W.tets)
+        for d in range(3):
+            rs = np.asarray(c.B[d].sum(axis=1)).ravel()
+            assert np.max(np.abs(rs - m)) <= 1e-12 * m.max()
+
+
+def test_dual_gradients_fd(oracle_mod):
+    """Reverse mode of the dual transfers against central differences."""
+    faces, X, tets, u_f = _tiny(oracle_mod)
+    ut = wl.gaussian_nodal(X.shape[0], 98)
+    c = oracle_mod.assemble(faces, X, tets, dual=True)
+    us = oracle_mod.transfer_velocity(c, u_f, "lumped")
+    _, gX = oracle_mod.velocity_vjp(c, u_f, us - ut, "lumped")
+    h = 1e-6
+    for D in wl.fd_directions(X.shape[0], 4, 5011):
+        Lp = oracle_mod.velocity_loss(faces, X + h * D, tets, u_f, ut, "lumped", dual=True)
+        Lm = oracle_mod.velocity_loss(faces, X - h * D, tets, u_f, ut, "lumped", dual=True)
+        fd = (Lp - Lm) / (2 * h)
+        an = float(np.sum(gX * D))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+    f_s = wl.gaussian_nodal(X.shape[0], 32)
+    g_ff = [np.asarray(u).ravel() for u in u_f]
+
+    def L(Xp):
+        cc = oracle_mod.assemble(faces, Xp, tets, dual=True)
+        ff = oracle_mod.transfer_force(cc, f_s, 0.7)
+        return sum(float(np.dot(ff[d], g_ff[d])) for d in range(3))
+
+    _, gXf = oracle_mod.force_vjp(c, f_s, g_ff, 0.7)
+    for D in wl.fd_directions(X.shape[0], 3, 5012):
+        fd = (L(X + h * D) - L(X - h * D)) / (2 * h)
+        an = float(np.sum(gXf * D))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
