@@ -99,12 +99,16 @@ def make_inputs(cfg, dev):
 
 
 class Step:
-    """Buffers and one full pass of the hot path for one precision."""
+    """Buffers and one full pass of the hot path for one precision.  With
+    dual=True the multipliers are the dual basis (S = lumped mass), so the
+    velocity transfer and its adjoint need no CG."""
 
-    def __init__(self, W, X, T, u64, f_s, u_t, precision):
+    def __init__(self, W, X, T, u64, f_s, u_t, precision, dual=False):
         import torch
         from paper_1810_13046_amd import Coupling
-        self.c = Coupling(W.faces, X, T, precision=precision, consistent=True)
+        self.dual = dual
+        self.mass = "lumped" if dual else "consistent"
+        self.c = Coupling(W.faces, X, T, precision=precision, consistent=not dual, dual=dual)
         dt = self.c.dtype
         self.X = X
         self.u = [u.to(dt).contiguous() for u in u64]
@@ -119,10 +123,10 @@ class Step:
     def run(self):
         c = self.c
         c.reassemble(self.X)
-        c.velocity(self.u, mass="consistent", rtol=1e-10, maxit=500, out=self.us)
+        c.velocity(self.u, mass=self.mass, rtol=1e-10, maxit=500, out=self.us)
         c.force(self.f_s, self.ff, alpha=1.0)
         g_us = self.us - self.u_t
-        c.velocity_vjp(g_us, u_f=self.u, u_s=self.us, mass="consistent", g_uf=self.g_uf,
+        c.velocity_vjp(g_us, u_f=self.u, u_s=self.us, mass=self.mass, g_uf=self.g_uf,
                        g_X=self.g_X, rtol=1e-10, maxit=500)
         c.force_vjp(self.u, f_s=self.f_s, alpha=1.0, g_fs=self.g_fs, g_X=self.g_X)
 
@@ -321,6 +325,17 @@ def main():
         del s64
         del mixed_keep
 
+    dual = None
+    if not args.profile_run:
+        log("[bench] dual-basis step (mixed): build")
+        sd = Step(W, X, T, u64, f_s, u_t, "fp32", dual=True)
+        ms_d, _ = time_steps(sd, args.steps, args.warmup)
+        dual = dict(ms_per_step=ms_d, value=n_tet / (ms_d * 1e-3),
+                    note="dual multipliers (S = lumped mass): reassembly, velocity, force, "
+                         "both adjoints; no CG")
+        log(f"[bench] dual {ms_d:.2f} ms/step")
+        del sd
+
     # dominant kernel of the mixed step and its roofline
     per_kernel = {k: v[1] for k, v in prof_mixed.items()}
     dom = max(per_kernel, key=per_kernel.get)
@@ -368,6 +383,7 @@ def main():
         },
         "fp64": fp64,
         "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / ms_mixed) if fp64 else None,
+        "dual_basis": dual,
         "roofline": roof,
         "roofline_apply": roof_apply,
         "cpu_baseline": cpu,

@@ -72,6 +72,14 @@ extern "C" {
 #define IBVT_NO_PIECE_STORE 2u      /* do not keep the pieces' moments; the
                                        reverse-mode calls then clip again
                                        (less device memory) */
+#define IBVT_DUAL_BASIS 4u          /* dual ("pseudo" L2) multipliers,
+                                       Section 2.3 eq. biorth: B_ij =
+                                       ∫ ψ_i N_j with ψ_i = 5λ_i − 1 on each
+                                       tet (∫ λ_j ψ_i = δ_ij |T|/4), so S is
+                                       the lumped mass diag(m): velocity
+                                       transfers take IBVT_LUMPED (consistent
+                                       is IBVT_E_INVALID) and
+                                       IBVT_FORCE_IS_LOAD applies diag(m)^-1 */
 
 /* transfer_force flags. */
 #define IBVT_FORCE_IS_LOAD 1u   /* f_s is a load vector: apply S^{-1}
@@ -134,6 +142,7 @@ typedef struct {
   int64_t dist_evals;        /* plane distances evaluated by the last
                                 assembly's clipping (vertices x planes) */
   int64_t cut_points;        /* edge-plane intersection points it made */
+  int64_t dual;              /* 1 if B holds the dual-multiplier integrals */
 } ibvt_info;
 
 /*

@@ -6,7 +6,9 @@ TransferForce:     f_f = alpha B(X)^T f_s          (a new fluid field)
     backward: g_fs = alpha B g_ff;  g_X = alpha * shape derivative
 
 Both call the C ABI (transfer_velocity / transfer_force and their
-_vjp entry points); no numerical step runs in Python.  With
+_vjp entry points); no numerical step runs in Python.  With dual=True the
+multipliers are the dual basis of Section 2.3 (eq. biorth) and S is the
+lumped mass.  With
 recompute_B=True the coupling is freed after the forward pass and
 assembled again from the saved X in the backward pass, so B and the piece
 store are not held between the two passes.
@@ -19,26 +21,26 @@ from .ibvt import Coupling
 
 
 class _Ctx:
-    def __init__(self, faces, tets, precision, mass, rtol, maxit):
+    def __init__(self, faces, tets, precision, mass, rtol, maxit, dual=False):
         self.faces, self.tets, self.precision = faces, tets, precision
-        self.mass, self.rtol, self.maxit = mass, rtol, maxit
+        self.mass, self.rtol, self.maxit, self.dual = mass, rtol, maxit, dual
 
 
 def _coupling(meta, X, existing):
     if existing is not None:
         return existing
     return Coupling(meta.faces, X.detach().contiguous(), meta.tets, precision=meta.precision,
-                    consistent=(meta.mass == "consistent"))
+                    consistent=(meta.mass == "consistent"), dual=meta.dual)
 
 
 class TransferVelocity(torch.autograd.Function):
     """u_s = TransferVelocity.apply(u_f0, u_f1, u_f2, X, faces, tets, precision,
-    mass, rtol, maxit, coupling, recompute_B) -> (3, n_vert)."""
+    mass, rtol, maxit, coupling, recompute_B, dual) -> (3, n_vert)."""
 
     @staticmethod
     def forward(ctx, u0, u1, u2, X, faces, tets, precision="fp64", mass="lumped", rtol=1e-12,
-                maxit=500, coupling=None, recompute_B=False):
-        meta = _Ctx(faces, tets, precision, mass, rtol, maxit)
+                maxit=500, coupling=None, recompute_B=False, dual=False):
+        meta = _Ctx(faces, tets, precision, mass, rtol, maxit, dual)
         c = _coupling(meta, X, coupling)
         u = [u0.contiguous(), u1.contiguous(), u2.contiguous()]
         us = c.velocity(u, mass=mass, rtol=rtol, maxit=maxit)
@@ -66,17 +68,17 @@ class TransferVelocity(torch.autograd.Function):
             c.free()
         gu = g_uf if need_u else [None, None, None]
         return (gu[0], gu[1], gu[2], g_X.to(X.dtype) if need_X else None,
-                None, None, None, None, None, None, None, None)
+                None, None, None, None, None, None, None, None, None)
 
 
 class TransferForce(torch.autograd.Function):
     """f_f = TransferForce.apply(f_s, X, faces, tets, precision, alpha,
-    coupling, recompute_B) -> tuple of 3 fluid arrays."""
+    coupling, recompute_B, dual) -> tuple of 3 fluid arrays."""
 
     @staticmethod
     def forward(ctx, f_s, X, faces, tets, precision="fp64", alpha=1.0, coupling=None,
-                recompute_B=False):
-        meta = _Ctx(faces, tets, precision, "lumped", 1e-12, 500)
+                recompute_B=False, dual=False):
+        meta = _Ctx(faces, tets, precision, "lumped", 1e-12, 500, dual)
         c = _coupling(meta, X, coupling)
         out = [torch.zeros(s, dtype=c.dtype, device=f_s.device) for s in
                [tuple(reversed(ls)) for ls in c.lattice_shapes]]
@@ -105,15 +107,16 @@ class TransferForce(torch.autograd.Function):
         if ctx.coupling is None:
             c.free()
         return (g_fs, g_X.to(X.dtype) if g_X is not None else None,
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
 def transfer_velocity(u_f, X, faces, tets, precision="fp64", mass="lumped", rtol=1e-12,
-                      maxit=500, coupling=None, recompute_B=False):
+                      maxit=500, coupling=None, recompute_B=False, dual=False):
     return TransferVelocity.apply(u_f[0], u_f[1], u_f[2], X, faces, tets, precision, mass, rtol,
-                                  maxit, coupling, recompute_B)
+                                  maxit, coupling, recompute_B, dual)
 
 
 def transfer_force(f_s, X, faces, tets, precision="fp64", alpha=1.0, coupling=None,
-                   recompute_B=False):
-    return TransferForce.apply(f_s, X, faces, tets, precision, alpha, coupling, recompute_B)
+                   recompute_B=False, dual=False):
+    return TransferForce.apply(f_s, X, faces, tets, precision, alpha, coupling, recompute_B,
+                               dual)

@@ -228,7 +228,7 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
     return set_error(IBVT_E_INVALID, "mesh X or tets is NULL");
   if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
     return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
-  if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE))
+  if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE | IBVT_DUAL_BASIS))
     return set_error(IBVT_E_INVALID, "unknown flags");
   ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
@@ -238,6 +238,7 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
   c->n_tet = mesh->n_tet;
   c->has_M = (flags & IBVT_BUILD_CONSISTENT_M) != 0;
   c->store_pieces = (flags & IBVT_NO_PIECE_STORE) == 0;
+  c->dual = (flags & IBVT_DUAL_BASIS) != 0;
   for (int e = 0; e < 3; ++e) c->n_cells[e] = grid->n_cells[e];
   st = setup_lattices(c, grid, stream);
   if (!st) st = ensure(c, c->X, size_t(3 * c->n_vert) * sizeof(double));
@@ -280,6 +281,8 @@ int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int
     if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
     return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
+  if (c->dual && mass != IBVT_LUMPED)
+    return set_error(IBVT_E_INVALID, "the dual basis has a diagonal S: use IBVT_LUMPED");
   if (info) std::memset(info, 0, sizeof(*info));
   if (mass == IBVT_LUMPED) return apply_B(c, u_f, u_s, true, stream);
   if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
@@ -301,10 +304,14 @@ int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double
   if (flags & ~IBVT_FORCE_IS_LOAD) return set_error(IBVT_E_INVALID, "unknown flags");
   if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
   if (flags & IBVT_FORCE_IS_LOAD) {
-    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
     const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
     int st = ensure(c, c->work2, size_t(3 * c->n_vert) * tsize);
     if (st) return st;
+    if (c->dual) {  // S = diag(m)
+      if ((st = lumped_solve(c, f_s, c->work2.p, stream))) return st;
+      return apply_Bt(c, c->work2.p, f_f, alpha, stream);
+    }
+    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
     const double rtol = c->precision == IBVT_FP32_MIXED ? 1e-6 : 1e-12;
     if ((st = mass_solve(c, f_s, c->work2.p, rtol, 500, stream, nullptr, false))) return st;
     return apply_Bt(c, c->work2.p, f_f, alpha, stream);
@@ -318,6 +325,8 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
   if (!c || !g_us) return set_error(IBVT_E_INVALID, "NULL argument");
   if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
     return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
+  if (c->dual && mass != IBVT_LUMPED)
+    return set_error(IBVT_E_INVALID, "the dual basis has a diagonal S: use IBVT_LUMPED");
   if (g_X && (!u_f || !u_s)) return set_error(IBVT_E_INVALID, "g_X needs u_f and u_s");
   if (g_X)
     for (int d = 0; d < 3; ++d)
@@ -386,6 +395,7 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->piece_store = c->mom_valid ? 1 : 0;
   info->dist_evals = c->stats.dist_evals;
   info->cut_points = c->stats.cut_points;
+  info->dual = c->dual ? 1 : 0;
   return IBVT_OK;
 }
 

@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(
     const int32_t* __restrict__ owner, const int64_t* __restrict__ pair_off,
     const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
     const double* __restrict__ lat, LatDesc ld, uint8_t* __restrict__ keep,
-    T* __restrict__ pval, T* __restrict__ pmom) {
+    T* __restrict__ pval, T* __restrict__ pmom, int dual) {
   __shared__ T red[kWave][kMom];
   __shared__ int rown[kWave];
   __shared__ int rlast[kWave];
@@ -485,6 +485,15 @@ __global__ __launch_bounds__(kWave) void k_integrate(
     const int64_t plane = n_pairs * 8;
     T b[4][8];
     mom_to_b<T>(M, LA, LG, [&](int i, int jj, T v) { b[i][jj] = sc * v; });
+    if (dual) {
+      // dual multipliers ψ_i = 5λ_i − Σ_k λ_k: ∫ ψ_i N_j = 5 b_ij − Σ_k b_kj
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const T sum = b[0][jj] + b[1][jj] + b[2][jj] + b[3][jj];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i][jj] = T(5) * b[i][jj] - sum;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) store_row<8>(pval + i * plane + pj * 8, b[i]);
   }
@@ -967,7 +976,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
         n_pairs, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(), c->owner.as<int32_t>(),
         c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), c->tetrec.as<double>(),
-        c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>());
+        c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>(),
+        c->dual ? 1 : 0);
   }
   if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
   // (IV) global assembly: rows of B^d

@@ -21,6 +21,16 @@ namespace ibvt {
 
 namespace {
 
+// Dual multipliers (eq. biorth): w = Σ_i z_i ψ_i with ψ_i = 5λ_i − 1 on the
+// tet equals Σ_i (5 z_i − Σ_k z_k) λ_i, so the shape terms keep their form
+// with these vertex weights.
+template <typename T>
+__device__ __forceinline__ void dual_weights(T zl[4]) {
+  const T s = zl[0] + zl[1] + zl[2] + zl[3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) zl[k] = T(5) * zl[k] - s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_shape_pairs(
     int64_t n_pairs, int64_t n_t, int64_t n_v, const int32_t* __restrict__ owner,
@@ -28,7 +38,7 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
     const uint8_t* __restrict__ keep, const double* __restrict__ X,
     const int32_t* __restrict__ tets, const double* __restrict__ lat, LatDesc ld,
     const T* __restrict__ z, const T* u0, const T* u1, const T* u2, T* __restrict__ pg,
-    unsigned* flags) {
+    int dual, unsigned* flags) {
   __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
   __shared__ uint32_t snb[kMaxV * kWave];
   const int lane = threadIdx.x;
@@ -42,13 +52,10 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
       for (int k = 0; k < 12; ++k) out[k] = T(0);
       continue;
     }
-    const int64_t tc = owner[p];
-    const int d = int(tc / n_t);
-    const int64_t t = tc - int64_t(d) * n_t;
-    const CellRange r = rng[tc];
-    const int64_t q = p - pair_off[tc];
-    const int ci[3] = {r.lo[0] + int(q % r.n[0]), r.lo[1] + int((q / r.n[0]) % r.n[1]),
-                       r.lo[2] + int(q / (int64_t(r.n[0]) * r.n[1]))};
+    int d, ci[3];
+    int64_t t;
+    double lo[3], hi[3];
+    pair_cell(p, n_t, owner, pair_off, rng, lat, ld, d, t, ci, lo, hi);
     TetGeom G;
     T zl[4];
     for (int k = 0; k < 4; ++k) {
@@ -58,13 +65,8 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
       G.V[k][2] = X[3 * v + 2];
       zl[k] = z[int64_t(d) * n_v + v];
     }
+    if (dual) dual_weights<T>(zl);
     tet_geom(G);
-    double lo[3], hi[3];
-    for (int e = 0; e < 3; ++e) {
-      const double* L = lat + ld.off[3 * d + e];
-      lo[e] = L[ci[e]];
-      hi[e] = L[ci[e] + 1];
-    }
     const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
     const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
     T ul[8];
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(256) void k_shape_mom(
     const uint8_t* __restrict__ keep, const T* __restrict__ pmom,
     const double* __restrict__ tetrec, const double* __restrict__ lat,
     const int32_t* __restrict__ tets, LatDesc ld, const T* __restrict__ z, const T* u0,
-    const T* u1, const T* u2, T* __restrict__ pg) {
+    const T* u1, const T* u2, T* __restrict__ pg, int dual) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
   T out[12];
@@ -115,7 +117,8 @@ __global__ __launch_bounds__(256) void k_shape_mom(
     pair_cell(p, n_t, owner, pair_off, rng, lat, ld, d, t, ci, lo, hi);
     const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
     const T* zd = z + int64_t(d) * n_v;
-    const T zl[4] = {zd[tv.x], zd[tv.y], zd[tv.z], zd[tv.w]};
+    T zl[4] = {zd[tv.x], zd[tv.y], zd[tv.z], zd[tv.w]};
+    if (dual) dual_weights<T>(zl);
     const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
     const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
     const int64_t n000 = ci[0] + NX * (ci[1] + NY * int64_t(ci[2]));
@@ -221,7 +224,7 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
         c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(),
         c->lat.as<double>(), c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
-        static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg);
+        static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg, c->dual ? 1 : 0);
   } else if (c->n_pairs > 0) {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
     ProfScope ps("shape_pairs", s);
@@ -229,7 +232,7 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
         c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->X.as<double>(), c->tets.as<int32_t>(),
         c->lat.as<double>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
-        static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg, flags);
+        static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg, c->dual ? 1 : 0, flags);
   }
   if ((st = hip_check(hipGetLastError(), "shape launch"))) return st;
   double* mcoef = nullptr;

@@ -92,6 +92,7 @@ struct ibvt_coupling {
   ibvt::DevBuf pmom;         // T n_pairs*kMomPad: per-pair piece moments (reverse mode)
   ibvt::DevBuf keep;         // uint8 n_pairs
   bool store_pieces = true;  // keep the moments of every piece (reverse mode)
+  bool dual = false;         // B holds the dual-multiplier integrals ∫ ψ_i N_j
   ibvt::DevBuf pool;         // T records of kRecord values
   int64_t pool_cap = 0;      // records
   int64_t pool_needed = 0;   // records the last assembly asked for

@@ -26,6 +26,7 @@ FP64, FP32_MIXED = 0, 1
 LUMPED, CONSISTENT = 0, 1
 BUILD_CONSISTENT_M = 1
 NO_PIECE_STORE = 2
+DUAL_BASIS = 4
 FORCE_IS_LOAD = 1
 
 EXPORTED = [
@@ -66,7 +67,7 @@ class _Info(ctypes.Structure):
                 ("nnz_mass", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("assemblies", ctypes.c_int64), ("subtets", ctypes.c_int64),
                 ("piece_store", ctypes.c_int64), ("dist_evals", ctypes.c_int64),
-                ("cut_points", ctypes.c_int64)]
+                ("cut_points", ctypes.c_int64), ("dual", ctypes.c_int64)]
 
 
 _lib = None
@@ -187,7 +188,7 @@ class Coupling:
     """A coupling handle: B^d, B^dT, masses for one grid and mesh."""
 
     def __init__(self, faces, X, tets, precision: str = "fp64", consistent: bool = True,
-                 store_pieces: bool = True, stream=None):
+                 store_pieces: bool = True, dual: bool = False, stream=None):
         import torch
         lib = load_library()
         if precision not in ("fp64", "fp32"):
@@ -208,7 +209,9 @@ class Coupling:
         m.X = _dev(X, torch.float64, 3 * self.n_vert, "X")
         m.tets = _dev(tets, torch.int32, 4 * self.n_tet, "tets") if self.n_tet else None
         h = ctypes.c_void_p()
-        flags = (BUILD_CONSISTENT_M if consistent else 0) | (0 if store_pieces else NO_PIECE_STORE)
+        flags = ((BUILD_CONSISTENT_M if consistent else 0) | (0 if store_pieces else NO_PIECE_STORE) |
+                 (DUAL_BASIS if dual else 0))
+        self.dual = bool(dual)
         _check(lib.assemble_coupling(ctypes.byref(g), ctypes.byref(m),
                                      FP64 if precision == "fp64" else FP32_MIXED, flags,
                                      _stream(stream), ctypes.byref(h)), "assemble_coupling")
@@ -308,7 +311,7 @@ class Coupling:
                     zero_tets=i.zero_tets, nnz=list(i.nnz), touched=list(i.touched),
                     nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies,
                     subtets=i.subtets, piece_store=bool(i.piece_store),
-                    dist_evals=i.dist_evals, cut_points=i.cut_points)
+                    dist_evals=i.dist_evals, cut_points=i.cut_points, dual=bool(i.dual))
 
     def export_csr(self, comp: int, transposed: bool = False):
         """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""
