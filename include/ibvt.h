@@ -264,6 +264,88 @@ const char* ibvt_last_error(void);
 int ibvt_lattice_coords(const ibvt_grid* grid, int comp, int axis, double* out, int64_t* n);
 
 /*
+ * Fixed-point (Picard) fluid-structure coupling, Section 3 Steps 1-6.
+ *
+ * fsi_step advances one time step.  It assembles T = S^{-1} B at the
+ * current configuration X = X_ref + u_hat0 (reassemble_coupling; the
+ * transfer follows the solid, Section 2.3), then iterates l = 1, 2, ...:
+ *   Step 1  w_s = T v_f                         (transfer_velocity, cfg->mass)
+ *   Step 2  u_hat = u_hat0 + dt w_s
+ *   Step 3  f_fsi = solid(u_hat)                 (caller's solid solver)
+ *   Step 4  f_tilde = alpha T^T f_fsi            (the literal transpose
+ *           B^T S^{-1} on the load f_fsi; with cfg->force_density != 0 the
+ *           result is divided node by node by the fluid lattice's Q1 lumped
+ *           volume, giving a force density for a finite-difference solver)
+ *   Step 5  v_f = fluid(f_tilde)                 (caller's fluid solver)
+ *   Step 6  stop when ||f_fsi,l − f_fsi,l−1||_inf < eps_abs (eq. AC) or
+ *           that norm / ||f_fsi,1||_inf < eps_rel (eq. RC); f_fsi,0 is the
+ *           caller's `f_prev` on entry (e.g. the previous step's force).
+ * Readings (the paper leaves them open): T is held fixed within the step;
+ * the reference norm of eq. RC is the first iteration's force.
+ *
+ * Callbacks run on the calling thread and enqueue their work on `stream`;
+ * they return an ibvt status (non-zero stops the step with that status).
+ *   solid(ctx, u_hat (3, n_vert), f_fsi (3, n_vert) out, stream)
+ *   fluid(ctx, f_tilde[3] in, v_f[3] out (may alias the caller's v_f), stream)
+ *
+ * Buffers (device, caller-owned; solid fields (3, n_vert), fluid fields per
+ * component as in the transfers, in the coupling's precision; X_ref double
+ * (n_vert, 3)): X_ref, u_hat0 in; v_f in/out; u_hat, w_s, f_fsi, f_tilde
+ * out; f_prev in (f_fsi,0) and overwritten (workspace).
+ * Errors: IBVT_E_INVALID (arguments, consistent mass not built, dual basis
+ * with IBVT_CONSISTENT), IBVT_E_NOT_CONVERGED (max_iter reached; results of
+ * the last iteration are written), or the status of a failed call or
+ * callback.
+ */
+typedef int (*ibvt_solid_fn)(void* ctx, const void* u_hat, void* f_fsi, hipStream_t stream);
+typedef int (*ibvt_fluid_fn)(void* ctx, void* const f_tilde[3], void* const v_f[3],
+                             hipStream_t stream);
+
+typedef struct {
+  double dt;              /* Δt of Step 2 */
+  double alpha;           /* L_ref / (ρ_f U_ref²) of Step 4 */
+  double eps_abs;         /* eq. AC threshold (<= 0: not used) */
+  double eps_rel;         /* eq. RC threshold (<= 0: not used) */
+  int32_t max_iter;       /* Picard iterations, >= 1 */
+  int32_t mass;           /* IBVT_LUMPED or IBVT_CONSISTENT for T */
+  int32_t force_density;  /* divide f_tilde by the fluid nodes' lumped volume */
+  int32_t cg_maxit;       /* consistent-mass CG */
+  double cg_rtol;
+} ibvt_fsi_config;
+
+typedef struct {
+  const double* X_ref;    /* (n_vert, 3) reference configuration */
+  const void* u_hat0;     /* (3, n_vert) displacement at the start of the step */
+  void* u_hat;            /* (3, n_vert) out */
+  void* w_s;              /* (3, n_vert) out: transferred velocity */
+  void* f_fsi;            /* (3, n_vert) out: reaction force, last iteration */
+  void* f_prev;           /* (3, n_vert) in: f_fsi,0; workspace */
+  void* v_f[3];           /* fluid velocity, in/out */
+  void* f_tilde[3];       /* transferred force, out */
+} ibvt_fsi_buffers;
+
+typedef struct {
+  int32_t iterations;     /* Picard iterations done */
+  int32_t converged;      /* 1 if eq. AC or eq. RC held */
+  double res_abs;         /* ||f_fsi,l − f_fsi,l−1||_inf at exit */
+  double res_rel;         /* res_abs / ||f_fsi,1||_inf */
+  double f1_norm;         /* ||f_fsi,1||_inf */
+} ibvt_fsi_report;
+
+int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffers* buf,
+             ibvt_solid_fn solid, void* solid_ctx, ibvt_fluid_fn fluid, void* fluid_ctx,
+             hipStream_t stream, ibvt_fsi_report* report);
+
+/*
+ * ibvt_fluid_lumped_volume — the Q1 lumped volume ∫ N_j of every node of
+ * component comp's lattice (the row sums of the fluid lattice's Q1 mass),
+ * a product of 1D hat integrals over the lattice hull: out (device, double,
+ * (n_z, n_y, n_x)).  Used to turn transferred loads into force densities.
+ * Errors: IBVT_E_INVALID.
+ */
+int ibvt_fluid_lumped_volume(const ibvt_grid* grid, int comp, double* out, hipStream_t stream);
+
+/*
  * Kernel tracing (process-wide; no paper counterpart).  While enabled, the
  * library records a HIP event pair on the caller's stream around each of
  * its main kernel launches.  ibvt_profile_read synchronizes those events and

@@ -110,7 +110,8 @@ void release_all(ibvt_coupling* c) {
                     &c->Mval32,   &c->Mdiag_inv, &c->flags_dev, &c->counters,  &c->scan_tmp,
                     &c->work,     &c->work2,     &c->zbuf,      &c->pool,      &c->pinfo,
                     &c->order,    &c->pscan,     &c->rowbox,    &c->rowcap,    &c->rowtmpoff,
-                    &c->rowtmpcol, &c->rowtmpval, &c->tetgrad, &c->mcoef};
+                    &c->rowtmpcol, &c->rowtmpval, &c->tetgrad, &c->mcoef,
+                    &c->fsiX,     &c->fsinorm,   &c->fvol};
   for (DevBuf* b : bufs) release(c, *b);
   for (int d = 0; d < 3; ++d) {
     release_csr(c, c->B[d]);

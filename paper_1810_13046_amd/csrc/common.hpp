@@ -47,6 +47,11 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }

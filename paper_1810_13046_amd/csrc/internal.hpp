@@ -83,6 +83,10 @@ struct ibvt_coupling {
   ibvt::DevBuf tetrec;       // double n_tet*16: per-tet record (vertices, determinant)
   ibvt::DevBuf tetgrad;      // double n_tet*12: ∇λ_i of every tet
   ibvt::DevBuf mcoef;        // double 3*n_tet: mass-term coefficients (reverse mode)
+  ibvt::DevBuf fsiX;         // double 3*n_vert: configuration of the coupling step
+  ibvt::DevBuf fsinorm;      // double: Step-6 norm partials
+  ibvt::DevBuf fvol;         // double: 1D Q1 lumped weights of the three lattices
+  bool fvol_ready = false;
   ibvt::DevBuf rng;          // CellRange 3*n_tet
   ibvt::DevBuf cnt;          // int64 3*n_tet
   ibvt::DevBuf pair_off;     // int64 3*n_tet + 1

@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libibvt.so")
 
 IBVT_OK = 0
+INVALID = 1
+NOT_CONVERGED = 5
 STATUS_NAMES = {
     0: "IBVT_OK", 1: "IBVT_E_INVALID", 2: "IBVT_E_OUT_OF_GRID", 3: "IBVT_E_HIP",
     4: "IBVT_E_NOMEM", 5: "IBVT_E_NOT_CONVERGED", 6: "IBVT_E_CAPACITY", 7: "IBVT_E_UNSUPPORTED",
@@ -33,7 +35,7 @@ EXPORTED = [
     "assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
     "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info", "coupling_export_csr",
     "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
-    "ibvt_profile_enable", "ibvt_profile_read",
+    "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
 ]
 
 
@@ -73,6 +75,31 @@ class _Info(ctypes.Structure):
 _lib = None
 
 
+class _FsiConfig(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("eps_abs", ctypes.c_double),
+                ("eps_rel", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mass", ctypes.c_int32),
+                ("force_density", ctypes.c_int32), ("cg_maxit", ctypes.c_int32),
+                ("cg_rtol", ctypes.c_double)]
+
+
+class _FsiBuffers(ctypes.Structure):
+    _fields_ = [("X_ref", ctypes.c_void_p), ("u_hat0", ctypes.c_void_p), ("u_hat", ctypes.c_void_p),
+                ("w_s", ctypes.c_void_p), ("f_fsi", ctypes.c_void_p), ("f_prev", ctypes.c_void_p),
+                ("v_f", ctypes.c_void_p * 3), ("f_tilde", ctypes.c_void_p * 3)]
+
+
+class _FsiReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("res_abs", ctypes.c_double), ("res_rel", ctypes.c_double),
+                ("f1_norm", ctypes.c_double)]
+
+
+_SOLID_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_void_p)
+_FLUID_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                             ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p)
+
+
 def load_library(path: str = LIB_PATH):
     """Load libibvt.so (raises if it has not been built)."""
     global _lib
@@ -102,9 +129,13 @@ def load_library(path: str = LIB_PATH):
     lib.ibvt_profile_enable.restype = None
     lib.ibvt_profile_read.argtypes = [P(ctypes.c_char_p), P(i64), P(dbl), ctypes.c_int]
     lib.ibvt_profile_read.restype = ctypes.c_int
+    lib.fsi_step.argtypes = [vp, P(_FsiConfig), P(_FsiBuffers), _SOLID_FN, vp, _FLUID_FN, vp, vp,
+                             P(_FsiReport)]
+    lib.ibvt_fluid_lumped_volume.argtypes = [P(_Grid), ctypes.c_int, vp, vp]
     for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
-                 "coupling_export_csr", "ibvt_lattice_coords"):
+                 "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
+                 "ibvt_fluid_lumped_volume"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -179,6 +210,29 @@ def _dev(t, dtype, numel, what):
 
 
 @dataclass
+class FsiReport:
+    iterations: int
+    converged: bool
+    res_abs: float
+    res_rel: float
+    f1_norm: float
+
+
+def fluid_lumped_volume(faces, comp: int, device=None, stream=None):
+    """Q1 lumped volume ∫ N_j of every node of component comp's lattice,
+    shape (n_z, n_y, n_x), float64 on the device."""
+    import torch
+    lib = load_library()
+    g, keep = _grid_struct(faces)
+    shape = tuple(reversed([len(a) for a in lattice_coords(faces, comp)]))
+    out = torch.empty(shape, dtype=torch.float64, device=device or "cuda")
+    _check(lib.ibvt_fluid_lumped_volume(ctypes.byref(g), comp, ctypes.c_void_p(out.data_ptr()),
+                                        _stream(stream)), "ibvt_fluid_lumped_volume")
+    del keep
+    return out
+
+
+@dataclass
 class SolveInfo:
     iterations: tuple
     rel_residual: tuple
@@ -223,6 +277,68 @@ class Coupling:
         self.n_fluid = [int(np.prod(s)) for s in self.lattice_shapes]
 
     # -- lifetime ---------------------------------------------------------
+    def fsi_step(self, X_ref, u_hat0, v_f, solid, fluid, *, dt, alpha=1.0, eps_abs=0.0,
+                 eps_rel=1e-8, max_iter=50, mass="lumped", force_density=False, cg_rtol=1e-10,
+                 cg_maxit=500, f_prev=None, stream=None, raise_not_converged=True):
+        """One time step of the Picard coupling (Section 3, Steps 1-6) through
+        the C driver.  solid(u_hat, f_fsi) fills f_fsi (3, n_vert) from the
+        displacement u_hat; fluid(f_tilde, v_f) updates the 3 fluid velocity
+        arrays v_f in place from the transferred force.  Both receive this
+        call's tensors and must enqueue their work on the current stream.
+        Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
+        import torch
+        dt_ = self.dtype
+        dev = X_ref.device
+        n = self.n_vert
+        out = dict(u_hat=torch.empty((3, n), dtype=dt_, device=dev),
+                   w_s=torch.empty((3, n), dtype=dt_, device=dev),
+                   f_fsi=torch.empty((3, n), dtype=dt_, device=dev),
+                   f_tilde=[torch.empty_like(v) for v in v_f])
+        fp = torch.zeros((3, n), dtype=dt_, device=dev) if f_prev is None else f_prev
+        cfg = _FsiConfig(float(dt), float(alpha), float(eps_abs), float(eps_rel), int(max_iter),
+                         LUMPED if mass == "lumped" else CONSISTENT, int(bool(force_density)),
+                         int(cg_maxit), float(cg_rtol))
+        buf = _FsiBuffers()
+        buf.X_ref = _dev(X_ref, torch.float64, 3 * n, "X_ref")
+        buf.u_hat0 = _dev(u_hat0, dt_, 3 * n, "u_hat0")
+        buf.u_hat = out["u_hat"].data_ptr()
+        buf.w_s = out["w_s"].data_ptr()
+        buf.f_fsi = out["f_fsi"].data_ptr()
+        buf.f_prev = _dev(fp, dt_, 3 * n, "f_prev")
+        for d in range(3):
+            buf.v_f[d] = _dev(v_f[d], dt_, self.n_fluid[d], f"v_f[{d}]")
+            buf.f_tilde[d] = out["f_tilde"][d].data_ptr()
+        errors = []
+
+        def _solid(ctx, u_ptr, f_ptr, s):
+            try:
+                solid(out["u_hat"], out["f_fsi"])
+                return 0
+            except BaseException as e:          # reported after the C call returns
+                errors.append(e)
+                return INVALID
+
+        def _fluid(ctx, ft_ptr, vf_ptr, s):
+            try:
+                fluid(out["f_tilde"], v_f)
+                return 0
+            except BaseException as e:
+                errors.append(e)
+                return INVALID
+
+        cs, cf = _SOLID_FN(_solid), _FLUID_FN(_fluid)
+        rep = _FsiReport()
+        st = _lib.fsi_step(self.handle, ctypes.byref(cfg), ctypes.byref(buf), cs, None, cf, None,
+                           _stream(stream), ctypes.byref(rep))
+        if errors:
+            raise errors[0]
+        report = FsiReport(int(rep.iterations), bool(rep.converged), float(rep.res_abs),
+                           float(rep.res_rel), float(rep.f1_norm))
+        if st != IBVT_OK and not (st == NOT_CONVERGED and not raise_not_converged):
+            _check(st, "fsi_step")
+        out["f_prev"] = fp
+        return report, out
+
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.coupling_free(self._h)

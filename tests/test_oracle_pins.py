@@ -475,3 +475,69 @@ def test_dual_gradients_fd(oracle_mod):
         fd = (L(X + h * D) - L(X - h * D)) / (2 * h)
         an = float(np.sum(gXf * D))
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+# ---------------------------------------------------------------------------
+# Picard coupling (Section 3) and the fluid lattice's lumped volume
+# ---------------------------------------------------------------------------
+
+def test_fluid_lumped_volume(oracle_mod):
+    """∫ N_j over the lattice hull = product of exact 1D hat integrals; the
+    volumes tile the hull."""
+    W = wl.workload(3, small=True)                 # stretched y faces
+    for d in range(3):
+        lat = oracle_mod.lattice(W.faces, d)
+        V = oracle_mod.fluid_lumped_volume(W.faces, d)
+        I = [np.array([hat_integral_exact(lat[e], k, lat[e][0], lat[e][-1])
+                       for k in range(lat[e].size)]) for e in range(3)]
+        ref = np.einsum("k,j,i->kji", I[2], I[1], I[0])
+        assert np.max(np.abs(V - ref)) <= 1e-15 * ref.max()
+        hull = np.prod([lat[e][-1] - lat[e][0] for e in range(3)])
+        assert abs(V.sum() - hull) <= 1e-13 * hull
+
+
+def _fsi_stubs(oracle_mod, n_vert, faces, seed):
+    """Linear solid and fluid operators: a spring toward a rest displacement
+    and a fluid whose velocity responds linearly to the force."""
+    rng = np.random.default_rng(seed)
+    u_rest = 1e-3 * rng.standard_normal((3, n_vert))
+    k_s = 10.0
+    v_base = [rng.standard_normal(oracle_mod.n_fluid(faces, d)) for d in range(3)]
+    beta = 0.5
+
+    def solid(u_hat):
+        return -k_s * (u_hat - u_rest)
+
+    def fluid(f_tilde):
+        return [v_base[d] + beta * f_tilde[d] for d in range(3)]
+
+    return solid, fluid, (u_rest, k_s, v_base, beta)
+
+
+@pytest.mark.parametrize("mode", ["lumped", "consistent", "dual"])
+def test_fsi_picard_reaches_the_fixed_point(oracle_mod, mode):
+    """With linear stubs the fixed point of Steps 1-5 solves
+    (I + k dt beta alpha T Tᵀ) f = −k (û0 − û_rest + dt T v_base) with
+    T = S⁻¹B; the Picard iteration (Step 6 stopping test) must land on the
+    direct solution of that dense system."""
+    faces, X, tets, _ = _tiny(oracle_mod)
+    n = X.shape[0]
+    dual = mode == "dual"
+    mass = "consistent" if mode == "consistent" else "lumped"
+    solid, fluid, (u_rest, k_s, v_base, beta) = _fsi_stubs(oracle_mod, n, faces, 21)
+    rng = np.random.default_rng(5)
+    u0 = 1e-3 * rng.standard_normal((3, n))
+    v0 = [np.zeros(oracle_mod.n_fluid(faces, d)) for d in range(3)]
+    dt, alpha = 0.05, 0.8
+    r = oracle_mod.fsi_step(faces, X, tets, u0, v0, solid, fluid, dt, alpha, eps_abs=1e-14,
+                            eps_rel=0.0, max_iter=200, mass=mass, dual=dual)
+    assert r["converged"]
+    c = oracle_mod.assemble(faces, X + u0.T, tets, dual=dual)
+    S = (oracle_mod.lumped_mass(c.X, tets) if mass == "lumped" else None)
+    Sm = np.diag(S) if S is not None else oracle_mod.consistent_mass(c.X, tets).toarray()
+    for d in range(3):
+        Td = np.linalg.solve(Sm, c.B[d].toarray())
+        A = np.eye(n) + k_s * dt * beta * alpha * Td @ Td.T
+        rhs = -k_s * (u0[d] - u_rest[d] + dt * Td @ v_base[d])
+        f_star = np.linalg.solve(A, rhs)
+        assert np.max(np.abs(r["f_fsi"][d] - f_star)) <= 1e-11 * max(1.0, np.max(np.abs(f_star)))
