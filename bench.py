@@ -193,6 +193,43 @@ def apply_rates(step, reps=20):
                 velocity_GBs=vel_bytes / vel_ms / 1e6, force_GBs=frc_bytes / frc_ms / 1e6)
 
 
+def fsi_rate(step, iters=6):
+    """One Picard time step (Section 3) through fsi_step with stub solvers
+    (a spring solid, a fluid whose velocity follows the force): ms of a step
+    with 1 and with `iters` iterations; their difference per extra iteration
+    is the cost of one Picard iteration (Steps 1-6 without real solvers)."""
+    import torch
+    c = step.c
+    n = c.n_vert
+    u0 = torch.zeros((3, n), dtype=c.dtype, device=step.X.device)
+    vf = [u.clone() for u in step.u]
+
+    def solid(u_hat, f):
+        torch.mul(u_hat, -10.0, out=f)
+
+    def fluid(ft, v):
+        for d in range(3):
+            v[d].add_(ft[d], alpha=1e-3)
+
+    def run(k):
+        c.fsi_step(step.X, u0, vf, solid, fluid, dt=1e-3, alpha=1.0, eps_abs=0.0, eps_rel=0.0,
+                   max_iter=k, mass=step.mass, raise_not_converged=False)
+
+    out = {}
+    for k in (1, iters):
+        run(k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run(k)
+        e1.record()
+        torch.cuda.synchronize()
+        out[k] = e0.elapsed_time(e1)
+    return dict(step_ms_1_iteration=out[1], step_ms=out[iters], iterations=iters,
+                ms_per_picard_iteration=(out[iters] - out[1]) / (iters - 1),
+                mass=step.mass, note="stub solvers; T assembled once per step at X_ref + u_hat0")
+
+
 def cpu_baseline(W, dev, tets_per_body):
     """The FP64 oracle on a bounded sample: the first `tets_per_body` tets of
     each body (a sub-mesh on the same grid), one full step."""
@@ -308,6 +345,11 @@ def main():
     rates_mixed = apply_rates(mixed)
     info = mixed.c.info()
     log(f"[bench] mixed {ms_mixed:.2f} ms/step; kernels {json.dumps(prof_mixed)}")
+    fsi = None
+    if not args.profile_run:
+        log("[bench] Picard coupling step (mixed)")
+        fsi = fsi_rate(mixed)
+        log(f"[bench] fsi {fsi['ms_per_picard_iteration']:.2f} ms per Picard iteration")
 
     fp64 = None
     if not args.skip_fp64:
@@ -384,6 +426,7 @@ def main():
         "fp64": fp64,
         "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / ms_mixed) if fp64 else None,
         "dual_basis": dual,
+        "fsi_picard": fsi,
         "roofline": roof,
         "roofline_apply": roof_apply,
         "cpu_baseline": cpu,
