@@ -53,12 +53,15 @@ DROP_REL = 1e-14
 
 
 def build(force: bool = True) -> str:
-    """Compile the C part of the oracle with gcc (plain C, OpenMP)."""
+    """Compile the C parts of the oracle (3D here, 2D in oracle.plane) with
+    gcc (plain C, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    from . import plane
+    plane.build(force)
     return _LIB
 
 

@@ -70,3 +70,36 @@ def ref_simplex_monomial(a, b, c):
     """∫ over {x,y,z>=0, x+y+z<=1} of x^a y^b z^c = a! b! c! / (a+b+c+3)!"""
     from math import factorial
     return Fraction(factorial(a) * factorial(b) * factorial(c), factorial(a + b + c + 3))
+
+
+def triangle_rule(n=6):
+    """Conical-product Gauss rule on a triangle: (u, v) in the unit square
+    maps to x = u, y = v (1-u), Jacobian (1-u); Gauss–Jacobi points in u
+    absorb it.  Exact for degree <= 2n-1.  Returns barycentric points (m,3)
+    and weights summing to 1."""
+    u, wu = _gj01(n, 1.0)
+    v, wv = _gj01(n, 0.0)
+    U, V = np.meshgrid(u, v, indexing="ij")
+    WU, WV = np.meshgrid(wu, wv, indexing="ij")
+    x = U
+    y = V * (1 - U)
+    wt = (WU * WV).ravel() * 2.0            # reference area 1/2 -> weights sum to 1
+    bary = np.stack([1 - x - y, x, y], axis=-1).reshape(-1, 3)
+    return bary, wt
+
+
+def tri_integral(P, f, n=6):
+    """∫_T f for triangle T with vertices P (3x2); f maps (m,2) points to (m, ...)."""
+    P = np.asarray(P, dtype=np.float64)
+    bary, wt = triangle_rule(n)
+    pts = bary @ P
+    a = P[1] - P[0]
+    b = P[2] - P[0]
+    area = 0.5 * abs(a[0] * b[1] - a[1] * b[0])
+    return area * np.tensordot(wt, f(pts), axes=(0, 0))
+
+
+def ref_triangle_monomial(a, b):
+    """∫ over {x,y>=0, x+y<=1} of x^a y^b = a! b! / (a+b+2)!"""
+    from math import factorial
+    return Fraction(factorial(a) * factorial(b), factorial(a + b + 2))

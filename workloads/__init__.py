@@ -4,3 +4,4 @@ This package holds input generation only (meshes, grids, fields, seeds);
 none of the transfer arithmetic lives here.
 """
 from .gen import *  # noqa: F401,F403
+from . import plane  # noqa: F401,E402  (two-dimensional workloads)
