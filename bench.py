@@ -16,6 +16,12 @@ The headline `value` is solid tets per second of that step in the
 mixed-precision path (double clipping, float quadrature and applies); the
 same step in FP64 is reported beside it.
 
+Also reported (not the headline): the same step with the dual multipliers,
+one Picard coupling step, and the planar coupling (Q1 quadrilateral lattice
+x P1 triangles) on the Turek–Hron-like reference mesh (43,824 triangles in a
+4608 x 762 grid, workloads/plane.py) in both precisions, with the 2D oracle
+timed on the same step.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
@@ -58,8 +64,8 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="149bbb65d5cd590c601ca7b33e46571c92bad0d2a78d039cff461352e5ff343c",
-                    bytes_mixed=55812873344)
+CLIP_TRAFFIC = dict(sources_sha256="73607bea0b4cf847c296d77e256acf3ed2dd716d25d4fec7f575d116dbe865b8",
+                    bytes_mixed=35620465920)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
 
@@ -114,11 +120,11 @@ class Step:
         self.u = [u.to(dt).contiguous() for u in u64]
         self.f_s = f_s.to(dt).contiguous()
         self.u_t = u_t.to(dt).contiguous()
-        self.us = torch.empty((3, X.shape[0]), dtype=dt, device=X.device)
+        self.us = torch.empty((self.c.nc, X.shape[0]), dtype=dt, device=X.device)
         self.ff = [torch.zeros_like(u) for u in self.u]
         self.g_uf = [torch.zeros_like(u) for u in self.u]
         self.g_fs = torch.zeros_like(self.f_s)
-        self.g_X = torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device)
+        self.g_X = torch.zeros((X.shape[0], X.shape[1]), dtype=torch.float64, device=X.device)
 
     def run(self):
         c = self.c
@@ -129,6 +135,68 @@ class Step:
         c.velocity_vjp(g_us, u_f=self.u, u_s=self.us, mass=self.mass, g_uf=self.g_uf,
                        g_X=self.g_X, rtol=1e-10, maxit=500)
         c.force_vjp(self.u, f_s=self.f_s, alpha=1.0, g_fs=self.g_fs, g_X=self.g_X)
+
+
+def make_inputs_planar(dev):
+    """The Turek–Hron-like reference mesh and grid (workloads/plane.py)."""
+    import torch
+    import workloads as wl
+    from paper_1810_13046_amd import lattice_coords
+    P2 = wl.plane
+    W = P2.workload2(5)
+    k, phi = P2.fourier_modes2(W.n_modes, W.kmax, 2100 + W.key)
+    u64 = [torch.as_tensor(P2.fourier_field2(k[d], phi[d], *lattice_coords(W.faces, d),
+                                             scale=W.extent), device=dev).contiguous()
+           for d in range(2)]
+    X = torch.as_tensor(W.X, device=dev).contiguous()
+    T = torch.as_tensor(W.tris, device=dev).contiguous()
+    f_s = torch.as_tensor(W.f_s(), device=dev).contiguous()
+    u_t = torch.as_tensor(W.u_target(), device=dev).contiguous()
+    torch.cuda.synchronize()
+    return W, X, T, u64, f_s, u_t
+
+
+def planar_oracle_step(W):
+    """The 2D oracle on the same step (assembly, consistent velocity by sparse
+    LU, force, both adjoints): seconds for the whole mesh."""
+    from oracle import plane as pl
+    import workloads as wl
+    P2 = wl.plane
+    k, phi = P2.fourier_modes2(W.n_modes, W.kmax, 2100 + W.key)
+    u = [P2.fourier_field2(k[d], phi[d], *pl.lattice(W.faces, d), scale=W.extent)
+         for d in range(2)]
+    t0 = time.perf_counter()
+    cpl = pl.assemble(W.faces, W.X, W.tris)
+    us = pl.transfer_velocity(cpl, u, "consistent")
+    pl.transfer_force(cpl, W.f_s(), 1.0)
+    pl.velocity_vjp(cpl, u, us - W.u_target(), "consistent")
+    pl.force_vjp(cpl, W.f_s(), [a.ravel() for a in u], 1.0)
+    return time.perf_counter() - t0
+
+
+def planar_leg(dev, steps, warmup, with_cpu):
+    W, X, T, u64, f_s, u_t = make_inputs_planar(dev)
+    n_tri = W.tris.shape[0]
+    out = dict(workload=W.name, n_tri=int(n_tri), n_vert=int(W.X.shape[0]),
+               grid_cells=list(W.n_cells), unit="solid triangles/s (same step as 3D)")
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] planar {prec} step")
+        st = Step(W, X, T, u64, f_s, u_t, prec)
+        ms, wall = time_steps(st, steps, warmup)
+        prof = kernel_profile(st)
+        info = st.c.info()
+        out[prec] = dict(ms_per_step=ms, wall_ms_per_step=wall, value=n_tri / (ms * 1e-3),
+                         kernels_ms={k: v[1] for k, v in prof.items()},
+                         kernel_launches={k: v[0] for k, v in prof.items()},
+                         pairs=info["pairs"], pieces=info["pieces"], nnz=info["nnz"][:2])
+        log(f"[bench] planar {prec} {ms:.3f} ms/step")
+        del st
+    if with_cpu:
+        sec = planar_oracle_step(W)
+        out["cpu_oracle"] = dict(value=n_tri / sec, seconds=sec, kind="oracle",
+                                 cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                                 sample="the whole mesh, one step")
+    return out
 
 
 def time_steps(step, steps, warmup):
@@ -388,6 +456,10 @@ def main():
                       launch_ms=rates_mixed["velocity_ms"],
                       algorithmic_bytes_per_launch=rates_mixed["velocity_bytes"])
 
+    planar = None
+    if not args.profile_run:
+        planar = planar_leg(dev, max(args.steps, 10), args.warmup, not args.skip_cpu)
+
     cpu = None
     if not args.skip_cpu:
         log("[bench] cpu baseline (oracle)")
@@ -427,6 +499,7 @@ def main():
         "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / ms_mixed) if fp64 else None,
         "dual_basis": dual,
         "fsi_picard": fsi,
+        "planar": planar,
         "roofline": roof,
         "roofline_apply": roof_apply,
         "cpu_baseline": cpu,

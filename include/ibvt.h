@@ -31,6 +31,14 @@
  *     convergence checks and when `info` is requested.
  *   - Every call returns an ibvt status; nothing throws across the ABI.
  *     ibvt_last_error() returns a thread-local message for the last failure.
+ *
+ * Planar couplings (assemble_coupling_2d: Q1 quadrilateral lattice x P1
+ * triangles, the setting of the paper's 2D experiments in Section 4) use the
+ * same handle and the same transfer calls with two components: solid fields
+ * are (2, n_vert), fluid fields u_f[0], u_f[1] are (n_y, n_x) arrays (u_f[2]
+ * is ignored and may be NULL), X and g_X are (n_vert, 2).  Areas replace
+ * volumes: m_i = Σ_{T∋i} |T|/3, M_il = |T|(1+δ_il)/12, and the dual
+ * multipliers are ψ_i = 4λ_i − 1 on each triangle.
  */
 #ifndef IBVT_H
 #define IBVT_H
@@ -143,6 +151,8 @@ typedef struct {
                                 assembly's clipping (vertices x planes) */
   int64_t cut_points;        /* edge-plane intersection points it made */
   int64_t dual;              /* 1 if B holds the dual-multiplier integrals */
+  int64_t dim;               /* 3, or 2 for a planar coupling (n_tet then
+                                counts triangles, component 2 is empty) */
 } ibvt_info;
 
 /*
@@ -164,6 +174,41 @@ typedef struct {
  */
 int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precision,
                       uint32_t flags, hipStream_t stream, ibvt_coupling** out);
+
+/* Planar grid: as ibvt_grid with two axes (component d on the faces normal
+ * to axis d, face midpoints along the other axis). */
+typedef struct {
+  int32_t n_cells[2];
+  const double* faces[2];
+} ibvt_grid2d;
+
+/* P1 triangle mesh: X device (n_vert, 2) double row-major; tris device
+ * (n_tri, 3) int32, either orientation. */
+typedef struct {
+  int64_t n_vert;
+  int64_t n_tri;
+  const double* X;
+  const int32_t* tris;
+} ibvt_mesh2d;
+
+/*
+ * assemble_coupling_2d — the planar coupling: B^d_ij = ∫ λ_i N^d_j dA for
+ *   d = 0, 1 (Section 2.3 over areas), B^dT, the lumped mass m_i =
+ *   Σ_{T∋i} |T|/3 and, with IBVT_BUILD_CONSISTENT_M, M_il = |T|(1+δ_il)/12.
+ *   Each triangle ∩ cell piece is integrated exactly from its ten moments
+ *   (monomials of degree <= 3 in cell-local coordinates, taken by Green's
+ *   theorem over the piece boundary with the boundary's intersections in
+ *   double); the moments are always kept for the reverse mode
+ *   (IBVT_NO_PIECE_STORE has no effect).  IBVT_DUAL_BASIS gives ψ_i =
+ *   4λ_i − 1.  The handle works with every transfer call (two components,
+ *   see the conventions above), reassemble_coupling (X (n_vert, 2)),
+ *   coupling_info and coupling_export_csr (comp 0 or 1); fsi_step returns
+ *   IBVT_E_UNSUPPORTED for it.
+ *   Errors: IBVT_E_INVALID, IBVT_E_OUT_OF_GRID, IBVT_E_CAPACITY,
+ *   IBVT_E_NOMEM, IBVT_E_HIP.
+ */
+int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int precision,
+                         uint32_t flags, hipStream_t stream, ibvt_coupling** out);
 
 /*
  * reassemble_coupling — rebuild the same coupling for moved vertices X
@@ -263,6 +308,9 @@ const char* ibvt_last_error(void);
  */
 int ibvt_lattice_coords(const ibvt_grid* grid, int comp, int axis, double* out, int64_t* n);
 
+/* ibvt_lattice_coords_2d — the same for a planar grid (comp, axis in {0, 1}). */
+int ibvt_lattice_coords_2d(const ibvt_grid2d* grid, int comp, int axis, double* out, int64_t* n);
+
 /*
  * Fixed-point (Picard) fluid-structure coupling, Section 3 Steps 1-6.
  *
@@ -293,9 +341,9 @@ int ibvt_lattice_coords(const ibvt_grid* grid, int comp, int axis, double* out, 
  * (n_vert, 3)): X_ref, u_hat0 in; v_f in/out; u_hat, w_s, f_fsi, f_tilde
  * out; f_prev in (f_fsi,0) and overwritten (workspace).
  * Errors: IBVT_E_INVALID (arguments, consistent mass not built, dual basis
- * with IBVT_CONSISTENT), IBVT_E_NOT_CONVERGED (max_iter reached; results of
- * the last iteration are written), or the status of a failed call or
- * callback.
+ * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (planar coupling),
+ * IBVT_E_NOT_CONVERGED (max_iter reached; results of the last iteration are
+ * written), or the status of a failed call or callback.
  */
 typedef int (*ibvt_solid_fn)(void* ctx, const void* u_hat, void* f_fsi, hipStream_t stream);
 typedef int (*ibvt_fluid_fn)(void* ctx, void* const f_tilde[3], void* const v_f[3],

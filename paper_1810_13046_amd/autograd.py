@@ -11,7 +11,9 @@ multipliers are the dual basis of Section 2.3 (eq. biorth) and S is the
 lumped mass.  With
 recompute_B=True the coupling is freed after the forward pass and
 assembled again from the saved X in the backward pass, so B and the piece
-store are not held between the two passes.
+store are not held between the two passes.  Planar couplings (two face
+arrays, X (n_vert, 2), triangles) take two fluid components: pass
+u_f = (u0, u1) and get two force arrays back.
 """
 from __future__ import annotations
 
@@ -35,45 +37,47 @@ def _coupling(meta, X, existing):
 
 class TransferVelocity(torch.autograd.Function):
     """u_s = TransferVelocity.apply(u_f0, u_f1, u_f2, X, faces, tets, precision,
-    mass, rtol, maxit, coupling, recompute_B, dual) -> (3, n_vert)."""
+    mass, rtol, maxit, coupling, recompute_B, dual) -> (nc, n_vert); u_f2 is
+    None for a planar coupling."""
 
     @staticmethod
     def forward(ctx, u0, u1, u2, X, faces, tets, precision="fp64", mass="lumped", rtol=1e-12,
                 maxit=500, coupling=None, recompute_B=False, dual=False):
         meta = _Ctx(faces, tets, precision, mass, rtol, maxit, dual)
         c = _coupling(meta, X, coupling)
-        u = [u0.contiguous(), u1.contiguous(), u2.contiguous()]
+        u = [v.contiguous() for v in (u0, u1, u2) if v is not None]
         us = c.velocity(u, mass=mass, rtol=rtol, maxit=maxit)
         ctx.meta = meta
+        ctx.nc = len(u)
         ctx.recompute = recompute_B and coupling is None
         ctx.coupling = None if ctx.recompute else c
-        ctx.save_for_backward(u[0], u[1], u[2], X, us)
+        ctx.save_for_backward(X, us, *u)
         if ctx.recompute:
             c.free()
         return us
 
     @staticmethod
     def backward(ctx, g_us):
-        u0, u1, u2, X, us = ctx.saved_tensors
+        X, us, *u = ctx.saved_tensors
         meta = ctx.meta
         c = ctx.coupling if ctx.coupling is not None else _coupling(meta, X, None)
-        u = [u0, u1, u2]
         need_u = any(ctx.needs_input_grad[:3])
         need_X = ctx.needs_input_grad[3]
         g_uf = [torch.zeros_like(v) for v in u] if need_u else None
-        g_X = torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device) if need_X else None
+        g_X = (torch.zeros((X.shape[0], X.shape[1]), dtype=torch.float64, device=X.device)
+               if need_X else None)
         c.velocity_vjp(g_us.contiguous().to(us.dtype), u_f=u, u_s=us, mass=meta.mass, g_uf=g_uf,
                        g_X=g_X, rtol=meta.rtol, maxit=meta.maxit)
         if ctx.coupling is None:
             c.free()
-        gu = g_uf if need_u else [None, None, None]
+        gu = (g_uf if need_u else []) + [None] * (3 - (ctx.nc if need_u else 0))
         return (gu[0], gu[1], gu[2], g_X.to(X.dtype) if need_X else None,
                 None, None, None, None, None, None, None, None, None)
 
 
 class TransferForce(torch.autograd.Function):
     """f_f = TransferForce.apply(f_s, X, faces, tets, precision, alpha,
-    coupling, recompute_B, dual) -> tuple of 3 fluid arrays."""
+    coupling, recompute_B, dual) -> tuple of nc fluid arrays."""
 
     @staticmethod
     def forward(ctx, f_s, X, faces, tets, precision="fp64", alpha=1.0, coupling=None,
@@ -93,15 +97,15 @@ class TransferForce(torch.autograd.Function):
         return tuple(out)
 
     @staticmethod
-    def backward(ctx, g0, g1, g2):
+    def backward(ctx, *grads):
         f_s, X = ctx.saved_tensors
         c = ctx.coupling if ctx.coupling is not None else _coupling(ctx.meta, X, None)
         g_ff = []
-        for g, s in zip((g0, g1, g2), c.lattice_shapes):
+        for g, s in zip(grads, c.lattice_shapes):
             g_ff.append(torch.zeros(tuple(reversed(s)), dtype=c.dtype, device=X.device)
                         if g is None else g.contiguous().to(c.dtype))
         g_fs = torch.zeros_like(f_s) if ctx.needs_input_grad[0] else None
-        g_X = (torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device)
+        g_X = (torch.zeros((X.shape[0], X.shape[1]), dtype=torch.float64, device=X.device)
                if ctx.needs_input_grad[1] else None)
         c.force_vjp(g_ff, f_s=f_s.contiguous(), alpha=ctx.alpha, g_fs=g_fs, g_X=g_X)
         if ctx.coupling is None:
@@ -112,7 +116,8 @@ class TransferForce(torch.autograd.Function):
 
 def transfer_velocity(u_f, X, faces, tets, precision="fp64", mass="lumped", rtol=1e-12,
                       maxit=500, coupling=None, recompute_B=False, dual=False):
-    return TransferVelocity.apply(u_f[0], u_f[1], u_f[2], X, faces, tets, precision, mass, rtol,
+    u2 = u_f[2] if len(u_f) > 2 else None
+    return TransferVelocity.apply(u_f[0], u_f[1], u2, X, faces, tets, precision, mass, rtol,
                                   maxit, coupling, recompute_B, dual)
 
 

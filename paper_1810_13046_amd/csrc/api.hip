@@ -180,6 +180,95 @@ int setup_lattices(ibvt_coupling* c, const ibvt_grid* g, hipStream_t s) {
 
 bool bad_ptr(const void* p) { return p == nullptr; }
 
+// Planar grids: the same checks and lattices over two axes.  The lattice
+// table keeps the 3 x 3 layout (entries of axis or component 2 stay empty).
+int validate_grid2d(const ibvt_grid2d* g) {
+  if (!g) return set_error(IBVT_E_INVALID, "grid is NULL");
+  for (int e = 0; e < 2; ++e) {
+    if (g->n_cells[e] < 2)
+      return set_error(IBVT_E_INVALID, "each axis needs at least 2 cells (cell-centre lattices)");
+    if (!g->faces[e]) return set_error(IBVT_E_INVALID, "grid faces pointer is NULL");
+    for (int k = 0; k <= g->n_cells[e]; ++k)
+      if (!std::isfinite(g->faces[e][k]))
+        return set_error(IBVT_E_INVALID, "non-finite face coordinate");
+    for (int k = 0; k < g->n_cells[e]; ++k)
+      if (!(g->faces[e][k + 1] > g->faces[e][k]))
+        return set_error(IBVT_E_INVALID, "face coordinates must be strictly increasing");
+  }
+  if ((int64_t(g->n_cells[0]) + 1) * (int64_t(g->n_cells[1]) + 1) >= (int64_t(1) << 31))
+    return set_error(IBVT_E_CAPACITY, "lattice has 2^31 nodes or more (int32 column indices)");
+  return IBVT_OK;
+}
+
+std::vector<double> lattice_axis2d(const ibvt_grid2d* g, int d, int e) {
+  ibvt_grid g3{};
+  for (int k = 0; k < 2; ++k) {
+    g3.n_cells[k] = g->n_cells[k];
+    g3.faces[k] = g->faces[k];
+  }
+  return lattice_axis(&g3, d, e);
+}
+
+int setup_lattices2d(ibvt_coupling* c, const ibvt_grid2d* g, hipStream_t s) {
+  int32_t off = 0;
+  for (int k = 0; k < 9; ++k) {
+    c->lat_host[k].clear();
+    c->ld.off[k] = 0;
+    c->ld.n[k] = 0;
+  }
+  for (int d = 0; d < 2; ++d) {
+    int64_t nf = 1;
+    for (int e = 0; e < 2; ++e) {
+      c->lat_host[3 * d + e] = lattice_axis2d(g, d, e);
+      c->ld.off[3 * d + e] = off;
+      c->ld.n[3 * d + e] = int32_t(c->lat_host[3 * d + e].size());
+      off += c->ld.n[3 * d + e];
+      nf *= c->ld.n[3 * d + e];
+    }
+    c->n_fluid[d] = nf;
+  }
+  c->n_fluid[2] = 0;
+  int st = ensure(c, c->lat, size_t(off) * sizeof(double));
+  if (st) return st;
+  std::vector<double> flat;
+  flat.reserve(off);
+  for (int k = 0; k < 9; ++k) flat.insert(flat.end(), c->lat_host[k].begin(), c->lat_host[k].end());
+  st = hip_check(hipMemcpyAsync(c->lat.p, flat.data(), flat.size() * sizeof(double),
+                                hipMemcpyHostToDevice, s),
+                 "lattice copy");
+  if (st) return st;
+  return hip_check(hipStreamSynchronize(s), "lattice sync");
+}
+
+// Copies the mesh, builds the topology and assembles; frees the handle on
+// failure.
+int finish_assembly(ibvt_coupling* c, const double* X, const int32_t* elems, hipStream_t stream,
+                    ibvt_coupling** out) {
+  const int K = c->dim + 1;
+  int st = ensure(c, c->X, size_t(c->dim * c->n_vert) * sizeof(double));
+  if (!st) st = ensure(c, c->tets, size_t(K * c->n_tet + 4) * sizeof(int32_t));
+  if (!st)
+    st = hip_check(hipMemcpyAsync(c->X.p, X, size_t(c->dim * c->n_vert) * sizeof(double),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "copy X");
+  if (!st && c->n_tet > 0)
+    st = hip_check(hipMemcpyAsync(c->tets.p, elems, size_t(K * c->n_tet) * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "copy elements");
+  if (!st) st = build_topology(c, stream);
+  if (!st) st = assemble_all(c, stream);
+  if (st) {
+    std::string keep_msg = g_last_error;
+    (void)hipStreamSynchronize(stream);
+    release_all(c);
+    delete c;
+    g_last_error = keep_msg;
+    return st;
+  }
+  *out = c;
+  return IBVT_OK;
+}
+
 }  // namespace
 }  // namespace ibvt
 
@@ -214,6 +303,17 @@ int ibvt_lattice_coords(const ibvt_grid* grid, int comp, int axis, double* out, 
   return IBVT_OK;
 }
 
+int ibvt_lattice_coords_2d(const ibvt_grid2d* grid, int comp, int axis, double* out, int64_t* n) {
+  int st = validate_grid2d(grid);
+  if (st) return st;
+  if (comp < 0 || comp > 1 || axis < 0 || axis > 1 || !n)
+    return set_error(IBVT_E_INVALID, "bad comp/axis or NULL n");
+  std::vector<double> v = lattice_axis2d(grid, comp, axis);
+  *n = int64_t(v.size());
+  if (out) std::memcpy(out, v.data(), v.size() * sizeof(double));
+  return IBVT_OK;
+}
+
 int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precision,
                       uint32_t flags, hipStream_t stream, ibvt_coupling** out) {
   if (!out) return set_error(IBVT_E_INVALID, "out is NULL");
@@ -242,33 +342,56 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
   c->dual = (flags & IBVT_DUAL_BASIS) != 0;
   for (int e = 0; e < 3; ++e) c->n_cells[e] = grid->n_cells[e];
   st = setup_lattices(c, grid, stream);
-  if (!st) st = ensure(c, c->X, size_t(3 * c->n_vert) * sizeof(double));
-  if (!st) st = ensure(c, c->tets, size_t(4 * c->n_tet + 4) * sizeof(int32_t));
-  if (!st)
-    st = hip_check(hipMemcpyAsync(c->X.p, mesh->X, size_t(3 * c->n_vert) * sizeof(double),
-                                  hipMemcpyDeviceToDevice, stream),
-                   "copy X");
-  if (!st && c->n_tet > 0)
-    st = hip_check(hipMemcpyAsync(c->tets.p, mesh->tets, size_t(4 * c->n_tet) * sizeof(int32_t),
-                                  hipMemcpyDeviceToDevice, stream),
-                   "copy tets");
-  if (!st) st = build_topology(c, stream);
-  if (!st) st = assemble_all(c, stream);
   if (st) {
-    std::string keep_msg = g_last_error;
-    (void)hipStreamSynchronize(stream);
     release_all(c);
     delete c;
-    g_last_error = keep_msg;
     return st;
   }
-  *out = c;
-  return IBVT_OK;
+  return finish_assembly(c, mesh->X, mesh->tets, stream, out);
+}
+
+int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int precision,
+                         uint32_t flags, hipStream_t stream, ibvt_coupling** out) {
+  if (!out) return set_error(IBVT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int st = validate_grid2d(grid);
+  if (st) return st;
+  if (!mesh) return set_error(IBVT_E_INVALID, "mesh is NULL");
+  if (mesh->n_vert < 1 || mesh->n_tri < 0)
+    return set_error(IBVT_E_INVALID, "mesh needs n_vert >= 1 and n_tri >= 0");
+  if (mesh->n_vert >= (int64_t(1) << 31) || mesh->n_tri >= (int64_t(1) << 31) / 3)
+    return set_error(IBVT_E_CAPACITY, "mesh too large for int32 indices");
+  if (bad_ptr(mesh->X) || (mesh->n_tri > 0 && bad_ptr(mesh->tris)))
+    return set_error(IBVT_E_INVALID, "mesh X or tris is NULL");
+  if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
+    return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
+  if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE | IBVT_DUAL_BASIS))
+    return set_error(IBVT_E_INVALID, "unknown flags");
+  ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
+  if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
+  c->dim = 2;
+  c->ncomp = 2;
+  c->precision = precision;
+  c->flags = flags;
+  c->n_vert = mesh->n_vert;
+  c->n_tet = mesh->n_tri;
+  c->has_M = (flags & IBVT_BUILD_CONSISTENT_M) != 0;
+  c->store_pieces = true;
+  c->dual = (flags & IBVT_DUAL_BASIS) != 0;
+  for (int e = 0; e < 2; ++e) c->n_cells[e] = grid->n_cells[e];
+  c->n_cells[2] = 0;
+  st = setup_lattices2d(c, grid, stream);
+  if (st) {
+    release_all(c);
+    delete c;
+    return st;
+  }
+  return finish_assembly(c, mesh->X, mesh->tris, stream, out);
 }
 
 int reassemble_coupling(ibvt_coupling* c, const double* X, hipStream_t stream) {
   if (!c || !X) return set_error(IBVT_E_INVALID, "NULL coupling or X");
-  int st = hip_check(hipMemcpyAsync(c->X.p, X, size_t(3 * c->n_vert) * sizeof(double),
+  int st = hip_check(hipMemcpyAsync(c->X.p, X, size_t(c->dim * c->n_vert) * sizeof(double),
                                     hipMemcpyDeviceToDevice, stream),
                      "copy X");
   if (st) return st;
@@ -278,7 +401,7 @@ int reassemble_coupling(ibvt_coupling* c, const double* X, hipStream_t stream) {
 int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int mass,
                       double cg_rtol, int cg_maxit, hipStream_t stream, ibvt_solve_info* info) {
   if (!c || !u_f || !u_s) return set_error(IBVT_E_INVALID, "NULL argument");
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < c->ncomp; ++d)
     if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
     return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
@@ -300,7 +423,7 @@ int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int
 int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double alpha,
                    uint32_t flags, hipStream_t stream) {
   if (!c || !f_s || !f_f) return set_error(IBVT_E_INVALID, "NULL argument");
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < c->ncomp; ++d)
     if (!f_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (flags & ~IBVT_FORCE_IS_LOAD) return set_error(IBVT_E_INVALID, "unknown flags");
   if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
@@ -330,10 +453,10 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
     return set_error(IBVT_E_INVALID, "the dual basis has a diagonal S: use IBVT_LUMPED");
   if (g_X && (!u_f || !u_s)) return set_error(IBVT_E_INVALID, "g_X needs u_f and u_s");
   if (g_X)
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < c->ncomp; ++d)
       if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (g_uf)
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < c->ncomp; ++d)
       if (!g_uf[d]) return set_error(IBVT_E_INVALID, "NULL g_uf component");
   const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
   // z = S^{-1} g_us lives in its own buffer (the shape kernel reuses work2)
@@ -348,15 +471,19 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
     if ((st = mass_solve(c, g_us, z, cg_rtol, cg_maxit, stream, nullptr, false))) return st;
   }
   if (g_uf && (st = apply_Bt(c, z, g_uf, 1.0, stream))) return st;
-  if (g_X && (st = shape_gradient(c, z, u_f, u_s, mass == IBVT_CONSISTENT ? 1 : 0, 1.0, g_X, stream)))
-    return st;
+  if (g_X) {
+    const int m = mass == IBVT_CONSISTENT ? 1 : 0;
+    st = c->dim == 2 ? shape_gradient_2d(c, z, u_f, u_s, m, 1.0, g_X, stream)
+                     : shape_gradient(c, z, u_f, u_s, m, 1.0, g_X, stream);
+    if (st) return st;
+  }
   return IBVT_OK;
 }
 
 int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s,
                        double alpha, void* g_fs, double* g_X, hipStream_t stream) {
   if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < c->ncomp; ++d)
     if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
   if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
   if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
@@ -368,7 +495,11 @@ int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* 
     if ((st = apply_B(c, g_ff, c->zbuf.p, false, stream))) return st;
     if ((st = axpy_solid(c, alpha, c->zbuf.p, g_fs, stream))) return st;
   }
-  if (g_X && (st = shape_gradient(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream))) return st;
+  if (g_X) {
+    st = c->dim == 2 ? shape_gradient_2d(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream)
+                     : shape_gradient(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream);
+    if (st) return st;
+  }
   return IBVT_OK;
 }
 
@@ -397,13 +528,14 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->dist_evals = c->stats.dist_evals;
   info->cut_points = c->stats.cut_points;
   info->dual = c->dual ? 1 : 0;
+  info->dim = c->dim;
   return IBVT_OK;
 }
 
 int coupling_export_csr(const ibvt_coupling* c, int comp, int transposed, int64_t* n_rows,
                         int64_t* nnz, int32_t* row_ptr, int32_t* col, double* val,
                         int32_t* row_map) {
-  if (!c || comp < 0 || comp > 2 || !n_rows || !nnz)
+  if (!c || comp < 0 || comp >= c->ncomp || !n_rows || !nnz)
     return set_error(IBVT_E_INVALID, "bad argument");
   const Csr& m = transposed ? c->Bt[comp] : c->B[comp];
   *n_rows = m.nrows;

@@ -9,13 +9,16 @@
 // scattered to the caller's full fluid arrays through the row map (each
 // fluid node appears once, so no atomics).
 //
-// Consistent mass: Jacobi-preconditioned CG on M for the three components
-// at once (one pass over M serves all three right-hand sides), with
+// Consistent mass: Jacobi-preconditioned CG on M for all components at
+// once (one pass over M serves every right-hand side), with
 // per-component scalars and stopping tests.  Reductions are two-stage
 // (per-block partials, then one block in fixed order), so results do not
 // depend on timing.  In the mixed-precision path an outer loop recomputes
 // the residual b - M x in double with double M values and solves the
 // correction with a float CG (iterative refinement).
+//
+// Solid vectors are component-major (ncomp, n_vert): three components in
+// three dimensions, two in the plane.
 #include "internal.hpp"
 
 #include <cmath>
@@ -66,10 +69,11 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs<T> a) {
 }
 
 template <typename T, int G>
-int launch_spmv(const SpmvArgs<T>& a, hipStream_t s, const char* name) {
-  int64_t mx = std::max(a.nrows[0], std::max(a.nrows[1], a.nrows[2]));
+int launch_spmv(const SpmvArgs<T>& a, int nc, hipStream_t s, const char* name) {
+  int64_t mx = 0;
+  for (int d = 0; d < nc; ++d) mx = std::max(mx, a.nrows[d]);
   if (mx <= 0) return IBVT_OK;
-  dim3 grid(unsigned(ceil_div(mx, kThreads / G)), 3);
+  dim3 grid(unsigned(ceil_div(mx, kThreads / G)), unsigned(nc));
   ProfScope ps(name, s);
   k_spmv<T, G><<<grid, kThreads, 0, s>>>(a);
   return hip_check(hipGetLastError(), "spmv launch");
@@ -87,13 +91,13 @@ struct CgScalars {
   int all;
 };
 
-// q = M p for the three components (values V, vectors T), plus per-block
+// q = M p for the NC components (values V, vectors T), plus per-block
 // partials of p·q.  kMG lanes per row stride through it (coalesced reads of
 // the row's columns and values) and reduce with lane shuffles in a fixed
 // order.
 constexpr int kMG = 8;
 
-template <typename T, typename V>
+template <typename T, typename V, int NC>
 __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t* __restrict__ rp,
                                                        const int32_t* __restrict__ col,
                                                        const V* __restrict__ val,
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t
           const T m = T(val[k]);
           s0 += m * p[j];
           s1 += m * p[n + j];
-          s2 += m * p[2 * n + j];
+          if (NC > 2) s2 += m * p[2 * n + j];
         }
       }
 #pragma unroll
@@ -126,10 +130,12 @@ __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t
       if (i < n && g == 0) {
         q[i] = s0;
         q[n + i] = s1;
-        q[2 * n + i] = s2;
         loc[0] += double(p[i]) * double(s0);
         loc[1] += double(p[n + i]) * double(s1);
-        loc[2] += double(p[2 * n + i]) * double(s2);
+        if (NC > 2) {
+          q[2 * n + i] = s2;
+          loc[2] += double(p[2 * n + i]) * double(s2);
+        }
       }
     }
   }
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce3(const double* __restrict__
 //  mode 0 (init):  r = b - q; z = Dinv r; p = z;  partials (r·z, b·b)
 //  mode 1 (update): x += α p; r -= α q; z = Dinv r; partials (r·z, r·r)
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_vec(int mode, int64_t n, const T* __restrict__ b,
+__global__ __launch_bounds__(kThreads) void k_cg_vec(int mode, int nc, int64_t n, const T* __restrict__ b,
                                                     const T* __restrict__ q, T* __restrict__ x,
                                                     T* __restrict__ r, T* __restrict__ z,
                                                     T* __restrict__ p, const double* __restrict__ dinv,
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_vec(int mode, int64_t n, const 
   double loc[6] = {0, 0, 0, 0, 0, 0};
   if (i < n && !(mode == 1 && sc->all)) {
     const double di = dinv[i];
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < nc; ++d) {
       const int64_t k = int64_t(d) * n + i;
       if (mode == 0) {
         const T rv = b[k] - q[k];
@@ -271,11 +277,11 @@ __global__ void k_cg_scalar(int step, CgScalars* sc, const double* __restrict__ 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_p(int64_t n, const T* __restrict__ z,
+__global__ __launch_bounds__(kThreads) void k_cg_p(int nc, int64_t n, const T* __restrict__ z,
                                                   T* __restrict__ p, const CgScalars* sc) {
   const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
   if (i >= n || sc->all) return;
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 0; d < nc; ++d) {
     if (sc->conv[d]) continue;
     const int64_t k = int64_t(d) * n + i;
     p[k] = z[k] + T(sc->beta[d]) * p[k];
@@ -285,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_p(int64_t n, const T* __restric
 // residual in double: res = b - M x  (b, x of type T; M double), kMG
 // lanes per row as in k_mass_spmv.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_residual64(int64_t n, const int64_t* __restrict__ rp,
+__global__ __launch_bounds__(kThreads) void k_residual64(int nc, int64_t n, const int64_t* __restrict__ rp,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val,
                                                         const T* __restrict__ b,
@@ -301,14 +307,14 @@ __global__ __launch_bounds__(kThreads) void k_residual64(int64_t n, const int64_
     if (i < n) {
       for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
         const int64_t j = col[k];
-        for (int d = 0; d < 3; ++d) s[d] += val[k] * x[int64_t(d) * n + j];
+        for (int d = 0; d < nc; ++d) s[d] += val[k] * x[int64_t(d) * n + j];
       }
     }
 #pragma unroll
     for (int o = kMG / 2; o > 0; o >>= 1)
       for (int d = 0; d < 3; ++d) s[d] += __shfl_xor(s[d], o, kWave);
     if (i < n && g == 0) {
-      for (int d = 0; d < 3; ++d) {
+      for (int d = 0; d < nc; ++d) {
         const double bv = double(b[int64_t(d) * n + i]);
         const double rv = bv - s[d];
         res[int64_t(d) * n + i] = rv;
@@ -336,11 +342,11 @@ __global__ void k_convert(int64_t n, const Tin* __restrict__ a, Tout* __restrict
 }
 
 template <typename T>
-__global__ void k_lumped_apply(int64_t n, const T* __restrict__ rhs, const T* __restrict__ minv,
-                               T* __restrict__ x) {
+__global__ void k_lumped_apply(int nc, int64_t n, const T* __restrict__ rhs,
+                               const T* __restrict__ minv, T* __restrict__ x) {
   const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
   if (i < n)
-    for (int d = 0; d < 3; ++d) x[int64_t(d) * n + i] = rhs[int64_t(d) * n + i] * minv[i];
+    for (int d = 0; d < nc; ++d) x[int64_t(d) * n + i] = rhs[int64_t(d) * n + i] * minv[i];
 }
 
 template <typename T>
@@ -394,13 +400,14 @@ int cg_workspace(ibvt_coupling* c, size_t tsize, CgWork& w) {
   return IBVT_OK;
 }
 
-// Plain CG on M (values V) for three right-hand sides b (type T), x in/out.
+// Plain CG on M (values V) for the right-hand sides b (type T), x in/out.
 // Returns iterations in info-like arrays through the scalars; checks
 // convergence on the host every `check` iterations.
 template <typename T, typename V>
 int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int maxit,
             const CgWork& w, hipStream_t s, int* iters_out, bool* converged) {
   const int64_t n = c->n_vert;
+  const int nc = c->ncomp;
   const unsigned nb = nblk(n);
   const unsigned nbm = nblk_rows(n);
   T* q = static_cast<T*>(w.vec);
@@ -411,9 +418,15 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
   const int32_t* col = c->M.col.as<int32_t>();
   const double* dinv = c->Mdiag_inv.as<double>();
   const double rtol2 = rtol * rtol;
+  auto mass_spmv = [&](const T* src, T* dst, double* part, const CgScalars* sc) {
+    if (nc == 3)
+      k_mass_spmv<T, V, 3><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, src, dst, part, sc);
+    else
+      k_mass_spmv<T, V, 2><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, src, dst, part, sc);
+  };
   // q = M x ; r = b - q ; z = D^-1 r ; p = z
-  k_mass_spmv<T, V><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, x, q, nullptr, nullptr);
-  k_cg_vec<T><<<nb, kThreads, 0, s>>>(0, n, b, q, x, r, z, p, dinv, w.part, w.sc);
+  mass_spmv(x, q, nullptr, nullptr);
+  k_cg_vec<T><<<nb, kThreads, 0, s>>>(0, nc, n, b, q, x, r, z, p, dinv, w.part, w.sc);
   k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
   k_cg_scalar<<<1, 64, 0, s>>>(0, w.sc, w.tmp, rtol2);
   int st = hip_check(hipGetLastError(), "cg init launch");
@@ -426,13 +439,13 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
     const int chunk = std::min(check, maxit - it);
     for (int k = 0; k < chunk; ++k) {
       ProfScope ps("cg_iteration", s);
-      k_mass_spmv<T, V><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, p, q, w.part, w.sc);
+      mass_spmv(p, q, w.part, w.sc);
       k_reduce3<<<1, kThreads, 0, s>>>(w.part, nbm, w.tmp);
       k_cg_scalar<<<1, 64, 0, s>>>(1, w.sc, w.tmp, rtol2);
-      k_cg_vec<T><<<nb, kThreads, 0, s>>>(1, n, b, q, x, r, z, p, dinv, w.part, w.sc);
+      k_cg_vec<T><<<nb, kThreads, 0, s>>>(1, nc, n, b, q, x, r, z, p, dinv, w.part, w.sc);
       k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
       k_cg_scalar<<<1, 64, 0, s>>>(2, w.sc, w.tmp, rtol2);
-      k_cg_p<T><<<nb, kThreads, 0, s>>>(n, z, p, w.sc);
+      k_cg_p<T><<<nb, kThreads, 0, s>>>(nc, n, z, p, w.sc);
     }
     it += chunk;
     if ((st = hip_check(hipGetLastError(), "cg launch"))) return st;
@@ -462,7 +475,8 @@ int true_residual(ibvt_coupling* c, const T* b, const double* x, const CgWork& w
                   double rel[3]) {
   const int64_t n = c->n_vert;
   const unsigned nb = nblk_rows(n);
-  k_residual64<T><<<nb, kThreads, 0, s>>>(n, c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>(),
+  k_residual64<T><<<nb, kThreads, 0, s>>>(c->ncomp, n, c->M.rowptr.as<int64_t>(),
+                                          c->M.col.as<int32_t>(),
                                           c->M.val.as<double>(), b, x, w.res64, w.part);
   k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
   double h[6];
@@ -489,7 +503,7 @@ int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale
     }
     a.scale = lumped_scale ? c->minv.as<float>() : nullptr;
     a.alpha = 1.0f;
-    return launch_spmv<float, 16>(a, s, "spmv_B");
+    return launch_spmv<float, 16>(a, c->ncomp, s, "spmv_B");
   }
   SpmvArgs<double> a{};
   for (int d = 0; d < 3; ++d) {
@@ -502,7 +516,7 @@ int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale
   }
   a.scale = lumped_scale ? c->minv.as<double>() : nullptr;
   a.alpha = 1.0;
-  return launch_spmv<double, 16>(a, s, "spmv_B");
+  return launch_spmv<double, 16>(a, c->ncomp, s, "spmv_B");
 }
 
 // out[d][rowmap[r]] += alpha * (B^dT ys_d)[r]
@@ -521,7 +535,7 @@ int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,
     }
     a.alpha = float(alpha);
     a.accumulate = 1;
-    return launch_spmv<float, 16>(a, s, "spmv_Bt");
+    return launch_spmv<float, 16>(a, c->ncomp, s, "spmv_Bt");
   }
   SpmvArgs<double> a{};
   for (int d = 0; d < 3; ++d) {
@@ -535,23 +549,23 @@ int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,
   }
   a.alpha = alpha;
   a.accumulate = 1;
-  return launch_spmv<double, 16>(a, s, "spmv_Bt");
+  return launch_spmv<double, 16>(a, c->ncomp, s, "spmv_Bt");
 }
 
 int lumped_solve(ibvt_coupling* c, const void* rhs, void* x, hipStream_t s) {
   const int64_t n = c->n_vert;
   if (c->precision == IBVT_FP32_MIXED)
-    k_lumped_apply<float><<<nblk(n), kThreads, 0, s>>>(n, static_cast<const float*>(rhs),
+    k_lumped_apply<float><<<nblk(n), kThreads, 0, s>>>(c->ncomp, n, static_cast<const float*>(rhs),
                                                        c->minv.as<float>(), static_cast<float*>(x));
   else
-    k_lumped_apply<double><<<nblk(n), kThreads, 0, s>>>(n, static_cast<const double*>(rhs),
+    k_lumped_apply<double><<<nblk(n), kThreads, 0, s>>>(c->ncomp, n, static_cast<const double*>(rhs),
                                                         c->minv.as<double>(),
                                                         static_cast<double*>(x));
   return hip_check(hipGetLastError(), "lumped launch");
 }
 
 int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream_t s) {
-  const int64_t n3 = 3 * c->n_vert;
+  const int64_t n3 = int64_t(c->ncomp) * c->n_vert;
   if (c->precision == IBVT_FP32_MIXED)
     k_axpy<float><<<nblk(n3), kThreads, 0, s>>>(n3, float(alpha), static_cast<const float*>(x),
                                                 static_cast<float*>(y));
@@ -561,12 +575,13 @@ int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream
   return hip_check(hipGetLastError(), "axpy launch");
 }
 
-// x = M^{-1} rhs (three components).  x holds the start (lumped solution)
+// x = M^{-1} rhs (every component).  x holds the start (lumped solution)
 // when x_has_guess.
 int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxit, hipStream_t s,
                ibvt_solve_info* info, bool x_has_guess) {
   if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built (flags)");
   const int64_t n = c->n_vert;
+  const int64_t nn = int64_t(c->ncomp) * n;
   int st;
   if (!x_has_guess && (st = lumped_solve(c, rhs, x, s))) return st;
   int iters[3] = {0, 0, 0};
@@ -589,7 +604,7 @@ int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxi
     if ((st = cg_workspace(c, sizeof(float), w))) return st;
     const float* b = static_cast<const float*>(rhs);
     float* xf = static_cast<float*>(x);
-    k_convert<float, double><<<nblk(3 * n), kThreads, 0, s>>>(3 * n, xf, w.x64);
+    k_convert<float, double><<<nblk(nn), kThreads, 0, s>>>(nn, xf, w.x64);
     float* e = static_cast<float*>(w.vec) + 4 * 3 * n;   // vectors 4 and 5 of the workspace
     float* rf = e + 3 * n;
     const double inner = std::max(1e-5, rtol);
@@ -600,17 +615,17 @@ int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxi
         conv = true;
         break;
       }
-      k_convert<double, float><<<nblk(3 * n), kThreads, 0, s>>>(3 * n, w.res64, rf);
-      if ((st = hip_check(hipMemsetAsync(e, 0, size_t(3 * n) * sizeof(float), s), "memset")))
+      k_convert<double, float><<<nblk(nn), kThreads, 0, s>>>(nn, w.res64, rf);
+      if ((st = hip_check(hipMemsetAsync(e, 0, size_t(nn) * sizeof(float), s), "memset")))
         return st;
       bool c2 = false;
       if ((st = cg_core<float, float>(c, c->Mval32.as<float>(), rf, e, inner, maxit, w, s, iters,
                                       &c2)))
         return st;
-      k_add_correction<<<nblk(3 * n), kThreads, 0, s>>>(3 * n, e, w.x64);
-      if (iters[0] + iters[1] + iters[2] >= 3 * maxit) break;
+      k_add_correction<<<nblk(nn), kThreads, 0, s>>>(nn, e, w.x64);
+      if (iters[0] + iters[1] + iters[2] >= c->ncomp * maxit) break;
     }
-    k_convert<double, float><<<nblk(3 * n), kThreads, 0, s>>>(3 * n, w.x64, xf);
+    k_convert<double, float><<<nblk(nn), kThreads, 0, s>>>(nn, w.x64, xf);
     if ((st = hip_check(hipGetLastError(), "refinement launch"))) return st;
   }
   if (info) {

@@ -54,32 +54,35 @@ __device__ __forceinline__ int lower_bound_d(const double* L, int n, double x) {
 // topology: vertex -> incident tets
 // ---------------------------------------------------------------------------
 
+// K vertices per element: 4 (tetrahedra) or 3 (triangles, the planar case).
+template <int K>
 __global__ void k_vt_count(int64_t n_t, int64_t n_v, const int32_t* __restrict__ tets,
                            unsigned long long* __restrict__ deg, unsigned* flags) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_t) return;
-  int v[4];
+  int v[K];
   bool bad = false;
-  for (int k = 0; k < 4; ++k) {
-    v[k] = tets[4 * t + k];
+  for (int k = 0; k < K; ++k) {
+    v[k] = tets[K * t + k];
     bad |= (v[k] < 0) || (int64_t(v[k]) >= n_v);
   }
-  for (int a = 0; a < 4; ++a)
-    for (int b = a + 1; b < 4; ++b) bad |= (v[a] == v[b]);
+  for (int a = 0; a < K; ++a)
+    for (int b = a + 1; b < K; ++b) bad |= (v[a] == v[b]);
   if (bad) {
     atomicOr(flags, kFlagValence);
     return;
   }
-  for (int k = 0; k < 4; ++k) atomicAdd(&deg[v[k]], 1ull);
+  for (int k = 0; k < K; ++k) atomicAdd(&deg[v[k]], 1ull);
 }
 
+template <int K>
 __global__ void k_vt_fill(int64_t n_t, const int32_t* __restrict__ tets,
                           const int64_t* __restrict__ vt_ptr, unsigned long long* __restrict__ cur,
                           int32_t* __restrict__ vt_tet) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_t) return;
-  for (int k = 0; k < 4; ++k) {
-    const int v = tets[4 * t + k];
+  for (int k = 0; k < K; ++k) {
+    const int v = tets[K * t + k];
     const int64_t pos = vt_ptr[v] + int64_t(atomicAdd(&cur[v], 1ull));
     vt_tet[pos] = int32_t(t);
   }
@@ -101,8 +104,8 @@ __global__ void k_sort_segments_i32(int64_t n, const int64_t* __restrict__ ptr,
   }
 }
 
-// Consistent-mass pattern: distinct vertices of the incident tets.
-template <bool FILL>
+// Consistent-mass pattern: distinct vertices of the incident elements.
+template <int K, bool FILL>
 __global__ void k_mass_pattern(int64_t n_v, const int64_t* __restrict__ vt_ptr,
                                const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
                                int64_t* __restrict__ rowcnt, const int64_t* __restrict__ rowptr,
@@ -117,8 +120,8 @@ __global__ void k_mass_pattern(int64_t n_v, const int64_t* __restrict__ vt_ptr,
     int nxt = INT_MAX;
     for (int64_t k = b; k < e; ++k) {
       const int64_t t = vt_tet[k];
-      for (int q = 0; q < 4; ++q) {
-        const int v = tets[4 * t + q];
+      for (int q = 0; q < K; ++q) {
+        const int v = tets[K * t + q];
         if (v > cur && v < nxt) nxt = v;
       }
     }
@@ -827,7 +830,10 @@ int resident_blocks(F f) {
   return cus * per_cu;
 }
 
+}  // namespace
+
 int read_back(ibvt_coupling* c, void* host, const void* dev, size_t bytes, hipStream_t s) {
+  (void)c;
   int st = hip_check(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s), "read back");
   if (st) return st;
   return hip_check(hipStreamSynchronize(s), "stream sync");
@@ -844,9 +850,11 @@ int check_flags(ibvt_coupling* c, hipStream_t s) {
   if (f & kFlagCapacity)
     return set_error(IBVT_E_CAPACITY, "clipped piece exceeded the 16-vertex capacity");
   if (f & kFlagTetSpan)
-    return set_error(IBVT_E_CAPACITY, "a tet spans more than 65535 cells of one lattice");
+    return set_error(IBVT_E_CAPACITY, "an element spans more than 65535 cells of one lattice");
   return IBVT_OK;
 }
+
+namespace {
 
 template <typename T>
 int assemble_typed(ibvt_coupling* c, hipStream_t s) {
@@ -1079,27 +1087,46 @@ int build_topology(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->flags_dev, 64))) return st;
   if ((st = ensure(c, c->counters, kCntSlots * sizeof(unsigned long long)))) return st;
   if ((st = ensure(c, c->vt_ptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, c->vt_tet, size_t(4 * n_t + 1) * sizeof(int32_t)))) return st;
+  const int K = c->dim + 1;  // vertices per element
+  if ((st = ensure(c, c->vt_tet, size_t(K * n_t + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->rownnz, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
   unsigned* flags = c->flags_dev.as<unsigned>();
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
   auto* deg = c->rownnz.as<unsigned long long>();  // scratch: degrees, then cursors
   if ((st = hip_check(hipMemsetAsync(deg, 0, size_t(n_v + 1) * sizeof(int64_t), s), "memset")))
     return st;
-  k_vt_count<<<blocks_for(n_t, 256), 256, 0, s>>>(n_t, n_v, c->tets.as<int32_t>(), deg, flags);
+  if (K == 4) k_vt_count<4><<<blocks_for(n_t, 256), 256, 0, s>>>(n_t, n_v, c->tets.as<int32_t>(), deg, flags);
+  else k_vt_count<3><<<blocks_for(n_t, 256), 256, 0, s>>>(n_t, n_v, c->tets.as<int32_t>(), deg, flags);
   if ((st = check_flags(c, s))) return st;
   if ((st = scan_i64(c, c->rownnz.as<int64_t>(), c->vt_ptr.as<int64_t>(), n_v, s))) return st;
   if ((st = hip_check(hipMemsetAsync(deg, 0, size_t(n_v + 1) * sizeof(int64_t), s), "memset")))
     return st;
-  k_vt_fill<<<blocks_for(n_t, 256), 256, 0, s>>>(n_t, c->tets.as<int32_t>(), c->vt_ptr.as<int64_t>(),
-                                                 deg, c->vt_tet.as<int32_t>());
+  if (K == 4)
+    k_vt_fill<4><<<blocks_for(n_t, 256), 256, 0, s>>>(n_t, c->tets.as<int32_t>(),
+                                                      c->vt_ptr.as<int64_t>(), deg,
+                                                      c->vt_tet.as<int32_t>());
+  else
+    k_vt_fill<3><<<blocks_for(n_t, 256), 256, 0, s>>>(n_t, c->tets.as<int32_t>(),
+                                                      c->vt_ptr.as<int64_t>(), deg,
+                                                      c->vt_tet.as<int32_t>());
   k_sort_segments_i32<<<blocks_for(n_v, 256), 256, 0, s>>>(n_v, c->vt_ptr.as<int64_t>(),
                                                            c->vt_tet.as<int32_t>());
   if ((st = hip_check(hipGetLastError(), "topology launch"))) return st;
   if (c->has_M) {
-    k_mass_pattern<false><<<blocks_for(n_v, 256), 256, 0, s>>>(
-        n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-        c->rownnz.as<int64_t>(), nullptr, nullptr);
+    auto pattern = [&](bool fill) {
+      const int64_t* vp = c->vt_ptr.as<int64_t>();
+      const int32_t* vt = c->vt_tet.as<int32_t>();
+      const int32_t* el = c->tets.as<int32_t>();
+      int64_t* cnt = fill ? nullptr : c->rownnz.as<int64_t>();
+      const int64_t* rp = fill ? c->M.rowptr.as<int64_t>() : nullptr;
+      int32_t* col = fill ? c->M.col.as<int32_t>() : nullptr;
+      const unsigned nb = blocks_for(n_v, 256);
+      if (K == 4 && !fill) k_mass_pattern<4, false><<<nb, 256, 0, s>>>(n_v, vp, vt, el, cnt, rp, col);
+      if (K == 4 && fill) k_mass_pattern<4, true><<<nb, 256, 0, s>>>(n_v, vp, vt, el, cnt, rp, col);
+      if (K == 3 && !fill) k_mass_pattern<3, false><<<nb, 256, 0, s>>>(n_v, vp, vt, el, cnt, rp, col);
+      if (K == 3 && fill) k_mass_pattern<3, true><<<nb, 256, 0, s>>>(n_v, vp, vt, el, cnt, rp, col);
+    };
+    pattern(false);
     if ((st = ensure(c, c->M.rowptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;
     if ((st = scan_i64(c, c->rownnz.as<int64_t>(), c->M.rowptr.as<int64_t>(), n_v, s))) return st;
     int64_t nnz = 0;
@@ -1110,15 +1137,14 @@ int build_topology(ibvt_coupling* c, hipStream_t s) {
     if ((st = ensure(c, c->M.val, size_t(nnz + 1) * sizeof(double)))) return st;
     if ((st = ensure(c, c->Mval32, size_t(nnz + 1) * sizeof(float)))) return st;
     if ((st = ensure(c, c->Mdiag_inv, size_t(n_v + 1) * sizeof(double)))) return st;
-    k_mass_pattern<true><<<blocks_for(n_v, 256), 256, 0, s>>>(
-        n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(), nullptr,
-        c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>());
+    pattern(true);
     if ((st = hip_check(hipGetLastError(), "mass pattern launch"))) return st;
   }
   return IBVT_OK;
 }
 
 int assemble_all(ibvt_coupling* c, hipStream_t s) {
+  if (c->dim == 2) return assemble_all_2d(c, s);
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
   int st;
   int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -71,7 +72,9 @@ struct AsmStats {
 struct ibvt_coupling {
   int precision = IBVT_FP64;
   uint32_t flags = 0;
-  int64_t n_vert = 0, n_tet = 0;
+  int dim = 3;    // 3: tetrahedra in a 3D grid; 2: triangles in a planar grid
+  int ncomp = 3;  // velocity components (= dim)
+  int64_t n_vert = 0, n_tet = 0;  // n_tet counts the elements (triangles when dim = 2)
   int32_t n_cells[3] = {0, 0, 0};
   std::vector<double> lat_host[9];
   ibvt::LatDesc ld{};
@@ -80,7 +83,8 @@ struct ibvt_coupling {
   ibvt::DevBuf X, tets;      // own copies
   ibvt::DevBuf vt_ptr, vt_tet;  // vertex -> incident tets (int64 ptr, int32 ids)
   ibvt::DevBuf tetvol;       // double n_tet
-  ibvt::DevBuf tetrec;       // double n_tet*16: per-tet record (vertices, determinant)
+  ibvt::DevBuf tetrec;       // double n_tet*16: per-tet record (vertices, determinant);
+                             // per triangle: 8 (vertices, determinant) when dim = 2
   ibvt::DevBuf tetgrad;      // double n_tet*12: ∇λ_i of every tet
   ibvt::DevBuf mcoef;        // double 3*n_tet: mass-term coefficients (reverse mode)
   ibvt::DevBuf fsiX;         // double 3*n_vert: configuration of the coupling step
@@ -92,7 +96,7 @@ struct ibvt_coupling {
   ibvt::DevBuf pair_off;     // int64 3*n_tet + 1
   int64_t n_pairs = 0;
   ibvt::DevBuf owner;        // int32 n_pairs
-  ibvt::DevBuf pval;         // T n_pairs*32
+  ibvt::DevBuf pval;         // T n_pairs*32 (n_pairs*12 when dim = 2)
   ibvt::DevBuf pmom;         // T n_pairs*kMomPad: per-pair piece moments (reverse mode)
   ibvt::DevBuf keep;         // uint8 n_pairs
   bool store_pieces = true;  // keep the moments of every piece (reverse mode)
@@ -152,8 +156,15 @@ int scan_i64(ibvt_coupling* c, const int64_t* in, int64_t* out, int64_t n, hipSt
 int scan_i32_to_i64(ibvt_coupling* c, const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
 
 // assemble.hip
-int build_topology(ibvt_coupling* c, hipStream_t s);
-int assemble_all(ibvt_coupling* c, hipStream_t s);
+int build_topology(ibvt_coupling* c, hipStream_t s);  // dim + 1 vertices per element
+int assemble_all(ibvt_coupling* c, hipStream_t s);    // dispatches on dim
+int read_back(ibvt_coupling* c, void* host, const void* dev, size_t bytes, hipStream_t s);
+int check_flags(ibvt_coupling* c, hipStream_t s);
+
+// assemble2d.hip: the planar coupling (Q1 quadrilateral lattice x P1 triangles)
+int assemble_all_2d(ibvt_coupling* c, hipStream_t s);
+int shape_gradient_2d(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
+                      int mass, double alpha, double* gX, hipStream_t s);
 
 // transpose.hip
 template <typename T>

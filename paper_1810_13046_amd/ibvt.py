@@ -36,6 +36,7 @@ EXPORTED = [
     "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info", "coupling_export_csr",
     "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
     "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
+    "assemble_coupling_2d", "ibvt_lattice_coords_2d",
 ]
 
 
@@ -55,6 +56,15 @@ class _Mesh(ctypes.Structure):
                 ("X", ctypes.c_void_p), ("tets", ctypes.c_void_p)]
 
 
+class _Grid2d(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32 * 2), ("faces", ctypes.c_void_p * 2)]
+
+
+class _Mesh2d(ctypes.Structure):
+    _fields_ = [("n_vert", ctypes.c_int64), ("n_tri", ctypes.c_int64),
+                ("X", ctypes.c_void_p), ("tris", ctypes.c_void_p)]
+
+
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32 * 3), ("rel_residual", ctypes.c_double * 3)]
 
@@ -69,7 +79,7 @@ class _Info(ctypes.Structure):
                 ("nnz_mass", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("assemblies", ctypes.c_int64), ("subtets", ctypes.c_int64),
                 ("piece_store", ctypes.c_int64), ("dist_evals", ctypes.c_int64),
-                ("cut_points", ctypes.c_int64), ("dual", ctypes.c_int64)]
+                ("cut_points", ctypes.c_int64), ("dual", ctypes.c_int64), ("dim", ctypes.c_int64)]
 
 
 _lib = None
@@ -132,10 +142,12 @@ def load_library(path: str = LIB_PATH):
     lib.fsi_step.argtypes = [vp, P(_FsiConfig), P(_FsiBuffers), _SOLID_FN, vp, _FLUID_FN, vp, vp,
                              P(_FsiReport)]
     lib.ibvt_fluid_lumped_volume.argtypes = [P(_Grid), ctypes.c_int, vp, vp]
+    lib.assemble_coupling_2d.argtypes = [P(_Grid2d), P(_Mesh2d), ctypes.c_int, u32, vp, P(vp)]
+    lib.ibvt_lattice_coords_2d.argtypes = [P(_Grid2d), ctypes.c_int, ctypes.c_int, vp, P(i64)]
     for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
-                 "ibvt_fluid_lumped_volume"):
+                 "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -148,25 +160,28 @@ def _check(st: int, where: str):
 
 
 def _grid_struct(faces):
+    """ibvt_grid (3 face arrays) or ibvt_grid2d (2 face arrays)."""
     faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
-    g = _Grid()
-    for e in range(3):
+    if len(faces) not in (2, 3):
+        raise ValueError("faces: 3 arrays (3D grid) or 2 (planar grid)")
+    g = _Grid() if len(faces) == 3 else _Grid2d()
+    for e in range(len(faces)):
         g.n_cells[e] = faces[e].size - 1
         g.faces[e] = faces[e].ctypes.data
     return g, faces
 
 
 def lattice_coords(faces, comp: int):
-    """Node coordinates of component `comp`'s lattice along x, y, z (host)."""
+    """Node coordinates of component `comp`'s lattice along each axis (host)."""
     lib = load_library()
     g, keep = _grid_struct(faces)
+    fn = lib.ibvt_lattice_coords if len(keep) == 3 else lib.ibvt_lattice_coords_2d
     out = []
-    for e in range(3):
+    for e in range(len(keep)):
         n = ctypes.c_int64()
-        _check(lib.ibvt_lattice_coords(ctypes.byref(g), comp, e, None, ctypes.byref(n)), "lattice")
+        _check(fn(ctypes.byref(g), comp, e, None, ctypes.byref(n)), "lattice")
         a = np.empty(n.value)
-        _check(lib.ibvt_lattice_coords(ctypes.byref(g), comp, e, a.ctypes.data, ctypes.byref(n)),
-               "lattice")
+        _check(fn(ctypes.byref(g), comp, e, a.ctypes.data, ctypes.byref(n)), "lattice")
         out.append(a)
     del keep
     return out
@@ -239,7 +254,12 @@ class SolveInfo:
 
 
 class Coupling:
-    """A coupling handle: B^d, B^dT, masses for one grid and mesh."""
+    """A coupling handle: B^d, B^dT, masses for one grid and mesh.
+
+    Three face arrays, X (n_vert, 3) and tets (n_tet, 4) make a 3D coupling;
+    two face arrays, X (n_vert, 2) and triangles (n_tri, 3) a planar one
+    (assemble_coupling_2d), whose solid fields are (2, n_vert) and whose
+    fluid fields are 2 arrays of shape (n_y, n_x)."""
 
     def __init__(self, faces, X, tets, precision: str = "fp64", consistent: bool = True,
                  store_pieces: bool = True, dual: bool = False, stream=None):
@@ -250,30 +270,37 @@ class Coupling:
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
+        self.dim = len(self.faces)
+        self.nc = self.dim
+        k = self.dim + 1
         self.n_vert = int(X.shape[0])
         self.n_tet = int(tets.shape[0])
-        if X.ndim != 2 or X.shape[1] != 3:
-            raise ValueError("X must be (n_vert, 3)")
-        if tets.ndim != 2 or tets.shape[1] != 4:
-            raise ValueError("tets must be (n_tet, 4)")
+        if X.ndim != 2 or X.shape[1] != self.dim:
+            raise ValueError(f"X must be (n_vert, {self.dim})")
+        if tets.ndim != 2 or tets.shape[1] != k:
+            raise ValueError(f"elements must be (n, {k})")
         g, keep = _grid_struct(self.faces)
-        m = _Mesh()
+        m = _Mesh() if self.dim == 3 else _Mesh2d()
         m.n_vert = self.n_vert
-        m.n_tet = self.n_tet
-        m.X = _dev(X, torch.float64, 3 * self.n_vert, "X")
-        m.tets = _dev(tets, torch.int32, 4 * self.n_tet, "tets") if self.n_tet else None
+        Xp = _dev(X, torch.float64, self.dim * self.n_vert, "X")
+        Tp = _dev(tets, torch.int32, k * self.n_tet, "elements") if self.n_tet else None
+        if self.dim == 3:
+            m.n_tet, m.X, m.tets = self.n_tet, Xp, Tp
+        else:
+            m.n_tri, m.X, m.tris = self.n_tet, Xp, Tp
         h = ctypes.c_void_p()
         flags = ((BUILD_CONSISTENT_M if consistent else 0) | (0 if store_pieces else NO_PIECE_STORE) |
                  (DUAL_BASIS if dual else 0))
         self.dual = bool(dual)
-        _check(lib.assemble_coupling(ctypes.byref(g), ctypes.byref(m),
-                                     FP64 if precision == "fp64" else FP32_MIXED, flags,
-                                     _stream(stream), ctypes.byref(h)), "assemble_coupling")
+        fn = lib.assemble_coupling if self.dim == 3 else lib.assemble_coupling_2d
+        _check(fn(ctypes.byref(g), ctypes.byref(m), FP64 if precision == "fp64" else FP32_MIXED,
+                  flags, _stream(stream), ctypes.byref(h)),
+               "assemble_coupling" if self.dim == 3 else "assemble_coupling_2d")
         self._h = h
         self.consistent = consistent
         del keep
         self.lattice_shapes = [tuple(len(a) for a in lattice_coords(self.faces, d))
-                               for d in range(3)]
+                               for d in range(self.nc)]
         self.n_fluid = [int(np.prod(s)) for s in self.lattice_shapes]
 
     # -- lifetime ---------------------------------------------------------
@@ -287,6 +314,8 @@ class Coupling:
         call's tensors and must enqueue their work on the current stream.
         Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
         import torch
+        if self.dim != 3:
+            raise IbvtError(7, "fsi_step", "the Picard driver takes 3D couplings only")
         dt_ = self.dtype
         dev = X_ref.device
         n = self.n_vert
@@ -358,63 +387,68 @@ class Coupling:
 
     def reassemble(self, X, stream=None):
         import torch
-        _check(_lib.reassemble_coupling(self.handle, _dev(X, torch.float64, 3 * self.n_vert, "X"),
+        _check(_lib.reassemble_coupling(self.handle,
+                                        _dev(X, torch.float64, self.dim * self.n_vert, "X"),
                                         _stream(stream)), "reassemble_coupling")
 
     # -- operations ---------------------------------------------------------
     def _fluid_ptrs(self, u, what):
-        if len(u) != 3:
-            raise ValueError(f"{what}: need 3 fluid components")
+        if len(u) != self.nc:
+            raise ValueError(f"{what}: need {self.nc} fluid components")
         arr = (ctypes.c_void_p * 3)()
-        for d in range(3):
+        for d in range(self.nc):
             arr[d] = _dev(u[d], self.dtype, self.n_fluid[d], f"{what}[{d}]")
         return arr
 
     def velocity(self, u_f, mass: str = "lumped", rtol: float = 1e-10, maxit: int = 500,
                  out=None, stream=None, with_info: bool = False):
-        """u_s = S^{-1} B u_f, returns (3, n_vert)."""
+        """u_s = S^{-1} B u_f, returns (nc, n_vert)."""
         import torch
         uf = self._fluid_ptrs(u_f, "u_f")
+        n = self.nc * self.n_vert
         if out is None:
-            out = torch.empty((3, self.n_vert), dtype=self.dtype, device=u_f[0].device)
+            out = torch.empty((self.nc, self.n_vert), dtype=self.dtype, device=u_f[0].device)
         info = _SolveInfo()
-        st = _lib.transfer_velocity(self.handle, uf, _dev(out, self.dtype, 3 * self.n_vert, "u_s"),
+        st = _lib.transfer_velocity(self.handle, uf, _dev(out, self.dtype, n, "u_s"),
                                     LUMPED if mass == "lumped" else CONSISTENT, float(rtol),
                                     int(maxit), _stream(stream),
                                     ctypes.byref(info) if with_info else None)
         _check(st, "transfer_velocity")
         if with_info:
-            return out, SolveInfo(tuple(info.iterations), tuple(info.rel_residual))
+            return out, SolveInfo(tuple(info.iterations)[:self.nc],
+                                  tuple(info.rel_residual)[:self.nc])
         return out
 
     def force(self, f_s, f_f, alpha: float = 1.0, load: bool = False, stream=None):
         """f_f[d] += alpha B^dT f_s[d] (in place), returns f_f."""
         ff = self._fluid_ptrs(f_f, "f_f")
-        _check(_lib.transfer_force(self.handle, _dev(f_s, self.dtype, 3 * self.n_vert, "f_s"), ff,
+        _check(_lib.transfer_force(self.handle, _dev(f_s, self.dtype, self.nc * self.n_vert, "f_s"), ff,
                                    float(alpha), FORCE_IS_LOAD if load else 0, _stream(stream)),
                "transfer_force")
         return f_f
 
     def velocity_vjp(self, g_us, u_f=None, u_s=None, mass: str = "lumped", g_uf=None, g_X=None,
                      rtol: float = 1e-12, maxit: int = 500, stream=None):
-        """Accumulates g_uf (3 fluid arrays) and g_X ((n_vert, 3) float64)."""
+        """Accumulates g_uf (nc fluid arrays) and g_X ((n_vert, dim) float64)."""
         import torch
+        n = self.nc * self.n_vert
         uf = self._fluid_ptrs(u_f, "u_f") if u_f is not None else None
         guf = self._fluid_ptrs(g_uf, "g_uf") if g_uf is not None else None
         _check(_lib.transfer_velocity_vjp(
-            self.handle, _dev(g_us, self.dtype, 3 * self.n_vert, "g_us"), uf,
-            _dev(u_s, self.dtype, 3 * self.n_vert, "u_s") if u_s is not None else None,
+            self.handle, _dev(g_us, self.dtype, n, "g_us"), uf,
+            _dev(u_s, self.dtype, n, "u_s") if u_s is not None else None,
             LUMPED if mass == "lumped" else CONSISTENT, float(rtol), int(maxit), guf,
-            _dev(g_X, torch.float64, 3 * self.n_vert, "g_X") if g_X is not None else None,
+            _dev(g_X, torch.float64, self.dim * self.n_vert, "g_X") if g_X is not None else None,
             _stream(stream)), "transfer_velocity_vjp")
 
     def force_vjp(self, g_ff, f_s=None, alpha: float = 1.0, g_fs=None, g_X=None, stream=None):
         import torch
+        n = self.nc * self.n_vert
         gff = self._fluid_ptrs(g_ff, "g_ff")
         _check(_lib.transfer_force_vjp(
-            self.handle, gff, _dev(f_s, self.dtype, 3 * self.n_vert, "f_s") if f_s is not None else None,
-            float(alpha), _dev(g_fs, self.dtype, 3 * self.n_vert, "g_fs") if g_fs is not None else None,
-            _dev(g_X, torch.float64, 3 * self.n_vert, "g_X") if g_X is not None else None,
+            self.handle, gff, _dev(f_s, self.dtype, n, "f_s") if f_s is not None else None,
+            float(alpha), _dev(g_fs, self.dtype, n, "g_fs") if g_fs is not None else None,
+            _dev(g_X, torch.float64, self.dim * self.n_vert, "g_X") if g_X is not None else None,
             _stream(stream)), "transfer_force_vjp")
 
     def info(self) -> dict:
@@ -427,7 +461,8 @@ class Coupling:
                     zero_tets=i.zero_tets, nnz=list(i.nnz), touched=list(i.touched),
                     nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies,
                     subtets=i.subtets, piece_store=bool(i.piece_store),
-                    dist_evals=i.dist_evals, cut_points=i.cut_points, dual=bool(i.dual))
+                    dist_evals=i.dist_evals, cut_points=i.cut_points, dual=bool(i.dual),
+                    dim=i.dim)
 
     def export_csr(self, comp: int, transposed: bool = False):
         """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""

@@ -77,3 +77,39 @@ def test_invalid_arguments_rejected_on_host(lib):
     # NULL handle
     assert lib.coupling_info(None, None) == 1
     lib.coupling_free(None)
+
+
+def test_planar_lattice_coords_follow_staggering(oracle_mod):
+    """Planar lattices (ibvt_lattice_coords_2d) equal the 2D oracle's."""
+    from oracle import plane
+    import workloads as wl
+    from paper_1810_13046_amd import lattice_coords
+    faces = [wl.uniform_faces(9), wl.stretched_faces(7, 3.0, -1.0, 1.0)]
+    for d in range(2):
+        got = lattice_coords(faces, d)
+        want = plane.lattice(faces, d)
+        assert len(got) == 2
+        for e in range(2):
+            assert np.array_equal(got[e], want[e])
+
+
+def test_planar_invalid_arguments_rejected_on_host(lib):
+    from paper_1810_13046_amd import ibvt
+    out = ctypes.c_void_p()
+    assert lib.assemble_coupling_2d(None, None, 0, 0, None, ctypes.byref(out)) == 1
+    faces = [np.array([0.0, 0.5, 0.4, 1.0]), np.linspace(0, 1, 4)]
+    g, keep = ibvt._grid_struct(faces)
+    m = ibvt._Mesh2d()
+    m.n_vert, m.n_tri, m.X, m.tris = 3, 1, 8, 8   # never dereferenced: grid fails first
+    assert lib.assemble_coupling_2d(ctypes.byref(g), ctypes.byref(m), 0, 0, None,
+                                    ctypes.byref(out)) == 1
+    assert b"increasing" in lib.ibvt_last_error()
+    faces = [np.linspace(0, 1, 4)] * 2
+    g, keep = ibvt._grid_struct(faces)
+    assert lib.assemble_coupling_2d(ctypes.byref(g), ctypes.byref(m), 7, 0, None,
+                                    ctypes.byref(out)) == 1
+    assert lib.assemble_coupling_2d(ctypes.byref(g), ctypes.byref(m), 0, 64, None,
+                                    ctypes.byref(out)) == 1
+    n = ctypes.c_int64()
+    assert lib.ibvt_lattice_coords_2d(ctypes.byref(g), 2, 0, None, ctypes.byref(n)) == 1
+    assert not out.value
