@@ -375,6 +375,8 @@ def main():
     ap.add_argument("--cpu-tets-per-body", type=int, default=8000)
     ap.add_argument("--profile-run", action="store_true",
                     help="one mixed-precision step and the applies only (for rocprofv3)")
+    ap.add_argument("--planar-only", action="store_true",
+                    help="only the planar leg (prints its JSON object; for rocprofv3)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -398,6 +400,9 @@ def main():
         return
     from paper_1810_13046_amd import load_library
     load_library()
+    if args.planar_only:
+        print(json.dumps(planar_leg(dev, args.steps, args.warmup, False)))
+        return
     if args.profile_run:
         args.skip_fp64 = True
         args.skip_cpu = True
