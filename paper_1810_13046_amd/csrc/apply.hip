@@ -11,9 +11,11 @@
 //
 // Consistent mass: Jacobi-preconditioned CG on M for all components at
 // once (one pass over M serves every right-hand side), with
-// per-component scalars and stopping tests.  Reductions are two-stage
-// (per-block partials, then one block in fixed order), so results do not
-// depend on timing.  In the mixed-precision path an outer loop recomputes
+// per-component scalars and stopping tests.  An iteration is five launches:
+// q = M p (k_cg_q), α (k_cg_alpha), the updates of x, r and z (k_cg_b), β
+// and the stopping test (k_cg_beta), and p = z + β p (k_cg_p); the two
+// single-block kernels reduce the per-block partials in a fixed order and
+// set the next scalars, so results do not depend on timing.  In the mixed-precision path an outer loop recomputes
 // the residual b - M x in double with double M values and solves the
 // correction with a float CG (iterative refinement).
 //
@@ -91,121 +93,60 @@ struct CgScalars {
   int all;
 };
 
-// q = M p for the NC components (values V, vectors T), plus per-block
-// partials of p·q.  kMG lanes per row stride through it (coalesced reads of
-// the row's columns and values) and reduce with lane shuffles in a fixed
-// order.
+// q = M x for the NC components (values V, vectors T), at the start of a
+// solve.  kMG lanes per row stride through it (coalesced reads of the row's
+// columns and values) and reduce with lane shuffles in a fixed order.
 constexpr int kMG = 8;
 
 template <typename T, typename V, int NC>
 __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t* __restrict__ rp,
                                                        const int32_t* __restrict__ col,
                                                        const V* __restrict__ val,
-                                                       const T* __restrict__ p, T* __restrict__ q,
-                                                       double* __restrict__ part,
-                                                       const CgScalars* sc) {
-  __shared__ double red[3][kThreads / kWave];
+                                                       const T* __restrict__ x, T* __restrict__ q) {
   const int g = threadIdx.x % kMG;
-  double loc[3] = {0, 0, 0};
-  if (!sc || !sc->all) {
-    // grid-stride over groups of kThreads / kMG rows (few blocks: few partials)
-    for (int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
-         i - threadIdx.x / kMG < n; i += int64_t(gridDim.x) * (kThreads / kMG)) {
-      T s0 = 0, s1 = 0, s2 = 0;
-      if (i < n) {
-        for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
-          const int64_t j = col[k];
-          const T m = T(val[k]);
-          s0 += m * p[j];
-          s1 += m * p[n + j];
-          if (NC > 2) s2 += m * p[2 * n + j];
-        }
-      }
+  for (int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
+       i - threadIdx.x / kMG < n; i += int64_t(gridDim.x) * (kThreads / kMG)) {
+    T sd[3] = {0, 0, 0};
+    if (i < n) {
+      for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
+        const int64_t j = col[k];
+        const T m = T(val[k]);
 #pragma unroll
-      for (int o = kMG / 2; o > 0; o >>= 1) {
-        s0 += __shfl_xor(s0, o, kWave);
-        s1 += __shfl_xor(s1, o, kWave);
-        s2 += __shfl_xor(s2, o, kWave);
-      }
-      if (i < n && g == 0) {
-        q[i] = s0;
-        q[n + i] = s1;
-        loc[0] += double(p[i]) * double(s0);
-        loc[1] += double(p[n + i]) * double(s1);
-        if (NC > 2) {
-          q[2 * n + i] = s2;
-          loc[2] += double(p[2 * n + i]) * double(s2);
-        }
+        for (int d = 0; d < NC; ++d) sd[d] += m * x[d * n + j];
       }
     }
-  }
-  if (!part) return;
-  for (int d = 0; d < 3; ++d) {
-    const double w = wave_sum(loc[d]);
-    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
-  }
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    double t = 0;
-    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
-    part[int64_t(blockIdx.x) * 3 + threadIdx.x] = t;
+#pragma unroll
+    for (int o = kMG / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int d = 0; d < NC; ++d) sd[d] += __shfl_xor(sd[d], o, kWave);
+    if (i < n && g == 0)
+#pragma unroll
+      for (int d = 0; d < NC; ++d) q[d * n + i] = sd[d];
   }
 }
 
-// Sum per-block partials (nb x 3) in fixed order into out[0..2].
-__global__ __launch_bounds__(kThreads) void k_reduce3(const double* __restrict__ part, int64_t nb,
-                                                     double* __restrict__ out) {
-  __shared__ double red[3][kThreads / kWave];
-  double loc[3] = {0, 0, 0};
-  for (int64_t b = threadIdx.x; b < nb; b += kThreads)
-    for (int d = 0; d < 3; ++d) loc[d] += part[b * 3 + d];
-  for (int d = 0; d < 3; ++d) {
-    const double w = wave_sum(loc[d]);
-    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
-  }
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    double t = 0;
-    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
-    out[threadIdx.x] = t;
-  }
-}
-
-// Elementwise steps with block partials of up to two dot products.
-//  mode 0 (init):  r = b - q; z = Dinv r; p = z;  partials (r·z, b·b)
-//  mode 1 (update): x += α p; r -= α q; z = Dinv r; partials (r·z, r·r)
+// Start of the CG: r = b - q (q = M x); z = D^-1 r; p = z; per-block
+// partials of (r·z, b·b).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_vec(int mode, int nc, int64_t n, const T* __restrict__ b,
-                                                    const T* __restrict__ q, T* __restrict__ x,
-                                                    T* __restrict__ r, T* __restrict__ z,
-                                                    T* __restrict__ p, const double* __restrict__ dinv,
-                                                    double* __restrict__ part, const CgScalars* sc) {
+__global__ __launch_bounds__(kThreads) void k_cg_init(int nc, int64_t n, const T* __restrict__ b,
+                                                     const T* __restrict__ q, T* __restrict__ r,
+                                                     T* __restrict__ z, T* __restrict__ p,
+                                                     const double* __restrict__ dinv,
+                                                     double* __restrict__ part) {
   __shared__ double red[6][kThreads / kWave];
   const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
   double loc[6] = {0, 0, 0, 0, 0, 0};
-  if (i < n && !(mode == 1 && sc->all)) {
+  if (i < n) {
     const double di = dinv[i];
     for (int d = 0; d < nc; ++d) {
       const int64_t k = int64_t(d) * n + i;
-      if (mode == 0) {
-        const T rv = b[k] - q[k];
-        const T zv = T(di * double(rv));
-        r[k] = rv;
-        z[k] = zv;
-        p[k] = zv;
-        loc[d] = double(rv) * double(zv);
-        loc[3 + d] = double(b[k]) * double(b[k]);
-      } else {
-        if (sc->conv[d]) continue;
-        const T al = T(sc->alpha[d]);
-        x[k] += al * p[k];
-        const T rv = r[k] - al * q[k];
-        const T zv = T(di * double(rv));
-        r[k] = rv;
-        z[k] = zv;
-        loc[d] = double(rv) * double(zv);
-        loc[3 + d] = double(rv) * double(rv);
-      }
+      const T rv = b[k] - q[k];
+      const T zv = T(di * double(rv));
+      r[k] = rv;
+      z[k] = zv;
+      p[k] = zv;
+      loc[d] = double(rv) * double(zv);
+      loc[3 + d] = double(b[k]) * double(b[k]);
     }
   }
   for (int d = 0; d < 6; ++d) {
@@ -238,44 +179,176 @@ __global__ __launch_bounds__(kThreads) void k_reduce6(const double* __restrict__
   }
 }
 
-// Scalar steps (one thread).
-//  step 0: after init reduce (rz, bb) in tmp[0..5]
-//  step 1: after pq reduce in tmp[0..2]: alpha
-//  step 2: after update reduce (rz_new, rr) in tmp[0..5]: beta, convergence
-__global__ void k_cg_scalar(int step, CgScalars* sc, const double* __restrict__ tmp, double rtol2) {
+// CG scalars after the start (one thread): r·z and b·b from tmp[0..5];
+// components with b = 0 are converged from the start.
+__global__ void k_cg_start(CgScalars* sc, const double* __restrict__ tmp) {
   if (threadIdx.x != 0) return;
-  if (step == 0) {
-    sc->all = 1;
-    for (int d = 0; d < 3; ++d) {
-      sc->rz[d] = tmp[d];
-      sc->bb[d] = tmp[3 + d];
-      sc->rr[d] = 0;
-      sc->iters[d] = 0;
-      // stop when the preconditioned start already meets the tolerance is
-      // decided after the first true residual norm: use r·z > 0 as "work left"
-      sc->conv[d] = (sc->bb[d] == 0.0) ? 1 : 0;
-      if (!sc->conv[d]) sc->all = 0;
-    }
-  } else if (step == 1) {
-    for (int d = 0; d < 3; ++d) {
-      sc->pq[d] = tmp[d];
-      sc->alpha[d] = (!sc->conv[d] && tmp[d] != 0.0) ? sc->rz[d] / tmp[d] : 0.0;
-    }
-  } else {
-    sc->all = 1;
-    for (int d = 0; d < 3; ++d) {
-      if (sc->conv[d]) continue;
-      const double rzn = tmp[d];
-      sc->rr[d] = tmp[3 + d];
-      sc->beta[d] = (sc->rz[d] != 0.0) ? rzn / sc->rz[d] : 0.0;
-      sc->rz[d] = rzn;
-      sc->iters[d] += 1;
-      if (sc->rr[d] <= rtol2 * sc->bb[d]) sc->conv[d] = 1;
-      else sc->all = 0;
-    }
+  sc->all = 1;
+  for (int d = 0; d < 3; ++d) {
+    sc->rz[d] = tmp[d];
+    sc->bb[d] = tmp[3 + d];
+    sc->rr[d] = 0;
+    sc->beta[d] = 0;
+    sc->alpha[d] = 0;
+    sc->iters[d] = 0;
+    sc->conv[d] = (sc->bb[d] == 0.0) ? 1 : 0;
+    if (!sc->conv[d]) sc->all = 0;
   }
 }
 
+// q = M p, with per-block partials of p·q (converged components are
+// carried along; their values are not used).
+template <typename T, typename V, int NC>
+__global__ __launch_bounds__(kThreads) void k_cg_q(int64_t n, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const V* __restrict__ val,
+                                                  const T* __restrict__ p, T* __restrict__ q,
+                                                  double* __restrict__ part,
+                                                  const CgScalars* sc) {
+  __shared__ double red[3][kThreads / kWave];
+  if (sc->all) return;
+  const int g = threadIdx.x % kMG;
+  double loc[3] = {0, 0, 0};
+  for (int64_t i = int64_t(blockIdx.x) * (kThreads / kMG) + threadIdx.x / kMG;
+       i - threadIdx.x / kMG < n; i += int64_t(gridDim.x) * (kThreads / kMG)) {
+    T sd[3] = {0, 0, 0};
+    if (i < n) {
+      for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
+        const int64_t j = col[k];
+        const T m = T(val[k]);
+#pragma unroll
+        for (int d = 0; d < NC; ++d) sd[d] += m * p[d * n + j];
+      }
+    }
+#pragma unroll
+    for (int o = kMG / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int d = 0; d < NC; ++d) sd[d] += __shfl_xor(sd[d], o, kWave);
+    if (i < n && g == 0) {
+#pragma unroll
+      for (int d = 0; d < NC; ++d) {
+        q[d * n + i] = sd[d];
+        loc[d] += double(p[d * n + i]) * double(sd[d]);
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < NC; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0;
+    if (threadIdx.x < NC)
+      for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
+    part[int64_t(blockIdx.x) * 3 + threadIdx.x] = t;
+  }
+}
+
+// α = (r·z)/(p·q) per active component from the partials of k_cg_q (one
+// block, fixed order).
+__global__ __launch_bounds__(kThreads) void k_cg_alpha(const double* __restrict__ part, int64_t nb,
+                                                      CgScalars* sc) {
+  __shared__ double red[3][kThreads / kWave];
+  if (sc->all) return;
+  double loc[3] = {0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nb; b += kThreads)
+    for (int d = 0; d < 3; ++d) loc[d] += part[b * 3 + d];
+  for (int d = 0; d < 3; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    double pq = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) pq += red[d][w];
+    sc->pq[d] = pq;
+    sc->alpha[d] = (!sc->conv[d] && pq != 0.0) ? sc->rz[d] / pq : 0.0;
+  }
+}
+
+// Iteration part B: x += α p, r -= α q, z = D^-1 r for the active
+// components, per-block partials of (r·z, r·r).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_b(int nc, int64_t n, const T* __restrict__ q,
+                                                  T* __restrict__ x, T* __restrict__ r,
+                                                  T* __restrict__ z, const T* __restrict__ p,
+                                                  const double* __restrict__ dinv,
+                                                  double* __restrict__ part,
+                                                  const CgScalars* sc) {
+  __shared__ double red[6][kThreads / kWave];
+  if (sc->all) return;
+  bool act[3];
+  T al[3];
+  for (int d = 0; d < 3; ++d) {
+    act[d] = d < nc && !sc->conv[d];
+    al[d] = T(sc->alpha[d]);
+  }
+  double loc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) {
+    const double di = dinv[i];
+    for (int d = 0; d < 3; ++d) {
+      if (!act[d]) continue;
+      const int64_t k = int64_t(d) * n + i;
+      x[k] += al[d] * p[k];
+      const T rv = r[k] - al[d] * q[k];
+      const T zv = T(di * double(rv));
+      r[k] = rv;
+      z[k] = zv;
+      loc[d] += double(rv) * double(zv);
+      loc[3 + d] += double(rv) * double(rv);
+    }
+  }
+  for (int d = 0; d < 6; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) t += red[threadIdx.x][w];
+    part[int64_t(blockIdx.x) * 6 + threadIdx.x] = t;
+  }
+}
+
+// β, iteration counts and per-component convergence (||r||² <= rtol²
+// ||b||²) from the partials of k_cg_b (one block, fixed order).
+__global__ __launch_bounds__(kThreads) void k_cg_beta(const double* __restrict__ part, int64_t nb,
+                                                     CgScalars* sc, double rtol2) {
+  __shared__ double red[6][kThreads / kWave];
+  if (sc->all) return;
+  double loc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nb; b += kThreads)
+    for (int d = 0; d < 6; ++d) loc[d] += part[b * 6 + d];
+  for (int d = 0; d < 6; ++d) {
+    const double w = wave_sum(loc[d]);
+    if (lane_id() == 0) red[d][threadIdx.x / kWave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[6];
+    for (int d = 0; d < 6; ++d) {
+      tot[d] = 0;
+      for (int w = 0; w < kThreads / kWave; ++w) tot[d] += red[d][w];
+    }
+    int all = 1;
+    for (int d = 0; d < 3; ++d) {
+      if (sc->conv[d]) continue;
+      sc->rr[d] = tot[3 + d];
+      sc->beta[d] = (sc->rz[d] != 0.0) ? tot[d] / sc->rz[d] : 0.0;
+      sc->rz[d] = tot[d];
+      sc->iters[d] += 1;
+      if (sc->rr[d] <= rtol2 * sc->bb[d]) sc->conv[d] = 1;
+      else all = 0;
+    }
+    sc->all = all;
+  }
+}
+
+// p = z + β p for the active components.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_p(int nc, int64_t n, const T* __restrict__ z,
                                                   T* __restrict__ p, const CgScalars* sc) {
@@ -361,6 +434,7 @@ __global__ void k_add_correction(int64_t n3, const float* __restrict__ e, double
 }
 
 inline unsigned nblk(int64_t n) { return unsigned(ceil_div(n > 0 ? n : 1, kThreads)); }
+
 // blocks of the row-group kernels (grid-stride over groups of kThreads / kMG
 // rows; capped so that their per-block partials stay few)
 inline unsigned nblk_rows(int64_t n) {
@@ -368,7 +442,8 @@ inline unsigned nblk_rows(int64_t n) {
 }
 
 // Workspace layout for the CG (bytes): scalars, partials, 6 vectors of T
-// (b copy not needed: rhs is read), plus double x/res for refinement.
+// (q, r, z, p and two refinement vectors; b is read in place), plus double
+// x/res for refinement.
 struct CgWork {
   CgScalars* sc;
   double* part;
@@ -418,17 +493,12 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
   const int32_t* col = c->M.col.as<int32_t>();
   const double* dinv = c->Mdiag_inv.as<double>();
   const double rtol2 = rtol * rtol;
-  auto mass_spmv = [&](const T* src, T* dst, double* part, const CgScalars* sc) {
-    if (nc == 3)
-      k_mass_spmv<T, V, 3><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, src, dst, part, sc);
-    else
-      k_mass_spmv<T, V, 2><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, src, dst, part, sc);
-  };
   // q = M x ; r = b - q ; z = D^-1 r ; p = z
-  mass_spmv(x, q, nullptr, nullptr);
-  k_cg_vec<T><<<nb, kThreads, 0, s>>>(0, nc, n, b, q, x, r, z, p, dinv, w.part, w.sc);
+  if (nc == 3) k_mass_spmv<T, V, 3><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, x, q);
+  else k_mass_spmv<T, V, 2><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, x, q);
+  k_cg_init<T><<<nb, kThreads, 0, s>>>(nc, n, b, q, r, z, p, dinv, w.part);
   k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
-  k_cg_scalar<<<1, 64, 0, s>>>(0, w.sc, w.tmp, rtol2);
+  k_cg_start<<<1, 64, 0, s>>>(w.sc, w.tmp);
   int st = hip_check(hipGetLastError(), "cg init launch");
   if (st) return st;
   const int check = 8;
@@ -439,12 +509,13 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
     const int chunk = std::min(check, maxit - it);
     for (int k = 0; k < chunk; ++k) {
       ProfScope ps("cg_iteration", s);
-      mass_spmv(p, q, w.part, w.sc);
-      k_reduce3<<<1, kThreads, 0, s>>>(w.part, nbm, w.tmp);
-      k_cg_scalar<<<1, 64, 0, s>>>(1, w.sc, w.tmp, rtol2);
-      k_cg_vec<T><<<nb, kThreads, 0, s>>>(1, nc, n, b, q, x, r, z, p, dinv, w.part, w.sc);
-      k_reduce6<<<1, kThreads, 0, s>>>(w.part, nb, w.tmp);
-      k_cg_scalar<<<1, 64, 0, s>>>(2, w.sc, w.tmp, rtol2);
+      if (nc == 3)
+        k_cg_q<T, V, 3><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, p, q, w.part, w.sc);
+      else
+        k_cg_q<T, V, 2><<<nbm, kThreads, 0, s>>>(n, rp, col, mval, p, q, w.part, w.sc);
+      k_cg_alpha<<<1, kThreads, 0, s>>>(w.part, nbm, w.sc);
+      k_cg_b<T><<<nb, kThreads, 0, s>>>(nc, n, q, x, r, z, p, dinv, w.part, w.sc);
+      k_cg_beta<<<1, kThreads, 0, s>>>(w.part, nb, w.sc, rtol2);
       k_cg_p<T><<<nb, kThreads, 0, s>>>(nc, n, z, p, w.sc);
     }
     it += chunk;
