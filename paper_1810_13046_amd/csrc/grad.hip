@@ -9,10 +9,12 @@
 // U = Σ u_j N_j (the Q1 interpolant):
 //   z^T (∂B/∂X_{a,k}) u = Σ_{T∋a} [ ∫ λ_a w ∂_k U + ∂_k λ_a ∫ w U ].
 // The bracket is a polynomial integral of degree <= 4 on each (tet,
-// component, cell) piece: k_shape_mom takes it from the piece moments kept
-// by the assembly, k_shape_pairs (when no moments are kept) clips the piece
-// again and integrates it; k_grad_gather sums it per vertex in a fixed order
-// and subtracts the mass term  z^T (∂S/∂X) u_s, with ∂|T|/∂X_a = |T| ∇λ_a
+// component, cell) piece: k_shape_tet takes it from the piece moments kept
+// by the assembly and sums it over the pieces of each (component, tet);
+// k_shape_pairs (when no moments are kept) clips every piece again and
+// integrates it, and k_pair_sums adds those per (component, tet);
+// k_grad_gather sums the per-tet terms per vertex in a fixed order and
+// subtracts the mass term  z^T (∂S/∂X) u_s, with ∂|T|/∂X_a = |T| ∇λ_a
 // (S consistent: |T|(1+δ_il)/20 per tet; lumped: |T|/4 on the diagonal).
 #include "geometry.hpp"
 #include "internal.hpp"
@@ -95,56 +97,91 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
 
-// Pair terms from the stored piece moments (no clipping, no quadrature): one
-// lane per pair.
+// Pair terms from the stored piece moments (no clipping, no quadrature),
+// summed over the pieces of each (component, tet): one lane per (component,
+// tet) walks the tet's pairs in cell order, so the tet's geometry, vertex
+// weights and lattice are set up once per lane.  Sums in double to
+// pgt[(d, t)][12] (vertex a, axis k at a*3 + k).
 template <typename T>
-__global__ __launch_bounds__(256) void k_shape_mom(
-    int64_t n_pairs, int64_t n_t, int64_t n_v, const int32_t* __restrict__ owner,
-    const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-    const uint8_t* __restrict__ keep, const T* __restrict__ pmom,
-    const double* __restrict__ tetrec, const double* __restrict__ lat,
-    const int32_t* __restrict__ tets, LatDesc ld, const T* __restrict__ z, const T* u0,
-    const T* u1, const T* u2, T* __restrict__ pg, int dual) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  T out[12];
+__global__ __launch_bounds__(256) void k_shape_tet(
+    int64_t n_t, int64_t n_v, const int64_t* __restrict__ pair_off,
+    const CellRange* __restrict__ rng, const uint8_t* __restrict__ keep,
+    const T* __restrict__ pmom, const double* __restrict__ tetrec,
+    const double* __restrict__ lat, const int32_t* __restrict__ tets, LatDesc ld,
+    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, double* __restrict__ pgt,
+    int dual) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= 3 * n_t) return;
+  const int d = int(w / n_t);
+  const int64_t t = w - int64_t(d) * n_t;
+  double acc[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) out[k] = T(0);
-  if (keep[p]) {
-    int d, ci[3];
-    int64_t t;
-    double lo[3], hi[3];
-    pair_cell(p, n_t, owner, pair_off, rng, lat, ld, d, t, ci, lo, hi);
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  const int64_t p0 = pair_off[w], p1 = pair_off[w + 1];
+  if (p1 > p0) {
     const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
     const T* zd = z + int64_t(d) * n_v;
     T zl[4] = {zd[tv.x], zd[tv.y], zd[tv.z], zd[tv.w]};
     if (dual) dual_weights<T>(zl);
     const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
     const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
-    const int64_t n000 = ci[0] + NX * (ci[1] + NY * int64_t(ci[2]));
-    T ul[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      ul[j] = u[n000 + (j & 1) + NX * (((j >> 1) & 1) + NY * (j >> 2))];
+    const double* L0 = lat + ld.off[3 * d + 0];
+    const double* L1 = lat + ld.off[3 * d + 1];
+    const double* L2 = lat + ld.off[3 * d + 2];
     double rec[kTetRec];
     load_row<kTetRec>(tetrec + t * kTetRec, rec);
-    T LA[4], LG[4][3];
-    rec_cell_lambda<T>(rec, lo, hi, LA, LG);
-    T M[kMomPad];
-    load_row<kMomPad>(pmom + p * kMomPad, M);
-    T A[12], Bs;
-    mom_shape<T>(M, LA, LG, zl, ul, A, Bs);
-    // ∂/∂x_k = (1/h_k) ∂/∂ξ_k; ∇λ_a = (cell-local gradient)/h
-    const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
+    TetGeom G;
+    for (int k = 0; k < 4; ++k)
+      for (int e = 0; e < 3; ++e) G.V[k][e] = rec[3 * k + e];
+    tet_geom(G);
+    const CellRange r = rng[w];
+    for (int64_t p = p0; p < p1; ++p) {
+      if (!keep[p]) continue;
+      const uint32_t q = uint32_t(p - p0);
+      const uint32_t qy = q / uint32_t(r.n[0]);
+      const uint32_t qz = qy / uint32_t(r.n[1]);
+      const int ci[3] = {r.lo[0] + int(q - qy * uint32_t(r.n[0])),
+                         r.lo[1] + int(qy - qz * uint32_t(r.n[1])), r.lo[2] + int(qz)};
+      const double lo[3] = {L0[ci[0]], L1[ci[1]], L2[ci[2]]};
+      const double hi[3] = {L0[ci[0] + 1], L1[ci[1] + 1], L2[ci[2] + 1]};
+      const int64_t n000 = ci[0] + NX * (ci[1] + NY * int64_t(ci[2]));
+      T ul[8];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const T ih = T(1.0 / (hi[k] - lo[k]));
+      for (int j = 0; j < 8; ++j)
+        ul[j] = u[n000 + (j & 1) + NX * (((j >> 1) & 1) + NY * (j >> 2))];
+      T LA[4], LG[4][3];
+      cell_lambda<T>(G, lo, hi, LA, LG);
+      T M[kMomPad];
+      load_row<kMomPad>(pmom + p * kMomPad, M);
+      T A[12], Bs;
+      mom_shape<T>(M, LA, LG, zl, ul, A, Bs);
+      // ∂/∂x_k = (1/h_k) ∂/∂ξ_k; ∇λ_a = (cell-local gradient)/h
+      const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) out[a * 3 + k] = sc * ih * (A[a * 3 + k] + LG[a][k] * Bs);
+      for (int k = 0; k < 3; ++k) {
+        const T ih = T(1.0 / (hi[k] - lo[k]));
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a * 3 + k] += double(sc * ih * (A[a * 3 + k] + LG[a][k] * Bs));
+      }
     }
   }
+  store_row<12>(pgt + w * 12, acc);
+}
+
+// Per (component, tet) sums of the per-pair terms of k_shape_pairs.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_sums(int64_t n_tc, const int64_t* __restrict__ pair_off,
+                                                   const T* __restrict__ pg,
+                                                   double* __restrict__ pgt) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= n_tc) return;
+  double acc[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) pg[p * 12 + k] = out[k];
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  for (int64_t p = pair_off[w]; p < pair_off[w + 1]; ++p)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] += double(pg[p * 12 + k]);
+  store_row<12>(pgt + w * 12, acc);
 }
 
 // Mass term coefficient per (component d, tet t): |T| · z_T^T S_T u_s,T with
@@ -175,15 +212,14 @@ __global__ __launch_bounds__(256) void k_mass_coef(int64_t n_t, int64_t n_v,
 }
 
 // One wavefront per vertex a: lanes take (incident tet, component) items,
-// sum the pair terms and the mass term, then a fixed-order wave reduction.
-// mcoef: per (component, tet) mass coefficients, or null for no mass term.
-template <typename T>
+// add the per-tet pair terms and the mass term, then a fixed-order wave
+// reduction.  mcoef: per (component, tet) mass coefficients, or null for no
+// mass term.
 __global__ __launch_bounds__(256) void k_grad_gather(
     int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
     const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
-    const int64_t* __restrict__ pair_off, const T* __restrict__ pg,
-    const double* __restrict__ tetgrad, const double* __restrict__ mcoef, double alpha,
-    double* __restrict__ gX) {
+    const double* __restrict__ pgt, const double* __restrict__ tetgrad,
+    const double* __restrict__ mcoef, double alpha, double* __restrict__ gX) {
   const int64_t a = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = lane_id();
   if (a >= n_v) return;
@@ -196,8 +232,7 @@ __global__ __launch_bounds__(256) void k_grad_gather(
     const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
     const int la = (tv.y == int32_t(a)) ? 1 : (tv.z == int32_t(a)) ? 2 : (tv.w == int32_t(a)) ? 3 : 0;
     const int64_t tc = int64_t(d) * n_t + t;
-    for (int64_t p = pair_off[tc]; p < pair_off[tc + 1]; ++p)
-      for (int e = 0; e < 3; ++e) g[e] += double(pg[p * 12 + la * 3 + e]);
+    for (int e = 0; e < 3; ++e) g[e] += pgt[tc * 12 + la * 3 + e];
     if (mcoef) {
       const double m = mcoef[tc];
       const double* ga = tetgrad + t * 12 + la * 3;
@@ -213,26 +248,36 @@ __global__ __launch_bounds__(256) void k_grad_gather(
 template <typename T>
 int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const void* us, int mass,
                 double alpha, double* gX, hipStream_t s) {
-  int st = ensure(c, c->work2, size_t(c->n_pairs + 1) * 12 * sizeof(T));
+  // per (component, tet) sums (double), then the per-pair terms of the
+  // re-clipping path
+  const size_t tc_bytes = (size_t(3 * c->n_tet + 1) * 12 * sizeof(double) + 255) & ~size_t(255);
+  const size_t pg_bytes = c->mom_valid ? 0 : size_t(c->n_pairs + 1) * 12 * sizeof(T);
+  int st = ensure(c, c->work2, tc_bytes + pg_bytes);
   if (st) return st;
-  T* pg = c->work2.as<T>();
+  double* pgt = c->work2.as<double>();
+  T* pg = reinterpret_cast<T*>(c->work2.as<char>() + tc_bytes);
   unsigned* flags = c->flags_dev.as<unsigned>();
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
-  if (c->n_pairs > 0 && c->mom_valid) {
+  if (c->mom_valid) {
     ProfScope ps("shape_moments", s);
-    k_shape_mom<T><<<unsigned(ceil_div(c->n_pairs, 256)), 256, 0, s>>>(
-        c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
-        c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(),
-        c->lat.as<double>(), c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
-        static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg, c->dual ? 1 : 0);
-  } else if (c->n_pairs > 0) {
+    if (c->n_tet > 0)
+      k_shape_tet<T><<<unsigned(ceil_div(3 * c->n_tet, 256)), 256, 0, s>>>(
+          c->n_tet, c->n_vert, c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
+          c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(), c->lat.as<double>(),
+          c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
+          static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pgt, c->dual ? 1 : 0);
+  } else {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
     ProfScope ps("shape_pairs", s);
-    k_shape_pairs<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
+    if (nb > 0)
+      k_shape_pairs<T><<<dim3(unsigned(nb)), kWave, 0, s>>>(
         c->n_pairs, c->n_tet, c->n_vert, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
         c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->X.as<double>(), c->tets.as<int32_t>(),
         c->lat.as<double>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
         static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pg, c->dual ? 1 : 0, flags);
+    if (c->n_tet > 0)
+      k_pair_sums<T><<<unsigned(ceil_div(3 * c->n_tet, 256)), 256, 0, s>>>(
+          3 * c->n_tet, c->pair_off.as<int64_t>(), pg, pgt);
   }
   if ((st = hip_check(hipGetLastError(), "shape launch"))) return st;
   double* mcoef = nullptr;
@@ -246,10 +291,9 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   const unsigned blocks = unsigned(ceil_div(c->n_vert * kWave, 256));
   ProfScope ps_g("grad_gather", s);
   if (c->n_vert > 0)
-    k_grad_gather<T><<<blocks, 256, 0, s>>>(c->n_vert, c->n_tet, c->vt_ptr.as<int64_t>(),
-                                            c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-                                            c->pair_off.as<int64_t>(), pg, c->tetgrad.as<double>(),
-                                            mcoef, alpha, gX);
+    k_grad_gather<<<blocks, 256, 0, s>>>(c->n_vert, c->n_tet, c->vt_ptr.as<int64_t>(),
+                                         c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(), pgt,
+                                         c->tetgrad.as<double>(), mcoef, alpha, gX);
   if ((st = hip_check(hipGetLastError(), "gather launch"))) return st;
   unsigned f = 0;
   if ((st = hip_check(hipMemcpyAsync(&f, flags, sizeof(f), hipMemcpyDeviceToHost, s), "read")))
