@@ -20,7 +20,8 @@
 //  transpose and the applies are shared with the 3D path (component count
 //  from the handle).
 //  reverse mode: k_shape2 turns the kept moments into the per-piece shape
-//  terms, k_grad2 sums them per vertex with the mass term.
+//  terms, k_pair_sums2 adds them per (component, triangle), k_grad2 sums
+//  those per vertex with the mass term.
 #include "internal.hpp"
 #include "plane.hpp"
 
@@ -475,13 +476,26 @@ __global__ void k_mass_coef2(int64_t n_t, int64_t n_v, const int32_t* __restrict
   out[t] = area[t] * sT;
 }
 
-// gX[a] += alpha (Σ over incident triangles, components, pieces of the pair
-// terms - mcoef_T ∇λ_a), one lane per vertex, fixed order.
+// Per (component, triangle) sums of the pair terms, pairs in order.
+__global__ void k_pair_sums2(int64_t n_tc, const int64_t* __restrict__ pair_off,
+                             const double* __restrict__ pg, double* __restrict__ pgt) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= n_tc) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t p = pair_off[w]; p < pair_off[w + 1]; ++p)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] += pg[p * 6 + k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pgt[w * 6 + k] = acc[k];
+}
+
+// gX[a] += alpha (Σ over incident triangles and components of the summed
+// pair terms - mcoef_T ∇λ_a), one lane per vertex, fixed order.
 __global__ void k_grad2(int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
                         const int32_t* __restrict__ vt_tri, const int32_t* __restrict__ tris,
-                        const int64_t* __restrict__ pair_off, const double* __restrict__ pg,
-                        const double* __restrict__ grad, const double* __restrict__ mcoef,
-                        double alpha, double* __restrict__ gX) {
+                        const double* __restrict__ pgt, const double* __restrict__ grad,
+                        const double* __restrict__ mcoef, double alpha,
+                        double* __restrict__ gX) {
   const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (a >= n_v) return;
   double g0 = 0.0, g1 = 0.0;
@@ -490,10 +504,8 @@ __global__ void k_grad2(int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt
     const int la = tris[3 * t + 1] == int32_t(a) ? 1 : (tris[3 * t + 2] == int32_t(a) ? 2 : 0);
     for (int d = 0; d < 2; ++d) {
       const int64_t tc = int64_t(d) * n_t + t;
-      for (int64_t p = pair_off[tc]; p < pair_off[tc + 1]; ++p) {
-        g0 += pg[p * 6 + 2 * la];
-        g1 += pg[p * 6 + 2 * la + 1];
-      }
+      g0 += pgt[tc * 6 + 2 * la];
+      g1 += pgt[tc * 6 + 2 * la + 1];
     }
     if (mcoef) {
       g0 -= mcoef[t] * grad[6 * t + 2 * la];
@@ -636,9 +648,11 @@ int shape2_typed(ibvt_coupling* c, const T* z, const T* u0, const T* u1, const T
                  double alpha, double* gX, hipStream_t s) {
   const int64_t n_t = c->n_tet, n_v = c->n_vert, n_pairs = c->n_pairs;
   int st;
-  if ((st = ensure(c, c->work2, size_t(n_pairs + 1) * 6 * sizeof(double)))) return st;
+  const size_t pg_bytes = (size_t(n_pairs + 1) * 6 * sizeof(double) + 255) & ~size_t(255);
+  if ((st = ensure(c, c->work2, pg_bytes + size_t(2 * n_t + 1) * 6 * sizeof(double)))) return st;
   if ((st = ensure(c, c->mcoef, size_t(n_t + 1) * sizeof(double)))) return st;
   double* pg = c->work2.as<double>();
+  double* pgt = reinterpret_cast<double*>(c->work2.as<char>() + pg_bytes);
   {
     ProfScope ps("shape2d", s);
     if (n_pairs > 0)
@@ -646,6 +660,9 @@ int shape2_typed(ibvt_coupling* c, const T* z, const T* u0, const T* u1, const T
           n_pairs, n_t, n_v, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(),
           c->rng.as<CellRange>(), c->keep.as<uint8_t>(), c->pmom.as<double>(), c->tetrec.as<double>(),
           c->tets.as<int32_t>(), c->lat.as<double>(), c->ld, z, u0, u1, pg, c->dual ? 1 : 0);
+    if (n_t > 0)
+      k_pair_sums2<<<blocks_for(2 * n_t, 256), 256, 0, s>>>(2 * n_t, c->pair_off.as<int64_t>(), pg,
+                                                             pgt);
     const double* mc = nullptr;
     if (mass >= 0) {
       k_mass_coef2<T><<<blocks_for(n_t, 256), 256, 0, s>>>(n_t, n_v, c->tets.as<int32_t>(),
@@ -654,9 +671,8 @@ int shape2_typed(ibvt_coupling* c, const T* z, const T* u0, const T* u1, const T
       mc = c->mcoef.as<double>();
     }
     k_grad2<<<blocks_for(n_v, 256), 256, 0, s>>>(n_v, n_t, c->vt_ptr.as<int64_t>(),
-                                                    c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-                                                    c->pair_off.as<int64_t>(), pg,
-                                                    c->tetgrad.as<double>(), mc, alpha, gX);
+                                                 c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+                                                 pgt, c->tetgrad.as<double>(), mc, alpha, gX);
   }
   return hip_check(hipGetLastError(), "shape launch");
 }
