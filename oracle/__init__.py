@@ -60,8 +60,9 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
-    from . import plane
+    from . import plane, unstructured
     plane.build(force)
+    unstructured.build(force)
     return _LIB
 
 

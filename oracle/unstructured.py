@@ -1,0 +1,195 @@
+"""FP64 CPU oracle of the coupling with an unstructured background mesh: a
+P1 tetrahedral fluid mesh against the P1 tetrahedral solid mesh.
+
+TEST INFRASTRUCTURE ONLY, like the rest of this package.
+
+Section 2.3 assembles the transfer for meshes that need not be structured:
+(I) the overlapping elements are found by a tree search, (II)-(III) the
+products of the two element bases are integrated on the intersections
+(piecewise affine meshes), (IV) the mortar matrices are assembled.  Here
+the fluid space is P1 on the fluid tets (collocated: every velocity
+component uses the same nodes and the same B):
+
+* candidate pairs: every (solid tet, fluid tet) with overlapping bounding
+  boxes (a k-d tree ball query on the box centres gives a superset, the
+  exact box test filters it; the GPU builds its own bounding-volume tree);
+* B_ij = ∫ λ_i μ_j dV per pair (C part, o3.c), summed;
+* S, the transfers and the dual multipliers as in the structured case
+  (oracle/__init__.py).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import DROP_REL, consistent_mass, lumped_mass, mass_solve, tet_volumes
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "o3.c")
+_LIB = os.path.join(_HERE, "_o3.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part with gcc (plain C, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        dp, i64p, i32p = P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_int32)
+        lib.o3_pairs.argtypes = [dp, i32p, dp, i32p, i64p, ctypes.c_int64, ctypes.c_double,
+                                 ctypes.c_int, dp, dp, P(ctypes.c_uint8)]
+        lib.o3_pairs.restype = ctypes.c_int
+        lib.o3_clip_volume.argtypes = [dp, dp]
+        lib.o3_clip_volume.restype = ctypes.c_double
+        lib.o3_int2.argtypes = [dp, dp, dp]
+        lib.o3_int2.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def tet_bounds(X, tets):
+    P = np.asarray(X)[tets]
+    return P.min(axis=1), P.max(axis=1)
+
+
+def candidate_pairs(Xs, tets_s, Xf, tets_f):
+    """(solid tet, fluid tet) pairs with overlapping closed bounding boxes,
+    sorted by solid tet then fluid tet.  Boxes that overlap have centres
+    closer than the sum of their half-diagonals, so a k-d tree ball query on
+    the fluid box centres gives a superset, which the exact box test then
+    filters."""
+    from scipy.spatial import cKDTree
+    mns, mxs = tet_bounds(Xs, tets_s)
+    mnf, mxf = tet_bounds(Xf, tets_f)
+    cs, cf = 0.5 * (mns + mxs), 0.5 * (mnf + mxf)
+    hs = 0.5 * np.linalg.norm(mxs - mns, axis=1)
+    hf = 0.5 * np.linalg.norm(mxf - mnf, axis=1)
+    tree = cKDTree(cf)
+    out = []
+    for s in range(tets_s.shape[0]):
+        cand = np.asarray(tree.query_ball_point(cs[s], hs[s] + hf.max() + 1e-12), dtype=np.int64)
+        ok = np.all((mxs[s] >= mnf[cand]) & (mns[s] <= mxf[cand]), axis=1)
+        f = np.sort(cand[ok])
+        out.append(np.stack([np.full(f.size, s, dtype=np.int64), f], axis=1))
+    if not out:
+        return np.zeros((0, 2), dtype=np.int64)
+    return np.ascontiguousarray(np.concatenate(out))
+
+
+@dataclass
+class Coupling:
+    """B (n_vert_solid x n_vert_fluid, CSR) plus what produced it."""
+    Xf: np.ndarray
+    tets_f: np.ndarray
+    X: np.ndarray
+    tets: np.ndarray
+    B: sp.csr_matrix
+    pairs: np.ndarray
+    vals: np.ndarray
+    keep: np.ndarray
+    stats: dict = field(default_factory=dict)
+    dual: bool = False
+
+
+def pair_values(Xs, tets_s, Xf, tets_f, pairs, drop_rel=DROP_REL, nthreads=0):
+    lib = _load()
+    Xs = np.ascontiguousarray(Xs, dtype=np.float64)
+    Xf = np.ascontiguousarray(Xf, dtype=np.float64)
+    ts = np.ascontiguousarray(tets_s, dtype=np.int32)
+    tf = np.ascontiguousarray(tets_f, dtype=np.int32)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int64)
+    n = pairs.shape[0]
+    vals = np.zeros((n, 16))
+    vols = np.zeros(n)
+    keep = np.zeros(n, dtype=np.uint8)
+    lib.o3_pairs(_dp(Xs), ts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(Xf),
+                 tf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                 pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, float(drop_rel),
+                 int(nthreads), _dp(vals), _dp(vols),
+                 keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return vals, vols, keep.astype(bool)
+
+
+def assemble(Xf, tets_f, Xs, tets_s, drop_rel=DROP_REL, dual=False, nthreads=0) -> Coupling:
+    """B_ij = ∫ λ_i μ_j (solid vertex i, fluid vertex j); with dual=True the
+    dual multipliers ψ_i = 5λ_i − 1 of each solid tet (a piece's values
+    become 5·b_i − Σ_k b_k)."""
+    Xs = np.ascontiguousarray(Xs, dtype=np.float64)
+    Xf = np.ascontiguousarray(Xf, dtype=np.float64)
+    tets_s = np.ascontiguousarray(tets_s, dtype=np.int32)
+    tets_f = np.ascontiguousarray(tets_f, dtype=np.int32)
+    t0 = time.perf_counter()
+    pairs = candidate_pairs(Xs, tets_s, Xf, tets_f)
+    vals, vols, keep = pair_values(Xs, tets_s, Xf, tets_f, pairs, drop_rel, nthreads)
+    pv = vals
+    if dual:
+        b = vals.reshape(-1, 4, 4)
+        pv = (5.0 * b - b.sum(axis=1, keepdims=True)).reshape(-1, 16)
+    sel = np.nonzero(keep)[0]
+    rows = np.repeat(tets_s[pairs[sel, 0]], 4, axis=1).reshape(-1)       # i major
+    cols = np.tile(tets_f[pairs[sel, 1]], (1, 4)).reshape(-1)            # j minor
+    B = sp.csr_matrix((pv[sel].reshape(-1), (rows, cols)), shape=(Xs.shape[0], Xf.shape[0]))
+    stats = dict(pairs=int(pairs.shape[0]), pieces=int(keep.sum()),
+                 dropped=int(((vols > 0) & ~keep).sum()),
+                 zero_tets=int((tet_volumes(Xs, tets_s) == 0).sum()),
+                 seconds=time.perf_counter() - t0)
+    return Coupling(Xf, tets_f, Xs, tets_s, B, pairs, vals, keep, stats, dual)
+
+
+def transfer_velocity(cpl: Coupling, u_f, mass="lumped"):
+    """w_s = S^{-1} B v_f for each component (u_f: (nc, n_vert_fluid))."""
+    if cpl.dual and mass == "consistent":
+        raise ValueError("the dual basis has a diagonal S: use mass='lumped'")
+    u_f = np.atleast_2d(np.asarray(u_f, dtype=np.float64))
+    rhs = np.stack([cpl.B @ u for u in u_f])
+    return mass_solve(cpl.X, cpl.tets, rhs, "lumped" if cpl.dual else mass)
+
+
+def transfer_force(cpl: Coupling, f_s, alpha=1.0, load=False, base=None):
+    """f_f = base + alpha B^T f_s per component, or alpha B^T S^{-1} f_s."""
+    f_s = np.atleast_2d(np.asarray(f_s, dtype=np.float64))
+    if load:
+        f_s = mass_solve(cpl.X, cpl.tets, f_s, "lumped" if cpl.dual else "consistent")
+    out = alpha * np.stack([cpl.B.T @ f for f in f_s])
+    if base is not None:
+        out = out + np.asarray(base, dtype=np.float64)
+    return out
+
+
+def clip_volume(S, F) -> float:
+    lib = _load()
+    a = np.ascontiguousarray(S, dtype=np.float64)
+    b = np.ascontiguousarray(F, dtype=np.float64)
+    return lib.o3_clip_volume(_dp(a), _dp(b))
+
+
+def int2(Y, f, g) -> float:
+    lib = _load()
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (Y, f, g)]
+    return lib.o3_int2(*[_dp(x) for x in arrs])
+
+
+__all__ = ["build", "candidate_pairs", "Coupling", "pair_values", "assemble",
+           "transfer_velocity", "transfer_force", "clip_volume", "int2", "tet_bounds",
+           "lumped_mass", "consistent_mass"]

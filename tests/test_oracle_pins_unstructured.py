@@ -1,0 +1,161 @@
+"""Pins of the FP64 oracle of the coupling with an unstructured (P1
+tetrahedral) fluid background (no GPU): closed forms, an independent Gauss
+rule, tilings, the symmetry of exchanging the two meshes, exact
+reproduction of affine fields, partition of unity and Monte Carlo brute
+force."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from tests.refquad import ref_simplex_monomial, tet_integral
+
+WU = wl.unstructured
+REF = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+
+
+@pytest.fixture(scope="module")
+def un(oracle_mod):
+    from oracle import unstructured
+    unstructured.build(force=False)
+    return unstructured
+
+
+@pytest.fixture(scope="module")
+def w1(un):
+    W = WU.workload_u(1)
+    return W, un.assemble(W.Xf, W.tets_f, W.X, W.tets)
+
+
+def test_int2_reference_simplex_monomials(un):
+    coord = [REF[:, 0], REF[:, 1], REF[:, 2]]
+    one = np.ones(4)
+    for a in range(3):
+        for b in range(3):
+            f = coord[a] if a < 3 else one
+            g = coord[b]
+            al = [0, 0, 0]
+            al[a] += 1
+            al[b] += 1
+            want = float(ref_simplex_monomial(*al))
+            assert un.int2(REF, f, g) == pytest.approx(want, rel=1e-14)
+    assert un.int2(REF, one, one) == pytest.approx(1 / 6, rel=1e-15)
+
+
+def test_int2_matches_gauss_rule(un):
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        Y = rng.uniform(-1, 2, size=(4, 3))
+        c = rng.standard_normal((2, 4))
+        f, g = (c[m, 0] + Y @ c[m, 1:] for m in range(2))
+        want = tet_integral(Y, lambda p: (c[0, 0] + p @ c[0, 1:]) * (c[1, 0] + p @ c[1, 1:]))
+        assert un.int2(Y, f, g) == pytest.approx(want, rel=1e-12, abs=1e-14)
+
+
+def test_clip_volume_closed_forms(un):
+    assert un.clip_volume(REF, REF) == pytest.approx(1 / 6, rel=1e-14)
+    assert un.clip_volume(REF, REF + 2.0) == 0.0
+    # a scaled copy inside
+    inner = 0.1 + 0.5 * REF   # largest coordinate sum 0.8: inside the simplex
+    assert un.clip_volume(inner, REF) == pytest.approx(0.125 / 6, rel=1e-14)
+    assert un.clip_volume(REF, inner) == pytest.approx(0.125 / 6, rel=1e-14)
+    # the simplex and its translate along x: {x >= a} ∩ S, volume (1 - a)^3/6
+    for a in (0.1, 0.35, 0.7):
+        assert un.clip_volume(REF, REF + [a, 0, 0]) == pytest.approx((1 - a) ** 3 / 6, rel=1e-13)
+    # sharing a face only
+    mirror = REF * [-1, 1, 1]
+    assert un.clip_volume(REF, mirror) == pytest.approx(0.0, abs=1e-16)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_clip_pieces_tile_the_tet(un, seed):
+    """A tet inside a tetrahedral mesh of a box: the pieces over all the
+    mesh's tets add up to its volume."""
+    rng = np.random.default_rng(seed)
+    box = WU.warped_box("b", 3, 0.2, 0.5, rng)
+    T = rng.uniform(0.1, 0.9, size=(4, 3))
+    vol = abs(np.linalg.det(T[1:] - T[0])) / 6
+    tot = sum(un.clip_volume(T, box.X[t]) for t in box.tets)
+    assert tot == pytest.approx(vol, rel=1e-12)
+
+
+def test_row_sums_are_lumped_mass_and_total_volume(un, w1):
+    """Σ_j μ_j = 1 inside the fluid mesh: row sums = ∫ λ_i; total = exact
+    beam volume."""
+    W, R = w1
+    m = un.lumped_mass(W.X, W.tets)
+    np.testing.assert_allclose(np.asarray(R.B.sum(axis=1)).ravel(), m, rtol=1e-12)
+    assert R.B.sum() == pytest.approx(0.4 * 0.1 * 0.1, rel=1e-13)
+
+
+def test_exchange_symmetry(un):
+    """B with the roles of the two meshes exchanged is the transpose."""
+    rng = np.random.default_rng(8)
+    A = WU.warped_box("a", 3, 0.2, 0.4, rng)
+    C = WU.warped_box("c", 4, 0.2, 0.4, rng)
+    R1 = un.assemble(A.X, A.tets, C.X, C.tets)
+    R2 = un.assemble(C.X, C.tets, A.X, A.tets)
+    D = (R1.B - R2.B.T).tocoo()
+    assert (np.abs(D.data).max() if D.nnz else 0.0) <= 1e-13 * np.abs(R1.B.data).max()
+    # column sums when the solid fills the fluid mesh's box: ∫ μ_j, the
+    # fluid mesh's lumped mass
+    mf = un.lumped_mass(C.X, C.tets)
+    np.testing.assert_allclose(np.asarray(R2.B.sum(axis=0)).ravel(), mf, rtol=1e-12)
+
+
+def test_affine_reproduction(un, w1):
+    """P1 fluid fields reproduce affine functions and ∫ λ_i u = Σ_l M_il u_l:
+    the consistent transfer returns u at the solid vertices."""
+    W, R = w1
+    co = (0.4, -1.1, 0.7, 2.3)
+    u = WU.linear_fields(W.Xf, co)
+    us = un.transfer_velocity(R, [u, 2 * u, -u], "consistent")
+    want = WU.linear_fields(W.X, co)
+    np.testing.assert_allclose(us[0], want, atol=1e-12)
+    np.testing.assert_allclose(us[1], 2 * want, atol=1e-12)
+
+
+def test_monte_carlo_entries(un):
+    """Entries of B for one solid tet against a small fluid mesh, by Monte
+    Carlo with a 5-sigma bound."""
+    rng = np.random.default_rng(21)
+    F = WU.warped_box("f", 2, 0.2, 0.3, rng)
+    S = np.array([[0.15, 0.2, 0.25], [0.8, 0.3, 0.2], [0.3, 0.85, 0.35], [0.35, 0.3, 0.9]])
+    R = un.assemble(F.X, F.tets, S, np.array([[0, 1, 2, 3]], dtype=np.int32))
+    B = R.B.toarray()
+    n = 400000
+    w = rng.dirichlet(np.ones(4), size=n)
+    pts = w @ S
+    vol = abs(np.linalg.det(S[1:] - S[0])) / 6
+    # fluid hats at the points: locate the containing fluid tet
+    acc = np.zeros((4, F.X.shape[0]))
+    sq = np.zeros((4, F.X.shape[0]))
+    found = np.zeros(n, dtype=bool)
+    for t in F.tets:
+        A = np.ones((4, 4))
+        A[:, 1:] = F.X[t]
+        coef = np.linalg.inv(A)
+        mu = np.column_stack([np.ones(n), pts]) @ coef
+        inside = np.all(mu >= -1e-14, axis=1) & ~found
+        found |= inside
+        for j in range(4):
+            contrib = w[inside] * mu[inside, j][:, None]
+            acc[:, t[j]] += contrib.sum(axis=0)
+            sq[:, t[j]] += (contrib ** 2).sum(axis=0)
+    assert found.all()
+    est = vol * acc / n
+    sd = vol * np.sqrt(np.maximum(sq / n - (acc / n) ** 2, 0) / n)
+    big = B > 1e-4          # entries the samples resolve: a 5-sigma bound
+    assert big.sum() > 20
+    assert np.all(np.abs(est - B)[big] <= 5 * sd[big])
+    # entries of tiny pieces (few or no samples): an absolute bound
+    assert np.all(np.abs(est - B)[~big] <= 3e-5)
+
+
+def test_dual_row_sums_and_reproduction(un, w1):
+    W, _ = w1
+    R = un.assemble(W.Xf, W.tets_f, W.X, W.tets, dual=True)
+    m = un.lumped_mass(W.X, W.tets)
+    np.testing.assert_allclose(np.asarray(R.B.sum(axis=1)).ravel(), m, rtol=1e-12)
+    co = (-0.3, 0.9, 1.4, -0.6)
+    us = un.transfer_velocity(R, [WU.linear_fields(W.Xf, co)], "lumped")
+    np.testing.assert_allclose(us[0], WU.linear_fields(W.X, co), atol=1e-11)
