@@ -64,7 +64,7 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="73607bea0b4cf847c296d77e256acf3ed2dd716d25d4fec7f575d116dbe865b8",
+CLIP_TRAFFIC = dict(sources_sha256="3f6d7d36f53611e8d0b2efea826040d74484b363a1539c9cbb17b0989b08cc5c",
                     bytes_mixed=35620465920)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
@@ -196,6 +196,84 @@ def planar_leg(dev, steps, warmup, with_cpu):
         out["cpu_oracle"] = dict(value=n_tri / sec, seconds=sec, kind="oracle",
                                  cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                                  sample="the whole mesh, one step")
+    return out
+
+
+class UStep:
+    """One pass over the unstructured coupling (P1 tetrahedral fluid mesh):
+    reassembly against the kept fluid tree, consistent velocity transfer,
+    force transfer and the fluid/solid cotangents of both adjoints (the
+    shape derivative is not defined for this background)."""
+
+    def __init__(self, W, X, T, Xf, Tf, u_f, f_s, precision):
+        import torch
+        from paper_1810_13046_amd import Coupling
+        self.c = Coupling(None, X, T, precision=precision, consistent=True, fluid_mesh=(Xf, Tf))
+        dt = self.c.dtype
+        self.X = X
+        self.u = [u.to(dt).contiguous() for u in u_f]
+        self.f_s = f_s.to(dt).contiguous()
+        self.us = torch.empty((3, X.shape[0]), dtype=dt, device=X.device)
+        self.ff = [torch.zeros_like(u) for u in self.u]
+        self.g_uf = [torch.zeros_like(u) for u in self.u]
+        self.g_fs = torch.zeros_like(self.f_s)
+
+    def run(self):
+        c = self.c
+        c.reassemble(self.X)
+        c.velocity(self.u, mass="consistent", rtol=1e-10, maxit=500, out=self.us)
+        c.force(self.f_s, self.ff, alpha=1.0)
+        c.velocity_vjp(self.us, mass="consistent", g_uf=self.g_uf, rtol=1e-10, maxit=500)
+        c.force_vjp(self.u, alpha=1.0, g_fs=self.g_fs)
+
+
+def unstructured_oracle_rate(W, n_sample):
+    """The oracle's assembly (candidate search, clipping, integration, B) on
+    the first n_sample solid tets of the same meshes: solid tets/s."""
+    from oracle import unstructured as un
+    un.build(force=False)
+    t0 = time.perf_counter()
+    un.assemble(W.Xf, W.tets_f, W.X, W.tets[:n_sample])
+    return n_sample / (time.perf_counter() - t0)
+
+
+def unstructured_leg(dev, steps, warmup, with_cpu):
+    import torch
+    import workloads as wl
+    W = wl.unstructured.workload_u(3)
+    X = torch.as_tensor(W.X, device=dev).contiguous()
+    T = torch.as_tensor(W.tets, device=dev).contiguous()
+    Xf = torch.as_tensor(W.Xf, device=dev).contiguous()
+    Tf = torch.as_tensor(W.tets_f, device=dev).contiguous()
+    u_f = [torch.as_tensor(u, device=dev).contiguous() for u in W.u_f()]
+    f_s = torch.as_tensor(W.f_s(), device=dev).contiguous()
+    n_tet = W.tets.shape[0]
+    out = dict(workload=W.name, n_tet=int(n_tet), n_vert=int(W.X.shape[0]),
+               fluid_tets=int(W.tets_f.shape[0]), fluid_vertices=int(W.Xf.shape[0]),
+               unit="solid tets/s (reassembly + consistent velocity + force + adjoint applies)")
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] unstructured {prec} step")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = UStep(W, X, T, Xf, Tf, u_f, f_s, prec)
+        torch.cuda.synchronize()
+        first = (time.perf_counter() - t0) * 1e3
+        ms, wall = time_steps(st, steps, warmup)
+        prof = kernel_profile(st)
+        info = st.c.info()
+        out[prec] = dict(ms_per_step=ms, wall_ms_per_step=wall, value=n_tet / (ms * 1e-3),
+                         first_assembly_with_tree_ms=first,
+                         kernels_ms={k: v[1] for k, v in prof.items()},
+                         kernel_launches={k: v[0] for k, v in prof.items()},
+                         pairs=info["pairs"], pieces=info["pieces"], nnz=info["nnz"][0])
+        log(f"[bench] unstructured {prec} {ms:.3f} ms/step")
+        del st
+    if with_cpu:
+        n_sample = 3000
+        rate = unstructured_oracle_rate(W, n_sample)
+        out["cpu_oracle"] = dict(value=rate, kind="oracle", unit="solid tets/s (assembly only)",
+                                 cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                                 sample=f"assembly of the first {n_sample} solid tets")
     return out
 
 
@@ -377,6 +455,8 @@ def main():
                     help="one mixed-precision step and the applies only (for rocprofv3)")
     ap.add_argument("--planar-only", action="store_true",
                     help="only the planar leg (prints its JSON object; for rocprofv3)")
+    ap.add_argument("--unstructured-only", action="store_true",
+                    help="only the unstructured-background leg (prints its JSON object)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -402,6 +482,9 @@ def main():
     load_library()
     if args.planar_only:
         print(json.dumps(planar_leg(dev, args.steps, args.warmup, False)))
+        return
+    if args.unstructured_only:
+        print(json.dumps(unstructured_leg(dev, args.steps, args.warmup, False)))
         return
     if args.profile_run:
         args.skip_fp64 = True
@@ -464,6 +547,9 @@ def main():
     planar = None
     if not args.profile_run:
         planar = planar_leg(dev, max(args.steps, 10), args.warmup, not args.skip_cpu)
+    unstructured = None
+    if not args.profile_run:
+        unstructured = unstructured_leg(dev, args.steps, args.warmup, not args.skip_cpu)
 
     cpu = None
     if not args.skip_cpu:
@@ -505,6 +591,7 @@ def main():
         "dual_basis": dual,
         "fsi_picard": fsi,
         "planar": planar,
+        "unstructured": unstructured,
         "roofline": roof,
         "roofline_apply": roof_apply,
         "cpu_baseline": cpu,

@@ -153,6 +153,8 @@ typedef struct {
   int64_t dual;              /* 1 if B holds the dual-multiplier integrals */
   int64_t dim;               /* 3, or 2 for a planar coupling (n_tet then
                                 counts triangles, component 2 is empty) */
+  int64_t unstructured;      /* 1 for a tetrahedral fluid background
+                                (n_fluid[d] = its vertices, lattice = 0) */
 } ibvt_info;
 
 /*
@@ -209,6 +211,28 @@ typedef struct {
  */
 int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int precision,
                          uint32_t flags, hipStream_t stream, ibvt_coupling** out);
+
+/*
+ * assemble_coupling_unstructured — the coupling with an unstructured fluid
+ *   background: the fluid space is P1 on the tetrahedral mesh `fluid`
+ *   (device X (n_vert, 3), tets (n_tet, 4); copied), collocated, so one
+ *   B_ij = ∫ λ_i μ_j (solid vertex i, fluid vertex j; μ_j the fluid P1
+ *   hats) serves the three velocity components (Section 2.3: transfer
+ *   between unstructured and structured meshes, (I) a tree search for the
+ *   overlapping elements, (II)-(III) exact integration on the intersections
+ *   of the piecewise affine elements, (IV) assembly).  The tree over the
+ *   fluid tets is built once per handle; reassemble_coupling moves the
+ *   solid only.  The fluid mesh must cover the solid (partition of unity
+ *   of the μ_j); solid parts outside it get no contribution.
+ *   Fluid fields u_f[d] / f_f[d] are nodal arrays of the fluid mesh's
+ *   n_vert values.  IBVT_DUAL_BASIS and IBVT_BUILD_CONSISTENT_M as for
+ *   grids; IBVT_NO_PIECE_STORE has no effect.  The reverse-mode calls give
+ *   g_uf / g_fs; a non-NULL g_X is refused with IBVT_E_UNSUPPORTED before
+ *   any output is touched.  fsi_step returns IBVT_E_UNSUPPORTED.
+ *   Errors: IBVT_E_INVALID, IBVT_E_CAPACITY, IBVT_E_NOMEM, IBVT_E_HIP.
+ */
+int assemble_coupling_unstructured(const ibvt_mesh* fluid, const ibvt_mesh* solid, int precision,
+                                   uint32_t flags, hipStream_t stream, ibvt_coupling** out);
 
 /*
  * reassemble_coupling — rebuild the same coupling for moved vertices X
@@ -341,7 +365,7 @@ int ibvt_lattice_coords_2d(const ibvt_grid2d* grid, int comp, int axis, double* 
  * (n_vert, 3)): X_ref, u_hat0 in; v_f in/out; u_hat, w_s, f_fsi, f_tilde
  * out; f_prev in (f_fsi,0) and overwritten (workspace).
  * Errors: IBVT_E_INVALID (arguments, consistent mass not built, dual basis
- * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (planar coupling),
+ * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (planar or unstructured coupling),
  * IBVT_E_NOT_CONVERGED (max_iter reached; results of the last iteration are
  * written), or the status of a failed call or callback.
  */

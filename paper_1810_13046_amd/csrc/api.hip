@@ -111,12 +111,16 @@ void release_all(ibvt_coupling* c) {
                     &c->work,     &c->work2,     &c->zbuf,      &c->pool,      &c->pinfo,
                     &c->order,    &c->pscan,     &c->rowbox,    &c->rowcap,    &c->rowtmpoff,
                     &c->rowtmpcol, &c->rowtmpval, &c->tetgrad, &c->mcoef,
-                    &c->fsiX,     &c->fsinorm,   &c->fvol};
+                    &c->fsiX,     &c->fsinorm,   &c->fvol,      &c->fX,        &c->ftets,
+                    &c->frec,     &c->fbox,      &c->forder,    &c->ftree,     &c->ucoo};
   for (DevBuf* b : bufs) release(c, *b);
-  for (int d = 0; d < 3; ++d) {
+  // an unstructured coupling's components share B[0] and Bt[0]
+  const int own = c->unstructured ? 1 : 3;
+  for (int d = 0; d < own; ++d) {
     release_csr(c, c->B[d]);
     release_csr(c, c->Bt[d]);
   }
+  for (int d = own; d < 3; ++d) c->B[d] = c->Bt[d] = Csr{};
   release_csr(c, c->M);
 }
 
@@ -350,6 +354,60 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
   return finish_assembly(c, mesh->X, mesh->tets, stream, out);
 }
 
+int assemble_coupling_unstructured(const ibvt_mesh* fluid, const ibvt_mesh* mesh, int precision,
+                                   uint32_t flags, hipStream_t stream, ibvt_coupling** out) {
+  if (!out) return set_error(IBVT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!fluid || !mesh) return set_error(IBVT_E_INVALID, "mesh is NULL");
+  if (fluid->n_vert < 4 || fluid->n_tet < 1 || mesh->n_vert < 1 || mesh->n_tet < 0)
+    return set_error(IBVT_E_INVALID, "fluid mesh needs tets; solid mesh needs n_vert >= 1");
+  if (fluid->n_vert >= (int64_t(1) << 31) || fluid->n_tet >= (int64_t(1) << 30) ||
+      mesh->n_vert >= (int64_t(1) << 31) || mesh->n_tet >= (int64_t(1) << 31) / 3)
+    return set_error(IBVT_E_CAPACITY, "mesh too large for int32 indices");
+  if (bad_ptr(fluid->X) || bad_ptr(fluid->tets) || bad_ptr(mesh->X) ||
+      (mesh->n_tet > 0 && bad_ptr(mesh->tets)))
+    return set_error(IBVT_E_INVALID, "mesh X or tets is NULL");
+  if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
+    return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
+  if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE | IBVT_DUAL_BASIS))
+    return set_error(IBVT_E_INVALID, "unknown flags");
+  ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
+  if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
+  c->unstructured = true;
+  c->precision = precision;
+  c->flags = flags;
+  c->n_vert = mesh->n_vert;
+  c->n_tet = mesh->n_tet;
+  c->n_fvert = fluid->n_vert;
+  c->n_ftet = fluid->n_tet;
+  c->has_M = (flags & IBVT_BUILD_CONSISTENT_M) != 0;
+  c->store_pieces = false;
+  c->dual = (flags & IBVT_DUAL_BASIS) != 0;
+  for (int d = 0; d < 3; ++d) c->n_fluid[d] = fluid->n_vert;
+  int st = ensure(c, c->fX, size_t(3 * fluid->n_vert) * sizeof(double));
+  if (!st) st = ensure(c, c->ftets, size_t(4 * fluid->n_tet) * sizeof(int32_t));
+  if (!st) st = ensure(c, c->flags_dev, 64);
+  if (!st) st = ensure(c, c->counters, kCntSlots * sizeof(unsigned long long));
+  if (!st)
+    st = hip_check(hipMemcpyAsync(c->fX.p, fluid->X, size_t(3 * fluid->n_vert) * sizeof(double),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "copy fluid X");
+  if (!st)
+    st = hip_check(hipMemcpyAsync(c->ftets.p, fluid->tets,
+                                  size_t(4 * fluid->n_tet) * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "copy fluid tets");
+  if (st) {
+    std::string keep_msg = g_last_error;
+    (void)hipStreamSynchronize(stream);
+    release_all(c);
+    delete c;
+    g_last_error = keep_msg;
+    return st;
+  }
+  return finish_assembly(c, mesh->X, mesh->tets, stream, out);
+}
+
 int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int precision,
                          uint32_t flags, hipStream_t stream, ibvt_coupling** out) {
   if (!out) return set_error(IBVT_E_INVALID, "out is NULL");
@@ -451,6 +509,8 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
     return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
   if (c->dual && mass != IBVT_LUMPED)
     return set_error(IBVT_E_INVALID, "the dual basis has a diagonal S: use IBVT_LUMPED");
+  if (g_X && c->unstructured)
+    return set_error(IBVT_E_UNSUPPORTED, "no shape derivative for an unstructured background");
   if (g_X && (!u_f || !u_s)) return set_error(IBVT_E_INVALID, "g_X needs u_f and u_s");
   if (g_X)
     for (int d = 0; d < c->ncomp; ++d)
@@ -485,6 +545,8 @@ int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* 
   if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
   for (int d = 0; d < c->ncomp; ++d)
     if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
+  if (g_X && c->unstructured)
+    return set_error(IBVT_E_UNSUPPORTED, "no shape derivative for an unstructured background");
   if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
   if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
   int st;
@@ -529,6 +591,7 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->cut_points = c->stats.cut_points;
   info->dual = c->dual ? 1 : 0;
   info->dim = c->dim;
+  info->unstructured = c->unstructured ? 1 : 0;
   return IBVT_OK;
 }
 

@@ -1044,20 +1044,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     if ((st = transpose_one<T>(c, d, s))) return st;
   }
   // masses
-  {
-    ProfScope ps("masses", s);
-  k_lumped<T><<<blocks_for(n_v, 256), 256, 0, s>>>(n_v, c->vt_ptr.as<int64_t>(),
-                                                   c->vt_tet.as<int32_t>(), c->tetvol.as<double>(),
-                                                   c->mlump.as<double>(), c->minv.as<T>());
-  if (c->has_M) {
-    k_mass_values<<<blocks_for(n_v * kWave, 256), 256, 0, s>>>(
-        n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-        c->tetvol.as<double>(), c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>(),
-        c->M.val.as<double>(), c->precision == IBVT_FP32_MIXED ? c->Mval32.as<float>() : nullptr,
-        c->Mdiag_inv.as<double>());
-  }
-  }
-  if ((st = hip_check(hipGetLastError(), "mass launch"))) return st;
+  if ((st = solid_masses(c, s))) return st;
   unsigned long long cnt[kCntSlots];
   if ((st = read_back(c, cnt, counters, sizeof(cnt), s))) return st;
   c->stats.pairs = n_pairs;
@@ -1080,6 +1067,27 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
 }
 
 }  // namespace
+
+int solid_masses(ibvt_coupling* c, hipStream_t s) {
+  const int64_t n_v = c->n_vert;
+  ProfScope ps("masses", s);
+  if (c->precision == IBVT_FP32_MIXED)
+    k_lumped<float><<<blocks_for(n_v, 256), 256, 0, s>>>(
+        n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tetvol.as<double>(),
+        c->mlump.as<double>(), c->minv.as<float>());
+  else
+    k_lumped<double><<<blocks_for(n_v, 256), 256, 0, s>>>(
+        n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tetvol.as<double>(),
+        c->mlump.as<double>(), c->minv.as<double>());
+  if (c->has_M) {
+    k_mass_values<<<blocks_for(n_v * kWave, 256), 256, 0, s>>>(
+        n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+        c->tetvol.as<double>(), c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>(),
+        c->M.val.as<double>(), c->precision == IBVT_FP32_MIXED ? c->Mval32.as<float>() : nullptr,
+        c->Mdiag_inv.as<double>());
+  }
+  return hip_check(hipGetLastError(), "mass launch");
+}
 
 int build_topology(ibvt_coupling* c, hipStream_t s) {
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
@@ -1145,6 +1153,7 @@ int build_topology(ibvt_coupling* c, hipStream_t s) {
 
 int assemble_all(ibvt_coupling* c, hipStream_t s) {
   if (c->dim == 2) return assemble_all_2d(c, s);
+  if (c->unstructured) return assemble_all_unstructured(c, s);
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
   int st;
   int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));

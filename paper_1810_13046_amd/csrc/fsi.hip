@@ -227,7 +227,8 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
              hipStream_t stream, ibvt_fsi_report* report) {
   if (report) *report = ibvt_fsi_report{};
   if (!c || !cfg || !buf || !solid || !fluid) return set_error(IBVT_E_INVALID, "NULL argument");
-  if (c->dim != 3) return set_error(IBVT_E_UNSUPPORTED, "fsi_step drives 3D couplings only");
+  if (c->dim != 3 || c->unstructured)
+    return set_error(IBVT_E_UNSUPPORTED, "fsi_step drives couplings with a 3D grid only");
   if (!buf->X_ref || !buf->u_hat0 || !buf->u_hat || !buf->w_s || !buf->f_fsi || !buf->f_prev)
     return set_error(IBVT_E_INVALID, "NULL solid buffer");
   for (int d = 0; d < 3; ++d)

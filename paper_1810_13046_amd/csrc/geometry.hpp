@@ -96,18 +96,22 @@ struct ClipCount {
   uint32_t cuts = 0;
 };
 
-// Keep the half-space sgn·(x_a − c) >= 0.  `live` is the mask of used
-// slots, all below NS.  Returns false if the fixed capacity or a walk bound
-// is exceeded.  The distance and adjacency passes run over all NS slots
+// Keep the half-space dist(v) >= 0, dist being the signed distance of the
+// point in slot v to the plane; a cut point is placed by interpolation and
+// then passed to place(w) (which moves it exactly onto an axis plane, or
+// does nothing for a general plane).  `live` is the mask of used slots, all
+// below NS.  Returns false if the fixed capacity or a walk bound is
+// exceeded.  The distance and adjacency passes run over all NS slots
 // (unused ones masked), so their reads are independent of each other.
-template <int NS = kMaxV>
-__host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int a, double c,
-                                          double sgn, ClipCount* cc = nullptr) {
+template <int NS, typename Dist, typename Place>
+__host__ __device__ __forceinline__ bool poly_clip_by(const PolyView& P, uint32_t& live,
+                                                      Dist&& dist, Place&& place,
+                                                      ClipCount* cc) {
   if (cc) cc->dist += uint32_t(__builtin_popcount(live));
   uint32_t out = 0;
 #pragma unroll
   for (int v = 0; v < NS; ++v) {
-    const double s = sgn * (P.co(v, a) - c);
+    const double s = dist(v);
     if (((live >> v) & 1u) && s < 0.0) out |= 1u << v;
   }
   if (!out) return true;
@@ -128,14 +132,14 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
   for (uint32_t m = out & adj; m; m &= m - 1) {
     const int u = ctz32(m);
     const double ux = P.x(u), uy = P.y(u), uz = P.z(u);
-    const double su = sgn * (P.co(u, a) - c);
+    const double su = dist(u);
     const uint32_t unb = P.nb(u);
     bool first = true;
     for (int k = 0; k < 3; ++k) {
       const int v = nb_get(unb, k);
       if (!((in >> v) & 1u)) continue;
       const double vx = P.x(v), vy = P.y(v), vz = P.z(v);
-      const double sv = sgn * (P.co(v, a) - c);
+      const double sv = dist(v);
       const double t = sv / (sv - su);
       int w;
       if (first) {
@@ -151,7 +155,7 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
       P.x(w) = vx + t * (ux - vx);
       P.y(w) = vy + t * (uy - vy);
       P.z(w) = vz + t * (uz - vz);
-      P.co(w, a) = c;
+      place(w);
       P.nb(w) = nb_pack(v, v, v);
       newm |= 1u << w;
     }
@@ -176,6 +180,16 @@ __host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int
   live = in | newm;
   if (cc) cc->cuts += uint32_t(__builtin_popcount(newm));
   return true;
+}
+
+// Keep the half-space sgn·(x_a − c) >= 0 (an axis plane; cut points are
+// set exactly onto it).
+template <int NS = kMaxV>
+__host__ __device__ inline bool poly_clip(const PolyView& P, uint32_t& live, int a, double c,
+                                          double sgn, ClipCount* cc = nullptr) {
+  return poly_clip_by<NS>(
+      P, live, [&](int v) { return sgn * (P.co(v, a) - c); }, [&](int w) { P.co(w, a) = c; },
+      cc);
 }
 
 // Clip by the six planes of the box [lo, hi].  mn/mx bound the original

@@ -74,6 +74,15 @@ struct ibvt_coupling {
   uint32_t flags = 0;
   int dim = 3;    // 3: tetrahedra in a 3D grid; 2: triangles in a planar grid
   int ncomp = 3;  // velocity components (= dim)
+  bool unstructured = false;  // P1 tetrahedral fluid mesh instead of a grid: one B,
+                              // shared by the three components (B[1], B[2] alias B[0])
+  int64_t n_fvert = 0, n_ftet = 0;  // fluid mesh sizes (unstructured)
+  ibvt::DevBuf fX, ftets;    // fluid mesh copies (unstructured)
+  ibvt::DevBuf frec, fbox;   // fluid tet records (vertex 0, ∇μ) and double boxes
+  ibvt::DevBuf forder;       // fluid tets in Morton order
+  ibvt::DevBuf ftree;        // float boxes of the implicit tree (8 per node)
+  int64_t ftree_leaves = 0;  // leaves of the tree (power of two)
+  ibvt::DevBuf ucoo;         // sort scratch of the unstructured assembly
   int64_t n_vert = 0, n_tet = 0;  // n_tet counts the elements (triangles when dim = 2)
   int32_t n_cells[3] = {0, 0, 0};
   std::vector<double> lat_host[9];
@@ -160,6 +169,13 @@ int build_topology(ibvt_coupling* c, hipStream_t s);  // dim + 1 vertices per el
 int assemble_all(ibvt_coupling* c, hipStream_t s);    // dispatches on dim
 int read_back(ibvt_coupling* c, void* host, const void* dev, size_t bytes, hipStream_t s);
 int check_flags(ibvt_coupling* c, hipStream_t s);
+// lumped (and, when built, consistent) mass of the solid tets from tetvol
+int solid_masses(ibvt_coupling* c, hipStream_t s);
+
+// unstructured.hip: P1 tetrahedral fluid background (tree search + general
+// tet ∩ tet clipping); the fluid tree is built once per handle
+int build_fluid_tree(ibvt_coupling* c, hipStream_t s);
+int assemble_all_unstructured(ibvt_coupling* c, hipStream_t s);
 
 // assemble2d.hip: the planar coupling (Q1 quadrilateral lattice x P1 triangles)
 int assemble_all_2d(ibvt_coupling* c, hipStream_t s);

@@ -1,0 +1,587 @@
+// Coupling with an unstructured fluid background: a P1 tetrahedral fluid
+// mesh against the P1 tetrahedral solid mesh.  Section 2.3 builds the
+// transfer between unstructured and structured meshes in four steps: (I) a
+// tree search for the overlapping elements, (II)-(III) integration of the
+// products of the two element bases on their intersections (piecewise
+// affine meshes), (IV) assembly of the mortar matrices.  The fluid space
+// is P1 on the fluid tets and collocated, so one B serves the three
+// velocity components.
+//
+//  k_tet_rec        per tet of either mesh: double bounding box and record
+//                   (vertices, ∇ of the four hats, determinant); a hat is
+//                   λ_k(x) = δ_k0 + ∇λ_k·(x − V0).
+//  k_box_partials / k_box_final
+//                   bounding box of the fluid mesh (fixed-order reduction).
+//  k_morton         30-bit Morton code of each fluid box centre; radix sort.
+//  k_tree_leaves / k_tree_level
+//                   an implicit binary tree over the sorted fluid tets
+//                   (heap layout, a power of two of leaves): leaf boxes, then
+//                   one launch per level up to the root (union of the two
+//                   children; float boxes rounded outward, so every box
+//                   contains its double one).  Built once per handle: the
+//                   fluid mesh does not move.
+//  k_search<FILL>   per solid tet: depth-first traversal with an explicit
+//                   stack; leaves compared with the exact double boxes;
+//                   count pass, prefix sum, fill pass (traversal order).
+//  k_pairs_u<T>     one lane per (solid tet, fluid tet) pair: the solid tet
+//                   clipped by the fluid tet's four half-spaces μ_k >= 0
+//                   (vertex graph in LDS, general planes), fanned into
+//                   sub-tetrahedra, ∫ λ_i μ_j integrated exactly on each
+//                   (the product of two affine factors:
+//                   ∫_τ f g = |τ|/20 (Σ_v f_v g_v + Σ_v f_v Σ_v g_v)).
+//  k_coo / sort / k_runs
+//                   the 16 entries of every kept pair keyed by (solid
+//                   vertex, fluid vertex), stable radix sort, one lane per
+//                   run of equal keys sums it in order -> CSR rows of B
+//                   (deterministic).
+#include <hipcub/hipcub.hpp>
+
+#include "internal.hpp"
+#include "tetpair.hpp"
+
+#include <cfloat>
+
+namespace ibvt {
+
+namespace {
+
+constexpr int kTreeStack = 64;
+
+inline unsigned blocks_for(int64_t n, int threads) {
+  return unsigned(ceil_div(n > 0 ? n : 1, threads));
+}
+
+// Per tet: box (mn, mx; 8 doubles with padding), record, volume (solid
+// mesh only: vol != null); flags non-finite coordinates and bad indices.
+__global__ void k_tet_rec(int64_t n_t, int64_t n_v, const double* __restrict__ X,
+                          const int32_t* __restrict__ tets, double* __restrict__ box,
+                          double* __restrict__ rec, double* __restrict__ vol, unsigned* flags) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_t) return;
+  TetGeom G;
+  bool ok = true, bad_index = false;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t v = tets[4 * t + k];
+    if (v < 0 || v >= n_v) {
+      bad_index = true;
+      ok = false;
+      break;
+    }
+    for (int e = 0; e < 3; ++e) {
+      G.V[k][e] = X[3 * v + e];
+      ok &= isfinite(G.V[k][e]);
+    }
+  }
+  if (!ok) {
+    atomicOr(flags, bad_index ? kFlagValence : kFlagNonFinite);
+    for (int k = 0; k < 8; ++k) box[8 * t + k] = 0.0;
+    for (int k = 0; k < kURec; ++k) rec[kURec * t + k] = 0.0;
+    if (vol) vol[t] = 0.0;
+    return;
+  }
+  tet_geom(G);
+  double b[8] = {G.mn[0], G.mn[1], G.mn[2], 0.0, G.mx[0], G.mx[1], G.mx[2], 0.0};
+  store_row<8>(box + 8 * t, b);
+  double r[kURec];
+  for (int k = 0; k < 4; ++k)
+    for (int e = 0; e < 3; ++e) {
+      r[3 * k + e] = G.V[k][e];
+      r[12 + 3 * k + e] = G.g[k][e];
+    }
+  r[24] = G.det;
+  r[25] = r[26] = r[27] = 0.0;
+  store_row<kURec>(rec + kURec * t, r);
+  if (vol) vol[t] = fabs(G.det) / 6.0;
+}
+
+// Bounding box of all fluid boxes: per-block partials, then one block.
+__global__ __launch_bounds__(256) void k_box_partials(int64_t n, const double* __restrict__ box,
+                                                      double* __restrict__ part) {
+  __shared__ double red[6][256 / kWave];
+  double m[6] = {DBL_MAX, DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x)
+    for (int e = 0; e < 3; ++e) {
+      m[e] = fmin(m[e], box[8 * t + e]);
+      m[3 + e] = fmax(m[3 + e], box[8 * t + 4 + e]);
+    }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int e = 0; e < 3; ++e) {
+      m[e] = fmin(m[e], __shfl_xor(m[e], o, kWave));
+      m[3 + e] = fmax(m[3 + e], __shfl_xor(m[3 + e], o, kWave));
+    }
+  if (lane_id() == 0)
+    for (int e = 0; e < 6; ++e) red[e][threadIdx.x / kWave] = m[e];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = red[threadIdx.x][0];
+    for (int w = 1; w < 256 / kWave; ++w)
+      v = threadIdx.x < 3 ? fmin(v, red[threadIdx.x][w]) : fmax(v, red[threadIdx.x][w]);
+    part[6 * blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+__global__ void k_box_final(int nb, const double* __restrict__ part, double* __restrict__ bb) {
+  if (threadIdx.x >= 6) return;
+  double v = part[threadIdx.x];
+  for (int b = 1; b < nb; ++b)
+    v = threadIdx.x < 3 ? fmin(v, part[6 * b + threadIdx.x]) : fmax(v, part[6 * b + threadIdx.x]);
+  bb[threadIdx.x] = v;
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__global__ void k_morton(int64_t n, const double* __restrict__ box, const double* __restrict__ bb,
+                         uint32_t* __restrict__ code, int32_t* __restrict__ idx) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  uint32_t q[3];
+  for (int e = 0; e < 3; ++e) {
+    const double c = 0.5 * (box[8 * t + e] + box[8 * t + 4 + e]);
+    const double ext = bb[3 + e] - bb[e];
+    const double u = ext > 0.0 ? (c - bb[e]) / ext : 0.0;
+    q[e] = uint32_t(fmin(fmax(u * 1024.0, 0.0), 1023.0));
+  }
+  code[t] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+  idx[t] = int32_t(t);
+}
+
+// Leaves of the implicit tree (node P - 1 + i): the box of the i-th fluid
+// tet in Morton order, rounded outward to float; empty beyond n.
+__global__ void k_tree_leaves(int64_t n, int64_t P, const int32_t* __restrict__ order,
+                              const double* __restrict__ box, float* __restrict__ tree) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  float b[8];
+  if (i < n) {
+    const int64_t t = order[i];
+    for (int e = 0; e < 3; ++e) {
+      b[e] = __double2float_rd(box[8 * t + e]);
+      b[4 + e] = __double2float_ru(box[8 * t + 4 + e]);
+    }
+  } else {
+    for (int e = 0; e < 3; ++e) {
+      b[e] = FLT_MAX;
+      b[4 + e] = -FLT_MAX;
+    }
+  }
+  b[3] = b[7] = 0.0f;
+  store_row<8>(tree + 8 * (P - 1 + i), b);
+}
+
+// Nodes [first, first + count) of one level: union of the children.
+__global__ void k_tree_level(int64_t first, int64_t count, float* __restrict__ tree) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const int64_t node = first + k;
+  float a[8], b[8];
+  load_row<8>(tree + 8 * (2 * node + 1), a);
+  load_row<8>(tree + 8 * (2 * node + 2), b);
+  for (int e = 0; e < 3; ++e) {
+    a[e] = fminf(a[e], b[e]);
+    a[4 + e] = fmaxf(a[4 + e], b[4 + e]);
+  }
+  store_row<8>(tree + 8 * node, a);
+}
+
+__device__ __forceinline__ bool boxes_meet(const double mn[3], const double mx[3],
+                                           const float* __restrict__ b) {
+  return mx[0] >= double(b[0]) && mn[0] <= double(b[4]) && mx[1] >= double(b[1]) &&
+         mn[1] <= double(b[5]) && mx[2] >= double(b[2]) && mn[2] <= double(b[6]);
+}
+
+// Tree search per solid tet.  FILL = false: count the fluid tets whose
+// closed double box meets the solid tet's; FILL = true: write them at
+// off[s] in traversal (Morton) order.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_search(int64_t n_s, const double* __restrict__ sbox,
+                                                int64_t P, int64_t n_f,
+                                                const float* __restrict__ tree,
+                                                const int32_t* __restrict__ order,
+                                                const double* __restrict__ fbox,
+                                                int64_t* __restrict__ cnt,
+                                                const int64_t* __restrict__ off,
+                                                int32_t* __restrict__ pf, unsigned* flags) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n_s) return;
+  double mn[3], mx[3];
+  for (int e = 0; e < 3; ++e) {
+    mn[e] = sbox[8 * s + e];
+    mx[e] = sbox[8 * s + 4 + e];
+  }
+  int64_t stack[kTreeStack];
+  int top = 0;
+  int64_t found = 0;
+  int64_t pos = FILL ? off[s] : 0;
+  if (boxes_meet(mn, mx, tree)) stack[top++] = 0;
+  while (top > 0) {
+    const int64_t node = stack[--top];
+    if (node >= P - 1) {
+      const int64_t i = node - (P - 1);
+      if (i >= n_f) continue;
+      const int64_t t = order[i];
+      const double* fb = fbox + 8 * t;
+      if (mx[0] >= fb[0] && mn[0] <= fb[4] && mx[1] >= fb[1] && mn[1] <= fb[5] &&
+          mx[2] >= fb[2] && mn[2] <= fb[6]) {
+        if (FILL) pf[pos++] = int32_t(t);
+        ++found;
+      }
+      continue;
+    }
+    const int64_t l = 2 * node + 1, r = 2 * node + 2;
+    const bool gl = boxes_meet(mn, mx, tree + 8 * l), gr = boxes_meet(mn, mx, tree + 8 * r);
+    if (top + 2 > kTreeStack) {
+      atomicOr(flags, kFlagCapacity);
+      return;
+    }
+    if (gr) stack[top++] = r;
+    if (gl) stack[top++] = l;
+  }
+  if (!FILL) cnt[s] = found;
+}
+
+// Owner solid tet of pair p: the last s with off[s] <= p.
+__device__ __forceinline__ int64_t pair_owner(int64_t p, int64_t n_s,
+                                              const int64_t* __restrict__ off) {
+  int64_t lo = 0, hi = n_s;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= p) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One lane per pair: the solid tet clipped by the fluid tet's four
+// half-spaces μ_k >= 0, fanned, and ∫ λ_i μ_j integrated exactly on each
+// sub-tetrahedron; vals[pair][i*4 + j] (dual: 5 b_i − Σ_k b_k), keep =
+// piece volume > drop_rel |T|.  Arithmetic in double (coordinates relative
+// to the solid tet's vertex 0); values stored as T.
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_pairs_u(
+    int64_t n_pairs, int64_t n_s, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ pf, const double* __restrict__ srec,
+    const double* __restrict__ frec, double drop_rel, int dual, uint8_t* __restrict__ keep,
+    T* __restrict__ vals, unsigned* flags, unsigned long long* counters) {
+  __shared__ double sx[kUSlots * kWave], sy[kUSlots * kWave], sz[kUSlots * kWave];
+  __shared__ uint32_t snb[kUSlots * kWave];
+  const int lane = threadIdx.x;
+  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << kUSlots) - 1u};
+  const int64_t p = int64_t(blockIdx.x) * kWave + lane;
+  bool kept = false, dropped = false, fail = false;
+  if (p < n_pairs) {
+    const int64_t s = pair_owner(p, n_s, off);
+    const int64_t f = pf[p];
+    double rs[kURec], rf[kURec];
+    load_row<kURec>(srec + kURec * s, rs);
+    load_row<kURec>(frec + kURec * f, rf);
+    double acc[16];
+    double vol = 0.0;
+    fail = !tet_pair_values(P, rs, rf, acc, vol);
+    kept = !fail && vol > drop_rel * fabs(rs[24]) / 6.0;
+    dropped = !fail && !kept && vol > 0.0;
+    if (kept && dual) {
+      for (int j = 0; j < 4; ++j) {
+        const double sj = acc[j] + acc[4 + j] + acc[8 + j] + acc[12 + j];
+        for (int i = 0; i < 4; ++i) acc[4 * i + j] = 5.0 * acc[4 * i + j] - sj;
+      }
+    }
+    T out[16];
+    for (int k = 0; k < 16; ++k) out[k] = kept ? T(acc[k]) : T(0);
+    store_row<16>(vals + 16 * p, out);
+    keep[p] = kept ? 1 : 0;
+  }
+  const uint64_t km = ballot64(kept), dm = ballot64(dropped), fm = ballot64(fail);
+  if (lane == 0) {
+    if (km) atomicAdd(&counters[kCntPieces], (unsigned long long)popc64(km));
+    if (dm) atomicAdd(&counters[kCntDropped], (unsigned long long)popc64(dm));
+    if (fm) atomicOr(flags, kFlagCapacity);
+  }
+}
+
+// Keys of the 16 entries of every pair (one lane per pair): (solid vertex
+// << 32) | fluid vertex for kept pairs, all ones otherwise; idx = entry.
+__global__ void k_coo(int64_t n_pairs, int64_t n_s, const int64_t* __restrict__ off,
+                      const int32_t* __restrict__ pf, const int32_t* __restrict__ tets_s,
+                      const int32_t* __restrict__ tets_f, const uint8_t* __restrict__ keep,
+                      uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const bool k = keep[p];
+  int32_t vs[4] = {0, 0, 0, 0}, vf[4] = {0, 0, 0, 0};
+  if (k) {
+    const int64_t s = pair_owner(p, n_s, off);
+    const int64_t f = pf[p];
+    for (int q = 0; q < 4; ++q) {
+      vs[q] = tets_s[4 * s + q];
+      vf[q] = tets_f[4 * f + q];
+    }
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int64_t e = 16 * p + 4 * i + j;
+      keys[e] = k ? ((uint64_t(uint32_t(vs[i])) << 32) | uint64_t(uint32_t(vf[j])))
+                  : ~uint64_t(0);
+      idx[e] = uint32_t(e);
+    }
+}
+
+// head[e] = 1 where a run of equal (valid) keys starts.
+__global__ void k_run_heads(int64_t n, const uint64_t* __restrict__ keys,
+                            int32_t* __restrict__ head) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint64_t k = keys[e];
+  head[e] = (k != ~uint64_t(0) && (e == 0 || keys[e - 1] != k)) ? 1 : 0;
+}
+
+// One lane per run: the run's values summed in sorted (= generation)
+// order; column and row of the entry.
+template <typename T>
+__global__ void k_run_sums(int64_t n, const uint64_t* __restrict__ keys,
+                           const uint32_t* __restrict__ idx, const int32_t* __restrict__ head,
+                           const int64_t* __restrict__ pos, const T* __restrict__ vals,
+                           int32_t* __restrict__ col, int32_t* __restrict__ row,
+                           T* __restrict__ val) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n || !head[e]) return;
+  const uint64_t k = keys[e];
+  double acc = 0.0;
+  for (int64_t q = e; q < n && keys[q] == k; ++q) acc += double(vals[idx[q]]);
+  const int64_t u = pos[e];
+  col[u] = int32_t(uint32_t(k & 0xffffffffu));
+  row[u] = int32_t(k >> 32);
+  val[u] = T(acc);
+}
+
+// rowptr[r] = first entry whose row is >= r (rows ascending).
+__global__ void k_row_ptr(int64_t n_rows, int64_t nnz, const int32_t* __restrict__ row,
+                          int64_t* __restrict__ rowptr) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r > n_rows) return;
+  int64_t lo = 0, hi = nnz;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (row[mid] < r) lo = mid + 1;
+    else hi = mid;
+  }
+  rowptr[r] = lo;
+}
+
+template <typename T>
+int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
+  const int64_t n_s = c->n_tet, n_v = c->n_vert;
+  unsigned* flags = c->flags_dev.as<unsigned>();
+  auto* counters = c->counters.as<unsigned long long>();
+  int st;
+  if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
+  if ((st = hip_check(hipMemsetAsync(counters, 0, kCntSlots * sizeof(unsigned long long), s),
+                      "memset")))
+    return st;
+  // (I) solid records and the tree search
+  {
+    ProfScope ps("tet_prep", s);
+    if (n_s > 0)
+      k_tet_rec<<<blocks_for(n_s, 256), 256, 0, s>>>(n_s, n_v, c->X.as<double>(),
+                                                     c->tets.as<int32_t>(), c->rowbox.as<double>(),
+                                                     c->tetrec.as<double>(), c->tetvol.as<double>(),
+                                                     flags);
+  }
+  {
+    ProfScope ps("tree_search", s);
+    if (n_s > 0)
+      k_search<false><<<blocks_for(n_s, 256), 256, 0, s>>>(
+          n_s, c->rowbox.as<double>(), c->ftree_leaves, c->n_ftet, c->ftree.as<float>(),
+          c->forder.as<int32_t>(), c->fbox.as<double>(), c->cnt.as<int64_t>(), nullptr, nullptr,
+          flags);
+  }
+  if ((st = hip_check(hipGetLastError(), "search launch"))) return st;
+  if ((st = scan_i64(c, c->cnt.as<int64_t>(), c->pair_off.as<int64_t>(), n_s, s))) return st;
+  if ((st = check_flags(c, s))) return st;
+  int64_t n_pairs = 0;
+  if ((st = read_back(c, &n_pairs, c->pair_off.as<int64_t>() + n_s, sizeof(int64_t), s)))
+    return st;
+  if (n_pairs >= (int64_t(1) << 31) / 16)
+    return set_error(IBVT_E_CAPACITY, "too many (solid tet, fluid tet) pairs");
+  c->n_pairs = n_pairs;
+  if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
+  if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 16 * sizeof(T)))) return st;
+  {
+    ProfScope ps("tree_search", s);
+    if (n_s > 0)
+      k_search<true><<<blocks_for(n_s, 256), 256, 0, s>>>(
+          n_s, c->rowbox.as<double>(), c->ftree_leaves, c->n_ftet, c->ftree.as<float>(),
+          c->forder.as<int32_t>(), c->fbox.as<double>(), nullptr, c->pair_off.as<int64_t>(),
+          c->owner.as<int32_t>(), flags);
+  }
+  // (II)-(III) clip and integrate every pair
+  if (n_pairs > 0) {
+    ProfScope ps("pairs_tet", s);
+    k_pairs_u<T><<<unsigned(ceil_div(n_pairs, kWave)), kWave, 0, s>>>(
+        n_pairs, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(), c->tetrec.as<double>(),
+        c->frec.as<double>(), 1e-14, c->dual ? 1 : 0, c->keep.as<uint8_t>(), c->pval.as<T>(),
+        flags, counters);
+  }
+  if ((st = hip_check(hipGetLastError(), "pairs launch"))) return st;
+  // (IV) B from the entries of the kept pairs: sort by (row, column), sum runs
+  const int64_t n_e = 16 * n_pairs;
+  size_t temp_bytes = 0;
+  if (n_e > 0 &&
+      (st = hip_check(hipcub::DeviceRadixSort::SortPairs(
+                          nullptr, temp_bytes, static_cast<const uint64_t*>(nullptr),
+                          static_cast<uint64_t*>(nullptr), static_cast<const uint32_t*>(nullptr),
+                          static_cast<uint32_t*>(nullptr), int(n_e), 0, 64, s),
+                      "sort size")))
+    return st;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t kb = al(size_t(n_e + 1) * 8), ib = al(size_t(n_e + 1) * 4);
+  const size_t hb = al(size_t(n_e + 1) * 4), pb = al(size_t(n_e + 2) * 8);
+  if ((st = ensure(c, c->ucoo, 2 * kb + 2 * ib + hb + pb + ib + al(temp_bytes) + 256))) return st;
+  char* base = c->ucoo.as<char>();
+  uint64_t* keys = reinterpret_cast<uint64_t*>(base);
+  uint64_t* skeys = reinterpret_cast<uint64_t*>(base + kb);
+  uint32_t* idx = reinterpret_cast<uint32_t*>(base + 2 * kb);
+  uint32_t* sidx = reinterpret_cast<uint32_t*>(base + 2 * kb + ib);
+  int32_t* head = reinterpret_cast<int32_t*>(base + 2 * kb + 2 * ib);
+  int64_t* pos = reinterpret_cast<int64_t*>(base + 2 * kb + 2 * ib + hb);
+  int32_t* rowid = reinterpret_cast<int32_t*>(base + 2 * kb + 2 * ib + hb + pb);
+  void* temp = base + 2 * kb + 3 * ib + hb + pb;
+  int64_t nnz = 0;
+  {
+    ProfScope ps("rows_sort", s);
+    if (n_e > 0) {
+      k_coo<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
+          n_pairs, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(), c->tets.as<int32_t>(),
+          c->ftets.as<int32_t>(), c->keep.as<uint8_t>(), keys, idx);
+      if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx,
+                                                             sidx, int(n_e), 0, 64, s),
+                          "entry sort")))
+        return st;
+      k_run_heads<<<blocks_for(n_e, 256), 256, 0, s>>>(n_e, skeys, head);
+      if ((st = scan_i32_to_i64(c, head, pos, n_e, s))) return st;
+      if ((st = read_back(c, &nnz, pos + n_e, sizeof(int64_t), s))) return st;
+    }
+  }
+  Csr& B = c->B[0];
+  B.nrows = n_v;
+  B.nnz = nnz;
+  if ((st = ensure(c, B.rowptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, B.col, size_t(nnz + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, B.val, size_t(nnz + 1) * sizeof(T)))) return st;
+  {
+    ProfScope ps("rows_gather", s);
+    if (n_e > 0)
+      k_run_sums<T><<<blocks_for(n_e, 256), 256, 0, s>>>(n_e, skeys, sidx, head, pos,
+                                                         c->pval.as<T>(), B.col.as<int32_t>(),
+                                                         rowid, B.val.as<T>());
+    k_row_ptr<<<blocks_for(n_v + 1, 256), 256, 0, s>>>(n_v, nnz, rowid, B.rowptr.as<int64_t>());
+  }
+  if ((st = hip_check(hipGetLastError(), "rows launch"))) return st;
+  {
+    ProfScope ps("transpose", s);
+    if ((st = transpose_one<T>(c, 0, s))) return st;
+  }
+  // the three velocity components share the fluid nodes: one B
+  c->B[1] = c->B[2] = c->B[0];
+  c->Bt[1] = c->Bt[2] = c->Bt[0];
+  if ((st = solid_masses(c, s))) return st;
+  unsigned long long cnt[kCntSlots];
+  if ((st = read_back(c, cnt, counters, sizeof(cnt), s))) return st;
+  c->stats.pairs = n_pairs;
+  c->stats.pieces = int64_t(cnt[kCntPieces]);
+  c->stats.dropped = int64_t(cnt[kCntDropped]);
+  c->stats.zero_tets = 0;
+  c->stats.subtets = 0;
+  c->stats.dist_evals = 0;
+  c->stats.cut_points = 0;
+  c->mom_valid = false;
+  c->stats.assemblies += 1;
+  return check_flags(c, s);
+}
+
+}  // namespace
+
+int build_fluid_tree(ibvt_coupling* c, hipStream_t s) {
+  const int64_t n_f = c->n_ftet;
+  int st;
+  if ((st = ensure(c, c->frec, size_t(n_f + 1) * kURec * sizeof(double)))) return st;
+  if ((st = ensure(c, c->fbox, size_t(n_f + 1) * 8 * sizeof(double)))) return st;
+  unsigned* flags = c->flags_dev.as<unsigned>();
+  if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
+  ProfScope ps("fluid_tree", s);
+  k_tet_rec<<<blocks_for(n_f, 256), 256, 0, s>>>(n_f, c->n_fvert, c->fX.as<double>(),
+                                                 c->ftets.as<int32_t>(), c->fbox.as<double>(),
+                                                 c->frec.as<double>(), nullptr, flags);
+  if ((st = hip_check(hipGetLastError(), "fluid record launch"))) return st;
+  if ((st = check_flags(c, s))) return st;
+  // bounding box of the fluid mesh
+  const int nbb = int(std::min<int64_t>(blocks_for(n_f, 256), 1024));
+  if ((st = ensure(c, c->ucoo, size_t(nbb + 2) * 6 * sizeof(double)))) return st;
+  double* part = c->ucoo.as<double>();
+  double* bb = part + 6 * nbb;
+  k_box_partials<<<nbb, 256, 0, s>>>(n_f, c->fbox.as<double>(), part);
+  k_box_final<<<1, 64, 0, s>>>(nbb, part, bb);
+  // Morton order
+  size_t temp_bytes = 0;
+  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(
+                          nullptr, temp_bytes, static_cast<const uint32_t*>(nullptr),
+                          static_cast<uint32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                          static_cast<int32_t*>(nullptr), int(n_f), 0, 30, s),
+                      "sort size")))
+    return st;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t cb = al(size_t(n_f + 1) * 4);
+  if ((st = ensure(c, c->pscan, 3 * cb + al(temp_bytes) + 256))) return st;
+  char* base = c->pscan.as<char>();
+  uint32_t* code = reinterpret_cast<uint32_t*>(base);
+  uint32_t* scode = reinterpret_cast<uint32_t*>(base + cb);
+  int32_t* idx = reinterpret_cast<int32_t*>(base + 2 * cb);
+  void* temp = base + 3 * cb;
+  if ((st = ensure(c, c->forder, size_t(n_f + 1) * sizeof(int32_t)))) return st;
+  k_morton<<<blocks_for(n_f, 256), 256, 0, s>>>(n_f, c->fbox.as<double>(), bb, code, idx);
+  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, code, scode, idx,
+                                                         c->forder.as<int32_t>(), int(n_f), 0, 30,
+                                                         s),
+                      "Morton sort")))
+    return st;
+  // implicit tree: P leaves (power of two), 2P - 1 nodes, levels bottom-up
+  int64_t P = 1;
+  while (P < n_f) P <<= 1;
+  if ((st = ensure(c, c->ftree, size_t(2 * P) * 8 * sizeof(float)))) return st;
+  k_tree_leaves<<<blocks_for(P, 256), 256, 0, s>>>(n_f, P, c->forder.as<int32_t>(),
+                                                   c->fbox.as<double>(), c->ftree.as<float>());
+  for (int64_t cnt = P / 2; cnt >= 1; cnt /= 2)
+    k_tree_level<<<blocks_for(cnt, 256), 256, 0, s>>>(cnt - 1, cnt, c->ftree.as<float>());
+  c->ftree_leaves = P;
+  return hip_check(hipGetLastError(), "tree launch");
+}
+
+int assemble_all_unstructured(ibvt_coupling* c, hipStream_t s) {
+  const int64_t n_s = c->n_tet, n_v = c->n_vert;
+  int st;
+  if (c->ftree_leaves == 0 && (st = build_fluid_tree(c, s))) return st;
+  if ((st = ensure(c, c->tetvol, size_t(n_s + 1) * sizeof(double)))) return st;
+  if ((st = ensure(c, c->tetrec, size_t(n_s + 1) * kURec * sizeof(double)))) return st;
+  if ((st = ensure(c, c->rowbox, size_t(n_s + 1) * 8 * sizeof(double)))) return st;
+  if ((st = ensure(c, c->cnt, size_t(n_s + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->pair_off, size_t(n_s + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->mark, size_t(c->n_fvert + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->cidx, size_t(c->n_fvert + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->mlump, size_t(n_v + 1) * sizeof(double)))) return st;
+  if (c->precision == IBVT_FP32_MIXED) {
+    if ((st = ensure(c, c->minv, size_t(n_v + 1) * sizeof(float)))) return st;
+    return assemble_u_typed<float>(c, s);
+  }
+  if ((st = ensure(c, c->minv, size_t(n_v + 1) * sizeof(double)))) return st;
+  return assemble_u_typed<double>(c, s);
+}
+
+}  // namespace ibvt

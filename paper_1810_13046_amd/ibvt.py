@@ -36,7 +36,7 @@ EXPORTED = [
     "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info", "coupling_export_csr",
     "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
     "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
-    "assemble_coupling_2d", "ibvt_lattice_coords_2d",
+    "assemble_coupling_2d", "ibvt_lattice_coords_2d", "assemble_coupling_unstructured",
 ]
 
 
@@ -79,7 +79,8 @@ class _Info(ctypes.Structure):
                 ("nnz_mass", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("assemblies", ctypes.c_int64), ("subtets", ctypes.c_int64),
                 ("piece_store", ctypes.c_int64), ("dist_evals", ctypes.c_int64),
-                ("cut_points", ctypes.c_int64), ("dual", ctypes.c_int64), ("dim", ctypes.c_int64)]
+                ("cut_points", ctypes.c_int64), ("dual", ctypes.c_int64), ("dim", ctypes.c_int64),
+                ("unstructured", ctypes.c_int64)]
 
 
 _lib = None
@@ -144,10 +145,12 @@ def load_library(path: str = LIB_PATH):
     lib.ibvt_fluid_lumped_volume.argtypes = [P(_Grid), ctypes.c_int, vp, vp]
     lib.assemble_coupling_2d.argtypes = [P(_Grid2d), P(_Mesh2d), ctypes.c_int, u32, vp, P(vp)]
     lib.ibvt_lattice_coords_2d.argtypes = [P(_Grid2d), ctypes.c_int, ctypes.c_int, vp, P(i64)]
+    lib.assemble_coupling_unstructured.argtypes = [P(_Mesh), P(_Mesh), ctypes.c_int, u32, vp, P(vp)]
     for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
-                 "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d"):
+                 "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d",
+                 "assemble_coupling_unstructured"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -259,16 +262,24 @@ class Coupling:
     Three face arrays, X (n_vert, 3) and tets (n_tet, 4) make a 3D coupling;
     two face arrays, X (n_vert, 2) and triangles (n_tri, 3) a planar one
     (assemble_coupling_2d), whose solid fields are (2, n_vert) and whose
-    fluid fields are 2 arrays of shape (n_y, n_x)."""
+    fluid fields are 2 arrays of shape (n_y, n_x).  With fluid_mesh =
+    (X_f, tets_f) (device tensors, a P1 tetrahedral fluid mesh) and faces =
+    None the background is unstructured (assemble_coupling_unstructured):
+    the fluid fields are 3 nodal arrays of the fluid mesh's vertices."""
 
     def __init__(self, faces, X, tets, precision: str = "fp64", consistent: bool = True,
-                 store_pieces: bool = True, dual: bool = False, stream=None):
+                 store_pieces: bool = True, dual: bool = False, stream=None, fluid_mesh=None):
         import torch
         lib = load_library()
         if precision not in ("fp64", "fp32"):
             raise ValueError("precision must be 'fp64' or 'fp32' (mixed)")
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.dual = bool(dual)
+        self.consistent = consistent
+        if fluid_mesh is not None:
+            self._init_unstructured(fluid_mesh, X, tets, precision, consistent, dual, stream)
+            return
         self.faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
         self.dim = len(self.faces)
         self.nc = self.dim
@@ -303,6 +314,33 @@ class Coupling:
                                for d in range(self.nc)]
         self.n_fluid = [int(np.prod(s)) for s in self.lattice_shapes]
 
+    def _init_unstructured(self, fluid_mesh, X, tets, precision, consistent, dual, stream):
+        import torch
+        Xf, tets_f = fluid_mesh
+        self.faces = None
+        self.dim = self.nc = 3
+        self.n_vert = int(X.shape[0])
+        self.n_tet = int(tets.shape[0])
+        if X.ndim != 2 or X.shape[1] != 3 or tets.ndim != 2 or tets.shape[1] != 4:
+            raise ValueError("solid: X (n_vert, 3) and tets (n_tet, 4)")
+        if Xf.ndim != 2 or Xf.shape[1] != 3 or tets_f.ndim != 2 or tets_f.shape[1] != 4:
+            raise ValueError("fluid mesh: X_f (n_vert, 3) and tets_f (n_tet, 4)")
+        mf, ms = _Mesh(), _Mesh()
+        mf.n_vert, mf.n_tet = int(Xf.shape[0]), int(tets_f.shape[0])
+        mf.X = _dev(Xf, torch.float64, 3 * mf.n_vert, "X_f")
+        mf.tets = _dev(tets_f, torch.int32, 4 * mf.n_tet, "tets_f")
+        ms.n_vert, ms.n_tet = self.n_vert, self.n_tet
+        ms.X = _dev(X, torch.float64, 3 * self.n_vert, "X")
+        ms.tets = _dev(tets, torch.int32, 4 * self.n_tet, "tets") if self.n_tet else None
+        flags = (BUILD_CONSISTENT_M if consistent else 0) | (DUAL_BASIS if dual else 0)
+        h = ctypes.c_void_p()
+        _check(_lib.assemble_coupling_unstructured(
+            ctypes.byref(mf), ctypes.byref(ms), FP64 if precision == "fp64" else FP32_MIXED,
+            flags, _stream(stream), ctypes.byref(h)), "assemble_coupling_unstructured")
+        self._h = h
+        self.lattice_shapes = [(mf.n_vert,)] * 3
+        self.n_fluid = [mf.n_vert] * 3
+
     # -- lifetime ---------------------------------------------------------
     def fsi_step(self, X_ref, u_hat0, v_f, solid, fluid, *, dt, alpha=1.0, eps_abs=0.0,
                  eps_rel=1e-8, max_iter=50, mass="lumped", force_density=False, cg_rtol=1e-10,
@@ -314,8 +352,8 @@ class Coupling:
         call's tensors and must enqueue their work on the current stream.
         Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
         import torch
-        if self.dim != 3:
-            raise IbvtError(7, "fsi_step", "the Picard driver takes 3D couplings only")
+        if self.dim != 3 or self.faces is None:
+            raise IbvtError(7, "fsi_step", "the Picard driver takes couplings with a 3D grid only")
         dt_ = self.dtype
         dev = X_ref.device
         n = self.n_vert
@@ -462,7 +500,7 @@ class Coupling:
                     nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies,
                     subtets=i.subtets, piece_store=bool(i.piece_store),
                     dist_evals=i.dist_evals, cut_points=i.cut_points, dual=bool(i.dual),
-                    dim=i.dim)
+                    dim=i.dim, unstructured=bool(i.unstructured))
 
     def export_csr(self, comp: int, transposed: bool = False):
         """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""

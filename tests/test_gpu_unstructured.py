@@ -1,0 +1,228 @@
+"""The coupling with an unstructured background (P1 tetrahedral fluid mesh x
+P1 solid tets) on the HIP path, through the C ABI, against the oracle
+(oracle/unstructured.py): B and B^T entry by entry, the candidate count of
+the tree search against the exact box test, transfers (lumped, consistent,
+load), dual multipliers, determinism and reassembly, the full-size case by
+sampled rows and exact affine reproduction, and error paths.  Tolerances:
+FP64 1e-12, FP32 1e-5 relative Frobenius."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as wl
+from tests.gpu_common import rel_fro, require_gpu, say, sparse_rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+WU = wl.unstructured
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+_cache = {}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def un():
+    from oracle import unstructured
+    unstructured.build(force=False)
+    return unstructured
+
+
+def ref(un, key, dual=False):
+    k = (key, dual)
+    if k not in _cache:
+        W = WU.workload_u(key)
+        _cache[k] = (W, un.assemble(W.Xf, W.tets_f, W.X, W.tets, dual=dual))
+    return _cache[k]
+
+
+def make(W, prec, dev, consistent=True, dual=False, X=None):
+    import torch
+    from paper_1810_13046_amd import Coupling
+    X = W.X if X is None else X
+    c = Coupling(None, to_dev(X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
+                 precision=prec, consistent=consistent, dual=dual,
+                 fluid_mesh=(to_dev(W.Xf, torch.float64, dev),
+                             to_dev(W.tets_f, torch.int32, dev)))
+    torch.cuda.synchronize()
+    return c
+
+
+def gpu_B(c):
+    rp, col, val = c.export_csr(0)
+    return sp.csr_matrix((val, col, rp), shape=(c.n_vert, c.n_fluid[0]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("key", [1, 2])
+def test_unstructured_B_matches_oracle(dev, un, key, prec):
+    W, R = ref(un, key)
+    say(f"[gpu] unstructured assemble {W.name} {prec}")
+    c = make(W, prec, dev)
+    info = c.info()
+    assert info["unstructured"] and info["n_fluid"] == [W.Xf.shape[0]] * 3
+    # the tree search returns exactly the pairs whose closed boxes meet
+    assert info["pairs"] == R.stats["pairs"]
+    assert abs(info["pieces"] - R.stats["pieces"]) <= 4
+    G = gpu_B(c)
+    fro, mx = sparse_rel(G, R.B)
+    say(f"  B: nnz {G.nnz} (oracle {R.B.nnz}) rel fro {fro:.2e} max {mx:.2e}")
+    assert fro <= TOL[prec] and (prec == "fp32" or mx <= TOL[prec])
+    for d in range(3):   # the components share B
+        rp, col, val = c.export_csr(d)
+        assert val.size == G.nnz
+    rp, col, val, rm = c.export_csr(0, transposed=True)
+    Bt = sp.csr_matrix((val, col, rp), shape=(rm.size, c.n_vert))
+    assert sparse_rel(Bt, R.B.T.tocsr()[rm])[0] <= TOL[prec]
+    c.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_unstructured_transfers_match_oracle(dev, un, prec):
+    import torch
+    W, R = ref(un, 2)
+    c = make(W, prec, dev)
+    dt = c.dtype
+    u_f = W.u_f()
+    ud = [to_dev(u, dt, dev) for u in u_f]
+    for mass in ("lumped", "consistent"):
+        say(f"[gpu] unstructured velocity {prec} {mass}")
+        us = c.velocity(ud, mass=mass, rtol=1e-13 if prec == "fp64" else 1e-6).cpu().numpy()
+        want = un.transfer_velocity(R, u_f, mass)
+        e = rel_fro(us, want)
+        say(f"  rel {e:.2e}")
+        assert e <= (TOL[prec] if mass == "lumped" else (1e-11 if prec == "fp64" else 1e-5))
+    f_s = W.f_s()
+    for load in (False, True):
+        say(f"[gpu] unstructured force load={load} {prec}")
+        base = np.random.default_rng(5).standard_normal(u_f.shape)
+        ff = [to_dev(b, dt, dev) for b in base]
+        c.force(to_dev(f_s, dt, dev), ff, alpha=0.8, load=load)
+        want = un.transfer_force(R, f_s, 0.8, load=load, base=base)
+        for d in range(3):
+            e = rel_fro(ff[d].cpu().numpy(), want[d])
+            assert e <= (TOL[prec] if not load else (1e-10 if prec == "fp64" else 1e-5)), (d, e)
+    # reverse mode: the fluid cotangent works, the shape derivative does not
+    from paper_1810_13046_amd import IbvtError
+    g_us = to_dev(W.f_s(), dt, dev)
+    g_uf = [torch.zeros_like(u) for u in ud]
+    c.velocity_vjp(g_us, u_f=ud, u_s=None, mass="lumped", g_uf=g_uf)
+    want = un.transfer_force(R, W.f_s() / un.lumped_mass(W.X, W.tets)[None, :], 1.0)
+    for d in range(3):
+        assert rel_fro(g_uf[d].cpu().numpy(), want[d]) <= TOL[prec]
+    g0 = [torch.zeros_like(u) for u in ud]
+    with pytest.raises(IbvtError) as e:
+        c.velocity_vjp(g_us, u_f=ud, u_s=g_us, mass="lumped", g_uf=g0,
+                       g_X=torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev))
+    assert e.value.name == "IBVT_E_UNSUPPORTED"
+    g_fs = torch.zeros_like(g_us)
+    with pytest.raises(IbvtError) as e:
+        c.force_vjp(ud, f_s=g_us, g_fs=g_fs,
+                    g_X=torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev))
+    assert e.value.name == "IBVT_E_UNSUPPORTED"
+    # refused before any output was touched
+    assert all(int(torch.count_nonzero(g)) == 0 for g in g0 + [g_fs])
+    c.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_unstructured_dual(dev, un, prec):
+    W, R = ref(un, 1, dual=True)
+    c = make(W, prec, dev, consistent=False, dual=True)
+    say(f"[gpu] unstructured dual {prec}")
+    assert sparse_rel(gpu_B(c), R.B)[0] <= TOL[prec]
+    co = (0.2, -0.7, 1.3, 0.5)
+    u = WU.linear_fields(W.Xf, co)
+    us = c.velocity([to_dev(u, c.dtype, dev)] * 3, mass="lumped").cpu().numpy()
+    assert np.max(np.abs(us - WU.linear_fields(W.X, co)[None, :])) <= (
+        1e-11 if prec == "fp64" else 1e-5)
+    c.free()
+
+
+def test_unstructured_determinism_and_reassembly(dev, un):
+    import torch
+    W, _ = ref(un, 1)
+    c1 = make(W, "fp64", dev)
+    c2 = make(W, "fp64", dev)
+    for a, b in zip(c1.export_csr(0), c2.export_csr(0)):
+        assert np.array_equal(a, b)
+    X1 = W.X + 4e-3 * np.sin(5.0 * W.X[:, [2, 0, 1]])
+    say("[gpu] unstructured reassemble")
+    c1.reassemble(to_dev(X1, torch.float64, dev))
+    R1 = un.assemble(W.Xf, W.tets_f, X1, W.tets)
+    fro, mx = sparse_rel(gpu_B(c1), R1.B)
+    assert fro <= 1e-12 and mx <= 1e-12
+    assert c1.info()["assemblies"] == 2
+    c1.free()
+    c2.free()
+
+
+def test_unstructured_full_size(dev, un):
+    """The 5.3M-tet warped fluid mesh with the 200k-tet beam: sampled rows of
+    B against the oracle (the rows' full vertex stars), and exact
+    reproduction of an affine field by the consistent transfer."""
+    import torch
+    W = WU.workload_u(3)
+    say(f"[gpu] unstructured full size: fluid {W.tets_f.shape[0]} tets, solid {W.tets.shape[0]}")
+    c = make(W, "fp64", dev)
+    G = gpu_B(c)
+    rng = np.random.default_rng(12)
+    verts = np.sort(rng.choice(W.X.shape[0], 24, replace=False))
+    star = np.nonzero(np.isin(W.tets, verts).any(axis=1))[0]
+    Rs = un.assemble(W.Xf, W.tets_f, W.X, W.tets[star])
+    fro, mx = sparse_rel(G[verts], Rs.B[verts])
+    say(f"  sampled rows rel fro {fro:.2e} max {mx:.2e}")
+    assert fro <= 1e-12 and mx <= 1e-12
+    co = (0.3, 1.1, -0.4, 0.9)
+    u = to_dev(WU.linear_fields(W.Xf, co), torch.float64, dev)
+    us, info = c.velocity([u, u, u], mass="consistent", rtol=1e-13, with_info=True)
+    err = np.max(np.abs(us.cpu().numpy() - WU.linear_fields(W.X, co)[None, :]))
+    say(f"  affine reproduction max error {err:.2e} ({info})")
+    assert err <= 1e-10
+    c.free()
+
+
+def test_unstructured_edge_cases(dev, un):
+    import torch
+    from paper_1810_13046_amd import Coupling, IbvtError
+    W, _ = ref(un, 1)
+    Xf = to_dev(W.Xf, torch.float64, dev)
+    Tf = to_dev(W.tets_f, torch.int32, dev)
+    # a solid tet partly outside the fluid mesh: only the inside part counts
+    say("[gpu] unstructured edge: solid leaving the fluid mesh")
+    S = np.array([[0.8, 0.5, 0.5], [1.2, 0.5, 0.5], [0.9, 0.8, 0.5], [0.9, 0.55, 0.8]])
+    T = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    c = Coupling(None, to_dev(S, torch.float64, dev), to_dev(T, torch.int32, dev),
+                 fluid_mesh=(Xf, Tf))
+    R = un.assemble(W.Xf, W.tets_f, S, T)
+    assert sparse_rel(gpu_B(c), R.B)[0] <= 1e-12
+    assert 0 < gpu_B(c).sum() < abs(np.linalg.det(S[1:] - S[0])) / 6
+    c.free()
+    say("[gpu] unstructured edge: empty solid mesh")
+    c = Coupling(None, to_dev(S, torch.float64, dev), torch.zeros((0, 4), dtype=torch.int32,
+                                                                  device=dev),
+                 fluid_mesh=(Xf, Tf))
+    assert c.info()["nnz"] == [0, 0, 0]
+    c.free()
+    say("[gpu] unstructured edge: bad indices and NaN")
+    bad = W.tets_f.copy()
+    bad[3, 2] = W.Xf.shape[0] + 5
+    with pytest.raises(IbvtError) as e:
+        Coupling(None, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
+                 fluid_mesh=(Xf, to_dev(bad, torch.int32, dev)))
+    assert e.value.name == "IBVT_E_INVALID"
+    Xn = W.Xf.copy()
+    Xn[7, 1] = np.nan
+    with pytest.raises(IbvtError) as e:
+        Coupling(None, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
+                 fluid_mesh=(to_dev(Xn, torch.float64, dev), Tf))
+    assert e.value.name == "IBVT_E_INVALID"
+    say("[gpu] unstructured edge: fsi_step refused")
+    c = make(W, "fp64", dev)
+    with pytest.raises(IbvtError) as e:
+        c.fsi_step(to_dev(W.X, torch.float64, dev), None, None, None, None, dt=1.0)
+    assert e.value.name == "IBVT_E_UNSUPPORTED"
+    c.free()
