@@ -557,14 +557,6 @@ __global__ __launch_bounds__(256) void k_row_box(int64_t n_v, int64_t n_t,
   cap[w] = sz;
 }
 
-// Orders the LDS accesses of one wave around this point (the wave's LDS
-// operations execute in issue order; this keeps the compiler from moving
-// them across).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // Exact floor(q / n) for q < 2^16 and 1 <= n < 2^16 as a multiply-high by
 // m = ceil(2^32 / n): with m n = 2^32 + e, 0 <= e < n, the error term q e / 2^32
 // stays below 1.  n = 1 (m = 2^32) is coded as m = 0.

@@ -26,10 +26,19 @@ enum Counter : int {
   kCntClass = 5,  // 5, 6, 7: pairs per cut class
   kCntDist = 8,   // signed distances evaluated by the clip
   kCntCutPts = 9, // cut points made by the clip
-  kCntSlots = 10,
+  kCntRowOverflow = 10,  // rows too wide for the LDS row gather (unstructured)
+  kCntSlots = 11,
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Orders the LDS accesses of one wave around this point (the wave's LDS
+// operations execute in issue order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

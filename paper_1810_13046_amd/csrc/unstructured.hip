@@ -29,11 +29,16 @@
 //                   sub-tetrahedra, ∫ λ_i μ_j integrated exactly on each
 //                   (the product of two affine factors:
 //                   ∫_τ f g = |τ|/20 (Σ_v f_v g_v + Σ_v f_v Σ_v g_v)).
+//  k_row_cap_u / k_rows_u<T> / k_rows_compact_u<T>
+//                   one wavefront per solid vertex: the kept pairs of its
+//                   incident tets in generation order, their entries summed
+//                   per fluid vertex in an LDS hash (pair order), the row
+//                   written sorted -> CSR rows of B (deterministic).
 //  k_coo / sort / k_runs
-//                   the 16 entries of every kept pair keyed by (solid
-//                   vertex, fluid vertex), stable radix sort, one lane per
-//                   run of equal keys sums it in order -> CSR rows of B
-//                   (deterministic).
+//                   for rows too wide for the LDS gather: the 16 entries of
+//                   every kept pair keyed by (solid vertex, fluid vertex),
+//                   stable radix sort over the key's used bits, one lane per
+//                   run of equal keys sums it in order (the same sums).
 #include <hipcub/hipcub.hpp>
 
 #include "internal.hpp"
@@ -307,11 +312,13 @@ __global__ __launch_bounds__(kWave) void k_pairs_u(
 }
 
 // Keys of the 16 entries of every pair (one lane per pair): (solid vertex
-// << 32) | fluid vertex for kept pairs, all ones otherwise; idx = entry.
+// << cb) | fluid vertex for kept pairs (cb bits hold any fluid vertex),
+// `none` (row n_vert: after every valid key) otherwise; idx = entry.
 __global__ void k_coo(int64_t n_pairs, int64_t n_s, const int64_t* __restrict__ off,
                       const int32_t* __restrict__ pf, const int32_t* __restrict__ tets_s,
                       const int32_t* __restrict__ tets_f, const uint8_t* __restrict__ keep,
-                      uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+                      int cb, uint64_t none, uint64_t* __restrict__ keys,
+                      uint32_t* __restrict__ idx) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
   const bool k = keep[p];
@@ -327,25 +334,24 @@ __global__ void k_coo(int64_t n_pairs, int64_t n_s, const int64_t* __restrict__ 
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) {
       const int64_t e = 16 * p + 4 * i + j;
-      keys[e] = k ? ((uint64_t(uint32_t(vs[i])) << 32) | uint64_t(uint32_t(vf[j])))
-                  : ~uint64_t(0);
+      keys[e] = k ? ((uint64_t(uint32_t(vs[i])) << cb) | uint64_t(uint32_t(vf[j]))) : none;
       idx[e] = uint32_t(e);
     }
 }
 
 // head[e] = 1 where a run of equal (valid) keys starts.
-__global__ void k_run_heads(int64_t n, const uint64_t* __restrict__ keys,
+__global__ void k_run_heads(int64_t n, uint64_t none, const uint64_t* __restrict__ keys,
                             int32_t* __restrict__ head) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const uint64_t k = keys[e];
-  head[e] = (k != ~uint64_t(0) && (e == 0 || keys[e - 1] != k)) ? 1 : 0;
+  head[e] = (k < none && (e == 0 || keys[e - 1] != k)) ? 1 : 0;
 }
 
 // One lane per run: the run's values summed in sorted (= generation)
 // order; column and row of the entry.
 template <typename T>
-__global__ void k_run_sums(int64_t n, const uint64_t* __restrict__ keys,
+__global__ void k_run_sums(int64_t n, int cb, const uint64_t* __restrict__ keys,
                            const uint32_t* __restrict__ idx, const int32_t* __restrict__ head,
                            const int64_t* __restrict__ pos, const T* __restrict__ vals,
                            int32_t* __restrict__ col, int32_t* __restrict__ row,
@@ -356,8 +362,8 @@ __global__ void k_run_sums(int64_t n, const uint64_t* __restrict__ keys,
   double acc = 0.0;
   for (int64_t q = e; q < n && keys[q] == k; ++q) acc += double(vals[idx[q]]);
   const int64_t u = pos[e];
-  col[u] = int32_t(uint32_t(k & 0xffffffffu));
-  row[u] = int32_t(k >> 32);
+  col[u] = int32_t(uint32_t(k & ((uint64_t(1) << cb) - 1)));
+  row[u] = int32_t(k >> cb);
   val[u] = T(acc);
 }
 
@@ -373,6 +379,320 @@ __global__ void k_row_ptr(int64_t n_rows, int64_t nnz, const int32_t* __restrict
     else hi = mid;
   }
   rowptr[r] = lo;
+}
+
+// Row scratch bound of each solid vertex: min(kURowMax, 4 x candidate
+// pairs of its incident tets) distinct columns.
+constexpr int kUHashBits = 9;
+constexpr int kUHash = 1 << kUHashBits;  // LDS hash slots per row
+constexpr int kURowMax = kUHash / 2;     // distinct columns a row may have here
+
+__global__ void k_row_cap_u(int64_t n_v, const int64_t* __restrict__ vt_ptr,
+                            const int32_t* __restrict__ vt_tet,
+                            const int64_t* __restrict__ pair_off, int64_t* __restrict__ cap) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  int64_t n = 0;
+  for (int64_t k = vt_ptr[i]; k < vt_ptr[i + 1]; ++k) {
+    const int64_t t = vt_tet[k];
+    n += pair_off[t + 1] - pair_off[t];
+  }
+  cap[i] = min<int64_t>(kURowMax, 4 * n);
+}
+
+// One wavefront per solid vertex i builds row i of B in LDS.  The row's
+// kept pairs are taken in generation order (incident tets ascending, then
+// their pairs), 16 per step, one entry per lane (lane = 4·pair + fluid
+// corner); the column (fluid vertex) finds its slot in an open-addressing
+// hash, and the 16 pairs of a step are added one after another, so every
+// column sums its contributions in pair order: the same order, and the
+// same double sums, as the sort-based assembly.  The row is written sorted
+// by column at tmp_off[i].  A row with more than kURowMax distinct columns
+// is counted in counters[kCntRowOverflow] and left empty (the caller then
+// assembles B by sorting instead).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_u(
+    int64_t n_v, const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_tet,
+    const int32_t* __restrict__ tets_s, const int64_t* __restrict__ pair_off,
+    const uint8_t* __restrict__ keep, const int32_t* __restrict__ pf,
+    const int32_t* __restrict__ tets_f, const T* __restrict__ pval,
+    const int64_t* __restrict__ tmp_off, int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val,
+    int64_t* __restrict__ rownnz, unsigned long long* __restrict__ counters) {
+  __shared__ int32_t s_key[4][kUHash];
+  __shared__ double s_acc[4][kUHash];  // summed in double in both precisions
+  __shared__ int32_t s_pbl[4][kWave];  // batch tet: first pair << 2 | local index of i
+  __shared__ int32_t s_ex[4][kWave];   // batch tet: exclusive prefix of pair counts
+  __shared__ int32_t s_kp[4][kWave];   // kept pairs of a step: pair << 2 | local index
+  __shared__ int32_t s_lc[4][kURowMax];
+  __shared__ double s_lv[4][kURowMax];
+  const int wib = threadIdx.x / kWave;
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  if (i >= n_v) return;
+  int32_t* key = s_key[wib];
+  double* acc = s_acc[wib];
+  int32_t* PBL = s_pbl[wib];
+  int32_t* EX = s_ex[wib];
+  int32_t* KP = s_kp[wib];
+  for (int k = lane; k < kUHash; k += kWave) {
+    key[k] = -1;
+    acc[k] = 0.0;
+  }
+  int nuniq = 0;
+  bool over = false;
+  const int64_t beg = vt_ptr[i], end = vt_ptr[i + 1];
+  const int u = lane >> 2, j = lane & 3;
+  for (int64_t kb = beg; kb < end && !over; kb += kWave) {
+    const int nk = int(min<int64_t>(kWave, end - kb));
+    int cnt = 0, pbl = 0;
+    if (lane < nk) {
+      const int64_t t = vt_tet[kb + lane];
+      const int4 tv = *reinterpret_cast<const int4*>(tets_s + 4 * t);
+      const int li =
+          (tv.y == int32_t(i)) ? 1 : (tv.z == int32_t(i)) ? 2 : (tv.w == int32_t(i)) ? 3 : 0;
+      const int64_t pb = pair_off[t];
+      cnt = int(pair_off[t + 1] - pb);
+      pbl = int32_t(pb << 2) | li;
+    }
+    int incl = cnt;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    const int tot = __shfl(incl, kWave - 1, kWave);
+    wave_lds_sync();
+    PBL[lane] = pbl;
+    EX[lane] = incl - cnt;
+    wave_lds_sync();
+    for (int q0 = 0; q0 < tot && !over; q0 += kWave) {
+      const int q = q0 + lane;
+      bool kept = false;
+      int32_t code = 0;
+      if (q < tot) {
+        // the last batch tet whose pairs start at or before q
+        int lo = 0, hi = nk - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (EX[mid] <= q) lo = mid;
+          else hi = mid - 1;
+        }
+        const int32_t m = PBL[lo];
+        const int32_t p = (m >> 2) + (q - EX[lo]);
+        kept = keep[p] != 0;
+        code = (p << 2) | (m & 3);
+      }
+      const uint64_t km = ballot64(kept);
+      const int nkept = popc64(km);
+      wave_lds_sync();
+      if (kept) KP[rank_below(km)] = code;
+      wave_lds_sync();
+      for (int s0 = 0; s0 < nkept; s0 += 16) {
+        const bool have = s0 + u < nkept;
+        int slot = 0;
+        bool inserted = false;
+        double val = 0.0;
+        if (have) {
+          const int32_t cd = KP[s0 + u];
+          const int64_t p = cd >> 2;
+          const int64_t f = pf[p];
+          const int32_t cv = tets_f[4 * f + j];
+          val = double(pval[16 * p + 4 * (cd & 3) + j]);
+          // open addressing; the table is never more than 5/8 full
+          uint32_t h = (uint32_t(cv) * 2654435769u) >> (32 - kUHashBits);
+          while (true) {
+            const int32_t prev = atomicCAS(&key[h], -1, cv);
+            if (prev == -1 || prev == cv) {
+              slot = int(h);
+              inserted = prev == -1;
+              break;
+            }
+            h = (h + 1) & (kUHash - 1);
+          }
+        }
+        nuniq += popc64(ballot64(inserted));
+        const int nstep = min(16, nkept - s0);
+        for (int uu = 0; uu < nstep; ++uu) {
+          wave_lds_sync();
+          if (have && u == uu)
+            __hip_atomic_fetch_add(&acc[slot], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+        if (nuniq > kURowMax) {
+          over = true;
+          break;
+        }
+      }
+    }
+  }
+  if (over) {
+    if (lane == 0) {
+      rownnz[i] = 0;
+      atomicAdd(&counters[kCntRowOverflow], 1ull);
+    }
+    return;
+  }
+  wave_lds_sync();
+  int32_t* LC = s_lc[wib];
+  double* LV = s_lv[wib];
+  int n = 0;
+  for (int k0 = 0; k0 < kUHash; k0 += kWave) {
+    const int32_t cv = key[k0 + lane];
+    const bool used = cv != -1;
+    const uint64_t m = ballot64(used);
+    if (used) {
+      LC[n + rank_below(m)] = cv;
+      LV[n + rank_below(m)] = acc[k0 + lane];
+    }
+    n += popc64(m);
+  }
+  wave_lds_sync();
+  const int64_t o = tmp_off[i];
+  for (int e = lane; e < n; e += kWave) {
+    const int32_t cv = LC[e];
+    int r = 0;
+    for (int x = 0; x < n; ++x) r += LC[x] < cv ? 1 : 0;
+    tmp_col[o + r] = cv;
+    tmp_val[o + r] = T(LV[e]);
+  }
+  if (lane == 0) rownnz[i] = n;
+}
+
+// Copies each row from the row scratch into the CSR arrays.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_compact_u(
+    int64_t n_v, const int64_t* __restrict__ tmp_off, const int32_t* __restrict__ tmp_col,
+    const T* __restrict__ tmp_val, const int64_t* __restrict__ rp, int32_t* __restrict__ col,
+    T* __restrict__ val) {
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  if (i >= n_v) return;
+  const int64_t src = tmp_off[i], dst = rp[i], n = rp[i + 1] - rp[i];
+  for (int64_t k = lane; k < n; k += kWave) {
+    col[dst + k] = tmp_col[src + k];
+    val[dst + k] = tmp_val[src + k];
+  }
+}
+
+// Rows of B by the LDS row gather; returns -1 (nothing written to B) when
+// some row has more than kURowMax distinct columns.
+template <typename T>
+int rows_by_lds(ibvt_coupling* c, int64_t n_pairs, hipStream_t s) {
+  const int64_t n_v = c->n_vert;
+  int st;
+  if ((st = ensure(c, c->rowcap, size_t(n_v + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->rowtmpoff, size_t(n_v + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->rownnz, size_t(n_v + 1) * sizeof(int64_t)))) return st;
+  {
+    ProfScope ps("rows_box", s);
+    if (n_v > 0)
+      k_row_cap_u<<<blocks_for(n_v, 256), 256, 0, s>>>(n_v, c->vt_ptr.as<int64_t>(),
+                                                       c->vt_tet.as<int32_t>(),
+                                                       c->pair_off.as<int64_t>(),
+                                                       c->rowcap.as<int64_t>());
+    if ((st = scan_i64(c, c->rowcap.as<int64_t>(), c->rowtmpoff.as<int64_t>(), n_v, s)))
+      return st;
+  }
+  int64_t n_tmp = 0;
+  if ((st = read_back(c, &n_tmp, c->rowtmpoff.as<int64_t>() + n_v, sizeof(int64_t), s)))
+    return st;
+  if ((st = ensure(c, c->rowtmpcol, size_t(n_tmp + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->rowtmpval, size_t(n_tmp + 1) * sizeof(T)))) return st;
+  auto* counters = c->counters.as<unsigned long long>();
+  Csr& B = c->B[0];
+  B.nrows = n_v;
+  if ((st = ensure(c, B.rowptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;
+  {
+    ProfScope ps("rows_gather", s);
+    if (n_v > 0)
+      k_rows_u<T><<<blocks_for(n_v * kWave, 256), 256, 0, s>>>(
+          n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+          c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->owner.as<int32_t>(),
+          c->ftets.as<int32_t>(), c->pval.as<T>(), c->rowtmpoff.as<int64_t>(),
+          c->rowtmpcol.as<int32_t>(), c->rowtmpval.as<T>(), c->rownnz.as<int64_t>(), counters);
+    if ((st = hip_check(hipGetLastError(), "row gather launch"))) return st;
+    if ((st = scan_i64(c, c->rownnz.as<int64_t>(), B.rowptr.as<int64_t>(), n_v, s))) return st;
+  }
+  unsigned long long over = 0;
+  if ((st = read_back(c, &over, counters + kCntRowOverflow, sizeof(over), s))) return st;
+  if (over) return -1;
+  int64_t nnz = 0;
+  if ((st = read_back(c, &nnz, B.rowptr.as<int64_t>() + n_v, sizeof(int64_t), s))) return st;
+  B.nnz = nnz;
+  if ((st = ensure(c, B.col, size_t(nnz + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, B.val, size_t(nnz + 1) * sizeof(T)))) return st;
+  {
+    ProfScope ps("rows_compact", s);
+    if (n_v > 0)
+      k_rows_compact_u<T><<<blocks_for(n_v * kWave, 256), 256, 0, s>>>(
+          n_v, c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(), c->rowtmpval.as<T>(),
+          B.rowptr.as<int64_t>(), B.col.as<int32_t>(), B.val.as<T>());
+  }
+  return hip_check(hipGetLastError(), "rows launch");
+}
+
+// Rows of B by sorting: the 16 entries of every pair keyed by (solid vertex,
+// fluid vertex), a stable radix sort, one lane per run of equal keys.
+template <typename T>
+int rows_by_sort(ibvt_coupling* c, int64_t n_pairs, hipStream_t s) {
+  const int64_t n_s = c->n_tet, n_v = c->n_vert;
+  int st;
+  const int64_t n_e = 16 * n_pairs;
+  // key bits: cb for the fluid vertex, then enough for rows 0..n_vert
+  auto bits = [](uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; };
+  const int cb = bits(uint64_t(c->n_fvert > 1 ? c->n_fvert - 1 : 0));
+  const int end_bit = cb + bits(uint64_t(n_v));
+  const uint64_t none = uint64_t(n_v) << cb;
+  size_t temp_bytes = 0;
+  if (n_e > 0 &&
+      (st = hip_check(hipcub::DeviceRadixSort::SortPairs(
+                          nullptr, temp_bytes, static_cast<const uint64_t*>(nullptr),
+                          static_cast<uint64_t*>(nullptr), static_cast<const uint32_t*>(nullptr),
+                          static_cast<uint32_t*>(nullptr), int(n_e), 0, end_bit, s),
+                      "sort size")))
+    return st;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t kb = al(size_t(n_e + 1) * 8), ib = al(size_t(n_e + 1) * 4);
+  const size_t hb = al(size_t(n_e + 1) * 4), pb = al(size_t(n_e + 2) * 8);
+  if ((st = ensure(c, c->ucoo, 2 * kb + 2 * ib + hb + pb + ib + al(temp_bytes) + 256))) return st;
+  char* base = c->ucoo.as<char>();
+  uint64_t* keys = reinterpret_cast<uint64_t*>(base);
+  uint64_t* skeys = reinterpret_cast<uint64_t*>(base + kb);
+  uint32_t* idx = reinterpret_cast<uint32_t*>(base + 2 * kb);
+  uint32_t* sidx = reinterpret_cast<uint32_t*>(base + 2 * kb + ib);
+  int32_t* head = reinterpret_cast<int32_t*>(base + 2 * kb + 2 * ib);
+  int64_t* pos = reinterpret_cast<int64_t*>(base + 2 * kb + 2 * ib + hb);
+  int32_t* rowid = reinterpret_cast<int32_t*>(base + 2 * kb + 2 * ib + hb + pb);
+  void* temp = base + 2 * kb + 3 * ib + hb + pb;
+  int64_t nnz = 0;
+  {
+    ProfScope ps("rows_sort", s);
+    if (n_e > 0) {
+      k_coo<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
+          n_pairs, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(), c->tets.as<int32_t>(),
+          c->ftets.as<int32_t>(), c->keep.as<uint8_t>(), cb, none, keys, idx);
+      if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx,
+                                                             sidx, int(n_e), 0, end_bit, s),
+                          "entry sort")))
+        return st;
+      k_run_heads<<<blocks_for(n_e, 256), 256, 0, s>>>(n_e, none, skeys, head);
+      if ((st = scan_i32_to_i64(c, head, pos, n_e, s))) return st;
+      if ((st = read_back(c, &nnz, pos + n_e, sizeof(int64_t), s))) return st;
+    }
+  }
+  Csr& B = c->B[0];
+  B.nrows = n_v;
+  B.nnz = nnz;
+  if ((st = ensure(c, B.rowptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, B.col, size_t(nnz + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, B.val, size_t(nnz + 1) * sizeof(T)))) return st;
+  {
+    ProfScope ps("rows_gather", s);
+    if (n_e > 0)
+      k_run_sums<T><<<blocks_for(n_e, 256), 256, 0, s>>>(n_e, cb, skeys, sidx, head, pos,
+                                                         c->pval.as<T>(), B.col.as<int32_t>(),
+                                                         rowid, B.val.as<T>());
+    k_row_ptr<<<blocks_for(n_v + 1, 256), 256, 0, s>>>(n_v, nnz, rowid, B.rowptr.as<int64_t>());
+  }
+  return hip_check(hipGetLastError(), "rows launch");
 }
 
 template <typename T>
@@ -431,60 +751,10 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
         flags, counters);
   }
   if ((st = hip_check(hipGetLastError(), "pairs launch"))) return st;
-  // (IV) B from the entries of the kept pairs: sort by (row, column), sum runs
-  const int64_t n_e = 16 * n_pairs;
-  size_t temp_bytes = 0;
-  if (n_e > 0 &&
-      (st = hip_check(hipcub::DeviceRadixSort::SortPairs(
-                          nullptr, temp_bytes, static_cast<const uint64_t*>(nullptr),
-                          static_cast<uint64_t*>(nullptr), static_cast<const uint32_t*>(nullptr),
-                          static_cast<uint32_t*>(nullptr), int(n_e), 0, 64, s),
-                      "sort size")))
-    return st;
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t kb = al(size_t(n_e + 1) * 8), ib = al(size_t(n_e + 1) * 4);
-  const size_t hb = al(size_t(n_e + 1) * 4), pb = al(size_t(n_e + 2) * 8);
-  if ((st = ensure(c, c->ucoo, 2 * kb + 2 * ib + hb + pb + ib + al(temp_bytes) + 256))) return st;
-  char* base = c->ucoo.as<char>();
-  uint64_t* keys = reinterpret_cast<uint64_t*>(base);
-  uint64_t* skeys = reinterpret_cast<uint64_t*>(base + kb);
-  uint32_t* idx = reinterpret_cast<uint32_t*>(base + 2 * kb);
-  uint32_t* sidx = reinterpret_cast<uint32_t*>(base + 2 * kb + ib);
-  int32_t* head = reinterpret_cast<int32_t*>(base + 2 * kb + 2 * ib);
-  int64_t* pos = reinterpret_cast<int64_t*>(base + 2 * kb + 2 * ib + hb);
-  int32_t* rowid = reinterpret_cast<int32_t*>(base + 2 * kb + 2 * ib + hb + pb);
-  void* temp = base + 2 * kb + 3 * ib + hb + pb;
-  int64_t nnz = 0;
-  {
-    ProfScope ps("rows_sort", s);
-    if (n_e > 0) {
-      k_coo<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
-          n_pairs, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(), c->tets.as<int32_t>(),
-          c->ftets.as<int32_t>(), c->keep.as<uint8_t>(), keys, idx);
-      if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx,
-                                                             sidx, int(n_e), 0, 64, s),
-                          "entry sort")))
-        return st;
-      k_run_heads<<<blocks_for(n_e, 256), 256, 0, s>>>(n_e, skeys, head);
-      if ((st = scan_i32_to_i64(c, head, pos, n_e, s))) return st;
-      if ((st = read_back(c, &nnz, pos + n_e, sizeof(int64_t), s))) return st;
-    }
-  }
-  Csr& B = c->B[0];
-  B.nrows = n_v;
-  B.nnz = nnz;
-  if ((st = ensure(c, B.rowptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, B.col, size_t(nnz + 1) * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, B.val, size_t(nnz + 1) * sizeof(T)))) return st;
-  {
-    ProfScope ps("rows_gather", s);
-    if (n_e > 0)
-      k_run_sums<T><<<blocks_for(n_e, 256), 256, 0, s>>>(n_e, skeys, sidx, head, pos,
-                                                         c->pval.as<T>(), B.col.as<int32_t>(),
-                                                         rowid, B.val.as<T>());
-    k_row_ptr<<<blocks_for(n_v + 1, 256), 256, 0, s>>>(n_v, nnz, rowid, B.rowptr.as<int64_t>());
-  }
-  if ((st = hip_check(hipGetLastError(), "rows launch"))) return st;
+  // (IV) B: rows gathered in LDS, or by sorting the entries when a row is
+  // too wide for that
+  if ((st = rows_by_lds<T>(c, n_pairs, s)) > 0) return st;
+  if (st < 0 && (st = rows_by_sort<T>(c, n_pairs, s))) return st;
   {
     ProfScope ps("transpose", s);
     if ((st = transpose_one<T>(c, 0, s))) return st;

@@ -160,6 +160,54 @@ def test_unstructured_determinism_and_reassembly(dev, un):
     c2.free()
 
 
+def test_unstructured_wide_rows_fall_back_to_sort(dev, un):
+    """Rows are gathered one wavefront per solid vertex in LDS; a vertex
+    whose tets meet more fluid vertices than that holds sends the assembly
+    through the sort-based path.  Both sum every entry in pair order, so the
+    rows of the beam's vertices come out bit-identical either way."""
+    import torch
+    from paper_1810_13046_amd import profile_enable, profile_read
+    W, R = ref(un, 1)
+    big = np.array([[0.1, 0.1, 0.1], [0.9, 0.1, 0.1], [0.1, 0.9, 0.1], [0.1, 0.1, 0.9]])
+    X2 = np.concatenate([W.X, big])
+    n0 = W.X.shape[0]
+    T2 = np.concatenate([W.tets, np.arange(n0, n0 + 4, dtype=np.int32)[None, :]])
+    runs = {}
+    for name, X, T in (("beam", W.X, W.tets), ("beam+big", X2, T2)):
+        say(f"[gpu] unstructured rows: {name}")
+        torch.cuda.synchronize()
+        profile_read()
+        profile_enable(True)
+        c = make(W, "fp64", dev, X=X) if name == "beam" else Coupling_for(W, X, T, dev)
+        prof = profile_read()
+        profile_enable(False)
+        runs[name] = (c, prof)
+    assert "rows_sort" not in runs["beam"][1] and "rows_compact" in runs["beam"][1]
+    assert "rows_sort" in runs["beam+big"][1]
+    Rb = un.assemble(W.Xf, W.tets_f, X2, T2)
+    G2 = gpu_B(runs["beam+big"][0])
+    fro, mx = sparse_rel(G2, Rb.B)
+    say(f"  sort path rel fro {fro:.2e} max {mx:.2e}; big-tet row nnz {G2[n0:].getnnz(axis=1)}")
+    assert fro <= 1e-12 and mx <= 1e-12
+    assert G2[n0:].getnnz(axis=1).max() > 256
+    rp1, col1, val1 = runs["beam"][0].export_csr(0)
+    rp2, col2, val2 = runs["beam+big"][0].export_csr(0)
+    assert np.array_equal(rp1, rp2[:n0 + 1])
+    assert np.array_equal(col1, col2[:rp1[-1]])
+    assert np.array_equal(val1, val2[:rp1[-1]])
+    for c, _ in runs.values():
+        c.free()
+
+
+def Coupling_for(W, X, T, dev):
+    import torch
+    from paper_1810_13046_amd import Coupling
+    c = Coupling(None, to_dev(X, torch.float64, dev), to_dev(T, torch.int32, dev),
+                 fluid_mesh=(to_dev(W.Xf, torch.float64, dev), to_dev(W.tets_f, torch.int32, dev)))
+    torch.cuda.synchronize()
+    return c
+
+
 def test_unstructured_full_size(dev, un):
     """The 5.3M-tet warped fluid mesh with the 200k-tet beam: sampled rows of
     B against the oracle (the rows' full vertex stars), and exact
