@@ -64,7 +64,7 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="3f6d7d36f53611e8d0b2efea826040d74484b363a1539c9cbb17b0989b08cc5c",
+CLIP_TRAFFIC = dict(sources_sha256="3ddf90cf53936be09269c2233bdca31697e4c842485a768d871463cbd8cff7aa",
                     bytes_mixed=35620465920)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
