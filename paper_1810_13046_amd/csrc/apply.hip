@@ -87,6 +87,7 @@ int launch_spmv(const SpmvArgs<T>& a, int nc, hipStream_t s, const char* name) {
 
 struct CgScalars {
   double rz[3], bb[3], rr[3], pq[3];
+  double rz0[3];  // r·z at the start (the host sizes its next chunk from the decay)
   double alpha[3], beta[3];
   int conv[3];
   int iters[3];
@@ -186,6 +187,7 @@ __global__ void k_cg_start(CgScalars* sc, const double* __restrict__ tmp) {
   sc->all = 1;
   for (int d = 0; d < 3; ++d) {
     sc->rz[d] = tmp[d];
+    sc->rz0[d] = tmp[d];
     sc->bb[d] = tmp[3 + d];
     sc->rr[d] = 0;
     sc->beta[d] = 0;
@@ -476,8 +478,11 @@ int cg_workspace(ibvt_coupling* c, size_t tsize, CgWork& w) {
 }
 
 // Plain CG on M (values V) for the right-hand sides b (type T), x in/out.
-// Returns iterations in info-like arrays through the scalars; checks
-// convergence on the host every `check` iterations.
+// Returns iterations in info-like arrays through the scalars.  The host
+// checks convergence after a first chunk of iterations, then sizes each next
+// chunk from the observed per-iteration decay of r·z so that the check lands
+// near the iteration that meets the tolerance (iterations past convergence
+// are no-ops on the device, so a late check costs only their launches).
 template <typename T, typename V>
 int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int maxit,
             const CgWork& w, hipStream_t s, int* iters_out, bool* converged) {
@@ -501,12 +506,12 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
   k_cg_start<<<1, 64, 0, s>>>(w.sc, w.tmp);
   int st = hip_check(hipGetLastError(), "cg init launch");
   if (st) return st;
-  const int check = 8;
   int it = 0;
+  int next = 6;
   CgScalars host{};
   *converged = false;
   while (it < maxit) {
-    const int chunk = std::min(check, maxit - it);
+    const int chunk = std::min(next, maxit - it);
     for (int k = 0; k < chunk; ++k) {
       ProfScope ps("cg_iteration", s);
       if (nc == 3)
@@ -528,6 +533,23 @@ int cg_core(ibvt_coupling* c, const V* mval, const T* b, T* x, double rtol, int 
       *converged = true;
       break;
     }
+    // iterations still needed by the slowest component, assuming r·r keeps
+    // decaying at the rate r·z has shown so far
+    double need = 0.0;
+    bool known = false;
+    for (int d = 0; d < nc; ++d) {
+      if (host.conv[d] || host.iters[d] <= 0) continue;
+      const double ratio = host.rz[d] / host.rz0[d];
+      if (!(ratio > 0.0 && ratio < 1.0) || !(host.rr[d] > 0.0) || !(host.bb[d] > 0.0)) {
+        known = false;
+        need = 0.0;
+        break;
+      }
+      const double q = std::pow(ratio, 1.0 / host.iters[d]);
+      need = std::max(need, std::log(rtol2 * host.bb[d] / host.rr[d]) / std::log(q));
+      known = true;
+    }
+    next = known ? std::min(32, std::max(1, int(std::ceil(need)))) : 8;
   }
   if (it == 0) {
     if ((st = hip_check(hipMemcpyAsync(&host, w.sc, sizeof(host), hipMemcpyDeviceToHost, s),

@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kRowNodes = 512;  // LDS box nodes per wave per pass in k_rows
 constexpr int kRowMap = 512;    // slots of the slot → tet map of k_rows (one window)
+constexpr int kRowBatch = 8;    // steps of 8 pairs whose loads k_rows issues together
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
   int lo = 0, hi = n;  // first index with L[idx] > x
@@ -660,40 +661,62 @@ __global__ __launch_bounds__(256) void k_rows(
         }
         wave_lds_sync();
         const int wend = min(tot, w0 + kRowMap);
-        for (int s0 = w0; s0 < wend; s0 += 8) {
-          const int sl = s0 + qq;
-          bool add = false;
-          int loc = 0;
-          double val = 0.0;
-          if (sl < wend) {
-            const int k = smap[sl - w0];
-            const int4 m1 = M1[k];
-            const uint32_t q = uint32_t(sl - EX[k]);
-            const uint32_t n0 = uint32_t(m1.x) & 0xffffu, n1 = uint32_t(m1.x) >> 16;
-            const uint32_t qy = div_magic(q, uint32_t(m1.z));
-            const int ix = int(q - qy * n0);
-            const uint32_t iz = div_magic(qy, uint32_t(m1.w));
-            const int iy = int(qy - iz * n1);
-            const int lin = m1.y + ix + bn0 * (iy + bn1 * int(iz)) + coff;
-            if (lin >= 0 && lin < span) {
-              const int4 m0 = M0[k];
-              const int64_t pb = int64_t((unsigned long long)(unsigned)m0.x |
-                                         ((unsigned long long)(unsigned)m0.y << 32));
-              const int64_t kb = int64_t((unsigned long long)(unsigned)m0.z |
-                                         ((unsigned long long)(unsigned)m0.w << 32));
-              const uint8_t kp = keep[kb + q];
-              const T v = pval[pb + int64_t(q) * 8 + jj];
-              add = kp != 0;
-              val = double(v);
-              loc = lin;
-            }
-          }
-          if (add) flg[loc] = 1;
+        // kRowBatch steps of 8 pairs at a time: their loads are issued
+        // together, then the steps are added in slot order as before
+        for (int s0 = w0; s0 < wend; s0 += 8 * kRowBatch) {
+          bool add[kRowBatch];
+          int loc[kRowBatch];
+          uint8_t kraw[kRowBatch];
+          T vraw[kRowBatch];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            wave_lds_sync();
-            if (add && qq == u)
-              __hip_atomic_fetch_add(&acc[loc], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          for (int b = 0; b < kRowBatch; ++b) {
+            const int sl = s0 + 8 * b + qq;
+            bool ok = false;
+            int lin = 0;
+            int64_t ko = 0, vo = 0;
+            if (sl < wend) {
+              const int k = smap[sl - w0];
+              const int4 m1 = M1[k];
+              const uint32_t q = uint32_t(sl - EX[k]);
+              const uint32_t n0 = uint32_t(m1.x) & 0xffffu, n1 = uint32_t(m1.x) >> 16;
+              const uint32_t qy = div_magic(q, uint32_t(m1.z));
+              const int ix = int(q - qy * n0);
+              const uint32_t iz = div_magic(qy, uint32_t(m1.w));
+              const int iy = int(qy - iz * n1);
+              lin = m1.y + ix + bn0 * (iy + bn1 * int(iz)) + coff;
+              if (lin >= 0 && lin < span) {
+                const int4 m0 = M0[k];
+                const int64_t pb = int64_t((unsigned long long)(unsigned)m0.x |
+                                           ((unsigned long long)(unsigned)m0.y << 32));
+                const int64_t kb = int64_t((unsigned long long)(unsigned)m0.z |
+                                           ((unsigned long long)(unsigned)m0.w << 32));
+                ok = true;
+                ko = kb + q;
+                vo = pb + int64_t(q) * 8 + jj;
+              }
+            }
+            // loaded by every lane (entry 0 stands in when there is none),
+            // so the loads of the whole batch are in flight together
+            kraw[b] = keep[ko];
+            vraw[b] = pval[vo];
+            add[b] = ok;
+            loc[b] = lin;
+          }
+#pragma unroll
+          for (int b = 0; b < kRowBatch; ++b) {
+            add[b] = add[b] && kraw[b] != 0;
+            if (add[b]) flg[loc[b]] = 1;
+          }
+#pragma unroll
+          for (int b = 0; b < kRowBatch; ++b) {
+            if (s0 + 8 * b >= wend) break;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              wave_lds_sync();
+              if (add[b] && qq == u)
+                __hip_atomic_fetch_add(&acc[loc[b]], double(vraw[b]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
           }
         }
       }
@@ -704,10 +727,13 @@ __global__ __launch_bounds__(256) void k_rows(
       const bool tch = k < span && flg[k] != 0;
       const uint64_t m = ballot64(tch);
       if (tch) {
-        const int64_t lin = c0 + k;
-        const int64_t gx = b.lo[0] + lin % bn0;
-        const int64_t gy = b.lo[1] + (lin / bn0) % bn1;
-        const int64_t gz = b.lo[2] + lin / (int64_t(bn0) * bn1);
+        // the box lies inside the lattice, whose node count fits int32
+        const uint32_t lin = uint32_t(c0 + k);
+        const uint32_t r = lin / uint32_t(bn0);
+        const uint32_t zq = r / uint32_t(bn1);
+        const int64_t gx = b.lo[0] + int64_t(lin - r * uint32_t(bn0));
+        const int64_t gy = b.lo[1] + int64_t(r - zq * uint32_t(bn1));
+        const int64_t gz = b.lo[2] + int64_t(zq);
         const int64_t pos = outpos + rank_below(m);
         tmp_col[pos] = int32_t(gx + NX * (gy + NY * gz));
         tmp_val[pos] = T(acc[k]);
