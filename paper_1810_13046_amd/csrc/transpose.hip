@@ -2,9 +2,11 @@
 //
 // The touched fluid nodes are compacted with a prefix sum over the lattice;
 // the nonzeros of B^d, taken in their CSR order (row i ascending, then
-// column), are sorted by compacted column with a stable LSD radix sort, so
-// each row of B^dT lists its vertices in ascending order.  No value is
-// reduced and no position depends on timing: the result is deterministic.
+// column), are sorted by compacted column with a stable LSD radix sort that
+// carries each nonzero's (value, row) along, so each row of B^dT lists its
+// vertices in ascending order and no gather by permutation follows.  No
+// value is reduced and no position depends on timing: the result is
+// deterministic.
 #include <hipcub/hipcub.hpp>
 
 #include "internal.hpp"
@@ -24,33 +26,43 @@ __global__ void k_compact(int64_t n, const int32_t* __restrict__ mark,
   if (j < n && mark[j]) rowmap[cidx[j]] = int32_t(j);
 }
 
-// keys[k] = compacted column of nonzero k; idx[k] = k; row[k] = its row.
-// One wave per row (coalesced writes).
+// A nonzero carried through the sort: its value and its row.
+template <typename T>
+struct ValRow {
+  T v;
+  int32_t r;
+};
+
+// keys[k] = compacted column of nonzero k, vr[k] = (value, row).  One wave
+// per row (coalesced reads and writes).
+template <typename T>
 __global__ __launch_bounds__(256) void k_keys(int64_t n_rows, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col,
+                                              const T* __restrict__ val,
                                               const int64_t* __restrict__ cidx,
-                                              int32_t* __restrict__ keys, int32_t* __restrict__ idx,
-                                              int32_t* __restrict__ row) {
+                                              int32_t* __restrict__ keys,
+                                              ValRow<T>* __restrict__ vr) {
   const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = lane_id();
   if (i >= n_rows) return;
   for (int64_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += kWave) {
     keys[k] = int32_t(cidx[col[k]]);
-    idx[k] = int32_t(k);
-    row[k] = int32_t(i);
+    ValRow<T> x;
+    x.v = val[k];
+    x.r = int32_t(i);
+    vr[k] = x;
   }
 }
 
 template <typename T>
 __global__ void k_tgather(int64_t nnz, const int32_t* __restrict__ skeys,
-                          const int32_t* __restrict__ perm, const int32_t* __restrict__ row,
-                          const T* __restrict__ val, int32_t* __restrict__ tcol,
+                          const ValRow<T>* __restrict__ svr, int32_t* __restrict__ tcol,
                           T* __restrict__ tval, int64_t* __restrict__ trowptr) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= nnz) return;
-  const int32_t k = perm[p];
-  tcol[p] = row[k];
-  tval[p] = val[k];
+  const ValRow<T> x = svr[p];
+  tcol[p] = x.r;
+  tval[p] = x.v;
   // every compacted row has at least one entry, so a row starts where the
   // sorted key changes
   if (p == 0 || skeys[p] != skeys[p - 1]) trowptr[skeys[p]] = p;
@@ -99,34 +111,34 @@ int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
     return hip_check(hipMemcpyAsync(Bt.rowptr.p, &z, sizeof(z), hipMemcpyHostToDevice, s),
                      "rowptr");
   }
-  // sort scratch: keys in/out, index in/out, row of each nonzero, cub temp
+  // sort scratch: keys in/out, (value, row) in/out, cub temp
   const int end_bit = end_bit_for(touched);
   size_t temp_bytes = 0;
   if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(
                           nullptr, temp_bytes, static_cast<const int32_t*>(nullptr),
-                          static_cast<int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
-                          static_cast<int32_t*>(nullptr), int(B.nnz), 0, end_bit, s),
+                          static_cast<int32_t*>(nullptr), static_cast<const ValRow<T>*>(nullptr),
+                          static_cast<ValRow<T>*>(nullptr), int(B.nnz), 0, end_bit, s),
                       "sort size")))
     return st;
-  const size_t n4 = (size_t(B.nnz) * sizeof(int32_t) + 255) & ~size_t(255);
-  if ((st = ensure(c, c->tbuf, 5 * n4 + temp_bytes + 256))) return st;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t n4 = al(size_t(B.nnz) * sizeof(int32_t));
+  const size_t nv = al(size_t(B.nnz) * sizeof(ValRow<T>));
+  if ((st = ensure(c, c->tbuf, 2 * n4 + 2 * nv + temp_bytes + 256))) return st;
   char* base = c->tbuf.as<char>();
   int32_t* keys = reinterpret_cast<int32_t*>(base);
   int32_t* skeys = reinterpret_cast<int32_t*>(base + n4);
-  int32_t* idx = reinterpret_cast<int32_t*>(base + 2 * n4);
-  int32_t* perm = reinterpret_cast<int32_t*>(base + 3 * n4);
-  int32_t* row = reinterpret_cast<int32_t*>(base + 4 * n4);
-  void* temp = base + 5 * n4;
-  k_keys<<<blocks_for(c->n_vert * kWave, 256), 256, 0, s>>>(c->n_vert, B.rowptr.as<int64_t>(),
-                                                    B.col.as<int32_t>(), c->cidx.as<int64_t>(),
-                                                    keys, idx, row);
-  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx, perm,
+  ValRow<T>* vr = reinterpret_cast<ValRow<T>*>(base + 2 * n4);
+  ValRow<T>* svr = reinterpret_cast<ValRow<T>*>(base + 2 * n4 + nv);
+  void* temp = base + 2 * n4 + 2 * nv;
+  k_keys<T><<<blocks_for(c->n_vert * kWave, 256), 256, 0, s>>>(
+      c->n_vert, B.rowptr.as<int64_t>(), B.col.as<int32_t>(), B.val.as<T>(),
+      c->cidx.as<int64_t>(), keys, vr);
+  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, vr, svr,
                                                          int(B.nnz), 0, end_bit, s),
                       "radix sort")))
     return st;
-  k_tgather<T><<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, skeys, perm, row, B.val.as<T>(),
-                                                      Bt.col.as<int32_t>(), Bt.val.as<T>(),
-                                                      Bt.rowptr.as<int64_t>());
+  k_tgather<T><<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, skeys, svr, Bt.col.as<int32_t>(),
+                                                      Bt.val.as<T>(), Bt.rowptr.as<int64_t>());
   return hip_check(hipGetLastError(), "transpose launch");
 }
 

@@ -50,7 +50,10 @@ namespace ibvt {
 
 namespace {
 
-constexpr int kTreeStack = 64;
+// Depth-first stack of the tree search: one pending sibling per level at
+// most, and the tree has at most 2^31 leaves (31 levels).
+constexpr int kTreeStack = 32;
+constexpr int kSearchThreads = 256;
 
 inline unsigned blocks_for(int64_t n, int threads) {
   return unsigned(ceil_div(n > 0 ? n : 1, threads));
@@ -206,7 +209,7 @@ __device__ __forceinline__ bool boxes_meet(const double mn[3], const double mx[3
 // closed double box meets the solid tet's; FILL = true: write them at
 // off[s] in traversal (Morton) order.
 template <bool FILL>
-__global__ __launch_bounds__(256) void k_search(int64_t n_s, const double* __restrict__ sbox,
+__global__ __launch_bounds__(kSearchThreads) void k_search(int64_t n_s, const double* __restrict__ sbox,
                                                 int64_t P, int64_t n_f,
                                                 const float* __restrict__ tree,
                                                 const int32_t* __restrict__ order,
@@ -214,6 +217,9 @@ __global__ __launch_bounds__(256) void k_search(int64_t n_s, const double* __res
                                                 int64_t* __restrict__ cnt,
                                                 const int64_t* __restrict__ off,
                                                 int32_t* __restrict__ pf, unsigned* flags) {
+  // the stacks live in LDS, entry k of thread j at k * kSearchThreads + j
+  __shared__ uint32_t s_stack[kTreeStack * kSearchThreads];
+  uint32_t* stack = s_stack + threadIdx.x;
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= n_s) return;
   double mn[3], mx[3];
@@ -221,13 +227,12 @@ __global__ __launch_bounds__(256) void k_search(int64_t n_s, const double* __res
     mn[e] = sbox[8 * s + e];
     mx[e] = sbox[8 * s + 4 + e];
   }
-  int64_t stack[kTreeStack];
   int top = 0;
   int64_t found = 0;
   int64_t pos = FILL ? off[s] : 0;
-  if (boxes_meet(mn, mx, tree)) stack[top++] = 0;
+  if (boxes_meet(mn, mx, tree)) stack[kSearchThreads * top++] = 0u;
   while (top > 0) {
-    const int64_t node = stack[--top];
+    const int64_t node = stack[kSearchThreads * --top];
     if (node >= P - 1) {
       const int64_t i = node - (P - 1);
       if (i >= n_f) continue;
@@ -246,8 +251,8 @@ __global__ __launch_bounds__(256) void k_search(int64_t n_s, const double* __res
       atomicOr(flags, kFlagCapacity);
       return;
     }
-    if (gr) stack[top++] = r;
-    if (gl) stack[top++] = l;
+    if (gr) stack[kSearchThreads * top++] = uint32_t(r);
+    if (gl) stack[kSearchThreads * top++] = uint32_t(l);
   }
   if (!FILL) cnt[s] = found;
 }
@@ -717,7 +722,7 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
   {
     ProfScope ps("tree_search", s);
     if (n_s > 0)
-      k_search<false><<<blocks_for(n_s, 256), 256, 0, s>>>(
+      k_search<false><<<blocks_for(n_s, kSearchThreads), kSearchThreads, 0, s>>>(
           n_s, c->rowbox.as<double>(), c->ftree_leaves, c->n_ftet, c->ftree.as<float>(),
           c->forder.as<int32_t>(), c->fbox.as<double>(), c->cnt.as<int64_t>(), nullptr, nullptr,
           flags);
@@ -737,7 +742,7 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
   {
     ProfScope ps("tree_search", s);
     if (n_s > 0)
-      k_search<true><<<blocks_for(n_s, 256), 256, 0, s>>>(
+      k_search<true><<<blocks_for(n_s, kSearchThreads), kSearchThreads, 0, s>>>(
           n_s, c->rowbox.as<double>(), c->ftree_leaves, c->n_ftet, c->ftree.as<float>(),
           c->forder.as<int32_t>(), c->fbox.as<double>(), nullptr, c->pair_off.as<int64_t>(),
           c->owner.as<int32_t>(), flags);
