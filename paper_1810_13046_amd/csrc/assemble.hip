@@ -29,8 +29,8 @@ namespace ibvt {
 
 namespace {
 
-constexpr int kRowNodes = 512;  // LDS box nodes per wave per pass in k_rows
-constexpr int kRowMap = 512;    // slots of the slot → tet map of k_rows (one window)
+constexpr int kRowNodes = 256;  // LDS box nodes per row per pass in k_rows
+constexpr int kRowMap = 256;    // slots of the slot → tet map of a k_rows row (one window)
 constexpr int kRowBatch = 8;    // steps of 8 pairs whose loads k_rows issues together
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
@@ -569,14 +569,15 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t q, uint32_t m) {
 }
 
 // Gather the pieces of the incident tets into the row's node box, kept in
-// LDS kRowNodes nodes at a time.  The row's pairs (incident tets ascending,
-// then cells) are taken 8 per step, one value per lane (lane = 8·pair +
-// corner); the 8 pairs are added to the box one after another, and the 8
-// corners of one pair are distinct nodes, so every node sums its
-// contributions in pair order (deterministic).  Per batch of 64 incident
-// tets, each tet's offsets are set up once in LDS and a slot → tet map
-// replaces a search per step.  Touched nodes are written column-sorted at
-// tmp_off[w].
+// LDS kRowNodes nodes at a time.  Each wavefront serves two rows, one per
+// 32-lane half, so the memory latency of one row's steps overlaps the
+// other's.  A row's pairs (incident tets ascending, then cells) are taken 4
+// per step, one value per lane (lane = 32·half + 8·pair + corner); the 4
+// pairs are added to the box one after another, and the 8 corners of one
+// pair are distinct nodes, so every node sums its contributions in pair
+// order (deterministic).  Per batch of 32 incident tets, each tet's offsets
+// are set up once in LDS and a slot → tet map replaces a search per step.
+// Touched nodes are written column-sorted at tmp_off[w].
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
     int64_t n_v, int64_t n_t, int64_t n_pairs, const int64_t* __restrict__ vt_ptr,
@@ -585,46 +586,53 @@ __global__ __launch_bounds__(256) void k_rows(
     const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
     const RowBox* __restrict__ box, const int64_t* __restrict__ tmp_off,
     int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz) {
-  __shared__ double s_acc[4][kRowNodes];  // summed in double in both precisions
-  __shared__ uint8_t s_flag[4][kRowNodes];
-  __shared__ int4 s_m0[4][kWave], s_m1[4][kWave];
-  __shared__ int s_ex[4][kWave];
-  __shared__ uint8_t s_map[4][kRowMap];
-  const int wib = threadIdx.x / kWave;
-  const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  constexpr int H = kWave / 2;                // lanes per row
+  __shared__ double s_acc[8][kRowNodes];      // summed in double in both precisions
+  __shared__ uint8_t s_flag[8][kRowNodes];
+  __shared__ int4 s_m0[8][H], s_m1[8][H];
+  __shared__ int s_ex[8][H];
+  __shared__ uint8_t s_map[8][kRowMap];
   const int lane = lane_id();
-  if (w >= 3 * n_v) return;
-  double* acc = s_acc[wib];
-  uint8_t* flg = s_flag[wib];
-  int4* M0 = s_m0[wib];
-  int4* M1 = s_m1[wib];
-  int* EX = s_ex[wib];
-  uint8_t* smap = s_map[wib];
-  const int d = int(w / n_v);
-  const int64_t i = w - int64_t(d) * n_v;
-  const RowBox b = box[w];
+  const int h = lane / H, hl = lane % H;
+  const int slot = 2 * (threadIdx.x / kWave) + h;  // this row's LDS slot in the block
+  const int64_t w = 2 * ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave) + h;
+  const bool live = w < 3 * n_v;
+  double* acc = s_acc[slot];
+  uint8_t* flg = s_flag[slot];
+  int4* M0 = s_m0[slot];
+  int4* M1 = s_m1[slot];
+  int* EX = s_ex[slot];
+  uint8_t* smap = s_map[slot];
+  const int d = live ? int(w / n_v) : 0;
+  const int64_t i = live ? w - int64_t(d) * n_v : 0;
+  RowBox b{};
+  if (live) b = box[w];
   const int bn0 = b.n[0], bn1 = b.n[1];
-  const int64_t total = int64_t(bn0) * bn1 * b.n[2];
-  int64_t outpos = tmp_off[w];
+  const int64_t total = live ? int64_t(bn0) * bn1 * b.n[2] : 0;
+  int64_t outpos = live ? tmp_off[w] : 0;
   const int64_t start = outpos;
   const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
-  const int64_t beg = vt_ptr[i], end = vt_ptr[i + 1];
-  const int qq = lane >> 3, jj = lane & 7;
+  const int64_t beg = live ? vt_ptr[i] : 0, end = live ? vt_ptr[i + 1] : 0;
+  const int qq = hl >> 3, jj = hl & 7;
   // box-linear offset of this lane's corner
   const int coff = (jj & 1) + bn0 * (((jj >> 1) & 1) + bn1 * (jj >> 2));
   const int64_t vplane = n_pairs * 8;
-  for (int64_t c0 = 0; c0 < total; c0 += kRowNodes) {
-    const int span = int(min<int64_t>(kRowNodes, total - c0));
-    for (int k = lane; k < span; k += kWave) {
+  // loop bounds common to both halves (each half masks its own work)
+  const int64_t total_max = max(total, __shfl_xor(total, H, kWave));
+  const int64_t ntet = end - beg;
+  const int64_t ntet_max = max(ntet, __shfl_xor(ntet, H, kWave));
+  for (int64_t c0 = 0; c0 < total_max; c0 += kRowNodes) {
+    const int span = int(max<int64_t>(0, min<int64_t>(kRowNodes, total - c0)));
+    for (int k = hl; k < span; k += H) {
       acc[k] = 0.0;
       flg[k] = 0;
     }
-    for (int64_t kb = beg; kb < end; kb += kWave) {
-      const int nk = int(min<int64_t>(kWave, end - kb));
+    for (int64_t kb0 = 0; kb0 < ntet_max; kb0 += H) {
+      const int nk = int(max<int64_t>(0, min<int64_t>(H, ntet - kb0)));
       int cnt = 0;
       wave_lds_sync();
-      if (lane < nk) {
-        const int64_t t = vt_tet[kb + lane];
+      if (hl < nk) {
+        const int64_t t = vt_tet[beg + kb0 + hl];
         const int64_t tc = int64_t(d) * n_t + t;
         const CellRange r = rng[tc];
         const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
@@ -638,39 +646,41 @@ __global__ __launch_bounds__(256) void k_rows(
                                              int64_t(bn1) * (r.lo[2] - b.lo[2])) -
                              c0);
         cnt = r.n[0] * r.n[1] * r.n[2];
-        M0[lane] = make_int4(int(pbase & 0xffffffffll), int(pbase >> 32),
-                             int(kbase & 0xffffffffll), int(kbase >> 32));
-        M1[lane] = make_int4(r.n[0] | (r.n[1] << 16), off0,
-                             int(magic_div(uint32_t(max(r.n[0], 1)))),
-                             int(magic_div(uint32_t(max(r.n[1], 1)))));
+        M0[hl] = make_int4(int(pbase & 0xffffffffll), int(pbase >> 32),
+                           int(kbase & 0xffffffffll), int(kbase >> 32));
+        M1[hl] = make_int4(r.n[0] | (r.n[1] << 16), off0,
+                           int(magic_div(uint32_t(max(r.n[0], 1)))),
+                           int(magic_div(uint32_t(max(r.n[1], 1)))));
       }
       int incl = cnt;
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int y = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += y;
+      for (int o = 1; o < H; o <<= 1) {
+        const int y = __shfl_up(incl, o, H);
+        if (hl >= o) incl += y;
       }
       const int excl = incl - cnt;
-      EX[lane] = excl;
-      const int tot = __shfl(incl, kWave - 1, kWave);
+      EX[hl] = excl;
+      const int tot = __shfl(incl, H - 1, H);
+      const int tot_max = max(tot, __shfl_xor(tot, H, kWave));
       // slots in windows of kRowMap: the map names each slot's tet
-      for (int w0 = 0; w0 < tot; w0 += kRowMap) {
+      for (int w0 = 0; w0 < tot_max; w0 += kRowMap) {
         wave_lds_sync();
         {
           const int a = max(excl, w0), e = min(incl, w0 + kRowMap);
-          for (int sl = a; sl < e; ++sl) smap[sl - w0] = uint8_t(lane);
+          for (int sl = a; sl < e; ++sl) smap[sl - w0] = uint8_t(hl);
         }
         wave_lds_sync();
         const int wend = min(tot, w0 + kRowMap);
-        // kRowBatch steps of 8 pairs at a time: their loads are issued
-        // together, then the steps are added in slot order as before
-        for (int s0 = w0; s0 < wend; s0 += 8 * kRowBatch) {
+        const int wend_max = max(wend, __shfl_xor(wend, H, kWave));
+        // kRowBatch steps of 4 pairs per row at a time: their loads are
+        // issued together, then the steps are added in slot order
+        for (int s0 = w0; s0 < wend_max; s0 += 4 * kRowBatch) {
           bool add[kRowBatch];
           int loc[kRowBatch];
           uint8_t kraw[kRowBatch];
           T vraw[kRowBatch];
 #pragma unroll
-          for (int b = 0; b < kRowBatch; ++b) {
-            const int sl = s0 + 8 * b + qq;
+          for (int bb = 0; bb < kRowBatch; ++bb) {
+            const int sl = s0 + 4 * bb + qq;
             bool ok = false;
             int lin = 0;
             int64_t ko = 0, vo = 0;
@@ -697,24 +707,24 @@ __global__ __launch_bounds__(256) void k_rows(
             }
             // loaded by every lane (entry 0 stands in when there is none),
             // so the loads of the whole batch are in flight together
-            kraw[b] = keep[ko];
-            vraw[b] = pval[vo];
-            add[b] = ok;
-            loc[b] = lin;
+            kraw[bb] = keep[ko];
+            vraw[bb] = pval[vo];
+            add[bb] = ok;
+            loc[bb] = lin;
           }
 #pragma unroll
-          for (int b = 0; b < kRowBatch; ++b) {
-            add[b] = add[b] && kraw[b] != 0;
-            if (add[b]) flg[loc[b]] = 1;
+          for (int bb = 0; bb < kRowBatch; ++bb) {
+            add[bb] = add[bb] && kraw[bb] != 0;
+            if (add[bb]) flg[loc[bb]] = 1;
           }
 #pragma unroll
-          for (int b = 0; b < kRowBatch; ++b) {
-            if (s0 + 8 * b >= wend) break;
+          for (int bb = 0; bb < kRowBatch; ++bb) {
+            if (s0 + 4 * bb >= wend_max) break;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 4; ++u) {
               wave_lds_sync();
-              if (add[b] && qq == u)
-                __hip_atomic_fetch_add(&acc[loc[b]], double(vraw[b]), __ATOMIC_RELAXED,
+              if (add[bb] && qq == u)
+                __hip_atomic_fetch_add(&acc[loc[bb]], double(vraw[bb]), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
           }
@@ -722,10 +732,11 @@ __global__ __launch_bounds__(256) void k_rows(
       }
     }
     wave_lds_sync();
-    for (int k0 = 0; k0 < span; k0 += kWave) {
-      const int k = k0 + lane;
+    const int span_max = max(span, __shfl_xor(span, H, kWave));
+    for (int k0 = 0; k0 < span_max; k0 += H) {
+      const int k = k0 + hl;
       const bool tch = k < span && flg[k] != 0;
-      const uint64_t m = ballot64(tch);
+      const uint32_t m = uint32_t(ballot64(tch) >> (H * h));
       if (tch) {
         // the box lies inside the lattice, whose node count fits int32
         const uint32_t lin = uint32_t(c0 + k);
@@ -734,15 +745,15 @@ __global__ __launch_bounds__(256) void k_rows(
         const int64_t gx = b.lo[0] + int64_t(lin - r * uint32_t(bn0));
         const int64_t gy = b.lo[1] + int64_t(r - zq * uint32_t(bn1));
         const int64_t gz = b.lo[2] + int64_t(zq);
-        const int64_t pos = outpos + rank_below(m);
+        const int64_t pos = outpos + __popc(m & ((1u << hl) - 1u));
         tmp_col[pos] = int32_t(gx + NX * (gy + NY * gz));
         tmp_val[pos] = T(acc[k]);
       }
-      outpos += popc64(m);
+      outpos += __popc(m);
     }
     wave_lds_sync();
   }
-  if (lane == 0) rownnz[w] = outpos - start;
+  if (live && hl == 0) rownnz[w] = outpos - start;
 }
 
 // Copy each row from the box-capacity scratch into the CSR arrays.
@@ -1022,10 +1033,10 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     return st;
   if ((st = ensure(c, c->rowtmpcol, size_t(tmp_total + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->rowtmpval, size_t(tmp_total + 1) * sizeof(T)))) return st;
-  const unsigned row_blocks = blocks_for(3 * n_v * kWave, 256);
   {
     ProfScope ps("rows_gather", s);
-    k_rows<T><<<row_blocks, 256, 0, s>>>(
+    // two rows per wavefront
+    k_rows<T><<<blocks_for(ceil_div(3 * n_v, 2) * kWave, 256), 256, 0, s>>>(
         n_v, n_t, n_pairs, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
         c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
         c->ld, c->rowbox.as<RowBox>(), c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(),
@@ -1050,7 +1061,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   }
   {
     ProfScope ps("rows_compact", s);
-    k_rows_compact<T><<<row_blocks, 256, 0, s>>>(
+    k_rows_compact<T><<<blocks_for(3 * n_v * kWave, 256), 256, 0, s>>>(
         n_v, c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(), c->rowtmpval.as<T>(),
         c->B[0].rowptr.as<int64_t>(), c->B[1].rowptr.as<int64_t>(), c->B[2].rowptr.as<int64_t>(),
         c->B[0].col.as<int32_t>(), c->B[1].col.as<int32_t>(), c->B[2].col.as<int32_t>(),
