@@ -29,8 +29,8 @@ namespace ibvt {
 
 namespace {
 
-constexpr int kRowNodes = 256;  // LDS box nodes per row per pass in k_rows
-constexpr int kRowMap = 256;    // slots of the slot → tet map of a k_rows row (one window)
+constexpr int kRowNodes = 128;  // LDS box nodes per row per pass in k_rows
+constexpr int kRowMap = 128;    // slots of the slot → tet map of a k_rows row (one window)
 constexpr int kRowBatch = 8;    // steps of 8 pairs whose loads k_rows issues together
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
@@ -568,16 +568,26 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t q, uint32_t m) {
   return m ? __umulhi(q, m) : q;
 }
 
+constexpr int kRowsPerWave = 4;  // rows served by one wavefront in k_rows
+
+// Maximum of x over the kRowsPerWave row groups of a wavefront (lanes
+// hl, hl + H, ...), for loop bounds common to all of them.
+__device__ __forceinline__ int64_t rows_max(int64_t x) {
+  for (int o = kWave / kRowsPerWave; o < kWave; o <<= 1) x = max(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+
 // Gather the pieces of the incident tets into the row's node box, kept in
-// LDS kRowNodes nodes at a time.  Each wavefront serves two rows, one per
-// 32-lane half, so the memory latency of one row's steps overlaps the
-// other's.  A row's pairs (incident tets ascending, then cells) are taken 4
-// per step, one value per lane (lane = 32·half + 8·pair + corner); the 4
-// pairs are added to the box one after another, and the 8 corners of one
-// pair are distinct nodes, so every node sums its contributions in pair
-// order (deterministic).  Per batch of 32 incident tets, each tet's offsets
-// are set up once in LDS and a slot → tet map replaces a search per step.
-// Touched nodes are written column-sorted at tmp_off[w].
+// LDS kRowNodes nodes at a time.  Each wavefront serves kRowsPerWave rows,
+// H = 64 / kRowsPerWave lanes each, so the memory latency of one row's steps
+// overlaps the others'.  A row's pairs (incident tets ascending, then cells)
+// are taken H / 8 per step, one value per lane (lane = H·row + 8·pair +
+// corner); the pairs of a step are added to the box one after another, and
+// the 8 corners of one pair are distinct nodes, so every node sums its
+// contributions in pair order (deterministic).  Per batch of H incident
+// tets, each tet's offsets are set up once in LDS and a slot → tet map
+// replaces a search per step.  Touched nodes are written column-sorted at
+// tmp_off[w].
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
     int64_t n_v, int64_t n_t, int64_t n_pairs, const int64_t* __restrict__ vt_ptr,
@@ -586,16 +596,19 @@ __global__ __launch_bounds__(256) void k_rows(
     const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
     const RowBox* __restrict__ box, const int64_t* __restrict__ tmp_off,
     int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz) {
-  constexpr int H = kWave / 2;                // lanes per row
-  __shared__ double s_acc[8][kRowNodes];      // summed in double in both precisions
-  __shared__ uint8_t s_flag[8][kRowNodes];
-  __shared__ int4 s_m0[8][H], s_m1[8][H];
-  __shared__ int s_ex[8][H];
-  __shared__ uint8_t s_map[8][kRowMap];
+  constexpr int H = kWave / kRowsPerWave;    // lanes per row
+  constexpr int PS = H / 8;                   // pairs per step
+  constexpr int RB = 4 * kRowsPerWave;        // rows per block
+  __shared__ double s_acc[RB][kRowNodes];     // summed in double in both precisions
+  __shared__ uint8_t s_flag[RB][kRowNodes];
+  __shared__ int4 s_m0[RB][H], s_m1[RB][H];
+  __shared__ int s_ex[RB][H];
+  __shared__ uint8_t s_map[RB][kRowMap];
   const int lane = lane_id();
   const int h = lane / H, hl = lane % H;
-  const int slot = 2 * (threadIdx.x / kWave) + h;  // this row's LDS slot in the block
-  const int64_t w = 2 * ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave) + h;
+  const int slot = kRowsPerWave * (threadIdx.x / kWave) + h;  // this row's LDS slot
+  const int64_t w =
+      kRowsPerWave * ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave) + h;
   const bool live = w < 3 * n_v;
   double* acc = s_acc[slot];
   uint8_t* flg = s_flag[slot];
@@ -618,9 +631,9 @@ __global__ __launch_bounds__(256) void k_rows(
   const int coff = (jj & 1) + bn0 * (((jj >> 1) & 1) + bn1 * (jj >> 2));
   const int64_t vplane = n_pairs * 8;
   // loop bounds common to both halves (each half masks its own work)
-  const int64_t total_max = max(total, __shfl_xor(total, H, kWave));
+  const int64_t total_max = rows_max(total);
   const int64_t ntet = end - beg;
-  const int64_t ntet_max = max(ntet, __shfl_xor(ntet, H, kWave));
+  const int64_t ntet_max = rows_max(ntet);
   for (int64_t c0 = 0; c0 < total_max; c0 += kRowNodes) {
     const int span = int(max<int64_t>(0, min<int64_t>(kRowNodes, total - c0)));
     for (int k = hl; k < span; k += H) {
@@ -660,7 +673,7 @@ __global__ __launch_bounds__(256) void k_rows(
       const int excl = incl - cnt;
       EX[hl] = excl;
       const int tot = __shfl(incl, H - 1, H);
-      const int tot_max = max(tot, __shfl_xor(tot, H, kWave));
+      const int tot_max = int(rows_max(int64_t(tot)));
       // slots in windows of kRowMap: the map names each slot's tet
       for (int w0 = 0; w0 < tot_max; w0 += kRowMap) {
         wave_lds_sync();
@@ -670,17 +683,17 @@ __global__ __launch_bounds__(256) void k_rows(
         }
         wave_lds_sync();
         const int wend = min(tot, w0 + kRowMap);
-        const int wend_max = max(wend, __shfl_xor(wend, H, kWave));
+        const int wend_max = int(rows_max(int64_t(wend)));
         // kRowBatch steps of 4 pairs per row at a time: their loads are
         // issued together, then the steps are added in slot order
-        for (int s0 = w0; s0 < wend_max; s0 += 4 * kRowBatch) {
+        for (int s0 = w0; s0 < wend_max; s0 += PS * kRowBatch) {
           bool add[kRowBatch];
           int loc[kRowBatch];
           uint8_t kraw[kRowBatch];
           T vraw[kRowBatch];
 #pragma unroll
           for (int bb = 0; bb < kRowBatch; ++bb) {
-            const int sl = s0 + 4 * bb + qq;
+            const int sl = s0 + PS * bb + qq;
             bool ok = false;
             int lin = 0;
             int64_t ko = 0, vo = 0;
@@ -719,9 +732,9 @@ __global__ __launch_bounds__(256) void k_rows(
           }
 #pragma unroll
           for (int bb = 0; bb < kRowBatch; ++bb) {
-            if (s0 + 4 * bb >= wend_max) break;
+            if (s0 + PS * bb >= wend_max) break;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < PS; ++u) {
               wave_lds_sync();
               if (add[bb] && qq == u)
                 __hip_atomic_fetch_add(&acc[loc[bb]], double(vraw[bb]), __ATOMIC_RELAXED,
@@ -732,11 +745,11 @@ __global__ __launch_bounds__(256) void k_rows(
       }
     }
     wave_lds_sync();
-    const int span_max = max(span, __shfl_xor(span, H, kWave));
+    const int span_max = int(rows_max(int64_t(span)));
     for (int k0 = 0; k0 < span_max; k0 += H) {
       const int k = k0 + hl;
       const bool tch = k < span && flg[k] != 0;
-      const uint32_t m = uint32_t(ballot64(tch) >> (H * h));
+      const uint32_t m = uint32_t(ballot64(tch) >> (H * h)) & uint32_t((uint64_t(1) << H) - 1);
       if (tch) {
         // the box lies inside the lattice, whose node count fits int32
         const uint32_t lin = uint32_t(c0 + k);
@@ -1035,8 +1048,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->rowtmpval, size_t(tmp_total + 1) * sizeof(T)))) return st;
   {
     ProfScope ps("rows_gather", s);
-    // two rows per wavefront
-    k_rows<T><<<blocks_for(ceil_div(3 * n_v, 2) * kWave, 256), 256, 0, s>>>(
+    // kRowsPerWave rows per wavefront
+    k_rows<T><<<blocks_for(ceil_div(3 * n_v, kRowsPerWave) * kWave, 256), 256, 0, s>>>(
         n_v, n_t, n_pairs, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
         c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
         c->ld, c->rowbox.as<RowBox>(), c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(),
