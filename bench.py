@@ -132,9 +132,10 @@ class Step:
         c.velocity(self.u, mass=self.mass, rtol=1e-10, maxit=500, out=self.us)
         c.force(self.f_s, self.ff, alpha=1.0)
         g_us = self.us - self.u_t
-        c.velocity_vjp(g_us, u_f=self.u, u_s=self.us, mass=self.mass, g_uf=self.g_uf,
-                       g_X=self.g_X, rtol=1e-10, maxit=500)
-        c.force_vjp(self.u, f_s=self.f_s, alpha=1.0, g_fs=self.g_fs, g_X=self.g_X)
+        # both adjoints (velocity: cotangent g_us; force: cotangent u_f) in
+        # one call, so their shape terms share one pass over the moments
+        c.vjp(g_us, self.u, u_f=self.u, u_s=self.us, f_s=self.f_s, mass=self.mass, alpha=1.0,
+              g_uf=self.g_uf, g_fs=self.g_fs, g_X=self.g_X, rtol=1e-10, maxit=500)
 
 
 def make_inputs_planar(dev):
@@ -223,8 +224,8 @@ class UStep:
         c.reassemble(self.X)
         c.velocity(self.u, mass="consistent", rtol=1e-10, maxit=500, out=self.us)
         c.force(self.f_s, self.ff, alpha=1.0)
-        c.velocity_vjp(self.us, mass="consistent", g_uf=self.g_uf, rtol=1e-10, maxit=500)
-        c.force_vjp(self.u, alpha=1.0, g_fs=self.g_fs)
+        c.vjp(self.us, self.u, mass="consistent", alpha=1.0, g_uf=self.g_uf, g_fs=self.g_fs,
+              rtol=1e-10, maxit=500)
 
 
 def unstructured_oracle_rate(W, n_sample):

@@ -299,6 +299,27 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
 int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s,
                        double alpha, void* g_fs, double* g_X, hipStream_t stream);
 
+/*
+ * transfer_vjp — both reverse-mode calls above in one: the effect of
+ *   transfer_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf,
+ *   g_X) followed by transfer_force_vjp(c, g_ff, f_s, alpha, g_fs, g_X),
+ *   for a caller that needs the adjoints of both transfers (the velocity
+ *   and the force of one coupling step, as in Section 3's loop).  When the
+ *   piece moments are stored (3D grid couplings without
+ *   IBVT_NO_PIECE_STORE) the two shape-derivative contractions are taken in
+ *   one pass over them; otherwise the two calls' paths run one after the
+ *   other.  Arguments, layouts, ownership and nullability as in the two
+ *   calls; g_X (nullable) receives both contributions (sums may differ from
+ *   the two separate calls by rounding).
+ *   Errors: those of the two calls (IBVT_E_INVALID, IBVT_E_NOT_CONVERGED,
+ *   IBVT_E_UNSUPPORTED, IBVT_E_HIP); nothing is accumulated when an argument
+ *   check fails.
+ */
+int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], const void* u_s,
+                 int mass, double cg_rtol, int cg_maxit, void* const g_uf[3],
+                 const void* const g_ff[3], const void* f_s, double alpha, void* g_fs,
+                 double* g_X, hipStream_t stream);
+
 /* coupling_info — fill *info (host).  Errors: IBVT_E_INVALID. */
 int coupling_info(const ibvt_coupling* c, ibvt_info* info);
 

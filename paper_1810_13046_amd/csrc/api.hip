@@ -501,9 +501,12 @@ int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double
   return apply_Bt(c, f_s, f_f, alpha, stream);
 }
 
-int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
-                          const void* u_s, int mass, double cg_rtol, int cg_maxit,
-                          void* const g_uf[3], double* g_X, hipStream_t stream) {
+namespace {
+
+// Argument checks of transfer_velocity_vjp (no work done).
+int check_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
+                       const void* u_s, int mass, double cg_rtol, int cg_maxit,
+                       void* const g_uf[3], double* g_X) {
   if (!c || !g_us) return set_error(IBVT_E_INVALID, "NULL argument");
   if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
     return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
@@ -518,19 +521,64 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
   if (g_uf)
     for (int d = 0; d < c->ncomp; ++d)
       if (!g_uf[d]) return set_error(IBVT_E_INVALID, "NULL g_uf component");
+  if (mass == IBVT_CONSISTENT) {
+    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
+    if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad CG rtol/maxit");
+  }
+  return IBVT_OK;
+}
+
+// Argument checks of transfer_force_vjp (no work done).
+int check_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s, double alpha,
+                    double* g_X) {
+  if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
+  for (int d = 0; d < c->ncomp; ++d)
+    if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
+  if (g_X && c->unstructured)
+    return set_error(IBVT_E_UNSUPPORTED, "no shape derivative for an unstructured background");
+  if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
+  if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
+  return IBVT_OK;
+}
+
+// z = S^{-1} g_us into c->zbuf, and g_uf += B^T z.
+int velocity_adjoint(ibvt_coupling* c, const void* g_us, int mass, double cg_rtol, int cg_maxit,
+                     void* const g_uf[3], hipStream_t stream, void** z_out) {
   const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
-  // z = S^{-1} g_us lives in its own buffer (the shape kernel reuses work2)
+  // z lives in its own buffer (the shape kernels reuse work2)
   int st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize);
   if (st) return st;
   void* z = c->zbuf.p;
   if (mass == IBVT_LUMPED) {
     if ((st = lumped_solve(c, g_us, z, stream))) return st;
-  } else {
-    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
-    if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad CG rtol/maxit");
-    if ((st = mass_solve(c, g_us, z, cg_rtol, cg_maxit, stream, nullptr, false))) return st;
+  } else if ((st = mass_solve(c, g_us, z, cg_rtol, cg_maxit, stream, nullptr, false))) {
+    return st;
   }
   if (g_uf && (st = apply_Bt(c, z, g_uf, 1.0, stream))) return st;
+  *z_out = z;
+  return IBVT_OK;
+}
+
+// g_fs += alpha B g_ff (B into scratch, then accumulate).
+int force_adjoint(ibvt_coupling* c, const void* const g_ff[3], double alpha, void* g_fs,
+                  hipStream_t stream) {
+  if (!g_fs) return IBVT_OK;
+  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+  int st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize);
+  if (st) return st;
+  if ((st = apply_B(c, g_ff, c->zbuf.p, false, stream))) return st;
+  return axpy_solid(c, alpha, c->zbuf.p, g_fs, stream);
+}
+
+}  // namespace
+
+int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
+                          const void* u_s, int mass, double cg_rtol, int cg_maxit,
+                          void* const g_uf[3], double* g_X, hipStream_t stream) {
+  int st = check_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf, g_X);
+  if (st) return st;
+  void* z = nullptr;
+  if ((st = velocity_adjoint(c, g_us, mass, cg_rtol, cg_maxit, g_uf, stream, &z))) return st;
   if (g_X) {
     const int m = mass == IBVT_CONSISTENT ? 1 : 0;
     st = c->dim == 2 ? shape_gradient_2d(c, z, u_f, u_s, m, 1.0, g_X, stream)
@@ -542,27 +590,35 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
 
 int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s,
                        double alpha, void* g_fs, double* g_X, hipStream_t stream) {
-  if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
-  for (int d = 0; d < c->ncomp; ++d)
-    if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
-  if (g_X && c->unstructured)
-    return set_error(IBVT_E_UNSUPPORTED, "no shape derivative for an unstructured background");
-  if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
-  if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
-  int st;
-  if (g_fs) {
-    // g_fs += alpha B g_ff: B into scratch, then accumulate
-    const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
-    if ((st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize))) return st;
-    if ((st = apply_B(c, g_ff, c->zbuf.p, false, stream))) return st;
-    if ((st = axpy_solid(c, alpha, c->zbuf.p, g_fs, stream))) return st;
-  }
+  int st = check_force_vjp(c, g_ff, f_s, alpha, g_X);
+  if (st) return st;
+  if ((st = force_adjoint(c, g_ff, alpha, g_fs, stream))) return st;
   if (g_X) {
     st = c->dim == 2 ? shape_gradient_2d(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream)
                      : shape_gradient(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream);
     if (st) return st;
   }
   return IBVT_OK;
+}
+
+int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], const void* u_s,
+                 int mass, double cg_rtol, int cg_maxit, void* const g_uf[3],
+                 const void* const g_ff[3], const void* f_s, double alpha, void* g_fs,
+                 double* g_X, hipStream_t stream) {
+  int st = check_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf, g_X);
+  if (st) return st;
+  if ((st = check_force_vjp(c, g_ff, f_s, alpha, g_X))) return st;
+  if (!(g_X && c->dim == 3 && c->mom_valid)) {
+    // no stored moments to share: the two calls
+    if ((st = transfer_force_vjp(c, g_ff, f_s, alpha, g_fs, g_X, stream))) return st;
+    return transfer_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf, g_X, stream);
+  }
+  // the force part first (its scratch is the buffer z then takes)
+  if ((st = force_adjoint(c, g_ff, alpha, g_fs, stream))) return st;
+  void* z = nullptr;
+  if ((st = velocity_adjoint(c, g_us, mass, cg_rtol, cg_maxit, g_uf, stream, &z))) return st;
+  const int m = mass == IBVT_CONSISTENT ? 1 : 0;
+  return shape_gradient_two(c, z, u_f, u_s, m, f_s, g_ff, alpha, g_X, stream);
 }
 
 int coupling_info(const ibvt_coupling* c, ibvt_info* info) {

@@ -101,15 +101,17 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
 // summed over the pieces of each (component, tet): one lane per (component,
 // tet) walks the tet's pairs in cell order, so the tet's geometry, vertex
 // weights and lattice are set up once per lane.  Sums in double to
-// pgt[(d, t)][12] (vertex a, axis k at a*3 + k).
-template <typename T>
+// pgt[(d, t)][12] (vertex a, axis k at a*3 + k).  With TWO, a second
+// contraction (solid weights z2, fluid field v, factor alpha2) is added from
+// the same moments: both adjoints' terms in one pass over the store.
+template <typename T, bool TWO>
 __global__ __launch_bounds__(256) void k_shape_tet(
     int64_t n_t, int64_t n_v, const int64_t* __restrict__ pair_off,
     const CellRange* __restrict__ rng, const uint8_t* __restrict__ keep,
     const T* __restrict__ pmom, const double* __restrict__ tetrec,
     const double* __restrict__ lat, const int32_t* __restrict__ tets, LatDesc ld,
-    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, double* __restrict__ pgt,
-    int dual) {
+    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, const T* __restrict__ z2,
+    const T* v0, const T* v1, const T* v2, double alpha2, double* __restrict__ pgt, int dual) {
   const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (w >= 3 * n_t) return;
   const int d = int(w / n_t);
@@ -124,6 +126,16 @@ __global__ __launch_bounds__(256) void k_shape_tet(
     T zl[4] = {zd[tv.x], zd[tv.y], zd[tv.z], zd[tv.w]};
     if (dual) dual_weights<T>(zl);
     const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
+    T zl2[4] = {T(0), T(0), T(0), T(0)};
+    const T* v = (d == 0) ? v0 : (d == 1 ? v1 : v2);
+    if (TWO) {
+      const T* z2d = z2 + int64_t(d) * n_v;
+      zl2[0] = z2d[tv.x];
+      zl2[1] = z2d[tv.y];
+      zl2[2] = z2d[tv.z];
+      zl2[3] = z2d[tv.w];
+      if (dual) dual_weights<T>(zl2);
+    }
     const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
     const double* L0 = lat + ld.off[3 * d + 0];
     const double* L1 = lat + ld.off[3 * d + 1];
@@ -162,6 +174,20 @@ __global__ __launch_bounds__(256) void k_shape_tet(
         const T ih = T(1.0 / (hi[k] - lo[k]));
 #pragma unroll
         for (int a = 0; a < 4; ++a) acc[a * 3 + k] += double(sc * ih * (A[a * 3 + k] + LG[a][k] * Bs));
+      }
+      if (TWO) {
+        T vl[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          vl[j] = v[n000 + (j & 1) + NX * (((j >> 1) & 1) + NY * (j >> 2))];
+        mom_shape<T>(M, LA, LG, zl2, vl, A, Bs);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T ih = T(1.0 / (hi[k] - lo[k]));
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            acc[a * 3 + k] += alpha2 * double(sc * ih * (A[a * 3 + k] + LG[a][k] * Bs));
+        }
       }
     }
   }
@@ -245,9 +271,12 @@ __global__ __launch_bounds__(256) void k_grad_gather(
     for (int e = 0; e < 3; ++e) gX[3 * a + e] += alpha * g[e];
 }
 
+// g_X += alpha (shape terms of (z, u) and the mass term of (z, us)) [+ alpha2
+// (shape terms of (z2, v)) when z2 is given; needs the stored moments].
 template <typename T>
 int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const void* us, int mass,
-                double alpha, double* gX, hipStream_t s) {
+                double alpha, double* gX, hipStream_t s, const void* z2 = nullptr,
+                const void* const* v = nullptr, double alpha2 = 0.0) {
   // per (component, tet) sums (double), then the per-pair terms of the
   // re-clipping path
   const size_t tc_bytes = (size_t(3 * c->n_tet + 1) * 12 * sizeof(double) + 255) & ~size_t(255);
@@ -260,12 +289,24 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
   if (c->mom_valid) {
     ProfScope ps("shape_moments", s);
-    if (c->n_tet > 0)
-      k_shape_tet<T><<<unsigned(ceil_div(3 * c->n_tet, 256)), 256, 0, s>>>(
+    const unsigned nb = unsigned(ceil_div(3 * c->n_tet, 256));
+    const T* zz = static_cast<const T*>(z);
+    const T* u0 = static_cast<const T*>(u[0]);
+    const T* u1 = static_cast<const T*>(u[1]);
+    const T* u2 = static_cast<const T*>(u[2]);
+    if (c->n_tet > 0 && z2)
+      k_shape_tet<T, true><<<nb, 256, 0, s>>>(
           c->n_tet, c->n_vert, c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
           c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(), c->lat.as<double>(),
-          c->tets.as<int32_t>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
-          static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), pgt, c->dual ? 1 : 0);
+          c->tets.as<int32_t>(), c->ld, zz, u0, u1, u2, static_cast<const T*>(z2),
+          static_cast<const T*>(v[0]), static_cast<const T*>(v[1]), static_cast<const T*>(v[2]),
+          alpha2 / alpha, pgt, c->dual ? 1 : 0);
+    else if (c->n_tet > 0)
+      k_shape_tet<T, false><<<nb, 256, 0, s>>>(
+          c->n_tet, c->n_vert, c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
+          c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(), c->lat.as<double>(),
+          c->tets.as<int32_t>(), c->ld, zz, u0, u1, u2, nullptr, nullptr, nullptr, nullptr, 0.0,
+          pgt, c->dual ? 1 : 0);
   } else {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
     ProfScope ps("shape_pairs", s);
@@ -309,6 +350,15 @@ int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], cons
                    int mass, double alpha, double* gX, hipStream_t s) {
   if (c->precision == IBVT_FP32_MIXED) return shape_typed<float>(c, z, u, us, mass, alpha, gX, s);
   return shape_typed<double>(c, z, u, us, mass, alpha, gX, s);
+}
+
+int shape_gradient_two(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
+                       int mass, const void* z2, const void* const v[3], double alpha2,
+                       double* gX, hipStream_t s) {
+  if (!c->mom_valid) return set_error(IBVT_E_INVALID, "the piece moments are not stored");
+  if (c->precision == IBVT_FP32_MIXED)
+    return shape_typed<float>(c, z, u, us, mass, 1.0, gX, s, z2, v, alpha2);
+  return shape_typed<double>(c, z, u, us, mass, 1.0, gX, s, z2, v, alpha2);
 }
 
 }  // namespace ibvt

@@ -197,5 +197,10 @@ int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream
 // grad.hip
 int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
                    int mass, double alpha, double* gX, hipStream_t s);
+// both adjoints' shape terms in one pass over the stored piece moments:
+// (z, u) with the mass term of (z, us), plus alpha2 · (z2, v)
+int shape_gradient_two(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
+                       int mass, const void* z2, const void* const v[3], double alpha2,
+                       double* gX, hipStream_t s);
 
 }  // namespace ibvt

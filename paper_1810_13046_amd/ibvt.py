@@ -37,6 +37,7 @@ EXPORTED = [
     "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
     "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
     "assemble_coupling_2d", "ibvt_lattice_coords_2d", "assemble_coupling_unstructured",
+    "transfer_vjp",
 ]
 
 
@@ -146,11 +147,13 @@ def load_library(path: str = LIB_PATH):
     lib.assemble_coupling_2d.argtypes = [P(_Grid2d), P(_Mesh2d), ctypes.c_int, u32, vp, P(vp)]
     lib.ibvt_lattice_coords_2d.argtypes = [P(_Grid2d), ctypes.c_int, ctypes.c_int, vp, P(i64)]
     lib.assemble_coupling_unstructured.argtypes = [P(_Mesh), P(_Mesh), ctypes.c_int, u32, vp, P(vp)]
+    lib.transfer_vjp.argtypes = [vp, vp, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int, P(vp),
+                                 P(vp), vp, dbl, vp, vp, vp]
     for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
                  "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d",
-                 "assemble_coupling_unstructured"):
+                 "assemble_coupling_unstructured", "transfer_vjp"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -488,6 +491,25 @@ class Coupling:
             float(alpha), _dev(g_fs, self.dtype, n, "g_fs") if g_fs is not None else None,
             _dev(g_X, torch.float64, self.dim * self.n_vert, "g_X") if g_X is not None else None,
             _stream(stream)), "transfer_force_vjp")
+
+    def vjp(self, g_us, g_ff, u_f=None, u_s=None, f_s=None, mass: str = "lumped",
+            alpha: float = 1.0, g_uf=None, g_fs=None, g_X=None, rtol: float = 1e-12,
+            maxit: int = 500, stream=None):
+        """velocity_vjp and force_vjp in one call (one pass over the stored
+        piece moments for both shape terms when they are kept)."""
+        import torch
+        n = self.nc * self.n_vert
+        uf = self._fluid_ptrs(u_f, "u_f") if u_f is not None else None
+        guf = self._fluid_ptrs(g_uf, "g_uf") if g_uf is not None else None
+        gff = self._fluid_ptrs(g_ff, "g_ff")
+        _check(_lib.transfer_vjp(
+            self.handle, _dev(g_us, self.dtype, n, "g_us"), uf,
+            _dev(u_s, self.dtype, n, "u_s") if u_s is not None else None,
+            LUMPED if mass == "lumped" else CONSISTENT, float(rtol), int(maxit), guf, gff,
+            _dev(f_s, self.dtype, n, "f_s") if f_s is not None else None, float(alpha),
+            _dev(g_fs, self.dtype, n, "g_fs") if g_fs is not None else None,
+            _dev(g_X, torch.float64, self.dim * self.n_vert, "g_X") if g_X is not None else None,
+            _stream(stream)), "transfer_vjp")
 
     def info(self) -> dict:
         i = _Info()
