@@ -23,7 +23,11 @@
 //  k_search<FILL>   per solid tet: depth-first traversal with an explicit
 //                   stack; leaves compared with the exact double boxes;
 //                   count pass, prefix sum, fill pass (traversal order).
-//  k_pairs_u<T>     one lane per (solid tet, fluid tet) pair: the solid tet
+//  k_sep_u / scan / k_list_u
+//                   candidates that a face plane of either tet separates
+//                   (all four vertices of one strictly outside a face of the
+//                   other) get keep = 0; the others are listed for the clip.
+//  k_pairs_u<T>     one lane per listed (solid tet, fluid tet) pair: the solid tet
 //                   clipped by the fluid tet's four half-spaces μ_k >= 0
 //                   (vertex graph in LDS, general planes), fanned into
 //                   sub-tetrahedra, ∫ λ_i μ_j integrated exactly on each
@@ -269,6 +273,55 @@ __device__ __forceinline__ int64_t pair_owner(int64_t p, int64_t n_s,
   return lo;
 }
 
+// True when the four vertices of tet record b lie strictly outside one
+// face plane of tet record a (a's hat λ_k < 0 at all of them, evaluated as
+// the clip evaluates it): the two tets are then disjoint.
+__device__ __forceinline__ bool face_separates(const double* __restrict__ a,
+                                               const double* __restrict__ b) {
+  double v[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) v[q][e] = b[3 * q + e];
+  const double a0[3] = {a[0], a[1], a[2]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* gk = a + 12 + 3 * k;
+    const double d0 = (k == 0) ? 1.0 : 0.0;
+    bool out = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      out &= d0 + gk[0] * (v[q][0] - a0[0]) + gk[1] * (v[q][1] - a0[1]) +
+                 gk[2] * (v[q][2] - a0[2]) < 0.0;
+    if (out) return true;
+  }
+  return false;
+}
+
+// One lane per candidate pair: cand = 0 (and keep = 0) when a face plane of
+// either tet separates them; those pairs are not clipped.
+__global__ void k_sep_u(int64_t n_pairs, int64_t n_s, const int64_t* __restrict__ off,
+                        const int32_t* __restrict__ pf, const double* __restrict__ srec,
+                        const double* __restrict__ frec, int32_t* __restrict__ cand,
+                        uint8_t* __restrict__ keep) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const int64_t s = pair_owner(p, n_s, off);
+  const int64_t f = pf[p];
+  const double* rs = srec + kURec * s;
+  const double* rf = frec + kURec * f;
+  const bool sep = face_separates(rf, rs) || face_separates(rs, rf);
+  cand[p] = sep ? 0 : 1;
+  if (sep) keep[p] = 0;
+}
+
+// list[pos[p]] = p for the pairs left to clip.
+__global__ void k_list_u(int64_t n_pairs, const int32_t* __restrict__ cand,
+                         const int64_t* __restrict__ pos, int32_t* __restrict__ list) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n_pairs && cand[p]) list[pos[p]] = int32_t(p);
+}
+
 // One lane per pair: the solid tet clipped by the fluid tet's four
 // half-spaces μ_k >= 0, fanned, and ∫ λ_i μ_j integrated exactly on each
 // sub-tetrahedron; vals[pair][i*4 + j] (dual: 5 b_i − Σ_k b_k), keep =
@@ -276,7 +329,7 @@ __device__ __forceinline__ int64_t pair_owner(int64_t p, int64_t n_s,
 // to the solid tet's vertex 0); values stored as T.
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_pairs_u(
-    int64_t n_pairs, int64_t n_s, const int64_t* __restrict__ off,
+    int64_t n_list, const int32_t* __restrict__ list, int64_t n_s, const int64_t* __restrict__ off,
     const int32_t* __restrict__ pf, const double* __restrict__ srec,
     const double* __restrict__ frec, double drop_rel, int dual, uint8_t* __restrict__ keep,
     T* __restrict__ vals, unsigned* flags, unsigned long long* counters) {
@@ -284,9 +337,10 @@ __global__ __launch_bounds__(kWave) void k_pairs_u(
   __shared__ uint32_t snb[kUSlots * kWave];
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << kUSlots) - 1u};
-  const int64_t p = int64_t(blockIdx.x) * kWave + lane;
+  const int64_t q = int64_t(blockIdx.x) * kWave + lane;
   bool kept = false, dropped = false, fail = false;
-  if (p < n_pairs) {
+  if (q < n_list) {
+    const int64_t p = list[q];
     const int64_t s = pair_owner(p, n_s, off);
     const int64_t f = pf[p];
     double rs[kURec], rf[kURec];
@@ -747,13 +801,32 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
           c->forder.as<int32_t>(), c->fbox.as<double>(), nullptr, c->pair_off.as<int64_t>(),
           c->owner.as<int32_t>(), flags);
   }
-  // (II)-(III) clip and integrate every pair
+  // (II)-(III) clip and integrate every pair that no face plane separates
   if (n_pairs > 0) {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t cb = al(size_t(n_pairs + 1) * sizeof(int32_t));
+    const size_t pb = al(size_t(n_pairs + 2) * sizeof(int64_t));
+    if ((st = ensure(c, c->ucoo, 2 * cb + pb + 256))) return st;
+    int32_t* cand = c->ucoo.as<int32_t>();
+    int64_t* pos = reinterpret_cast<int64_t*>(c->ucoo.as<char>() + cb);
+    int32_t* list = reinterpret_cast<int32_t*>(c->ucoo.as<char>() + cb + pb);
+    int64_t n_list = 0;
+    {
+      ProfScope ps("pairs_filter", s);
+      k_sep_u<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
+          n_pairs, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(), c->tetrec.as<double>(),
+          c->frec.as<double>(), cand, c->keep.as<uint8_t>());
+      if ((st = scan_i32_to_i64(c, cand, pos, n_pairs, s))) return st;
+      k_list_u<<<blocks_for(n_pairs, 256), 256, 0, s>>>(n_pairs, cand, pos, list);
+      if ((st = hip_check(hipGetLastError(), "filter launch"))) return st;
+    }
+    if ((st = read_back(c, &n_list, pos + n_pairs, sizeof(int64_t), s))) return st;
     ProfScope ps("pairs_tet", s);
-    k_pairs_u<T><<<unsigned(ceil_div(n_pairs, kWave)), kWave, 0, s>>>(
-        n_pairs, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(), c->tetrec.as<double>(),
-        c->frec.as<double>(), 1e-14, c->dual ? 1 : 0, c->keep.as<uint8_t>(), c->pval.as<T>(),
-        flags, counters);
+    if (n_list > 0)
+      k_pairs_u<T><<<unsigned(ceil_div(n_list, kWave)), kWave, 0, s>>>(
+          n_list, list, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(),
+          c->tetrec.as<double>(), c->frec.as<double>(), 1e-14, c->dual ? 1 : 0,
+          c->keep.as<uint8_t>(), c->pval.as<T>(), flags, counters);
   }
   if ((st = hip_check(hipGetLastError(), "pairs launch"))) return st;
   // (IV) B: rows gathered in LDS, or by sorting the entries when a row is
