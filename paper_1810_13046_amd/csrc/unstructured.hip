@@ -20,9 +20,11 @@
 //                   children; float boxes rounded outward, so every box
 //                   contains its double one).  Built once per handle: the
 //                   fluid mesh does not move.
-//  k_search<FILL>   per solid tet: depth-first traversal with an explicit
-//                   stack; leaves compared with the exact double boxes;
-//                   count pass, prefix sum, fill pass (traversal order).
+//  k_search<MODE>   per solid tet: depth-first traversal with an explicit
+//                   stack; leaves compared with the exact double boxes; one
+//                   pass counts and keeps up to kSearchCap finds per tet,
+//                   prefix sum, copy into place (traversal order); a second
+//                   traversal fills in place when some tet found more.
 //  k_sep_u / scan / k_list_u
 //                   candidates that a face plane of either tet separates
 //                   (all four vertices of one strictly outside a face of the
@@ -58,6 +60,9 @@ namespace {
 // most, and the tree has at most 2^31 leaves (31 levels).
 constexpr int kTreeStack = 32;
 constexpr int kSearchThreads = 256;
+// Finds per solid tet that the first search pass keeps (beyond it, a second
+// traversal fills the pairs in place).
+constexpr int kSearchCap = 64;
 
 inline unsigned blocks_for(int64_t n, int threads) {
   return unsigned(ceil_div(n > 0 ? n : 1, threads));
@@ -212,7 +217,10 @@ __device__ __forceinline__ bool boxes_meet(const double mn[3], const double mx[3
 // Tree search per solid tet.  FILL = false: count the fluid tets whose
 // closed double box meets the solid tet's; FILL = true: write them at
 // off[s] in traversal (Morton) order.
-template <bool FILL>
+// MODE 0: count the finds of each solid tet (cnt); MODE 1: write them at
+// off[s] (pf); MODE 2: count them and keep the first kSearchCap at
+// tmp[s * kSearchCap] (*ovf = 1 when a tet has more).
+template <int MODE>
 __global__ __launch_bounds__(kSearchThreads) void k_search(int64_t n_s, const double* __restrict__ sbox,
                                                 int64_t P, int64_t n_f,
                                                 const float* __restrict__ tree,
@@ -220,7 +228,9 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(int64_t n_s, const do
                                                 const double* __restrict__ fbox,
                                                 int64_t* __restrict__ cnt,
                                                 const int64_t* __restrict__ off,
-                                                int32_t* __restrict__ pf, unsigned* flags) {
+                                                int32_t* __restrict__ pf, unsigned* flags,
+                                                int32_t* __restrict__ tmp, unsigned* ovf) {
+  constexpr bool FILL = MODE == 1;
   // the stacks live in LDS, entry k of thread j at k * kSearchThreads + j
   __shared__ uint32_t s_stack[kTreeStack * kSearchThreads];
   uint32_t* stack = s_stack + threadIdx.x;
@@ -245,6 +255,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(int64_t n_s, const do
       if (mx[0] >= fb[0] && mn[0] <= fb[4] && mx[1] >= fb[1] && mn[1] <= fb[5] &&
           mx[2] >= fb[2] && mn[2] <= fb[6]) {
         if (FILL) pf[pos++] = int32_t(t);
+        if (MODE == 2 && found < kSearchCap) tmp[s * kSearchCap + found] = int32_t(t);
         ++found;
       }
       continue;
@@ -259,6 +270,16 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(int64_t n_s, const do
     if (gl) stack[kSearchThreads * top++] = uint32_t(l);
   }
   if (!FILL) cnt[s] = found;
+  if (MODE == 2 && found > kSearchCap) atomicOr(ovf, 1u);
+}
+
+// pf[off[s] + k] = tmp[s * kSearchCap + k] for the finds of each solid tet.
+__global__ void k_search_copy(int64_t n_s, const int64_t* __restrict__ off,
+                              const int32_t* __restrict__ tmp, int32_t* __restrict__ pf) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n_s) return;
+  const int64_t o = off[s], n = off[s + 1] - o;
+  for (int64_t k = 0; k < n; ++k) pf[o + k] = tmp[s * kSearchCap + k];
 }
 
 // Owner solid tet of pair p: the last s with off[s] <= p.
@@ -773,13 +794,19 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
                                                      c->tetrec.as<double>(), c->tetvol.as<double>(),
                                                      flags);
   }
+  // first pass: counts, and the finds of each tet up to kSearchCap
+  const size_t tmp_bytes = (size_t(n_s + 1) * kSearchCap * sizeof(int32_t) + 255) & ~size_t(255);
+  if ((st = ensure(c, c->ucoo, tmp_bytes + 256))) return st;
+  int32_t* stmp = c->ucoo.as<int32_t>();
+  unsigned* ovf = reinterpret_cast<unsigned*>(c->ucoo.as<char>() + tmp_bytes);
+  if ((st = hip_check(hipMemsetAsync(ovf, 0, sizeof(unsigned), s), "memset"))) return st;
   {
     ProfScope ps("tree_search", s);
     if (n_s > 0)
-      k_search<false><<<blocks_for(n_s, kSearchThreads), kSearchThreads, 0, s>>>(
+      k_search<2><<<blocks_for(n_s, kSearchThreads), kSearchThreads, 0, s>>>(
           n_s, c->rowbox.as<double>(), c->ftree_leaves, c->n_ftet, c->ftree.as<float>(),
           c->forder.as<int32_t>(), c->fbox.as<double>(), c->cnt.as<int64_t>(), nullptr, nullptr,
-          flags);
+          flags, stmp, ovf);
   }
   if ((st = hip_check(hipGetLastError(), "search launch"))) return st;
   if ((st = scan_i64(c, c->cnt.as<int64_t>(), c->pair_off.as<int64_t>(), n_s, s))) return st;
@@ -793,13 +820,18 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
   if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 16 * sizeof(T)))) return st;
+  unsigned over = 0;
+  if ((st = read_back(c, &over, ovf, sizeof(over), s))) return st;
   {
     ProfScope ps("tree_search", s);
-    if (n_s > 0)
-      k_search<true><<<blocks_for(n_s, kSearchThreads), kSearchThreads, 0, s>>>(
+    if (n_s > 0 && over)  // some tet found more than kSearchCap: traverse again
+      k_search<1><<<blocks_for(n_s, kSearchThreads), kSearchThreads, 0, s>>>(
           n_s, c->rowbox.as<double>(), c->ftree_leaves, c->n_ftet, c->ftree.as<float>(),
           c->forder.as<int32_t>(), c->fbox.as<double>(), nullptr, c->pair_off.as<int64_t>(),
-          c->owner.as<int32_t>(), flags);
+          c->owner.as<int32_t>(), flags, nullptr, nullptr);
+    else if (n_s > 0)
+      k_search_copy<<<blocks_for(n_s, 256), 256, 0, s>>>(n_s, c->pair_off.as<int64_t>(), stmp,
+                                                        c->owner.as<int32_t>());
   }
   // (II)-(III) clip and integrate every pair that no face plane separates
   if (n_pairs > 0) {
