@@ -45,7 +45,9 @@ struct SpmvArgs {
   int accumulate;
 };
 
-template <typename T, int G>
+// G lanes per row, U entries per lane per round (their loads issued
+// together; the per-lane order of the sums is the entry order).
+template <typename T, int G, int U>
 __global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs<T> a) {
   const int d = blockIdx.y;
   const int64_t row = int64_t(blockIdx.x) * (kThreads / G) + threadIdx.x / G;
@@ -57,7 +59,22 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs<T> a) {
     const int32_t* __restrict__ col = a.col[d];
     const T* __restrict__ val = a.val[d];
     const T* __restrict__ x = a.x[d];
-    for (int64_t k = b + g; k < e; k += G) s += val[k] * x[col[k]];
+    for (int64_t k0 = b + g; k0 < e; k0 += U * G) {
+      int32_t c[U];
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + int64_t(u) * G;
+        c[u] = k < e ? col[k] : 0;
+        v[u] = k < e ? val[k] : T(0);
+      }
+      T xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u] = k0 + int64_t(u) * G < e ? x[c[u]] : T(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k0 + int64_t(u) * G < e) s += v[u] * xv[u];
+    }
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
@@ -70,15 +87,27 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs<T> a) {
   }
 }
 
-template <typename T, int G>
-int launch_spmv(const SpmvArgs<T>& a, int nc, hipStream_t s, const char* name) {
+template <typename T, int G, int U>
+int launch_spmv_g(const SpmvArgs<T>& a, int nc, hipStream_t s, const char* name) {
   int64_t mx = 0;
   for (int d = 0; d < nc; ++d) mx = std::max(mx, a.nrows[d]);
   if (mx <= 0) return IBVT_OK;
   dim3 grid(unsigned(ceil_div(mx, kThreads / G)), unsigned(nc));
   ProfScope ps(name, s);
-  k_spmv<T, G><<<grid, kThreads, 0, s>>>(a);
+  k_spmv<T, G, U><<<grid, kThreads, 0, s>>>(a);
   return hip_check(hipGetLastError(), "spmv launch");
+}
+
+// Rows averaging fewer than 56 entries (B: a vertex's fluid nodes) take 8
+// lanes with 8 entries each per round; longer rows (B^T: a fluid node's
+// vertices) 16 lanes with 4 (the faster of the shapes measured on MI355X
+// for each).
+template <typename T>
+int launch_spmv(const SpmvArgs<T>& a, int nc, int64_t nnz, hipStream_t s, const char* name) {
+  int64_t rows = 0;
+  for (int d = 0; d < nc; ++d) rows += a.nrows[d];
+  if (nnz < 56 * rows) return launch_spmv_g<T, 8, 8>(a, nc, s, name);
+  return launch_spmv_g<T, 16, 4>(a, nc, s, name);
 }
 
 // ---------------------------------------------------------------------------
@@ -215,11 +244,26 @@ __global__ __launch_bounds__(kThreads) void k_cg_q(int64_t n, const int64_t* __r
        i - threadIdx.x / kMG < n; i += int64_t(gridDim.x) * (kThreads / kMG)) {
     T sd[3] = {0, 0, 0};
     if (i < n) {
-      for (int64_t k = rp[i] + g; k < rp[i + 1]; k += kMG) {
-        const int64_t j = col[k];
-        const T m = T(val[k]);
+      const int64_t e = rp[i + 1];
+      // two entries per lane per round, their loads issued together (same
+      // per-lane order of the sums)
+      for (int64_t k0 = rp[i] + g; k0 < e; k0 += 2 * kMG) {
+        const int64_t k1 = k0 + kMG;
+        const int64_t j0 = col[k0];
+        const int64_t j1 = k1 < e ? col[k1] : j0;
+        const T m0 = T(val[k0]);
+        const T m1 = k1 < e ? T(val[k1]) : T(0);
+        T p0[NC], p1[NC];
 #pragma unroll
-        for (int d = 0; d < NC; ++d) sd[d] += m * p[d * n + j];
+        for (int d = 0; d < NC; ++d) {
+          p0[d] = p[d * n + j0];
+          p1[d] = p[d * n + j1];
+        }
+#pragma unroll
+        for (int d = 0; d < NC; ++d) {
+          sd[d] += m0 * p0[d];
+          if (k1 < e) sd[d] += m1 * p1[d];
+        }
       }
     }
 #pragma unroll
@@ -584,6 +628,8 @@ int true_residual(ibvt_coupling* c, const T* b, const double* x, const CgWork& w
 
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s) {
   const int64_t n = c->n_vert;
+  int64_t nnz = 0;
+  for (int d = 0; d < c->ncomp; ++d) nnz += c->B[d].nnz;
   if (c->precision == IBVT_FP32_MIXED) {
     SpmvArgs<float> a{};
     for (int d = 0; d < 3; ++d) {
@@ -596,7 +642,7 @@ int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale
     }
     a.scale = lumped_scale ? c->minv.as<float>() : nullptr;
     a.alpha = 1.0f;
-    return launch_spmv<float, 16>(a, c->ncomp, s, "spmv_B");
+    return launch_spmv<float>(a, c->ncomp, nnz, s, "spmv_B");
   }
   SpmvArgs<double> a{};
   for (int d = 0; d < 3; ++d) {
@@ -609,12 +655,14 @@ int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale
   }
   a.scale = lumped_scale ? c->minv.as<double>() : nullptr;
   a.alpha = 1.0;
-  return launch_spmv<double, 16>(a, c->ncomp, s, "spmv_B");
+  return launch_spmv<double>(a, c->ncomp, nnz, s, "spmv_B");
 }
 
 // out[d][rowmap[r]] += alpha * (B^dT ys_d)[r]
 int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha, hipStream_t s) {
   const int64_t n = c->n_vert;
+  int64_t nnz = 0;
+  for (int d = 0; d < c->ncomp; ++d) nnz += c->Bt[d].nnz;
   if (c->precision == IBVT_FP32_MIXED) {
     SpmvArgs<float> a{};
     for (int d = 0; d < 3; ++d) {
@@ -628,7 +676,7 @@ int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,
     }
     a.alpha = float(alpha);
     a.accumulate = 1;
-    return launch_spmv<float, 16>(a, c->ncomp, s, "spmv_Bt");
+    return launch_spmv<float>(a, c->ncomp, nnz, s, "spmv_Bt");
   }
   SpmvArgs<double> a{};
   for (int d = 0; d < 3; ++d) {
@@ -642,7 +690,7 @@ int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,
   }
   a.alpha = alpha;
   a.accumulate = 1;
-  return launch_spmv<double, 16>(a, c->ncomp, s, "spmv_Bt");
+  return launch_spmv<double>(a, c->ncomp, nnz, s, "spmv_Bt");
 }
 
 int lumped_solve(ibvt_coupling* c, const void* rhs, void* x, hipStream_t s) {
