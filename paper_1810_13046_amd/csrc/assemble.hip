@@ -770,6 +770,7 @@ __global__ __launch_bounds__(256) void k_rows(
 }
 
 // Copy each row from the box-capacity scratch into the CSR arrays.
+constexpr int kCompactLanes = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows_compact(
     int64_t n_v, const int64_t* __restrict__ tmp_off, const int32_t* __restrict__ tmp_col,
@@ -777,8 +778,9 @@ __global__ __launch_bounds__(256) void k_rows_compact(
     const int64_t* __restrict__ rp1, const int64_t* __restrict__ rp2, int32_t* __restrict__ c0,
     int32_t* __restrict__ c1, int32_t* __restrict__ c2, T* __restrict__ v0, T* __restrict__ v1,
     T* __restrict__ v2) {
-  const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const int lane = lane_id();
+  // kCompactLanes lanes per row
+  const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kCompactLanes;
+  const int lane = threadIdx.x % kCompactLanes;
   if (w >= 3 * n_v) return;
   const int d = int(w / n_v);
   const int64_t i = w - int64_t(d) * n_v;
@@ -786,7 +788,7 @@ __global__ __launch_bounds__(256) void k_rows_compact(
   int32_t* col = d == 0 ? c0 : (d == 1 ? c1 : c2);
   T* val = d == 0 ? v0 : (d == 1 ? v1 : v2);
   const int64_t src = tmp_off[w], dst = rp[i], n = rp[i + 1] - rp[i];
-  for (int64_t k = lane; k < n; k += kWave) {
+  for (int64_t k = lane; k < n; k += kCompactLanes) {
     col[dst + k] = tmp_col[src + k];
     val[dst + k] = tmp_val[src + k];
   }
@@ -1074,7 +1076,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   }
   {
     ProfScope ps("rows_compact", s);
-    k_rows_compact<T><<<blocks_for(3 * n_v * kWave, 256), 256, 0, s>>>(
+    k_rows_compact<T><<<blocks_for(3 * n_v * kCompactLanes, 256), 256, 0, s>>>(
         n_v, c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(), c->rowtmpval.as<T>(),
         c->B[0].rowptr.as<int64_t>(), c->B[1].rowptr.as<int64_t>(), c->B[2].rowptr.as<int64_t>(),
         c->B[0].col.as<int32_t>(), c->B[1].col.as<int32_t>(), c->B[2].col.as<int32_t>(),
