@@ -64,7 +64,7 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="f63733b5a9df6773c3c5840c3d108b114797348ee912bbbe721668a407820c7d",
+CLIP_TRAFFIC = dict(sources_sha256="abf8f1cd297fd8dcdb30d79d5d5fab17ec520d3f57c96dfd89569b13fe2c5177",
                     bytes_mixed=35621870624)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]

@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kRowNodes = 128;  // LDS box nodes per row per pass in k_rows
 constexpr int kRowMap = 128;    // slots of the slot → tet map of a k_rows row (one window)
-constexpr int kRowBatch = 8;    // steps of 8 pairs whose loads k_rows issues together
+constexpr int kRowBatch = 4;    // steps whose loads k_rows issues together
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
   int lo = 0, hi = n;  // first index with L[idx] > x
