@@ -126,7 +126,7 @@ struct CgScalars {
 // q = M x for the NC components (values V, vectors T), at the start of a
 // solve.  kMG lanes per row stride through it (coalesced reads of the row's
 // columns and values) and reduce with lane shuffles in a fixed order.
-constexpr int kMG = 8;
+constexpr int kMG = 4;  // the fastest of 2, 4, 8, 16 on MI355X for P1 mass rows (~15 entries)
 
 template <typename T, typename V, int NC>
 __global__ __launch_bounds__(kThreads) void k_mass_spmv(int64_t n, const int64_t* __restrict__ rp,
