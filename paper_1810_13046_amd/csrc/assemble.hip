@@ -811,48 +811,51 @@ __global__ void k_lumped(int64_t n_v, const int64_t* __restrict__ vt_ptr,
   minv[i] = (s > 0.0) ? T(1.0 / s) : T(0);
 }
 
-// Consistent mass rows M_il = Σ_{T ∋ i, l} |T|(1 + δ_il)/20, one wave per
-// vertex: lane k holds column k of the row, and the incident tets are
-// broadcast one at a time (sum order = incident-tet order).
+// Consistent mass rows M_il = Σ_{T ∋ i, l} |T|(1 + δ_il)/20, kMassLanes
+// lanes per vertex (rows hold ~15 columns): lane k holds column k of the
+// row, and the incident tets are broadcast one at a time within the lane
+// group (sum order = incident-tet order).
+constexpr int kMassLanes = 16;
 __global__ __launch_bounds__(256) void k_mass_values(
     int64_t n_v, const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_tet,
     const int32_t* __restrict__ tets, const double* __restrict__ tetvol,
     const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     double* __restrict__ val, float* __restrict__ val32, double* __restrict__ dinv) {
-  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const int lane = lane_id();
-  if (i >= n_v) return;
+  constexpr int H = kMassLanes;
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / H;
+  const int hl = threadIdx.x % H;
+  if (i >= n_v) return;  // whole lane groups leave together
   const int64_t rb = rowptr[i], re = rowptr[i + 1];
   const int64_t tb = vt_ptr[i], te = vt_ptr[i + 1];
   double diag = 0.0;
-  for (int64_t c0 = rb; c0 < re; c0 += kWave) {
-    const bool has = c0 + lane < re;
-    const int l = has ? col[c0 + lane] : -1;
+  for (int64_t c0 = rb; c0 < re; c0 += H) {
+    const bool has = c0 + hl < re;
+    const int l = has ? col[c0 + hl] : -1;
     double a = 0.0;
-    for (int64_t k0 = tb; k0 < te; k0 += kWave) {
-      const int nk = int(min<int64_t>(kWave, te - k0));
+    for (int64_t k0 = tb; k0 < te; k0 += H) {
+      const int nk = int(min<int64_t>(H, te - k0));
       int4 tv = make_int4(-1, -1, -1, -1);
       double w = 0.0;
-      if (lane < nk) {
-        const int64_t t = vt_tet[k0 + lane];
+      if (hl < nk) {
+        const int64_t t = vt_tet[k0 + hl];
         tv = *reinterpret_cast<const int4*>(tets + 4 * t);
         w = tetvol[t] / 20.0;
       }
       for (int k = 0; k < nk; ++k) {
-        const int v0 = __builtin_amdgcn_readlane(tv.x, k), v1 = __builtin_amdgcn_readlane(tv.y, k),
-                  v2 = __builtin_amdgcn_readlane(tv.z, k), v3 = __builtin_amdgcn_readlane(tv.w, k);
-        const double wk = __shfl(w, k, kWave);
+        const int v0 = __shfl(tv.x, k, H), v1 = __shfl(tv.y, k, H), v2 = __shfl(tv.z, k, H),
+                  v3 = __shfl(tv.w, k, H);
+        const double wk = __shfl(w, k, H);
         if (l == v0 || l == v1 || l == v2 || l == v3) a += (int64_t(l) == i) ? 2.0 * wk : wk;
       }
     }
     if (has) {
-      val[c0 + lane] = a;
-      if (val32) val32[c0 + lane] = float(a);
+      val[c0 + hl] = a;
+      if (val32) val32[c0 + hl] = float(a);
       if (int64_t(l) == i) diag = a;
     }
   }
-  diag = wave_sum(diag);
-  if (lane == 0) dinv[i] = (diag > 0.0) ? 1.0 / diag : 0.0;
+  for (int o = H / 2; o > 0; o >>= 1) diag += __shfl_xor(diag, o, H);
+  if (hl == 0) dinv[i] = (diag > 0.0) ? 1.0 / diag : 0.0;
 }
 
 inline unsigned blocks_for(int64_t n, int threads) {
@@ -1124,7 +1127,7 @@ int solid_masses(ibvt_coupling* c, hipStream_t s) {
         n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tetvol.as<double>(),
         c->mlump.as<double>(), c->minv.as<double>());
   if (c->has_M) {
-    k_mass_values<<<blocks_for(n_v * kWave, 256), 256, 0, s>>>(
+    k_mass_values<<<blocks_for(n_v * kMassLanes, 256), 256, 0, s>>>(
         n_v, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
         c->tetvol.as<double>(), c->M.rowptr.as<int64_t>(), c->M.col.as<int32_t>(),
         c->M.val.as<double>(), c->precision == IBVT_FP32_MIXED ? c->Mval32.as<float>() : nullptr,
