@@ -33,8 +33,9 @@ struct ValRow {
   int32_t r;
 };
 
-// keys[k] = compacted column of nonzero k, vr[k] = (value, row).  One wave
-// per row (coalesced reads and writes).
+// keys[k] = compacted column of nonzero k, vr[k] = (value, row).
+// kKeyLanes lanes per row (coalesced reads and writes).
+constexpr int kKeyLanes = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_keys(int64_t n_rows, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col,
@@ -42,10 +43,10 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n_rows, const int64_t* __r
                                               const int64_t* __restrict__ cidx,
                                               int32_t* __restrict__ keys,
                                               ValRow<T>* __restrict__ vr) {
-  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const int lane = lane_id();
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kKeyLanes;
+  const int lane = threadIdx.x % kKeyLanes;
   if (i >= n_rows) return;
-  for (int64_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += kWave) {
+  for (int64_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += kKeyLanes) {
     keys[k] = int32_t(cidx[col[k]]);
     ValRow<T> x;
     x.v = val[k];
@@ -130,7 +131,7 @@ int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
   ValRow<T>* vr = reinterpret_cast<ValRow<T>*>(base + 2 * n4);
   ValRow<T>* svr = reinterpret_cast<ValRow<T>*>(base + 2 * n4 + nv);
   void* temp = base + 2 * n4 + 2 * nv;
-  k_keys<T><<<blocks_for(c->n_vert * kWave, 256), 256, 0, s>>>(
+  k_keys<T><<<blocks_for(c->n_vert * kKeyLanes, 256), 256, 0, s>>>(
       c->n_vert, B.rowptr.as<int64_t>(), B.col.as<int32_t>(), B.val.as<T>(),
       c->cidx.as<int64_t>(), keys, vr);
   if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, vr, svr,
