@@ -3,18 +3,22 @@
 //  k_tet_prep      per tet: bounding box -> cell index range on each
 //                  component's lattice (replaces the tree search: on a
 //                  rectilinear grid the overlap candidates of a tet are an
-//                  index box), volume, validity checks.
-//  scan            candidate (tet, component, cell) pair offsets.
-//  k_clip<T>       one lane per pair: clip the tet by the cell's six planes
-//                  in double and integrate λ_i N_j on the piece (32 values).
-//  k_rows<T,FILL>  one wavefront per (solid vertex, component): gathers the
-//                  pieces of the vertex's incident tets into a dense node box
-//                  held in registers, in a fixed order (deterministic, no
-//                  atomics on values), and writes the CSR row (count pass,
-//                  then fill pass).
-//  transpose       B^dT over the touched fluid nodes (integer atomics for
-//                  positions, then each row sorted by vertex index, so the
-//                  result does not depend on timing).
+//                  index box), volume, geometry record, validity checks.
+//  scan / k_owner  candidate (tet, component, cell) pair offsets and owners.
+//  k_pair_key      pairs ordered by the cell planes the tet straddles, in
+//                  classes by cut count (vertex slots 10, 12, 16).
+//  k_clip<T,MAXV>  one lane per pair: clip the tet by the straddled cell
+//                  planes in double (vertex graph in LDS), fan the piece
+//                  into sub-tetrahedra and store them as records.
+//  k_integrate<T>  one lane per record: its 35 cell-local moments, summed
+//                  per pair; then one lane per pair turns them into the 32
+//                  values ∫ λ_i N_j.
+//  k_row_box / k_rows<T> / k_rows_compact<T>
+//                  each (solid vertex, component) row gathered in an LDS
+//                  node box, pairs added in a fixed order (deterministic,
+//                  no value atomics outside LDS), written column-sorted,
+//                  then compacted into CSR.
+//  transpose       B^dT over the touched fluid nodes (transpose.hip).
 //  masses          lumped m_i = Σ_{T∋i} |T|/4 and the consistent P1 mass
 //                  matrix |T|(1+δ_il)/20 (Section 2.1), per vertex in
 //                  incident-tet order.
