@@ -2,9 +2,10 @@
 // f_f += alpha B^T f_s, plus the consistent-mass solve.
 //
 // SpMV: CSR with a group of G lanes per row (rows of B hold a few tens of
-// entries); the group strides through the row so each wave reads
-// contiguous runs of values and column indices, reduces with lane shuffles
-// and writes one result per row.  The three velocity components run in one
+// entries, rows of B^T about twice as many); the group strides through the
+// row, each lane issuing the loads of U entries at a time, so each wave
+// reads contiguous runs of values and column indices with several gathers
+// in flight, reduces with lane shuffles and writes one result per row.  The three velocity components run in one
 // launch (grid.y).  B^T rows are the touched fluid nodes; their results are
 // scattered to the caller's full fluid arrays through the row map (each
 // fluid node appears once, so no atomics).
@@ -15,9 +16,11 @@
 // q = M p (k_cg_q), α (k_cg_alpha), the updates of x, r and z (k_cg_b), β
 // and the stopping test (k_cg_beta), and p = z + β p (k_cg_p); the two
 // single-block kernels reduce the per-block partials in a fixed order and
-// set the next scalars, so results do not depend on timing.  In the mixed-precision path an outer loop recomputes
-// the residual b - M x in double with double M values and solves the
-// correction with a float CG (iterative refinement).
+// set the next scalars, so results do not depend on timing.  The host reads
+// the convergence flags only where the observed decay of r·z predicts the
+// tolerance.  In the mixed-precision path an outer loop recomputes the
+// residual b - M x in double with double M values and solves the correction
+// with a float CG (iterative refinement).
 //
 // Solid vectors are component-major (ncomp, n_vert): three components in
 // three dimensions, two in the plane.
