@@ -186,10 +186,11 @@ static double int2(double vt, const double* f, const double* g) {
 }
 
 /* One pair: solid tet S (vertices, λ coefficients), fluid tet F (vertices,
- * μ coefficients).  val[i*4 + j] = ∫ λ_i μ_j over S ∩ F; returns the piece
- * volume. */
+ * μ coefficients).  val[i*4 + j] = ∫ λ_i μ_j over S ∩ F and, when lam is
+ * given, lam[a*4 + i] = ∫ λ_a λ_i over it (the reverse mode's second
+ * integral); returns the piece volume. */
 static double piece(const double S[4][3], const double ls[4][4], const double F[4][3],
-                    const double lf[4][4], double* val) {
+                    const double lf[4][4], double* val, double* lam) {
   static __thread Polyh poly;
   poly.nf = 4;
   static const int fv[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
@@ -203,6 +204,7 @@ static double piece(const double S[4][3], const double ls[4][4], const double F[
     clip_plane(&poly, nrm, -lf[k][0]);
   }
   memset(val, 0, 16 * sizeof(double));
+  if (lam) memset(lam, 0, 16 * sizeof(double));
   if (poly.nf == 0) return 0.0;
   double apex[3] = {0, 0, 0};
   int cnt = 0;
@@ -228,6 +230,9 @@ static double piece(const double S[4][3], const double ls[4][4], const double F[
         }
       for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) val[i * 4 + j] += int2(vt, la[i], mu[j]);
+      if (lam)
+        for (int a = 0; a < 4; ++a)
+          for (int i = 0; i < 4; ++i) lam[a * 4 + i] += int2(vt, la[a], la[i]);
     }
   }
   (void)F;
@@ -235,12 +240,13 @@ static double piece(const double S[4][3], const double ls[4][4], const double F[
 }
 
 /* Integrate the listed (solid tet, fluid tet) pairs.  pairs: (n_pairs, 2)
- * int64.  Outputs vals (n_pairs, 16), vols, keep (vol > drop_rel·|T|).
+ * int64.  Outputs vals (n_pairs, 16), lams (n_pairs, 16; nullable), vols,
+ * keep (vol > drop_rel·|T|).
  * zero_tets counts solid tets of zero volume among the pairs' solid tets
  * (their pairs are written as empty).  Returns 0. */
 int o3_pairs(const double* Xs, const int32_t* tets_s, const double* Xf, const int32_t* tets_f,
              const int64_t* pairs, int64_t n_pairs, double drop_rel, int nthreads, double* vals,
-             double* vols, uint8_t* keep) {
+             double* lams, double* vols, uint8_t* keep) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -257,11 +263,12 @@ int o3_pairs(const double* Xs, const int32_t* tets_s, const double* Xf, const in
     double volF = tet_volume(F[0], F[1], F[2], F[3]);
     if (volS == 0.0 || volF == 0.0 || barycentric(S, ls) != 0 || barycentric(F, lf) != 0) {
       memset(vals + 16 * p, 0, 16 * sizeof(double));
+      if (lams) memset(lams + 16 * p, 0, 16 * sizeof(double));
       vols[p] = 0.0;
       keep[p] = 0;
       continue;
     }
-    double vol = piece(S, ls, F, lf, vals + 16 * p);
+    double vol = piece(S, ls, F, lf, vals + 16 * p, lams ? lams + 16 * p : NULL);
     vols[p] = vol;
     keep[p] = vol > drop_rel * volS;
   }
@@ -274,7 +281,7 @@ double o3_clip_volume(const double* Sp, const double* Fp) {
   for (int v = 0; v < 4; ++v)
     for (int e = 0; e < 3; ++e) { S[v][e] = Sp[3 * v + e]; F[v][e] = Fp[3 * v + e]; }
   if (barycentric(S, ls) != 0 || barycentric(F, lf) != 0) return 0.0;
-  return piece(S, ls, F, lf, val);
+  return piece(S, ls, F, lf, val, NULL);
 }
 
 /* Exposed for the pins: ∫_τ f g for affine f, g given at τ's vertices. */

@@ -15,7 +15,11 @@ component uses the same nodes and the same B):
   exact box test filters it; the GPU builds its own bounding-volume tree);
 * B_ij = ∫ λ_i μ_j dV per pair (C part, o3.c), summed;
 * S, the transfers and the dual multipliers as in the structured case
-  (oracle/__init__.py).
+  (oracle/__init__.py);
+* reverse mode: z = S^{-1} g, B^T z, and the shape derivative with respect
+  to the solid vertices (the transport form of the structured case with the
+  fluid P1 hats in place of the Q1 hats; ∫ λ_a λ_i per piece is the second
+  integral it needs).
 """
 from __future__ import annotations
 
@@ -28,7 +32,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from . import DROP_REL, consistent_mass, lumped_mass, mass_solve, tet_volumes
+from . import (DROP_REL, _mass_shape_term, barycentric_gradients, consistent_mass, lumped_mass,
+               mass_solve, tet_volumes)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "o3.c")
@@ -54,7 +59,7 @@ def _load():
         P = ctypes.POINTER
         dp, i64p, i32p = P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_int32)
         lib.o3_pairs.argtypes = [dp, i32p, dp, i32p, i64p, ctypes.c_int64, ctypes.c_double,
-                                 ctypes.c_int, dp, dp, P(ctypes.c_uint8)]
+                                 ctypes.c_int, dp, dp, dp, P(ctypes.c_uint8)]
         lib.o3_pairs.restype = ctypes.c_int
         lib.o3_clip_volume.argtypes = [dp, dp]
         lib.o3_clip_volume.restype = ctypes.c_double
@@ -112,7 +117,9 @@ class Coupling:
     dual: bool = False
 
 
-def pair_values(Xs, tets_s, Xf, tets_f, pairs, drop_rel=DROP_REL, nthreads=0):
+def pair_values(Xs, tets_s, Xf, tets_f, pairs, drop_rel=DROP_REL, nthreads=0, with_lam=False):
+    """vals (n, 16): ∫ λ_i μ_j per pair (i*4 + j); vols; keep; and with
+    with_lam also lams (n, 16): ∫ λ_a λ_i per pair (a*4 + i)."""
     lib = _load()
     Xs = np.ascontiguousarray(Xs, dtype=np.float64)
     Xf = np.ascontiguousarray(Xf, dtype=np.float64)
@@ -121,13 +128,16 @@ def pair_values(Xs, tets_s, Xf, tets_f, pairs, drop_rel=DROP_REL, nthreads=0):
     pairs = np.ascontiguousarray(pairs, dtype=np.int64)
     n = pairs.shape[0]
     vals = np.zeros((n, 16))
+    lams = np.zeros((n, 16)) if with_lam else None
     vols = np.zeros(n)
     keep = np.zeros(n, dtype=np.uint8)
     lib.o3_pairs(_dp(Xs), ts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(Xf),
                  tf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                  pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, float(drop_rel),
-                 int(nthreads), _dp(vals), _dp(vols),
+                 int(nthreads), _dp(vals), _dp(lams) if with_lam else None, _dp(vols),
                  keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if with_lam:
+        return vals, lams, vols, keep.astype(bool)
     return vals, vols, keep.astype(bool)
 
 
@@ -177,6 +187,76 @@ def transfer_force(cpl: Coupling, f_s, alpha=1.0, load=False, base=None):
     return out
 
 
+def _mass_kind(cpl: Coupling, mass: str) -> str:
+    if cpl.dual and mass == "consistent":
+        raise ValueError("the dual basis has a diagonal S: use mass='lumped'")
+    return "lumped" if cpl.dual else mass
+
+
+def _shape_terms(cpl: Coupling, z, u):
+    """Σ over the pieces of the shape-derivative terms of B contracted with
+    the solid weights z (nc, n_vert) and the fluid nodal fields u (nc,
+    n_vert_fluid), as (n_vert, 3).  Moving vertex a of a solid tet moves its
+    points by λ_a e_k while the fluid hats μ_j stay where they are, so
+        ∂B_ij/∂X_{a,k} = Σ_{T∋a} ∫_T (λ_a λ_i ∂_k μ_j + ∂_k λ_a λ_i μ_j)
+    (the same transport form as for the grid).  On a piece inside fluid tet
+    F the interpolant U = Σ_j u_j μ_j has the constant gradient Σ_j u_j ∇μ_j,
+    so a piece adds ∂_k U · Σ_i z_i ∫ λ_a λ_i + ∂_k λ_a · Σ_ij z_i u_j ∫ λ_i μ_j.
+    With dual multipliers the weights are 5 z_i − Σ_k z_k."""
+    z = np.atleast_2d(np.asarray(z, dtype=np.float64))
+    u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    vals, lams, _, keep = pair_values(cpl.X, cpl.tets, cpl.Xf, cpl.tets_f, cpl.pairs, with_lam=True)
+    sel = np.nonzero(keep)[0]
+    ps, pf = cpl.pairs[sel, 0], cpl.pairs[sel, 1]
+    V = vals[sel].reshape(-1, 4, 4)                       # [p, i, j]
+    L = lams[sel].reshape(-1, 4, 4)                       # [p, a, i]
+    grad_l = barycentric_gradients(cpl.X, cpl.tets)[ps]   # [p, a, k]
+    grad_m = barycentric_gradients(cpl.Xf, cpl.tets_f)[pf]
+    vs, vf = cpl.tets[ps], cpl.tets_f[pf]
+    g = np.zeros((cpl.X.shape[0], 3))
+    for d in range(z.shape[0]):
+        zl = z[d][vs]
+        if cpl.dual:
+            zl = 5.0 * zl - zl.sum(axis=1, keepdims=True)
+        ul = u[d][vf]
+        grad_u = np.einsum("pj,pjk->pk", ul, grad_m)
+        zL = np.einsum("pi,pai->pa", zl, L)
+        zVu = np.einsum("pi,pij,pj->p", zl, V, ul)
+        term = zL[:, :, None] * grad_u[:, None, :] + grad_l * zVu[:, None, None]
+        for a in range(4):
+            np.add.at(g, vs[:, a], term[:, a, :])
+    return g
+
+
+def velocity_vjp(cpl: Coupling, u_f, g_us, mass="lumped"):
+    """Reverse mode of u_s = S^{-1} B(X) u_f: z = S^{-1} g_us; returns
+    (g_uf = B^T z per component, g_X = Σ_d z_d^T (∂B/∂X) u_f,d − Σ_d z_d^T
+    (∂S/∂X) u_s,d)."""
+    mk = _mass_kind(cpl, mass)
+    z = mass_solve(cpl.X, cpl.tets, np.atleast_2d(np.asarray(g_us, dtype=np.float64)), mk)
+    u_f = np.atleast_2d(np.asarray(u_f, dtype=np.float64))
+    u_s = transfer_velocity(cpl, u_f, mass)
+    g_uf = np.stack([cpl.B.T @ zd for zd in z])
+    g_X = _shape_terms(cpl, z, u_f) - _mass_shape_term(cpl.X, cpl.tets, z, u_s, mk)
+    return g_uf, g_X
+
+
+def force_vjp(cpl: Coupling, f_s, g_ff, alpha=1.0):
+    """Reverse mode of f_f = alpha B(X)^T f_s: returns (g_fs = alpha B g_ff,
+    g_X = alpha Σ_d f_s,d^T (∂B/∂X) g_ff,d)."""
+    f_s = np.atleast_2d(np.asarray(f_s, dtype=np.float64))
+    g_ff = np.atleast_2d(np.asarray(g_ff, dtype=np.float64))
+    g_fs = alpha * np.stack([cpl.B @ g for g in g_ff])
+    return g_fs, alpha * _shape_terms(cpl, f_s, g_ff)
+
+
+def velocity_loss(Xf, tets_f, X, tets, u_f, u_target, mass="lumped", dual=False):
+    """L = 1/2 ||u_s − u_target||^2 with u_s = S^{-1} B u_f assembled at X."""
+    cpl = assemble(Xf, tets_f, X, tets, dual=dual)
+    r = transfer_velocity(cpl, u_f, mass) - u_target
+    return 0.5 * float(np.sum(r * r))
+
+
 def clip_volume(S, F) -> float:
     lib = _load()
     a = np.ascontiguousarray(S, dtype=np.float64)
@@ -191,5 +271,5 @@ def int2(Y, f, g) -> float:
 
 
 __all__ = ["build", "candidate_pairs", "Coupling", "pair_values", "assemble",
-           "transfer_velocity", "transfer_force", "clip_volume", "int2", "tet_bounds",
-           "lumped_mass", "consistent_mass"]
+           "transfer_velocity", "transfer_force", "velocity_vjp", "force_vjp", "velocity_loss",
+           "clip_volume", "int2", "tet_bounds", "lumped_mass", "consistent_mass"]

@@ -1,8 +1,8 @@
 """Pins of the FP64 oracle of the coupling with an unstructured (P1
 tetrahedral) fluid background (no GPU): closed forms, an independent Gauss
 rule, tilings, the symmetry of exchanging the two meshes, exact
-reproduction of affine fields, partition of unity and Monte Carlo brute
-force."""
+reproduction of affine fields, partition of unity, Monte Carlo brute force,
+and central finite differences of the reverse mode's shape derivative."""
 import numpy as np
 import pytest
 
@@ -159,3 +159,62 @@ def test_dual_row_sums_and_reproduction(un, w1):
     co = (-0.3, 0.9, 1.4, -0.6)
     us = un.transfer_velocity(R, [WU.linear_fields(W.Xf, co)], "lumped")
     np.testing.assert_allclose(us[0], WU.linear_fields(W.X, co), atol=1e-11)
+
+
+def _fd(f, X, D, h=1e-6):
+    return (f(X + h * D) - f(X - h * D)) / (2 * h)
+
+
+@pytest.mark.parametrize("mass,dual", [("lumped", False), ("consistent", False), ("lumped", True)])
+def test_velocity_shape_derivative_matches_finite_differences(un, w1, mass, dual):
+    """g_X of L = 1/2 ||S^{-1} B(X) u_f − u_t||^2 against central differences
+    of the assembled transfer along random directions."""
+    W, _ = w1
+    R = un.assemble(W.Xf, W.tets_f, W.X, W.tets, dual=dual)
+    u_f = W.u_f()
+    u_t = np.random.default_rng(41).standard_normal((3, W.X.shape[0]))
+    r = un.transfer_velocity(R, u_f, mass) - u_t
+    _, gX = un.velocity_vjp(R, u_f, r, mass)
+    rng = np.random.default_rng(42)
+    for _ in range(3):
+        D = rng.standard_normal(W.X.shape)
+        fd = _fd(lambda Y: un.velocity_loss(W.Xf, W.tets_f, Y, W.tets, u_f, u_t, mass, dual), W.X, D)
+        an = float(np.sum(gX * D))
+        assert abs(an - fd) <= 1e-6 * abs(fd) + 1e-10, (an, fd)
+
+
+def test_force_shape_derivative_matches_finite_differences(un, w1):
+    """g_X of φ = α Σ_d f_s,d^T B(X) g_ff,d against central differences."""
+    W, R = w1
+    f_s = W.f_s()
+    g_ff = np.random.default_rng(43).standard_normal((3, W.Xf.shape[0]))
+    alpha = 0.7
+    _, gX = un.force_vjp(R, f_s, g_ff, alpha)
+
+    def phi(Y):
+        C = un.assemble(W.Xf, W.tets_f, Y, W.tets)
+        return alpha * float(sum(f_s[d] @ (C.B @ g_ff[d]) for d in range(3)))
+
+    rng = np.random.default_rng(44)
+    for _ in range(3):
+        D = rng.standard_normal(W.X.shape)
+        fd = _fd(phi, W.X, D)
+        an = float(np.sum(gX * D))
+        assert abs(an - fd) <= 1e-6 * abs(fd) + 1e-10, (an, fd)
+
+
+def test_shape_derivative_of_rigid_translation_is_zero_for_affine_fields(un, w1):
+    """Translating the solid inside the fluid mesh leaves ∫ λ_i U unchanged
+    when U is affine (the P1 fluid interpolant reproduces it exactly and
+    the integral only sees U on the solid), so the velocity-force pairing's
+    derivative along a uniform translation vanishes."""
+    W, R = w1
+    co = (0.2, -0.5, 0.8, 1.1)
+    U = WU.linear_fields(W.Xf, co)
+    f_s = W.f_s()
+    _, gX = un.force_vjp(R, f_s, [U, U, U], 1.0)
+    # d/dε Σ_i f_i ∫ λ_i U(x + ε e_k) = Σ_i f_i ∫ λ_i ∂_k U = ∂_k U Σ_i f_i m_i
+    m = un.lumped_mass(W.X, W.tets)
+    for k in range(3):
+        want = co[1 + k] * float(sum(f_s[d] @ m for d in range(3)))
+        assert abs(gX[:, k].sum() - want) <= 1e-10 * (1 + abs(want))
