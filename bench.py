@@ -203,8 +203,8 @@ def planar_leg(dev, steps, warmup, with_cpu):
 class UStep:
     """One pass over the unstructured coupling (P1 tetrahedral fluid mesh):
     reassembly against the kept fluid tree, consistent velocity transfer,
-    force transfer and the fluid/solid cotangents of both adjoints (the
-    shape derivative is not defined for this background)."""
+    force transfer and both adjoints with the shape gradient (the same step
+    as on the grid)."""
 
     def __init__(self, W, X, T, Xf, Tf, u_f, f_s, precision):
         import torch
@@ -218,14 +218,15 @@ class UStep:
         self.ff = [torch.zeros_like(u) for u in self.u]
         self.g_uf = [torch.zeros_like(u) for u in self.u]
         self.g_fs = torch.zeros_like(self.f_s)
+        self.g_X = torch.zeros((X.shape[0], 3), dtype=torch.float64, device=X.device)
 
     def run(self):
         c = self.c
         c.reassemble(self.X)
         c.velocity(self.u, mass="consistent", rtol=1e-10, maxit=500, out=self.us)
         c.force(self.f_s, self.ff, alpha=1.0)
-        c.vjp(self.us, self.u, mass="consistent", alpha=1.0, g_uf=self.g_uf, g_fs=self.g_fs,
-              rtol=1e-10, maxit=500)
+        c.vjp(self.us, self.u, u_f=self.u, u_s=self.us, f_s=self.f_s, mass="consistent",
+              alpha=1.0, g_uf=self.g_uf, g_fs=self.g_fs, g_X=self.g_X, rtol=1e-10, maxit=500)
 
 
 def unstructured_oracle_rate(W, n_sample):
@@ -251,7 +252,7 @@ def unstructured_leg(dev, steps, warmup, with_cpu):
     n_tet = W.tets.shape[0]
     out = dict(workload=W.name, n_tet=int(n_tet), n_vert=int(W.X.shape[0]),
                fluid_tets=int(W.tets_f.shape[0]), fluid_vertices=int(W.Xf.shape[0]),
-               unit="solid tets/s (reassembly + consistent velocity + force + adjoint applies)")
+               unit="solid tets/s (reassembly + consistent velocity + force + both adjoints)")
     for prec in ("fp32", "fp64"):
         log(f"[bench] unstructured {prec} step")
         torch.cuda.synchronize()

@@ -226,9 +226,12 @@ int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int p
  *   of the μ_j); solid parts outside it get no contribution.
  *   Fluid fields u_f[d] / f_f[d] are nodal arrays of the fluid mesh's
  *   n_vert values.  IBVT_DUAL_BASIS and IBVT_BUILD_CONSISTENT_M as for
- *   grids; IBVT_NO_PIECE_STORE has no effect.  The reverse-mode calls give
- *   g_uf / g_fs; a non-NULL g_X is refused with IBVT_E_UNSUPPORTED before
- *   any output is touched.  fsi_step returns IBVT_E_UNSUPPORTED.
+ *   grids; IBVT_NO_PIECE_STORE has no effect (the per-pair integrals ∫ λ_i μ_j
+ *   and ∫ λ_a λ_i are always kept).  The reverse-mode calls give g_uf, g_fs
+ *   and the shape derivative g_X, the transport form of the grid case with
+ *   the fluid P1 hats μ_j fixed in space:
+ *     ∂B_ij/∂X_{a,k} = Σ_{T∋a} ∫_T (λ_a λ_i ∂_k μ_j + ∂_k λ_a λ_i μ_j).
+ *   fsi_step returns IBVT_E_UNSUPPORTED.
  *   Errors: IBVT_E_INVALID, IBVT_E_CAPACITY, IBVT_E_NOMEM, IBVT_E_HIP.
  */
 int assemble_coupling_unstructured(const ibvt_mesh* fluid, const ibvt_mesh* solid, int precision,
@@ -305,15 +308,15 @@ int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* 
  *   g_X) followed by transfer_force_vjp(c, g_ff, f_s, alpha, g_fs, g_X),
  *   for a caller that needs the adjoints of both transfers (the velocity
  *   and the force of one coupling step, as in Section 3's loop).  When the
- *   piece moments are stored (3D grid couplings without
- *   IBVT_NO_PIECE_STORE) the two shape-derivative contractions are taken in
- *   one pass over them; otherwise the two calls' paths run one after the
- *   other.  Arguments, layouts, ownership and nullability as in the two
+ *   per-pair integrals are stored (3D grid couplings without
+ *   IBVT_NO_PIECE_STORE, and unstructured couplings) the two
+ *   shape-derivative contractions are taken in one pass over them;
+ *   otherwise (planar couplings, re-clipped pieces) the two calls' paths run
+ *   one after the other.  Arguments, layouts, ownership and nullability as in the two
  *   calls; g_X (nullable) receives both contributions (sums may differ from
  *   the two separate calls by rounding).
  *   Errors: those of the two calls (IBVT_E_INVALID, IBVT_E_NOT_CONVERGED,
- *   IBVT_E_UNSUPPORTED, IBVT_E_HIP); nothing is accumulated when an argument
- *   check fails.
+ *   IBVT_E_HIP); nothing is accumulated when an argument check fails.
  */
 int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], const void* u_s,
                  int mass, double cg_rtol, int cg_maxit, void* const g_uf[3],

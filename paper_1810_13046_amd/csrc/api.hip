@@ -512,8 +512,6 @@ int check_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f
     return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
   if (c->dual && mass != IBVT_LUMPED)
     return set_error(IBVT_E_INVALID, "the dual basis has a diagonal S: use IBVT_LUMPED");
-  if (g_X && c->unstructured)
-    return set_error(IBVT_E_UNSUPPORTED, "no shape derivative for an unstructured background");
   if (g_X && (!u_f || !u_s)) return set_error(IBVT_E_INVALID, "g_X needs u_f and u_s");
   if (g_X)
     for (int d = 0; d < c->ncomp; ++d)
@@ -534,8 +532,6 @@ int check_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s
   if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
   for (int d = 0; d < c->ncomp; ++d)
     if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
-  if (g_X && c->unstructured)
-    return set_error(IBVT_E_UNSUPPORTED, "no shape derivative for an unstructured background");
   if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
   if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
   return IBVT_OK;
@@ -581,8 +577,9 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
   if ((st = velocity_adjoint(c, g_us, mass, cg_rtol, cg_maxit, g_uf, stream, &z))) return st;
   if (g_X) {
     const int m = mass == IBVT_CONSISTENT ? 1 : 0;
-    st = c->dim == 2 ? shape_gradient_2d(c, z, u_f, u_s, m, 1.0, g_X, stream)
-                     : shape_gradient(c, z, u_f, u_s, m, 1.0, g_X, stream);
+    st = c->unstructured ? shape_gradient_unstructured(c, z, u_f, u_s, m, 1.0, g_X, stream)
+         : c->dim == 2   ? shape_gradient_2d(c, z, u_f, u_s, m, 1.0, g_X, stream)
+                         : shape_gradient(c, z, u_f, u_s, m, 1.0, g_X, stream);
     if (st) return st;
   }
   return IBVT_OK;
@@ -594,8 +591,10 @@ int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* 
   if (st) return st;
   if ((st = force_adjoint(c, g_ff, alpha, g_fs, stream))) return st;
   if (g_X) {
-    st = c->dim == 2 ? shape_gradient_2d(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream)
-                     : shape_gradient(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream);
+    st = c->unstructured
+             ? shape_gradient_unstructured(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream)
+         : c->dim == 2 ? shape_gradient_2d(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream)
+                       : shape_gradient(c, f_s, g_ff, nullptr, -1, alpha, g_X, stream);
     if (st) return st;
   }
   return IBVT_OK;
@@ -608,7 +607,7 @@ int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], c
   int st = check_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf, g_X);
   if (st) return st;
   if ((st = check_force_vjp(c, g_ff, f_s, alpha, g_X))) return st;
-  if (!(g_X && c->dim == 3 && c->mom_valid)) {
+  if (!(g_X && c->dim == 3 && (c->unstructured || c->mom_valid))) {
     // no stored moments to share: the two calls
     if ((st = transfer_force_vjp(c, g_ff, f_s, alpha, g_fs, g_X, stream))) return st;
     return transfer_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf, g_X, stream);
@@ -618,6 +617,8 @@ int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], c
   void* z = nullptr;
   if ((st = velocity_adjoint(c, g_us, mass, cg_rtol, cg_maxit, g_uf, stream, &z))) return st;
   const int m = mass == IBVT_CONSISTENT ? 1 : 0;
+  if (c->unstructured)
+    return shape_gradient_unstructured_two(c, z, u_f, u_s, m, f_s, g_ff, alpha, g_X, stream);
   return shape_gradient_two(c, z, u_f, u_s, m, f_s, g_ff, alpha, g_X, stream);
 }
 

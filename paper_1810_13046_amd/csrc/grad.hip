@@ -240,11 +240,11 @@ __global__ __launch_bounds__(256) void k_mass_coef(int64_t n_t, int64_t n_v,
 // One wavefront per vertex a: lanes take (incident tet, component) items,
 // add the per-tet pair terms and the mass term, then a fixed-order wave
 // reduction.  mcoef: per (component, tet) mass coefficients, or null for no
-// mass term.
+// mass term; tetgrad: ∇λ of every tet (12 doubles at stride gstride).
 __global__ __launch_bounds__(256) void k_grad_gather(
     int64_t n_v, int64_t n_t, const int64_t* __restrict__ vt_ptr,
     const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
-    const double* __restrict__ pgt, const double* __restrict__ tetgrad,
+    const double* __restrict__ pgt, const double* __restrict__ tetgrad, int gstride,
     const double* __restrict__ mcoef, double alpha, double* __restrict__ gX) {
   const int64_t a = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int lane = lane_id();
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void k_grad_gather(
     for (int e = 0; e < 3; ++e) g[e] += pgt[tc * 12 + la * 3 + e];
     if (mcoef) {
       const double m = mcoef[tc];
-      const double* ga = tetgrad + t * 12 + la * 3;
+      const double* ga = tetgrad + t * gstride + la * 3;
 #pragma unroll
       for (int e = 0; e < 3; ++e) g[e] -= m * ga[e];
     }
@@ -269,6 +269,29 @@ __global__ __launch_bounds__(256) void k_grad_gather(
   for (int e = 0; e < 3; ++e) g[e] = wave_sum(g[e]);
   if (lane == 0)
     for (int e = 0; e < 3; ++e) gX[3 * a + e] += alpha * g[e];
+}
+
+// g_X += alpha Σ (per-(component, tet) pair terms pgt − mass term of (z, us)),
+// gathered per vertex in a fixed order.
+template <typename T>
+int gather_typed(ibvt_coupling* c, const double* pgt, const void* z, const void* us, int mass,
+                 double alpha, double* gX, const double* grad, int gstride, hipStream_t s) {
+  int st;
+  double* mcoef = nullptr;
+  if (mass >= 0 && c->n_tet > 0) {
+    if ((st = ensure(c, c->mcoef, size_t(3 * c->n_tet + 1) * sizeof(double)))) return st;
+    mcoef = c->mcoef.as<double>();
+    k_mass_coef<T><<<unsigned(ceil_div(3 * c->n_tet, 256)), 256, 0, s>>>(
+        c->n_tet, c->n_vert, c->tets.as<int32_t>(), c->tetvol.as<double>(),
+        static_cast<const T*>(z), static_cast<const T*>(us), mass, mcoef);
+  }
+  const unsigned blocks = unsigned(ceil_div(c->n_vert * kWave, 256));
+  ProfScope ps_g("grad_gather", s);
+  if (c->n_vert > 0)
+    k_grad_gather<<<blocks, 256, 0, s>>>(c->n_vert, c->n_tet, c->vt_ptr.as<int64_t>(),
+                                         c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(), pgt, grad,
+                                         gstride, mcoef, alpha, gX);
+  return hip_check(hipGetLastError(), "gather launch");
 }
 
 // g_X += alpha (shape terms of (z, u) and the mass term of (z, us)) [+ alpha2
@@ -321,21 +344,8 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
           3 * c->n_tet, c->pair_off.as<int64_t>(), pg, pgt);
   }
   if ((st = hip_check(hipGetLastError(), "shape launch"))) return st;
-  double* mcoef = nullptr;
-  if (mass >= 0 && c->n_tet > 0) {
-    if ((st = ensure(c, c->mcoef, size_t(3 * c->n_tet + 1) * sizeof(double)))) return st;
-    mcoef = c->mcoef.as<double>();
-    k_mass_coef<T><<<unsigned(ceil_div(3 * c->n_tet, 256)), 256, 0, s>>>(
-        c->n_tet, c->n_vert, c->tets.as<int32_t>(), c->tetvol.as<double>(),
-        static_cast<const T*>(z), static_cast<const T*>(us), mass, mcoef);
-  }
-  const unsigned blocks = unsigned(ceil_div(c->n_vert * kWave, 256));
-  ProfScope ps_g("grad_gather", s);
-  if (c->n_vert > 0)
-    k_grad_gather<<<blocks, 256, 0, s>>>(c->n_vert, c->n_tet, c->vt_ptr.as<int64_t>(),
-                                         c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(), pgt,
-                                         c->tetgrad.as<double>(), mcoef, alpha, gX);
-  if ((st = hip_check(hipGetLastError(), "gather launch"))) return st;
+  if ((st = gather_typed<T>(c, pgt, z, us, mass, alpha, gX, c->tetgrad.as<double>(), 12, s)))
+    return st;
   unsigned f = 0;
   if ((st = hip_check(hipMemcpyAsync(&f, flags, sizeof(f), hipMemcpyDeviceToHost, s), "read")))
     return st;
@@ -350,6 +360,13 @@ int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], cons
                    int mass, double alpha, double* gX, hipStream_t s) {
   if (c->precision == IBVT_FP32_MIXED) return shape_typed<float>(c, z, u, us, mass, alpha, gX, s);
   return shape_typed<double>(c, z, u, us, mass, alpha, gX, s);
+}
+
+int shape_gather(ibvt_coupling* c, const double* pgt, const void* z, const void* us, int mass,
+                 double alpha, double* gX, const double* grad, int gstride, hipStream_t s) {
+  if (c->precision == IBVT_FP32_MIXED)
+    return gather_typed<float>(c, pgt, z, us, mass, alpha, gX, grad, gstride, s);
+  return gather_typed<double>(c, pgt, z, us, mass, alpha, gX, grad, gstride, s);
 }
 
 int shape_gradient_two(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,

@@ -176,6 +176,17 @@ int solid_masses(ibvt_coupling* c, hipStream_t s);
 // tet ∩ tet clipping); the fluid tree is built once per handle
 int build_fluid_tree(ibvt_coupling* c, hipStream_t s);
 int assemble_all_unstructured(ibvt_coupling* c, hipStream_t s);
+// unstructured.hip: g_X += alpha (shape terms of (z, u) [− mass term of
+// (z, us) when mass >= 0]) from the stored per-pair integrals
+int shape_gradient_unstructured(ibvt_coupling* c, const void* z, const void* const u[3],
+                                const void* us, int mass, double alpha, double* gX,
+                                hipStream_t s);
+// both adjoints in one pass: (z, u) with the mass term of (z, us), plus
+// alpha2 · (z2, v)
+int shape_gradient_unstructured_two(ibvt_coupling* c, const void* z, const void* const u[3],
+                                    const void* us, int mass, const void* z2,
+                                    const void* const v[3], double alpha2, double* gX,
+                                    hipStream_t s);
 
 // assemble2d.hip: the planar coupling (Q1 quadrilateral lattice x P1 triangles)
 int assemble_all_2d(ibvt_coupling* c, hipStream_t s);
@@ -197,6 +208,11 @@ int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream
 // grad.hip
 int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
                    int mass, double alpha, double* gX, hipStream_t s);
+// g_X += alpha Σ (per-(component, tet) pair terms pgt[(d, t)][12] − mass
+// term of (z, us) when mass >= 0), gathered per vertex in a fixed order;
+// grad: ∇λ of every tet, 12 doubles at stride gstride.
+int shape_gather(ibvt_coupling* c, const double* pgt, const void* z, const void* us, int mass,
+                 double alpha, double* gX, const double* grad, int gstride, hipStream_t s);
 // both adjoints' shape terms in one pass over the stored piece moments:
 // (z, u) with the mass term of (z, us), plus alpha2 · (z2, v)
 int shape_gradient_two(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,

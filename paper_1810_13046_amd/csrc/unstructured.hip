@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kWave) void k_pairs_u(
     int64_t n_list, const int32_t* __restrict__ list, int64_t n_s, const int64_t* __restrict__ off,
     const int32_t* __restrict__ pf, const double* __restrict__ srec,
     const double* __restrict__ frec, double drop_rel, int dual, uint8_t* __restrict__ keep,
-    T* __restrict__ vals, unsigned* flags, unsigned long long* counters) {
+    T* __restrict__ vals, T* __restrict__ lams, unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[kUSlots * kWave], sy[kUSlots * kWave], sz[kUSlots * kWave];
   __shared__ uint32_t snb[kUSlots * kWave];
   const int lane = threadIdx.x;
@@ -367,9 +367,9 @@ __global__ __launch_bounds__(kWave) void k_pairs_u(
     double rs[kURec], rf[kURec];
     load_row<kURec>(srec + kURec * s, rs);
     load_row<kURec>(frec + kURec * f, rf);
-    double acc[16];
+    double acc[16], lam[10];
     double vol = 0.0;
-    fail = !tet_pair_values(P, rs, rf, acc, vol);
+    fail = !tet_pair_values(P, rs, rf, acc, vol, lam);
     kept = !fail && vol > drop_rel * fabs(rs[24]) / 6.0;
     dropped = !fail && !kept && vol > 0.0;
     if (kept && dual) {
@@ -381,6 +381,9 @@ __global__ __launch_bounds__(kWave) void k_pairs_u(
     T out[16];
     for (int k = 0; k < 16; ++k) out[k] = kept ? T(acc[k]) : T(0);
     store_row<16>(vals + 16 * p, out);
+    T lo[kULam];
+    for (int k = 0; k < kULam; ++k) lo[k] = (kept && k < 10) ? T(lam[k]) : T(0);
+    store_row<kULam>(lams + kULam * p, lo);
     keep[p] = kept ? 1 : 0;
   }
   const uint64_t km = ballot64(kept), dm = ballot64(dropped), fm = ballot64(fail);
@@ -820,6 +823,7 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
   if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 16 * sizeof(T)))) return st;
+  if ((st = ensure(c, c->pmom, size_t(n_pairs + 1) * kULam * sizeof(T)))) return st;
   unsigned over = 0;
   if ((st = read_back(c, &over, ovf, sizeof(over), s))) return st;
   {
@@ -858,7 +862,7 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
       k_pairs_u<T><<<unsigned(ceil_div(n_list, kWave)), kWave, 0, s>>>(
           n_list, list, n_s, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(),
           c->tetrec.as<double>(), c->frec.as<double>(), 1e-14, c->dual ? 1 : 0,
-          c->keep.as<uint8_t>(), c->pval.as<T>(), flags, counters);
+          c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>(), flags, counters);
   }
   if ((st = hip_check(hipGetLastError(), "pairs launch"))) return st;
   // (IV) B: rows gathered in LDS, or by sorting the entries when a row is
@@ -885,6 +889,149 @@ int assemble_u_typed(ibvt_coupling* c, hipStream_t s) {
   c->mom_valid = false;
   c->stats.assemblies += 1;
   return check_flags(c, s);
+}
+
+// Reverse mode, one lane per (component d, solid tet s) walking the tet's
+// kept pairs.  Moving vertex a of the solid tet moves its points by λ_a e_k
+// while the fluid hats stay fixed, so with w = Σ_i z'_i λ_i (z' the dual
+// weights 5 z_i − Σ_k z_k with dual multipliers, else z) and U = Σ_j u_j μ_j
+// (constant gradient on the pair's fluid tet) a pair adds
+//   ∂_k U · Σ_i z'_i ∫ λ_a λ_i  +  ∂_k λ_a · Σ_ij z_i u_j vals_ij
+// (vals holds ∫ ψ_i μ_j with dual multipliers, which carries the weights).
+// Sums in double to pgt[(d, s)][12] (vertex a, axis k at a*3 + k).  With
+// TWO a second contraction (weights z2, fluid field v, factor alpha2) is
+// added from the same pair data: both adjoints in one pass.
+template <typename T, bool TWO>
+__global__ __launch_bounds__(256) void k_shape_u(
+    int64_t n_s, int64_t n_v, const int64_t* __restrict__ off, const int32_t* __restrict__ pf,
+    const uint8_t* __restrict__ keep, const T* __restrict__ vals, const T* __restrict__ lams,
+    const double* __restrict__ srec, const double* __restrict__ frec,
+    const int32_t* __restrict__ tets_s, const int32_t* __restrict__ tets_f,
+    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, const T* __restrict__ z2,
+    const T* v0, const T* v1, const T* v2, double alpha2, int dual, double* __restrict__ pgt) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= 3 * n_s) return;
+  const int d = int(w / n_s);
+  const int64_t s = w - int64_t(d) * n_s;
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  const int64_t p0 = off[s], p1 = off[s + 1];
+  if (p1 > p0) {
+    const int4 tv = *reinterpret_cast<const int4*>(tets_s + 4 * s);
+    const T* zd = z + int64_t(d) * n_v;
+    const double zl[4] = {double(zd[tv.x]), double(zd[tv.y]), double(zd[tv.z]),
+                          double(zd[tv.w])};
+    double zw[4] = {zl[0], zl[1], zl[2], zl[3]};
+    if (dual) {
+      const double sum = zl[0] + zl[1] + zl[2] + zl[3];
+      for (int i = 0; i < 4; ++i) zw[i] = 5.0 * zl[i] - sum;
+    }
+    double zl2[4] = {0.0, 0.0, 0.0, 0.0}, zw2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (TWO) {
+      const T* z2d = z2 + int64_t(d) * n_v;
+      zl2[0] = double(z2d[tv.x]);
+      zl2[1] = double(z2d[tv.y]);
+      zl2[2] = double(z2d[tv.z]);
+      zl2[3] = double(z2d[tv.w]);
+      const double sum = zl2[0] + zl2[1] + zl2[2] + zl2[3];
+      for (int i = 0; i < 4; ++i) zw2[i] = dual ? 5.0 * zl2[i] - sum : zl2[i];
+    }
+    const T* v = (d == 0) ? v0 : (d == 1 ? v1 : v2);
+    const double* gl = srec + kURec * s + 12;  // ∇λ_a at gl[3a + k]
+    const T* u = (d == 0) ? u0 : (d == 1 ? u1 : u2);
+    for (int64_t p = p0; p < p1; ++p) {
+      if (!keep[p]) continue;
+      const int64_t f = pf[p];
+      const int4 fv = *reinterpret_cast<const int4*>(tets_f + 4 * f);
+      const double ul[4] = {double(u[fv.x]), double(u[fv.y]), double(u[fv.z]), double(u[fv.w])};
+      const double* gm = frec + kURec * f + 12;  // ∇μ_j at gm[3j + k]
+      double gu[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        gu[k] = ul[0] * gm[k] + ul[1] * gm[3 + k] + ul[2] * gm[6 + k] + ul[3] * gm[9 + k];
+      T V[16], L[kULam];
+      load_row<16>(vals + 16 * p, V);
+      load_row<kULam>(lams + kULam * p, L);
+      double zvu = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double r = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r += double(V[4 * i + j]) * ul[j];
+        zvu += zl[i] * r;
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        double zla = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) zla += zw[i] * double(L[lam_index(a, i)]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[a * 3 + k] += gu[k] * zla + gl[3 * a + k] * zvu;
+      }
+      if (TWO) {
+        const double vl[4] = {double(v[fv.x]), double(v[fv.y]), double(v[fv.z]),
+                              double(v[fv.w])};
+        double gv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          gv[k] = vl[0] * gm[k] + vl[1] * gm[3 + k] + vl[2] * gm[6 + k] + vl[3] * gm[9 + k];
+        double zvv = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double r = 0.0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) r += double(V[4 * i + j]) * vl[j];
+          zvv += zl2[i] * r;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          double zla = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) zla += zw2[i] * double(L[lam_index(a, i)]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            acc[a * 3 + k] += alpha2 * (gv[k] * zla + gl[3 * a + k] * zvv);
+        }
+      }
+    }
+  }
+  store_row<12>(pgt + w * 12, acc);
+}
+
+template <typename T>
+int shape_u_typed(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
+                  int mass, double alpha, double* gX, hipStream_t s, const void* z2 = nullptr,
+                  const void* const* v = nullptr, double alpha2 = 0.0) {
+  if (c->n_pairs > 0 && !c->pmom.p)
+    return set_error(IBVT_E_INVALID, "the per-pair integrals are not stored");
+  const size_t tc_bytes = (size_t(3 * c->n_tet + 1) * 12 * sizeof(double) + 255) & ~size_t(255);
+  int st = ensure(c, c->work2, tc_bytes);
+  if (st) return st;
+  double* pgt = c->work2.as<double>();
+  {
+    ProfScope ps("shape_terms", s);
+    const unsigned nb = blocks_for(3 * c->n_tet, 256);
+    const T* zz = static_cast<const T*>(z);
+    const T* u0 = static_cast<const T*>(u[0]);
+    const T* u1 = static_cast<const T*>(u[1]);
+    const T* u2 = static_cast<const T*>(u[2]);
+    if (c->n_tet > 0 && z2)
+      k_shape_u<T, true><<<nb, 256, 0, s>>>(
+          c->n_tet, c->n_vert, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(),
+          c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>(), c->tetrec.as<double>(),
+          c->frec.as<double>(), c->tets.as<int32_t>(), c->ftets.as<int32_t>(), zz, u0, u1, u2,
+          static_cast<const T*>(z2), static_cast<const T*>(v[0]), static_cast<const T*>(v[1]),
+          static_cast<const T*>(v[2]), alpha2 / alpha, c->dual ? 1 : 0, pgt);
+    else if (c->n_tet > 0)
+      k_shape_u<T, false><<<nb, 256, 0, s>>>(
+          c->n_tet, c->n_vert, c->pair_off.as<int64_t>(), c->owner.as<int32_t>(),
+          c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>(), c->tetrec.as<double>(),
+          c->frec.as<double>(), c->tets.as<int32_t>(), c->ftets.as<int32_t>(), zz, u0, u1, u2,
+          nullptr, nullptr, nullptr, nullptr, 0.0, c->dual ? 1 : 0, pgt);
+  }
+  if ((st = hip_check(hipGetLastError(), "shape launch"))) return st;
+  return shape_gather(c, pgt, z, us, mass, alpha, gX, c->tetrec.as<double>() + 12, kURec, s);
 }
 
 }  // namespace
@@ -962,6 +1109,26 @@ int assemble_all_unstructured(ibvt_coupling* c, hipStream_t s) {
   }
   if ((st = ensure(c, c->minv, size_t(n_v + 1) * sizeof(double)))) return st;
   return assemble_u_typed<double>(c, s);
+}
+
+}  // namespace ibvt
+
+namespace ibvt {
+
+int shape_gradient_unstructured(ibvt_coupling* c, const void* z, const void* const u[3],
+                                const void* us, int mass, double alpha, double* gX,
+                                hipStream_t s) {
+  if (c->precision == IBVT_FP32_MIXED) return shape_u_typed<float>(c, z, u, us, mass, alpha, gX, s);
+  return shape_u_typed<double>(c, z, u, us, mass, alpha, gX, s);
+}
+
+int shape_gradient_unstructured_two(ibvt_coupling* c, const void* z, const void* const u[3],
+                                    const void* us, int mass, const void* z2,
+                                    const void* const v[3], double alpha2, double* gX,
+                                    hipStream_t s) {
+  if (c->precision == IBVT_FP32_MIXED)
+    return shape_u_typed<float>(c, z, u, us, mass, 1.0, gX, s, z2, v, alpha2);
+  return shape_u_typed<double>(c, z, u, us, mass, 1.0, gX, s, z2, v, alpha2);
 }
 
 }  // namespace ibvt

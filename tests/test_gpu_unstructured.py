@@ -2,8 +2,9 @@
 P1 solid tets) on the HIP path, through the C ABI, against the oracle
 (oracle/unstructured.py): B and B^T entry by entry, the candidate count of
 the tree search against the exact box test, transfers (lumped, consistent,
-load), dual multipliers, determinism and reassembly, the full-size case by
-sampled rows and exact affine reproduction, and error paths.  Tolerances:
+load), the reverse mode with the shape derivative, dual multipliers,
+determinism and reassembly, the full-size case by sampled rows and exact
+affine reproduction, and error paths.  Tolerances:
 FP64 1e-12, FP32 1e-5 relative Frobenius."""
 import numpy as np
 import pytest
@@ -105,26 +106,34 @@ def test_unstructured_transfers_match_oracle(dev, un, prec):
         for d in range(3):
             e = rel_fro(ff[d].cpu().numpy(), want[d])
             assert e <= (TOL[prec] if not load else (1e-10 if prec == "fp64" else 1e-5)), (d, e)
-    # reverse mode: the fluid cotangent works, the shape derivative does not
-    from paper_1810_13046_amd import IbvtError
-    g_us = to_dev(W.f_s(), dt, dev)
-    g_uf = [torch.zeros_like(u) for u in ud]
-    c.velocity_vjp(g_us, u_f=ud, u_s=None, mass="lumped", g_uf=g_uf)
-    want = un.transfer_force(R, W.f_s() / un.lumped_mass(W.X, W.tets)[None, :], 1.0)
-    for d in range(3):
-        assert rel_fro(g_uf[d].cpu().numpy(), want[d]) <= TOL[prec]
-    g0 = [torch.zeros_like(u) for u in ud]
-    with pytest.raises(IbvtError) as e:
-        c.velocity_vjp(g_us, u_f=ud, u_s=g_us, mass="lumped", g_uf=g0,
-                       g_X=torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev))
-    assert e.value.name == "IBVT_E_UNSUPPORTED"
-    g_fs = torch.zeros_like(g_us)
-    with pytest.raises(IbvtError) as e:
-        c.force_vjp(ud, f_s=g_us, g_fs=g_fs,
-                    g_X=torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev))
-    assert e.value.name == "IBVT_E_UNSUPPORTED"
-    # refused before any output was touched
-    assert all(int(torch.count_nonzero(g)) == 0 for g in g0 + [g_fs])
+    # reverse mode: fluid cotangents and the shape derivative, both adjoints
+    g_tol = 1e-10 if prec == "fp64" else 1e-4
+    g_us_np = np.random.default_rng(8).standard_normal((3, W.X.shape[0]))
+    g_us = to_dev(g_us_np, dt, dev)
+    for mass in ("lumped", "consistent"):
+        say(f"[gpu] unstructured velocity vjp {prec} {mass}")
+        rt = 1e-14 if prec == "fp64" else 1e-7
+        us = c.velocity(ud, mass=mass, rtol=rt)
+        g_uf = [torch.zeros_like(u) for u in ud]
+        g_X = torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev)
+        c.velocity_vjp(g_us, u_f=ud, u_s=us, mass=mass, g_uf=g_uf, g_X=g_X, rtol=rt)
+        want_uf, want_X = un.velocity_vjp(R, u_f, g_us_np, mass)
+        e = rel_fro(g_X.cpu().numpy(), want_X)
+        say(f"  g_X rel {e:.2e}")
+        assert e <= g_tol
+        for d in range(3):
+            assert rel_fro(g_uf[d].cpu().numpy(), want_uf[d]) <= g_tol
+    say(f"[gpu] unstructured force vjp {prec}")
+    g_ff_np = np.random.default_rng(9).standard_normal((3, W.Xf.shape[0]))
+    g_fs = torch.zeros((3, W.X.shape[0]), dtype=dt, device=dev)
+    g_X = torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev)
+    c.force_vjp([to_dev(g, dt, dev) for g in g_ff_np], f_s=to_dev(f_s, dt, dev), alpha=1.3,
+                g_fs=g_fs, g_X=g_X)
+    want_fs, want_X = un.force_vjp(R, f_s, g_ff_np, 1.3)
+    e = rel_fro(g_X.cpu().numpy(), want_X)
+    say(f"  g_X rel {e:.2e}")
+    assert e <= g_tol
+    assert rel_fro(g_fs.cpu().numpy(), want_fs) <= TOL[prec]
     c.free()
 
 
@@ -139,6 +148,16 @@ def test_unstructured_dual(dev, un, prec):
     us = c.velocity([to_dev(u, c.dtype, dev)] * 3, mass="lumped").cpu().numpy()
     assert np.max(np.abs(us - WU.linear_fields(W.X, co)[None, :])) <= (
         1e-11 if prec == "fp64" else 1e-5)
+    # the shape derivative with the dual weights
+    import torch
+    u_f = W.u_f()
+    ud = [to_dev(x, c.dtype, dev) for x in u_f]
+    usd = c.velocity(ud, mass="lumped")
+    g_us_np = np.random.default_rng(10).standard_normal((3, W.X.shape[0]))
+    g_X = torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev)
+    c.velocity_vjp(to_dev(g_us_np, c.dtype, dev), u_f=ud, u_s=usd, mass="lumped", g_X=g_X)
+    _, want_X = un.velocity_vjp(R, u_f, g_us_np, "lumped")
+    assert rel_fro(g_X.cpu().numpy(), want_X) <= (1e-10 if prec == "fp64" else 1e-4)
     c.free()
 
 

@@ -3,7 +3,7 @@ call — on the HIP path, through the C ABI: against the oracle's two adjoints
 summed, and against the two separate calls (with stored moments the two
 shape contractions share one pass over them; without, the two calls' paths
 run in turn).  Also the dual multipliers, the planar and unstructured
-couplings, and refusals that must leave every output untouched.
+couplings, and a refused call that must leave every output untouched.
 Tolerances: g_X against the oracle 1e-10 (FP64) / 1e-4 (FP32) relative, as
 for the separate calls; fused against separate 1e-12 (FP64) / 1e-5 (FP32),
 since only the order of the sums into g_X differs."""
@@ -143,43 +143,32 @@ def test_vjp_both_planar(dev, prec):
     c.free()
 
 
-def test_vjp_both_refusals_touch_nothing(dev):
+def test_vjp_both_unstructured_and_refusals(dev):
+    """The unstructured coupling contracts both adjoints in one pass over its
+    per-pair integrals; a non-finite α is refused before any output is
+    touched."""
     import torch
     from paper_1810_13046_amd import Coupling, IbvtError
     WU = wl.unstructured
     W = WU.workload_u(1)
-    say("[gpu] vjp both: unstructured and bad arguments")
+    say("[gpu] vjp both: unstructured, and a refused call")
     c = Coupling(None, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
                  fluid_mesh=(to_dev(W.Xf, torch.float64, dev), to_dev(W.tets_f, torch.int32, dev)))
     u = [to_dev(x, torch.float64, dev) for x in W.u_f()]
+    us = c.velocity(u, mass="lumped")
     g_us = to_dev(W.f_s(), torch.float64, dev)
     f_s = to_dev(W.f_s()[::-1].copy(), torch.float64, dev)
-    # without g_X the unstructured coupling gives both cotangents
-    both_ways_noX(c, dev, u, g_us, f_s)
+    g_ff = [torch.flip(x, dims=[0]).contiguous() for x in u]
+    (uf1, fs1, X1), (uf2, fs2, X2) = both_ways(c, dev, u, us, g_us, g_ff, f_s, 0.9, "lumped",
+                                              1e-12)
+    for d in range(3):
+        np.testing.assert_array_equal(uf1[d], uf2[d])
+    np.testing.assert_array_equal(fs1, fs2)
+    assert rel_fro(X1, X2) <= 1e-12
     g_uf, g_fs, g_X = zeros_like_all(c, dev, u)
     with pytest.raises(IbvtError) as e:
-        c.vjp(g_us, u, u_f=u, u_s=g_us, f_s=f_s, g_uf=g_uf, g_fs=g_fs, g_X=g_X)
-    assert e.value.name == "IBVT_E_UNSUPPORTED"
-    with pytest.raises(IbvtError) as e:
-        c.vjp(g_us, u, f_s=f_s, alpha=float("nan"), g_uf=g_uf, g_fs=g_fs)
+        c.vjp(g_us, g_ff, u_f=u, u_s=us, f_s=f_s, alpha=float("nan"), g_uf=g_uf, g_fs=g_fs,
+              g_X=g_X)
     assert e.value.name == "IBVT_E_INVALID"
     assert all(int(torch.count_nonzero(g)) == 0 for g in g_uf + [g_fs, g_X])
     c.free()
-
-
-def both_ways_noX(c, dev, u, g_us, f_s):
-    import torch
-    out = []
-    for fused in (True, False):
-        g_uf = [torch.zeros_like(x) for x in u]
-        g_fs = torch.zeros_like(g_us)
-        if fused:
-            c.vjp(g_us, u, f_s=f_s, alpha=0.9, g_uf=g_uf, g_fs=g_fs)
-        else:
-            c.velocity_vjp(g_us, g_uf=g_uf)
-            c.force_vjp(u, f_s=f_s, alpha=0.9, g_fs=g_fs)
-        out.append(([g.cpu().numpy() for g in g_uf], g_fs.cpu().numpy(), None))
-    for d in range(3):
-        np.testing.assert_array_equal(out[0][0][d], out[1][0][d])
-    np.testing.assert_array_equal(out[0][1], out[1][1])
-    return out
