@@ -13,7 +13,10 @@ recompute_B=True the coupling is freed after the forward pass and
 assembled again from the saved X in the backward pass, so B and the piece
 store are not held between the two passes.  Planar couplings (two face
 arrays, X (n_vert, 2), triangles) take two fluid components: pass
-u_f = (u0, u1) and get two force arrays back.
+u_f = (u0, u1) and get two force arrays back.  An unstructured coupling
+(Coupling(None, X, tets, fluid_mesh=...)) is passed as `coupling` (faces
+None; fluid fields are nodal arrays of the fluid mesh); it is not
+reassembled by recompute_B.
 """
 from __future__ import annotations
 
