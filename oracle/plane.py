@@ -397,6 +397,66 @@ def velocity_loss(faces, X, tris, u_f, u_target, mass="lumped", dual=False):
 
 
 # ----------------------------------------------------------------------------
+# Fixed-point (Picard) coupling of Section 3 in the plane
+# ----------------------------------------------------------------------------
+
+def fluid_lumped_volume(faces, d: int):
+    """∫ N_j over the hull of component d's planar lattice for every node,
+    shape (n_y, n_x): a product of two 1D hat integrals, each half the
+    length of the node's neighbouring intervals."""
+    w = []
+    for L in lattice(faces, d):
+        h = np.diff(L)
+        we = np.zeros(L.size)
+        we[:-1] += 0.5 * h
+        we[1:] += 0.5 * h
+        w.append(we)
+    return np.outer(w[1], w[0])
+
+
+def fsi_step(faces, X_ref, tris, u_hat0, v_f, solid, fluid, dt, alpha=1.0, eps_abs=0.0,
+             eps_rel=1e-8, max_iter=50, mass="lumped", force_density=False, dual=False,
+             f_prev=None):
+    """One time step of the Picard iteration of Section 3 for a planar
+    coupling, in the steps' order: T = S^{-1} B assembled at X_ref + u_hat0
+    and held for the step; 1. w_s = T v_f; 2. u_hat = u_hat0 + dt w_s;
+    3. f_fsi = solid(u_hat); 4. f_tilde = alpha B^T S^{-1} f_fsi (divided by
+    the fluid nodes' lumped area with force_density); 5. v_f = fluid(f_tilde);
+    6. stop when ||f_l − f_{l−1}||_inf < eps_abs or that over ||f_1||_inf <
+    eps_rel; f_0 = f_prev (zeros by default).  Returns the last iteration's
+    fields and the iteration count."""
+    X = np.asarray(X_ref, dtype=np.float64) + np.asarray(u_hat0, dtype=np.float64).T
+    cpl = assemble(faces, X, tris, dual=dual)
+    S = _mass_of(cpl, mass)
+    u_hat0 = np.asarray(u_hat0, dtype=np.float64)
+    v = [np.asarray(a, dtype=np.float64).ravel().copy() for a in v_f]
+    f_old = np.zeros_like(u_hat0) if f_prev is None else np.asarray(f_prev, dtype=np.float64)
+    areas = [fluid_lumped_volume(faces, d).ravel() for d in range(2)] if force_density else None
+    f1 = None
+    out = {}
+    for it in range(1, max_iter + 1):
+        w_s = mass_solve(X, tris, np.stack([cpl.B[d] @ v[d] for d in range(2)]), S)
+        u_hat = u_hat0 + dt * w_s
+        f = np.asarray(solid(u_hat), dtype=np.float64)
+        g = mass_solve(X, tris, f, S)
+        f_tilde = [alpha * (cpl.B[d].T @ g[d]) for d in range(2)]
+        if force_density:
+            f_tilde = [f_tilde[d] / areas[d] for d in range(2)]
+        v = [np.asarray(a, dtype=np.float64).ravel() for a in fluid(f_tilde)]
+        res = float(np.max(np.abs(f - f_old)))
+        if it == 1:
+            f1 = float(np.max(np.abs(f)))
+        rel = res / f1 if f1 > 0 else (np.inf if res > 0 else 0.0)
+        f_old = f
+        out = dict(iterations=it, w_s=w_s, u_hat=u_hat, f_fsi=f, f_tilde=f_tilde, v_f=v,
+                   res_abs=res, res_rel=rel, f1_norm=f1, converged=False, B=cpl.B)
+        if (eps_abs > 0 and res < eps_abs) or (eps_rel > 0 and rel < eps_rel):
+            out["converged"] = True
+            break
+    return out
+
+
+# ----------------------------------------------------------------------------
 # Small helpers exposed for the pins
 # ----------------------------------------------------------------------------
 

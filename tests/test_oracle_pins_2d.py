@@ -349,3 +349,81 @@ def test_force_gradient_fd(pl):
     for D in P2.fd_directions2(X.shape[0], 3, 83):
         fd = (L(X + h * D) - L(X - h * D)) / (2 * h)
         assert float(np.sum(gX * D)) == pytest.approx(fd, rel=2e-6, abs=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Picard coupling (Section 3) in the plane
+# ---------------------------------------------------------------------------
+
+def test_fluid_lumped_area(pl):
+    """∫ N_j over the lattice hull, against a two-point Gauss rule per cell
+    (exact for the bilinear hat) with the hat read off a piecewise-linear
+    interpolant of a unit vector; the areas tile the hull."""
+    faces = [np.concatenate([[0.0], np.cumsum(np.random.default_rng(3).uniform(0.5, 2.0, 9))]),
+             np.linspace(-0.2, 0.3, 7)]
+    g = np.array([-1.0, 1.0]) / np.sqrt(3.0)
+    for d in range(2):
+        lat = pl.lattice(faces, d)
+        A = pl.fluid_lumped_volume(faces, d)
+        assert A.shape == (lat[1].size, lat[0].size)
+        q = []
+        for L in lat:
+            h = np.diff(L)
+            xs = (0.5 * (L[:-1] + L[1:])[:, None] + 0.5 * h[:, None] * g[None, :]).ravel()
+            ws = np.repeat(0.5 * h, 2)
+            q.append((xs, ws))
+        for j in range(lat[1].size):
+            for i in range(lat[0].size):
+                ex = np.zeros(lat[0].size)
+                ex[i] = 1.0
+                ey = np.zeros(lat[1].size)
+                ey[j] = 1.0
+                hx = np.interp(q[0][0], lat[0], ex)
+                hy = np.interp(q[1][0], lat[1], ey)
+                ref = float(hx @ q[0][1]) * float(hy @ q[1][1])
+                assert abs(A[j, i] - ref) <= 1e-15 * max(1.0, ref)
+        hull = (lat[0][-1] - lat[0][0]) * (lat[1][-1] - lat[1][0])
+        assert abs(A.sum() - hull) <= 1e-13 * hull
+
+
+@pytest.mark.parametrize("mode,density", [("lumped", False), ("consistent", False),
+                                          ("dual", False), ("lumped", True)])
+def test_fsi_picard_reaches_the_fixed_point(pl, mode, density):
+    """With a linear spring for the solid and a fluid whose velocity responds
+    linearly to the force, the fixed point of Steps 1-5 solves
+    (I + k dt beta alpha T D⁻¹ Tᵀ) f = −k (û0 − û_rest + dt T v_base) per
+    component, T = S⁻¹B and D the fluid nodes' lumped areas (identity
+    without the density option): the Picard loop must land on the direct
+    solution of that dense system."""
+    faces, X, tris = _small_case()
+    n = X.shape[0]
+    dual = mode == "dual"
+    mass = "consistent" if mode == "consistent" else "lumped"
+    rng = np.random.default_rng(21)
+    u_rest = 1e-3 * rng.standard_normal((2, n))
+    v_base = [rng.standard_normal(pl.n_fluid(faces, d)) for d in range(2)]
+    k_s, beta = 10.0, 0.5 if not density else 0.5 / 400.0
+
+    def solid(u_hat):
+        return -k_s * (u_hat - u_rest)
+
+    def fluid(f_tilde):
+        return [v_base[d] + beta * f_tilde[d] for d in range(2)]
+
+    u0 = 1e-3 * np.random.default_rng(5).standard_normal((2, n))
+    v0 = [np.zeros(pl.n_fluid(faces, d)) for d in range(2)]
+    dt, alpha = 0.05, 0.8
+    r = pl.fsi_step(faces, X, tris, u0, v0, solid, fluid, dt, alpha, eps_abs=1e-14, eps_rel=0.0,
+                    max_iter=200, mass=mass, force_density=density, dual=dual)
+    assert r["converged"]
+    c = pl.assemble(faces, X + u0.T, tris, dual=dual)
+    Sm = (np.diag(pl.lumped_mass(c.X, tris)) if mass == "lumped"
+          else pl.consistent_mass(c.X, tris).toarray())
+    for d in range(2):
+        Td = np.linalg.solve(Sm, c.B[d].toarray())
+        Dinv = (1.0 / pl.fluid_lumped_volume(faces, d).ravel() if density
+                else np.ones(Td.shape[1]))
+        A = np.eye(n) + k_s * dt * beta * alpha * (Td * Dinv[None, :]) @ Td.T
+        rhs = -k_s * (u0[d] - u_rest[d] + dt * Td @ v_base[d])
+        f_star = np.linalg.solve(A, rhs)
+        assert np.max(np.abs(r["f_fsi"][d] - f_star)) <= 1e-11 * max(1.0, np.max(np.abs(f_star)))
