@@ -204,8 +204,9 @@ typedef struct {
  *   (IBVT_NO_PIECE_STORE has no effect).  IBVT_DUAL_BASIS gives ψ_i =
  *   4λ_i − 1.  The handle works with every transfer call (two components,
  *   see the conventions above), reassemble_coupling (X (n_vert, 2)),
- *   coupling_info and coupling_export_csr (comp 0 or 1); fsi_step returns
- *   IBVT_E_UNSUPPORTED for it.
+ *   coupling_info, coupling_export_csr (comp 0 or 1) and fsi_step (two
+ *   components, X_ref (n_vert, 2); the density option divides by the
+ *   nodes' Q1 lumped area).
  *   Errors: IBVT_E_INVALID, IBVT_E_OUT_OF_GRID, IBVT_E_CAPACITY,
  *   IBVT_E_NOMEM, IBVT_E_HIP.
  */
@@ -381,15 +382,17 @@ int ibvt_lattice_coords_2d(const ibvt_grid2d* grid, int comp, int axis, double* 
  *
  * Callbacks run on the calling thread and enqueue their work on `stream`;
  * they return an ibvt status (non-zero stops the step with that status).
- *   solid(ctx, u_hat (3, n_vert), f_fsi (3, n_vert) out, stream)
- *   fluid(ctx, f_tilde[3] in, v_f[3] out (may alias the caller's v_f), stream)
+ * With nc the coupling's component count (3, or 2 for a planar coupling):
+ *   solid(ctx, u_hat (nc, n_vert), f_fsi (nc, n_vert) out, stream)
+ *   fluid(ctx, f_tilde[nc] in, v_f[nc] out (may alias the caller's v_f), stream)
  *
- * Buffers (device, caller-owned; solid fields (3, n_vert), fluid fields per
+ * Buffers (device, caller-owned; solid fields (nc, n_vert), fluid fields per
  * component as in the transfers, in the coupling's precision; X_ref double
- * (n_vert, 3)): X_ref, u_hat0 in; v_f in/out; u_hat, w_s, f_fsi, f_tilde
- * out; f_prev in (f_fsi,0) and overwritten (workspace).
+ * (n_vert, dim)): X_ref, u_hat0 in; v_f in/out; u_hat, w_s, f_fsi, f_tilde
+ * out; f_prev in (f_fsi,0) and overwritten (workspace).  A planar coupling
+ * reads v_f[0..1] and f_tilde[0..1] only.
  * Errors: IBVT_E_INVALID (arguments, consistent mass not built, dual basis
- * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (planar or unstructured coupling),
+ * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (unstructured coupling),
  * IBVT_E_NOT_CONVERGED (max_iter reached; results of the last iteration are
  * written), or the status of a failed call or callback.
  */
@@ -410,12 +413,12 @@ typedef struct {
 } ibvt_fsi_config;
 
 typedef struct {
-  const double* X_ref;    /* (n_vert, 3) reference configuration */
-  const void* u_hat0;     /* (3, n_vert) displacement at the start of the step */
-  void* u_hat;            /* (3, n_vert) out */
-  void* w_s;              /* (3, n_vert) out: transferred velocity */
-  void* f_fsi;            /* (3, n_vert) out: reaction force, last iteration */
-  void* f_prev;           /* (3, n_vert) in: f_fsi,0; workspace */
+  const double* X_ref;    /* (n_vert, dim) reference configuration */
+  const void* u_hat0;     /* (nc, n_vert) displacement at the start of the step */
+  void* u_hat;            /* (nc, n_vert) out */
+  void* w_s;              /* (nc, n_vert) out: transferred velocity */
+  void* f_fsi;            /* (nc, n_vert) out: reaction force, last iteration */
+  void* f_prev;           /* (nc, n_vert) in: f_fsi,0; workspace */
   void* v_f[3];           /* fluid velocity, in/out */
   void* f_tilde[3];       /* transferred force, out */
 } ibvt_fsi_buffers;

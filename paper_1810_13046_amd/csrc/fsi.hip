@@ -1,5 +1,6 @@
 // Fixed-point (Picard) fluid-structure coupling of Section 3 (Steps 1-6) on
-// top of the transfers, and the fluid lattice's Q1 lumped volume.
+// top of the transfers (3D and planar grid couplings), and the fluid
+// lattice's Q1 lumped volume.
 //
 // The driver runs the transfers, the Step-2 update and the Step-6 residual
 // on the device; the solid and fluid solves are the caller's callbacks.
@@ -18,14 +19,14 @@ constexpr int kThreads = 256;
 inline unsigned nblk(int64_t n) { return unsigned(ceil_div(n > 0 ? n : 1, kThreads)); }
 
 // X[i][e] = X_ref[i][e] + u0[e][i]  (current configuration from the
-// displacement at the start of the step)
+// displacement at the start of the step; dim coordinates per vertex)
 template <typename T>
-__global__ void k_configuration(int64_t n, const double* __restrict__ Xref,
+__global__ void k_configuration(int64_t n, int dim, const double* __restrict__ Xref,
                                 const T* __restrict__ u0, double* __restrict__ X) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= 3 * n) return;
-  const int64_t i = k / 3;
-  const int e = int(k - 3 * i);
+  if (k >= dim * n) return;
+  const int64_t i = k / dim;
+  const int e = int(k - dim * i);
   X[k] = Xref[k] + double(u0[int64_t(e) * n + i]);
 }
 
@@ -85,6 +86,16 @@ __global__ void k_density(int64_t nf, int nx, int ny, const double* __restrict__
   f[j] = T(double(f[j]) / (wx[ix] * wy[iy] * wz[iz]));
 }
 
+// f[j] /= wx[ix] wy[iy] over an (n_y, n_x) planar lattice
+template <typename T>
+__global__ void k_density2(int64_t nf, int nx, const double* __restrict__ wx,
+                           const double* __restrict__ wy, T* __restrict__ f) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nf) return;
+  const int64_t ix = j % nx, iy = j / nx;
+  f[j] = T(double(f[j]) / (wx[ix] * wy[iy]));
+}
+
 __global__ void k_volume(int64_t nf, int nx, int ny, const double* __restrict__ wx,
                          const double* __restrict__ wy, const double* __restrict__ wz,
                          double* __restrict__ out) {
@@ -106,8 +117,8 @@ std::vector<double> hat_weights(const std::vector<double>& L) {
   return w;
 }
 
-// 1D hat weights of the three lattices (9 arrays, offsets as the lattice
-// coordinates) uploaded once per coupling.
+// 1D hat weights of the lattices (offsets as the lattice coordinates; the
+// planar coupling's unused axes are empty) uploaded once per coupling.
 int fluid_weights(ibvt_coupling* c, hipStream_t s) {
   if (c->fvol_ready) return IBVT_OK;
   std::vector<double> all;
@@ -130,11 +141,12 @@ template <typename T>
 int fsi_typed(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffers* buf,
               ibvt_solid_fn solid, void* sctx, ibvt_fluid_fn fluid, void* fctx, hipStream_t s,
               ibvt_fsi_report* rep) {
-  const int64_t n = c->n_vert, n3 = 3 * n;
+  const int nc = c->ncomp;  // = dim
+  const int64_t n = c->n_vert, n3 = int64_t(nc) * n;
   int st;
   // current configuration and T there
   if ((st = ensure(c, c->fsiX, size_t(n3) * sizeof(double)))) return st;
-  k_configuration<T><<<nblk(n3), kThreads, 0, s>>>(n, buf->X_ref,
+  k_configuration<T><<<nblk(n3), kThreads, 0, s>>>(n, c->dim, buf->X_ref,
                                                    static_cast<const T*>(buf->u_hat0),
                                                    c->fsiX.as<double>());
   if ((st = hip_check(hipGetLastError(), "configuration launch"))) return st;
@@ -164,7 +176,7 @@ int fsi_typed(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffe
     // Step 3: the solid solve
     if ((st = solid(sctx, buf->u_hat, buf->f_fsi, s))) return st;
     // Step 4: f_tilde = alpha B^T S^{-1} f_fsi (the literal T^T on the load)
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < nc; ++d)
       if ((st = hip_check(hipMemsetAsync(ft[d], 0, size_t(c->n_fluid[d]) * sizeof(T), s),
                           "clear f_tilde")))
         return st;
@@ -174,11 +186,16 @@ int fsi_typed(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffe
     if ((st = apply_Bt(c, c->work2.p, ft, cfg->alpha, s))) return st;
     if (cfg->force_density) {
       const double* w = c->fvol.as<double>();
-      for (int d = 0; d < 3; ++d) {
+      for (int d = 0; d < nc; ++d) {
         const int nx = c->ld.n[3 * d], ny = c->ld.n[3 * d + 1];
-        k_density<T><<<nblk(c->n_fluid[d]), kThreads, 0, s>>>(
-            c->n_fluid[d], nx, ny, w + c->ld.off[3 * d], w + c->ld.off[3 * d + 1],
-            w + c->ld.off[3 * d + 2], static_cast<T*>(ft[d]));
+        if (c->dim == 2)
+          k_density2<T><<<nblk(c->n_fluid[d]), kThreads, 0, s>>>(
+              c->n_fluid[d], nx, w + c->ld.off[3 * d], w + c->ld.off[3 * d + 1],
+              static_cast<T*>(ft[d]));
+        else
+          k_density<T><<<nblk(c->n_fluid[d]), kThreads, 0, s>>>(
+              c->n_fluid[d], nx, ny, w + c->ld.off[3 * d], w + c->ld.off[3 * d + 1],
+              w + c->ld.off[3 * d + 2], static_cast<T*>(ft[d]));
       }
       if ((st = hip_check(hipGetLastError(), "density launch"))) return st;
     }
@@ -227,11 +244,11 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
              hipStream_t stream, ibvt_fsi_report* report) {
   if (report) *report = ibvt_fsi_report{};
   if (!c || !cfg || !buf || !solid || !fluid) return set_error(IBVT_E_INVALID, "NULL argument");
-  if (c->dim != 3 || c->unstructured)
-    return set_error(IBVT_E_UNSUPPORTED, "fsi_step drives couplings with a 3D grid only");
+  if (c->unstructured)
+    return set_error(IBVT_E_UNSUPPORTED, "fsi_step drives couplings with a grid only");
   if (!buf->X_ref || !buf->u_hat0 || !buf->u_hat || !buf->w_s || !buf->f_fsi || !buf->f_prev)
     return set_error(IBVT_E_INVALID, "NULL solid buffer");
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < c->ncomp; ++d)
     if (!buf->v_f[d] || !buf->f_tilde[d]) return set_error(IBVT_E_INVALID, "NULL fluid buffer");
   if (cfg->max_iter < 1 || !std::isfinite(cfg->dt) || !std::isfinite(cfg->alpha))
     return set_error(IBVT_E_INVALID, "max_iter >= 1, finite dt and alpha required");

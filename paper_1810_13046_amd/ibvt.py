@@ -349,33 +349,36 @@ class Coupling:
                  eps_rel=1e-8, max_iter=50, mass="lumped", force_density=False, cg_rtol=1e-10,
                  cg_maxit=500, f_prev=None, stream=None, raise_not_converged=True):
         """One time step of the Picard coupling (Section 3, Steps 1-6) through
-        the C driver.  solid(u_hat, f_fsi) fills f_fsi (3, n_vert) from the
-        displacement u_hat; fluid(f_tilde, v_f) updates the 3 fluid velocity
-        arrays v_f in place from the transferred force.  Both receive this
+        the C driver.  solid(u_hat, f_fsi) fills f_fsi (nc, n_vert) from the
+        displacement u_hat; fluid(f_tilde, v_f) updates the nc fluid velocity
+        arrays v_f in place from the transferred force (nc = 3, or 2 for a
+        planar coupling, whose X_ref is (n_vert, 2)).  Both receive this
         call's tensors and must enqueue their work on the current stream.
         Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
         import torch
-        if self.dim != 3 or self.faces is None:
-            raise IbvtError(7, "fsi_step", "the Picard driver takes couplings with a 3D grid only")
+        if self.faces is None:
+            raise IbvtError(7, "fsi_step", "the Picard driver takes couplings with a grid only")
         dt_ = self.dtype
         dev = X_ref.device
-        n = self.n_vert
-        out = dict(u_hat=torch.empty((3, n), dtype=dt_, device=dev),
-                   w_s=torch.empty((3, n), dtype=dt_, device=dev),
-                   f_fsi=torch.empty((3, n), dtype=dt_, device=dev),
+        n, nc = self.n_vert, self.nc
+        out = dict(u_hat=torch.empty((nc, n), dtype=dt_, device=dev),
+                   w_s=torch.empty((nc, n), dtype=dt_, device=dev),
+                   f_fsi=torch.empty((nc, n), dtype=dt_, device=dev),
                    f_tilde=[torch.empty_like(v) for v in v_f])
-        fp = torch.zeros((3, n), dtype=dt_, device=dev) if f_prev is None else f_prev
+        fp = torch.zeros((nc, n), dtype=dt_, device=dev) if f_prev is None else f_prev
         cfg = _FsiConfig(float(dt), float(alpha), float(eps_abs), float(eps_rel), int(max_iter),
                          LUMPED if mass == "lumped" else CONSISTENT, int(bool(force_density)),
                          int(cg_maxit), float(cg_rtol))
         buf = _FsiBuffers()
-        buf.X_ref = _dev(X_ref, torch.float64, 3 * n, "X_ref")
-        buf.u_hat0 = _dev(u_hat0, dt_, 3 * n, "u_hat0")
+        buf.X_ref = _dev(X_ref, torch.float64, self.dim * n, "X_ref")
+        buf.u_hat0 = _dev(u_hat0, dt_, nc * n, "u_hat0")
         buf.u_hat = out["u_hat"].data_ptr()
         buf.w_s = out["w_s"].data_ptr()
         buf.f_fsi = out["f_fsi"].data_ptr()
-        buf.f_prev = _dev(fp, dt_, 3 * n, "f_prev")
-        for d in range(3):
+        buf.f_prev = _dev(fp, dt_, nc * n, "f_prev")
+        if len(v_f) != nc:
+            raise IbvtError(INVALID, "fsi_step", f"v_f needs {nc} fluid arrays")
+        for d in range(nc):
             buf.v_f[d] = _dev(v_f[d], dt_, self.n_fluid[d], f"v_f[{d}]")
             buf.f_tilde[d] = out["f_tilde"][d].data_ptr()
         errors = []
