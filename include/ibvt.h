@@ -58,7 +58,8 @@ extern "C" {
                                    lattice's node hull */
 #define IBVT_E_HIP 3            /* a HIP runtime call failed */
 #define IBVT_E_NOMEM 4          /* device allocation failed */
-#define IBVT_E_NOT_CONVERGED 5  /* CG reached maxit; results are written */
+#define IBVT_E_NOT_CONVERGED 5  /* a solve reached its iteration limit;
+                                   results are written */
 #define IBVT_E_CAPACITY 6       /* an internal fixed capacity was exceeded
                                    (clipped-piece vertices, vertex valence,
                                    index range); the coupling is unusable */
@@ -68,12 +69,14 @@ extern "C" {
 #define IBVT_FP64 0             /* everything in double */
 #define IBVT_FP32_MIXED 1       /* double coordinates, plane distances and
                                    cut points; float quadrature, float B
-                                   values and float transfers; CG with float
-                                   inner iterations and a double residual */
+                                   values and float transfers; mass solves
+                                   with float inner iterations and a double
+                                   residual */
 
 /* Mass matrix used for S. */
 #define IBVT_LUMPED 0           /* S = diag(m), m_i = ∫ λ_i = Σ_{T∋i} |T|/4 */
-#define IBVT_CONSISTENT 1       /* S = M, M_il = ∫ λ_i λ_l, Jacobi-PCG solve */
+#define IBVT_CONSISTENT 1       /* S = M, M_il = ∫ λ_i λ_l, solved by a
+                                   Jacobi-scaled Chebyshev iteration */
 
 /* assemble_coupling flags. */
 #define IBVT_BUILD_CONSISTENT_M 1u  /* also build the consistent mass matrix */
@@ -254,7 +257,10 @@ int reassemble_coupling(ibvt_coupling* c, const double* X, hipStream_t stream);
  *   u_s: (3, n_vert) output, overwritten.
  *   mass: IBVT_LUMPED or IBVT_CONSISTENT (needs IBVT_BUILD_CONSISTENT_M).
  *   cg_rtol, cg_maxit: stop when ||b - M x|| <= cg_rtol ||b|| per component
- *   (ignored for IBVT_LUMPED).  info: nullable.
+ *   (checked in double after each cycle of Chebyshev iterations on D^-1 M,
+ *   D = diag M, whose spectrum lies in [1/2, 5/2] for P1 tetrahedra and
+ *   [1/2, 2] for triangles), at most cg_maxit iterations (ignored for
+ *   IBVT_LUMPED).  info: nullable.
  *   Errors: IBVT_E_INVALID, IBVT_E_NOT_CONVERGED (u_s holds the last
  *   iterate), IBVT_E_HIP.
  */
@@ -408,7 +414,7 @@ typedef struct {
   int32_t max_iter;       /* Picard iterations, >= 1 */
   int32_t mass;           /* IBVT_LUMPED or IBVT_CONSISTENT for T */
   int32_t force_density;  /* divide f_tilde by the fluid nodes' lumped volume */
-  int32_t cg_maxit;       /* consistent-mass CG */
+  int32_t cg_maxit;       /* consistent-mass solve: iteration limit */
   double cg_rtol;
 } ibvt_fsi_config;
 

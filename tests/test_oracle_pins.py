@@ -541,3 +541,29 @@ def test_fsi_picard_reaches_the_fixed_point(oracle_mod, mode):
         rhs = -k_s * (u0[d] - u_rest[d] + dt * Td @ v_base[d])
         f_star = np.linalg.solve(A, rhs)
         assert np.max(np.abs(r["f_fsi"][d] - f_star)) <= 1e-11 * max(1.0, np.max(np.abs(f_star)))
+
+
+# ---------------------------------------------------------------------------
+# Spectrum of the Jacobi-scaled P1 mass (the bounds the consistent solve
+# relies on)
+# ---------------------------------------------------------------------------
+
+def test_jacobi_scaled_mass_spectrum_bounds(oracle_mod):
+    """The eigenvalues of D⁻¹M (D = diag M) for the consistent P1 mass lie in
+    [1/2, 5/2] whatever the element shapes: each element's D_e⁻¹M_e =
+    (I + 11ᵀ)/2 has eigenvalues 1/2 (three times) and 5/2, and the Rayleigh
+    quotient of the assembled pair is a ratio of sums of the elements'
+    quotients.  Checked on a jittered mesh with a graded and a sliver
+    element, and the single-element extremes attained exactly."""
+    _, X, tets, _ = _tiny(oracle_mod)
+    rng = np.random.default_rng(8)
+    X = X * np.array([1.0, 3.0, 0.2]) + 1e-3 * rng.standard_normal(X.shape)
+    M = oracle_mod.consistent_mass(X, tets).toarray()
+    d = np.diag(M)
+    lam = np.linalg.eigvalsh(M / np.sqrt(np.outer(d, d)))
+    assert lam.min() >= 0.5 - 1e-12 and lam.max() <= 2.5 + 1e-12
+    T1 = np.array([[0, 0, 0], [1, 0, 0], [0.3, 2, 0], [0.1, 0.2, 1e-3]], dtype=np.float64)
+    M1 = oracle_mod.consistent_mass(T1, np.array([[0, 1, 2, 3]])).toarray()
+    d1 = np.diag(M1)
+    lam1 = np.linalg.eigvalsh(M1 / np.sqrt(np.outer(d1, d1)))
+    np.testing.assert_allclose(lam1, [0.5, 0.5, 0.5, 2.5], atol=1e-12)

@@ -427,3 +427,22 @@ def test_fsi_picard_reaches_the_fixed_point(pl, mode, density):
         rhs = -k_s * (u0[d] - u_rest[d] + dt * Td @ v_base[d])
         f_star = np.linalg.solve(A, rhs)
         assert np.max(np.abs(r["f_fsi"][d] - f_star)) <= 1e-11 * max(1.0, np.max(np.abs(f_star)))
+
+
+def test_jacobi_scaled_mass_spectrum_bounds(pl):
+    """The eigenvalues of D⁻¹M for the consistent planar P1 mass lie in
+    [1/2, 2]: each triangle's D_e⁻¹M_e = (I + 11ᵀ)/2 has eigenvalues 1/2
+    (twice) and 2, and the assembled Rayleigh quotient is a ratio of sums of
+    the elements' quotients.  A jittered graded mesh, and one triangle's
+    extremes exactly."""
+    _, X, tris = _small_case()
+    X = X * np.array([1.0, 4.0]) + 1e-3 * np.random.default_rng(9).standard_normal(X.shape)
+    M = pl.consistent_mass(X, tris).toarray()
+    d = np.diag(M)
+    lam = np.linalg.eigvalsh(M / np.sqrt(np.outer(d, d)))
+    assert lam.min() >= 0.5 - 1e-12 and lam.max() <= 2.0 + 1e-12
+    T1 = np.array([[0, 0], [1, 0], [0.3, 1e-3]], dtype=np.float64)
+    M1 = pl.consistent_mass(T1, np.array([[0, 1, 2]])).toarray()
+    d1 = np.diag(M1)
+    lam1 = np.linalg.eigvalsh(M1 / np.sqrt(np.outer(d1, d1)))
+    np.testing.assert_allclose(lam1, [0.5, 0.5, 2.0], atol=1e-12)
