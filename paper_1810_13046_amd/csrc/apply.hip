@@ -588,12 +588,16 @@ int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxi
     k_convert<float, double><<<nblk(nn), kThreads, 0, s>>>(nn, xf, w.x64);
     float* e = static_cast<float*>(w.vec) + 4 * 3 * n;   // vectors 4 and 5 of the workspace
     float* rf = e + 3 * n;
-    const int per_cycle = cheb_iterations(kb, 0.1 * std::max(1e-5, rtol));
     for (;;) {
       if ((st = true_residual<float>(c, b, w.x64, w, s, rel))) return st;
       if ((conv = converged()) || done >= maxit) break;
       k_convert<double, float><<<nblk(nn), kThreads, 0, s>>>(nn, w.res64, rf);
-      const int it = std::min(per_cycle, maxit - done);
+      // the reduction still needed (rtol over the largest relative
+      // residual), at most what float iterations can give
+      double worst = 0.0;
+      for (int d = 0; d < c->ncomp; ++d) worst = std::max(worst, rel[d]);
+      const double want = std::min(0.1, std::max(1e-5, rtol / worst));
+      const int it = std::min(cheb_iterations(kb, 0.1 * want), maxit - done);
       if ((st = cheb_cycle<float, float>(c, c->Mval32.as<float>(), rf, e, true, it, w, s)))
         return st;
       k_add_correction<<<nblk(nn), kThreads, 0, s>>>(nn, e, w.x64);
