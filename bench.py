@@ -9,7 +9,7 @@ and synthetic (see workloads/gen.py), resident in HBM before timing.
 
 One step = the whole hot path on that input:
   reassemble B^d (all three velocity lattices) for the current positions,
-  velocity transfer with the consistent mass (CG to 1e-10),
+  velocity transfer with the consistent mass (solved to 1e-10),
   force transfer,
   reverse mode of both transfers (fluid cotangents and the shape gradient).
 The headline `value` is solid tets per second of that step in the
@@ -107,7 +107,7 @@ def make_inputs(cfg, dev):
 class Step:
     """Buffers and one full pass of the hot path for one precision.  With
     dual=True the multipliers are the dual basis (S = lumped mass), so the
-    velocity transfer and its adjoint need no CG."""
+    velocity transfer and its adjoint need no mass solve."""
 
     def __init__(self, W, X, T, u64, f_s, u_t, precision, dual=False):
         import torch
@@ -532,7 +532,7 @@ def main():
         ms_d, _ = time_steps(sd, args.steps, args.warmup)
         dual = dict(ms_per_step=ms_d, value=n_tet / (ms_d * 1e-3),
                     note="dual multipliers (S = lumped mass): reassembly, velocity, force, "
-                         "both adjoints; no CG")
+                         "both adjoints; no mass solve")
         log(f"[bench] dual {ms_d:.2f} ms/step")
         del sd
 
@@ -571,12 +571,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 quadrature/applies, f64 clipping and CG residual",
+        "dtype": "f32 quadrature/applies, f64 clipping and mass-solve residual",
         "data": "synthetic (seeded meshes and Fourier velocity fields)",
         "config": {
             "workload": W.name, "n_tet": int(n_tet), "n_vert": int(W.X.shape[0]),
             "grid_cells": list(W.n_cells), "y_stretch_ratio": 4.0, "bodies": len(W.bodies),
-            "mass": "consistent", "cg_rtol": 1e-10, "parallelism": "single GPU",
+            "mass": "consistent", "solve_rtol": 1e-10, "parallelism": "single GPU",
         },
         "assembly": {"pairs": info["pairs"], "pieces": info["pieces"], "subtets": info["subtets"],
                      "nnz": info["nnz"], "touched": info["touched"],

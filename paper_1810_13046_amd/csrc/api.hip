@@ -287,7 +287,7 @@ const char* ibvt_status_string(int status) {
     case IBVT_E_OUT_OF_GRID: return "solid outside the fluid lattice";
     case IBVT_E_HIP: return "HIP runtime error";
     case IBVT_E_NOMEM: return "out of device memory";
-    case IBVT_E_NOT_CONVERGED: return "CG did not converge";
+    case IBVT_E_NOT_CONVERGED: return "iteration limit reached before convergence";
     case IBVT_E_CAPACITY: return "internal capacity exceeded";
     case IBVT_E_UNSUPPORTED: return "unsupported combination";
     default: return "unknown status";
@@ -468,7 +468,7 @@ int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int
   if (info) std::memset(info, 0, sizeof(*info));
   if (mass == IBVT_LUMPED) return apply_B(c, u_f, u_s, true, stream);
   if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
-  if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad CG rtol/maxit");
+  if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad mass-solve rtol/maxit");
   // rhs = B u_f into the scratch, start from the lumped solution in u_s
   const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
   int st = ensure(c, c->work2, size_t(3 * c->n_vert) * tsize);
@@ -521,7 +521,7 @@ int check_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f
       if (!g_uf[d]) return set_error(IBVT_E_INVALID, "NULL g_uf component");
   if (mass == IBVT_CONSISTENT) {
     if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
-    if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad CG rtol/maxit");
+    if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad mass-solve rtol/maxit");
   }
   return IBVT_OK;
 }

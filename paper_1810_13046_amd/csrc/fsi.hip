@@ -259,7 +259,7 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
   if (!c->dual && cfg->mass == IBVT_CONSISTENT) {
     if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
     if (!(cfg->cg_rtol > 0.0) || cfg->cg_maxit < 1)
-      return set_error(IBVT_E_INVALID, "bad CG rtol/maxit");
+      return set_error(IBVT_E_INVALID, "bad mass-solve rtol/maxit");
   }
   if (c->precision == IBVT_FP32_MIXED)
     return fsi_typed<float>(c, cfg, buf, solid, solid_ctx, fluid, fluid_ctx, stream, report);

@@ -136,8 +136,8 @@ struct ibvt_coupling {
   ibvt::DevBuf flags_dev;    // unsigned
   ibvt::DevBuf counters;     // unsigned long long kCntSlots
   ibvt::DevBuf scan_tmp;     // scan scratch
-  ibvt::DevBuf work;         // transfer scratch (CG vectors etc.)
-  ibvt::DevBuf work2;        // shape-gradient per-pair scratch / CG right-hand side
+  ibvt::DevBuf work;         // transfer scratch (mass-solve vectors etc.)
+  ibvt::DevBuf work2;        // shape-gradient per-pair scratch / mass-solve right-hand side
   ibvt::DevBuf zbuf;         // solid-sized scratch of the reverse-mode calls
   ibvt::DevBuf host_pinned;  // small pinned host buffer for read-backs
   ibvt::AsmStats stats;

@@ -250,8 +250,8 @@ def test_edge_cases(dev):
         Coupling(faces, to_dev(X, torch.float64, dev),
                  to_dev(np.array([[0, 1, 2, 9]], dtype=np.int32), torch.int32, dev))
     assert e.value.name == "IBVT_E_INVALID"
-    # CG that cannot converge in one iteration
-    say("[gpu] edge: CG maxit")
+    # a mass solve that cannot converge in one iteration
+    say("[gpu] edge: mass solve maxit")
     W, _ = ref("beam144_grid32")
     c = make("beam144_grid32", "fp64", dev)
     ud = [to_dev(u, torch.float64, dev) for u in fluid_fields(W)]
