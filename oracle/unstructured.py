@@ -19,7 +19,8 @@ component uses the same nodes and the same B):
 * reverse mode: z = S^{-1} g, B^T z, and the shape derivative with respect
   to the solid vertices (the transport form of the structured case with the
   fluid P1 hats in place of the Q1 hats; ∫ λ_a λ_i per piece is the second
-  integral it needs).
+  integral it needs);
+* the Picard step of Section 3 over this coupling (fsi_step).
 """
 from __future__ import annotations
 
@@ -255,6 +256,48 @@ def velocity_loss(Xf, tets_f, X, tets, u_f, u_target, mass="lumped", dual=False)
     cpl = assemble(Xf, tets_f, X, tets, dual=dual)
     r = transfer_velocity(cpl, u_f, mass) - u_target
     return 0.5 * float(np.sum(r * r))
+
+
+def fsi_step(Xf, tets_f, X_ref, tets, u_hat0, v_f, solid, fluid, dt, alpha=1.0, eps_abs=0.0,
+             eps_rel=1e-8, max_iter=50, mass="lumped", force_density=False, dual=False,
+             f_prev=None):
+    """One time step of the Picard iteration of Section 3 with the P1 fluid
+    mesh as the background, in the steps' order: T = S^{-1} B assembled at
+    X_ref + u_hat0 and held for the step; 1. w_s = T v_f; 2. u_hat = u_hat0
+    + dt w_s; 3. f_fsi = solid(u_hat); 4. f_tilde = alpha B^T S^{-1} f_fsi
+    (divided by the fluid nodes' lumped volume ∫ μ_j with force_density);
+    5. v_f = fluid(f_tilde); 6. stop when ||f_l − f_{l−1}||_inf < eps_abs or
+    that over ||f_1||_inf < eps_rel; f_0 = f_prev (zeros by default).
+    v_f: three nodal arrays of the fluid mesh."""
+    X = np.asarray(X_ref, dtype=np.float64) + np.asarray(u_hat0, dtype=np.float64).T
+    cpl = assemble(Xf, tets_f, X, tets, dual=dual)
+    S = _mass_kind(cpl, mass)
+    u_hat0 = np.asarray(u_hat0, dtype=np.float64)
+    v = [np.asarray(a, dtype=np.float64).ravel().copy() for a in v_f]
+    f_old = np.zeros_like(u_hat0) if f_prev is None else np.asarray(f_prev, dtype=np.float64)
+    vol = lumped_mass(Xf, tets_f, Xf.shape[0]) if force_density else None
+    f1 = None
+    out = {}
+    for it in range(1, max_iter + 1):
+        w_s = mass_solve(X, tets, np.stack([cpl.B @ v[d] for d in range(3)]), S)
+        u_hat = u_hat0 + dt * w_s
+        f = np.asarray(solid(u_hat), dtype=np.float64)
+        g = mass_solve(X, tets, f, S)
+        f_tilde = [alpha * (cpl.B.T @ g[d]) for d in range(3)]
+        if force_density:
+            f_tilde = [f_tilde[d] / vol for d in range(3)]
+        v = [np.asarray(a, dtype=np.float64).ravel() for a in fluid(f_tilde)]
+        res = float(np.max(np.abs(f - f_old)))
+        if it == 1:
+            f1 = float(np.max(np.abs(f)))
+        rel = res / f1 if f1 > 0 else (np.inf if res > 0 else 0.0)
+        f_old = f
+        out = dict(iterations=it, w_s=w_s, u_hat=u_hat, f_fsi=f, f_tilde=f_tilde, v_f=v,
+                   res_abs=res, res_rel=rel, f1_norm=f1, converged=False, B=cpl.B)
+        if (eps_abs > 0 and res < eps_abs) or (eps_rel > 0 and rel < eps_rel):
+            out["converged"] = True
+            break
+    return out
 
 
 def clip_volume(S, F) -> float:

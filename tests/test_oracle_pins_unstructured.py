@@ -218,3 +218,49 @@ def test_shape_derivative_of_rigid_translation_is_zero_for_affine_fields(un, w1)
     for k in range(3):
         want = co[1 + k] * float(sum(f_s[d] @ m for d in range(3)))
         assert abs(gX[:, k].sum() - want) <= 1e-10 * (1 + abs(want))
+
+
+@pytest.mark.parametrize("mode,density", [("lumped", False), ("consistent", False),
+                                          ("dual", False), ("lumped", True)])
+def test_fsi_picard_reaches_the_fixed_point(un, w1, mode, density):
+    """With a linear spring for the solid and a fluid whose nodal velocity
+    responds linearly to the force, the fixed point of Steps 1-5 solves
+    (I + k dt beta alpha T D⁻¹ Tᵀ) f = −k (û0 − û_rest + dt T v_base) per
+    component, T = S⁻¹B and D the fluid nodes' lumped volumes ∫ μ_j (the
+    identity without the density option): the Picard loop must land on the
+    direct solution of that dense system."""
+    from oracle import consistent_mass, lumped_mass
+    W, _ = w1
+    n = W.X.shape[0]
+    nf = W.Xf.shape[0]
+    dual = mode == "dual"
+    mass = "consistent" if mode == "consistent" else "lumped"
+    rng = np.random.default_rng(21)
+    u_rest = 1e-3 * rng.standard_normal((3, n))
+    v_base = [rng.standard_normal(nf) for _ in range(3)]
+    k_s, beta = 10.0, 0.5
+    if density:
+        beta *= lumped_mass(W.Xf, W.tets_f).min()
+
+    def solid(u_hat):
+        return -k_s * (u_hat - u_rest)
+
+    def fluid(f_tilde):
+        return [v_base[d] + beta * f_tilde[d] for d in range(3)]
+
+    u0 = 1e-3 * np.random.default_rng(5).standard_normal((3, n))
+    dt, alpha = 0.05, 0.8
+    r = un.fsi_step(W.Xf, W.tets_f, W.X, W.tets, u0, [np.zeros(nf)] * 3, solid, fluid, dt, alpha,
+                    eps_abs=1e-14, eps_rel=0.0, max_iter=200, mass=mass, force_density=density,
+                    dual=dual)
+    assert r["converged"]
+    c = un.assemble(W.Xf, W.tets_f, W.X + u0.T, W.tets, dual=dual)
+    Sm = (np.diag(lumped_mass(c.X, W.tets)) if mass == "lumped"
+          else consistent_mass(c.X, W.tets).toarray())
+    T = np.linalg.solve(Sm, c.B.toarray())
+    Dinv = 1.0 / lumped_mass(W.Xf, W.tets_f) if density else np.ones(nf)
+    A = np.eye(n) + k_s * dt * beta * alpha * (T * Dinv[None, :]) @ T.T
+    for d in range(3):
+        rhs = -k_s * (u0[d] - u_rest[d] + dt * T @ v_base[d])
+        f_star = np.linalg.solve(A, rhs)
+        assert np.max(np.abs(r["f_fsi"][d] - f_star)) <= 1e-11 * max(1.0, np.max(np.abs(f_star)))
