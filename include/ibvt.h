@@ -235,7 +235,8 @@ int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int p
  *   and the shape derivative g_X, the transport form of the grid case with
  *   the fluid P1 hats μ_j fixed in space:
  *     ∂B_ij/∂X_{a,k} = Σ_{T∋a} ∫_T (λ_a λ_i ∂_k μ_j + ∂_k λ_a λ_i μ_j).
- *   fsi_step returns IBVT_E_UNSUPPORTED.
+ *   fsi_step drives it with v_f and f_tilde nodal arrays of the fluid mesh
+ *   (its force-density option is refused: IBVT_E_UNSUPPORTED).
  *   Errors: IBVT_E_INVALID, IBVT_E_CAPACITY, IBVT_E_NOMEM, IBVT_E_HIP.
  */
 int assemble_coupling_unstructured(const ibvt_mesh* fluid, const ibvt_mesh* solid, int precision,
@@ -398,7 +399,8 @@ int ibvt_lattice_coords_2d(const ibvt_grid2d* grid, int comp, int axis, double* 
  * out; f_prev in (f_fsi,0) and overwritten (workspace).  A planar coupling
  * reads v_f[0..1] and f_tilde[0..1] only.
  * Errors: IBVT_E_INVALID (arguments, consistent mass not built, dual basis
- * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (unstructured coupling),
+ * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (force density with an
+ * unstructured coupling),
  * IBVT_E_NOT_CONVERGED (max_iter reached; results of the last iteration are
  * written), or the status of a failed call or callback.
  */

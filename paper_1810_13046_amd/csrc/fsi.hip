@@ -1,6 +1,7 @@
 // Fixed-point (Picard) fluid-structure coupling of Section 3 (Steps 1-6) on
-// top of the transfers (3D and planar grid couplings), and the fluid
-// lattice's Q1 lumped volume.
+// top of the transfers (3D and planar grid couplings, and the unstructured
+// coupling without the force-density option), and the fluid lattice's Q1
+// lumped volume.
 //
 // The driver runs the transfers, the Step-2 update and the Step-6 residual
 // on the device; the solid and fluid solves are the caller's callbacks.
@@ -244,8 +245,8 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
              hipStream_t stream, ibvt_fsi_report* report) {
   if (report) *report = ibvt_fsi_report{};
   if (!c || !cfg || !buf || !solid || !fluid) return set_error(IBVT_E_INVALID, "NULL argument");
-  if (c->unstructured)
-    return set_error(IBVT_E_UNSUPPORTED, "fsi_step drives couplings with a grid only");
+  if (c->unstructured && cfg->force_density)
+    return set_error(IBVT_E_UNSUPPORTED, "the force density needs a fluid lattice");
   if (!buf->X_ref || !buf->u_hat0 || !buf->u_hat || !buf->w_s || !buf->f_fsi || !buf->f_prev)
     return set_error(IBVT_E_INVALID, "NULL solid buffer");
   for (int d = 0; d < c->ncomp; ++d)

@@ -352,12 +352,12 @@ class Coupling:
         the C driver.  solid(u_hat, f_fsi) fills f_fsi (nc, n_vert) from the
         displacement u_hat; fluid(f_tilde, v_f) updates the nc fluid velocity
         arrays v_f in place from the transferred force (nc = 3, or 2 for a
-        planar coupling, whose X_ref is (n_vert, 2)).  Both receive this
+        planar coupling, whose X_ref is (n_vert, 2); with an unstructured
+        coupling the v_f are nodal arrays of the fluid mesh and
+        force_density is refused).  Both receive this
         call's tensors and must enqueue their work on the current stream.
         Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
         import torch
-        if self.faces is None:
-            raise IbvtError(7, "fsi_step", "the Picard driver takes couplings with a grid only")
         dt_ = self.dtype
         dev = X_ref.device
         n, nc = self.n_vert, self.nc
