@@ -236,7 +236,8 @@ int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int p
  *   the fluid P1 hats μ_j fixed in space:
  *     ∂B_ij/∂X_{a,k} = Σ_{T∋a} ∫_T (λ_a λ_i ∂_k μ_j + ∂_k λ_a λ_i μ_j).
  *   fsi_step drives it with v_f and f_tilde nodal arrays of the fluid mesh
- *   (its force-density option is refused: IBVT_E_UNSUPPORTED).
+ *   (the force-density option divides by the fluid nodes' lumped volumes
+ *   ∫ μ_j = Σ_{T∋j} |T|/4, built on first use).
  *   Errors: IBVT_E_INVALID, IBVT_E_CAPACITY, IBVT_E_NOMEM, IBVT_E_HIP.
  */
 int assemble_coupling_unstructured(const ibvt_mesh* fluid, const ibvt_mesh* solid, int precision,
@@ -378,8 +379,9 @@ int ibvt_lattice_coords_2d(const ibvt_grid2d* grid, int comp, int axis, double* 
  *   Step 3  f_fsi = solid(u_hat)                 (caller's solid solver)
  *   Step 4  f_tilde = alpha T^T f_fsi            (the literal transpose
  *           B^T S^{-1} on the load f_fsi; with cfg->force_density != 0 the
- *           result is divided node by node by the fluid lattice's Q1 lumped
- *           volume, giving a force density for a finite-difference solver)
+ *           result is divided node by node by the fluid nodes' lumped
+ *           volume, Q1 over a lattice's hull or P1 on an unstructured
+ *           background, giving a force density for the fluid solver)
  *   Step 5  v_f = fluid(f_tilde)                 (caller's fluid solver)
  *   Step 6  stop when ||f_fsi,l − f_fsi,l−1||_inf < eps_abs (eq. AC) or
  *           that norm / ||f_fsi,1||_inf < eps_rel (eq. RC); f_fsi,0 is the
@@ -399,8 +401,7 @@ int ibvt_lattice_coords_2d(const ibvt_grid2d* grid, int comp, int axis, double* 
  * out; f_prev in (f_fsi,0) and overwritten (workspace).  A planar coupling
  * reads v_f[0..1] and f_tilde[0..1] only.
  * Errors: IBVT_E_INVALID (arguments, consistent mass not built, dual basis
- * with IBVT_CONSISTENT), IBVT_E_UNSUPPORTED (force density with an
- * unstructured coupling),
+ * with IBVT_CONSISTENT),
  * IBVT_E_NOT_CONVERGED (max_iter reached; results of the last iteration are
  * written), or the status of a failed call or callback.
  */

@@ -1,11 +1,12 @@
 // Fixed-point (Picard) fluid-structure coupling of Section 3 (Steps 1-6) on
 // top of the transfers (3D and planar grid couplings, and the unstructured
-// coupling without the force-density option), and the fluid lattice's Q1
-// lumped volume.
+// coupling), and the fluid lattice's Q1 lumped volume.
 //
 // The driver runs the transfers, the Step-2 update and the Step-6 residual
 // on the device; the solid and fluid solves are the caller's callbacks.
 // Each iteration reads back two numbers (the infinity norms of Step 6).
+#include <hipcub/hipcub.hpp>
+
 #include <cmath>
 #include <vector>
 
@@ -106,6 +107,90 @@ __global__ void k_volume(int64_t nf, int nx, int ny, const double* __restrict__ 
   out[j] = wx[ix] * wy[r % ny] * wz[r / ny];
 }
 
+// f[j] /= vol[j] for nodal fluid values (unstructured background)
+template <typename T>
+__global__ void k_density_nodal(int64_t nf, const double* __restrict__ vol, T* __restrict__ f) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < nf) f[j] = T(double(f[j]) / vol[j]);
+}
+
+// One item per (fluid tet, corner), in tet-major order: key = the corner's
+// vertex, value = |T| / 4.
+__global__ void k_fvol_items(int64_t n_ft, const int32_t* __restrict__ tets,
+                             const double* __restrict__ X, int32_t* __restrict__ keys,
+                             double* __restrict__ vals) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= 4 * n_ft) return;
+  const int64_t t = k >> 2;
+  const int32_t* v = tets + 4 * t;
+  const double* a = X + 3 * int64_t(v[0]);
+  double e[3][3];
+  for (int m = 0; m < 3; ++m) {
+    const double* b = X + 3 * int64_t(v[m + 1]);
+    for (int c = 0; c < 3; ++c) e[m][c] = b[c] - a[c];
+  }
+  const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                     e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                     e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+  keys[k] = v[k & 3];
+  vals[k] = fabs(det) / 24.0;
+}
+
+// vol[j] = Σ of vertex j's items, in tet order (the items were sorted by a
+// stable sort of the tet-major order): one thread per vertex, its run found
+// by binary search.
+__global__ void k_fvol_sum(int64_t n_v, int64_t n_items, const int32_t* __restrict__ skeys,
+                           const double* __restrict__ svals, double* __restrict__ vol) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n_v) return;
+  int64_t lo = 0, hi = n_items;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (skeys[mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  double sum = 0.0;
+  for (int64_t k = lo; k < n_items && skeys[k] == j; ++k) sum += svals[k];
+  vol[j] = sum;
+}
+
+// Lumped volume ∫ μ_j = Σ_{T∋j} |T| / 4 of every fluid node of an
+// unstructured background, into c->fvol (deterministic: no value atomics).
+int fluid_nodal_volumes(ibvt_coupling* c, hipStream_t s) {
+  const int64_t n_ft = c->n_ftet, n_fv = c->n_fvert, n_items = 4 * n_ft;
+  int st;
+  if ((st = ensure(c, c->fvol, size_t(n_fv + 1) * sizeof(double)))) return st;
+  int end_bit = 1;
+  while ((int64_t(1) << end_bit) < n_fv + 1) ++end_bit;
+  size_t temp_bytes = 0;
+  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(
+                          nullptr, temp_bytes, static_cast<const int32_t*>(nullptr),
+                          static_cast<int32_t*>(nullptr), static_cast<const double*>(nullptr),
+                          static_cast<double*>(nullptr), int(n_items), 0, end_bit, s),
+                      "sort size")))
+    return st;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t n4 = al(size_t(n_items) * sizeof(int32_t)), n8 = al(size_t(n_items) * sizeof(double));
+  if ((st = ensure(c, c->tbuf, 2 * n4 + 2 * n8 + temp_bytes + 256))) return st;
+  char* base = c->tbuf.as<char>();
+  int32_t* keys = reinterpret_cast<int32_t*>(base);
+  int32_t* skeys = reinterpret_cast<int32_t*>(base + n4);
+  double* vals = reinterpret_cast<double*>(base + 2 * n4);
+  double* svals = reinterpret_cast<double*>(base + 2 * n4 + n8);
+  void* temp = base + 2 * n4 + 2 * n8;
+  if (n_items > 0) {
+    k_fvol_items<<<nblk(n_items), kThreads, 0, s>>>(n_ft, c->ftets.as<int32_t>(),
+                                                    c->fX.as<double>(), keys, vals);
+    if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, vals,
+                                                           svals, int(n_items), 0, end_bit, s),
+                        "radix sort")))
+      return st;
+  }
+  k_fvol_sum<<<nblk(n_fv), kThreads, 0, s>>>(n_fv, n_items, skeys, svals, c->fvol.as<double>());
+  if ((st = hip_check(hipGetLastError(), "fluid volume launch"))) return st;
+  return hip_check(hipStreamSynchronize(s), "sync");
+}
+
 // ∫ of the 1D hats of a lattice over its hull [L_0, L_{n-1}]
 std::vector<double> hat_weights(const std::vector<double>& L) {
   const size_t n = L.size();
@@ -122,6 +207,12 @@ std::vector<double> hat_weights(const std::vector<double>& L) {
 // planar coupling's unused axes are empty) uploaded once per coupling.
 int fluid_weights(ibvt_coupling* c, hipStream_t s) {
   if (c->fvol_ready) return IBVT_OK;
+  if (c->unstructured) {
+    const int st = fluid_nodal_volumes(c, s);
+    if (st) return st;
+    c->fvol_ready = true;
+    return IBVT_OK;
+  }
   std::vector<double> all;
   for (int k = 0; k < 9; ++k) {
     const std::vector<double> w = hat_weights(c->lat_host[k]);
@@ -185,7 +276,12 @@ int fsi_typed(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffe
     else st = mass_solve(c, buf->f_fsi, c->work2.p, cfg->cg_rtol, cfg->cg_maxit, s, nullptr, false);
     if (st) return st;
     if ((st = apply_Bt(c, c->work2.p, ft, cfg->alpha, s))) return st;
-    if (cfg->force_density) {
+    if (cfg->force_density && c->unstructured) {
+      for (int d = 0; d < nc; ++d)
+        k_density_nodal<T><<<nblk(c->n_fluid[d]), kThreads, 0, s>>>(
+            c->n_fluid[d], c->fvol.as<double>(), static_cast<T*>(ft[d]));
+      if ((st = hip_check(hipGetLastError(), "density launch"))) return st;
+    } else if (cfg->force_density) {
       const double* w = c->fvol.as<double>();
       for (int d = 0; d < nc; ++d) {
         const int nx = c->ld.n[3 * d], ny = c->ld.n[3 * d + 1];
@@ -245,8 +341,6 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
              hipStream_t stream, ibvt_fsi_report* report) {
   if (report) *report = ibvt_fsi_report{};
   if (!c || !cfg || !buf || !solid || !fluid) return set_error(IBVT_E_INVALID, "NULL argument");
-  if (c->unstructured && cfg->force_density)
-    return set_error(IBVT_E_UNSUPPORTED, "the force density needs a fluid lattice");
   if (!buf->X_ref || !buf->u_hat0 || !buf->u_hat || !buf->w_s || !buf->f_fsi || !buf->f_prev)
     return set_error(IBVT_E_INVALID, "NULL solid buffer");
   for (int d = 0; d < c->ncomp; ++d)

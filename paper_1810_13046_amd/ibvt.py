@@ -353,8 +353,8 @@ class Coupling:
         displacement u_hat; fluid(f_tilde, v_f) updates the nc fluid velocity
         arrays v_f in place from the transferred force (nc = 3, or 2 for a
         planar coupling, whose X_ref is (n_vert, 2); with an unstructured
-        coupling the v_f are nodal arrays of the fluid mesh and
-        force_density is refused).  Both receive this
+        coupling the v_f are nodal arrays of the fluid mesh and the force
+        density divides by the nodes' lumped volumes ∫ μ_j).  Both receive this
         call's tensors and must enqueue their work on the current stream.
         Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
         import torch

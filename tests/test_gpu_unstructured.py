@@ -287,20 +287,21 @@ def test_unstructured_edge_cases(dev, un):
         Coupling(None, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
                  fluid_mesh=(to_dev(Xn, torch.float64, dev), Tf))
     assert e.value.name == "IBVT_E_INVALID"
-    say("[gpu] unstructured edge: fsi_step with the force density refused")
+    say("[gpu] unstructured edge: fsi_step with two fluid arrays refused")
     c = make(W, "fp64", dev)
-    v = [torch.zeros(c.n_fluid[0], dtype=torch.float64, device=dev) for _ in range(3)]
+    v = [torch.zeros(c.n_fluid[0], dtype=torch.float64, device=dev) for _ in range(2)]
     with pytest.raises(IbvtError) as e:
         c.fsi_step(to_dev(W.X, torch.float64, dev),
                    torch.zeros((3, W.X.shape[0]), dtype=torch.float64, device=dev), v,
-                   lambda u, f: f.zero_(), lambda ft, vv: None, dt=1.0, force_density=True)
-    assert e.value.name == "IBVT_E_UNSUPPORTED"
+                   lambda u, f: f.zero_(), lambda ft, vv: None, dt=1.0)
+    assert e.value.name == "IBVT_E_INVALID"
     c.free()
 
 
-@pytest.mark.parametrize("mode", ["lumped", "consistent", "dual"])
+@pytest.mark.parametrize("mode,density", [("lumped", False), ("consistent", False),
+                                          ("dual", False), ("lumped", True)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_unstructured_fsi_step_matches_oracle(dev, un, prec, mode):
+def test_unstructured_fsi_step_matches_oracle(dev, un, prec, mode, density):
     """The Picard driver (Section 3, Steps 1-6) over the unstructured
     coupling, with a linear spring for the solid and a fluid whose nodal
     velocity responds linearly to the force, against the oracle's loop: FP64
@@ -315,13 +316,17 @@ def test_unstructured_fsi_step_matches_oracle(dev, un, prec, mode):
     u_rest = 1e-3 * rng.standard_normal((3, n))
     v_base = [rng.standard_normal(nf) for _ in range(3)]
     k_s, beta = 10.0, 0.5
+    if density:  # force densities are loads over node volumes: keep the map contractive
+        from oracle import lumped_mass
+        beta *= lumped_mass(W.Xf, W.tets_f).min()
     u0 = 1e-3 * np.random.default_rng(4).standard_normal((3, n))
     dt, alpha = 0.05, 0.8
-    say(f"[gpu] unstructured fsi_step {prec} {mode}")
+    say(f"[gpu] unstructured fsi_step {prec} {mode} density={density}")
     ref_ = un.fsi_step(W.Xf, W.tets_f, W.X, W.tets, u0, [np.zeros(nf)] * 3,
                        lambda u: -k_s * (u - u_rest),
                        lambda ft: [v_base[d] + beta * ft[d] for d in range(3)],
-                       dt, alpha, eps_abs=1e-13, eps_rel=0.0, max_iter=200, mass=mass, dual=dual)
+                       dt, alpha, eps_abs=1e-13, eps_rel=0.0, max_iter=200, mass=mass,
+                       force_density=density, dual=dual)
     assert ref_["converged"]
     c = make(W, prec, dev, consistent=(mass == "consistent"), dual=dual)
     dt_ = c.dtype
@@ -339,7 +344,7 @@ def test_unstructured_fsi_step_matches_oracle(dev, un, prec, mode):
     rep, out = c.fsi_step(to_dev(W.X, torch.float64, dev), to_dev(u0, dt_, dev), vf, solid, fluid,
                           dt=dt, alpha=alpha, eps_abs=1e-13 if prec == "fp64" else 0.0,
                           eps_rel=0.0 if prec == "fp64" else 1e-4, max_iter=200, mass=mass,
-                          cg_rtol=1e-14 if prec == "fp64" else 1e-7)
+                          force_density=density, cg_rtol=1e-14 if prec == "fp64" else 1e-7)
     say(f"  iterations gpu {rep.iterations} oracle {ref_['iterations']} res {rep.res_abs:.2e}")
     assert rep.converged
     tol = 1e-10 if prec == "fp64" else 1e-4
