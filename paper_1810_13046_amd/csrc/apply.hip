@@ -386,6 +386,7 @@ ChebBounds cheb_bounds(const ibvt_coupling* c) {
 // eps in magnitude there (T_k(σ1) >= 1/eps): the error's energy norm is then
 // reduced by eps at least.
 int cheb_iterations(const ChebBounds& k, double eps) {
+  if (!(eps < 1.0)) return 1;  // a loose tolerance: one iteration, then the residual test
   const double it = std::acosh(1.0 / eps) / std::acosh(k.sigma1);
   return std::max(1, int(std::ceil(it)));
 }
