@@ -454,6 +454,15 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
 int ibvt_fluid_lumped_volume(const ibvt_grid* grid, int comp, double* out, hipStream_t stream);
 
 /*
+ * ibvt_fluid_lumped_volume_2d — the planar counterpart: the Q1 lumped area
+ * ∫ N_j dA of every node of component comp (0 or 1) of a planar grid, a
+ * product of two 1D hat integrals over the lattice hull: out (device,
+ * double, (n_y, n_x)).  Errors: IBVT_E_INVALID.
+ */
+int ibvt_fluid_lumped_volume_2d(const ibvt_grid2d* grid, int comp, double* out,
+                                hipStream_t stream);
+
+/*
  * Kernel tracing (process-wide; no paper counterpart).  While enabled, the
  * library records a HIP event pair on the caller's stream around each of
  * its main kernel launches.  ibvt_profile_read synchronizes those events and

@@ -361,6 +361,40 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
   return fsi_typed<double>(c, cfg, buf, solid, solid_ctx, fluid, fluid_ctx, stream, report);
 }
 
+int ibvt_fluid_lumped_volume_2d(const ibvt_grid2d* grid, int comp, double* out,
+                                hipStream_t stream) {
+  if (!grid || !out || comp < 0 || comp > 1) return set_error(IBVT_E_INVALID, "bad argument");
+  std::vector<double> w[2];
+  for (int e = 0; e < 2; ++e) {
+    int64_t n = 0;
+    int st = ibvt_lattice_coords_2d(grid, comp, e, nullptr, &n);
+    if (st) return st;
+    std::vector<double> L(static_cast<size_t>(n));
+    if ((st = ibvt_lattice_coords_2d(grid, comp, e, L.data(), &n))) return st;
+    w[e] = hat_weights(L);
+  }
+  const size_t total = w[0].size() + w[1].size() + 1;
+  double* dw = nullptr;
+  int st = hip_check(hipMallocAsync(reinterpret_cast<void**>(&dw), total * sizeof(double), stream),
+                     "weights alloc");
+  if (st) return st;
+  std::vector<double> all(w[0]);
+  all.insert(all.end(), w[1].begin(), w[1].end());
+  all.push_back(1.0);  // the unit third axis of k_volume
+  st = hip_check(hipMemcpyAsync(dw, all.data(), total * sizeof(double), hipMemcpyHostToDevice,
+                                stream),
+                 "weights copy");
+  const int64_t nx = int64_t(w[0].size()), ny = int64_t(w[1].size());
+  if (!st) {
+    k_volume<<<nblk(nx * ny), kThreads, 0, stream>>>(nx * ny, int(nx), int(ny), dw, dw + nx,
+                                                     dw + nx + ny, out);
+    st = hip_check(hipGetLastError(), "area launch");
+  }
+  const int st2 = hip_check(hipStreamSynchronize(stream), "sync");
+  (void)hipFreeAsync(dw, stream);
+  return st ? st : st2;
+}
+
 int ibvt_fluid_lumped_volume(const ibvt_grid* grid, int comp, double* out, hipStream_t stream) {
   if (!grid || !out || comp < 0 || comp > 2) return set_error(IBVT_E_INVALID, "bad argument");
   std::vector<double> w[3];

@@ -37,7 +37,7 @@ EXPORTED = [
     "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
     "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
     "assemble_coupling_2d", "ibvt_lattice_coords_2d", "assemble_coupling_unstructured",
-    "transfer_vjp",
+    "transfer_vjp", "ibvt_fluid_lumped_volume_2d",
 ]
 
 
@@ -144,6 +144,7 @@ def load_library(path: str = LIB_PATH):
     lib.fsi_step.argtypes = [vp, P(_FsiConfig), P(_FsiBuffers), _SOLID_FN, vp, _FLUID_FN, vp, vp,
                              P(_FsiReport)]
     lib.ibvt_fluid_lumped_volume.argtypes = [P(_Grid), ctypes.c_int, vp, vp]
+    lib.ibvt_fluid_lumped_volume_2d.argtypes = [P(_Grid2d), ctypes.c_int, vp, vp]
     lib.assemble_coupling_2d.argtypes = [P(_Grid2d), P(_Mesh2d), ctypes.c_int, u32, vp, P(vp)]
     lib.ibvt_lattice_coords_2d.argtypes = [P(_Grid2d), ctypes.c_int, ctypes.c_int, vp, P(i64)]
     lib.assemble_coupling_unstructured.argtypes = [P(_Mesh), P(_Mesh), ctypes.c_int, u32, vp, P(vp)]
@@ -153,7 +154,7 @@ def load_library(path: str = LIB_PATH):
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
                  "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d",
-                 "assemble_coupling_unstructured", "transfer_vjp"):
+                 "assemble_coupling_unstructured", "transfer_vjp", "ibvt_fluid_lumped_volume_2d"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -241,14 +242,16 @@ class FsiReport:
 
 def fluid_lumped_volume(faces, comp: int, device=None, stream=None):
     """Q1 lumped volume ∫ N_j of every node of component comp's lattice,
-    shape (n_z, n_y, n_x), float64 on the device."""
+    shape (n_z, n_y, n_x) (with two face arrays the planar lumped area,
+    shape (n_y, n_x)), float64 on the device."""
     import torch
     lib = load_library()
     g, keep = _grid_struct(faces)
     shape = tuple(reversed([len(a) for a in lattice_coords(faces, comp)]))
     out = torch.empty(shape, dtype=torch.float64, device=device or "cuda")
-    _check(lib.ibvt_fluid_lumped_volume(ctypes.byref(g), comp, ctypes.c_void_p(out.data_ptr()),
-                                        _stream(stream)), "ibvt_fluid_lumped_volume")
+    fn = lib.ibvt_fluid_lumped_volume if len(keep) == 3 else lib.ibvt_fluid_lumped_volume_2d
+    _check(fn(ctypes.byref(g), comp, ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+           "ibvt_fluid_lumped_volume")
     del keep
     return out
 

@@ -381,3 +381,16 @@ def test_fsi_step_matches_oracle(dev, pl, prec, mode, density):
         assert rel_fro(out["f_tilde"][d].cpu().numpy().ravel(), ref_["f_tilde"][d]) <= tol, d
         assert rel_fro(vf[d].cpu().numpy().ravel(), ref_["v_f"][d]) <= tol, d
     c.free()
+
+
+def test_fluid_lumped_area_matches_oracle(dev, pl):
+    """ibvt_fluid_lumped_volume_2d against the planar oracle's lumped areas
+    (products of exact 1D hat integrals), on the clustered reference grid."""
+    from paper_1810_13046_amd import fluid_lumped_volume
+    W = P2.workload2(5)
+    say("[gpu] planar lumped areas")
+    for d in range(2):
+        got = fluid_lumped_volume(W.faces, d, device=dev).cpu().numpy()
+        want = pl.fluid_lumped_volume(W.faces, d)
+        assert got.shape == want.shape
+        assert np.max(np.abs(got - want)) <= 1e-15 * want.max()
