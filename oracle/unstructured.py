@@ -285,7 +285,10 @@ def fsi_step(Xf, tets_f, X_ref, tets, u_hat0, v_f, solid, fluid, dt, alpha=1.0, 
         g = mass_solve(X, tets, f, S)
         f_tilde = [alpha * (cpl.B.T @ g[d]) for d in range(3)]
         if force_density:
-            f_tilde = [f_tilde[d] / vol for d in range(3)]
+            # a fluid vertex no tet touches has no volume and receives no
+            # load; its density is taken as zero
+            f_tilde = [np.divide(f_tilde[d], vol, out=np.zeros_like(f_tilde[d]), where=vol > 0)
+                       for d in range(3)]
         v = [np.asarray(a, dtype=np.float64).ravel() for a in fluid(f_tilde)]
         res = float(np.max(np.abs(f - f_old)))
         if it == 1:

@@ -184,6 +184,15 @@ int setup_lattices(ibvt_coupling* c, const ibvt_grid* g, hipStream_t s) {
 
 bool bad_ptr(const void* p) { return p == nullptr; }
 
+// A handle whose last assembly failed holds matrices and per-pair data of
+// different assemblies: every call that reads them is refused.
+int require_ready(const ibvt_coupling* c) {
+  if (!c->ready)
+    return set_error(IBVT_E_INVALID,
+                     "the coupling's last assembly failed: reassemble it successfully first");
+  return IBVT_OK;
+}
+
 // Planar grids: the same checks and lattices over two axes.  The lattice
 // table keeps the 3 x 3 layout (entries of axis or component 2 stay empty).
 int validate_grid2d(const ibvt_grid2d* g) {
@@ -271,6 +280,71 @@ int finish_assembly(ibvt_coupling* c, const double* X, const int32_t* elems, hip
   }
   *out = c;
   return IBVT_OK;
+}
+
+// Argument checks of transfer_velocity_vjp (no work done).
+int check_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
+                       const void* u_s, int mass, double cg_rtol, int cg_maxit,
+                       void* const g_uf[3], double* g_X) {
+  if (!c || !g_us) return set_error(IBVT_E_INVALID, "NULL argument");
+  if (int st0 = require_ready(c)) return st0;
+  if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
+    return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
+  if (c->dual && mass != IBVT_LUMPED)
+    return set_error(IBVT_E_INVALID, "the dual basis has a diagonal S: use IBVT_LUMPED");
+  if (g_X && (!u_f || !u_s)) return set_error(IBVT_E_INVALID, "g_X needs u_f and u_s");
+  if (g_X)
+    for (int d = 0; d < c->ncomp; ++d)
+      if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
+  if (g_uf)
+    for (int d = 0; d < c->ncomp; ++d)
+      if (!g_uf[d]) return set_error(IBVT_E_INVALID, "NULL g_uf component");
+  if (mass == IBVT_CONSISTENT) {
+    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
+    if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad mass-solve rtol/maxit");
+  }
+  return IBVT_OK;
+}
+
+// Argument checks of transfer_force_vjp (no work done).
+int check_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s, double alpha,
+                    double* g_X) {
+  if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
+  if (int st0 = require_ready(c)) return st0;
+  for (int d = 0; d < c->ncomp; ++d)
+    if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
+  if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
+  if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
+  return IBVT_OK;
+}
+
+// z = S^{-1} g_us into c->zbuf, and g_uf += B^T z.
+int velocity_adjoint(ibvt_coupling* c, const void* g_us, int mass, double cg_rtol, int cg_maxit,
+                     void* const g_uf[3], hipStream_t stream, void** z_out) {
+  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+  // z lives in its own buffer (the shape kernels reuse work2)
+  int st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize);
+  if (st) return st;
+  void* z = c->zbuf.p;
+  if (mass == IBVT_LUMPED) {
+    if ((st = lumped_solve(c, g_us, z, stream))) return st;
+  } else if ((st = mass_solve(c, g_us, z, cg_rtol, cg_maxit, stream, nullptr, false))) {
+    return st;
+  }
+  if (g_uf && (st = apply_Bt(c, z, g_uf, 1.0, stream))) return st;
+  *z_out = z;
+  return IBVT_OK;
+}
+
+// g_fs += alpha B g_ff (B into scratch, then accumulate).
+int force_adjoint(ibvt_coupling* c, const void* const g_ff[3], double alpha, void* g_fs,
+                  hipStream_t stream) {
+  if (!g_fs) return IBVT_OK;
+  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+  int st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize);
+  if (st) return st;
+  if ((st = apply_B(c, g_ff, c->zbuf.p, false, stream))) return st;
+  return axpy_solid(c, alpha, c->zbuf.p, g_fs, stream);
 }
 
 }  // namespace
@@ -459,6 +533,7 @@ int reassemble_coupling(ibvt_coupling* c, const double* X, hipStream_t stream) {
 int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int mass,
                       double cg_rtol, int cg_maxit, hipStream_t stream, ibvt_solve_info* info) {
   if (!c || !u_f || !u_s) return set_error(IBVT_E_INVALID, "NULL argument");
+  if (int st0 = require_ready(c)) return st0;
   for (int d = 0; d < c->ncomp; ++d)
     if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
@@ -481,6 +556,7 @@ int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int
 int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double alpha,
                    uint32_t flags, hipStream_t stream) {
   if (!c || !f_s || !f_f) return set_error(IBVT_E_INVALID, "NULL argument");
+  if (int st0 = require_ready(c)) return st0;
   for (int d = 0; d < c->ncomp; ++d)
     if (!f_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (flags & ~IBVT_FORCE_IS_LOAD) return set_error(IBVT_E_INVALID, "unknown flags");
@@ -501,72 +577,6 @@ int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double
   return apply_Bt(c, f_s, f_f, alpha, stream);
 }
 
-namespace {
-
-// Argument checks of transfer_velocity_vjp (no work done).
-int check_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
-                       const void* u_s, int mass, double cg_rtol, int cg_maxit,
-                       void* const g_uf[3], double* g_X) {
-  if (!c || !g_us) return set_error(IBVT_E_INVALID, "NULL argument");
-  if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
-    return set_error(IBVT_E_INVALID, "mass must be IBVT_LUMPED or IBVT_CONSISTENT");
-  if (c->dual && mass != IBVT_LUMPED)
-    return set_error(IBVT_E_INVALID, "the dual basis has a diagonal S: use IBVT_LUMPED");
-  if (g_X && (!u_f || !u_s)) return set_error(IBVT_E_INVALID, "g_X needs u_f and u_s");
-  if (g_X)
-    for (int d = 0; d < c->ncomp; ++d)
-      if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
-  if (g_uf)
-    for (int d = 0; d < c->ncomp; ++d)
-      if (!g_uf[d]) return set_error(IBVT_E_INVALID, "NULL g_uf component");
-  if (mass == IBVT_CONSISTENT) {
-    if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built");
-    if (!(cg_rtol > 0.0) || cg_maxit < 1) return set_error(IBVT_E_INVALID, "bad mass-solve rtol/maxit");
-  }
-  return IBVT_OK;
-}
-
-// Argument checks of transfer_force_vjp (no work done).
-int check_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* f_s, double alpha,
-                    double* g_X) {
-  if (!c || !g_ff) return set_error(IBVT_E_INVALID, "NULL argument");
-  for (int d = 0; d < c->ncomp; ++d)
-    if (!g_ff[d]) return set_error(IBVT_E_INVALID, "NULL g_ff component");
-  if (g_X && !f_s) return set_error(IBVT_E_INVALID, "g_X needs f_s");
-  if (!std::isfinite(alpha)) return set_error(IBVT_E_INVALID, "alpha must be finite");
-  return IBVT_OK;
-}
-
-// z = S^{-1} g_us into c->zbuf, and g_uf += B^T z.
-int velocity_adjoint(ibvt_coupling* c, const void* g_us, int mass, double cg_rtol, int cg_maxit,
-                     void* const g_uf[3], hipStream_t stream, void** z_out) {
-  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
-  // z lives in its own buffer (the shape kernels reuse work2)
-  int st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize);
-  if (st) return st;
-  void* z = c->zbuf.p;
-  if (mass == IBVT_LUMPED) {
-    if ((st = lumped_solve(c, g_us, z, stream))) return st;
-  } else if ((st = mass_solve(c, g_us, z, cg_rtol, cg_maxit, stream, nullptr, false))) {
-    return st;
-  }
-  if (g_uf && (st = apply_Bt(c, z, g_uf, 1.0, stream))) return st;
-  *z_out = z;
-  return IBVT_OK;
-}
-
-// g_fs += alpha B g_ff (B into scratch, then accumulate).
-int force_adjoint(ibvt_coupling* c, const void* const g_ff[3], double alpha, void* g_fs,
-                  hipStream_t stream) {
-  if (!g_fs) return IBVT_OK;
-  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
-  int st = ensure(c, c->zbuf, size_t(3 * c->n_vert) * tsize);
-  if (st) return st;
-  if ((st = apply_B(c, g_ff, c->zbuf.p, false, stream))) return st;
-  return axpy_solid(c, alpha, c->zbuf.p, g_fs, stream);
-}
-
-}  // namespace
 
 int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3],
                           const void* u_s, int mass, double cg_rtol, int cg_maxit,
@@ -657,6 +667,7 @@ int coupling_export_csr(const ibvt_coupling* c, int comp, int transposed, int64_
                         int32_t* row_map) {
   if (!c || comp < 0 || comp >= c->ncomp || !n_rows || !nnz)
     return set_error(IBVT_E_INVALID, "bad argument");
+  if (int st0 = require_ready(c)) return st0;
   const Csr& m = transposed ? c->Bt[comp] : c->B[comp];
   *n_rows = m.nrows;
   *nnz = m.nnz;

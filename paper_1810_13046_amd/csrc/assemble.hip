@@ -1202,9 +1202,30 @@ int build_topology(ibvt_coupling* c, hipStream_t s) {
   return IBVT_OK;
 }
 
+namespace {
+int assemble_grid(ibvt_coupling* c, hipStream_t s);
+}  // namespace
+
+// Every assembly starts by marking the handle unusable and marks it usable
+// only when every step has succeeded, so that a failed reassembly (a solid
+// leaving the lattice, a capacity error) cannot leave transfers running on a
+// mix of old matrices and new per-pair data.
 int assemble_all(ibvt_coupling* c, hipStream_t s) {
-  if (c->dim == 2) return assemble_all_2d(c, s);
-  if (c->unstructured) return assemble_all_unstructured(c, s);
+  c->ready = false;
+  c->mom_valid = false;
+  const int st = c->dim == 2 ? assemble_all_2d(c, s)
+                 : c->unstructured ? assemble_all_unstructured(c, s)
+                                   : assemble_grid(c, s);
+  if (st) {
+    c->mom_valid = false;
+    return st;
+  }
+  c->ready = true;
+  return IBVT_OK;
+}
+
+namespace {
+int assemble_grid(ibvt_coupling* c, hipStream_t s) {
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
   int st;
   int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));
@@ -1226,5 +1247,6 @@ int assemble_all(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->minv, size_t(n_v + 1) * sizeof(double)))) return st;
   return assemble_typed<double>(c, s);
 }
+}  // namespace
 
 }  // namespace ibvt

@@ -85,7 +85,8 @@ __global__ void k_density(int64_t nf, int nx, int ny, const double* __restrict__
   if (j >= nf) return;
   const int64_t ix = j % nx, r = j / nx;
   const int64_t iy = r % ny, iz = r / ny;
-  f[j] = T(double(f[j]) / (wx[ix] * wy[iy] * wz[iz]));
+  const double w = wx[ix] * wy[iy] * wz[iz];  // > 0 on lattices of two or more cells per axis
+  f[j] = w > 0.0 ? T(double(f[j]) / w) : T(0);
 }
 
 // f[j] /= wx[ix] wy[iy] over an (n_y, n_x) planar lattice
@@ -95,7 +96,8 @@ __global__ void k_density2(int64_t nf, int nx, const double* __restrict__ wx,
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= nf) return;
   const int64_t ix = j % nx, iy = j / nx;
-  f[j] = T(double(f[j]) / (wx[ix] * wy[iy]));
+  const double w = wx[ix] * wy[iy];
+  f[j] = w > 0.0 ? T(double(f[j]) / w) : T(0);
 }
 
 __global__ void k_volume(int64_t nf, int nx, int ny, const double* __restrict__ wx,
@@ -111,7 +113,8 @@ __global__ void k_volume(int64_t nf, int nx, int ny, const double* __restrict__ 
 template <typename T>
 __global__ void k_density_nodal(int64_t nf, const double* __restrict__ vol, T* __restrict__ f) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j < nf) f[j] = T(double(f[j]) / vol[j]);
+  // a node no tet touches has no volume and no load: its density is zero
+  if (j < nf) f[j] = vol[j] > 0.0 ? T(double(f[j]) / vol[j]) : T(0);
 }
 
 // One item per (fluid tet, corner), in tet-major order: key = the corner's

@@ -114,6 +114,7 @@ struct ibvt_coupling {
   int64_t pool_cap = 0;      // records
   int64_t pool_needed = 0;   // records the last assembly asked for
   bool mom_valid = false;    // pmom holds the moments of every kept piece of the last assembly
+  bool ready = false;        // the last assembly completed: B, B^T and the masses are usable
   ibvt::DevBuf pinfo;        // uint64 n_pairs: first record << 8 | records (0: dropped)
   ibvt::DevBuf order;        // int32 n_pairs: pairs sorted by cut pattern
   ibvt::DevBuf pscan;        // sort keys and scratch

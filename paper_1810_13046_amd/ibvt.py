@@ -358,8 +358,9 @@ class Coupling:
         planar coupling, whose X_ref is (n_vert, 2); with an unstructured
         coupling the v_f are nodal arrays of the fluid mesh and the force
         density divides by the nodes' lumped volumes ∫ μ_j).  Both receive this
-        call's tensors and must enqueue their work on the current stream.
-        Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
+        call's tensors and must enqueue their work on the current stream
+        (with an explicit `stream`, that stream is made current for the
+        call, so the callbacks and the driver share it).  Returns (report, dict of u_hat, w_s, f_fsi, f_tilde)."""
         import torch
         dt_ = self.dtype
         dev = X_ref.device
@@ -404,8 +405,14 @@ class Coupling:
 
         cs, cf = _SOLID_FN(_solid), _FLUID_FN(_fluid)
         rep = _FsiReport()
-        st = _lib.fsi_step(self.handle, ctypes.byref(cfg), ctypes.byref(buf), cs, None, cf, None,
-                           _stream(stream), ctypes.byref(rep))
+        # the callbacks enqueue on torch's current stream: make it the
+        # driver's stream for the duration of the call, so Steps 3 and 5
+        # are ordered with the driver's own kernels
+        import contextlib
+        scope = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+        with scope:
+            st = _lib.fsi_step(self.handle, ctypes.byref(cfg), ctypes.byref(buf), cs, None, cf,
+                               None, _stream(stream), ctypes.byref(rep))
         if errors:
             raise errors[0]
         report = FsiReport(int(rep.iterations), bool(rep.converged), float(rep.res_abs),

@@ -86,3 +86,39 @@ WORKLOADS = {
 def workload(name):
     cfg, small = WORKLOADS[name]
     return wl.workload(cfg, small=small)
+
+
+def sampled_rows_check(c, faces, X, tets, u_f, f_s, n_rows, seed, us=None, ff=None):
+    """Sampled rows of B^d and columns of B^dT of a GPU coupling against the
+    oracle, which integrates only the tets that touch them; with us (lumped
+    velocity, (3, n_v)) and ff (force, 3 flat arrays) also the transferred
+    values there.  Returns the largest relative Frobenius error of each
+    kind."""
+    import scipy.sparse as sp_
+    bounds = oracle.tet_bounds(X, tets)
+    rng = np.random.default_rng(seed)
+    verts = np.sort(rng.choice(X.shape[0], n_rows, replace=False))
+    star = oracle.vertex_star(tets, verts)
+    R = oracle.assemble(faces, X, tets, subset=star)
+    m = oracle.lumped_mass(X, tets[star], n_vert=X.shape[0])
+    err = dict(rows=0.0, cols=0.0, velocity=0.0, force=0.0)
+    for d in range(3):
+        rp, col, val = c.export_csr(d)
+        G = sp_.csr_matrix((val, col, rp), shape=(X.shape[0], oracle.n_fluid(faces, d)))
+        Gs, Rs = G[verts], R.B[d][verts]
+        err["rows"] = max(err["rows"], sp_.linalg.norm(Gs - Rs) / sp_.linalg.norm(Rs))
+        if us is not None:
+            want = (Rs @ np.asarray(u_f[d]).ravel()) / m[verts]
+            err["velocity"] = max(err["velocity"], rel_fro(us[d][verts], want))
+        cols = np.unique(Rs.indices)
+        pick = np.sort(rng.choice(cols, min(16, cols.size), replace=False))
+        nx, ny, _ = oracle.lattice_shape(faces, d)
+        sub = np.unique(np.concatenate([
+            oracle.tets_touching_node(faces, X, tets, d, (j % nx, (j // nx) % ny, j // (nx * ny)),
+                                      bounds) for j in pick]))
+        Rc = oracle.assemble(faces, X, tets, subset=sub).B[d].tocsc()[:, pick]
+        Gc = G.tocsc()[:, pick]
+        err["cols"] = max(err["cols"], sp_.linalg.norm(Gc - Rc) / sp_.linalg.norm(Rc))
+        if ff is not None:
+            err["force"] = max(err["force"], rel_fro(ff[d][pick], Rc.T @ f_s[d]))
+    return err

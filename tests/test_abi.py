@@ -31,6 +31,22 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(ibvt.EXPORTED) == names
 
 
+def test_exported_set_equals_declared_set(lib):
+    """The library's dynamic symbol table holds the declared calls and
+    nothing else (no internal helper is reachable through the ABI)."""
+    import shutil
+    import subprocess
+    from paper_1810_13046_amd import ibvt
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", ibvt.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines()
+                       if len(ln.split()) >= 3 and ln.split()[1] in ("T", "W", "D", "B", "V")})
+    assert exported == declared_functions()
+
+
 def test_status_strings(lib):
     for st in range(8):
         assert lib.ibvt_status_string(st)

@@ -263,3 +263,44 @@ def test_edge_cases(dev):
     _, info = c.velocity(ud, mass="consistent", rtol=20.0, maxit=5, with_info=True)
     assert info.iterations[0] == 1 and max(info.rel_residual) <= 20.0
     c.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_failed_reassembly_refuses_transfers_until_reassembled(dev, prec):
+    """A reassembly that fails (a vertex leaves the lattice hull) leaves the
+    handle unusable: transfers, reverse-mode calls and the export are
+    refused on the host; a later successful reassembly makes it usable again
+    with the right matrices."""
+    import torch
+    from paper_1810_13046_amd import IbvtError
+    W, R = ref("beam144_grid32")
+    c = make("beam144_grid32", prec, dev)
+    dt = c.dtype
+    ud = [to_dev(u, dt, dev) for u in fluid_fields(W)]
+    Xo = W.X.copy()
+    Xo[0] = [0.001, 0.5, 0.5]
+    say(f"[gpu] failed reassembly {prec}")
+    with pytest.raises(IbvtError) as e:
+        c.reassemble(to_dev(Xo, torch.float64, dev))
+    assert e.value.name == "IBVT_E_OUT_OF_GRID"
+    us = torch.zeros((3, W.X.shape[0]), dtype=dt, device=dev)
+    for call in (lambda: c.velocity(ud, out=us),
+                 lambda: c.velocity(ud, mass="consistent", out=us),
+                 lambda: c.force(us, [torch.zeros_like(u) for u in ud]),
+                 lambda: c.velocity_vjp(us, u_f=ud, u_s=us,
+                                        g_X=torch.zeros((W.X.shape[0], 3), dtype=torch.float64,
+                                                        device=dev)),
+                 lambda: c.force_vjp(ud, f_s=us, g_fs=torch.zeros_like(us)),
+                 lambda: c.vjp(us, ud, u_f=ud, u_s=us, f_s=us,
+                               g_X=torch.zeros((W.X.shape[0], 3), dtype=torch.float64,
+                                               device=dev)),
+                 lambda: c.export_csr(0)):
+        with pytest.raises(IbvtError) as e:
+            call()
+        assert e.value.name == "IBVT_E_INVALID"
+    assert float(us.abs().sum()) == 0.0  # nothing was written
+    c.reassemble(to_dev(W.X, torch.float64, dev))
+    for d in range(3):
+        fro, mx = sparse_rel(gpu_csr(c, d, oracle.n_fluid(W.faces, d)), R.B[d])
+        assert fro <= TOL[prec]
+    c.free()

@@ -357,3 +357,43 @@ def test_unstructured_fsi_step_matches_oracle(dev, un, prec, mode, density):
         assert rel_fro(out["f_tilde"][d].cpu().numpy(), ref_["f_tilde"][d]) <= tol, d
         assert rel_fro(vf[d].cpu().numpy(), ref_["v_f"][d]) <= tol, d
     c.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_unstructured_fsi_density_with_an_orphan_fluid_vertex(dev, un, prec):
+    """A fluid vertex no fluid tet uses (zero lumped volume): the driver's
+    force density there is zero, every value is finite, and the rest matches
+    the oracle's loop."""
+    import torch
+    W = WU.workload_u(2)
+    n, nf = W.X.shape[0], W.Xf.shape[0]
+    Xf2 = np.vstack([W.Xf, W.Xf[:1] + 0.01])
+    rng = np.random.default_rng(9)
+    u0 = 1e-3 * rng.standard_normal((3, n))
+    vb = [np.concatenate([rng.standard_normal(nf), [0.0]]) for _ in range(3)]
+    say(f"[gpu] unstructured fsi_step with an orphan fluid vertex {prec}")
+    ref_ = un.fsi_step(Xf2, W.tets_f, W.X, W.tets, u0, [np.zeros(nf + 1)] * 3,
+                       lambda u: -10.0 * u, lambda ft: [vb[d] + 1e-6 * ft[d] for d in range(3)],
+                       0.05, 0.8, eps_abs=0.0, eps_rel=0.0, max_iter=2, force_density=True)
+    from paper_1810_13046_amd import Coupling
+    c = Coupling(None, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
+                 precision=prec, consistent=False,
+                 fluid_mesh=(to_dev(Xf2, torch.float64, dev), to_dev(W.tets_f, torch.int32, dev)))
+    dt_ = c.dtype
+    vbd = [to_dev(v, dt_, dev) for v in vb]
+    vf = [torch.zeros_like(v) for v in vbd]
+
+    def fluid(f_tilde, v):
+        for d in range(3):
+            torch.add(vbd[d], f_tilde[d], alpha=1e-6, out=v[d])
+
+    rep, out = c.fsi_step(to_dev(W.X, torch.float64, dev), to_dev(u0, dt_, dev), vf,
+                          lambda u, f: torch.mul(u, -10.0, out=f), fluid, dt=0.05, alpha=0.8,
+                          eps_abs=0.0, eps_rel=0.0, max_iter=2, force_density=True,
+                          raise_not_converged=False)
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for d in range(3):
+        ft = out["f_tilde"][d].cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(ft)) and ft[nf] == 0.0
+        assert rel_fro(ft, ref_["f_tilde"][d]) <= tol, d
+    c.free()

@@ -264,3 +264,28 @@ def test_fsi_picard_reaches_the_fixed_point(un, w1, mode, density):
         rhs = -k_s * (u0[d] - u_rest[d] + dt * T @ v_base[d])
         f_star = np.linalg.solve(A, rhs)
         assert np.max(np.abs(r["f_fsi"][d] - f_star)) <= 1e-11 * max(1.0, np.max(np.abs(f_star)))
+
+
+def test_fsi_density_of_an_orphan_fluid_vertex_is_zero(un, w1):
+    """A fluid vertex that no fluid tet uses has no lumped volume and
+    receives no load; with the force-density option its density is zero
+    (not 0/0), and every other node is what it is without that vertex."""
+    W, _ = w1
+    n, nf = W.X.shape[0], W.Xf.shape[0]
+    Xf2 = np.vstack([W.Xf, W.Xf[:1] + 0.01])
+    rng = np.random.default_rng(8)
+    u0 = 1e-3 * rng.standard_normal((3, n))
+    v0 = [rng.standard_normal(nf) for _ in range(3)]
+
+    def run(Xf, extra):
+        v = [np.concatenate([a, np.zeros(extra)]) for a in v0]
+        return un.fsi_step(Xf, W.tets_f, W.X, W.tets, u0, v, lambda u: -10.0 * u,
+                           lambda ft: [a + 1e-6 * f for a, f in zip(v, ft)], 0.05, 0.8,
+                           eps_abs=0.0, eps_rel=0.0, max_iter=2, force_density=True)
+
+    a, b = run(W.Xf, 0), run(Xf2, 1)
+    for d in range(3):
+        assert np.all(np.isfinite(b["f_tilde"][d]))
+        assert b["f_tilde"][d][nf] == 0.0
+        assert np.max(np.abs(b["f_tilde"][d][:nf] - a["f_tilde"][d])) <= 1e-12 * max(
+            1.0, np.max(np.abs(a["f_tilde"][d])))
