@@ -25,10 +25,19 @@
  *   - Fluid and solid fields are double for IBVT_FP64 couplings and float
  *     for IBVT_FP32_MIXED couplings.  Coordinates X and the gradient g_X are
  *     always double.
- *   - Work is enqueued on `stream` in order.  Calls that size device
- *     buffers (assembly) synchronize the stream once or twice to read
- *     counts; transfers synchronize only for the consistent-mass solve's
- *     convergence checks and when `info` is requested.
+ *   - Work is enqueued on `stream` in order.  Assembly reads counts back
+ *     to size its buffers: a grid reassembly synchronizes the stream seven
+ *     times (four packed read-backs of counts and status flags, one per
+ *     velocity component in the transpose), a few more when a handle is
+ *     created (lattices, topology, mass pattern); planar and unstructured
+ *     assemblies a similar fixed number.  Transfers synchronize only for
+ *     the consistent-mass solve's convergence checks and when `info` is
+ *     requested.
+ *   - The library's device buffers grow stream-ordered (hipMallocAsync and
+ *     hipFreeAsync on the call's stream), so growing them does not
+ *     synchronize the device.  Calls on one handle with different streams
+ *     must be ordered by the caller (an event or a synchronization), as
+ *     for the data they share.
  *   - Every call returns an ibvt status; nothing throws across the ABI.
  *     ibvt_last_error() returns a thread-local message for the last failure.
  *
@@ -158,6 +167,9 @@ typedef struct {
                                 counts triangles, component 2 is empty) */
   int64_t unstructured;      /* 1 for a tetrahedral fluid background
                                 (n_fluid[d] = its vertices, lattice = 0) */
+  int64_t plane_cuts;        /* (pair, cell plane) clips run by the last
+                                assembly (grids: the cell planes each
+                                piece's tet straddles) */
 } ibvt_info;
 
 /*

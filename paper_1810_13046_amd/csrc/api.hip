@@ -64,20 +64,22 @@ int hip_check(hipError_t e, const char* what) {
 int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 1;
   if (b.p && b.cap >= bytes) return IBVT_OK;
+  // stream-ordered: the old buffer is released after the work queued on
+  // the call's stream, and growing does not synchronize the device
   if (b.p) {
-    hipError_t e = hipFree(b.p);
+    hipError_t e = hipFreeAsync(b.p, c->stream);
     c->device_bytes -= int64_t(b.cap);
     b.p = nullptr;
     b.cap = 0;
-    if (e != hipSuccess) return hip_check(e, "hipFree");
+    if (e != hipSuccess) return hip_check(e, "hipFreeAsync");
   }
   // grow with headroom so a moving mesh does not reallocate every step
   const size_t want = bytes + bytes / 8 + 256;
-  hipError_t e = hipMalloc(&b.p, want);
+  hipError_t e = hipMallocAsync(&b.p, want, c->stream);
   if (e != hipSuccess) {
     b.p = nullptr;
     (void)hipGetLastError();
-    return hip_check(e, "hipMalloc");
+    return hip_check(e, "hipMallocAsync");
   }
   b.cap = want;
   c->device_bytes += int64_t(want);
@@ -86,7 +88,7 @@ int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes) {
 
 void release(ibvt_coupling* c, DevBuf& b) {
   if (b.p) {
-    (void)hipFree(b.p);
+    (void)hipFreeAsync(b.p, c->stream);
     c->device_bytes -= int64_t(b.cap);
   }
   b.p = nullptr;
@@ -112,8 +114,13 @@ void release_all(ibvt_coupling* c) {
                     &c->order,    &c->pscan,     &c->rowbox,    &c->rowcap,    &c->rowtmpoff,
                     &c->rowtmpcol, &c->rowtmpval, &c->tetgrad, &c->mcoef,
                     &c->fsiX,     &c->fsinorm,   &c->fvol,      &c->fX,        &c->ftets,
-                    &c->frec,     &c->fbox,      &c->forder,    &c->ftree,     &c->ucoo};
+                    &c->frec,     &c->fbox,      &c->forder,    &c->ftree,     &c->ucoo,
+                    &c->rb};
   for (DevBuf* b : bufs) release(c, *b);
+  if (c->host_rb) {
+    (void)hipHostFree(c->host_rb);
+    c->host_rb = nullptr;
+  }
   // an unstructured coupling's components share B[0] and Bt[0]
   const int own = c->unstructured ? 1 : 3;
   for (int d = 0; d < own; ++d) {
@@ -411,6 +418,7 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
     return set_error(IBVT_E_INVALID, "unknown flags");
   ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
+  c->stream = stream;
   c->precision = precision;
   c->flags = flags;
   c->n_vert = mesh->n_vert;
@@ -448,6 +456,7 @@ int assemble_coupling_unstructured(const ibvt_mesh* fluid, const ibvt_mesh* mesh
   ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
   c->unstructured = true;
+  c->stream = stream;
   c->precision = precision;
   c->flags = flags;
   c->n_vert = mesh->n_vert;
@@ -503,6 +512,7 @@ int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int p
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
   c->dim = 2;
   c->ncomp = 2;
+  c->stream = stream;
   c->precision = precision;
   c->flags = flags;
   c->n_vert = mesh->n_vert;
@@ -523,6 +533,7 @@ int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int p
 
 int reassemble_coupling(ibvt_coupling* c, const double* X, hipStream_t stream) {
   if (!c || !X) return set_error(IBVT_E_INVALID, "NULL coupling or X");
+  c->stream = stream;
   int st = hip_check(hipMemcpyAsync(c->X.p, X, size_t(c->dim * c->n_vert) * sizeof(double),
                                     hipMemcpyDeviceToDevice, stream),
                      "copy X");
@@ -534,6 +545,7 @@ int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int
                       double cg_rtol, int cg_maxit, hipStream_t stream, ibvt_solve_info* info) {
   if (!c || !u_f || !u_s) return set_error(IBVT_E_INVALID, "NULL argument");
   if (int st0 = require_ready(c)) return st0;
+  c->stream = stream;
   for (int d = 0; d < c->ncomp; ++d)
     if (!u_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (mass != IBVT_LUMPED && mass != IBVT_CONSISTENT)
@@ -557,6 +569,7 @@ int transfer_force(ibvt_coupling* c, const void* f_s, void* const f_f[3], double
                    uint32_t flags, hipStream_t stream) {
   if (!c || !f_s || !f_f) return set_error(IBVT_E_INVALID, "NULL argument");
   if (int st0 = require_ready(c)) return st0;
+  c->stream = stream;
   for (int d = 0; d < c->ncomp; ++d)
     if (!f_f[d]) return set_error(IBVT_E_INVALID, "NULL fluid component");
   if (flags & ~IBVT_FORCE_IS_LOAD) return set_error(IBVT_E_INVALID, "unknown flags");
@@ -583,6 +596,7 @@ int transfer_velocity_vjp(ibvt_coupling* c, const void* g_us, const void* const 
                           void* const g_uf[3], double* g_X, hipStream_t stream) {
   int st = check_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf, g_X);
   if (st) return st;
+  c->stream = stream;
   void* z = nullptr;
   if ((st = velocity_adjoint(c, g_us, mass, cg_rtol, cg_maxit, g_uf, stream, &z))) return st;
   if (g_X) {
@@ -599,6 +613,7 @@ int transfer_force_vjp(ibvt_coupling* c, const void* const g_ff[3], const void* 
                        double alpha, void* g_fs, double* g_X, hipStream_t stream) {
   int st = check_force_vjp(c, g_ff, f_s, alpha, g_X);
   if (st) return st;
+  c->stream = stream;
   if ((st = force_adjoint(c, g_ff, alpha, g_fs, stream))) return st;
   if (g_X) {
     st = c->unstructured
@@ -616,6 +631,7 @@ int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], c
                  double* g_X, hipStream_t stream) {
   int st = check_velocity_vjp(c, g_us, u_f, u_s, mass, cg_rtol, cg_maxit, g_uf, g_X);
   if (st) return st;
+  c->stream = stream;
   if ((st = check_force_vjp(c, g_ff, f_s, alpha, g_X))) return st;
   if (!(g_X && c->dim == 3 && (c->unstructured || c->mom_valid))) {
     // no stored moments to share: the two calls
@@ -656,6 +672,7 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->piece_store = c->mom_valid ? 1 : 0;
   info->dist_evals = c->stats.dist_evals;
   info->cut_points = c->stats.cut_points;
+  info->plane_cuts = c->stats.plane_cuts;
   info->dual = c->dual ? 1 : 0;
   info->dim = c->dim;
   info->unstructured = c->unstructured ? 1 : 0;
@@ -747,7 +764,9 @@ int ibvt_profile_read(const char** names, int64_t* launches, double* ms, int max
 void coupling_free(ibvt_coupling* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  c->stream = nullptr;  // the caller's streams may be gone: free on the null stream
   release_all(c);
+  (void)hipStreamSynchronize(nullptr);
   delete c;
 }
 

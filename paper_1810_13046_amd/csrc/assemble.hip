@@ -249,7 +249,7 @@ __device__ __forceinline__ void pair_geometry(int64_t p, int64_t n_t, const int3
 // slots); sorting by the key gives every wave the same sequence of clips.
 __global__ void k_pair_key(int64_t n_pairs, const int32_t* __restrict__ owner,
                            const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-                           uint8_t* __restrict__ key, int32_t* __restrict__ idx) {
+                           uint8_t* __restrict__ key) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p < n_pairs) {
     const int64_t tc = owner[p];
@@ -266,26 +266,7 @@ __global__ void k_pair_key(int64_t n_pairs, const int32_t* __restrict__ owner,
     const int cuts = __popc(pattern);
     const int cls = cuts <= 3 ? 0 : (cuts == 4 ? 1 : 2);
     key[p] = uint8_t(cls * 64 + pattern);
-    idx[p] = int32_t(p);
   }
-}
-
-// Class sizes from the sorted keys: first index with key >= 64·k.
-__global__ void k_class_bounds(int64_t n, const uint8_t* __restrict__ skeys,
-                               unsigned long long* __restrict__ out) {
-  const int k = threadIdx.x;
-  __shared__ int64_t first[4];
-  if (k < 4) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (int(skeys[mid]) < 64 * k) lo = mid + 1;
-      else hi = mid;
-    }
-    first[k] = (k == 3) ? n : lo;
-  }
-  __syncthreads();
-  if (k < 3) out[k] = (unsigned long long)(first[k + 1] - first[k]);
 }
 
 // Clip every (tet, component, cell) pair in double, one lane per pair, and
@@ -298,14 +279,23 @@ __global__ void k_class_bounds(int64_t n, const uint8_t* __restrict__ skeys,
 // summed per wave and added once at the end.
 template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_clip(
-    int64_t n_list, const int32_t* __restrict__ order, int64_t n_t, const int32_t* __restrict__ owner,
+    const int64_t* __restrict__ cls_first, const int64_t* __restrict__ cls_end,
+    const int32_t* __restrict__ order_all, int64_t n_t, const int32_t* __restrict__ owner,
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
     const double* __restrict__ tetrec, const double* __restrict__ lat, LatDesc ld,
     double drop_rel, T* __restrict__ pool, int64_t pool_cap, uint64_t* __restrict__ pinfo,
-    int chunk, unsigned* flags, unsigned long long* counters) {
+    unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
   __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
+  // this class's stretch of the pair order (read here, so the host needs
+  // no class sizes); chunk ~ 1/8 of a wave's expected records (about 3 per
+  // pair), so the unused chunk tails stay a few percent of the store
+  const int64_t first = *cls_first;
+  const int64_t n_list = *cls_end - first;
+  const int32_t* __restrict__ order = order_all + first;
+  const int chunk = int(min<int64_t>(
+      2048, max<int64_t>(1, (3 * n_list) / (8 * int64_t(gridDim.x)))));
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   unsigned long long nk = 0, nd = 0, ns = 0;
   ClipCount cc;
@@ -344,7 +334,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
     if (wave_total > cleft) {
       const int take = wave_total > chunk ? wave_total : chunk;
       unsigned long long b = 0;
-      if (lane == 0) b = atomicAdd(&counters[kCntPool], (unsigned long long)take);
+      if (lane == 0) b = atomicAdd(&counters[kCntPoolUsed], (unsigned long long)take);
       cbase = __shfl(b, 0, kWave);
       cleft = take;
     }
@@ -368,7 +358,9 @@ __global__ __launch_bounds__(kWave) void k_clip(
         const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
         const double vol = vol6 * cv / 6.0;
         const bool kp = vol > drop_rel * (fabs(G.det) / 6.0);
-        pinfo[p] = kp ? ((uint64_t(my) << 8) | uint64_t(nsub)) : 0;
+        // records past the store's end were not written: the pair reads as
+        // empty, and the host sees the overflow and runs the clip again
+        pinfo[p] = (kp && fits) ? ((uint64_t(my) << 8) | uint64_t(nsub)) : 0;
         if (kp) ++nk;
         else if (vol > 0.0) ++nd;
       }
@@ -379,8 +371,10 @@ __global__ __launch_bounds__(kWave) void k_clip(
   ns = wave_sum(ns);
   const unsigned long long ndist = wave_sum((unsigned long long)cc.dist);
   const unsigned long long ncut = wave_sum((unsigned long long)cc.cuts);
+  const unsigned long long npl = wave_sum((unsigned long long)cc.planes);
   const uint64_t fm = ballot64(fail);
   if (lane == 0) {
+    if (npl) atomicAdd(&counters[kCntPlanes], npl);
     if (nk) atomicAdd(&counters[kCntPieces], nk);
     if (nd) atomicAdd(&counters[kCntDropped], nd);
     if (ns) atomicAdd(&counters[kCntSubtets], ns);
@@ -890,10 +884,7 @@ int read_back(ibvt_coupling* c, void* host, const void* dev, size_t bytes, hipSt
   return hip_check(hipStreamSynchronize(s), "stream sync");
 }
 
-int check_flags(ibvt_coupling* c, hipStream_t s) {
-  unsigned f = 0;
-  int st = read_back(c, &f, c->flags_dev.p, sizeof(unsigned), s);
-  if (st) return st;
+int flags_status(unsigned f) {
   if (f & kFlagNonFinite) return set_error(IBVT_E_INVALID, "non-finite vertex coordinate");
   if (f & kFlagValence) return set_error(IBVT_E_INVALID, "tet vertex index out of range or repeated");
   if (f & kFlagOutOfGrid)
@@ -902,6 +893,51 @@ int check_flags(ibvt_coupling* c, hipStream_t s) {
     return set_error(IBVT_E_CAPACITY, "clipped piece exceeded the 16-vertex capacity");
   if (f & kFlagTetSpan)
     return set_error(IBVT_E_CAPACITY, "an element spans more than 65535 cells of one lattice");
+  return IBVT_OK;
+}
+
+int check_flags(ibvt_coupling* c, hipStream_t s) {
+  unsigned f = 0;
+  int st = read_back(c, &f, c->flags_dev.p, sizeof(unsigned), s);
+  if (st) return st;
+  return flags_status(f);
+}
+
+namespace {
+constexpr int kMaxCounts = 16;
+struct CountSrc {
+  const int64_t* p[kMaxCounts];
+};
+__global__ void k_gather_counts(CountSrc src, int n, const unsigned* __restrict__ flags,
+                                int64_t* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k < n) out[k] = *src.p[k];
+  if (k == 0) out[kMaxCounts] = int64_t(*flags);
+}
+}  // namespace
+
+int read_counts(ibvt_coupling* c, const int64_t* const* srcs, int n, int64_t* out, hipStream_t s) {
+  if (n < 0 || n > kMaxCounts) return set_error(IBVT_E_INVALID, "read_counts: too many values");
+  int st = ensure(c, c->rb, (kMaxCounts + 1) * sizeof(int64_t));
+  if (st) return st;
+  if (!c->host_rb) {
+    void* h = nullptr;
+    if ((st = hip_check(hipHostMalloc(&h, (kMaxCounts + 1) * sizeof(int64_t), hipHostMallocDefault),
+                        "hipHostMalloc")))
+      return st;
+    c->host_rb = static_cast<int64_t*>(h);
+  }
+  CountSrc src{};
+  for (int k = 0; k < n; ++k) src.p[k] = srcs[k];
+  k_gather_counts<<<1, 64, 0, s>>>(src, n, c->flags_dev.as<unsigned>(), c->rb.as<int64_t>());
+  if ((st = hip_check(hipGetLastError(), "count gather launch"))) return st;
+  if ((st = hip_check(hipMemcpyAsync(c->host_rb, c->rb.p, (kMaxCounts + 1) * sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, s),
+                      "read back")))
+    return st;
+  if ((st = hip_check(hipStreamSynchronize(s), "stream sync"))) return st;
+  for (int k = 0; k < n; ++k) out[k] = c->host_rb[k];
+  c->host_flags = unsigned(c->host_rb[kMaxCounts]);
   return IBVT_OK;
 }
 
@@ -928,118 +964,43 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   }
   if ((st = hip_check(hipGetLastError(), "prep launch"))) return st;
   if ((st = scan_i64(c, c->cnt.as<int64_t>(), c->pair_off.as<int64_t>(), 3 * n_t, s))) return st;
-  if ((st = check_flags(c, s))) return st;
+  // read-back 1: pair count and status flags
   int64_t n_pairs = 0;
-  if ((st = read_back(c, &n_pairs, c->pair_off.as<int64_t>() + 3 * n_t, sizeof(int64_t), s)))
-    return st;
-  if (n_pairs >= (int64_t(1) << 40))
-    return set_error(IBVT_E_CAPACITY, "too many (tet, cell) pairs");
+  {
+    const int64_t* src[1] = {c->pair_off.as<int64_t>() + 3 * n_t};
+    if ((st = read_counts(c, src, 1, &n_pairs, s))) return st;
+  }
+  if ((st = flags_status(c->host_flags))) return st;
+  if (n_pairs >= (int64_t(1) << 31) - 1)
+    return set_error(IBVT_E_CAPACITY, "2^31 or more (tet, cell) pairs");
   c->n_pairs = n_pairs;
   if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
   if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 32 * sizeof(T)))) return st;
-  c->mom_valid = false;
   if ((st = ensure(c, c->pmom, size_t(n_pairs + 1) * kMomPad * sizeof(T)))) return st;
+  if ((st = ensure(c, c->pinfo, size_t(n_pairs + 1) * sizeof(uint64_t)))) return st;
+  if ((st = ensure(c, c->order, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   k_owner<<<blocks_for(3 * n_t, 256), 256, 0, s>>>(3 * n_t, c->pair_off.as<int64_t>(),
                                                    c->owner.as<int32_t>());
-  // piece store: the fan sub-tetrahedra of every kept piece (integrated
-  // below, and again by the reverse mode)
-  if ((st = ensure(c, c->pinfo, size_t(n_pairs + 1) * sizeof(uint64_t)))) return st;
-  // pair lists ordered by (cut class, straddled-plane pattern)
-  if (n_pairs >= (int64_t(1) << 31) - 1)
-    return set_error(IBVT_E_CAPACITY, "2^31 or more (tet, cell) pairs");
-  if ((st = ensure(c, c->order, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
-  int64_t class_count[3] = {0, 0, 0};
+  // pair order by (cut class, straddled-plane pattern), stable: a counting
+  // sort on the 8-bit keys (sort.hip); the class boundaries stay on the
+  // device and the clip launches read them there
+  const int64_t* cls_start = nullptr;
+  int64_t ntiles = 0;
   if (n_pairs > 0) {
     ProfScope ps("pair_order", s);
-    size_t temp_bytes = 0;
-    if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(
-                            nullptr, temp_bytes, static_cast<const uint8_t*>(nullptr),
-                            static_cast<uint8_t*>(nullptr), static_cast<const int32_t*>(nullptr),
-                            static_cast<int32_t*>(nullptr), int(n_pairs), 0, 8, s),
-                        "sort size")))
-      return st;
     const size_t kb = (size_t(n_pairs + 1) + 255) & ~size_t(255);
-    const size_t ib = (size_t(n_pairs + 1) * sizeof(int32_t) + 255) & ~size_t(255);
-    if ((st = ensure(c, c->pscan, 2 * kb + ib + temp_bytes + 256))) return st;
+    if ((st = ensure(c, c->pscan, kb + sort_pass_bytes(n_pairs, 8)))) return st;
     uint8_t* keys = c->pscan.as<uint8_t>();
-    uint8_t* skeys = keys + kb;
-    int32_t* idx = reinterpret_cast<int32_t*>(c->pscan.as<char>() + 2 * kb);
-    void* temp = c->pscan.as<char>() + 2 * kb + ib;
-    auto* cc = counters + kCntClass;
+    void* scratch = c->pscan.as<char>() + kb;
     k_pair_key<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
-        n_pairs, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), keys,
-        idx);
-    if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, idx,
-                                                           c->order.as<int32_t>(), int(n_pairs), 0,
-                                                           8, s),
-                        "pair sort")))
-      return st;
-    k_class_bounds<<<1, 64, 0, s>>>(n_pairs, skeys, cc);
-    unsigned long long h[3];
-    if ((st = read_back(c, h, cc, sizeof(h), s))) return st;
-    for (int k = 0; k < 3; ++k) class_count[k] = int64_t(h[k]);
+        n_pairs, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), keys);
+    if ((st = hip_check(hipGetLastError(), "pair key launch"))) return st;
+    if ((st = order_by_byte_key(c, n_pairs, keys, c->order.as<int32_t>(), scratch, s))) return st;
+    cls_start = sort_digit_starts(scratch, n_pairs, 8);
+    ntiles = sort_tiles(n_pairs);
   }
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    const int64_t want = std::max<int64_t>(int64_t(3.25 * double(n_pairs)) + 1024,
-                                           c->pool_needed + c->pool_needed / 32 + 1024);
-    if (int64_t(c->pool.cap / (kRecord * sizeof(T))) < want &&
-        (st = ensure(c, c->pool, size_t(want) * kRecord * sizeof(T))))
-      return st;
-    c->pool_cap = int64_t(c->pool.cap / (kRecord * sizeof(T)));
-    // clear pieces/dropped and subtets/store counters (zero-tet count stays)
-    if ((st = hip_check(hipMemsetAsync(counters + kCntPieces, 0, 2 * sizeof(unsigned long long), s),
-                        "memset")) ||
-        (st = hip_check(hipMemsetAsync(counters + kCntSubtets, 0, 2 * sizeof(unsigned long long), s),
-                        "memset")))
-      return st;
-    // (II) clip every pair, grouped by the number of planes it can be cut by
-    // (fewer vertex slots per lane, more resident waves)
-    {
-      ProfScope ps("clip", s);
-      int64_t first = 0;
-      for (int k = 0; k < 3; ++k) {
-        const int64_t n_k = class_count[k];
-        if (n_k > 0) {
-          const int resident =
-              k == 0 ? resident_blocks(k_clip<T, 10>)
-                     : (k == 1 ? resident_blocks(k_clip<T, 12>) : resident_blocks(k_clip<T, kMaxV>));
-          const int64_t nb = std::min<int64_t>(ceil_div(n_k, kWave), resident);
-          const int32_t* ord = c->order.as<int32_t>() + first;
-          // chunk ~ 1/8 of a wave's expected records (about 3 per pair),
-          // so the unused chunk tails stay a few percent of the store
-          const int chunk =
-              int(std::min<int64_t>(2048, (3 * n_k) / (8 * nb)));
-#define IBVT_CLIP_ARGS                                                                          \
-  n_k, ord, n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),     \
-      c->tetrec.as<double>(), c->lat.as<double>(), c->ld, 1e-14, c->pool.as<T>(), c->pool_cap,   \
-      c->pinfo.as<uint64_t>(), chunk, flags, counters
-          if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-          else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-          else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-#undef IBVT_CLIP_ARGS
-        }
-        first += n_k;
-      }
-    }
-    if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
-    unsigned long long used = 0;
-    if ((st = read_back(c, &used, counters + kCntPool, sizeof(used), s))) return st;
-    c->pool_needed = int64_t(used);
-    if (c->pool_needed <= c->pool_cap) break;
-    if (attempt == 1) return set_error(IBVT_E_CAPACITY, "piece store could not be sized");
-  }
-  // (III) integrate every stored sub-tetrahedron, summed per pair
-  if (n_pairs > 0) {
-    ProfScope ps("integrate", s);
-    k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
-        n_pairs, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(), c->owner.as<int32_t>(),
-        c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), c->tetrec.as<double>(),
-        c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>(),
-        c->dual ? 1 : 0);
-  }
-  if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
-  // (IV) global assembly: rows of B^d
+  // (IV, set-up) each row's node box: from the cell ranges alone
   if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
   if ((st = ensure(c, c->rowcap, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->rowtmpoff, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
@@ -1051,8 +1012,66 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   }
   if ((st = scan_i64(c, c->rowcap.as<int64_t>(), c->rowtmpoff.as<int64_t>(), 3 * n_v, s))) return st;
   int64_t tmp_total = 0;
-  if ((st = read_back(c, &tmp_total, c->rowtmpoff.as<int64_t>() + 3 * n_v, sizeof(int64_t), s)))
-    return st;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const int64_t want = std::max<int64_t>(int64_t(3.25 * double(n_pairs)) + 1024,
+                                           c->pool_needed + c->pool_needed / 32 + 1024);
+    if (int64_t(c->pool.cap / (kRecord * sizeof(T))) < want &&
+        (st = ensure(c, c->pool, size_t(want) * kRecord * sizeof(T))))
+      return st;
+    c->pool_cap = int64_t(c->pool.cap / (kRecord * sizeof(T)));
+    // clear the clip's counters (the zero-tet count of the preparation stays)
+    for (int k : {int(kCntPieces), int(kCntDropped), int(kCntSubtets), int(kCntPoolUsed),
+                  int(kCntDist), int(kCntCutPts), int(kCntPlanes)})
+      if ((st = hip_check(hipMemsetAsync(counters + k, 0, sizeof(unsigned long long), s),
+                          "memset")))
+        return st;
+    if (n_pairs > 0) {
+      // (II) clip every pair, one launch per cut class (fewer vertex slots
+      // per lane, more resident waves); each launch reads its class's
+      // stretch of the order from the sort's digit starts
+      ProfScope ps("clip", s);
+      for (int k = 0; k < 3; ++k) {
+        const int resident =
+            k == 0 ? resident_blocks(k_clip<T, 10>)
+                   : (k == 1 ? resident_blocks(k_clip<T, 12>) : resident_blocks(k_clip<T, kMaxV>));
+        const int64_t nb = std::min<int64_t>(ceil_div(n_pairs, kWave), resident);
+#define IBVT_CLIP_ARGS                                                                         \
+  cls_start + 64 * k * ntiles, cls_start + 64 * (k + 1) * ntiles, c->order.as<int32_t>(), n_t, \
+      c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),               \
+      c->tetrec.as<double>(), c->lat.as<double>(), c->ld, 1e-14, c->pool.as<T>(), c->pool_cap,  \
+      c->pinfo.as<uint64_t>(), flags, counters
+        if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+        else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+        else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+#undef IBVT_CLIP_ARGS
+      }
+    }
+    if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
+    // (III) integrate every stored sub-tetrahedron, summed per pair (pairs
+    // whose records did not fit the store read as empty)
+    if (n_pairs > 0) {
+      ProfScope ps("integrate", s);
+      k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
+          n_pairs, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(), c->owner.as<int32_t>(),
+          c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), c->tetrec.as<double>(),
+          c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>(),
+          c->dual ? 1 : 0);
+    }
+    if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
+    // read-back 2: records the clip asked for, the row scratch size, flags
+    int64_t rb2[2] = {0, 0};
+    {
+      const int64_t* src[2] = {reinterpret_cast<const int64_t*>(counters + kCntPoolUsed),
+                               c->rowtmpoff.as<int64_t>() + 3 * n_v};
+      if ((st = read_counts(c, src, 2, rb2, s))) return st;
+    }
+    if ((st = flags_status(c->host_flags))) return st;
+    c->pool_needed = rb2[0];
+    tmp_total = rb2[1];
+    if (c->pool_needed <= c->pool_cap) break;
+    if (attempt == 1) return set_error(IBVT_E_CAPACITY, "piece store could not be sized");
+  }
+  // (IV) global assembly: rows of B^d
   if ((st = ensure(c, c->rowtmpcol, size_t(tmp_total + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->rowtmpval, size_t(tmp_total + 1) * sizeof(T)))) return st;
   {
@@ -1070,11 +1089,16 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     if ((st = scan_i64(c, c->rownnz.as<int64_t>() + d * n_v, c->B[d].rowptr.as<int64_t>(), n_v, s)))
       return st;
   }
-  if ((st = check_flags(c, s))) return st;
+  // read-back 3: nonzeros of the three components, flags
+  int64_t nnzs[3] = {0, 0, 0};
+  {
+    const int64_t* src[3] = {c->B[0].rowptr.as<int64_t>() + n_v, c->B[1].rowptr.as<int64_t>() + n_v,
+                             c->B[2].rowptr.as<int64_t>() + n_v};
+    if ((st = read_counts(c, src, 3, nnzs, s))) return st;
+  }
+  if ((st = flags_status(c->host_flags))) return st;
   for (int d = 0; d < 3; ++d) {
-    int64_t nnz = 0;
-    if ((st = read_back(c, &nnz, c->B[d].rowptr.as<int64_t>() + n_v, sizeof(int64_t), s)))
-      return st;
+    const int64_t nnz = nnzs[d];
     c->B[d].nnz = nnz;
     if (nnz >= (int64_t(1) << 31) - 1)
       return set_error(IBVT_E_CAPACITY, "more than 2^31 nonzeros in one component of B");
@@ -1096,25 +1120,32 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   }
   // masses
   if ((st = solid_masses(c, s))) return st;
-  unsigned long long cnt[kCntSlots];
-  if ((st = read_back(c, cnt, counters, sizeof(cnt), s))) return st;
+  // read-back 4: the counters of the assembly, flags
+  int64_t cnt[kCntSlots];
+  {
+    const int64_t* src[kCntSlots];
+    for (int k = 0; k < kCntSlots; ++k) src[k] = reinterpret_cast<const int64_t*>(counters + k);
+    if ((st = read_counts(c, src, kCntSlots, cnt, s))) return st;
+  }
   c->stats.pairs = n_pairs;
-  c->stats.pieces = int64_t(cnt[kCntPieces]);
-  c->stats.dropped = int64_t(cnt[kCntDropped]);
-  c->stats.zero_tets = int64_t(cnt[kCntZeroTets]);
-  c->stats.subtets = int64_t(cnt[kCntSubtets]);
-  c->stats.dist_evals = int64_t(cnt[kCntDist]);
-  c->stats.cut_points = int64_t(cnt[kCntCutPts]);
+  c->stats.pieces = cnt[kCntPieces];
+  c->stats.dropped = cnt[kCntDropped];
+  c->stats.zero_tets = cnt[kCntZeroTets];
+  c->stats.subtets = cnt[kCntSubtets];
+  c->stats.dist_evals = cnt[kCntDist];
+  c->stats.cut_points = cnt[kCntCutPts];
+  c->stats.plane_cuts = cnt[kCntPlanes];
+  c->stats.assemblies += 1;
+  if ((st = flags_status(c->host_flags))) return st;
   c->mom_valid = c->store_pieces;
   if (!c->store_pieces) {
     // memory-saving mode: no piece store kept; the reverse mode clips again
-    if ((st = hip_check(hipStreamSynchronize(s), "sync"))) return st;
+    // (the stream is idle after the read-back)
     release(c, c->pool);
     release(c, c->pmom);
     c->pool_cap = 0;
   }
-  c->stats.assemblies += 1;
-  return check_flags(c, s);
+  return IBVT_OK;
 }
 
 }  // namespace

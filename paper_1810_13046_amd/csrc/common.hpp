@@ -22,12 +22,13 @@ enum Counter : int {
   kCntDropped = 1,
   kCntZeroTets = 2,
   kCntSubtets = 3,
-  kCntPool = 4,
+  kCntPoolUsed = 4,  // piece-store records the clip asked for
   kCntClass = 5,  // 5, 6, 7: pairs per cut class
   kCntDist = 8,   // signed distances evaluated by the clip
   kCntCutPts = 9, // cut points made by the clip
   kCntRowOverflow = 10,  // rows too wide for the LDS row gather (unstructured)
-  kCntSlots = 11,
+  kCntPlanes = 11,  // (pair, cell plane) clips run by the clip
+  kCntSlots = 12,
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -344,6 +344,7 @@ int fsi_step(ibvt_coupling* c, const ibvt_fsi_config* cfg, const ibvt_fsi_buffer
              hipStream_t stream, ibvt_fsi_report* report) {
   if (report) *report = ibvt_fsi_report{};
   if (!c || !cfg || !buf || !solid || !fluid) return set_error(IBVT_E_INVALID, "NULL argument");
+  c->stream = stream;
   if (!buf->X_ref || !buf->u_hat0 || !buf->u_hat || !buf->w_s || !buf->f_fsi || !buf->f_prev)
     return set_error(IBVT_E_INVALID, "NULL solid buffer");
   for (int d = 0; d < c->ncomp; ++d)

@@ -89,9 +89,10 @@ __host__ __device__ inline uint32_t poly_init_tet(const PolyView& P, const doubl
   return 0xFu;
 }
 
-// Work counts of the clip (for throughput figures): signed distances
-// evaluated and cut points made.
+// Work counts of the clip (for throughput figures): planes clipped by,
+// signed distances evaluated and cut points made.
 struct ClipCount {
+  uint32_t planes = 0;
   uint32_t dist = 0;
   uint32_t cuts = 0;
 };
@@ -107,7 +108,10 @@ template <int NS, typename Dist, typename Place>
 __host__ __device__ __forceinline__ bool poly_clip_by(const PolyView& P, uint32_t& live,
                                                       Dist&& dist, Place&& place,
                                                       ClipCount* cc) {
-  if (cc) cc->dist += uint32_t(__builtin_popcount(live));
+  if (cc) {
+    cc->planes += 1;
+    cc->dist += uint32_t(__builtin_popcount(live));
+  }
   uint32_t out = 0;
 #pragma unroll
   for (int v = 0; v < NS; ++v) {

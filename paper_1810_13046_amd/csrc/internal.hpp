@@ -64,12 +64,14 @@ __device__ __forceinline__ void pair_cell(int64_t p, int64_t n_t, const int32_t*
 struct AsmStats {
   int64_t pairs = 0, pieces = 0, dropped = 0, zero_tets = 0, subtets = 0;
   int64_t dist_evals = 0, cut_points = 0;  // clip work of the last assembly
+  int64_t plane_cuts = 0;                  // (pair, cell plane) clips it ran
   int64_t assemblies = 0;
 };
 
 }  // namespace ibvt
 
 struct ibvt_coupling {
+  hipStream_t stream = nullptr;  // stream of the current call: buffers grow and shrink on it
   int precision = IBVT_FP64;
   uint32_t flags = 0;
   int dim = 3;    // 3: tetrahedra in a 3D grid; 2: triangles in a planar grid
@@ -140,7 +142,9 @@ struct ibvt_coupling {
   ibvt::DevBuf work;         // transfer scratch (mass-solve vectors etc.)
   ibvt::DevBuf work2;        // shape-gradient per-pair scratch / mass-solve right-hand side
   ibvt::DevBuf zbuf;         // solid-sized scratch of the reverse-mode calls
-  ibvt::DevBuf host_pinned;  // small pinned host buffer for read-backs
+  int64_t* host_rb = nullptr;  // pinned host block of the packed read-backs (hipHostMalloc)
+  ibvt::DevBuf rb;           // device block gathered for one read-back
+  unsigned host_flags = 0;   // status flags of the last packed read-back
   ibvt::AsmStats stats;
   int64_t device_bytes = 0;
 };
@@ -170,6 +174,11 @@ int build_topology(ibvt_coupling* c, hipStream_t s);  // dim + 1 vertices per el
 int assemble_all(ibvt_coupling* c, hipStream_t s);    // dispatches on dim
 int read_back(ibvt_coupling* c, void* host, const void* dev, size_t bytes, hipStream_t s);
 int check_flags(ibvt_coupling* c, hipStream_t s);
+// One stream synchronisation for several device counts: out[k] = *srcs[k]
+// (n <= 16 int64 values) and the status flag word into c->host_flags.
+int read_counts(ibvt_coupling* c, const int64_t* const* srcs, int n, int64_t* out, hipStream_t s);
+// Status of a flag word (IBVT_OK when no flag is set).
+int flags_status(unsigned f);
 // lumped (and, when built, consistent) mass of the solid tets from tetvol
 int solid_masses(ibvt_coupling* c, hipStream_t s);
 
@@ -197,6 +206,35 @@ int shape_gradient_2d(ibvt_coupling* c, const void* z, const void* const u[3], c
 // transpose.hip
 template <typename T>
 int transpose_one(ibvt_coupling* c, int d, hipStream_t s);
+
+// sort.hip: stable sorts by small integer keys (digit passes of at most
+// kMaxDigitBits bits; n < 2^31).
+constexpr int kMaxDigitBits = 11;
+// A nonzero carried through the transpose's sort: its value and its row.
+struct SortVal32 {
+  float v;
+  int32_t r;
+};
+struct SortVal64 {
+  double v;
+  int32_t r;
+};
+int64_t sort_tiles(int64_t n);
+// scratch bytes of one digit pass over n items with 2^bits digits
+size_t sort_pass_bytes(int64_t n, int bits);
+// after a pass with 2^bits digits over n items: the first output position
+// of digit k is at [k * sort_tiles(n)] of this array (device); entry
+// 2^bits * sort_tiles(n) holds n
+const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits);
+// order = the indices 0..n-1 stably sorted by their 8-bit keys
+int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
+                      void* scratch, hipStream_t s);
+// stable sort of (keys, vals) by keys < 2^end_bit (end_bit <= 2 kMaxDigitBits)
+// in two digit passes through (keys_tmp, vals_tmp); the result is in
+// (keys, vals).
+template <typename V>
+int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals,
+                   int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s);
 
 // apply.hip
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s);

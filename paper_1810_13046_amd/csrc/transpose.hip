@@ -172,11 +172,10 @@ int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
     k_mark<<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, B.col.as<int32_t>(), c->mark.as<int32_t>());
   if ((st = scan_i32_to_i64(c, c->mark.as<int32_t>(), c->cidx.as<int64_t>(), nf, s))) return st;
   int64_t touched = 0;
-  if ((st = hip_check(hipMemcpyAsync(&touched, c->cidx.as<int64_t>() + nf, sizeof(int64_t),
-                                     hipMemcpyDeviceToHost, s),
-                      "read touched")))
-    return st;
-  if ((st = hip_check(hipStreamSynchronize(s), "sync"))) return st;
+  {
+    const int64_t* src[1] = {c->cidx.as<int64_t>() + nf};
+    if ((st = read_counts(c, src, 1, &touched, s))) return st;
+  }
   Bt.nrows = touched;
   Bt.nnz = B.nnz;
   if ((st = ensure(c, Bt.rowptr, size_t(touched + 1) * sizeof(int64_t)))) return st;

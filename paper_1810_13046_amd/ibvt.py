@@ -81,7 +81,7 @@ class _Info(ctypes.Structure):
                 ("assemblies", ctypes.c_int64), ("subtets", ctypes.c_int64),
                 ("piece_store", ctypes.c_int64), ("dist_evals", ctypes.c_int64),
                 ("cut_points", ctypes.c_int64), ("dual", ctypes.c_int64), ("dim", ctypes.c_int64),
-                ("unstructured", ctypes.c_int64)]
+                ("unstructured", ctypes.c_int64), ("plane_cuts", ctypes.c_int64)]
 
 
 _lib = None
@@ -535,7 +535,7 @@ class Coupling:
                     nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies,
                     subtets=i.subtets, piece_store=bool(i.piece_store),
                     dist_evals=i.dist_evals, cut_points=i.cut_points, dual=bool(i.dual),
-                    dim=i.dim, unstructured=bool(i.unstructured))
+                    dim=i.dim, unstructured=bool(i.unstructured), plane_cuts=i.plane_cuts)
 
     def export_csr(self, comp: int, transposed: bool = False):
         """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""
