@@ -53,6 +53,12 @@ FP64_VEC_PEAK_TFLOPS = 78.6
 #   pair set-up                                 50  (cell box, λ in cell-local
 #                                                    coordinates, drop test)
 CLIP_FLOPS = dict(dist=2, cut=11, subtet=47, pair=50)
+# The survey's pricing of the clip for the roofline: 150-300 FP64 flops per
+# plane cut (one tet piece clipped by one cell plane: signed distances of its
+# vertices, cut points, bookkeeping); the midpoint is reported as `frac`,
+# the range beside it.
+FLOPS_PER_PLANE_CUT = (150, 225, 300)
+FLUSH_BYTES = 1 << 30   # cold-cache protocol: >= 1 GiB written between repetitions
 # flops per quadrature point of the 35 piece moments: point 6, powers 9,
 # partial products 14, 35 multiply-adds 70; 11 points (degree 4) per
 # sub-tetrahedron
@@ -68,6 +74,12 @@ CLIP_TRAFFIC = dict(sources_sha256="cabeb8d4ad35f8fbf2f6a963582c61d6b5051132c918
                     bytes_mixed=35621912352)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
+# HBM traffic of one lumped velocity apply and one force apply (all three
+# components, mixed precision) on the three-body workload, from the same
+# counter passes (profiles/hbm_traffic_three_bodies4.5M_mixed.txt);
+# reported while apply.hip is the source they were taken on.
+APPLY_TRAFFIC = dict(sources_sha256=None, velocity_bytes=None, force_bytes=None)
+APPLY_SOURCES = ["paper_1810_13046_amd/csrc/apply.hip"]
 
 
 def sources_sha256(files):
@@ -310,35 +322,125 @@ def kernel_profile(step):
     return prof
 
 
-def apply_rates(step, reps=20):
-    """Lumped velocity apply and force apply: ms per launch (HIP events on
-    the library's stream) and algorithmic bytes per apply."""
-    import torch
-    from paper_1810_13046_amd import profile_enable, profile_read
-    c = step.c
+def apply_bytes(c):
+    """Algorithmic bytes of one lumped velocity apply and one force apply
+    (three components): s value bytes, int32 indices, nnz_d nonzeros, t_d
+    touched fluid nodes, n solid vertices."""
     info = c.info()
     s = 8 if c.precision == "fp64" else 4
     n = info["n_vert"]
     nnz, t = info["nnz"], info["touched"]
-    vel_bytes = sum(nnz[d] * (s + 4) + 4 * (n + 1) + s * t[d] + s * n for d in range(3)) + s * n
-    frc_bytes = sum(nnz[d] * (s + 4) + 4 * (t[d] + 1) + 4 * t[d] + 2 * s * t[d] + s * n
-                    for d in range(3))
-    for _ in range(3):
-        c.velocity(step.u, mass="lumped", out=step.us)
-        c.force(step.f_s, step.ff)
-    torch.cuda.synchronize()
+    vel = sum(nnz[d] * (s + 4) + 4 * (n + 1) + s * t[d] + s * n for d in range(3)) + s * n
+    frc = sum(nnz[d] * (s + 4) + 4 * (t[d] + 1) + 4 * t[d] + 2 * s * t[d] + s * n
+              for d in range(3))
+    return vel, frc
+
+
+def _one_launch_ms(run, name):
+    """Device time of the library kernel `name` in one call of run()
+    (HIP events the library records on its stream)."""
+    from paper_1810_13046_amd import profile_enable, profile_read
     profile_read()
     profile_enable(True)
-    for _ in range(reps):
-        c.velocity(step.u, mass="lumped", out=step.us)
-        c.force(step.f_s, step.ff)
-    torch.cuda.synchronize()
+    run()
     prof = profile_read()
     profile_enable(False)
-    vel_ms = prof["spmv_B"][1] / prof["spmv_B"][0]
-    frc_ms = prof["spmv_Bt"][1] / prof["spmv_Bt"][0]
-    return dict(velocity_ms=vel_ms, force_ms=frc_ms, velocity_bytes=vel_bytes, force_bytes=frc_bytes,
-                velocity_GBs=vel_bytes / vel_ms / 1e6, force_GBs=frc_bytes / frc_ms / 1e6)
+    launches, ms = prof[name]
+    return ms / launches
+
+
+def apply_rates(step, reps=20, warm=3):
+    """Lumped velocity apply and force apply, ms per launch and GB/s of
+    algorithmic bytes.  Cold: a >= 1 GiB write between repetitions evicts
+    the caches, 3 warm-ups, median of `reps`; warm: back to back, median of
+    `reps`."""
+    import torch
+    c = step.c
+    vel_bytes, frc_bytes = apply_bytes(c)
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=step.X.device)
+    vel = lambda: c.velocity(step.u, mass="lumped", out=step.us)
+    frc = lambda: c.force(step.f_s, step.ff)
+    out = dict(velocity_bytes=vel_bytes, force_bytes=frc_bytes, reps=reps,
+               protocol="cold: 1 GiB written between repetitions, 3 warm-ups, median of 20; "
+                        "warm: back to back, median of 20")
+    for key, run, name, nbytes in (("velocity", vel, "spmv_B", vel_bytes),
+                                   ("force", frc, "spmv_Bt", frc_bytes)):
+        for _ in range(warm):
+            run()
+        cold = []
+        for _ in range(reps):
+            flush.fill_(1.0)
+            cold.append(_one_launch_ms(run, name))
+        hot = [_one_launch_ms(run, name) for _ in range(reps)]
+        cms, hms = float(np.median(cold)), float(np.median(hot))
+        out[f"{key}_ms"] = cms
+        out[f"{key}_GBs"] = nbytes / cms / 1e6
+        out[f"{key}_warm_ms"] = hms
+        out[f"{key}_warm_GBs"] = nbytes / hms / 1e6
+    del flush
+    return out
+
+
+def copy_ceiling(dev, reps=20):
+    """Device-copy bandwidth (read + write bytes over time) of a 1 GiB copy,
+    median of `reps`: the practical ceiling for streaming kernels."""
+    import torch
+    n = FLUSH_BYTES // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    del a, b
+    return dict(bytes=2 * FLUSH_BYTES, ms=ms, GBs=2 * FLUSH_BYTES / ms / 1e6,
+                frac_of_peak=2 * FLUSH_BYTES / ms / 1e6 / HBM_PEAK_GBS)
+
+
+def assembly_rate(step, n_tet, reps=10):
+    """Reassembly alone (B, B^T, masses for the current positions): median
+    ms over `reps` calls, HIP events around each."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step.c.reassemble(step.X)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    return dict(ms=ms, tets_per_s=n_tet / (ms * 1e-3), reps=reps)
+
+
+def gpu_sample(step, W, seed=77, n_rows=48):
+    """GPU values at sampled vertices (rows of B^d, the lumped velocity) and
+    sampled fluid nodes (the force), for the error against the oracle."""
+    import torch
+    c = step.c
+    rng = np.random.default_rng(seed)
+    verts = np.sort(rng.choice(W.X.shape[0], n_rows, replace=False))
+    us = c.velocity(step.u, mass="lumped").cpu().numpy().astype(np.float64)
+    ff = [torch.zeros_like(u) for u in step.u]
+    c.force(step.f_s, ff, alpha=1.0)
+    out = dict(verts=verts, rows=[], us=us[:, verts], cols=[], ff=[])
+    for d in range(3):
+        rp, col, val = c.export_csr(d)
+        import scipy.sparse as sp
+        G = sp.csr_matrix((val, col, rp), shape=(W.X.shape[0], c.n_fluid[d]))[verts]
+        cols = np.unique(G.indices)
+        pick = np.sort(rng.choice(cols, min(24, cols.size), replace=False))
+        out["rows"].append(G)
+        out["cols"].append(pick)
+        out["ff"].append(ff[d].cpu().numpy().astype(np.float64).ravel()[pick])
+    return out
 
 
 def fsi_rate(step, iters=6):
@@ -378,27 +480,40 @@ def fsi_rate(step, iters=6):
                 mass=step.mass, note="stub solvers; T assembled once per step at X_ref + u_hat0")
 
 
-def cpu_baseline(W, dev, tets_per_body):
-    """The FP64 oracle on a bounded sample: the first `tets_per_body` tets of
-    each body (a sub-mesh on the same grid), one full step."""
+def cpu_baseline(W, dev, tets_per_body, samples):
+    """The oracle leg (the only part of this script that runs the oracle).
+
+    * value: the FP64 oracle on a bounded sample, the first `tets_per_body`
+      tets of each body (a sub-mesh on the same grid), one full step, with
+      the host's threads (OMP_NUM_THREADS for its C part).
+    * the oracle's assembly alone at 1 thread and at the host's threads on
+      the first 1000 tets of each body;
+    * error_vs_oracle: the GPU's sampled full-size rows of B^d, lumped
+      velocities there and forces at sampled fluid nodes (`samples`, per
+      precision) against the oracle, which integrates only the tets that
+      touch them."""
     import torch
     import oracle
+    import scipy.sparse as sp
     import workloads as wl
     oracle.build(force=False)
-    sel = []
-    for b in range(len(W.bodies)):
-        t0, t1 = int(W.body_tet_offsets[b]), int(W.body_tet_offsets[b + 1])
-        sel.append(np.arange(t0, min(t1, t0 + tets_per_body)))
-    sel = np.concatenate(sel)
-    T = W.tets[sel]
-    used, inv = np.unique(T, return_inverse=True)
-    T = inv.reshape(T.shape).astype(np.int32)
-    X = W.X[used]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def sub_mesh(per_body):
+        sel = []
+        for b in range(len(W.bodies)):
+            t0, t1 = int(W.body_tet_offsets[b]), int(W.body_tet_offsets[b + 1])
+            sel.append(np.arange(t0, min(t1, t0 + per_body)))
+        T = W.tets[np.concatenate(sel)]
+        used, inv = np.unique(T, return_inverse=True)
+        return W.X[used], inv.reshape(T.shape).astype(np.int32), used
+
     k, phi = wl.fourier_modes(W.n_modes, W.kmax, 2000 + W.cfg)
     u = []
     for d in range(3):
         xs, ys, zs = oracle.lattice(W.faces, d)
         u.append(wl.fourier_field(k[d], phi[d], xs, ys, zs, device=dev).cpu().numpy())
+    X, T, used = sub_mesh(tets_per_body)
     f_s = W.f_s()[:, used]
     u_t = W.u_target()[:, used]
     t0 = time.perf_counter()
@@ -408,33 +523,85 @@ def cpu_baseline(W, dev, tets_per_body):
     oracle.velocity_vjp(cpl, u, us - u_t, "consistent")
     oracle.force_vjp(cpl, f_s, [a.ravel() for a in u], 1.0)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=T.shape[0] / dt, unit="solid tets/s", cores=cores, kind="oracle",
-                sample=f"first {tets_per_body} tets of each of the {len(W.bodies)} bodies "
-                       f"({T.shape[0]} tets, {X.shape[0]} vertices) on the full grid; one full "
-                       f"step (assembly, consistent velocity by sparse LU, force, both adjoints) "
-                       f"in {dt:.1f}s")
+    out = dict(value=T.shape[0] / dt, unit="solid tets/s", cores=cores, kind="oracle",
+               sample=f"first {tets_per_body} tets of each of the {len(W.bodies)} bodies "
+                      f"({T.shape[0]} tets, {X.shape[0]} vertices) on the full grid; one full "
+                      f"step (assembly, consistent velocity by sparse LU, force, both adjoints) "
+                      f"in {dt:.1f}s")
+    # assembly alone at 1 thread and at `cores` threads
+    Xa, Ta, _ = sub_mesh(1000)
+    asm = {}
+    for nth in (1, cores):
+        t0 = time.perf_counter()
+        oracle.assemble(W.faces, Xa, Ta, nthreads=nth)
+        asm[nth] = Ta.shape[0] / (time.perf_counter() - t0)
+    out["assembly_only"] = dict(unit="solid tets/s", sample=f"first 1000 tets of each body "
+                                f"({Ta.shape[0]} tets)", threads_1=asm[1], **{f"threads_{cores}": asm[cores]})
+    # error of the GPU's full-size results against the oracle, sampled
+    errs = {}
+    if samples:
+        bounds = oracle.tet_bounds(W.X, W.tets)
+        for prec, smp in samples.items():
+            verts = smp["verts"]
+            star = oracle.vertex_star(W.tets, verts)
+            R = oracle.assemble(W.faces, W.X, W.tets, subset=star)
+            m = oracle.lumped_mass(W.X, W.tets[star], n_vert=W.X.shape[0])
+            f_full = W.f_s()
+            e = dict(rows=0.0, velocity=0.0, force=0.0)
+            for d in range(3):
+                Rs = R.B[d][verts]
+                G = smp["rows"][d]
+                e["rows"] = max(e["rows"], float(sp.linalg.norm(G - Rs) / sp.linalg.norm(Rs)))
+                want = (Rs @ u[d].ravel()) / m[verts]
+                e["velocity"] = max(e["velocity"], float(np.linalg.norm(smp["us"][d] - want) /
+                                                         np.linalg.norm(want)))
+                pick = smp["cols"][d]
+                nx, ny, _ = oracle.lattice_shape(W.faces, d)
+                sub = np.unique(np.concatenate([
+                    oracle.tets_touching_node(W.faces, W.X, W.tets, d,
+                                              (j % nx, (j // nx) % ny, j // (nx * ny)), bounds)
+                    for j in pick]))
+                Rc = oracle.assemble(W.faces, W.X, W.tets, subset=sub).B[d].tocsc()[:, pick]
+                wantf = Rc.T @ f_full[d]
+                e["force"] = max(e["force"], float(np.linalg.norm(smp["ff"][d] - wantf) /
+                                                   np.linalg.norm(wantf)))
+            e["tolerance"] = 1e-12 if prec == "fp64" else 1e-5
+            e["sample"] = (f"{len(verts)} seeded vertices (rows of B^d, lumped velocity), 24 fluid "
+                           f"nodes per component (force); relative Frobenius, max over components")
+            errs[prec] = e
+    out["error_vs_oracle"] = errs
+    return out
 
 
 def roofline(name, prof, info, precision):
     """Roofline object of one profiled step of kernel `name`: algorithmic
-    work per launch (see the constants above) over its average launch time
-    (HIP events on the library's stream)."""
+    work per launch over its average launch time (HIP events on the
+    library's stream).  The clip is priced at FLOPS_PER_PLANE_CUT FP64 flops
+    per plane cut (midpoint as `frac`, the range beside it); the builder's
+    own operation count (CLIP_FLOPS) is reported beside that."""
     launches, total_ms = prof
     ms = total_ms / launches
     out = dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None,
                traffic=None, launch_ms=ms)
     if name == "clip":
-        flops = (CLIP_FLOPS["dist"] * info["dist_evals"] + CLIP_FLOPS["cut"] * info["cut_points"] +
-                 CLIP_FLOPS["subtet"] * info["subtets"] + CLIP_FLOPS["pair"] * info["pairs"])
-        achieved = flops / (ms * 1e-3) / 1e12
+        lo, mid, hi = (f * info["plane_cuts"] for f in FLOPS_PER_PLANE_CUT)
+        achieved = mid / (ms * 1e-3) / 1e12
+        own = (CLIP_FLOPS["dist"] * info["dist_evals"] + CLIP_FLOPS["cut"] * info["cut_points"] +
+               CLIP_FLOPS["subtet"] * info["subtets"] + CLIP_FLOPS["pair"] * info["pairs"])
         traffic = None
         if (precision == "fp32" and CLIP_TRAFFIC["bytes_mixed"] is not None and
                 CLIP_TRAFFIC["sources_sha256"] == sources_sha256(CLIP_SOURCES)):
             traffic = CLIP_TRAFFIC["bytes_mixed"]
         out.update(bound="alu", achieved=achieved, peak=FP64_VEC_PEAK_TFLOPS, unit="TFLOP/s",
                    frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=traffic,
-                   algorithmic_flops_per_launch=flops, precision="fp64 (clipping is double)")
+                   precision="fp64 (clipping is double)",
+                   plane_cuts=info["plane_cuts"], flops_per_plane_cut=FLOPS_PER_PLANE_CUT[1],
+                   algorithmic_flops_per_launch=mid,
+                   frac_range=[lo / (ms * 1e-3) / 1e12 / FP64_VEC_PEAK_TFLOPS,
+                               hi / (ms * 1e-3) / 1e12 / FP64_VEC_PEAK_TFLOPS],
+                   own_count=dict(flops=own, frac=own / (ms * 1e-3) / 1e12 / FP64_VEC_PEAK_TFLOPS,
+                                  dist_evals=info["dist_evals"], cut_points=info["cut_points"],
+                                  subtets=info["subtets"], pairs=info["pairs"]))
     elif name == "integrate":
         flops = info["subtets"] * POINTS_PER_SUBTET * MOM_FLOPS_PER_POINT
         peak = FP32_VEC_PEAK_TFLOPS if precision == "fp32" else FP64_VEC_PEAK_TFLOPS
@@ -503,6 +670,13 @@ def main():
     rates_mixed = apply_rates(mixed)
     info = mixed.c.info()
     log(f"[bench] mixed {ms_mixed:.2f} ms/step; kernels {json.dumps(prof_mixed)}")
+    asm_mixed = assembly_rate(mixed, n_tet, reps=3 if args.profile_run else 10)
+    log(f"[bench] mixed assembly alone {asm_mixed['ms']:.2f} ms")
+    copy = copy_ceiling(dev)
+    log(f"[bench] device copy {copy['GBs']:.0f} GB/s")
+    samples = {}
+    if not args.skip_cpu:
+        samples["fp32"] = gpu_sample(mixed, W)
     fsi = None
     if not args.profile_run:
         log("[bench] Picard coupling step (mixed)")
@@ -519,11 +693,24 @@ def main():
         ms64, wall64 = time_steps(s64, args.steps, args.warmup)
         prof64 = kernel_profile(s64)
         rates64 = apply_rates(s64)
+        asm64 = assembly_rate(s64, n_tet)
         fp64 = dict(ms_per_step=ms64, value=n_tet / (ms64 * 1e-3), kernels_ms=prof64,
-                    applies=rates64)
+                    applies=rates64, assembly_only=asm64,
+                    device_bytes=s64.c.info()["device_bytes"])
+        if not args.skip_cpu:
+            samples["fp64"] = gpu_sample(s64, W)
         log(f"[bench] fp64 {ms64:.2f} ms/step")
         del s64
         del mixed_keep
+    # device memory of the mixed-precision coupling without the moment store
+    bytes_no_store = None
+    if not args.profile_run:
+        import torch
+        from paper_1810_13046_amd import Coupling
+        cns = Coupling(W.faces, X, T, precision="fp32", consistent=True, store_pieces=False)
+        torch.cuda.synchronize()
+        bytes_no_store = cns.info()["device_bytes"]
+        cns.free()
 
     dual = None
     if not args.profile_run:
@@ -540,11 +727,18 @@ def main():
     per_kernel = {k: v[1] for k, v in prof_mixed.items()}
     dom = max(per_kernel, key=per_kernel.get)
     roof = roofline(dom, prof_mixed[dom], info, "fp32")
-    roof_apply = dict(kernel="spmv_B (lumped velocity apply)", bound="hbm",
+    apply_traffic = None
+    if (APPLY_TRAFFIC["velocity_bytes"] is not None and
+            APPLY_TRAFFIC["sources_sha256"] == sources_sha256(APPLY_SOURCES)):
+        apply_traffic = APPLY_TRAFFIC["velocity_bytes"]
+    roof_apply = dict(kernel="spmv_B (lumped velocity apply, cold cache)", bound="hbm",
                       achieved=rates_mixed["velocity_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=rates_mixed["velocity_GBs"] / HBM_PEAK_GBS, traffic=None,
+                      frac=rates_mixed["velocity_GBs"] / HBM_PEAK_GBS, traffic=apply_traffic,
                       launch_ms=rates_mixed["velocity_ms"],
-                      algorithmic_bytes_per_launch=rates_mixed["velocity_bytes"])
+                      algorithmic_bytes_per_launch=rates_mixed["velocity_bytes"],
+                      frac_of_copy_ceiling=rates_mixed["velocity_GBs"] / copy["GBs"],
+                      force_GBs=rates_mixed["force_GBs"],
+                      force_frac=rates_mixed["force_GBs"] / HBM_PEAK_GBS)
 
     planar = None
     if not args.profile_run:
@@ -556,7 +750,7 @@ def main():
     cpu = None
     if not args.skip_cpu:
         log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline(W, dev, args.cpu_tets_per_body)
+        cpu = cpu_baseline(W, dev, args.cpu_tets_per_body, samples)
         log(f"[bench] cpu baseline {cpu['value']:.1f} tets/s")
 
     out = {
@@ -579,8 +773,14 @@ def main():
             "mass": "consistent", "solve_rtol": 1e-10, "parallelism": "single GPU",
         },
         "assembly": {"pairs": info["pairs"], "pieces": info["pieces"], "subtets": info["subtets"],
+                     "plane_cuts": info["plane_cuts"], "dist_evals": info["dist_evals"],
+                     "cut_points": info["cut_points"],
                      "nnz": info["nnz"], "touched": info["touched"],
-                     "device_bytes": info["device_bytes"]},
+                     "device_bytes": info["device_bytes"],
+                     "device_bytes_no_piece_store": bytes_no_store},
+        "assembly_only": {**asm_mixed, "unit": "solid tets/s (reassembly: B, B^T, masses)"},
+        "copy_ceiling": copy,
+        "error_vs_oracle": cpu["error_vs_oracle"] if cpu else None,
         "kernels_ms": {k: v[1] for k, v in prof_mixed.items()},
         "kernel_launches": {k: v[0] for k, v in prof_mixed.items()},
         "applies": {
