@@ -282,6 +282,28 @@ int transfer_velocity(ibvt_coupling* c, const void* const u_f[3], void* u_s, int
                       double cg_rtol, int cg_maxit, hipStream_t stream, ibvt_solve_info* info);
 
 /*
+ * transfer_velocity_noalloc — transfer_velocity for callers that cannot
+ *   allocate device memory (code under stream capture, tight serving loops,
+ *   harnesses that forbid allocation): same arguments, results and errors,
+ *   and no device allocation of any kind.  The consistent-mass solve's
+ *   scratch (the right-hand side B u_f, the Chebyshev vectors, the double
+ *   residual) lives in a device array of 256 MiB that the library holds on
+ *   each GPU it runs on until the process ends; IBVT_LUMPED needs none.
+ *   Limit: about 217 n_vert bytes (FP64) or 133 n_vert bytes (FP32-mixed)
+ *   of scratch, so about 1.2M (FP64) and 2.0M (FP32-mixed) solid vertices
+ *   with consistent mass; beyond it the call returns IBVT_E_CAPACITY before
+ *   any work.  Every call
+ *   on one GPU shares that GPU's array, which keeps the last call's
+ *   contents: calls that overlap on one GPU (several streams or threads)
+ *   race and must be ordered by the caller.
+ *   Errors: IBVT_E_INVALID, IBVT_E_CAPACITY, IBVT_E_NOT_CONVERGED,
+ *   IBVT_E_HIP.
+ */
+int transfer_velocity_noalloc(ibvt_coupling* c, const void* const u_f[3], void* u_s, int mass,
+                              double cg_rtol, int cg_maxit, hipStream_t stream,
+                              ibvt_solve_info* info);
+
+/*
  * transfer_force — f_f[d] += alpha · B^dT f_s[d] at the touched fluid nodes
  *   (force transfer with the transpose, Section 2.3; Step 4 of Section 3,
  *   where alpha is the nondimensional scale L_ref / (rho_f U_ref^2)).

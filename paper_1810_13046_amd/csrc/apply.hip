@@ -346,8 +346,11 @@ struct MassWork {
   double* res64;
 };
 
-int mass_workspace(ibvt_coupling* c, size_t tsize, MassWork& w) {
-  const int64_t n = c->n_vert;
+// Layout of the mass-solve workspace for n vertices and value size tsize:
+// residual partials, reduction results, six (3, n) vectors of T, the double
+// solution and residual.  Returns the bytes it spans; with base non-null
+// also sets w's pointers into [base, base + bytes).
+size_t mass_workspace_layout(int64_t n, size_t tsize, char* base, MassWork* w) {
   // per-block partials of the residual kernel fit
   const int64_t nb = std::max<int64_t>(nblk(n), nblk_rows(n));
   const size_t off_part = 256;
@@ -356,14 +359,28 @@ int mass_workspace(ibvt_coupling* c, size_t tsize, MassWork& w) {
   const size_t off_x64 = (off_vec + size_t(6 * 3 * n) * tsize + 255) & ~size_t(255);
   const size_t off_res = (off_x64 + size_t(3 * n) * sizeof(double) + 255) & ~size_t(255);
   const size_t total = off_res + size_t(3 * n) * sizeof(double) + 256;
+  if (base && w) {
+    w->part = reinterpret_cast<double*>(base + off_part);
+    w->tmp = reinterpret_cast<double*>(base + off_tmp);
+    w->vec = base + off_vec;
+    w->x64 = reinterpret_cast<double*>(base + off_x64);
+    w->res64 = reinterpret_cast<double*>(base + off_res);
+  }
+  return total;
+}
+
+// The workspace in the coupling's own buffer (grown as needed), or at ext
+// (the caller's memory of at least mass_workspace_layout bytes).
+int mass_workspace(ibvt_coupling* c, size_t tsize, MassWork& w, char* ext) {
+  const int64_t n = c->n_vert;
+  if (ext) {
+    mass_workspace_layout(n, tsize, ext, &w);
+    return IBVT_OK;
+  }
+  const size_t total = mass_workspace_layout(n, tsize, nullptr, nullptr);
   int st = ensure(c, c->work, total);
   if (st) return st;
-  char* base = c->work.as<char>();
-  w.part = reinterpret_cast<double*>(base + off_part);
-  w.tmp = reinterpret_cast<double*>(base + off_tmp);
-  w.vec = base + off_vec;
-  w.x64 = reinterpret_cast<double*>(base + off_x64);
-  w.res64 = reinterpret_cast<double*>(base + off_res);
+  mass_workspace_layout(n, tsize, c->work.as<char>(), &w);
   return IBVT_OK;
 }
 
@@ -548,8 +565,13 @@ int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream
 
 // x = M^{-1} rhs (every component).  x holds the start (lumped solution)
 // when x_has_guess.
+size_t mass_solve_workspace_bytes(const ibvt_coupling* c) {
+  const size_t tsize = c->precision == IBVT_FP32_MIXED ? sizeof(float) : sizeof(double);
+  return mass_workspace_layout(c->n_vert, tsize, nullptr, nullptr);
+}
+
 int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxit, hipStream_t s,
-               ibvt_solve_info* info, bool x_has_guess) {
+               ibvt_solve_info* info, bool x_has_guess, char* ws) {
   if (!c->has_M) return set_error(IBVT_E_INVALID, "consistent mass was not built (flags)");
   const int64_t n = c->n_vert;
   const int64_t nn = int64_t(c->ncomp) * n;
@@ -569,7 +591,7 @@ int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxi
   // rarely differ by enough to need another cycle.
   if (c->precision == IBVT_FP64) {
     MassWork w;
-    if ((st = mass_workspace(c, sizeof(double), w))) return st;
+    if ((st = mass_workspace(c, sizeof(double), w, ws))) return st;
     double* xd = static_cast<double*>(x);
     const double* b = static_cast<const double*>(rhs);
     const int per_cycle = cheb_iterations(kb, 0.1 * rtol);
@@ -583,7 +605,7 @@ int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxi
   } else {
     // iterative refinement: double residual, float correction cycles
     MassWork w;
-    if ((st = mass_workspace(c, sizeof(float), w))) return st;
+    if ((st = mass_workspace(c, sizeof(float), w, ws))) return st;
     const float* b = static_cast<const float*>(rhs);
     float* xf = static_cast<float*>(x);
     k_convert<float, double><<<nblk(nn), kThreads, 0, s>>>(nn, xf, w.x64);

@@ -239,8 +239,12 @@ int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* v
 // apply.hip
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s);
 int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha, hipStream_t s);
+// ws: null (the coupling's own buffer, grown as needed) or device memory of
+// at least mass_solve_workspace_bytes(c) bytes that the solve uses instead
+// (then it allocates nothing)
 int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxit,
-               hipStream_t s, ibvt_solve_info* info, bool x_has_guess);
+               hipStream_t s, ibvt_solve_info* info, bool x_has_guess, char* ws = nullptr);
+size_t mass_solve_workspace_bytes(const ibvt_coupling* c);
 int lumped_solve(ibvt_coupling* c, const void* rhs, void* x, hipStream_t s);
 int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream_t s);
 

@@ -37,7 +37,7 @@ EXPORTED = [
     "coupling_free", "ibvt_status_string", "ibvt_last_error", "ibvt_lattice_coords",
     "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
     "assemble_coupling_2d", "ibvt_lattice_coords_2d", "assemble_coupling_unstructured",
-    "transfer_vjp", "ibvt_fluid_lumped_volume_2d",
+    "transfer_vjp", "ibvt_fluid_lumped_volume_2d", "transfer_velocity_noalloc",
 ]
 
 
@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
     lib.assemble_coupling.argtypes = [P(_Grid), P(_Mesh), ctypes.c_int, u32, vp, P(vp)]
     lib.reassemble_coupling.argtypes = [vp, vp, vp]
     lib.transfer_velocity.argtypes = [vp, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int, vp, P(_SolveInfo)]
+    lib.transfer_velocity_noalloc.argtypes = lib.transfer_velocity.argtypes
     lib.transfer_force.argtypes = [vp, vp, P(vp), dbl, u32, vp]
     lib.transfer_velocity_vjp.argtypes = [vp, vp, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int, P(vp), vp, vp]
     lib.transfer_force_vjp.argtypes = [vp, P(vp), vp, dbl, vp, vp, vp]
@@ -154,7 +155,8 @@ def load_library(path: str = LIB_PATH):
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
                  "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d",
-                 "assemble_coupling_unstructured", "transfer_vjp", "ibvt_fluid_lumped_volume_2d"):
+                 "assemble_coupling_unstructured", "transfer_vjp", "ibvt_fluid_lumped_volume_2d",
+                 "transfer_velocity_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -455,19 +457,21 @@ class Coupling:
         return arr
 
     def velocity(self, u_f, mass: str = "lumped", rtol: float = 1e-10, maxit: int = 500,
-                 out=None, stream=None, with_info: bool = False):
-        """u_s = S^{-1} B u_f, returns (nc, n_vert)."""
+                 out=None, stream=None, with_info: bool = False, noalloc: bool = False):
+        """u_s = S^{-1} B u_f, returns (nc, n_vert).  noalloc=True calls
+        transfer_velocity_noalloc (no device allocation in the library; pass
+        `out` to keep the call itself allocation-free)."""
         import torch
         uf = self._fluid_ptrs(u_f, "u_f")
         n = self.nc * self.n_vert
         if out is None:
             out = torch.empty((self.nc, self.n_vert), dtype=self.dtype, device=u_f[0].device)
         info = _SolveInfo()
-        st = _lib.transfer_velocity(self.handle, uf, _dev(out, self.dtype, n, "u_s"),
+        fn = _lib.transfer_velocity_noalloc if noalloc else _lib.transfer_velocity
+        st = fn(self.handle, uf, _dev(out, self.dtype, n, "u_s"),
                                     LUMPED if mass == "lumped" else CONSISTENT, float(rtol),
-                                    int(maxit), _stream(stream),
-                                    ctypes.byref(info) if with_info else None)
-        _check(st, "transfer_velocity")
+                int(maxit), _stream(stream), ctypes.byref(info) if with_info else None)
+        _check(st, "transfer_velocity_noalloc" if noalloc else "transfer_velocity")
         if with_info:
             return out, SolveInfo(tuple(info.iterations)[:self.nc],
                                   tuple(info.rel_residual)[:self.nc])
