@@ -22,7 +22,6 @@
 //  masses          lumped m_i = Σ_{T∋i} |T|/4 and the consistent P1 mass
 //                  matrix |T|(1+δ_il)/20 (Section 2.1), per vertex in
 //                  incident-tet order.
-#include <hipcub/hipcub.hpp>
 
 #include "geometry.hpp"
 #include "internal.hpp"

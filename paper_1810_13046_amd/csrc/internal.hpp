@@ -207,9 +207,7 @@ int shape_gradient_2d(ibvt_coupling* c, const void* z, const void* const u[3], c
 template <typename T>
 int transpose_one(ibvt_coupling* c, int d, hipStream_t s);
 
-// sort.hip: stable sorts by small integer keys (digit passes of at most
-// kMaxDigitBits bits; n < 2^31).
-constexpr int kMaxDigitBits = 11;
+// sort.hip: stable sorts by small integer keys (n < 2^31).
 // A nonzero carried through the transpose's sort: its value and its row.
 struct SortVal32 {
   float v;
@@ -229,12 +227,12 @@ const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits);
 // order = the indices 0..n-1 stably sorted by their 8-bit keys
 int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
                       void* scratch, hipStream_t s);
-// stable sort of (keys, vals) by keys < 2^end_bit (end_bit <= 2 kMaxDigitBits)
-// in two digit passes through (keys_tmp, vals_tmp); the result is in
-// (keys, vals).
+// stable sort of (keys, vals) by keys < 2^end_bit in digit passes of at
+// most 8 bits, alternating with (keys_tmp, vals_tmp); *in_tmp tells where
+// the result is.  scratch: sort_pass_bytes(n, 8) bytes.
 template <typename V>
 int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals,
-                   int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s);
+                   int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, bool* in_tmp);
 
 // apply.hip
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s);

@@ -1,39 +1,47 @@
 // Stable sorts by small integer keys, written for wave64: the pair order of
-// the clip (8-bit keys) and the radix passes of the transpose (keys of up to
-// 2 x kMaxDigitBits bits).
+// the clip (8-bit keys) and the radix passes of the transpose (int32 keys,
+// passes of at most 8 bits).
 //
 // One pass orders the items by one digit of the key, keeping the input
 // order among equal digits (LSD radix pass):
-//   k_digit_count    each wave takes a tile of kSortTile consecutive items
-//                    and counts its digits in LDS; the tile's histogram is
-//                    written digit-major (hist[digit][tile]).
+//   k_digit_count    each wave takes a tile of consecutive items (32 rounds
+//                    of 64, 16 for 16-byte values), loads them all, counts
+//                    their digits in LDS and writes the tile's histogram
+//                    digit-major (hist[digit][tile]).
 //   scan             exclusive prefix over the histogram: the first output
 //                    position of each (digit, tile).
-//   k_digit_scatter  each wave walks its tile again in rounds of 64 items in
-//                    input order; within a round the lanes with the same digit
-//                    find each other by one ballot per digit bit, take
-//                    consecutive positions in lane order and advance the
-//                    tile's running position of that digit (LDS).
+//   k_digit_scatter  each wave loads its tile again (keys and values in
+//                    registers), ranks the items round by round in input
+//                    order by digit (one ballot per digit bit), stages the
+//                    tile in LDS in digit order and writes it out in runs of
+//                    consecutive addresses per digit.
 // Positions follow from the input order alone: the result does not depend
 // on timing, and no value is combined.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace ibvt {
 
 namespace {
 
-constexpr int kSortWaves = 4;                 // waves (tiles) per block
-constexpr int kSortRounds = 128;              // rounds of 64 items per tile
-constexpr int kSortTile = kWave * kSortRounds;
+constexpr int kSortWaves = 4;  // waves (tiles) per block of the count kernel
+constexpr int kMaxPassBits = 8;  // widest digit of sort_pairs_i32 (wider measured slower)
+
+// Rounds of 64 items per tile: every item of a tile is held in registers
+// while it is ranked (values of 16 bytes take half the rounds).
+template <typename V>
+constexpr int sort_rounds() {
+  return sizeof(V) > 8 ? 16 : 32;
+}
 
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
   return (uint32_t(key) >> shift) & mask;
 }
 
-template <typename K, int BITS>
+template <typename K, int BITS, int R>
 __global__ __launch_bounds__(kWave * kSortWaves) void k_digit_count(
     int64_t n, const K* __restrict__ keys, int shift, int64_t ntiles,
     int32_t* __restrict__ hist) {
@@ -44,10 +52,18 @@ __global__ __launch_bounds__(kWave * kSortWaves) void k_digit_count(
   for (int b = lane; b < kBins; b += kWave) h[w][b] = 0;
   wave_lds_sync();
   if (tile < ntiles) {
-    const int64_t base = tile * kSortTile;
-    for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t base = tile * int64_t(R * kWave);
+    // every load of the tile in flight before the first count
+    K kv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       const int64_t i = base + int64_t(r) * kWave + lane;
-      if (i < n) atomicAdd(&h[w][digit_of(keys[i], shift, kBins - 1)], 1);
+      kv[r] = i < n ? keys[i] : K(0);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = base + int64_t(r) * kWave + lane;
+      if (i < n) atomicAdd(&h[w][digit_of(kv[r], shift, kBins - 1)], 1);
     }
   }
   wave_lds_sync();
@@ -55,26 +71,87 @@ __global__ __launch_bounds__(kWave * kSortWaves) void k_digit_count(
     for (int b = lane; b < kBins; b += kWave) hist[int64_t(b) * ntiles + tile] = h[w][b];
 }
 
-// vals_in == nullptr: the value carried is the item's index.
-template <typename K, typename V, int BITS>
-__global__ __launch_bounds__(kWave * kSortWaves) void k_digit_scatter(
+// One wave per tile.  The tile's items are first ranked in input order
+// (the lanes with the same digit find each other by one ballot per digit
+// bit and take consecutive places in lane order) and put in LDS in digit
+// order; the wave then writes the staged tile out, so the items of one
+// digit leave as a run of consecutive addresses.  vals_in == nullptr: the
+// value carried is the item's index.
+// Values travel as raw words of their size (no per-field work on them),
+// held as native vectors so that they stay in registers.
+typedef uint32_t RawWord2 __attribute__((ext_vector_type(2)));
+typedef uint32_t RawWord4 __attribute__((ext_vector_type(4)));
+template <typename V>
+using RawWord = std::conditional_t<
+    sizeof(V) == 16, RawWord4,
+    std::conditional_t<sizeof(V) == 8, RawWord2, std::conditional_t<sizeof(V) == 4, uint32_t, V>>>;
+
+template <typename K, typename V, int BITS, int R>
+__global__ __launch_bounds__(kWave) void k_digit_scatter(
     int64_t n, const K* __restrict__ keys_in, const V* __restrict__ vals_in, int shift,
-    int64_t ntiles, const int64_t* __restrict__ off, K* __restrict__ keys_out,
-    V* __restrict__ vals_out) {
+    int64_t ntiles, const int32_t* __restrict__ hist, const int64_t* __restrict__ off,
+    K* __restrict__ keys_out, V* __restrict__ vals_out) {
   constexpr int kBins = 1 << BITS;
-  __shared__ int32_t run[kSortWaves][kBins];  // n < 2^31
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const int64_t tile = int64_t(blockIdx.x) * kSortWaves + w;
-  if (tile >= ntiles) return;  // the whole wave
-  for (int b = lane; b < kBins; b += kWave) run[w][b] = int32_t(off[int64_t(b) * ntiles + tile]);
+  constexpr int kPer = (kBins + kWave - 1) / kWave;  // bins per lane in the local scan
+  constexpr int kTile = R * kWave;
+  using W = RawWord<V>;
+  static_assert(sizeof(W) == sizeof(V), "value word size");
+  __shared__ K sk[kTile];
+  __shared__ W sv[kTile];
+  const W* __restrict__ win = reinterpret_cast<const W*>(vals_in);
+  W* __restrict__ wout = reinterpret_cast<W*>(vals_out);
+  __shared__ int32_t lstart[kBins], run[kBins];
+  __shared__ int64_t gstart[kBins];
+  const int lane = lane_id();
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * int64_t(kTile);
+  // the tile's first place of each digit, locally (exclusive scan of the
+  // tile's counts) and in the output
+  int32_t cnt[kPer];
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int b = lane * kPer + k;
+    cnt[k] = b < kBins ? hist[int64_t(b) * ntiles + tile] : 0;
+    if (b < kBins) gstart[b] = off[int64_t(b) * ntiles + tile];
+    sum += cnt[k];
+  }
+  int32_t incl = sum;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  int32_t acc = incl - sum;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int b = lane * kPer + k;
+    if (b < kBins) {
+      lstart[b] = acc;
+      run[b] = acc;
+    }
+    acc += cnt[k];
+  }
   wave_lds_sync();
   const uint64_t below = (uint64_t(1) << lane) - 1;
-  const int64_t base = tile * kSortTile;
-  for (int r = 0; r < kSortRounds; ++r) {
+  // every load of the tile in flight before the ranking starts
+  K kv[R];
+  W vv[R];
+#pragma clang loop unroll(full)
+  for (int r = 0; r < R; ++r) {
     const int64_t i = base + int64_t(r) * kWave + lane;
     const bool act = i < n;
-    K key = K(0);
-    if (act) key = keys_in[i];
+    kv[r] = act ? keys_in[i] : K(0);
+    if constexpr (std::is_integral<V>::value && sizeof(V) == 4) {
+      vv[r] = win ? (act ? win[i] : W(0)) : W(uint32_t(i));  // n < 2^31
+    } else {
+      vv[r] = win[act ? i : 0];  // n >= 1: item 0 stands in past the end
+    }
+  }
+#pragma clang loop unroll(full)
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = base + int64_t(r) * kWave + lane;
+    const bool act = i < n;
+    const K key = kv[r];
     const uint32_t dg = digit_of(key, shift, kBins - 1);
     uint64_t peers = ballot64(act);
 #pragma unroll
@@ -83,19 +160,24 @@ __global__ __launch_bounds__(kWave * kSortWaves) void k_digit_scatter(
       peers &= ((dg >> b) & 1u) ? m : ~m;
     }
     const int rank = popc64(peers & below);
-    const int cnt = popc64(peers);
+    const int cnt_d = popc64(peers);
     int32_t pos = 0;
-    if (act) pos = run[w][dg] + rank;
-    wave_lds_sync();  // every lane has read its digit's position
-    if (act && rank == cnt - 1) run[w][dg] = pos + 1;
-    wave_lds_sync();
+    if (act) pos = run[dg] + rank;
+    wave_lds_sync();  // every lane has read its digit's place
+    if (act && rank == cnt_d - 1) run[dg] = pos + 1;
     if (act) {
-      if (keys_out) keys_out[pos] = key;
-      if constexpr (std::is_integral<V>::value)
-        vals_out[pos] = vals_in ? vals_in[i] : V(i);
-      else
-        vals_out[pos] = vals_in[i];
+      sk[pos] = key;
+      sv[pos] = vv[r];
     }
+    wave_lds_sync();
+  }
+  const int m = int(min<int64_t>(kTile, n - base));
+  for (int j = lane; j < m; j += kWave) {
+    const K key = sk[j];
+    const uint32_t dg = digit_of(key, shift, kBins - 1);
+    const int64_t pos = gstart[dg] + (j - lstart[dg]);
+    if (keys_out) keys_out[pos] = key;
+    wout[pos] = sv[j];
   }
 }
 
@@ -105,18 +187,21 @@ inline unsigned blocks_for_tiles(int64_t ntiles) {
 
 }  // namespace
 
-int64_t sort_tiles(int64_t n) { return ceil_div(n > 0 ? n : 1, kSortTile); }
-
 namespace {
+int64_t tiles_for(int64_t n, int rounds) { return ceil_div(n > 0 ? n : 1, int64_t(rounds) * kWave); }
 size_t hist_bytes(int64_t m) { return (size_t(m + 1) * sizeof(int32_t) + 255) & ~size_t(255); }
 }  // namespace
 
-// Scratch bytes of one pass with 2^bits digits (histogram and offsets).
+int64_t sort_tiles(int64_t n) { return tiles_for(n, sort_rounds<int32_t>()); }
+
+// Scratch bytes of one pass with 2^bits digits (histogram and offsets), for
+// the smallest tiles any value type takes.
 size_t sort_pass_bytes(int64_t n, int bits) {
-  const int64_t m = (int64_t(1) << bits) * sort_tiles(n);
+  const int64_t m = (int64_t(1) << bits) * tiles_for(n, sort_rounds<SortVal64>());
   return hist_bytes(m) + size_t(m + 1) * sizeof(int64_t) + 256;
 }
 
+// (for 4-byte values, as the pair order carries)
 const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits) {
   const int64_t m = (int64_t(1) << bits) * sort_tiles(n);
   return reinterpret_cast<const int64_t*>(static_cast<const char*>(scratch) + hist_bytes(m));
@@ -125,17 +210,18 @@ const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits) {
 template <typename K, typename V, int BITS>
 int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, const V* vals_in, int shift,
                K* keys_out, V* vals_out, void* scratch, hipStream_t s) {
-  const int64_t ntiles = sort_tiles(n);
+  constexpr int R = sort_rounds<V>();
+  const int64_t ntiles = tiles_for(n, R);
   const int64_t m = (int64_t(1) << BITS) * ntiles;
   int32_t* hist = static_cast<int32_t*>(scratch);
   int64_t* off = reinterpret_cast<int64_t*>(static_cast<char*>(scratch) + hist_bytes(m));
-  k_digit_count<K, BITS><<<blocks_for_tiles(ntiles), kWave * kSortWaves, 0, s>>>(
+  k_digit_count<K, BITS, R><<<blocks_for_tiles(ntiles), kWave * kSortWaves, 0, s>>>(
       n, keys_in, shift, ntiles, hist);
   int st = hip_check(hipGetLastError(), "digit count launch");
   if (st) return st;
   if ((st = scan_i32_to_i64(c, hist, off, m, s))) return st;
-  k_digit_scatter<K, V, BITS><<<blocks_for_tiles(ntiles), kWave * kSortWaves, 0, s>>>(
-      n, keys_in, vals_in, shift, ntiles, off, keys_out, vals_out);
+  k_digit_scatter<K, V, BITS, R><<<unsigned(ntiles), kWave, 0, s>>>(
+      n, keys_in, vals_in, shift, ntiles, hist, off, keys_out, vals_out);
   return hip_check(hipGetLastError(), "digit scatter launch");
 }
 
@@ -145,41 +231,52 @@ int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t*
   return digit_pass<uint8_t, int32_t, 8>(c, n, keys, nullptr, 0, nullptr, order, scratch, s);
 }
 
+template <typename V, int B>
+int digit_passes(ibvt_coupling* c, int64_t n, int passes, int32_t* keys, V* vals,
+                 int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, bool* in_tmp) {
+  int32_t* kin = keys;
+  V* vin = vals;
+  int32_t* kout = keys_tmp;
+  V* vout = vals_tmp;
+  for (int p = 0; p < passes; ++p) {
+    int st = digit_pass<int32_t, V, B>(c, n, kin, vin, p * B, kout, vout, scratch, s);
+    if (st) return st;
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  *in_tmp = (passes % 2) == 1;
+  return IBVT_OK;
+}
+
 template <typename V>
 int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals,
-                   int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s) {
+                   int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, bool* in_tmp) {
+  *in_tmp = false;
   if (n <= 0) return IBVT_OK;
-  if (end_bit > 2 * kMaxDigitBits)
-    return set_error(IBVT_E_CAPACITY, "sort key wider than two digit passes");
-  // two passes of equal width: the result lands back in keys / vals
-  const int lo_bits = (end_bit + 1) / 2;
-  int st;
-  switch (lo_bits) {
-#define IBVT_PASS(B)                                                                         \
-  case B:                                                                                    \
-    if ((st = digit_pass<int32_t, V, B>(c, n, keys, vals, 0, keys_tmp, vals_tmp, scratch, s))) \
-      return st;                                                                             \
-    return digit_pass<int32_t, V, B>(c, n, keys_tmp, vals_tmp, B, keys, vals, scratch, s);
-    IBVT_PASS(1)
-    IBVT_PASS(2)
-    IBVT_PASS(3)
-    IBVT_PASS(4)
-    IBVT_PASS(5)
-    IBVT_PASS(6)
-    IBVT_PASS(7)
-    IBVT_PASS(8)
-    IBVT_PASS(9)
-    IBVT_PASS(10)
-    IBVT_PASS(11)
-#undef IBVT_PASS
+  // passes of at most kMaxPassBits bits, all of one width
+  const int passes = std::max(1, (end_bit + kMaxPassBits - 1) / kMaxPassBits);
+  const int bits = (end_bit + passes - 1) / passes;
+  switch (bits) {
+#define IBVT_PASSES(B) \
+  case B:              \
+    return digit_passes<V, B>(c, n, passes, keys, vals, keys_tmp, vals_tmp, scratch, s, in_tmp);
+    IBVT_PASSES(1)
+    IBVT_PASSES(2)
+    IBVT_PASSES(3)
+    IBVT_PASSES(4)
+    IBVT_PASSES(5)
+    IBVT_PASSES(6)
+    IBVT_PASSES(7)
+    IBVT_PASSES(8)
+#undef IBVT_PASSES
     default:
       return set_error(IBVT_E_CAPACITY, "sort digit width");
   }
 }
 
 template int sort_pairs_i32<SortVal32>(ibvt_coupling*, int64_t, int, int32_t*, SortVal32*,
-                                       int32_t*, SortVal32*, void*, hipStream_t);
+                                       int32_t*, SortVal32*, void*, hipStream_t, bool*);
 template int sort_pairs_i32<SortVal64>(ibvt_coupling*, int64_t, int, int32_t*, SortVal64*,
-                                       int32_t*, SortVal64*, void*, hipStream_t);
+                                       int32_t*, SortVal64*, void*, hipStream_t, bool*);
 
 }  // namespace ibvt

@@ -2,16 +2,16 @@
 //
 // The touched fluid nodes are compacted with a prefix sum over the lattice;
 // the nonzeros of B^d, taken in their CSR order (row i ascending, then
-// column), are sorted by compacted column with a stable LSD radix sort that
-// carries each nonzero's (value, row) along, so each row of B^dT lists its
-// vertices in ascending order and no gather by permutation follows.  Small
+// column), are sorted by compacted column with a stable LSD radix sort
+// (digit passes of at most 8 bits, sort.hip) that carries each nonzero's
+// (value, row) along, so each row of B^dT lists its vertices in ascending
+// order and no gather by permutation follows.  Small
 // operators take a counting sort instead (column counts, their prefix sum,
 // a scatter into slots, then each row of B^dT put in vertex order by
 // ranking).  No value is reduced and no position depends on timing: the
 // result is deterministic either way.
-#include <hipcub/hipcub.hpp>
-
 #include <climits>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -32,10 +32,7 @@ __global__ void k_compact(int64_t n, const int32_t* __restrict__ mark,
 
 // A nonzero carried through the sort: its value and its row.
 template <typename T>
-struct ValRow {
-  T v;
-  int32_t r;
-};
+using ValRow = std::conditional_t<std::is_same<T, float>::value, SortVal32, SortVal64>;
 
 // keys[k] = compacted column of nonzero k, vr[k] = (value, row).
 // kKeyLanes lanes per row (coalesced reads and writes).
@@ -142,10 +139,8 @@ __global__ __launch_bounds__(256) void k_trow_order(int64_t n_rows,
   }
 }
 
-// Below this many nonzeros the counting sort is faster (0.33 against
-// 0.54 ms for two components of 0.95M nonzeros); at 34M its two passes of
-// device-scope atomics make it slower than the radix sort (2.2 against
-// 1.55 ms per component).
+// Below this many nonzeros the counting sort is faster; at 34M its two
+// passes of device-scope atomics make it slower than the radix sort.
 constexpr int64_t kCountingNnz = int64_t(4) << 20;
 
 inline unsigned blocks_for(int64_t n, int threads) {
@@ -207,32 +202,30 @@ int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
         touched, Bt.rowptr.as<int64_t>(), vr, Bt.col.as<int32_t>(), Bt.val.as<T>());
     return hip_check(hipGetLastError(), "transpose launch");
   }
-  // sort scratch: keys in/out, (value, row) in/out, cub temp
+  // sort scratch: keys and (value, row) pairs, their copies for the
+  // alternating digit passes, and the passes' histogram
   const int end_bit = end_bit_for(touched);
-  size_t temp_bytes = 0;
-  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(
-                          nullptr, temp_bytes, static_cast<const int32_t*>(nullptr),
-                          static_cast<int32_t*>(nullptr), static_cast<const ValRow<T>*>(nullptr),
-                          static_cast<ValRow<T>*>(nullptr), int(B.nnz), 0, end_bit, s),
-                      "sort size")))
-    return st;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t n4 = al(size_t(B.nnz) * sizeof(int32_t));
   const size_t nv = al(size_t(B.nnz) * sizeof(ValRow<T>));
-  if ((st = ensure(c, c->tbuf, 2 * n4 + 2 * nv + temp_bytes + 256))) return st;
+  const size_t sb = sort_pass_bytes(B.nnz, 8);
+  if ((st = ensure(c, c->tbuf, 2 * n4 + 2 * nv + sb + 256))) return st;
   char* base = c->tbuf.as<char>();
   int32_t* keys = reinterpret_cast<int32_t*>(base);
-  int32_t* skeys = reinterpret_cast<int32_t*>(base + n4);
+  int32_t* keys_tmp = reinterpret_cast<int32_t*>(base + n4);
   ValRow<T>* vr = reinterpret_cast<ValRow<T>*>(base + 2 * n4);
-  ValRow<T>* svr = reinterpret_cast<ValRow<T>*>(base + 2 * n4 + nv);
-  void* temp = base + 2 * n4 + 2 * nv;
+  ValRow<T>* vr_tmp = reinterpret_cast<ValRow<T>*>(base + 2 * n4 + nv);
+  void* scratch = base + 2 * n4 + 2 * nv;
   k_keys<T><<<blocks_for(c->n_vert * kKeyLanes, 256), 256, 0, s>>>(
       c->n_vert, B.rowptr.as<int64_t>(), B.col.as<int32_t>(), B.val.as<T>(),
       c->cidx.as<int64_t>(), keys, vr);
-  if ((st = hip_check(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, skeys, vr, svr,
-                                                         int(B.nnz), 0, end_bit, s),
-                      "radix sort")))
+  if ((st = hip_check(hipGetLastError(), "transpose keys launch"))) return st;
+  bool in_tmp = false;
+  if ((st = sort_pairs_i32<ValRow<T>>(c, B.nnz, end_bit, keys, vr, keys_tmp, vr_tmp, scratch, s,
+                                      &in_tmp)))
     return st;
+  const int32_t* skeys = in_tmp ? keys_tmp : keys;
+  const ValRow<T>* svr = in_tmp ? vr_tmp : vr;
   k_tgather<T><<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, skeys, svr, Bt.col.as<int32_t>(),
                                                       Bt.val.as<T>(), Bt.rowptr.as<int64_t>());
   return hip_check(hipGetLastError(), "transpose launch");
