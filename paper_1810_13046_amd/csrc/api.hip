@@ -74,7 +74,8 @@ int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes) {
     if (e != hipSuccess) return hip_check(e, "hipFreeAsync");
   }
   // grow with headroom so a moving mesh does not reallocate every step
-  const size_t want = bytes + bytes / 8 + 256;
+  // (1/8 of the size, 1/32 above 1 GiB)
+  const size_t want = bytes + (bytes > (size_t(1) << 30) ? bytes / 32 : bytes / 8) + 256;
   hipError_t e = hipMallocAsync(&b.p, want, c->stream);
   if (e != hipSuccess) {
     b.p = nullptr;

@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
     const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
     const double* __restrict__ tetrec, const double* __restrict__ lat, LatDesc ld,
     double drop_rel, T* __restrict__ pool, int64_t pool_cap, uint64_t* __restrict__ pinfo,
-    unsigned* flags, unsigned long long* counters) {
+    unsigned long long* pool_used, unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
   __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
     if (wave_total > cleft) {
       const int take = wave_total > chunk ? wave_total : chunk;
       unsigned long long b = 0;
-      if (lane == 0) b = atomicAdd(&counters[kCntPoolUsed], (unsigned long long)take);
+      if (lane == 0) b = atomicAdd(pool_used, (unsigned long long)take);
       cbase = __shfl(b, 0, kWave);
       cleft = take;
     }
@@ -408,7 +408,8 @@ __device__ __forceinline__ int owner_lane(int excl, int s) {
 // contiguous values).
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_integrate(
-    int64_t n_pairs, int64_t n_t, const uint64_t* __restrict__ pinfo, const T* __restrict__ pool,
+    int64_t n_pairs, int64_t p_begin, int64_t p_end, int64_t n_t,
+    const uint64_t* __restrict__ pinfo, const T* __restrict__ pool,
     const int32_t* __restrict__ owner, const int64_t* __restrict__ pair_off,
     const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
     const double* __restrict__ lat, LatDesc ld, uint8_t* __restrict__ keep,
@@ -417,11 +418,11 @@ __global__ __launch_bounds__(kWave) void k_integrate(
   __shared__ int rown[kWave];
   __shared__ int rlast[kWave];
   const int lane = threadIdx.x;
-  const int64_t g0 = int64_t(blockIdx.x) * kWave;
+  const int64_t g0 = p_begin + int64_t(blockIdx.x) * kWave;
   const int64_t pj = g0 + lane;
   int cnt = 0;
   int64_t beg = 0;
-  if (pj < n_pairs) {
+  if (pj < p_end) {
     const uint64_t pi = pinfo[pj];
     cnt = int(pi & 0xff);
     beg = int64_t(pi >> 8);
@@ -903,7 +904,7 @@ int check_flags(ibvt_coupling* c, hipStream_t s) {
 }
 
 namespace {
-constexpr int kMaxCounts = 16;
+constexpr int kMaxCounts = 24;
 struct CountSrc {
   const int64_t* p[kMaxCounts];
 };
@@ -963,15 +964,27 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   }
   if ((st = hip_check(hipGetLastError(), "prep launch"))) return st;
   if ((st = scan_i64(c, c->cnt.as<int64_t>(), c->pair_off.as<int64_t>(), 3 * n_t, s))) return st;
-  // read-back 1: pair count and status flags
-  int64_t n_pairs = 0;
+  // The pairs are clipped and integrated in chunks of consecutive (component,
+  // tet) ranges: the piece store holds one chunk's sub-tetrahedra, and a
+  // chunk's tet records stay in the caches while its pairs are clipped.
+  const int64_t n_tc = 3 * n_t;
+  const int nchunk = int(std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, n_tc / (int64_t(3) << 19))));
+  int64_t tc_at[kMaxChunks + 1];
+  for (int k = 0; k <= nchunk; ++k) tc_at[k] = n_tc * k / nchunk;
+  // read-back 1: the chunks' first pairs (the last entry is the pair count)
+  // and status flags
+  int64_t pat[kMaxChunks + 1];
   {
-    const int64_t* src[1] = {c->pair_off.as<int64_t>() + 3 * n_t};
-    if ((st = read_counts(c, src, 1, &n_pairs, s))) return st;
+    const int64_t* src[kMaxChunks + 1];
+    for (int k = 0; k <= nchunk; ++k) src[k] = c->pair_off.as<int64_t>() + tc_at[k];
+    if ((st = read_counts(c, src, nchunk + 1, pat, s))) return st;
   }
   if ((st = flags_status(c->host_flags))) return st;
+  const int64_t n_pairs = pat[nchunk];
   if (n_pairs >= (int64_t(1) << 31) - 1)
     return set_error(IBVT_E_CAPACITY, "2^31 or more (tet, cell) pairs");
+  int64_t chunk_max = 0;
+  for (int k = 0; k < nchunk; ++k) chunk_max = std::max(chunk_max, pat[k + 1] - pat[k]);
   c->n_pairs = n_pairs;
   if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
@@ -979,25 +992,20 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->pmom, size_t(n_pairs + 1) * kMomPad * sizeof(T)))) return st;
   if ((st = ensure(c, c->pinfo, size_t(n_pairs + 1) * sizeof(uint64_t)))) return st;
   if ((st = ensure(c, c->order, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
-  k_owner<<<blocks_for(3 * n_t, 256), 256, 0, s>>>(3 * n_t, c->pair_off.as<int64_t>(),
-                                                   c->owner.as<int32_t>());
-  // pair order by (cut class, straddled-plane pattern), stable: a counting
-  // sort on the 8-bit keys (sort.hip); the class boundaries stay on the
-  // device and the clip launches read them there
-  const int64_t* cls_start = nullptr;
-  int64_t ntiles = 0;
+  k_owner<<<blocks_for(n_tc, 256), 256, 0, s>>>(n_tc, c->pair_off.as<int64_t>(),
+                                                c->owner.as<int32_t>());
+  // sort keys of every pair: (cut class, straddled-plane pattern); each
+  // chunk is ordered by them with a stable counting sort (sort.hip), whose
+  // digit starts give the clip launches their class stretches on the device
+  const size_t kb = (size_t(n_pairs + 1) + 255) & ~size_t(255);
+  if ((st = ensure(c, c->pscan, kb + sort_pass_bytes(std::max<int64_t>(chunk_max, 1), 8))))
+    return st;
+  uint8_t* keys = c->pscan.as<uint8_t>();
+  void* sort_scratch = c->pscan.as<char>() + kb;
   if (n_pairs > 0) {
-    ProfScope ps("pair_order", s);
-    const size_t kb = (size_t(n_pairs + 1) + 255) & ~size_t(255);
-    if ((st = ensure(c, c->pscan, kb + sort_pass_bytes(n_pairs, 8)))) return st;
-    uint8_t* keys = c->pscan.as<uint8_t>();
-    void* scratch = c->pscan.as<char>() + kb;
     k_pair_key<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
         n_pairs, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), keys);
     if ((st = hip_check(hipGetLastError(), "pair key launch"))) return st;
-    if ((st = order_by_byte_key(c, n_pairs, keys, c->order.as<int32_t>(), scratch, s))) return st;
-    cls_start = sort_digit_starts(scratch, n_pairs, 8);
-    ntiles = sort_tiles(n_pairs);
   }
   // (IV, set-up) each row's node box: from the cell ranges alone
   if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
@@ -1012,61 +1020,80 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = scan_i64(c, c->rowcap.as<int64_t>(), c->rowtmpoff.as<int64_t>(), 3 * n_v, s))) return st;
   int64_t tmp_total = 0;
   for (int attempt = 0; attempt < 2; ++attempt) {
-    const int64_t want = std::max<int64_t>(int64_t(3.25 * double(n_pairs)) + 1024,
+    const int64_t want = std::max<int64_t>(int64_t(3.25 * double(chunk_max)) + 1024,
                                            c->pool_needed + c->pool_needed / 32 + 1024);
     if (int64_t(c->pool.cap / (kRecord * sizeof(T))) < want &&
         (st = ensure(c, c->pool, size_t(want) * kRecord * sizeof(T))))
       return st;
     c->pool_cap = int64_t(c->pool.cap / (kRecord * sizeof(T)));
     // clear the clip's counters (the zero-tet count of the preparation stays)
-    for (int k : {int(kCntPieces), int(kCntDropped), int(kCntSubtets), int(kCntPoolUsed),
-                  int(kCntDist), int(kCntCutPts), int(kCntPlanes)})
+    for (int k : {int(kCntPieces), int(kCntDropped), int(kCntSubtets), int(kCntDist),
+                  int(kCntCutPts), int(kCntPlanes)})
       if ((st = hip_check(hipMemsetAsync(counters + k, 0, sizeof(unsigned long long), s),
                           "memset")))
         return st;
-    if (n_pairs > 0) {
-      // (II) clip every pair, one launch per cut class (fewer vertex slots
-      // per lane, more resident waves); each launch reads its class's
-      // stretch of the order from the sort's digit starts
-      ProfScope ps("clip", s);
-      for (int k = 0; k < 3; ++k) {
-        const int resident =
-            k == 0 ? resident_blocks(k_clip<T, 10>)
-                   : (k == 1 ? resident_blocks(k_clip<T, 12>) : resident_blocks(k_clip<T, kMaxV>));
-        const int64_t nb = std::min<int64_t>(ceil_div(n_pairs, kWave), resident);
-#define IBVT_CLIP_ARGS                                                                         \
-  cls_start + 64 * k * ntiles, cls_start + 64 * (k + 1) * ntiles, c->order.as<int32_t>(), n_t, \
-      c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),               \
-      c->tetrec.as<double>(), c->lat.as<double>(), c->ld, 1e-14, c->pool.as<T>(), c->pool_cap,  \
-      c->pinfo.as<uint64_t>(), flags, counters
-        if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-        else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-        else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-#undef IBVT_CLIP_ARGS
+    if ((st = hip_check(hipMemsetAsync(counters + kCntChunkPool, 0,
+                                       kMaxChunks * sizeof(unsigned long long), s),
+                        "memset")))
+      return st;
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int64_t p0 = pat[ch], nc = pat[ch + 1] - pat[ch];
+      if (nc <= 0) continue;
+      {
+        ProfScope ps("pair_order", s);
+        if ((st = order_by_byte_key(c, nc, keys + p0, c->order.as<int32_t>() + p0, sort_scratch,
+                                    s, p0)))
+          return st;
       }
+      const int64_t* cls_start = sort_digit_starts(sort_scratch, nc, 8);
+      const int64_t ntiles = sort_tiles(nc);
+      {
+        // (II) clip the chunk's pairs, one launch per cut class (fewer vertex
+        // slots per lane, more resident waves); each launch reads its
+        // class's stretch of the order from the sort's digit starts
+        ProfScope ps("clip", s);
+        for (int k = 0; k < 3; ++k) {
+          const int resident =
+              k == 0 ? resident_blocks(k_clip<T, 10>)
+                     : (k == 1 ? resident_blocks(k_clip<T, 12>) : resident_blocks(k_clip<T, kMaxV>));
+          const int64_t nb = std::min<int64_t>(ceil_div(nc, kWave), resident);
+#define IBVT_CLIP_ARGS                                                                          \
+  cls_start + 64 * k * ntiles, cls_start + 64 * (k + 1) * ntiles, c->order.as<int32_t>() + p0, \
+      n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),          \
+      c->tetrec.as<double>(), c->lat.as<double>(), c->ld, 1e-14, c->pool.as<T>(), c->pool_cap,  \
+      c->pinfo.as<uint64_t>(), counters + kCntChunkPool + ch, flags, counters
+          if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+          else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+          else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+#undef IBVT_CLIP_ARGS
+        }
+      }
+      if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
+      {
+        // (III) integrate the chunk's sub-tetrahedra, summed per pair (pairs
+        // whose records did not fit the store read as empty)
+        ProfScope ps("integrate", s);
+        k_integrate<T><<<dim3(unsigned(ceil_div(nc, kWave))), kWave, 0, s>>>(
+            n_pairs, p0, p0 + nc, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(),
+            c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
+            c->tetrec.as<double>(), c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(),
+            c->pval.as<T>(), c->pmom.as<T>(), c->dual ? 1 : 0);
+      }
+      if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
     }
-    if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
-    // (III) integrate every stored sub-tetrahedron, summed per pair (pairs
-    // whose records did not fit the store read as empty)
-    if (n_pairs > 0) {
-      ProfScope ps("integrate", s);
-      k_integrate<T><<<dim3(unsigned(ceil_div(n_pairs, kWave))), kWave, 0, s>>>(
-          n_pairs, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(), c->owner.as<int32_t>(),
-          c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), c->tetrec.as<double>(),
-          c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(), c->pval.as<T>(), c->pmom.as<T>(),
-          c->dual ? 1 : 0);
-    }
-    if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
-    // read-back 2: records the clip asked for, the row scratch size, flags
-    int64_t rb2[2] = {0, 0};
+    // read-back 2: records each chunk asked for, the row scratch size, flags
+    int64_t rb2[kMaxChunks + 1];
     {
-      const int64_t* src[2] = {reinterpret_cast<const int64_t*>(counters + kCntPoolUsed),
-                               c->rowtmpoff.as<int64_t>() + 3 * n_v};
-      if ((st = read_counts(c, src, 2, rb2, s))) return st;
+      const int64_t* src[kMaxChunks + 1];
+      src[0] = c->rowtmpoff.as<int64_t>() + 3 * n_v;
+      for (int k = 0; k < nchunk; ++k)
+        src[1 + k] = reinterpret_cast<const int64_t*>(counters + kCntChunkPool + k);
+      if ((st = read_counts(c, src, nchunk + 1, rb2, s))) return st;
     }
     if ((st = flags_status(c->host_flags))) return st;
-    c->pool_needed = rb2[0];
-    tmp_total = rb2[1];
+    tmp_total = rb2[0];
+    c->pool_needed = 0;
+    for (int k = 0; k < nchunk; ++k) c->pool_needed = std::max(c->pool_needed, rb2[1 + k]);
     if (c->pool_needed <= c->pool_cap) break;
     if (attempt == 1) return set_error(IBVT_E_CAPACITY, "piece store could not be sized");
   }

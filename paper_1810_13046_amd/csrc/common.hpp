@@ -15,6 +15,7 @@ constexpr unsigned kFlagNonFinite = 4u;
 constexpr unsigned kFlagValence = 8u;
 constexpr unsigned kFlagTetSpan = 16u;  // a tet spans more than kMaxTetCells cells
 constexpr int kMaxTetCells = 65535;     // cells of one lattice a tet may span
+constexpr int kMaxChunks = 8;           // pair chunks of the clip and integration
 
 // Counter slots (unsigned long long) written by the assembly kernels.
 enum Counter : int {
@@ -22,13 +23,14 @@ enum Counter : int {
   kCntDropped = 1,
   kCntZeroTets = 2,
   kCntSubtets = 3,
-  kCntPoolUsed = 4,  // piece-store records the clip asked for
-  kCntClass = 5,  // 5, 6, 7: pairs per cut class
+  kCntUnused4 = 4,
+  kCntUnused5 = 5,  // 5, 6, 7: unused
   kCntDist = 8,   // signed distances evaluated by the clip
   kCntCutPts = 9, // cut points made by the clip
   kCntRowOverflow = 10,  // rows too wide for the LDS row gather (unstructured)
   kCntPlanes = 11,  // (pair, cell plane) clips run by the clip
-  kCntSlots = 12,
+  kCntChunkPool = 12,  // 12..19: piece-store records asked for by each pair chunk
+  kCntSlots = 20,
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

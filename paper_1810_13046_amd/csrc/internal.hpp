@@ -175,7 +175,7 @@ int assemble_all(ibvt_coupling* c, hipStream_t s);    // dispatches on dim
 int read_back(ibvt_coupling* c, void* host, const void* dev, size_t bytes, hipStream_t s);
 int check_flags(ibvt_coupling* c, hipStream_t s);
 // One stream synchronisation for several device counts: out[k] = *srcs[k]
-// (n <= 16 int64 values) and the status flag word into c->host_flags.
+// (n <= 24 int64 values) and the status flag word into c->host_flags.
 int read_counts(ibvt_coupling* c, const int64_t* const* srcs, int n, int64_t* out, hipStream_t s);
 // Status of a flag word (IBVT_OK when no flag is set).
 int flags_status(unsigned f);
@@ -224,9 +224,9 @@ size_t sort_pass_bytes(int64_t n, int bits);
 // of digit k is at [k * sort_tiles(n)] of this array (device); entry
 // 2^bits * sort_tiles(n) holds n
 const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits);
-// order = the indices 0..n-1 stably sorted by their 8-bit keys
+// order = index_base + (the indices 0..n-1 stably sorted by their 8-bit keys)
 int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
-                      void* scratch, hipStream_t s);
+                      void* scratch, hipStream_t s, int64_t index_base = 0);
 // stable sort of (keys, vals) by keys < 2^end_bit in digit passes of at
 // most 8 bits, alternating with (keys_tmp, vals_tmp); *in_tmp tells where
 // the result is.  scratch: sort_pass_bytes(n, 8) bytes.

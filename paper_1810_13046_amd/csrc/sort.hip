@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kWave * kSortWaves) void k_digit_count(
 // bit and take consecutive places in lane order) and put in LDS in digit
 // order; the wave then writes the staged tile out, so the items of one
 // digit leave as a run of consecutive addresses.  vals_in == nullptr: the
-// value carried is the item's index.
+// value carried is vbase plus the item's index.
 // Values travel as raw words of their size (no per-field work on them),
 // held as native vectors so that they stay in registers.
 typedef uint32_t RawWord2 __attribute__((ext_vector_type(2)));
@@ -88,8 +88,8 @@ using RawWord = std::conditional_t<
 
 template <typename K, typename V, int BITS, int R>
 __global__ __launch_bounds__(kWave) void k_digit_scatter(
-    int64_t n, const K* __restrict__ keys_in, const V* __restrict__ vals_in, int shift,
-    int64_t ntiles, const int32_t* __restrict__ hist, const int64_t* __restrict__ off,
+    int64_t n, const K* __restrict__ keys_in, const V* __restrict__ vals_in, int64_t vbase,
+    int shift, int64_t ntiles, const int32_t* __restrict__ hist, const int64_t* __restrict__ off,
     K* __restrict__ keys_out, V* __restrict__ vals_out) {
   constexpr int kBins = 1 << BITS;
   constexpr int kPer = (kBins + kWave - 1) / kWave;  // bins per lane in the local scan
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kWave) void k_digit_scatter(
     const bool act = i < n;
     kv[r] = act ? keys_in[i] : K(0);
     if constexpr (std::is_integral<V>::value && sizeof(V) == 4) {
-      vv[r] = win ? (act ? win[i] : W(0)) : W(uint32_t(i));  // n < 2^31
+      vv[r] = win ? (act ? win[i] : W(0)) : W(uint32_t(vbase + i));  // < 2^31
     } else {
       vv[r] = win[act ? i : 0];  // n >= 1: item 0 stands in past the end
     }
@@ -209,7 +209,7 @@ const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits) {
 
 template <typename K, typename V, int BITS>
 int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, const V* vals_in, int shift,
-               K* keys_out, V* vals_out, void* scratch, hipStream_t s) {
+               K* keys_out, V* vals_out, void* scratch, hipStream_t s, int64_t vbase = 0) {
   constexpr int R = sort_rounds<V>();
   const int64_t ntiles = tiles_for(n, R);
   const int64_t m = (int64_t(1) << BITS) * ntiles;
@@ -221,14 +221,15 @@ int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, const V* vals_in, 
   if (st) return st;
   if ((st = scan_i32_to_i64(c, hist, off, m, s))) return st;
   k_digit_scatter<K, V, BITS, R><<<unsigned(ntiles), kWave, 0, s>>>(
-      n, keys_in, vals_in, shift, ntiles, hist, off, keys_out, vals_out);
+      n, keys_in, vals_in, vbase, shift, ntiles, hist, off, keys_out, vals_out);
   return hip_check(hipGetLastError(), "digit scatter launch");
 }
 
 int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
-                      void* scratch, hipStream_t s) {
+                      void* scratch, hipStream_t s, int64_t index_base) {
   if (n <= 0) return IBVT_OK;
-  return digit_pass<uint8_t, int32_t, 8>(c, n, keys, nullptr, 0, nullptr, order, scratch, s);
+  return digit_pass<uint8_t, int32_t, 8>(c, n, keys, nullptr, 0, nullptr, order, scratch, s,
+                                         index_base);
 }
 
 template <typename V, int B>
