@@ -65,20 +65,21 @@ FLUSH_BYTES = 1 << 30   # cold-cache protocol: >= 1 GiB written between repetiti
 MOM_FLOPS_PER_POINT = 99
 POINTS_PER_SUBTET = 11
 
-# HBM traffic of the clip step (both slot-class launches of one assembly) on
+# HBM traffic of the clip step (all launches of one assembly) on
 # the three-body workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counter
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="cabeb8d4ad35f8fbf2f6a963582c61d6b5051132c9182e61302edb9beedced2b",
-                    bytes_mixed=35621912352)
+CLIP_TRAFFIC = dict(sources_sha256="f0b0b051f179133c483ab330703376a94d76c77fcb745a74b37980feae518193",
+                    bytes_mixed=35766846896)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
 # HBM traffic of one lumped velocity apply and one force apply (all three
 # components, mixed precision) on the three-body workload, from the same
 # counter passes (profiles/hbm_traffic_three_bodies4.5M_mixed.txt);
 # reported while apply.hip is the source they were taken on.
-APPLY_TRAFFIC = dict(sources_sha256=None, velocity_bytes=None, force_bytes=None)
+APPLY_TRAFFIC = dict(sources_sha256="2b89fa181c472f095536b4e9b230087f4505674885b13e32bb939a249ed6ab1d",
+                     velocity_bytes=972432981, force_bytes=980896541)
 APPLY_SOURCES = ["paper_1810_13046_amd/csrc/apply.hip"]
 
 
@@ -574,15 +575,18 @@ def cpu_baseline(W, dev, tets_per_body, samples):
 
 
 def roofline(name, prof, info, precision):
-    """Roofline object of one profiled step of kernel `name`: algorithmic
-    work per launch over its average launch time (HIP events on the
-    library's stream).  The clip is priced at FLOPS_PER_PLANE_CUT FP64 flops
-    per plane cut (midpoint as `frac`, the range beside it); the builder's
-    own operation count (CLIP_FLOPS) is reported beside that."""
+    """Roofline object of kernel `name` over one profiled step: its
+    algorithmic work in one assembly over the summed device time of its
+    launches in that assembly (HIP events on the library's stream; the clip
+    runs as one launch per (pair chunk, cut class), the integration as one
+    per chunk).  The clip is priced at FLOPS_PER_PLANE_CUT FP64 flops per
+    plane cut (midpoint as `frac`, the range beside it); the builder's own
+    operation count (CLIP_FLOPS) is reported beside that."""
     launches, total_ms = prof
-    ms = total_ms / launches
-    out = dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None,
-               traffic=None, launch_ms=ms)
+    ms = total_ms
+    out = dict(kernel=name + " (all launches of one assembly)", bound="unknown", achieved=None,
+               peak=None, unit=None, frac=None, traffic=None, launch_ms=ms,
+               timed_launches=launches)
     if name == "clip":
         lo, mid, hi = (f * info["plane_cuts"] for f in FLOPS_PER_PLANE_CUT)
         achieved = mid / (ms * 1e-3) / 1e12
