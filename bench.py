@@ -70,7 +70,7 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="f0b0b051f179133c483ab330703376a94d76c77fcb745a74b37980feae518193",
+CLIP_TRAFFIC = dict(sources_sha256="3cc04ebcc30b06ef0147270d2c6784d466b8c900d65695a7e30c7e1a5251d5aa",
                     bytes_mixed=35766846896)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]

@@ -401,7 +401,7 @@ __device__ __forceinline__ int owner_lane(int excl, int s) {
 }
 
 // (III) integrate every stored sub-tetrahedron: its 35 moments (cell-local,
-// centred) with the 14-point rule, summed per pair in record order through
+// centred) with the 11-point degree-4 rule, summed per pair in record order through
 // LDS (deterministic) into pmom[pair][m] (rows of kMomPad).  Then each lane
 // turns its pair's moments into the 4 x 8 values ∫ λ_i N_j, written to
 // pval[i][pair][j] (local-vertex major: each vertex row of a pair is 8

@@ -14,11 +14,14 @@
 // vertex with distance >= 0 is inside.
 //
 // Integration: the piece is fanned into sub-tetrahedra from its lowest
-// vertex (faces through that vertex are skipped); on each, λ_i N_j is a
-// degree-4 polynomial and a symmetric 14-point degree-5 rule integrates it
-// exactly.  Coordinates are cell-local (ξ = (x − x0)/h ∈ [0, 1]^3), so the
-// Q1 hats are ξ or 1 − ξ per axis and float arithmetic keeps its relative
-// precision in the mixed-precision path.
+// vertex (faces through that vertex are skipped).  The assembly integrates
+// the 35 monomial moments of degree <= 4 of each sub-tetrahedron with a
+// symmetric 11-point degree-4 rule (subtet_moments), from which every
+// integrand λ_i N_j follows; the reverse mode's re-clipping path integrates
+// its degree-4 integrands directly with a symmetric 14-point degree-5 rule
+// (subtet_integrate, subtet_grad).  Coordinates are cell-local
+// (ξ = (x − x0)/h ∈ [0, 1]^3), so the Q1 hats are ξ or 1 − ξ per axis and
+// float arithmetic keeps its relative precision in the mixed-precision path.
 //
 // Everything here is __host__ __device__: the storage of the vertex graph
 // is a strided view (stride 64 = one slot per lane in LDS on the GPU).
