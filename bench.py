@@ -122,12 +122,13 @@ class Step:
     dual=True the multipliers are the dual basis (S = lumped mass), so the
     velocity transfer and its adjoint need no mass solve."""
 
-    def __init__(self, W, X, T, u64, f_s, u_t, precision, dual=False):
+    def __init__(self, W, X, T, u64, f_s, u_t, precision, dual=False, store_B=True):
         import torch
         from paper_1810_13046_amd import Coupling
         self.dual = dual
         self.mass = "lumped" if dual else "consistent"
-        self.c = Coupling(W.faces, X, T, precision=precision, consistent=not dual, dual=dual)
+        self.c = Coupling(W.faces, X, T, precision=precision, consistent=not dual, dual=dual,
+                          store_B=store_B)
         dt = self.c.dtype
         self.X = X
         self.u = [u.to(dt).contiguous() for u in u64]
@@ -727,6 +728,19 @@ def main():
         log(f"[bench] dual {ms_d:.2f} ms/step")
         del sd
 
+    matrix_free = None
+    if not args.profile_run:
+        log("[bench] step without stored matrices (mixed): build")
+        smf = Step(W, X, T, u64, f_s, u_t, "fp32", store_B=False)
+        ms_mf, _ = time_steps(smf, max(1, min(args.steps, 3)), 1)
+        matrix_free = dict(ms_per_step=ms_mf, value=n_tet / (ms_mf * 1e-3),
+                           device_bytes=smf.c.info()["device_bytes"],
+                           note="IBVT_NO_STORE_B: no B, B^T or per-pair data held; the "
+                                "consistent velocity, the force and both adjoints clip and "
+                                "integrate every piece again")
+        log(f"[bench] without stored matrices {ms_mf:.2f} ms/step")
+        del smf
+
     # dominant kernel of the mixed step and its roofline
     per_kernel = {k: v[1] for k, v in prof_mixed.items()}
     dom = max(per_kernel, key=per_kernel.get)
@@ -795,6 +809,7 @@ def main():
         "fp64": fp64,
         "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / ms_mixed) if fp64 else None,
         "dual_basis": dual,
+        "without_stored_matrices": matrix_free,
         "fsi_picard": fsi,
         "planar": planar,
         "unstructured": unstructured,

@@ -100,6 +100,18 @@ extern "C" {
                                        transfers take IBVT_LUMPED (consistent
                                        is IBVT_E_INVALID) and
                                        IBVT_FORCE_IS_LOAD applies diag(m)^-1 */
+#define IBVT_NO_STORE_B 8u          /* grids only: keep neither B, B^T nor
+                                       any per-pair data, only the per-tet
+                                       data and the solid masses; every
+                                       product with B or B^T and the shape
+                                       derivative clip and integrate the
+                                       pieces again (the memory-saving
+                                       recompute form of the reverse mode).
+                                       B^T products add into the fluid
+                                       arrays with atomic adds, so their
+                                       rounding is not bitwise repeatable;
+                                       coupling_export_csr is
+                                       IBVT_E_UNSUPPORTED */
 
 /* transfer_force flags. */
 #define IBVT_FORCE_IS_LOAD 1u   /* f_s is a load vector: apply S^{-1}
@@ -170,7 +182,34 @@ typedef struct {
   int64_t plane_cuts;        /* (pair, cell plane) clips run by the last
                                 assembly (grids: the cell planes each
                                 piece's tet straddles) */
+  int64_t matrix_free;       /* 1 if built with IBVT_NO_STORE_B (nnz,
+                                touched, pieces, subtets and the clip
+                                counters are then 0) */
 } ibvt_info;
+
+/* Device allocator for a coupling's own buffers: alloc returns device
+ * memory of at least `bytes` bytes, usable in stream order on `stream`, or
+ * NULL (the calling entry point then fails with IBVT_E_NOMEM); free
+ * releases memory alloc returned, in stream order on `stream`.  ctx is
+ * passed back unchanged.  Both may be called from any entry point that
+ * grows or frees a buffer (assembly, reassembly, the first call that needs
+ * a workspace, coupling_free). */
+typedef struct {
+  void* (*alloc)(size_t bytes, hipStream_t stream, void* ctx);
+  void (*free)(void* ptr, hipStream_t stream, void* ctx);
+  void* ctx;
+} ibvt_alloc;
+
+/*
+ * ibvt_set_allocator — the allocator of the couplings created after this
+ *   call (a caching allocator such as PyTorch's, so that the library's
+ *   buffers come from the same pool as the caller's tensors).  Each handle
+ *   keeps the allocator it was created with and frees with it.  NULL
+ *   restores the default, hipMallocAsync / hipFreeAsync on the call's
+ *   stream.  Thread-safe with respect to concurrent handle creation.
+ *   Errors: IBVT_E_INVALID (a non-NULL a with a NULL alloc or free).
+ */
+int ibvt_set_allocator(const ibvt_alloc* a);
 
 /*
  * assemble_coupling — build B^d (d = 0, 1, 2) for the mesh and grid.
@@ -186,8 +225,11 @@ typedef struct {
  *   precision: IBVT_FP64 or IBVT_FP32_MIXED.
  *   out: receives a new handle owned by the library (free with
  *   coupling_free).  On failure *out is set to NULL.
+ *   Limits: fewer than 2^30 tets, at most 2^21 cells along each axis,
+ *   fewer than 2^31 (tet, cell) pairs and nonzeros per component
+ *   (IBVT_E_UNSUPPORTED, IBVT_E_CAPACITY beyond them).
  *   Errors: IBVT_E_INVALID, IBVT_E_OUT_OF_GRID, IBVT_E_CAPACITY,
- *   IBVT_E_NOMEM, IBVT_E_HIP.
+ *   IBVT_E_UNSUPPORTED, IBVT_E_NOMEM, IBVT_E_HIP.
  */
 int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precision,
                       uint32_t flags, hipStream_t stream, ibvt_coupling** out);
@@ -368,6 +410,33 @@ int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], c
 
 /* coupling_info — fill *info (host).  Errors: IBVT_E_INVALID. */
 int coupling_info(const ibvt_coupling* c, ibvt_info* info);
+
+/* Counters of one body: the tets of a mesh grouped into bodies by
+ * consecutive index ranges. */
+typedef struct {
+  int64_t tets;       /* tets (triangles) of the body */
+  int64_t zero_tets;  /* of zero volume (skipped by the assembly) */
+  int64_t pairs;      /* (tet, component, cell) candidate pairs (unstructured:
+                         (solid tet, fluid tet) pairs) */
+  int64_t pieces;     /* pairs whose piece the last assembly kept (volume >
+                         1e-14 |T|); -1 for a coupling built with
+                         IBVT_NO_STORE_B, which keeps no per-pair data */
+  double volume;      /* Σ |T| over the body (area for a planar mesh) */
+} ibvt_body_info;
+
+/*
+ * coupling_body_info — per-body counters of the last assembly, for meshes
+ *   made of several bodies (a diagnostic: it synchronises the stream).
+ *   Body b holds tets tet_offsets[b] .. tet_offsets[b+1] - 1; tet_offsets
+ *   is a host array of n_bodies + 1 non-decreasing entries, the first 0
+ *   and the last n_tet.  out: host array of n_bodies entries.  Summed over
+ *   the bodies, the counters equal coupling_info's pairs, pieces and
+ *   zero_tets.
+ *   Errors: IBVT_E_INVALID (NULL pointers, n_bodies < 1, bad offsets, a
+ *   handle whose last assembly failed), IBVT_E_NOMEM, IBVT_E_HIP.
+ */
+int coupling_body_info(ibvt_coupling* c, int32_t n_bodies, const int64_t* tet_offsets,
+                       ibvt_body_info* out, hipStream_t stream);
 
 /*
  * coupling_export_csr — copy B^d (transposed = 0: rows = solid vertices) or

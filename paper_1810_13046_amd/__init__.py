@@ -12,5 +12,5 @@ Autograd forms live in paper_1810_13046_amd.autograd.
 """
 from .ibvt import (  # noqa: F401
     Coupling, FsiReport, IbvtError, fluid_lumped_volume, lattice_coords, load_library, LIB_PATH,
-    EXPORTED, profile_enable, profile_read,
+    EXPORTED, profile_enable, profile_read, use_torch_allocator,
 )

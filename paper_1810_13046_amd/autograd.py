@@ -9,9 +9,12 @@ Both call the C ABI (transfer_velocity / transfer_force and their
 _vjp entry points); no numerical step runs in Python.  With dual=True the
 multipliers are the dual basis of Section 2.3 (eq. biorth) and S is the
 lumped mass.  With
-recompute_B=True the coupling is freed after the forward pass and
-assembled again from the saved X in the backward pass, so B and the piece
-store are not held between the two passes.  Planar couplings (two face
+recompute_B=True a 3D grid coupling is built without stored matrices
+(IBVT_NO_STORE_B): the forward and the backward pass clip and integrate the
+pieces again, so neither B, B^T nor any per-pair data is ever held (the
+force-spreading products then add with atomics: equal to the stored form to
+rounding, not bit for bit).  A planar coupling is instead freed after the
+forward pass and assembled again from the saved X in the backward pass.  Planar couplings (two face
 arrays, X (n_vert, 2), triangles) take two fluid components: pass
 u_f = (u0, u1) and get two force arrays back.  An unstructured coupling
 (Coupling(None, X, tets, fluid_mesh=...)) is passed as `coupling` (faces
@@ -31,11 +34,17 @@ class _Ctx:
         self.mass, self.rtol, self.maxit, self.dual = mass, rtol, maxit, dual
 
 
-def _coupling(meta, X, existing):
+def _coupling(meta, X, existing, store_B=True):
     if existing is not None:
         return existing
     return Coupling(meta.faces, X.detach().contiguous(), meta.tets, precision=meta.precision,
-                    consistent=(meta.mass == "consistent"), dual=meta.dual)
+                    consistent=(meta.mass == "consistent"), dual=meta.dual, store_B=store_B)
+
+
+def _matrix_free(meta, recompute, existing):
+    """recompute_B on a 3D grid: a coupling that keeps no matrices, held
+    between the passes (it holds per-tet data only)."""
+    return recompute and existing is None and meta.faces is not None and len(meta.faces) == 3
 
 
 class TransferVelocity(torch.autograd.Function):
@@ -47,12 +56,13 @@ class TransferVelocity(torch.autograd.Function):
     def forward(ctx, u0, u1, u2, X, faces, tets, precision="fp64", mass="lumped", rtol=1e-12,
                 maxit=500, coupling=None, recompute_B=False, dual=False):
         meta = _Ctx(faces, tets, precision, mass, rtol, maxit, dual)
-        c = _coupling(meta, X, coupling)
+        mf = _matrix_free(meta, recompute_B, coupling)
+        c = _coupling(meta, X, coupling, store_B=not mf)
         u = [v.contiguous() for v in (u0, u1, u2) if v is not None]
         us = c.velocity(u, mass=mass, rtol=rtol, maxit=maxit)
         ctx.meta = meta
         ctx.nc = len(u)
-        ctx.recompute = recompute_B and coupling is None
+        ctx.recompute = recompute_B and coupling is None and not mf
         ctx.coupling = None if ctx.recompute else c
         ctx.save_for_backward(X, us, *u)
         if ctx.recompute:
@@ -86,13 +96,14 @@ class TransferForce(torch.autograd.Function):
     def forward(ctx, f_s, X, faces, tets, precision="fp64", alpha=1.0, coupling=None,
                 recompute_B=False, dual=False):
         meta = _Ctx(faces, tets, precision, "lumped", 1e-12, 500, dual)
-        c = _coupling(meta, X, coupling)
+        mf = _matrix_free(meta, recompute_B, coupling)
+        c = _coupling(meta, X, coupling, store_B=not mf)
         out = [torch.zeros(s, dtype=c.dtype, device=f_s.device) for s in
                [tuple(reversed(ls)) for ls in c.lattice_shapes]]
         c.force(f_s.contiguous(), out, alpha=alpha)
         ctx.meta = meta
         ctx.alpha = alpha
-        ctx.recompute = recompute_B and coupling is None
+        ctx.recompute = recompute_B and coupling is None and not mf
         ctx.coupling = None if ctx.recompute else c
         ctx.save_for_backward(f_s, X)
         if ctx.recompute:

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibvt.so")
-SOURCES = ["scan.hip", "sort.hip", "assemble.hip", "assemble2d.hip", "unstructured.hip", "transpose.hip",
+SOURCES = ["scan.hip", "sort.hip", "assemble.hip", "matfree.hip", "assemble2d.hip", "unstructured.hip", "transpose.hip",
            "apply.hip", "grad.hip", "api.hip", "fsi.hip", "noalloc.hip"]
 ARCH = "gfx950"
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ibvt.h")

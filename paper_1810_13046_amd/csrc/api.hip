@@ -4,6 +4,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -61,13 +62,32 @@ int hip_check(hipError_t e, const char* what) {
   return set_error(IBVT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+namespace {
+std::mutex g_alloc_mu;
+ibvt_alloc g_alloc{};  // allocator of new handles (null members: hipMallocAsync)
+
+// Stream-ordered release of one buffer through the handle's allocator.
+hipError_t free_buffer(ibvt_coupling* c, void* p) {
+  if (c->alloc.free) {
+    c->alloc.free(p, c->stream, c->alloc.ctx);
+    return hipSuccess;
+  }
+  return hipFreeAsync(p, c->stream);
+}
+
+ibvt_alloc current_allocator() {
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  return g_alloc;
+}
+}  // namespace
+
 int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 1;
   if (b.p && b.cap >= bytes) return IBVT_OK;
   // stream-ordered: the old buffer is released after the work queued on
   // the call's stream, and growing does not synchronize the device
   if (b.p) {
-    hipError_t e = hipFreeAsync(b.p, c->stream);
+    hipError_t e = free_buffer(c, b.p);
     c->device_bytes -= int64_t(b.cap);
     b.p = nullptr;
     b.cap = 0;
@@ -76,11 +96,16 @@ int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes) {
   // grow with headroom so a moving mesh does not reallocate every step
   // (1/8 of the size, 1/32 above 1 GiB)
   const size_t want = bytes + (bytes > (size_t(1) << 30) ? bytes / 32 : bytes / 8) + 256;
-  hipError_t e = hipMallocAsync(&b.p, want, c->stream);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    (void)hipGetLastError();
-    return hip_check(e, "hipMallocAsync");
+  if (c->alloc.alloc) {
+    b.p = c->alloc.alloc(want, c->stream, c->alloc.ctx);
+    if (!b.p) return set_error(IBVT_E_NOMEM, "the coupling's allocator returned NULL");
+  } else {
+    hipError_t e = hipMallocAsync(&b.p, want, c->stream);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      (void)hipGetLastError();
+      return hip_check(e, "hipMallocAsync");
+    }
   }
   b.cap = want;
   c->device_bytes += int64_t(want);
@@ -89,7 +114,7 @@ int ensure(ibvt_coupling* c, DevBuf& b, size_t bytes) {
 
 void release(ibvt_coupling* c, DevBuf& b) {
   if (b.p) {
-    (void)hipFreeAsync(b.p, c->stream);
+    (void)free_buffer(c, b.p);
     c->device_bytes -= int64_t(b.cap);
   }
   b.p = nullptr;
@@ -97,6 +122,57 @@ void release(ibvt_coupling* c, DevBuf& b) {
 }
 
 namespace {
+
+// Per-body sums, one block per body: tets, zero-volume tets and volume over
+// the body's tet range, candidate pairs and kept pieces over its pair range
+// in each of the `groups` pair groups (pair_off over groups x n_t).  Output
+// cnt[b][4] = (tets, zero tets, pairs, pieces), vol[b].
+constexpr int kBodyThreads = 256;
+__global__ __launch_bounds__(kBodyThreads) void k_body_info(
+    const int64_t* __restrict__ off, int64_t n_t, int groups, const double* __restrict__ tetvol,
+    const int64_t* __restrict__ pair_off, const uint8_t* __restrict__ keep,
+    int64_t* __restrict__ cnt, double* __restrict__ vol) {
+  __shared__ unsigned long long s_zero[kBodyThreads / kWave], s_kept[kBodyThreads / kWave];
+  __shared__ double s_vol[kBodyThreads / kWave];
+  const int b = blockIdx.x;
+  const int64_t t0 = off[b], t1 = off[b + 1];
+  unsigned long long zero = 0, kept = 0;
+  double v = 0.0;
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += kBodyThreads) {
+    const double x = tetvol[t];
+    v += x;
+    zero += (x == 0.0) ? 1u : 0u;
+  }
+  int64_t pairs = 0;
+  for (int g = 0; g < groups; ++g) {
+    const int64_t p0 = pair_off[int64_t(g) * n_t + t0], p1 = pair_off[int64_t(g) * n_t + t1];
+    pairs += p1 - p0;
+    if (keep)
+      for (int64_t p = p0 + threadIdx.x; p < p1; p += kBodyThreads) kept += keep[p] ? 1u : 0u;
+  }
+  zero = wave_sum(zero);
+  kept = wave_sum(kept);
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    s_zero[w] = zero;
+    s_kept[w] = kept;
+    s_vol[w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kBodyThreads / kWave; ++k) {
+      zero += s_zero[k];
+      kept += s_kept[k];
+      v += s_vol[k];
+    }
+    cnt[4 * b + 0] = t1 - t0;
+    cnt[4 * b + 1] = int64_t(zero);
+    cnt[4 * b + 2] = pairs;
+    cnt[4 * b + 3] = keep ? int64_t(kept) : -1;
+    vol[b] = v;
+  }
+}
 
 void release_csr(ibvt_coupling* c, Csr& m) {
   release(c, m.rowptr);
@@ -116,7 +192,7 @@ void release_all(ibvt_coupling* c) {
                     &c->rowtmpcol, &c->rowtmpval, &c->tetgrad, &c->mcoef,
                     &c->fsiX,     &c->fsinorm,   &c->fvol,      &c->fX,        &c->ftets,
                     &c->frec,     &c->fbox,      &c->forder,    &c->ftree,     &c->ucoo,
-                    &c->rb};
+                    &c->rb,       &c->bodyinfo};
   for (DevBuf* b : bufs) release(c, *b);
   if (c->host_rb) {
     (void)hipHostFree(c->host_rb);
@@ -415,17 +491,19 @@ int assemble_coupling(const ibvt_grid* grid, const ibvt_mesh* mesh, int precisio
     return set_error(IBVT_E_INVALID, "mesh X or tets is NULL");
   if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
     return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
-  if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE | IBVT_DUAL_BASIS))
+  if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE | IBVT_DUAL_BASIS | IBVT_NO_STORE_B))
     return set_error(IBVT_E_INVALID, "unknown flags");
   ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
+  c->alloc = current_allocator();
   c->stream = stream;
   c->precision = precision;
   c->flags = flags;
   c->n_vert = mesh->n_vert;
   c->n_tet = mesh->n_tet;
   c->has_M = (flags & IBVT_BUILD_CONSISTENT_M) != 0;
-  c->store_pieces = (flags & IBVT_NO_PIECE_STORE) == 0;
+  c->matrix_free = (flags & IBVT_NO_STORE_B) != 0;
+  c->store_pieces = (flags & IBVT_NO_PIECE_STORE) == 0 && !c->matrix_free;
   c->dual = (flags & IBVT_DUAL_BASIS) != 0;
   for (int e = 0; e < 3; ++e) c->n_cells[e] = grid->n_cells[e];
   st = setup_lattices(c, grid, stream);
@@ -452,10 +530,13 @@ int assemble_coupling_unstructured(const ibvt_mesh* fluid, const ibvt_mesh* mesh
     return set_error(IBVT_E_INVALID, "mesh X or tets is NULL");
   if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
     return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
+  if (flags & IBVT_NO_STORE_B)
+    return set_error(IBVT_E_UNSUPPORTED, "IBVT_NO_STORE_B is for grid couplings");
   if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE | IBVT_DUAL_BASIS))
     return set_error(IBVT_E_INVALID, "unknown flags");
   ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
+  c->alloc = current_allocator();
   c->unstructured = true;
   c->stream = stream;
   c->precision = precision;
@@ -507,10 +588,13 @@ int assemble_coupling_2d(const ibvt_grid2d* grid, const ibvt_mesh2d* mesh, int p
     return set_error(IBVT_E_INVALID, "mesh X or tris is NULL");
   if (precision != IBVT_FP64 && precision != IBVT_FP32_MIXED)
     return set_error(IBVT_E_INVALID, "precision must be IBVT_FP64 or IBVT_FP32_MIXED");
+  if (flags & IBVT_NO_STORE_B)
+    return set_error(IBVT_E_UNSUPPORTED, "IBVT_NO_STORE_B is for grid couplings");
   if (flags & ~(IBVT_BUILD_CONSISTENT_M | IBVT_NO_PIECE_STORE | IBVT_DUAL_BASIS))
     return set_error(IBVT_E_INVALID, "unknown flags");
   ibvt_coupling* c = new (std::nothrow) ibvt_coupling();
   if (!c) return set_error(IBVT_E_NOMEM, "host allocation failed");
+  c->alloc = current_allocator();
   c->dim = 2;
   c->ncomp = 2;
   c->stream = stream;
@@ -677,6 +761,7 @@ int coupling_info(const ibvt_coupling* c, ibvt_info* info) {
   info->dual = c->dual ? 1 : 0;
   info->dim = c->dim;
   info->unstructured = c->unstructured ? 1 : 0;
+  info->matrix_free = c->matrix_free ? 1 : 0;
   return IBVT_OK;
 }
 
@@ -686,6 +771,8 @@ int coupling_export_csr(const ibvt_coupling* c, int comp, int transposed, int64_
   if (!c || comp < 0 || comp >= c->ncomp || !n_rows || !nnz)
     return set_error(IBVT_E_INVALID, "bad argument");
   if (int st0 = require_ready(c)) return st0;
+  if (c->matrix_free)
+    return set_error(IBVT_E_UNSUPPORTED, "the coupling keeps no matrices (IBVT_NO_STORE_B)");
   const Csr& m = transposed ? c->Bt[comp] : c->B[comp];
   *n_rows = m.nrows;
   *nnz = m.nnz;
@@ -760,6 +847,61 @@ int ibvt_profile_read(const char** names, int64_t* launches, double* ms, int max
     ++k;
   }
   return k;
+}
+
+int coupling_body_info(ibvt_coupling* c, int32_t n_bodies, const int64_t* tet_offsets,
+                       ibvt_body_info* out, hipStream_t stream) {
+  if (!c || !tet_offsets || !out) return set_error(IBVT_E_INVALID, "NULL argument");
+  if (n_bodies < 1) return set_error(IBVT_E_INVALID, "n_bodies must be >= 1");
+  if (int st0 = require_ready(c)) return st0;
+  if (tet_offsets[0] != 0 || tet_offsets[n_bodies] != c->n_tet)
+    return set_error(IBVT_E_INVALID, "tet_offsets must start at 0 and end at n_tet");
+  for (int32_t b = 0; b < n_bodies; ++b)
+    if (tet_offsets[b + 1] < tet_offsets[b])
+      return set_error(IBVT_E_INVALID, "tet_offsets must not decrease");
+  c->stream = stream;
+  const size_t ob = (size_t(n_bodies + 1) * sizeof(int64_t) + 255) & ~size_t(255);
+  const size_t cb = (size_t(n_bodies) * 4 * sizeof(int64_t) + 255) & ~size_t(255);
+  int st = ensure(c, c->bodyinfo, ob + cb + size_t(n_bodies) * sizeof(double));
+  if (st) return st;
+  int64_t* doff = c->bodyinfo.as<int64_t>();
+  int64_t* dcnt = reinterpret_cast<int64_t*>(c->bodyinfo.as<char>() + ob);
+  double* dvol = reinterpret_cast<double*>(c->bodyinfo.as<char>() + ob + cb);
+  if ((st = hip_check(hipMemcpyAsync(doff, tet_offsets, size_t(n_bodies + 1) * sizeof(int64_t),
+                                     hipMemcpyHostToDevice, stream),
+                      "copy offsets")))
+    return st;
+  const int groups = c->unstructured ? 1 : c->ncomp;
+  const uint8_t* keep = (c->matrix_free || c->n_pairs == 0) ? nullptr : c->keep.as<uint8_t>();
+  k_body_info<<<unsigned(n_bodies), kBodyThreads, 0, stream>>>(
+      doff, c->n_tet, groups, c->tetvol.as<double>(), c->pair_off.as<int64_t>(), keep, dcnt, dvol);
+  if ((st = hip_check(hipGetLastError(), "body info launch"))) return st;
+  std::vector<int64_t> hc(size_t(n_bodies) * 4);
+  std::vector<double> hv(static_cast<size_t>(n_bodies));
+  if ((st = hip_check(hipMemcpyAsync(hc.data(), dcnt, hc.size() * sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, stream),
+                      "read counters")) ||
+      (st = hip_check(hipMemcpyAsync(hv.data(), dvol, hv.size() * sizeof(double),
+                                     hipMemcpyDeviceToHost, stream),
+                      "read volumes")) ||
+      (st = hip_check(hipStreamSynchronize(stream), "sync")))
+    return st;
+  for (int32_t b = 0; b < n_bodies; ++b) {
+    out[b].tets = hc[4 * size_t(b) + 0];
+    out[b].zero_tets = hc[4 * size_t(b) + 1];
+    out[b].pairs = hc[4 * size_t(b) + 2];
+    out[b].pieces = hc[4 * size_t(b) + 3];
+    out[b].volume = hv[size_t(b)];
+  }
+  return IBVT_OK;
+}
+
+int ibvt_set_allocator(const ibvt_alloc* a) {
+  if (a && (!a->alloc || !a->free))
+    return set_error(IBVT_E_INVALID, "an allocator needs both alloc and free");
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  g_alloc = a ? *a : ibvt_alloc{};
+  return IBVT_OK;
 }
 
 void coupling_free(ibvt_coupling* c) {

@@ -474,6 +474,7 @@ int true_residual(ibvt_coupling* c, const T* b, const double* x, const MassWork&
 }  // namespace
 
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s) {
+  if (c->matrix_free) return apply_B_matfree(c, x, y, lumped_scale, s);
   const int64_t n = c->n_vert;
   int64_t nnz = 0;
   for (int d = 0; d < c->ncomp; ++d) nnz += c->B[d].nnz;
@@ -507,6 +508,7 @@ int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale
 
 // out[d][rowmap[r]] += alpha * (B^dT ys_d)[r]
 int apply_Bt(ibvt_coupling* c, const void* ys, void* const out[3], double alpha, hipStream_t s) {
+  if (c->matrix_free) return apply_Bt_matfree(c, ys, out, alpha, s);
   const int64_t n = c->n_vert;
   int64_t nnz = 0;
   for (int d = 0; d < c->ncomp; ++d) nnz += c->Bt[d].nnz;

@@ -5,8 +5,10 @@
 //                  rectilinear grid the overlap candidates of a tet are an
 //                  index box), volume, geometry record, validity checks.
 //  scan / k_owner  candidate (tet, component, cell) pair offsets and owners.
-//  k_pair_key      pairs ordered by the cell planes the tet straddles, in
-//                  classes by cut count (vertex slots 10, 12, 16).
+//  k_pair_key      per chunk of pairs: sort key (the cell planes the tet
+//                  straddles, in classes by cut count: vertex slots 10,
+//                  12, 16) and 16-byte descriptor; a counting sort puts
+//                  the descriptors in clip order.
 //  k_clip<T,MAXV>  one lane per pair: clip the tet by the straddled cell
 //                  planes in double (vertex graph in LDS), fan the piece
 //                  into sub-tetrahedra and store them as records.
@@ -229,34 +231,24 @@ __global__ void k_owner(int64_t n_tc, const int64_t* __restrict__ off, int32_t* 
 // clip + integrate, one lane per (tet, component, cell) pair
 // ---------------------------------------------------------------------------
 
-// Pair geometry for the clip: cell box of the pair, tet vertices and box.
-__device__ __forceinline__ void pair_geometry(int64_t p, int64_t n_t, const int32_t* owner,
-                                              const int64_t* pair_off, const CellRange* rng,
-                                              const double* tetrec, const double* lat,
-                                              const LatDesc& ld, int& d, int64_t& t, int ci[3],
-                                              TetGeom& G, double lo[3], double hi[3]) {
-  pair_cell(p, n_t, owner, pair_off, rng, lat, ld, d, t, ci, lo, hi);
-  double r[kTetRec];
-  load_row<kTetRec>(tetrec + t * kTetRec, r);
-  load_tet_box(G, r);
-}
-
 // Which of the six cell planes a pair's tet straddles, from indices alone:
 // the low plane of cell ci cuts the tet iff ci > first cell of the tet's
 // range, the high plane iff ci < last.  Sort key = class · 64 + pattern,
 // class 0: <= 3 cuts, 1: 4, 2: >= 5 (classes need 10, 12, 16 vertex
 // slots); sorting by the key gives every wave the same sequence of clips.
-__global__ void k_pair_key(int64_t n_pairs, const int32_t* __restrict__ owner,
+// Also writes the pair's descriptor (pair_desc), which the sort carries.
+// One chunk of pairs: p0 .. p0 + n - 1 (outputs indexed from 0).
+__global__ void k_pair_key(int64_t p0, int64_t n, int64_t n_t, const int32_t* __restrict__ owner,
                            const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-                           uint8_t* __restrict__ key) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p < n_pairs) {
-    const int64_t tc = owner[p];
+                           uint8_t* __restrict__ key, PairDesc* __restrict__ desc) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const PairDesc q = pair_desc(p0 + i, n_t, owner, pair_off, rng);
+    const int64_t tc = owner[p0 + i];
     const CellRange r = rng[tc];
-    const uint32_t q = uint32_t(p - pair_off[tc]);
-    const uint32_t n0 = uint32_t(r.n[0]), n1 = uint32_t(r.n[1]);
-    const uint32_t qy = q / n0, qz = qy / n1;
-    const int c[3] = {int(q - qy * n0), int(qy - qz * n1), int(qz)};
+    constexpr uint64_t m = (uint64_t(1) << kCellBits) - 1;
+    const int c[3] = {int(q.cell & m) - r.lo[0], int((q.cell >> kCellBits) & m) - r.lo[1],
+                      int(q.cell >> (2 * kCellBits)) - r.lo[2]};
     int pattern = 0;
     for (int e = 0; e < 3; ++e) {
       if (c[e] > 0) pattern |= 1 << (2 * e);
@@ -264,26 +256,27 @@ __global__ void k_pair_key(int64_t n_pairs, const int32_t* __restrict__ owner,
     }
     const int cuts = __popc(pattern);
     const int cls = cuts <= 3 ? 0 : (cuts == 4 ? 1 : 2);
-    key[p] = uint8_t(cls * 64 + pattern);
+    key[i] = uint8_t(cls * 64 + pattern);
+    desc[i] = q;
   }
 }
 
 // Clip every (tet, component, cell) pair in double, one lane per pair, and
-// store the fan sub-tetrahedra of the piece.  The grid is sized to the
-// resident waves and each wave loops over batches of 64 pairs.  A wave takes
-// store space in chunks of `chunk` records (one atomic per chunk, not per
-// batch: same-address atomics serialise device-wide) and hands each batch a
+// store the fan sub-tetrahedra of the piece.  The pairs come as descriptors
+// in clip order (pattern-sorted).  The grid is sized to the resident waves
+// and each wave loops over batches of 64 pairs.  A wave takes store space in
+// chunks of `chunk` records (one atomic per chunk, not per batch:
+// same-address atomics serialise device-wide) and hands each batch a
 // contiguous block of its chunk, so every pair's records are contiguous and
 // in fan order; the unused tail of a chunk is left empty.  The counters are
 // summed per wave and added once at the end.
 template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_clip(
     const int64_t* __restrict__ cls_first, const int64_t* __restrict__ cls_end,
-    const int32_t* __restrict__ order_all, int64_t n_t, const int32_t* __restrict__ owner,
-    const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-    const double* __restrict__ tetrec, const double* __restrict__ lat, LatDesc ld,
-    double drop_rel, T* __restrict__ pool, int64_t pool_cap, uint64_t* __restrict__ pinfo,
-    unsigned long long* pool_used, unsigned* flags, unsigned long long* counters) {
+    const PairDesc* __restrict__ desc_all, const double* __restrict__ tetrec,
+    const double* __restrict__ lat, LatDesc ld, double drop_rel, T* __restrict__ pool,
+    int64_t pool_cap, uint64_t* __restrict__ pinfo, unsigned long long* pool_used,
+    unsigned* flags, unsigned long long* counters) {
   __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
   __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
@@ -292,7 +285,7 @@ __global__ __launch_bounds__(kWave) void k_clip(
   // pair), so the unused chunk tails stay a few percent of the store
   const int64_t first = *cls_first;
   const int64_t n_list = *cls_end - first;
-  const int32_t* __restrict__ order = order_all + first;
+  const PairDesc* __restrict__ desc = desc_all + first;
   const int chunk = int(min<int64_t>(
       2048, max<int64_t>(1, (3 * n_list) / (8 * int64_t(gridDim.x)))));
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
@@ -303,9 +296,9 @@ __global__ __launch_bounds__(kWave) void k_clip(
   bool fail = false;
   for (int64_t p0 = int64_t(blockIdx.x) * kWave; p0 < n_list; p0 += int64_t(gridDim.x) * kWave) {
     const bool active = p0 + lane < n_list;
-    const int64_t p = active ? int64_t(order[p0 + lane]) : 0;
     TetGeom G;
     double lo[3], hi[3];
+    int64_t p = 0;
     uint32_t live = 0;
     uint64_t seen = 0;
     int want = 0;
@@ -313,7 +306,10 @@ __global__ __launch_bounds__(kWave) void k_clip(
     if (active) {
       int d, ci[3];
       int64_t t;
-      pair_geometry(p, n_t, owner, pair_off, rng, tetrec, lat, ld, d, t, ci, G, lo, hi);
+      desc_cell(desc[p0 + lane], lat, ld, p, d, t, ci, lo, hi);
+      double r[kTetRec];
+      load_row<kTetRec>(tetrec + t * kTetRec, r);
+      load_tet_box(G, r);
       live = poly_init_tet(P, G.V, G.det < 0.0);
       ok = poly_clip_box<MAXV>(P, live, lo, hi, G.mn, G.mx, &cc);
       if (ok) {
@@ -345,9 +341,15 @@ __global__ __launch_bounds__(kWave) void k_clip(
       const bool fits = my + want <= pool_cap;
       double vol6 = 0.0;
       int nsub = 0;
-      if (ok && want > 0)
-        ok = emit_subtets<T>(P, live, seen, lo, hi, fits ? pool + my * kRecord : nullptr, want,
-                             vol6, nsub);
+      if (ok && want > 0) {
+        T* rec = pool + my * kRecord;
+        ok = emit_subtets<T>(
+            P, live, seen, lo, hi,
+            [&](int k, const T(&r)[kRecord]) {
+              if (fits && k < want) store_row<kRecord>(rec + int64_t(k) * kRecord, r);
+            },
+            vol6, nsub);
+      }
       if (ok && nsub != want) ok = false;
       ns += unsigned(nsub);
       if (!ok) {
@@ -446,13 +448,14 @@ __global__ __launch_bounds__(kWave) void k_integrate(
 #pragma unroll
     for (int k = 0; k < kMom; ++k) M[k] = T(0);
     if (s < total) {
-      const T* rec = pool + (int64_t(bj) + (s - ex_j)) * kRecord;
+      T r[kRecord];
+      load_row<kRecord>(pool + (int64_t(bj) + (s - ex_j)) * kRecord, r);
       T y[4][3];
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int e = 0; e < 3; ++e) y[v][e] = rec[v * 3 + e];
-      subtet_moments<T>(y, rec[12], M);
+        for (int e = 0; e < 3; ++e) y[v][e] = r[v * 3 + e];
+      subtet_moments<T>(y, subtet_det<T>(y[0], y[1], y[2], y[3]), M);
     }
 #pragma unroll
     for (int k = 0; k < kMom; ++k) red[lane][k] = M[k];
@@ -943,6 +946,35 @@ int read_counts(ibvt_coupling* c, const int64_t* const* srcs, int n, int64_t* ou
 
 namespace {
 
+// Without stored matrices (IBVT_NO_STORE_B): after the overlap candidates,
+// only the solid masses and the per-(component, tet) buffer of the
+// matrix-free products (3 n_t x 4 values) are built.
+template <typename T>
+int finish_matfree(ibvt_coupling* c, hipStream_t s) {
+  int st;
+  if ((st = ensure(c, c->pval, size_t(3 * c->n_tet + 1) * 4 * sizeof(T)))) return st;
+  for (int d = 0; d < 3; ++d) {
+    c->B[d].nnz = 0;
+    c->Bt[d].nrows = 0;
+    c->Bt[d].nnz = 0;
+  }
+  if ((st = solid_masses(c, s))) return st;
+  int64_t zero = 0;
+  {
+    const int64_t* src[1] = {
+        reinterpret_cast<const int64_t*>(c->counters.as<unsigned long long>() + kCntZeroTets)};
+    if ((st = read_counts(c, src, 1, &zero, s))) return st;
+  }
+  if ((st = flags_status(c->host_flags))) return st;
+  const int64_t done = c->stats.assemblies + 1;
+  c->stats = AsmStats{};
+  c->stats.pairs = c->n_pairs;
+  c->stats.zero_tets = zero;
+  c->stats.assemblies = done;
+  c->mom_valid = false;
+  return IBVT_OK;
+}
+
 template <typename T>
 int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
@@ -983,30 +1015,30 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   const int64_t n_pairs = pat[nchunk];
   if (n_pairs >= (int64_t(1) << 31) - 1)
     return set_error(IBVT_E_CAPACITY, "2^31 or more (tet, cell) pairs");
+  c->n_pairs = n_pairs;
+  if (c->matrix_free) return finish_matfree<T>(c, s);
   int64_t chunk_max = 0;
   for (int k = 0; k < nchunk; ++k) chunk_max = std::max(chunk_max, pat[k + 1] - pat[k]);
-  c->n_pairs = n_pairs;
   if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
   if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 32 * sizeof(T)))) return st;
   if ((st = ensure(c, c->pmom, size_t(n_pairs + 1) * kMomPad * sizeof(T)))) return st;
   if ((st = ensure(c, c->pinfo, size_t(n_pairs + 1) * sizeof(uint64_t)))) return st;
-  if ((st = ensure(c, c->order, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
+  // the clip order of one chunk at a time, as pair descriptors
+  if ((st = ensure(c, c->order, size_t(chunk_max + 1) * sizeof(PairDesc)))) return st;
   k_owner<<<blocks_for(n_tc, 256), 256, 0, s>>>(n_tc, c->pair_off.as<int64_t>(),
                                                 c->owner.as<int32_t>());
-  // sort keys of every pair: (cut class, straddled-plane pattern); each
-  // chunk is ordered by them with a stable counting sort (sort.hip), whose
-  // digit starts give the clip launches their class stretches on the device
-  const size_t kb = (size_t(n_pairs + 1) + 255) & ~size_t(255);
-  if ((st = ensure(c, c->pscan, kb + sort_pass_bytes(std::max<int64_t>(chunk_max, 1), 8))))
+  // per chunk: sort keys (cut class, straddled-plane pattern) and pair
+  // descriptors, ordered by a stable counting sort (sort.hip) whose digit
+  // starts give the clip launches their class stretches on the device
+  const size_t kb = (size_t(chunk_max + 1) + 255) & ~size_t(255);
+  const size_t db = size_t(chunk_max + 1) * sizeof(PairDesc);
+  if ((st = ensure(c, c->pscan,
+                   kb + db + sort_pass_bytes(std::max<int64_t>(chunk_max, 1), 8))))
     return st;
   uint8_t* keys = c->pscan.as<uint8_t>();
-  void* sort_scratch = c->pscan.as<char>() + kb;
-  if (n_pairs > 0) {
-    k_pair_key<<<blocks_for(n_pairs, 256), 256, 0, s>>>(
-        n_pairs, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(), keys);
-    if ((st = hip_check(hipGetLastError(), "pair key launch"))) return st;
-  }
+  PairDesc* desc_in = reinterpret_cast<PairDesc*>(c->pscan.as<char>() + kb);
+  void* sort_scratch = c->pscan.as<char>() + kb + db;
   // (IV, set-up) each row's node box: from the cell ranges alone
   if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
   if ((st = ensure(c, c->rowcap, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
@@ -1041,8 +1073,12 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
       if (nc <= 0) continue;
       {
         ProfScope ps("pair_order", s);
-        if ((st = order_by_byte_key(c, nc, keys + p0, c->order.as<int32_t>() + p0, sort_scratch,
-                                    s, p0)))
+        k_pair_key<<<blocks_for(nc, 256), 256, 0, s>>>(p0, nc, n_t, c->owner.as<int32_t>(),
+                                                      c->pair_off.as<int64_t>(),
+                                                      c->rng.as<CellRange>(), keys, desc_in);
+        if ((st = hip_check(hipGetLastError(), "pair key launch"))) return st;
+        if ((st = order_pairs_by_byte_key(c, nc, keys, desc_in, c->order.as<PairDesc>(),
+                                          sort_scratch, s)))
           return st;
       }
       const int64_t* cls_start = sort_digit_starts(sort_scratch, nc, 8);
@@ -1058,8 +1094,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
                      : (k == 1 ? resident_blocks(k_clip<T, 12>) : resident_blocks(k_clip<T, kMaxV>));
           const int64_t nb = std::min<int64_t>(ceil_div(nc, kWave), resident);
 #define IBVT_CLIP_ARGS                                                                          \
-  cls_start + 64 * k * ntiles, cls_start + 64 * (k + 1) * ntiles, c->order.as<int32_t>() + p0, \
-      n_t, c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),          \
+  cls_start + 64 * k * ntiles, cls_start + 64 * (k + 1) * ntiles, c->order.as<PairDesc>(),    \
       c->tetrec.as<double>(), c->lat.as<double>(), c->ld, 1e-14, c->pool.as<T>(), c->pool_cap,  \
       c->pinfo.as<uint64_t>(), counters + kCntChunkPool + ch, flags, counters
           if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
@@ -1285,7 +1320,13 @@ namespace {
 int assemble_grid(ibvt_coupling* c, hipStream_t s) {
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
   int st;
+  // the clip's pair descriptors pack the tet and cell indices
+  if (n_t >= kMaxDescTets) return set_error(IBVT_E_UNSUPPORTED, "2^30 or more tets");
+  for (int k = 0; k < 9; ++k)
+    if (c->ld.n[k] > (1 << kCellBits))
+      return set_error(IBVT_E_UNSUPPORTED, "more than 2^21 lattice cells along one axis");
   int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));
+  if (c->matrix_free) nf_max = 0;  // no transpose
   if ((st = ensure(c, c->tetvol, size_t(n_t + 1) * sizeof(double)))) return st;
   if ((st = ensure(c, c->tetrec, size_t(n_t + 1) * kTetRec * sizeof(double)))) return st;
   if ((st = ensure(c, c->tetgrad, size_t(n_t + 1) * 12 * sizeof(double)))) return st;

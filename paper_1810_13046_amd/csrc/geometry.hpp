@@ -606,16 +606,12 @@ struct TetGeom {
   double mn[3], mx[3];  // bounding box
 };
 
-__host__ __device__ inline void tet_geom(TetGeom& G) {
-  for (int a = 0; a < 3; ++a) {
-    G.mn[a] = fmin(fmin(G.V[0][a], G.V[1][a]), fmin(G.V[2][a], G.V[3][a]));
-    G.mx[a] = fmax(fmax(G.V[0][a], G.V[1][a]), fmax(G.V[2][a], G.V[3][a]));
-  }
+// e1 · (e2 × e3) with e_k = V_k − V_0; c receives the cofactor rows
+// (e2 × e3, e3 × e1, e1 × e2).
+__host__ __device__ inline double tet_det(const double V[4][3], double c[3][3]) {
   double e[3][3];
   for (int k = 0; k < 3; ++k)
-    for (int a = 0; a < 3; ++a) e[k][a] = G.V[k + 1][a] - G.V[0][a];
-  // cofactor rows: ∇λ_1 = (e2 × e3)/det, ∇λ_2 = (e3 × e1)/det, ∇λ_3 = (e1 × e2)/det
-  double c[3][3];
+    for (int a = 0; a < 3; ++a) e[k][a] = V[k + 1][a] - V[0][a];
   for (int k = 0; k < 3; ++k) {
     const double* p = e[(k + 1) % 3];
     const double* q = e[(k + 2) % 3];
@@ -623,7 +619,21 @@ __host__ __device__ inline void tet_geom(TetGeom& G) {
     c[k][1] = p[2] * q[0] - p[0] * q[2];
     c[k][2] = p[0] * q[1] - p[1] * q[0];
   }
-  G.det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+  return e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+}
+
+__host__ __device__ inline void tet_box(TetGeom& G) {
+  for (int a = 0; a < 3; ++a) {
+    G.mn[a] = fmin(fmin(G.V[0][a], G.V[1][a]), fmin(G.V[2][a], G.V[3][a]));
+    G.mx[a] = fmax(fmax(G.V[0][a], G.V[1][a]), fmax(G.V[2][a], G.V[3][a]));
+  }
+}
+
+__host__ __device__ inline void tet_geom(TetGeom& G) {
+  tet_box(G);
+  // cofactor rows: ∇λ_1 = (e2 × e3)/det, ∇λ_2 = (e3 × e1)/det, ∇λ_3 = (e1 × e2)/det
+  double c[3][3];
+  G.det = tet_det(G.V, c);
   const double inv = (G.det != 0.0) ? 1.0 / G.det : 0.0;
   for (int a = 0; a < 3; ++a) {
     G.g[1][a] = c[0][a] * inv;
@@ -633,26 +643,22 @@ __host__ __device__ inline void tet_geom(TetGeom& G) {
   }
 }
 
-// Per-tet record read by every pair of the tet: the four vertices and the
-// determinant e1·(e2 × e3) (16 doubles, one 128-byte line).
-constexpr int kTetRec = 16;
+// Per-tet record read by every pair of the tet: its four vertices (12
+// doubles, 96 bytes; the determinant is recomputed where it is needed).
+constexpr int kTetRec = 12;
 
 __host__ __device__ inline void store_tet_rec(const TetGeom& G, double* r) {
   for (int k = 0; k < 4; ++k)
     for (int e = 0; e < 3; ++e) r[3 * k + e] = G.V[k][e];
-  r[12] = G.det;
-  r[13] = r[14] = r[15] = 0.0;
 }
 
 // Vertices, determinant and bounding box from a tet record (gradients unset).
 __host__ __device__ inline void load_tet_box(TetGeom& G, const double r[kTetRec]) {
   for (int k = 0; k < 4; ++k)
     for (int e = 0; e < 3; ++e) G.V[k][e] = r[3 * k + e];
-  G.det = r[12];
-  for (int a = 0; a < 3; ++a) {
-    G.mn[a] = fmin(fmin(G.V[0][a], G.V[1][a]), fmin(G.V[2][a], G.V[3][a]));
-    G.mx[a] = fmax(fmax(G.V[0][a], G.V[1][a]), fmax(G.V[2][a], G.V[3][a]));
-  }
+  double c[3][3];
+  G.det = tet_det(G.V, c);
+  tet_box(G);
 }
 
 // λ_i in cell-local coordinates: λ_i(ξ) = λ_i(lo) + (∇λ_i ∘ h)·ξ.
@@ -679,20 +685,31 @@ __host__ __device__ inline void rec_cell_lambda(const double r[kTetRec], const d
   cell_lambda<T>(G, lo, hi, LA, LG);
 }
 
-// Sub-tetrahedron record of the piece store: 4 vertices (cell-local) and
-// the determinant, kRecord values of type T.
-constexpr int kRecord = 13;
+// Sub-tetrahedron record of the piece store: its 4 vertices (cell-local),
+// kRecord values of type T (whole 16-byte words; the determinant follows
+// from the vertices, subtet_det).
+constexpr int kRecord = 12;
+
+// Determinant d0 · (d1 × d2), d_k = y_{k+1} − y_0, of a sub-tetrahedron (the
+// same expression the clip sums into the piece volume).
+template <typename T>
+__host__ __device__ __forceinline__ T subtet_det(const T ya[3], const T yv[3], const T y1[3],
+                                                 const T y2[3]) {
+  const T d0[3] = {yv[0] - ya[0], yv[1] - ya[1], yv[2] - ya[2]};
+  const T d1[3] = {y1[0] - ya[0], y1[1] - ya[1], y1[2] - ya[2]};
+  const T d2[3] = {y2[0] - ya[0], y2[1] - ya[1], y2[2] - ya[2]};
+  return d0[0] * (d1[1] * d2[2] - d1[2] * d2[1]) - d0[1] * (d1[0] * d2[2] - d1[2] * d2[0]) +
+         d0[2] * (d1[0] * d2[1] - d1[1] * d2[0]);
+}
 
 // Clip tet ∩ box and integrate.  Returns false on a capacity/walk failure.
 // vol6 receives 6·|piece| in cell-local units (times the cell volume gives
 // 6|piece|), acc the 32 unscaled sums (caller scales by cellvol/6·(−1)).
-// The piece must already be clipped (live = its vertex mask).  With rec
-// non-null, the first `cap` sub-tetrahedra are also written there.
+// The piece must already be clipped (live = its vertex mask).
 template <typename T>
 __host__ __device__ inline bool integrate_piece(const PolyView& P, uint32_t live, const TetGeom& G,
                                                 const double lo[3], const double hi[3],
-                                                double& vol6, T acc[32], int& nsub, T* rec,
-                                                int cap) {
+                                                double& vol6, T acc[32], int& nsub) {
   for (int k = 0; k < 32; ++k) acc[k] = T(0);
   vol6 = 0.0;
   nsub = 0;
@@ -716,12 +733,6 @@ __host__ __device__ inline bool integrate_piece(const PolyView& P, uint32_t live
     T y[4][3];
     for (int v = 0; v < 4; ++v)
       for (int e = 0; e < 3; ++e) y[v][e] = T(yd[v][e]);
-    if (rec && nsub < cap) {
-      T* r = rec + nsub * kRecord;
-      for (int v = 0; v < 4; ++v)
-        for (int e = 0; e < 3; ++e) r[v * 3 + e] = y[v][e];
-      r[12] = T(det);
-    }
     ++nsub;
     subtet_integrate<T>(y, T(det), LA, LG, acc);
   });
@@ -757,16 +768,16 @@ __host__ __device__ inline int poly_fan_prepare(const PolyView& P, uint32_t live
   return total;
 }
 
-// Write the fan's sub-tetrahedra of a clipped piece as records (cell-local
-// coordinates and determinant, rounded to T) at rec (up to cap of them);
+// Hand the fan's sub-tetrahedra of a clipped piece to put(k, r) in fan
+// order (k = 0, 1, ...; r = the record: cell-local vertices rounded to T);
 // vol6 receives the piece's 6·volume in cell-local units (double).  The faces
 // not marked in `seen` are walked once each; the apex, the face's first
 // vertex and the previous vertex stay in registers, so each sub-tetrahedron
 // reads one new vertex.
-template <typename T>
+template <typename T, typename Put>
 __host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, uint64_t seen,
-                                             const double lo[3], const double hi[3], T* rec,
-                                             int cap, double& vol6, int& nsub) {
+                                             const double lo[3], const double hi[3], Put&& put,
+                                             double& vol6, int& nsub) {
   vol6 = 0.0;
   nsub = 0;
   if (!live) return true;
@@ -786,7 +797,6 @@ __host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, u
     const uint32_t vw = P.nb(v);
     double yv[3];
     local(v, yv);
-    const double d0[3] = {yv[0] - ya[0], yv[1] - ya[1], yv[2] - ya[2]};
     for (int k = 0; k < 3; ++k) {
       if ((seen >> (3 * v + k)) & 1ull) continue;
       seen |= 1ull << (3 * v + k);
@@ -801,22 +811,15 @@ __host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, u
         if (f2 == v) break;
         double y2[3];
         local(f2, y2);
-        const double d1[3] = {y1[0] - ya[0], y1[1] - ya[1], y1[2] - ya[2]};
-        const double d2[3] = {y2[0] - ya[0], y2[1] - ya[1], y2[2] - ya[2]};
-        const double det = d0[0] * (d1[1] * d2[2] - d1[2] * d2[1]) -
-                           d0[1] * (d1[0] * d2[2] - d1[2] * d2[0]) +
-                           d0[2] * (d1[0] * d2[1] - d1[1] * d2[0]);
-        vsum += det;
-        if (rec && nsub < cap) {
-          T* r = rec + nsub * kRecord;
-          for (int e = 0; e < 3; ++e) {
-            r[e] = T(ya[e]);
-            r[3 + e] = T(yv[e]);
-            r[6 + e] = T(y1[e]);
-            r[9 + e] = T(y2[e]);
-          }
-          r[12] = T(det);
+        vsum += subtet_det<double>(ya, yv, y1, y2);
+        T r[kRecord];
+        for (int e = 0; e < 3; ++e) {
+          r[e] = T(ya[e]);
+          r[3 + e] = T(yv[e]);
+          r[6 + e] = T(y1[e]);
+          r[9 + e] = T(y2[e]);
         }
+        put(nsub, r);
         ++nsub;
         prev = f1;
         f1 = f2;
@@ -841,7 +844,7 @@ __host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom&
     nsub = 0;
     return false;
   }
-  return integrate_piece<T>(P, live, G, lo, hi, vol6, acc, nsub, nullptr, 0);
+  return integrate_piece<T>(P, live, G, lo, hi, vol6, acc, nsub);
 }
 
 // Clip tet ∩ box and call sub(y, det) for every sub-tetrahedron (cell-local

@@ -358,6 +358,7 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
 
 int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,
                    int mass, double alpha, double* gX, hipStream_t s) {
+  if (c->matrix_free) return shape_gradient_matfree(c, z, u, us, mass, alpha, gX, s);
   if (c->precision == IBVT_FP32_MIXED) return shape_typed<float>(c, z, u, us, mass, alpha, gX, s);
   return shape_typed<double>(c, z, u, us, mass, alpha, gX, s);
 }

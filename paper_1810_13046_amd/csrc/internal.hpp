@@ -61,6 +61,54 @@ __device__ __forceinline__ void pair_cell(int64_t p, int64_t n_t, const int32_t*
   }
 }
 
+// A (tet, component, cell) pair as the clip reads it: the pair's index,
+// the tet and component (t | d << 30) and the cell (three lattice indices of
+// kCellBits bits).  Written next to the sort key and carried by the sort
+// into clip order, so the clip reads one 16-byte word per pair.
+struct PairDesc {
+  int32_t p;
+  uint32_t td;
+  uint64_t cell;
+};
+constexpr int kCellBits = 21;
+constexpr int64_t kMaxDescTets = int64_t(1) << 30;
+
+__device__ __forceinline__ PairDesc pair_desc(int64_t p, int64_t n_t, const int32_t* owner,
+                                              const int64_t* pair_off, const CellRange* rng) {
+  const int64_t tc = owner[p];
+  const int d = (tc >= n_t) + (tc >= 2 * n_t);
+  const int64_t t = tc - int64_t(d) * n_t;
+  const CellRange r = rng[tc];
+  const uint32_t q = uint32_t(p - pair_off[tc]);
+  const uint32_t n0 = uint32_t(r.n[0]), n1 = uint32_t(r.n[1]);
+  const uint32_t qy = q / n0, qz = qy / n1;
+  PairDesc o;
+  o.p = int32_t(p);
+  o.td = uint32_t(t) | (uint32_t(d) << 30);
+  o.cell = uint64_t(uint32_t(r.lo[0]) + (q - qy * n0)) |
+           (uint64_t(uint32_t(r.lo[1]) + (qy - qz * n1)) << kCellBits) |
+           (uint64_t(uint32_t(r.lo[2]) + qz) << (2 * kCellBits));
+  return o;
+}
+
+// Cell of a described pair and its box [lo, hi].
+__device__ __forceinline__ void desc_cell(const PairDesc& q, const double* lat, const LatDesc& ld,
+                                          int64_t& p, int& d, int64_t& t, int ci[3], double lo[3],
+                                          double hi[3]) {
+  constexpr uint64_t m = (uint64_t(1) << kCellBits) - 1;
+  p = q.p;
+  d = int(q.td >> 30);
+  t = int64_t(q.td & ((1u << 30) - 1u));
+  ci[0] = int(q.cell & m);
+  ci[1] = int((q.cell >> kCellBits) & m);
+  ci[2] = int(q.cell >> (2 * kCellBits));
+  for (int e = 0; e < 3; ++e) {
+    const double* L = lat + ld.off[3 * d + e];
+    lo[e] = L[ci[e]];
+    hi[e] = L[ci[e] + 1];
+  }
+}
+
 struct AsmStats {
   int64_t pairs = 0, pieces = 0, dropped = 0, zero_tets = 0, subtets = 0;
   int64_t dist_evals = 0, cut_points = 0;  // clip work of the last assembly
@@ -72,6 +120,7 @@ struct AsmStats {
 
 struct ibvt_coupling {
   hipStream_t stream = nullptr;  // stream of the current call: buffers grow and shrink on it
+  ibvt_alloc alloc{};            // allocator of the handle's buffers (null: hipMallocAsync)
   int precision = IBVT_FP64;
   uint32_t flags = 0;
   int dim = 3;    // 3: tetrahedra in a 3D grid; 2: triangles in a planar grid
@@ -111,6 +160,7 @@ struct ibvt_coupling {
   ibvt::DevBuf pmom;         // T n_pairs*kMomPad: per-pair piece moments (reverse mode)
   ibvt::DevBuf keep;         // uint8 n_pairs
   bool store_pieces = true;  // keep the moments of every piece (reverse mode)
+  bool matrix_free = false;  // IBVT_NO_STORE_B: no B, B^T or per-pair data; products clip again
   bool dual = false;         // B holds the dual-multiplier integrals ∫ ψ_i N_j
   ibvt::DevBuf pool;         // T records of kRecord values
   int64_t pool_cap = 0;      // records
@@ -144,6 +194,7 @@ struct ibvt_coupling {
   ibvt::DevBuf zbuf;         // solid-sized scratch of the reverse-mode calls
   int64_t* host_rb = nullptr;  // pinned host block of the packed read-backs (hipHostMalloc)
   ibvt::DevBuf rb;           // device block gathered for one read-back
+  ibvt::DevBuf bodyinfo;     // coupling_body_info: offsets and per-body sums
   unsigned host_flags = 0;   // status flags of the last packed read-back
   ibvt::AsmStats stats;
   int64_t device_bytes = 0;
@@ -224,9 +275,9 @@ size_t sort_pass_bytes(int64_t n, int bits);
 // of digit k is at [k * sort_tiles(n)] of this array (device); entry
 // 2^bits * sort_tiles(n) holds n
 const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits);
-// order = index_base + (the indices 0..n-1 stably sorted by their 8-bit keys)
-int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
-                      void* scratch, hipStream_t s, int64_t index_base = 0);
+// out = the pair descriptors desc[0..n-1] stably sorted by their 8-bit keys
+int order_pairs_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys,
+                            const PairDesc* desc, PairDesc* out, void* scratch, hipStream_t s);
 // stable sort of (keys, vals) by keys < 2^end_bit in digit passes of at
 // most 8 bits, alternating with (keys_tmp, vals_tmp); *in_tmp tells where
 // the result is.  scratch: sort_pass_bytes(n, 8) bytes.
@@ -245,6 +296,15 @@ int mass_solve(ibvt_coupling* c, const void* rhs, void* x, double rtol, int maxi
 size_t mass_solve_workspace_bytes(const ibvt_coupling* c);
 int lumped_solve(ibvt_coupling* c, const void* rhs, void* x, hipStream_t s);
 int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream_t s);
+
+// matfree.hip: the products and the shape gradient of a coupling built with
+// IBVT_NO_STORE_B, clipping and integrating every piece again
+int apply_B_matfree(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale,
+                    hipStream_t s);
+int apply_Bt_matfree(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,
+                     hipStream_t s);
+int shape_gradient_matfree(ibvt_coupling* c, const void* z, const void* const u[3],
+                           const void* us, int mass, double alpha, double* gX, hipStream_t s);
 
 // grad.hip
 int shape_gradient(ibvt_coupling* c, const void* z, const void* const u[3], const void* us,

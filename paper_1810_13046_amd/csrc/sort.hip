@@ -75,8 +75,8 @@ __global__ __launch_bounds__(kWave * kSortWaves) void k_digit_count(
 // (the lanes with the same digit find each other by one ballot per digit
 // bit and take consecutive places in lane order) and put in LDS in digit
 // order; the wave then writes the staged tile out, so the items of one
-// digit leave as a run of consecutive addresses.  vals_in == nullptr: the
-// value carried is vbase plus the item's index.
+// digit leave as a run of consecutive addresses.  The value carried with
+// item i is src.load<W>(i, active) (an input array's entry).
 // Values travel as raw words of their size (no per-field work on them),
 // held as native vectors so that they stay in registers.
 typedef uint32_t RawWord2 __attribute__((ext_vector_type(2)));
@@ -86,11 +86,21 @@ using RawWord = std::conditional_t<
     sizeof(V) == 16, RawWord4,
     std::conditional_t<sizeof(V) == 8, RawWord2, std::conditional_t<sizeof(V) == 4, uint32_t, V>>>;
 
-template <typename K, typename V, int BITS, int R>
+// values from an array (entry 0 stands in past the end; n >= 1)
+template <typename V>
+struct ArrayVals {
+  const V* v;
+  template <typename W>
+  __device__ __forceinline__ W load(int64_t i, bool act) const {
+    return reinterpret_cast<const W*>(v)[act ? i : 0];
+  }
+};
+
+template <typename K, typename V, int BITS, int R, typename Src>
 __global__ __launch_bounds__(kWave) void k_digit_scatter(
-    int64_t n, const K* __restrict__ keys_in, const V* __restrict__ vals_in, int64_t vbase,
-    int shift, int64_t ntiles, const int32_t* __restrict__ hist, const int64_t* __restrict__ off,
-    K* __restrict__ keys_out, V* __restrict__ vals_out) {
+    int64_t n, const K* __restrict__ keys_in, Src src, int shift, int64_t ntiles,
+    const int32_t* __restrict__ hist, const int64_t* __restrict__ off, K* __restrict__ keys_out,
+    V* __restrict__ vals_out) {
   constexpr int kBins = 1 << BITS;
   constexpr int kPer = (kBins + kWave - 1) / kWave;  // bins per lane in the local scan
   constexpr int kTile = R * kWave;
@@ -98,7 +108,6 @@ __global__ __launch_bounds__(kWave) void k_digit_scatter(
   static_assert(sizeof(W) == sizeof(V), "value word size");
   __shared__ K sk[kTile];
   __shared__ W sv[kTile];
-  const W* __restrict__ win = reinterpret_cast<const W*>(vals_in);
   W* __restrict__ wout = reinterpret_cast<W*>(vals_out);
   __shared__ int32_t lstart[kBins], run[kBins];
   __shared__ int64_t gstart[kBins];
@@ -141,11 +150,7 @@ __global__ __launch_bounds__(kWave) void k_digit_scatter(
     const int64_t i = base + int64_t(r) * kWave + lane;
     const bool act = i < n;
     kv[r] = act ? keys_in[i] : K(0);
-    if constexpr (std::is_integral<V>::value && sizeof(V) == 4) {
-      vv[r] = win ? (act ? win[i] : W(0)) : W(uint32_t(vbase + i));  // < 2^31
-    } else {
-      vv[r] = win[act ? i : 0];  // n >= 1: item 0 stands in past the end
-    }
+    vv[r] = src.template load<W>(i, act);
   }
 #pragma clang loop unroll(full)
   for (int r = 0; r < R; ++r) {
@@ -192,7 +197,7 @@ int64_t tiles_for(int64_t n, int rounds) { return ceil_div(n > 0 ? n : 1, int64_
 size_t hist_bytes(int64_t m) { return (size_t(m + 1) * sizeof(int32_t) + 255) & ~size_t(255); }
 }  // namespace
 
-int64_t sort_tiles(int64_t n) { return tiles_for(n, sort_rounds<int32_t>()); }
+int64_t sort_tiles(int64_t n) { return tiles_for(n, sort_rounds<PairDesc>()); }
 
 // Scratch bytes of one pass with 2^bits digits (histogram and offsets), for
 // the smallest tiles any value type takes.
@@ -201,15 +206,15 @@ size_t sort_pass_bytes(int64_t n, int bits) {
   return hist_bytes(m) + size_t(m + 1) * sizeof(int64_t) + 256;
 }
 
-// (for 4-byte values, as the pair order carries)
+// (for the pair order's 16-byte descriptors)
 const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits) {
   const int64_t m = (int64_t(1) << bits) * sort_tiles(n);
   return reinterpret_cast<const int64_t*>(static_cast<const char*>(scratch) + hist_bytes(m));
 }
 
-template <typename K, typename V, int BITS>
-int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, const V* vals_in, int shift,
-               K* keys_out, V* vals_out, void* scratch, hipStream_t s, int64_t vbase = 0) {
+template <typename K, typename V, int BITS, typename Src>
+int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, Src src, int shift, K* keys_out,
+               V* vals_out, void* scratch, hipStream_t s) {
   constexpr int R = sort_rounds<V>();
   const int64_t ntiles = tiles_for(n, R);
   const int64_t m = (int64_t(1) << BITS) * ntiles;
@@ -220,16 +225,17 @@ int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, const V* vals_in, 
   int st = hip_check(hipGetLastError(), "digit count launch");
   if (st) return st;
   if ((st = scan_i32_to_i64(c, hist, off, m, s))) return st;
-  k_digit_scatter<K, V, BITS, R><<<unsigned(ntiles), kWave, 0, s>>>(
-      n, keys_in, vals_in, vbase, shift, ntiles, hist, off, keys_out, vals_out);
+  k_digit_scatter<K, V, BITS, R, Src><<<unsigned(ntiles), kWave, 0, s>>>(
+      n, keys_in, src, shift, ntiles, hist, off, keys_out, vals_out);
   return hip_check(hipGetLastError(), "digit scatter launch");
 }
 
-int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
-                      void* scratch, hipStream_t s, int64_t index_base) {
+int order_pairs_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys,
+                            const PairDesc* desc, PairDesc* out, void* scratch, hipStream_t s) {
   if (n <= 0) return IBVT_OK;
-  return digit_pass<uint8_t, int32_t, 8>(c, n, keys, nullptr, 0, nullptr, order, scratch, s,
-                                         index_base);
+  static_assert(sizeof(PairDesc) == 16, "16-byte pair descriptor");
+  return digit_pass<uint8_t, PairDesc, 8>(c, n, keys, ArrayVals<PairDesc>{desc}, 0, nullptr, out,
+                                          scratch, s);
 }
 
 template <typename V, int B>
@@ -240,7 +246,7 @@ int digit_passes(ibvt_coupling* c, int64_t n, int passes, int32_t* keys, V* vals
   int32_t* kout = keys_tmp;
   V* vout = vals_tmp;
   for (int p = 0; p < passes; ++p) {
-    int st = digit_pass<int32_t, V, B>(c, n, kin, vin, p * B, kout, vout, scratch, s);
+    int st = digit_pass<int32_t, V, B>(c, n, kin, ArrayVals<V>{vin}, p * B, kout, vout, scratch, s);
     if (st) return st;
     std::swap(kin, kout);
     std::swap(vin, vout);

@@ -29,6 +29,7 @@ LUMPED, CONSISTENT = 0, 1
 BUILD_CONSISTENT_M = 1
 NO_PIECE_STORE = 2
 DUAL_BASIS = 4
+NO_STORE_B = 8
 FORCE_IS_LOAD = 1
 
 EXPORTED = [
@@ -38,6 +39,7 @@ EXPORTED = [
     "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
     "assemble_coupling_2d", "ibvt_lattice_coords_2d", "assemble_coupling_unstructured",
     "transfer_vjp", "ibvt_fluid_lumped_volume_2d", "transfer_velocity_noalloc",
+    "coupling_body_info", "ibvt_set_allocator",
 ]
 
 
@@ -81,7 +83,21 @@ class _Info(ctypes.Structure):
                 ("assemblies", ctypes.c_int64), ("subtets", ctypes.c_int64),
                 ("piece_store", ctypes.c_int64), ("dist_evals", ctypes.c_int64),
                 ("cut_points", ctypes.c_int64), ("dual", ctypes.c_int64), ("dim", ctypes.c_int64),
-                ("unstructured", ctypes.c_int64), ("plane_cuts", ctypes.c_int64)]
+                ("unstructured", ctypes.c_int64), ("plane_cuts", ctypes.c_int64),
+                ("matrix_free", ctypes.c_int64)]
+
+
+class _BodyInfo(ctypes.Structure):
+    _fields_ = [("tets", ctypes.c_int64), ("zero_tets", ctypes.c_int64), ("pairs", ctypes.c_int64),
+                ("pieces", ctypes.c_int64), ("volume", ctypes.c_double)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Alloc(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 _lib = None
@@ -151,15 +167,49 @@ def load_library(path: str = LIB_PATH):
     lib.assemble_coupling_unstructured.argtypes = [P(_Mesh), P(_Mesh), ctypes.c_int, u32, vp, P(vp)]
     lib.transfer_vjp.argtypes = [vp, vp, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int, P(vp),
                                  P(vp), vp, dbl, vp, vp, vp]
+    lib.coupling_body_info.argtypes = [vp, i32, P(i64), P(_BodyInfo), vp]
+    lib.ibvt_set_allocator.argtypes = [P(_Alloc)]
     for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
                  "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d",
                  "assemble_coupling_unstructured", "transfer_vjp", "ibvt_fluid_lumped_volume_2d",
-                 "transfer_velocity_noalloc"):
+                 "transfer_velocity_noalloc", "coupling_body_info", "ibvt_set_allocator"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+# torch's caching allocator behind ibvt_set_allocator (the callbacks must
+# outlive every coupling created while they are set)
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  stream or 0)
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:
+        pass
+
+
+_TORCH_ALLOC = _Alloc(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Couplings created after this call take their device buffers from
+    torch's caching allocator (enable=True) or from hipMallocAsync
+    (enable=False); each coupling frees with the allocator it was made with
+    (ibvt_set_allocator)."""
+    lib = load_library()
+    _check(lib.ibvt_set_allocator(ctypes.byref(_TORCH_ALLOC) if enable else None),
+           "ibvt_set_allocator")
 
 
 def _check(st: int, where: str):
@@ -273,10 +323,13 @@ class Coupling:
     fluid fields are 2 arrays of shape (n_y, n_x).  With fluid_mesh =
     (X_f, tets_f) (device tensors, a P1 tetrahedral fluid mesh) and faces =
     None the background is unstructured (assemble_coupling_unstructured):
-    the fluid fields are 3 nodal arrays of the fluid mesh's vertices."""
+    the fluid fields are 3 nodal arrays of the fluid mesh's vertices.
+    store_B=False (3D grids only) keeps no matrices: every transfer and
+    adjoint clips and integrates the pieces again (IBVT_NO_STORE_B)."""
 
     def __init__(self, faces, X, tets, precision: str = "fp64", consistent: bool = True,
-                 store_pieces: bool = True, dual: bool = False, stream=None, fluid_mesh=None):
+                 store_pieces: bool = True, dual: bool = False, stream=None, fluid_mesh=None,
+                 store_B: bool = True):
         import torch
         lib = load_library()
         if precision not in ("fp64", "fp32"):
@@ -286,6 +339,8 @@ class Coupling:
         self.dual = bool(dual)
         self.consistent = consistent
         if fluid_mesh is not None:
+            if not store_B:
+                raise ValueError("store_B=False is for grid couplings")
             self._init_unstructured(fluid_mesh, X, tets, precision, consistent, dual, stream)
             return
         self.faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
@@ -309,7 +364,7 @@ class Coupling:
             m.n_tri, m.X, m.tris = self.n_tet, Xp, Tp
         h = ctypes.c_void_p()
         flags = ((BUILD_CONSISTENT_M if consistent else 0) | (0 if store_pieces else NO_PIECE_STORE) |
-                 (DUAL_BASIS if dual else 0))
+                 (DUAL_BASIS if dual else 0) | (0 if store_B else NO_STORE_B))
         self.dual = bool(dual)
         fn = lib.assemble_coupling if self.dim == 3 else lib.assemble_coupling_2d
         _check(fn(ctypes.byref(g), ctypes.byref(m), FP64 if precision == "fp64" else FP32_MIXED,
@@ -539,7 +594,21 @@ class Coupling:
                     nnz_mass=i.nnz_mass, device_bytes=i.device_bytes, assemblies=i.assemblies,
                     subtets=i.subtets, piece_store=bool(i.piece_store),
                     dist_evals=i.dist_evals, cut_points=i.cut_points, dual=bool(i.dual),
-                    dim=i.dim, unstructured=bool(i.unstructured), plane_cuts=i.plane_cuts)
+                    dim=i.dim, unstructured=bool(i.unstructured), plane_cuts=i.plane_cuts,
+                    matrix_free=bool(i.matrix_free))
+
+    def body_info(self, tet_offsets, stream=None) -> list:
+        """Per-body counters (coupling_body_info): body b holds tets
+        tet_offsets[b] .. tet_offsets[b+1]-1; a list of dicts."""
+        off = np.ascontiguousarray(np.asarray(tet_offsets, dtype=np.int64))
+        n = off.size - 1
+        if n < 1:
+            raise ValueError("tet_offsets needs at least two entries")
+        out = (_BodyInfo * n)()
+        _check(_lib.coupling_body_info(self.handle, n, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       out, _stream(stream)), "coupling_body_info")
+        return [dict(tets=b.tets, zero_tets=b.zero_tets, pairs=b.pairs, pieces=b.pieces,
+                     volume=b.volume) for b in out]
 
     def export_csr(self, comp: int, transposed: bool = False):
         """(row_ptr, col, val[, row_map]) as numpy arrays (synchronizes)."""

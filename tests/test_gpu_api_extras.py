@@ -1,0 +1,98 @@
+"""Two interface extras on the HIP path, through the C ABI: the per-body
+counters (coupling_body_info) and a caller-supplied device allocator
+(ibvt_set_allocator, here PyTorch's caching allocator).
+
+Per-body counters are checked against what the mesh fixes by itself
+(each body's tet count, zero-volume tets and volume from the vertex
+coordinates, in numpy) and against coupling_info's totals; the transfers of
+a coupling whose buffers come from the caller's allocator against the FP64
+oracle (1e-12 relative)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_common import fluid_fields, rel_fro, require_gpu, say, to_dev, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def tet_volumes(X, T):
+    P = X[T]
+    e = P[:, 1:, :] - P[:, :1, :]
+    return np.abs(np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2]))) / 6.0
+
+
+@pytest.mark.parametrize("store_B", [True, False])
+def test_body_counters(dev, store_B):
+    import torch
+    from paper_1810_13046_amd import Coupling, IbvtError
+    W = workload("three_bodies12k_grid512x256x256s")
+    off = np.asarray(W.body_tet_offsets, dtype=np.int64)
+    assert off.size >= 3 and off[0] == 0 and off[-1] == W.tets.shape[0]
+    say(f"[gpu] body counters store_B={store_B}: {off.size - 1} bodies")
+    c = Coupling(W.faces, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
+                 precision="fp64", store_B=store_B)
+    bodies = c.body_info(off)
+    info = c.info()
+    vol = tet_volumes(W.X, W.tets)
+    for b, r in enumerate(bodies):
+        v = vol[off[b]:off[b + 1]]
+        assert r["tets"] == off[b + 1] - off[b]
+        assert r["zero_tets"] == int(np.count_nonzero(v == 0.0))
+        assert abs(r["volume"] - v.sum()) <= 1e-12 * v.sum()
+        assert r["pairs"] > 0
+        assert r["pieces"] == (-1 if not store_B else r["pieces"])
+    assert sum(r["pairs"] for r in bodies) == info["pairs"]
+    assert sum(r["zero_tets"] for r in bodies) == info["zero_tets"]
+    if store_B:
+        assert sum(r["pieces"] for r in bodies) == info["pieces"]
+        assert all(0 < r["pieces"] <= r["pairs"] for r in bodies)
+    # one body holding everything equals the totals; bad offsets are refused
+    whole = c.body_info([0, W.tets.shape[0]])[0]
+    assert whole["pairs"] == info["pairs"]
+    for bad in ([1, W.tets.shape[0]], [0, W.tets.shape[0] - 1], [0, 10, 5, W.tets.shape[0]]):
+        with pytest.raises(IbvtError):
+            c.body_info(bad)
+    c.free()
+
+
+def test_caller_allocator(dev):
+    import torch
+    from paper_1810_13046_amd import Coupling, use_torch_allocator
+    W = workload("plate4320_grid256s_tilted")
+    R = oracle.assemble(W.faces, W.X, W.tets)
+    X = to_dev(W.X, torch.float64, dev)
+    T = to_dev(W.tets, torch.int32, dev)
+    u_f = fluid_fields(W)
+    ud = [to_dev(u, torch.float64, dev) for u in u_f]
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated(dev)
+    use_torch_allocator(True)
+    try:
+        say("[gpu] coupling on torch's caching allocator")
+        c = Coupling(W.faces, X, T, precision="fp64", consistent=True)
+        torch.cuda.synchronize()
+        held = torch.cuda.memory_allocated(dev) - before
+        nbytes = c.info()["device_bytes"]
+        say(f"  device_bytes {nbytes}, torch allocated {held}")
+        assert nbytes > 0 and held >= nbytes
+        us = c.velocity(ud, mass="consistent", rtol=1e-14).cpu().numpy()
+        assert rel_fro(us, oracle.transfer_velocity(R, u_f, "consistent")) <= 5e-12
+        c.reassemble(X)
+        us = c.velocity(ud, mass="lumped").cpu().numpy()
+        assert rel_fro(us, oracle.transfer_velocity(R, u_f, "lumped")) <= 1e-12
+        c.free()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated(dev) == before
+    finally:
+        use_torch_allocator(False)
+    # the default allocator again: torch's count does not move
+    c = Coupling(W.faces, X, T, precision="fp64", consistent=True)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated(dev) == before
+    c.free()
