@@ -910,6 +910,9 @@ void coupling_free(ibvt_coupling* c) {
   c->stream = nullptr;  // the caller's streams may be gone: free on the null stream
   release_all(c);
   (void)hipStreamSynchronize(nullptr);
+  for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_sorted})
+    if (e) (void)hipEventDestroy(e);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
 }
 

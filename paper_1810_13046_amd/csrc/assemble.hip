@@ -946,6 +946,19 @@ int read_counts(ibvt_coupling* c, const int64_t* const* srcs, int n, int64_t* ou
 
 namespace {
 
+// The assembly's second stream and its events, made on first use (default
+// priority, no timing) and destroyed with the handle.
+int side_stream(ibvt_coupling* c) {
+  int st;
+  if (!c->side &&
+      (st = hip_check(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "stream")))
+    return st;
+  for (hipEvent_t* e : {&c->ev_fork, &c->ev_join, &c->ev_sorted})
+    if (!*e && (st = hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "event")))
+      return st;
+  return IBVT_OK;
+}
+
 // Without stored matrices (IBVT_NO_STORE_B): after the overlap candidates,
 // only the solid masses and the per-(component, tet) buffer of the
 // matrix-free products (3 n_t x 4 values) are built.
@@ -1039,6 +1052,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   uint8_t* keys = c->pscan.as<uint8_t>();
   PairDesc* desc_in = reinterpret_cast<PairDesc*>(c->pscan.as<char>() + kb);
   void* sort_scratch = c->pscan.as<char>() + kb + db;
+  if ((st = side_stream(c))) return st;
   // (IV, set-up) each row's node box: from the cell ranges alone
   if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
   if ((st = ensure(c, c->rowcap, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
@@ -1068,19 +1082,30 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
                                        kMaxChunks * sizeof(unsigned long long), s),
                         "memset")))
       return st;
-    for (int ch = 0; ch < nchunk; ++ch) {
+    // Chunks with pairs, in order.  Per chunk: the clip's classes 12 and 16
+    // run on the side stream beside class 10 (they fill its tail), and the
+    // next chunk's pair order is made on the side stream while this chunk
+    // integrates (the order and the sort scratch are free once the clip has
+    // read them; the store is reused only after the integration).
+    int live[kMaxChunks];
+    int n_live = 0;
+    for (int ch = 0; ch < nchunk; ++ch)
+      if (pat[ch + 1] > pat[ch]) live[n_live++] = ch;
+    auto order_chunk = [&](int ch, hipStream_t q) -> int {
       const int64_t p0 = pat[ch], nc = pat[ch + 1] - pat[ch];
-      if (nc <= 0) continue;
-      {
-        ProfScope ps("pair_order", s);
-        k_pair_key<<<blocks_for(nc, 256), 256, 0, s>>>(p0, nc, n_t, c->owner.as<int32_t>(),
-                                                      c->pair_off.as<int64_t>(),
-                                                      c->rng.as<CellRange>(), keys, desc_in);
-        if ((st = hip_check(hipGetLastError(), "pair key launch"))) return st;
-        if ((st = order_pairs_by_byte_key(c, nc, keys, desc_in, c->order.as<PairDesc>(),
-                                          sort_scratch, s)))
-          return st;
-      }
+      ProfScope ps("pair_order", q);
+      k_pair_key<<<blocks_for(nc, 256), 256, 0, q>>>(p0, nc, n_t, c->owner.as<int32_t>(),
+                                                    c->pair_off.as<int64_t>(),
+                                                    c->rng.as<CellRange>(), keys, desc_in);
+      int r = hip_check(hipGetLastError(), "pair key launch");
+      if (r) return r;
+      return order_pairs_by_byte_key(c, nc, keys, desc_in, c->order.as<PairDesc>(), sort_scratch,
+                                     q);
+    };
+    if (n_live > 0 && (st = order_chunk(live[0], s))) return st;
+    for (int li = 0; li < n_live; ++li) {
+      const int ch = live[li];
+      const int64_t p0 = pat[ch], nc = pat[ch + 1] - pat[ch];
       const int64_t* cls_start = sort_digit_starts(sort_scratch, nc, 8);
       const int64_t ntiles = sort_tiles(nc);
       {
@@ -1088,7 +1113,11 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
         // slots per lane, more resident waves); each launch reads its
         // class's stretch of the order from the sort's digit starts
         ProfScope ps("clip", s);
-        for (int k = 0; k < 3; ++k) {
+        if ((st = hip_check(hipEventRecord(c->ev_fork, s), "event")) ||
+            (st = hip_check(hipStreamWaitEvent(c->side, c->ev_fork, 0), "stream wait")))
+          return st;
+        for (int k = 2; k >= 0; --k) {
+          hipStream_t ks = k == 0 ? s : c->side;
           const int resident =
               k == 0 ? resident_blocks(k_clip<T, 10>)
                      : (k == 1 ? resident_blocks(k_clip<T, 12>) : resident_blocks(k_clip<T, kMaxV>));
@@ -1097,13 +1126,24 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   cls_start + 64 * k * ntiles, cls_start + 64 * (k + 1) * ntiles, c->order.as<PairDesc>(),    \
       c->tetrec.as<double>(), c->lat.as<double>(), c->ld, 1e-14, c->pool.as<T>(), c->pool_cap,  \
       c->pinfo.as<uint64_t>(), counters + kCntChunkPool + ch, flags, counters
-          if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-          else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
-          else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, s>>>(IBVT_CLIP_ARGS);
+          if (k == 0) k_clip<T, 10><<<dim3(unsigned(nb)), kWave, 0, ks>>>(IBVT_CLIP_ARGS);
+          else if (k == 1) k_clip<T, 12><<<dim3(unsigned(nb)), kWave, 0, ks>>>(IBVT_CLIP_ARGS);
+          else k_clip<T, kMaxV><<<dim3(unsigned(nb)), kWave, 0, ks>>>(IBVT_CLIP_ARGS);
 #undef IBVT_CLIP_ARGS
         }
+        if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
+        if ((st = hip_check(hipEventRecord(c->ev_join, c->side), "event")) ||
+            (st = hip_check(hipStreamWaitEvent(s, c->ev_join, 0), "stream wait")))
+          return st;
       }
-      if ((st = hip_check(hipGetLastError(), "clip launch"))) return st;
+      const bool next = li + 1 < n_live;
+      if (next) {
+        if ((st = hip_check(hipEventRecord(c->ev_fork, s), "event")) ||
+            (st = hip_check(hipStreamWaitEvent(c->side, c->ev_fork, 0), "stream wait")) ||
+            (st = order_chunk(live[li + 1], c->side)) ||
+            (st = hip_check(hipEventRecord(c->ev_sorted, c->side), "event")))
+          return st;
+      }
       {
         // (III) integrate the chunk's sub-tetrahedra, summed per pair (pairs
         // whose records did not fit the store read as empty)
@@ -1115,6 +1155,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
             c->pval.as<T>(), c->pmom.as<T>(), c->dual ? 1 : 0);
       }
       if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
+      if (next && (st = hip_check(hipStreamWaitEvent(s, c->ev_sorted, 0), "stream wait")))
+        return st;
     }
     // read-back 2: records each chunk asked for, the row scratch size, flags
     int64_t rb2[kMaxChunks + 1];

@@ -100,6 +100,16 @@ struct ClipCount {
   uint32_t cuts = 0;
 };
 
+// sv / den for 0 <= sv <= den, den > 0 (the parameter of a cut point on
+// an edge): the hardware reciprocal refined by two Newton steps, within an
+// ulp or two of the quotient (device code only).
+__device__ __forceinline__ double cut_param(double sv, double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(fma(-den, r, 1.0), r, r);
+  r = fma(fma(-den, r, 1.0), r, r);
+  return sv * r;
+}
+
 // Keep the half-space dist(v) >= 0, dist being the signed distance of the
 // point in slot v to the plane; a cut point is placed by interpolation and
 // then passed to place(w) (which moves it exactly onto an axis plane, or
@@ -127,16 +137,16 @@ __host__ __device__ __forceinline__ bool poly_clip_by(const PolyView& P, uint32_
     return true;
   }
   const uint32_t in = live & ~out;
-  uint32_t adj = 0;  // vertices adjacent to an inside vertex
-#pragma unroll
-  for (int v = 0; v < NS; ++v) {
-    const uint32_t w = P.nb(v);
-    if ((in >> v) & 1u) adj |= (1u << nb_get(w, 0)) | (1u << nb_get(w, 1)) | (1u << nb_get(w, 2));
+  uint32_t adj = 0;  // outside vertices with an inside neighbour
+  for (uint32_t m = out; m; m &= m - 1) {
+    const int u = ctz32(m);
+    const uint32_t w = P.nb(u);
+    if (((1u << nb_get(w, 0)) | (1u << nb_get(w, 1)) | (1u << nb_get(w, 2))) & in) adj |= 1u << u;
   }
   // free slots: never used, or outside with no inside neighbour
   uint32_t freem = (~live & P.all) | (out & ~adj);
   uint32_t newm = 0;
-  for (uint32_t m = out & adj; m; m &= m - 1) {
+  for (uint32_t m = adj; m; m &= m - 1) {
     const int u = ctz32(m);
     const double ux = P.x(u), uy = P.y(u), uz = P.z(u);
     const double su = dist(u);
@@ -147,7 +157,7 @@ __host__ __device__ __forceinline__ bool poly_clip_by(const PolyView& P, uint32_
       if (!((in >> v) & 1u)) continue;
       const double vx = P.x(v), vy = P.y(v), vz = P.z(v);
       const double sv = dist(v);
-      const double t = sv / (sv - su);
+      const double t = cut_param(sv, sv - su);
       int w;
       if (first) {
         w = u;  // v's neighbour entry already names u

@@ -121,6 +121,8 @@ struct AsmStats {
 struct ibvt_coupling {
   hipStream_t stream = nullptr;  // stream of the current call: buffers grow and shrink on it
   ibvt_alloc alloc{};            // allocator of the handle's buffers (null: hipMallocAsync)
+  hipStream_t side = nullptr;    // the assembly's second stream (default priority), and
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_sorted = nullptr;  // its joins
   int precision = IBVT_FP64;
   uint32_t flags = 0;
   int dim = 3;    // 3: tetrahedra in a 3D grid; 2: triangles in a planar grid
