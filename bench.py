@@ -688,6 +688,11 @@ def main():
         fsi = fsi_rate(mixed)
         log(f"[bench] fsi {fsi['ms_per_picard_iteration']:.2f} ms per Picard iteration")
 
+    # what the coupling holds once the assembly's scratch is released
+    mixed.c.release_scratch()
+    import torch
+    torch.cuda.synchronize()
+    bytes_released = mixed.c.info()["device_bytes"]
     fp64 = None
     if not args.skip_fp64:
         del mixed.c
@@ -795,6 +800,7 @@ def main():
                      "cut_points": info["cut_points"],
                      "nnz": info["nnz"], "touched": info["touched"],
                      "device_bytes": info["device_bytes"],
+                     "device_bytes_after_release_scratch": bytes_released,
                      "device_bytes_no_piece_store": bytes_no_store},
         "assembly_only": {**asm_mixed, "unit": "solid tets/s (reassembly: B, B^T, masses)"},
         "copy_ceiling": copy,

@@ -411,6 +411,18 @@ int transfer_vjp(ibvt_coupling* c, const void* g_us, const void* const u_f[3], c
 /* coupling_info — fill *info (host).  Errors: IBVT_E_INVALID. */
 int coupling_info(const ibvt_coupling* c, ibvt_info* info);
 
+/*
+ * coupling_release_scratch — return the device memory that only the
+ *   assembly uses (grid couplings: the piece store, the per-pair values and
+ *   record offsets, the row and transpose scratch, the pair order), keeping
+ *   what the transfers and the reverse mode read (B, B^T, masses, piece
+ *   moments, per-tet data).  For callers that hold couplings between
+ *   reassemblies; the next reassembly allocates the scratch again.  Other
+ *   couplings: nothing is released.  Stream-ordered on `stream`.
+ *   Errors: IBVT_E_INVALID (NULL handle).
+ */
+int coupling_release_scratch(ibvt_coupling* c, hipStream_t stream);
+
 /* Counters of one body: the tets of a mesh grouped into bodies by
  * consecutive index ranges. */
 typedef struct {

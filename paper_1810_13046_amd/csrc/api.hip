@@ -849,6 +849,18 @@ int ibvt_profile_read(const char** names, int64_t* launches, double* ms, int max
   return k;
 }
 
+int coupling_release_scratch(ibvt_coupling* c, hipStream_t stream) {
+  if (!c) return set_error(IBVT_E_INVALID, "NULL handle");
+  if (c->dim != 3 || c->unstructured) return IBVT_OK;
+  c->stream = stream;
+  for (DevBuf* b : {&c->pool, &c->pinfo, &c->rowtmpcol, &c->rowtmpval, &c->rowbox, &c->rowcap,
+                    &c->rowtmpoff, &c->tbuf, &c->order, &c->pscan, &c->mark, &c->cidx})
+    release(c, *b);
+  if (!c->matrix_free) release(c, c->pval);  // the matrix-free products keep their buffer
+  c->pool_cap = 0;
+  return IBVT_OK;
+}
+
 int coupling_body_info(ibvt_coupling* c, int32_t n_bodies, const int64_t* tet_offsets,
                        ibvt_body_info* out, hipStream_t stream) {
   if (!c || !tet_offsets || !out) return set_error(IBVT_E_INVALID, "NULL argument");

@@ -39,7 +39,7 @@ EXPORTED = [
     "ibvt_profile_enable", "ibvt_profile_read", "fsi_step", "ibvt_fluid_lumped_volume",
     "assemble_coupling_2d", "ibvt_lattice_coords_2d", "assemble_coupling_unstructured",
     "transfer_vjp", "ibvt_fluid_lumped_volume_2d", "transfer_velocity_noalloc",
-    "coupling_body_info", "ibvt_set_allocator",
+    "coupling_body_info", "ibvt_set_allocator", "coupling_release_scratch",
 ]
 
 
@@ -169,12 +169,14 @@ def load_library(path: str = LIB_PATH):
                                  P(vp), vp, dbl, vp, vp, vp]
     lib.coupling_body_info.argtypes = [vp, i32, P(i64), P(_BodyInfo), vp]
     lib.ibvt_set_allocator.argtypes = [P(_Alloc)]
+    lib.coupling_release_scratch.argtypes = [vp, vp]
     for name in ("assemble_coupling", "reassemble_coupling", "transfer_velocity", "transfer_force",
                  "transfer_velocity_vjp", "transfer_force_vjp", "coupling_info",
                  "coupling_export_csr", "ibvt_lattice_coords", "fsi_step",
                  "ibvt_fluid_lumped_volume", "assemble_coupling_2d", "ibvt_lattice_coords_2d",
                  "assemble_coupling_unstructured", "transfer_vjp", "ibvt_fluid_lumped_volume_2d",
-                 "transfer_velocity_noalloc", "coupling_body_info", "ibvt_set_allocator"):
+                 "transfer_velocity_noalloc", "coupling_body_info", "ibvt_set_allocator",
+                 "coupling_release_scratch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -596,6 +598,13 @@ class Coupling:
                     dist_evals=i.dist_evals, cut_points=i.cut_points, dual=bool(i.dual),
                     dim=i.dim, unstructured=bool(i.unstructured), plane_cuts=i.plane_cuts,
                     matrix_free=bool(i.matrix_free))
+
+    def release_scratch(self, stream=None):
+        """Return the assembly-only device memory (coupling_release_scratch);
+        transfers and the reverse mode keep working, and the next
+        reassembly allocates it again."""
+        _check(_lib.coupling_release_scratch(self.handle, _stream(stream)),
+               "coupling_release_scratch")
 
     def body_info(self, tet_offsets, stream=None) -> list:
         """Per-body counters (coupling_body_info): body b holds tets

@@ -1,6 +1,7 @@
-"""Two interface extras on the HIP path, through the C ABI: the per-body
-counters (coupling_body_info) and a caller-supplied device allocator
-(ibvt_set_allocator, here PyTorch's caching allocator).
+"""Interface extras on the HIP path, through the C ABI: the per-body
+counters (coupling_body_info), a caller-supplied device allocator
+(ibvt_set_allocator, here PyTorch's caching allocator) and the release of
+the assembly's scratch (coupling_release_scratch).
 
 Per-body counters are checked against what the mesh fixes by itself
 (each body's tet count, zero-volume tets and volume from the vertex
@@ -95,4 +96,49 @@ def test_caller_allocator(dev):
     c = Coupling(W.faces, X, T, precision="fp64", consistent=True)
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated(dev) == before
+    c.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_release_scratch_keeps_transfers_and_adjoints(dev, prec):
+    """After coupling_release_scratch the coupling holds less device memory
+    and gives bit-identical transfers and adjoints; a reassembly afterwards
+    gives bit-identical matrices again."""
+    import torch
+    from paper_1810_13046_amd import Coupling
+    W = workload("plate4320_grid256s_tilted")
+    X = to_dev(W.X, torch.float64, dev)
+    c = Coupling(W.faces, X, to_dev(W.tets, torch.int32, dev), precision=prec, consistent=True)
+    dt = c.dtype
+    ud = [to_dev(u, dt, dev) for u in fluid_fields(W)]
+    f_s = to_dev(W.f_s(), dt, dev)
+
+    def run():
+        us = c.velocity(ud, mass="consistent", rtol=1e-12 if prec == "fp64" else 1e-7)
+        ff = [torch.zeros_like(u) for u in ud]
+        c.force(f_s, ff, alpha=0.5)
+        g_uf = [torch.zeros_like(u) for u in ud]
+        g_X = torch.zeros((W.X.shape[0], 3), dtype=torch.float64, device=dev)
+        c.velocity_vjp(us - 1.0, u_f=ud, u_s=us, mass="consistent", g_uf=g_uf, g_X=g_X,
+                       rtol=1e-12 if prec == "fp64" else 1e-7)
+        torch.cuda.synchronize()
+        return [us] + ff + g_uf + [g_X]
+
+    before = run()
+    csr = [c.export_csr(d) for d in range(3)]
+    held = c.info()["device_bytes"]
+    c.release_scratch()
+    torch.cuda.synchronize()
+    after_bytes = c.info()["device_bytes"]
+    say(f"[gpu] release scratch {prec}: {held} -> {after_bytes} bytes")
+    assert after_bytes < held
+    for a, b in zip(before, run()):
+        assert torch.equal(a, b)
+    c.reassemble(X)
+    for d in range(3):
+        rp, col, val = c.export_csr(d)
+        assert np.array_equal(rp, csr[d][0]) and np.array_equal(col, csr[d][1])
+        assert np.array_equal(val, csr[d][2])
+    for a, b in zip(before, run()):
+        assert torch.equal(a, b)
     c.free()
