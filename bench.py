@@ -540,39 +540,146 @@ def cpu_baseline(W, dev, tets_per_body, samples):
     out["assembly_only"] = dict(unit="solid tets/s", sample=f"first 1000 tets of each body "
                                 f"({Ta.shape[0]} tets)", threads_1=asm[1], **{f"threads_{cores}": asm[cores]})
     # error of the GPU's full-size results against the oracle, sampled
-    errs = {}
-    if samples:
-        bounds = oracle.tet_bounds(W.X, W.tets)
-        for prec, smp in samples.items():
-            verts = smp["verts"]
-            star = oracle.vertex_star(W.tets, verts)
-            R = oracle.assemble(W.faces, W.X, W.tets, subset=star)
-            m = oracle.lumped_mass(W.X, W.tets[star], n_vert=W.X.shape[0])
-            f_full = W.f_s()
-            e = dict(rows=0.0, velocity=0.0, force=0.0)
-            for d in range(3):
-                Rs = R.B[d][verts]
-                G = smp["rows"][d]
-                e["rows"] = max(e["rows"], float(sp.linalg.norm(G - Rs) / sp.linalg.norm(Rs)))
-                want = (Rs @ u[d].ravel()) / m[verts]
-                e["velocity"] = max(e["velocity"], float(np.linalg.norm(smp["us"][d] - want) /
-                                                         np.linalg.norm(want)))
-                pick = smp["cols"][d]
-                nx, ny, _ = oracle.lattice_shape(W.faces, d)
-                sub = np.unique(np.concatenate([
-                    oracle.tets_touching_node(W.faces, W.X, W.tets, d,
-                                              (j % nx, (j // nx) % ny, j // (nx * ny)), bounds)
-                    for j in pick]))
-                Rc = oracle.assemble(W.faces, W.X, W.tets, subset=sub).B[d].tocsc()[:, pick]
-                wantf = Rc.T @ f_full[d]
-                e["force"] = max(e["force"], float(np.linalg.norm(smp["ff"][d] - wantf) /
-                                                   np.linalg.norm(wantf)))
-            e["tolerance"] = 1e-12 if prec == "fp64" else 1e-5
-            e["sample"] = (f"{len(verts)} seeded vertices (rows of B^d, lumped velocity), 24 fluid "
-                           f"nodes per component (force); relative Frobenius, max over components")
-            errs[prec] = e
+    errs = {prec: sampled_errors(W, u, smp, prec) for prec, smp in (samples or {}).items()}
     out["error_vs_oracle"] = errs
     return out
+
+
+def sampled_errors(W, u, smp, prec):
+    """Relative Frobenius errors of a GPU sample (gpu_sample) against the
+    oracle, which integrates only the tets that touch the sampled rows and
+    fluid nodes (oracle use: the measurement legs only)."""
+    import oracle
+    import scipy.sparse as sp
+    bounds = oracle.tet_bounds(W.X, W.tets)
+    verts = smp["verts"]
+    star = oracle.vertex_star(W.tets, verts)
+    R = oracle.assemble(W.faces, W.X, W.tets, subset=star)
+    m = oracle.lumped_mass(W.X, W.tets[star], n_vert=W.X.shape[0])
+    f_full = W.f_s()
+    e = dict(rows=0.0, velocity=0.0, force=0.0)
+    for d in range(3):
+        Rs = R.B[d][verts]
+        G = smp["rows"][d]
+        e["rows"] = max(e["rows"], float(sp.linalg.norm(G - Rs) / sp.linalg.norm(Rs)))
+        want = (Rs @ u[d].ravel()) / m[verts]
+        e["velocity"] = max(e["velocity"], float(np.linalg.norm(smp["us"][d] - want) /
+                                                 np.linalg.norm(want)))
+        pick = smp["cols"][d]
+        nx, ny, _ = oracle.lattice_shape(W.faces, d)
+        sub = np.unique(np.concatenate([
+            oracle.tets_touching_node(W.faces, W.X, W.tets, d,
+                                      (j % nx, (j // nx) % ny, j // (nx * ny)), bounds)
+            for j in pick]))
+        Rc = oracle.assemble(W.faces, W.X, W.tets, subset=sub).B[d].tocsc()[:, pick]
+        wantf = Rc.T @ f_full[d]
+        e["force"] = max(e["force"], float(np.linalg.norm(smp["ff"][d] - wantf) /
+                                           np.linalg.norm(wantf)))
+    e["tolerance"] = 1e-12 if prec == "fp64" else 1e-5
+    e["sample"] = (f"{len(verts)} seeded vertices (rows of B^d, lumped velocity), 24 fluid "
+                   f"nodes per component (force); relative Frobenius, max over components")
+    return e
+
+
+def backward_ms(step, reps=5):
+    """The velocity adjoint with the shape derivative (consistent mass): median
+    ms of `reps` calls after one warm-up, HIP events around each."""
+    import torch
+    c = step.c
+    c.velocity(step.u, mass="consistent", rtol=1e-10, maxit=500, out=step.us)
+    g_us = step.us - step.u_t
+
+    def run():
+        c.velocity_vjp(g_us, u_f=step.u, u_s=step.us, mass="consistent", g_uf=step.g_uf,
+                       g_X=step.g_X, rtol=1e-10, maxit=500)
+    run()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def per_config(dev, with_cpu):
+    """Every workload (1..5) at its full size: reassembly rate and the apply
+    rates (cold protocol) in both precisions, the error against the oracle
+    (whole B and transfers for the two small workloads, sampled rows and
+    nodes otherwise), the velocity adjoint with and without stored matrices
+    for the differentiable and time-series workloads, and the oracle's own
+    assembly rate at 1 thread and at the host's threads."""
+    import torch
+    import oracle
+    import scipy.sparse as sp
+    if with_cpu:
+        oracle.build(force=False)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rows = []
+    for cfg in (1, 2, 3, 4, 5):
+        W, X, T, u64, f_s, u_t = make_inputs(cfg, dev)
+        n_tet = int(W.tets.shape[0])
+        u_np = [u.cpu().numpy() for u in u64]
+        R = None
+        if with_cpu and n_tet <= 60000:
+            R = oracle.assemble(W.faces, W.X, W.tets)
+        row = dict(config=cfg, workload=W.name, n_tet=n_tet, n_vert=int(W.X.shape[0]),
+                   grid_cells=list(W.n_cells))
+        for prec in ("fp64", "fp32"):
+            st = Step(W, X, T, u64, f_s, u_t, prec)
+            asm = assembly_rate(st, n_tet, reps=5)
+            rates = apply_rates(st)
+            r = dict(assembly_ms=asm["ms"], assembly_tets_per_s=asm["tets_per_s"],
+                     velocity_per_s=1e3 / rates["velocity_ms"], velocity_GBs=rates["velocity_GBs"],
+                     velocity_frac=rates["velocity_GBs"] / HBM_PEAK_GBS,
+                     force_per_s=1e3 / rates["force_ms"], force_GBs=rates["force_GBs"],
+                     force_frac=rates["force_GBs"] / HBM_PEAK_GBS,
+                     device_bytes=st.c.info()["device_bytes"])
+            if with_cpu and R is not None:
+                e = dict(B=0.0)
+                for d in range(3):
+                    rp, col, val = st.c.export_csr(d)
+                    G = sp.csr_matrix((val, col, rp), shape=R.B[d].shape)
+                    e["B"] = max(e["B"], float(sp.linalg.norm(G - R.B[d]) / sp.linalg.norm(R.B[d])))
+                us = st.c.velocity(st.u, mass="lumped").cpu().numpy().astype(np.float64)
+                want = oracle.transfer_velocity(R, u_np, "lumped")
+                e["velocity"] = float(np.linalg.norm(us - want) / np.linalg.norm(want))
+                ff = [torch.zeros_like(u) for u in st.u]
+                st.c.force(st.f_s, ff, alpha=1.0)
+                wantf = oracle.transfer_force(R, W.f_s(), 1.0)
+                e["force"] = max(float(np.linalg.norm(ff[d].cpu().numpy().ravel() - wantf[d]) /
+                                       np.linalg.norm(wantf[d])) for d in range(3))
+                e["sample"] = "whole B^d, lumped velocity and force; relative Frobenius"
+                r["error_vs_oracle"] = e
+            elif with_cpu:
+                r["error_vs_oracle"] = sampled_errors(W, u_np, gpu_sample(st, W), prec)
+            if cfg in (3, 4):
+                r["backward_stored_ms"] = backward_ms(st)
+            del st
+            if cfg in (3, 4):
+                smf = Step(W, X, T, u64, f_s, u_t, prec, store_B=False)
+                r["backward_recompute_ms"] = backward_ms(smf)
+                r["recompute_device_bytes"] = smf.c.info()["device_bytes"]
+                del smf
+            row[prec] = r
+            log(f"[bench] config {cfg} {prec}: assembly {asm['ms']:.3f} ms, velocity "
+                f"{rates['velocity_GBs']:.0f} GB/s, force {rates['force_GBs']:.0f} GB/s")
+        if with_cpu:
+            n1 = min(n_tet, 2000)
+            nn = min(n_tet, 40000)
+            asm_cpu = {}
+            for nth, n in ((1, n1), (cores, nn)):
+                t0 = time.perf_counter()
+                oracle.assemble(W.faces, W.X, W.tets[:n], nthreads=nth)
+                asm_cpu[nth] = n / (time.perf_counter() - t0)
+            row["oracle_assembly"] = dict(unit="solid tets/s", threads_1=asm_cpu[1],
+                                          **{f"threads_{cores}": asm_cpu[cores]},
+                                          sample=f"first {n1} tets (1 thread), first {nn} tets "
+                                                 f"({cores} threads)", cores=cores)
+        rows.append(row)
+    return rows
 
 
 def roofline(name, prof, info, precision):
@@ -631,6 +738,8 @@ def main():
                     help="only the planar leg (prints its JSON object; for rocprofv3)")
     ap.add_argument("--unstructured-only", action="store_true",
                     help="only the unstructured-background leg (prints its JSON object)")
+    ap.add_argument("--per-config", action="store_true",
+                    help="every workload at full size (rates, errors, adjoints; JSON list)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -656,6 +765,9 @@ def main():
     load_library()
     if args.planar_only:
         print(json.dumps(planar_leg(dev, args.steps, args.warmup, False)))
+        return
+    if args.per_config:
+        print(json.dumps(per_config(dev, not args.skip_cpu)))
         return
     if args.unstructured_only:
         print(json.dumps(unstructured_leg(dev, args.steps, args.warmup, False)))
