@@ -1093,7 +1093,9 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
       if (pat[ch + 1] > pat[ch]) live[n_live++] = ch;
     auto order_chunk = [&](int ch, hipStream_t q) -> int {
       const int64_t p0 = pat[ch], nc = pat[ch + 1] - pat[ch];
-      ProfScope ps("pair_order", q);
+      // the next chunk's order runs beside the integration: its span is
+      // shared with it
+      ProfScope ps(q == s ? "pair_order" : "pair_order_beside_integrate", q);
       k_pair_key<<<blocks_for(nc, 256), 256, 0, q>>>(p0, nc, n_t, c->owner.as<int32_t>(),
                                                     c->pair_off.as<int64_t>(),
                                                     c->rng.as<CellRange>(), keys, desc_in);
