@@ -34,9 +34,7 @@ namespace ibvt {
 
 namespace {
 
-constexpr int kRowNodes = 128;  // LDS box nodes per row per pass in k_rows
-constexpr int kRowMap = 128;    // slots of the slot → tet map of a k_rows row (one window)
-constexpr int kRowBatch = 4;    // steps whose loads k_rows issues together
+constexpr int kRowNodes = 80;   // LDS box nodes per row per pass in k_rows
 
 __device__ __forceinline__ int upper_bound_d(const double* L, int n, double x) {
   int lo = 0, hi = n;  // first index with L[idx] > x
@@ -569,7 +567,7 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t q, uint32_t m) {
   return m ? __umulhi(q, m) : q;
 }
 
-constexpr int kRowsPerWave = 4;  // rows served by one wavefront in k_rows
+constexpr int kRowsPerWave = 8;  // rows served by one wavefront in k_rows
 
 // Maximum of x over the kRowsPerWave row groups of a wavefront (lanes
 // hl, hl + H, ...), for loop bounds common to all of them.
@@ -581,13 +579,14 @@ __device__ __forceinline__ int64_t rows_max(int64_t x) {
 // Gather the pieces of the incident tets into the row's node box, kept in
 // LDS kRowNodes nodes at a time.  Each wavefront serves kRowsPerWave rows,
 // H = 64 / kRowsPerWave lanes each, so the memory latency of one row's steps
-// overlaps the others'.  A row's pairs (incident tets ascending, then cells)
-// are taken H / 8 per step, one value per lane (lane = H·row + 8·pair +
-// corner); the pairs of a step are added to the box one after another, and
-// the 8 corners of one pair are distinct nodes, so every node sums its
-// contributions in pair order (deterministic).  Per batch of H incident
-// tets, each tet's offsets are set up once in LDS and a slot → tet map
-// replaces a search per step.  Touched nodes are written column-sorted at
+// overlaps the others'.  The row's incident tets are taken in ascending
+// order; for each, the lanes take its pairs (cells), H at a time, each lane
+// loading its pair's 8 values of this vertex at once, and the values are
+// added corner by corner: for one corner the cells of one tet are distinct,
+// so are the nodes they add to, and every node sums its contributions in
+// the order (tet, corner) whatever the timing (deterministic, no value
+// atomics outside LDS).  Per batch of H incident tets, each tet's offsets
+// are set up once in LDS.  Touched nodes are written column-sorted at
 // tmp_off[w].
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
@@ -597,14 +596,11 @@ __global__ __launch_bounds__(256) void k_rows(
     const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
     const RowBox* __restrict__ box, const int64_t* __restrict__ tmp_off,
     int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz) {
-  constexpr int H = kWave / kRowsPerWave;    // lanes per row
-  constexpr int PS = H / 8;                   // pairs per step
-  constexpr int RB = 4 * kRowsPerWave;        // rows per block
-  __shared__ double s_acc[RB][kRowNodes];     // summed in double in both precisions
+  constexpr int H = kWave / kRowsPerWave;  // lanes per row
+  constexpr int RB = 4 * kRowsPerWave;     // rows per block
+  __shared__ double s_acc[RB][kRowNodes];  // summed in double in both precisions
   __shared__ uint8_t s_flag[RB][kRowNodes];
   __shared__ int4 s_m0[RB][H], s_m1[RB][H];
-  __shared__ int s_ex[RB][H];
-  __shared__ uint8_t s_map[RB][kRowMap];
   const int lane = lane_id();
   const int h = lane / H, hl = lane % H;
   const int slot = kRowsPerWave * (threadIdx.x / kWave) + h;  // this row's LDS slot
@@ -615,8 +611,6 @@ __global__ __launch_bounds__(256) void k_rows(
   uint8_t* flg = s_flag[slot];
   int4* M0 = s_m0[slot];
   int4* M1 = s_m1[slot];
-  int* EX = s_ex[slot];
-  uint8_t* smap = s_map[slot];
   const int d = live ? int(w / n_v) : 0;
   const int64_t i = live ? w - int64_t(d) * n_v : 0;
   RowBox b{};
@@ -627,11 +621,12 @@ __global__ __launch_bounds__(256) void k_rows(
   const int64_t start = outpos;
   const int64_t NX = ld.n[3 * d + 0], NY = ld.n[3 * d + 1];
   const int64_t beg = live ? vt_ptr[i] : 0, end = live ? vt_ptr[i + 1] : 0;
-  const int qq = hl >> 3, jj = hl & 7;
-  // box-linear offset of this lane's corner
-  const int coff = (jj & 1) + bn0 * (((jj >> 1) & 1) + bn1 * (jj >> 2));
+  // box-linear offsets of the 8 corners of a cell
+  int coff[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) coff[j] = (j & 1) + bn0 * (((j >> 1) & 1) + bn1 * (j >> 2));
   const int64_t vplane = n_pairs * 8;
-  // loop bounds common to both halves (each half masks its own work)
+  // loop bounds common to the row groups of the wave (each masks its own work)
   const int64_t total_max = rows_max(total);
   const int64_t ntet = end - beg;
   const int64_t ntet_max = rows_max(ntet);
@@ -643,7 +638,6 @@ __global__ __launch_bounds__(256) void k_rows(
     }
     for (int64_t kb0 = 0; kb0 < ntet_max; kb0 += H) {
       const int nk = int(max<int64_t>(0, min<int64_t>(H, ntet - kb0)));
-      int cnt = 0;
       wave_lds_sync();
       if (hl < nk) {
         const int64_t t = vt_tet[beg + kb0 + hl];
@@ -652,94 +646,55 @@ __global__ __launch_bounds__(256) void k_rows(
         const int4 tv = *reinterpret_cast<const int4*>(tets + 4 * t);
         const int li =
             (tv.y == int32_t(i)) ? 1 : (tv.z == int32_t(i)) ? 2 : (tv.w == int32_t(i)) ? 3 : 0;
-        const int64_t kbase = pair_off[tc];                     // pair of cell 0
-        const int64_t pbase = int64_t(li) * vplane + kbase * 8;  // its pval row
+        const int64_t kbase = pair_off[tc];  // pair of cell 0
         // box-linear offset of the tet's first cell in this pass
         const int off0 = int(int64_t(r.lo[0] - b.lo[0]) +
                              int64_t(bn0) * ((r.lo[1] - b.lo[1]) +
                                              int64_t(bn1) * (r.lo[2] - b.lo[2])) -
                              c0);
-        cnt = r.n[0] * r.n[1] * r.n[2];
-        M0[hl] = make_int4(int(pbase & 0xffffffffll), int(pbase >> 32),
-                           int(kbase & 0xffffffffll), int(kbase >> 32));
+        const int cnt = r.n[0] * r.n[1] * r.n[2];
+        M0[hl] = make_int4(int(kbase & 0xffffffffll), int(kbase >> 32), li, cnt);
         M1[hl] = make_int4(r.n[0] | (r.n[1] << 16), off0,
                            int(magic_div(uint32_t(max(r.n[0], 1)))),
                            int(magic_div(uint32_t(max(r.n[1], 1)))));
       }
-      int incl = cnt;
-      for (int o = 1; o < H; o <<= 1) {
-        const int y = __shfl_up(incl, o, H);
-        if (hl >= o) incl += y;
-      }
-      const int excl = incl - cnt;
-      EX[hl] = excl;
-      const int tot = __shfl(incl, H - 1, H);
-      const int tot_max = int(rows_max(int64_t(tot)));
-      // slots in windows of kRowMap: the map names each slot's tet
-      for (int w0 = 0; w0 < tot_max; w0 += kRowMap) {
-        wave_lds_sync();
-        {
-          const int a = max(excl, w0), e = min(incl, w0 + kRowMap);
-          for (int sl = a; sl < e; ++sl) smap[sl - w0] = uint8_t(hl);
+      wave_lds_sync();
+      const int nk_max = int(rows_max(int64_t(nk)));
+      for (int kk = 0; kk < nk_max; ++kk) {
+        int4 m0 = make_int4(0, 0, 0, 0), m1 = make_int4(0, 0, 0, 0);
+        if (kk < nk) {
+          m0 = M0[kk];
+          m1 = M1[kk];
         }
-        wave_lds_sync();
-        const int wend = min(tot, w0 + kRowMap);
-        const int wend_max = int(rows_max(int64_t(wend)));
-        // kRowBatch steps of 4 pairs per row at a time: their loads are
-        // issued together, then the steps are added in slot order
-        for (int s0 = w0; s0 < wend_max; s0 += PS * kRowBatch) {
-          bool add[kRowBatch];
-          int loc[kRowBatch];
-          uint8_t kraw[kRowBatch];
-          T vraw[kRowBatch];
-#pragma unroll
-          for (int bb = 0; bb < kRowBatch; ++bb) {
-            const int sl = s0 + PS * bb + qq;
-            bool ok = false;
-            int lin = 0;
-            int64_t ko = 0, vo = 0;
-            if (sl < wend) {
-              const int k = smap[sl - w0];
-              const int4 m1 = M1[k];
-              const uint32_t q = uint32_t(sl - EX[k]);
-              const uint32_t n0 = uint32_t(m1.x) & 0xffffu, n1 = uint32_t(m1.x) >> 16;
-              const uint32_t qy = div_magic(q, uint32_t(m1.z));
-              const int ix = int(q - qy * n0);
-              const uint32_t iz = div_magic(qy, uint32_t(m1.w));
-              const int iy = int(qy - iz * n1);
-              lin = m1.y + ix + bn0 * (iy + bn1 * int(iz)) + coff;
-              if (lin >= 0 && lin < span) {
-                const int4 m0 = M0[k];
-                const int64_t pb = int64_t((unsigned long long)(unsigned)m0.x |
-                                           ((unsigned long long)(unsigned)m0.y << 32));
-                const int64_t kb = int64_t((unsigned long long)(unsigned)m0.z |
-                                           ((unsigned long long)(unsigned)m0.w << 32));
-                ok = true;
-                ko = kb + q;
-                vo = pb + int64_t(q) * 8 + jj;
-              }
-            }
-            // loaded by every lane (entry 0 stands in when there is none),
-            // so the loads of the whole batch are in flight together
-            kraw[bb] = keep[ko];
-            vraw[bb] = pval[vo];
-            add[bb] = ok;
-            loc[bb] = lin;
+        const int cnt = m0.w;
+        const int cnt_max = int(rows_max(int64_t(cnt)));
+        const int64_t kbase = int64_t((unsigned long long)(unsigned)m0.x |
+                                      ((unsigned long long)(unsigned)m0.y << 32));
+        const uint32_t n0 = uint32_t(m1.x) & 0xffffu, n1 = uint32_t(m1.x) >> 16;
+        for (int q0 = 0; q0 < cnt_max; q0 += H) {
+          const int q = q0 + hl;
+          bool add = false;
+          int base = 0;
+          T v[8];
+          if (q < cnt) {
+            const uint32_t qy = div_magic(uint32_t(q), uint32_t(m1.z));
+            const int ix = int(uint32_t(q) - qy * n0);
+            const uint32_t iz = div_magic(qy, uint32_t(m1.w));
+            const int iy = int(qy - iz * n1);
+            base = m1.y + ix + bn0 * (iy + bn1 * int(iz));
+            const int64_t ko = kbase + q;
+            add = keep[ko] != 0;
+            load_row<8>(pval + int64_t(m0.z) * vplane + ko * 8, v);
           }
+          // corner by corner: the cells of one tet are distinct, so one
+          // corner's adds go to distinct nodes
 #pragma unroll
-          for (int bb = 0; bb < kRowBatch; ++bb) {
-            add[bb] = add[bb] && kraw[bb] != 0;
-            if (add[bb]) flg[loc[bb]] = 1;
-          }
-#pragma unroll
-          for (int bb = 0; bb < kRowBatch; ++bb) {
-            if (s0 + PS * bb >= wend_max) break;
-#pragma unroll
-            for (int u = 0; u < PS; ++u) {
-              wave_lds_sync();
-              if (add[bb] && qq == u)
-                __hip_atomic_fetch_add(&acc[loc[bb]], double(vraw[bb]), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+          for (int j = 0; j < 8; ++j) {
+            const int lin = base + coff[j];
+            if (add && lin >= 0 && lin < span) {
+              __hip_atomic_fetch_add(&acc[lin], double(v[j]), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WAVEFRONT);
+              flg[lin] = 1;
             }
           }
         }
