@@ -414,9 +414,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(
     const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
     const double* __restrict__ lat, LatDesc ld, uint8_t* __restrict__ keep,
     T* __restrict__ pval, T* __restrict__ pmom, int dual) {
-  __shared__ T red[kWave][kMom];
-  __shared__ int rown[kWave];
-  __shared__ int rlast[kWave];
+  __shared__ __align__(16) T red[kWave][kMomPad];  // a record's moments per row, padded
   const int lane = threadIdx.x;
   const int64_t g0 = p_begin + int64_t(blockIdx.x) * kWave;
   const int64_t pj = g0 + lane;
@@ -455,17 +453,23 @@ __global__ __launch_bounds__(kWave) void k_integrate(
         for (int e = 0; e < 3; ++e) y[v][e] = r[v * 3 + e];
       subtet_moments<T>(y, subtet_det<T>(y[0], y[1], y[2], y[3]), M);
     }
+    {
+      T Mp[kMomPad];
 #pragma unroll
-    for (int k = 0; k < kMom; ++k) red[lane][k] = M[k];
-    rown[lane] = j;
-    rlast[lane] = (s < total) && (s + 1 == in_j);
+      for (int k = 0; k < kMom; ++k) Mp[k] = M[k];
+      Mp[kMom] = T(0);
+      store_row<kMomPad>(&red[lane][0], Mp);  // 16-byte LDS writes
+    }
+    // the record that ends each pair, and each record's pair, are uniform
+    // across the wave: a ballot and lane reads (no LDS)
+    const uint64_t last = ballot64((s < total) && (s + 1 == in_j));
     __syncthreads();
     if (lane < kMom) {
       const int rows = min(kWave, total - s0);
       for (int r = 0; r < rows; ++r) {
         run += red[r][lane];
-        if (rlast[r]) {
-          pmom[(g0 + rown[r]) * kMomPad + lane] = run;
+        if ((last >> r) & 1ull) {
+          pmom[(g0 + __builtin_amdgcn_readlane(j, r)) * kMomPad + lane] = run;
           run = T(0);
         }
       }
