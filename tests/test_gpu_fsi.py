@@ -1,7 +1,8 @@
 """Picard coupling (Section 3, Steps 1-6) through the C driver fsi_step,
 against the oracle's loop with the same linear stub solvers, and the fluid
-lattice's lumped volume.  FP64: same iteration count, fields within 1e-10
-relative; FP32-mixed: fields within 1e-4 of the FP64 oracle."""
+lattice's lumped volume.  FP64: same iteration count (within one), fields
+within 1e-10 relative; FP32-mixed: fields within 1e-4 of the FP64 oracle;
+with stored matrices and without (IBVT_NO_STORE_B)."""
 import numpy as np
 import pytest
 
@@ -37,10 +38,11 @@ def _stubs(W, seed, density):
     return u_rest, 10.0, v_base, beta
 
 
+@pytest.mark.parametrize("store_B", [True, False])
 @pytest.mark.parametrize("density", [False, True])
 @pytest.mark.parametrize("mode", ["lumped", "consistent", "dual"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_fsi_step_matches_oracle(dev, prec, mode, density):
+def test_fsi_step_matches_oracle(dev, prec, mode, density, store_B):
     import torch
     from paper_1810_13046_amd import Coupling
     name = "beam144_grid32" if prec == "fp32" else "plate4320_grid256s_tilted"
@@ -56,7 +58,7 @@ def test_fsi_step_matches_oracle(dev, prec, mode, density):
     # FP32: the transferred velocity's rounding (about 1e-7 of |w|, times dt k)
     # sets a floor near 5e-6 on the force residual relative to the force
     eps_rel = 0.0 if prec == "fp64" else 1e-4
-    say(f"[gpu] fsi_step {name} {prec} {mode} density={density}")
+    say(f"[gpu] fsi_step {name} {prec} {mode} density={density} store_B={store_B}")
     ref = oracle.fsi_step(W.faces, W.X, W.tets, u0, [np.zeros_like(v) for v in v_base],
                           lambda u: -k_s * (u - u_rest),
                           lambda ft: [v_base[d] + beta * ft[d] for d in range(3)],
@@ -64,7 +66,7 @@ def test_fsi_step_matches_oracle(dev, prec, mode, density):
                           force_density=density, dual=dual)
     assert ref["converged"]
     c = Coupling(W.faces, to_dev(W.X, torch.float64, dev), to_dev(W.tets, torch.int32, dev),
-                 precision=prec, consistent=(mass == "consistent"), dual=dual)
+                 precision=prec, consistent=(mass == "consistent"), dual=dual, store_B=store_B)
     dt_ = c.dtype
     ur = to_dev(u_rest, dt_, dev)
     vb = [to_dev(v.reshape(tuple(reversed(oracle.lattice_shape(W.faces, d)))), dt_, dev)
