@@ -854,9 +854,13 @@ int coupling_release_scratch(ibvt_coupling* c, hipStream_t stream) {
   if (c->dim != 3 || c->unstructured) return IBVT_OK;
   c->stream = stream;
   for (DevBuf* b : {&c->pool, &c->pinfo, &c->rowtmpcol, &c->rowtmpval, &c->rowbox, &c->rowcap,
-                    &c->rowtmpoff, &c->tbuf, &c->order, &c->pscan, &c->mark, &c->cidx})
+                    &c->rowtmpoff, &c->tbuf, &c->pscan, &c->mark, &c->cidx})
     release(c, *b);
-  if (!c->matrix_free) release(c, c->pval);  // the matrix-free products keep their buffer
+  // the matrix-free products keep their per-tet buffer and item order
+  if (!c->matrix_free) {
+    release(c, c->pval);
+    release(c, c->order);
+  }
   c->pool_cap = 0;
   return IBVT_OK;
 }

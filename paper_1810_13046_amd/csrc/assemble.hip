@@ -931,6 +931,7 @@ int finish_matfree(ibvt_coupling* c, hipStream_t s) {
     c->Bt[d].nnz = 0;
   }
   if ((st = solid_masses(c, s))) return st;
+  if ((st = matfree_order(c, s))) return st;
   int64_t zero = 0;
   {
     const int64_t* src[1] = {

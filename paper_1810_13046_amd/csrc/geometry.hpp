@@ -844,12 +844,12 @@ __host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, u
   return true;
 }
 
-template <typename T>
+template <typename T, int NS = kMaxV>
 __host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom& G,
                                                const double lo[3], const double hi[3],
                                                double& vol6, T acc[32], int& nsub) {
   uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
-  if (!poly_clip_box(P, live, lo, hi, G.mn, G.mx)) {
+  if (!poly_clip_box<NS>(P, live, lo, hi, G.mn, G.mx)) {
     vol6 = 0.0;
     nsub = 0;
     return false;
@@ -860,13 +860,13 @@ __host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom&
 // Clip tet ∩ box and call sub(y, det) for every sub-tetrahedron (cell-local
 // coordinates as T, determinant as double).  Also returns the λ
 // coefficients in cell-local coordinates and 6|piece| (cell-local units).
-template <typename T, typename F>
+template <typename T, int NS = kMaxV, typename F>
 __host__ __device__ inline bool clip_fan_local(const PolyView& P, const TetGeom& G,
                                                const double lo[3], const double hi[3], T LA[4],
                                                T LG[4][3], double& vol6, F&& sub) {
   vol6 = 0.0;
   uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
-  if (!poly_clip_box(P, live, lo, hi, G.mn, G.mx)) return false;
+  if (!poly_clip_box<NS>(P, live, lo, hi, G.mn, G.mx)) return false;
   const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
   cell_lambda<T>(G, lo, hi, LA, LG);
   if (!live) return true;

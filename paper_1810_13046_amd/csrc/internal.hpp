@@ -270,13 +270,17 @@ struct SortVal64 {
   double v;
   int32_t r;
 };
-int64_t sort_tiles(int64_t n);
+// tiles of a pass over n items carrying values of value_bytes bytes
+int64_t sort_tiles(int64_t n, int value_bytes = 16);
 // scratch bytes of one digit pass over n items with 2^bits digits
 size_t sort_pass_bytes(int64_t n, int bits);
 // after a pass with 2^bits digits over n items: the first output position
-// of digit k is at [k * sort_tiles(n)] of this array (device); entry
-// 2^bits * sort_tiles(n) holds n
-const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits);
+// of digit k is at [k * sort_tiles(n, value_bytes)] of this array
+// (device); entry 2^bits * sort_tiles(n, value_bytes) holds n
+const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits, int value_bytes = 16);
+// order = the indices 0..n-1 stably sorted by their 8-bit keys
+int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
+                      void* scratch, hipStream_t s);
 // out = the pair descriptors desc[0..n-1] stably sorted by their 8-bit keys
 int order_pairs_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys,
                             const PairDesc* desc, PairDesc* out, void* scratch, hipStream_t s);
@@ -301,6 +305,9 @@ int axpy_solid(ibvt_coupling* c, double alpha, const void* x, void* y, hipStream
 
 // matfree.hip: the products and the shape gradient of a coupling built with
 // IBVT_NO_STORE_B, clipping and integrating every piece again
+// sort the (component, tet) items of a matrix-free coupling by slot class
+// and cell count (into c->order, with the class bounds after the indices)
+int matfree_order(ibvt_coupling* c, hipStream_t s);
 int apply_B_matfree(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale,
                     hipStream_t s);
 int apply_Bt_matfree(ibvt_coupling* c, const void* ys, void* const out[3], double alpha,

@@ -7,7 +7,10 @@
 // (the order of its pairs in the assembled coupling), clips each cell in
 // double (vertex graph in LDS), integrates λ_i N_j on the piece exactly and
 // applies the assembly's drop rule (pieces of volume <= 1e-14 |T| are left
-// out), then:
+// out).  The (component, tet) items are ordered once per assembly by the
+// vertex slots their cells need (the most planes any of their cells cuts:
+// <= 3, 4, >= 5 → 10, 12, 16 slots, one launch each) and, within a class,
+// by their cell count, so the lanes of a wave walk similar loops; then:
 //   k_mf_tet_apply    B x:   pt[(d,t)][i] = Σ_cells Σ_j b_ij x_d[node_j]
 //                     (sums in double), then k_mf_rows adds them per vertex
 //                     over its incident tets in a fixed order and scales by
@@ -64,7 +67,7 @@ __device__ __forceinline__ void range_cell(const CellRange& r, int64_t q, const 
 // b[i][j] = ∫ λ_i N_j over tet ∩ box (ψ_i = 5λ_i − Σ_k λ_k for the dual
 // basis); keep = the piece passes the drop rule.  False on a capacity or
 // walk failure.
-template <typename T>
+template <typename T, int NS>
 __device__ __forceinline__ bool piece_values(const PolyView& P, const TetGeom& G,
                                              const double lo[3], const double hi[3], int dual,
                                              T b[4][8], bool& keep) {
@@ -72,7 +75,7 @@ __device__ __forceinline__ bool piece_values(const PolyView& P, const TetGeom& G
   T acc[32];
   int nsub = 0;
   keep = false;
-  if (!clip_integrate<T>(P, G, lo, hi, vol6, acc, nsub)) return false;
+  if (!clip_integrate<T, NS>(P, G, lo, hi, vol6, acc, nsub)) return false;
   const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
   keep = vol6 * cv / 6.0 > kDropRel * (fabs(G.det) / 6.0);
   const T sc = T(-cv / 6.0);
@@ -104,18 +107,36 @@ __device__ __forceinline__ int64_t corner_node(const int ci[3], int j, int64_t N
   return (ci[0] + (j & 1)) + NX * ((ci[1] + ((j >> 1) & 1)) + NY * int64_t(ci[2] + (j >> 2)));
 }
 
-template <typename T>
+// One slot class of the (component, tet) order: items order[*first ..
+// *end) (device pointers: the class bounds stay on the device).
+struct TcList {
+  const int32_t* order;
+  const int64_t* first;
+  const int64_t* end;
+};
+
+// Walk the class's items, one per lane, in batches of 64 over a grid sized
+// to the resident waves; body(w) handles item w.
+template <typename F>
+__device__ __forceinline__ void for_each_item(const TcList& lst, F&& body) {
+  const int64_t f = *lst.first, n = *lst.end - f;
+  for (int64_t i0 = int64_t(blockIdx.x) * kWave; i0 < n; i0 += int64_t(gridDim.x) * kWave) {
+    const int64_t i = i0 + threadIdx.x;
+    if (i < n) body(int64_t(lst.order[f + i]));
+  }
+}
+
+template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_mf_tet_apply(
-    int64_t n_t, const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
+    TcList lst, int64_t n_t, const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
     const double* __restrict__ lat, LatDesc ld, const T* x0, const T* x1, const T* x2, int dual,
     T* __restrict__ pt, unsigned* flags) {
-  __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
-  __shared__ uint32_t snb[kMaxV * kWave];
+  __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
+  __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
-  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave};
-  const int64_t w = int64_t(blockIdx.x) * kWave + lane;
+  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   bool fail = false;
-  if (w < 3 * n_t) {
+  for_each_item(lst, [&](int64_t w) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     TetCells tc;
     if (tet_cells(w, n_t, rng, tc)) {
@@ -129,7 +150,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_apply(
         range_cell(tc.r, q, lat, ld, tc.d, ci, lo, hi);
         T b[4][8];
         bool keep;
-        if (!piece_values<T>(P, G, lo, hi, dual, b, keep)) {
+        if (!piece_values<T, MAXV>(P, G, lo, hi, dual, b, keep)) {
           fail = true;
           continue;
         }
@@ -148,7 +169,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_apply(
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) pt[w * 4 + i] = T(acc[i]);
-  }
+  });
   const uint64_t fm = ballot64(fail);
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
@@ -179,19 +200,20 @@ __global__ __launch_bounds__(256) void k_mf_rows(int64_t n_v, int64_t n_t, int n
   y[w] = v;
 }
 
-template <typename T>
+template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_mf_tet_spread(
-    int64_t n_t, int64_t n_v, const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
-    const int32_t* __restrict__ tets, const double* __restrict__ lat, LatDesc ld,
-    const T* __restrict__ ys, double alpha, int dual, T* o0, T* o1, T* o2, unsigned* flags) {
-  __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
-  __shared__ uint32_t snb[kMaxV * kWave];
+    TcList lst, int64_t n_t, int64_t n_v, const CellRange* __restrict__ rng,
+    const double* __restrict__ tetrec, const int32_t* __restrict__ tets,
+    const double* __restrict__ lat, LatDesc ld, const T* __restrict__ ys, double alpha, int dual,
+    T* o0, T* o1, T* o2, unsigned* flags) {
+  __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
+  __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
-  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave};
-  const int64_t w = int64_t(blockIdx.x) * kWave + lane;
+  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   bool fail = false;
-  TetCells tc;
-  if (w < 3 * n_t && tet_cells(w, n_t, rng, tc)) {
+  for_each_item(lst, [&](int64_t w) {
+    TetCells tc;
+    if (!tet_cells(w, n_t, rng, tc)) return;
     TetGeom G;
     load_tet(tetrec, tc.t, G);
     T zl[4];
@@ -207,7 +229,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_spread(
       range_cell(tc.r, q, lat, ld, tc.d, ci, lo, hi);
       T b[4][8];
       bool keep;
-      if (!piece_values<T>(P, G, lo, hi, dual, b, keep)) {
+      if (!piece_values<T, MAXV>(P, G, lo, hi, dual, b, keep)) {
         fail = true;
         continue;
       }
@@ -218,7 +240,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_spread(
         unsafeAtomicAdd(out + corner_node(ci, j, NX, NY), T(alpha * double(s)));
       }
     }
-  }
+  });
   const uint64_t fm = ballot64(fail);
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
@@ -231,19 +253,18 @@ __device__ __forceinline__ void dual_weights_mf(T zl[4]) {
   for (int k = 0; k < 4; ++k) zl[k] = T(5) * zl[k] - s;
 }
 
-template <typename T>
+template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_mf_tet_shape(
-    int64_t n_t, int64_t n_v, const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
-    const int32_t* __restrict__ tets, const double* __restrict__ lat, LatDesc ld,
-    const T* __restrict__ z, const T* u0, const T* u1, const T* u2, int dual,
-    double* __restrict__ pgt, unsigned* flags) {
-  __shared__ double sx[kMaxV * kWave], sy[kMaxV * kWave], sz[kMaxV * kWave];
-  __shared__ uint32_t snb[kMaxV * kWave];
+    TcList lst, int64_t n_t, int64_t n_v, const CellRange* __restrict__ rng,
+    const double* __restrict__ tetrec, const int32_t* __restrict__ tets,
+    const double* __restrict__ lat, LatDesc ld, const T* __restrict__ z, const T* u0,
+    const T* u1, const T* u2, int dual, double* __restrict__ pgt, unsigned* flags) {
+  __shared__ double sx[MAXV * kWave], sy[MAXV * kWave], sz[MAXV * kWave];
+  __shared__ uint32_t snb[MAXV * kWave];
   const int lane = threadIdx.x;
-  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave};
-  const int64_t w = int64_t(blockIdx.x) * kWave + lane;
+  const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   bool fail = false;
-  if (w < 3 * n_t) {
+  for_each_item(lst, [&](int64_t w) {
     double acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
@@ -270,7 +291,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_shape(
 #pragma unroll
         for (int k = 0; k < 12; ++k) A[k] = T(0);
         double vol6 = 0.0;
-        const bool ok = clip_fan_local<T>(P, G, lo, hi, LA, LG, vol6,
+        const bool ok = clip_fan_local<T, MAXV>(P, G, lo, hi, LA, LG, vol6,
                                           [&](const T (&y)[4][3], double det) {
                                             subtet_grad<T>(y, T(det), LA, LG, zl, ul, A, Bs);
                                           });
@@ -290,12 +311,67 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_shape(
       }
     }
     store_row<12>(pgt + w * 12, acc);
-  }
+  });
   const uint64_t fm = ballot64(fail);
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
 
-inline unsigned tet_blocks(int64_t n_t) { return unsigned(ceil_div(3 * n_t > 0 ? 3 * n_t : 1, kWave)); }
+// Sort key of (component, tet) w: class · 64 + min(cells, 63).  A cell of
+// the range is cut by at most min(n_e − 1, 2) planes of axis e (one where
+// the range has two cells, two inside a longer one), so the item's class is
+// that of its most-cut cell: <= 3 planes → 0 (10 slots), 4 → 1 (12),
+// >= 5 → 2 (16), the classes of the assembly's pair order.
+__global__ void k_mf_key(int64_t n_tc, const CellRange* __restrict__ rng,
+                         uint8_t* __restrict__ key) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= n_tc) return;
+  const CellRange r = rng[w];
+  int cuts = 0;
+  int64_t cells = 1;
+  for (int e = 0; e < 3; ++e) {
+    cuts += min(max(r.n[e] - 1, 0), 2);
+    cells *= r.n[e];
+  }
+  const int cls = cuts <= 3 ? 0 : (cuts == 4 ? 1 : 2);
+  key[w] = uint8_t(cls * 64 + int(min<int64_t>(max<int64_t>(cells, 0), 63)));
+}
+
+// bounds[k] = first position of class k in the order, bounds[3] = n_tc.
+__global__ void k_mf_bounds(const int64_t* __restrict__ starts, int64_t ntiles,
+                            int64_t* __restrict__ bounds) {
+  const int k = threadIdx.x;
+  if (k < 4) bounds[k] = starts[int64_t(64 * k) * ntiles];
+}
+
+constexpr int kMfClasses = 3;
+constexpr int kMfSlots[kMfClasses] = {10, 12, 16};
+
+// Resident waves of one class kernel: LDS per wave is 28 bytes per slot and
+// lane (160 KB per CU), over 256 CUs, a few rounds deep so the tail of
+// the walk balances.
+inline unsigned class_blocks(int64_t n_tc, int k) {
+  const int64_t per_cu = (160 * 1024) / (int64_t(kMfSlots[k]) * 28 * kWave);
+  const int64_t want = 256 * per_cu * 4;
+  return unsigned(std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(n_tc, kWave))));
+}
+
+inline int64_t* class_bounds(ibvt_coupling* c) {
+  const size_t ob = (size_t(3 * c->n_tet) * sizeof(int32_t) + 255) & ~size_t(255);
+  return reinterpret_cast<int64_t*>(c->order.as<char>() + ob);
+}
+
+inline TcList class_list(ibvt_coupling* c, int k) {
+  const int64_t* b = class_bounds(c);
+  return TcList{c->order.as<int32_t>(), b + k, b + k + 1};
+}
+
+// Launch kernel kern<MAXV> for the three slot classes on stream s.
+#define IBVT_MF_CLASSES(KERN, T, ...)                                                   \
+  do {                                                                                  \
+    KERN<T, 10><<<class_blocks(3 * n_t, 0), kWave, 0, s>>>(class_list(c, 0), __VA_ARGS__); \
+    KERN<T, 12><<<class_blocks(3 * n_t, 1), kWave, 0, s>>>(class_list(c, 1), __VA_ARGS__); \
+    KERN<T, 16><<<class_blocks(3 * n_t, 2), kWave, 0, s>>>(class_list(c, 2), __VA_ARGS__); \
+  } while (0)
 
 template <typename T>
 int apply_B_typed(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale,
@@ -304,7 +380,7 @@ int apply_B_typed(ibvt_coupling* c, const void* const x[3], void* y, bool lumped
   T* pt = c->pval.as<T>();  // 3 n_t x 4, sized by the assembly
   ProfScope ps("mf_apply", s);
   if (n_t > 0)
-    k_mf_tet_apply<T><<<tet_blocks(n_t), kWave, 0, s>>>(
+    IBVT_MF_CLASSES(k_mf_tet_apply, T,
         n_t, c->rng.as<CellRange>(), c->tetrec.as<double>(), c->lat.as<double>(), c->ld,
         static_cast<const T*>(x[0]), static_cast<const T*>(x[1]), static_cast<const T*>(x[2]),
         c->dual ? 1 : 0, pt, c->flags_dev.as<unsigned>());
@@ -320,7 +396,7 @@ int apply_Bt_typed(ibvt_coupling* c, const void* ys, void* const out[3], double 
   const int64_t n_t = c->n_tet;
   ProfScope ps("mf_spread", s);
   if (n_t > 0)
-    k_mf_tet_spread<T><<<tet_blocks(n_t), kWave, 0, s>>>(
+    IBVT_MF_CLASSES(k_mf_tet_spread, T,
         n_t, c->n_vert, c->rng.as<CellRange>(), c->tetrec.as<double>(), c->tets.as<int32_t>(),
         c->lat.as<double>(), c->ld, static_cast<const T*>(ys), alpha, c->dual ? 1 : 0,
         static_cast<T*>(out[0]), static_cast<T*>(out[1]), static_cast<T*>(out[2]),
@@ -340,7 +416,7 @@ int shape_typed_mf(ibvt_coupling* c, const void* z, const void* const u[3], cons
   {
     ProfScope ps("mf_shape", s);
     if (n_t > 0)
-      k_mf_tet_shape<T><<<tet_blocks(n_t), kWave, 0, s>>>(
+      IBVT_MF_CLASSES(k_mf_tet_shape, T,
           n_t, c->n_vert, c->rng.as<CellRange>(), c->tetrec.as<double>(), c->tets.as<int32_t>(),
           c->lat.as<double>(), c->ld, static_cast<const T*>(z), static_cast<const T*>(u[0]),
           static_cast<const T*>(u[1]), static_cast<const T*>(u[2]), c->dual ? 1 : 0, pgt, flags);
@@ -352,6 +428,30 @@ int shape_typed_mf(ibvt_coupling* c, const void* z, const void* const u[3], cons
 }
 
 }  // namespace
+
+#undef IBVT_MF_CLASSES
+
+// The (component, tet) order of the products (slot class, then cell
+// count); kept with the coupling until it is freed or reassembled.
+int matfree_order(ibvt_coupling* c, hipStream_t s) {
+  const int64_t n_tc = 3 * c->n_tet;
+  const size_t ob = (size_t(n_tc) * sizeof(int32_t) + 255) & ~size_t(255);
+  int st = ensure(c, c->order, ob + 4 * sizeof(int64_t));
+  if (st) return st;
+  const size_t kb = (size_t(n_tc + 1) + 255) & ~size_t(255);
+  if ((st = ensure(c, c->pscan, kb + sort_pass_bytes(std::max<int64_t>(n_tc, 1), 8)))) return st;
+  uint8_t* keys = c->pscan.as<uint8_t>();
+  void* scratch = c->pscan.as<char>() + kb;
+  int64_t* bounds = class_bounds(c);
+  if (n_tc == 0)
+    return hip_check(hipMemsetAsync(bounds, 0, 4 * sizeof(int64_t), s), "memset");
+  k_mf_key<<<unsigned(ceil_div(n_tc, 256)), 256, 0, s>>>(n_tc, c->rng.as<CellRange>(), keys);
+  if ((st = hip_check(hipGetLastError(), "matrix-free key launch"))) return st;
+  if ((st = order_by_byte_key(c, n_tc, keys, c->order.as<int32_t>(), scratch, s))) return st;
+  k_mf_bounds<<<1, kWave, 0, s>>>(sort_digit_starts(scratch, n_tc, 8, 4), sort_tiles(n_tc, 4),
+                                  bounds);
+  return hip_check(hipGetLastError(), "matrix-free bounds launch");
+}
 
 // A piece never needs more than the 16 vertex slots of the re-clipping
 // kernels; were a walk to fail, the kernels flag it on the device, and the

@@ -96,6 +96,14 @@ struct ArrayVals {
   }
 };
 
+// the item's own index as the value (an order of the items)
+struct IndexVals {
+  template <typename W>
+  __device__ __forceinline__ W load(int64_t i, bool) const {
+    return W(uint32_t(i));
+  }
+};
+
 template <typename K, typename V, int BITS, int R, typename Src>
 __global__ __launch_bounds__(kWave) void k_digit_scatter(
     int64_t n, const K* __restrict__ keys_in, Src src, int shift, int64_t ntiles,
@@ -197,7 +205,9 @@ int64_t tiles_for(int64_t n, int rounds) { return ceil_div(n > 0 ? n : 1, int64_
 size_t hist_bytes(int64_t m) { return (size_t(m + 1) * sizeof(int32_t) + 255) & ~size_t(255); }
 }  // namespace
 
-int64_t sort_tiles(int64_t n) { return tiles_for(n, sort_rounds<PairDesc>()); }
+int64_t sort_tiles(int64_t n, int value_bytes) {
+  return tiles_for(n, value_bytes > 8 ? sort_rounds<PairDesc>() : sort_rounds<int32_t>());
+}
 
 // Scratch bytes of one pass with 2^bits digits (histogram and offsets), for
 // the smallest tiles any value type takes.
@@ -207,8 +217,8 @@ size_t sort_pass_bytes(int64_t n, int bits) {
 }
 
 // (for the pair order's 16-byte descriptors)
-const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits) {
-  const int64_t m = (int64_t(1) << bits) * sort_tiles(n);
+const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits, int value_bytes) {
+  const int64_t m = (int64_t(1) << bits) * sort_tiles(n, value_bytes);
   return reinterpret_cast<const int64_t*>(static_cast<const char*>(scratch) + hist_bytes(m));
 }
 
@@ -228,6 +238,12 @@ int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, Src src, int shift
   k_digit_scatter<K, V, BITS, R, Src><<<unsigned(ntiles), kWave, 0, s>>>(
       n, keys_in, src, shift, ntiles, hist, off, keys_out, vals_out);
   return hip_check(hipGetLastError(), "digit scatter launch");
+}
+
+int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
+                      void* scratch, hipStream_t s) {
+  if (n <= 0) return IBVT_OK;
+  return digit_pass<uint8_t, int32_t, 8>(c, n, keys, IndexVals{}, 0, nullptr, order, scratch, s);
 }
 
 int order_pairs_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys,
