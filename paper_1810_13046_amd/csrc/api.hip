@@ -192,7 +192,8 @@ void release_all(ibvt_coupling* c) {
                     &c->rowtmpcol, &c->rowtmpval, &c->tetgrad, &c->mcoef,
                     &c->fsiX,     &c->fsinorm,   &c->fvol,      &c->fX,        &c->ftets,
                     &c->frec,     &c->fbox,      &c->forder,    &c->ftree,     &c->ucoo,
-                    &c->rb,       &c->bodyinfo};
+                    &c->rb,       &c->bodyinfo,  &c->tcorder,   &c->rowspilloff,
+                    &c->rowspill};
   for (DevBuf* b : bufs) release(c, *b);
   if (c->host_rb) {
     (void)hipHostFree(c->host_rb);
@@ -854,7 +855,8 @@ int coupling_release_scratch(ibvt_coupling* c, hipStream_t stream) {
   if (c->dim != 3 || c->unstructured) return IBVT_OK;
   c->stream = stream;
   for (DevBuf* b : {&c->pool, &c->pinfo, &c->rowtmpcol, &c->rowtmpval, &c->rowbox, &c->rowcap,
-                    &c->rowtmpoff, &c->tbuf, &c->pscan, &c->mark, &c->cidx})
+                    &c->rowtmpoff, &c->tbuf, &c->pscan, &c->mark, &c->cidx, &c->rowspilloff,
+                    &c->rowspill})
     release(c, *b);
   // the matrix-free products keep their per-tet buffer and item order
   if (!c->matrix_free) {

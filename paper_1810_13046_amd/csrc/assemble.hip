@@ -404,11 +404,12 @@ __device__ __forceinline__ int owner_lane(int excl, int s) {
 // centred) with the 11-point degree-4 rule, summed per pair in record order through
 // LDS (deterministic) into pmom[pair][m] (rows of kMomPad).  Then each lane
 // turns its pair's moments into the 4 x 8 values ∫ λ_i N_j, written to
-// pval[i][pair][j] (local-vertex major: each vertex row of a pair is 8
-// contiguous values).
+// pval[i][pair - p_begin][j] (the chunk's pairs only; local-vertex major:
+// each vertex row of a pair is 8 contiguous values, planes of plane_pairs
+// pairs).
 template <typename T>
 __global__ __launch_bounds__(kWave) void k_integrate(
-    int64_t n_pairs, int64_t p_begin, int64_t p_end, int64_t n_t,
+    int64_t plane_pairs, int64_t p_begin, int64_t p_end, int64_t n_t,
     const uint64_t* __restrict__ pinfo, const T* __restrict__ pool,
     const int32_t* __restrict__ owner, const int64_t* __restrict__ pair_off,
     const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(
     T LA[4], LG[4][3];
     rec_cell_lambda<T>(rec, lo, hi, LA, LG);
     const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
-    const int64_t plane = n_pairs * 8;
+    const int64_t plane = plane_pairs * 8;
     T b[4][8];
     mom_to_b<T>(M, LA, LG, [&](int i, int jj, T v) { b[i][jj] = sc * v; });
     if (dual) {
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(
       }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) store_row<8>(pval + i * plane + pj * 8, b[i]);
+    for (int i = 0; i < 4; ++i) store_row<8>(pval + i * plane + (pj - p_begin) * 8, b[i]);
   }
 }
 
@@ -512,43 +513,70 @@ __global__ __launch_bounds__(kWave) void k_integrate(
 
 // Node box of row (vertex i, component d): the union of the cell ranges of
 // the incident tets, as lo[3] and extent[3] (nodes); its size bounds the row.
+// chunks = first | last << 8: the pair chunks holding the row's pairs (0xff:
+// the row has none).
 struct RowBox {
   int32_t lo[3];
   int32_t n[3];
+  int32_t chunks;
 };
 
+// The (component, tet) ranges of the pair chunks: chunk k holds the items
+// [at[k], at[k + 1]).
+struct ChunkBounds {
+  int64_t at[kMaxChunks + 1];
+  int n;
+};
+
+__device__ __forceinline__ int chunk_of(const ChunkBounds& cb, int64_t tc) {
+  int k = 0;
+  for (int j = 1; j < cb.n; ++j) k += tc >= cb.at[j] ? 1 : 0;
+  return k;
+}
+
 // kBoxG lanes per row: each takes every kBoxG-th incident tet, then the
-// group reduces its bounds with lane shuffles.
+// group reduces its bounds with lane shuffles.  Also the row's first and
+// last pair chunk; a row without pairs gets rownnz = 0 here (no chunk
+// gathers it).
 constexpr int kBoxG = 16;
 
-__global__ __launch_bounds__(256) void k_row_box(int64_t n_v, int64_t n_t,
+__global__ __launch_bounds__(256) void k_row_box(int64_t n_v, int64_t n_t, ChunkBounds cb,
                                                  const int64_t* __restrict__ vt_ptr,
                                                  const int32_t* __restrict__ vt_tet,
                                                  const CellRange* __restrict__ rng,
                                                  RowBox* __restrict__ box,
-                                                 int64_t* __restrict__ cap) {
+                                                 int64_t* __restrict__ cap,
+                                                 int64_t* __restrict__ rownnz) {
   const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kBoxG;
   const int g = threadIdx.x % kBoxG;
   const bool active = w < 3 * n_v;
   int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
+  int cmin = INT_MAX, cmax = INT_MIN;
   if (active) {
     const int d = int(w / n_v);
     const int64_t i = w - int64_t(d) * n_v;
     for (int64_t k = vt_ptr[i] + g; k < vt_ptr[i + 1]; k += kBoxG) {
-      const CellRange r = rng[int64_t(d) * n_t + vt_tet[k]];
+      const int64_t tc = int64_t(d) * n_t + vt_tet[k];
+      const CellRange r = rng[tc];
       if (int64_t(r.n[0]) * r.n[1] * r.n[2] == 0) continue;
       for (int e = 0; e < 3; ++e) {
         bmin[e] = min(bmin[e], r.lo[e]);
         bmax[e] = max(bmax[e], r.lo[e] + r.n[e]);
       }
+      const int ch = chunk_of(cb, tc);
+      cmin = min(cmin, ch);
+      cmax = max(cmax, ch);
     }
   }
 #pragma unroll
-  for (int o = kBoxG / 2; o > 0; o >>= 1)
+  for (int o = kBoxG / 2; o > 0; o >>= 1) {
     for (int e = 0; e < 3; ++e) {
       bmin[e] = min(bmin[e], __shfl_xor(bmin[e], o, kWave));
       bmax[e] = max(bmax[e], __shfl_xor(bmax[e], o, kWave));
     }
+    cmin = min(cmin, __shfl_xor(cmin, o, kWave));
+    cmax = max(cmax, __shfl_xor(cmax, o, kWave));
+  }
   if (!active || g != 0) return;
   RowBox b;
   int64_t sz = 1;
@@ -557,8 +585,20 @@ __global__ __launch_bounds__(256) void k_row_box(int64_t n_v, int64_t n_t,
     b.n[e] = bmin[e] <= bmax[e] ? bmax[e] - bmin[e] + 1 : 0;
     sz *= b.n[e];
   }
+  b.chunks = cmin <= cmax ? (cmin | (cmax << 8)) : (0xff | (0xff << 8));
   box[w] = b;
   cap[w] = sz;
+  if (cmin > cmax) rownnz[w] = 0;
+}
+
+// Spill capacity of each row: its box size if its pairs lie in more than one
+// chunk (the partial sums wait between the chunks), else 0 (in place).
+__global__ void k_row_spill_cap(int64_t n_rows, const RowBox* __restrict__ box,
+                                int64_t* __restrict__ cap) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= n_rows) return;
+  const int ch = box[w].chunks;
+  if ((ch & 0xff) == 0xff || (ch & 0xff) == (ch >> 8)) cap[w] = 0;
 }
 
 // Exact floor(q / n) for q < 2^16 and 1 <= n < 2^16 as a multiply-high by
@@ -592,14 +632,25 @@ __device__ __forceinline__ int64_t rows_max(int64_t x) {
 // atomics outside LDS).  Per batch of H incident tets, each tet's offsets
 // are set up once in LDS.  Touched nodes are written column-sorted at
 // tmp_off[w].
+//
+// One launch per pair chunk ch (items [tc_lo, tc_hi), pairs from p_base,
+// values in pval planes of plane_pairs pairs), over the rows w_begin ..
+// w_begin + n_rows - 1: a row takes the incident tets of the chunk.  A row
+// whose pairs lie in several chunks starts from zero in its first chunk,
+// keeps its node sums (double) and touched flags in its spill space between
+// the chunks, and is written in its last; the chunks come in tet order, so
+// every node still sums in (tet, corner) order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows(
-    int64_t n_v, int64_t n_t, int64_t n_pairs, const int64_t* __restrict__ vt_ptr,
+    int64_t n_v, int64_t n_t, int ch, int64_t tc_lo, int64_t tc_hi, int64_t p_base,
+    int64_t plane_pairs, int64_t w_begin, int64_t n_rows, const int64_t* __restrict__ vt_ptr,
     const int32_t* __restrict__ vt_tet, const int32_t* __restrict__ tets,
     const CellRange* __restrict__ rng, const int64_t* __restrict__ pair_off,
     const uint8_t* __restrict__ keep, const T* __restrict__ pval, LatDesc ld,
     const RowBox* __restrict__ box, const int64_t* __restrict__ tmp_off,
-    int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz) {
+    int32_t* __restrict__ tmp_col, T* __restrict__ tmp_val, int64_t* __restrict__ rownnz,
+    const int64_t* __restrict__ spill_off, double* __restrict__ spill_acc,
+    uint8_t* __restrict__ spill_flg) {
   constexpr int H = kWave / kRowsPerWave;  // lanes per row
   constexpr int RB = 4 * kRowsPerWave;     // rows per block
   __shared__ double s_acc[RB][kRowNodes];  // summed in double in both precisions
@@ -608,17 +659,22 @@ __global__ __launch_bounds__(256) void k_rows(
   const int lane = lane_id();
   const int h = lane / H, hl = lane % H;
   const int slot = kRowsPerWave * (threadIdx.x / kWave) + h;  // this row's LDS slot
-  const int64_t w =
+  const int64_t wl =
       kRowsPerWave * ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave) + h;
-  const bool live = w < 3 * n_v;
+  const int64_t w = w_begin + wl;
   double* acc = s_acc[slot];
   uint8_t* flg = s_flag[slot];
   int4* M0 = s_m0[slot];
   int4* M1 = s_m1[slot];
+  RowBox b{};
+  if (wl < n_rows) b = box[w];
+  // rows of this chunk: first <= ch <= last
+  const int cf = b.chunks & 0xff, cl = (b.chunks >> 8) & 0xff;
+  const bool live = wl < n_rows && cf != 0xff && cf <= ch && ch <= cl;
+  const bool first = cf == ch, last = cl == ch;
+  const int64_t so = (live && !(first && last)) ? spill_off[w] : 0;
   const int d = live ? int(w / n_v) : 0;
   const int64_t i = live ? w - int64_t(d) * n_v : 0;
-  RowBox b{};
-  if (live) b = box[w];
   const int bn0 = b.n[0], bn1 = b.n[1];
   const int64_t total = live ? int64_t(bn0) * bn1 * b.n[2] : 0;
   int64_t outpos = live ? tmp_off[w] : 0;
@@ -629,7 +685,7 @@ __global__ __launch_bounds__(256) void k_rows(
   int coff[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) coff[j] = (j & 1) + bn0 * (((j >> 1) & 1) + bn1 * (j >> 2));
-  const int64_t vplane = n_pairs * 8;
+  const int64_t vplane = plane_pairs * 8;
   // loop bounds common to the row groups of the wave (each masks its own work)
   const int64_t total_max = rows_max(total);
   const int64_t ntet = end - beg;
@@ -637,8 +693,8 @@ __global__ __launch_bounds__(256) void k_rows(
   for (int64_t c0 = 0; c0 < total_max; c0 += kRowNodes) {
     const int span = int(max<int64_t>(0, min<int64_t>(kRowNodes, total - c0)));
     for (int k = hl; k < span; k += H) {
-      acc[k] = 0.0;
-      flg[k] = 0;
+      acc[k] = first ? 0.0 : spill_acc[so + c0 + k];
+      flg[k] = first ? 0 : spill_flg[so + c0 + k];
     }
     for (int64_t kb0 = 0; kb0 < ntet_max; kb0 += H) {
       const int nk = int(max<int64_t>(0, min<int64_t>(H, ntet - kb0)));
@@ -656,7 +712,8 @@ __global__ __launch_bounds__(256) void k_rows(
                              int64_t(bn0) * ((r.lo[1] - b.lo[1]) +
                                              int64_t(bn1) * (r.lo[2] - b.lo[2])) -
                              c0);
-        const int cnt = r.n[0] * r.n[1] * r.n[2];
+        // tets of other chunks add nothing here
+        const int cnt = (tc >= tc_lo && tc < tc_hi) ? r.n[0] * r.n[1] * r.n[2] : 0;
         M0[hl] = make_int4(int(kbase & 0xffffffffll), int(kbase >> 32), li, cnt);
         M1[hl] = make_int4(r.n[0] | (r.n[1] << 16), off0,
                            int(magic_div(uint32_t(max(r.n[0], 1)))),
@@ -688,7 +745,7 @@ __global__ __launch_bounds__(256) void k_rows(
             base = m1.y + ix + bn0 * (iy + bn1 * int(iz));
             const int64_t ko = kbase + q;
             add = keep[ko] != 0;
-            load_row<8>(pval + int64_t(m0.z) * vplane + ko * 8, v);
+            load_row<8>(pval + int64_t(m0.z) * vplane + (ko - p_base) * 8, v);
           }
           // corner by corner: the cells of one tet are distinct, so one
           // corner's adds go to distinct nodes
@@ -705,10 +762,15 @@ __global__ __launch_bounds__(256) void k_rows(
       }
     }
     wave_lds_sync();
+    if (!last)
+      for (int k = hl; k < span; k += H) {
+        spill_acc[so + c0 + k] = acc[k];
+        spill_flg[so + c0 + k] = flg[k];
+      }
     const int span_max = int(rows_max(int64_t(span)));
     for (int k0 = 0; k0 < span_max; k0 += H) {
       const int k = k0 + hl;
-      const bool tch = k < span && flg[k] != 0;
+      const bool tch = last && k < span && flg[k] != 0;
       const uint32_t m = uint32_t(ballot64(tch) >> (H * h)) & uint32_t((uint64_t(1) << H) - 1);
       if (tch) {
         // the box lies inside the lattice, whose node count fits int32
@@ -726,7 +788,7 @@ __global__ __launch_bounds__(256) void k_rows(
     }
     wave_lds_sync();
   }
-  if (live && hl == 0) rownnz[w] = outpos - start;
+  if (live && last && hl == 0) rownnz[w] = outpos - start;
 }
 
 // Copy each row from the box-capacity scratch into the CSR arrays.
@@ -974,15 +1036,48 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   // chunk's tet records stay in the caches while its pairs are clipped.
   const int64_t n_tc = 3 * n_t;
   const int nchunk = int(std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, n_tc / (int64_t(3) << 19))));
-  int64_t tc_at[kMaxChunks + 1];
-  for (int k = 0; k <= nchunk; ++k) tc_at[k] = n_tc * k / nchunk;
-  // read-back 1: the chunks' first pairs (the last entry is the pair count)
-  // and status flags
-  int64_t pat[kMaxChunks + 1];
+  ChunkBounds cb{};
+  cb.n = nchunk;
+  for (int k = 0; k <= nchunk; ++k) cb.at[k] = n_tc * k / nchunk;
+  const int64_t* tc_at = cb.at;
+  // (IV, set-up) each row's node box and its first and last chunk: from the
+  // cell ranges alone.  Rows gather their pairs after each chunk's
+  // integration, so the per-pair values are held for one chunk only; a row
+  // whose pairs lie in several chunks keeps its partial sums in spill space
+  // of its box size.
+  if (!c->matrix_free) {
+    if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
+    if ((st = ensure(c, c->rowcap, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
+    if ((st = ensure(c, c->rowtmpoff, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
+    if ((st = ensure(c, c->rowspilloff, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
+    if ((st = ensure(c, c->rownnz, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
+    {
+      ProfScope ps("rows_box", s);
+      k_row_box<<<blocks_for(3 * n_v * kBoxG, 256), 256, 0, s>>>(
+          n_v, n_t, cb, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->rng.as<CellRange>(),
+          c->rowbox.as<RowBox>(), c->rowcap.as<int64_t>(), c->rownnz.as<int64_t>());
+    }
+    if ((st = hip_check(hipGetLastError(), "row box launch"))) return st;
+    if ((st = scan_i64(c, c->rowcap.as<int64_t>(), c->rowtmpoff.as<int64_t>(), 3 * n_v, s)))
+      return st;
+    k_row_spill_cap<<<blocks_for(3 * n_v, 256), 256, 0, s>>>(3 * n_v, c->rowbox.as<RowBox>(),
+                                                            c->rowcap.as<int64_t>());
+    if ((st = hip_check(hipGetLastError(), "row spill launch"))) return st;
+    if ((st = scan_i64(c, c->rowcap.as<int64_t>(), c->rowspilloff.as<int64_t>(), 3 * n_v, s)))
+      return st;
+  }
+  // read-back 1: the chunks' first pairs (the last entry is the pair count),
+  // the row scratch and spill sizes, and status flags
+  int64_t pat[kMaxChunks + 3];
   {
-    const int64_t* src[kMaxChunks + 1];
+    const int64_t* src[kMaxChunks + 3];
     for (int k = 0; k <= nchunk; ++k) src[k] = c->pair_off.as<int64_t>() + tc_at[k];
-    if ((st = read_counts(c, src, nchunk + 1, pat, s))) return st;
+    int nsrc = nchunk + 1;
+    if (!c->matrix_free) {
+      src[nsrc++] = c->rowtmpoff.as<int64_t>() + 3 * n_v;
+      src[nsrc++] = c->rowspilloff.as<int64_t>() + 3 * n_v;
+    }
+    if ((st = read_counts(c, src, nsrc, pat, s))) return st;
   }
   if ((st = flags_status(c->host_flags))) return st;
   const int64_t n_pairs = pat[nchunk];
@@ -990,11 +1085,19 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     return set_error(IBVT_E_CAPACITY, "2^31 or more (tet, cell) pairs");
   c->n_pairs = n_pairs;
   if (c->matrix_free) return finish_matfree<T>(c, s);
+  const int64_t tmp_total = pat[nchunk + 1], spill_total = pat[nchunk + 2];
   int64_t chunk_max = 0;
   for (int k = 0; k < nchunk; ++k) chunk_max = std::max(chunk_max, pat[k + 1] - pat[k]);
   if ((st = ensure(c, c->owner, size_t(n_pairs + 1) * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->keep, size_t(n_pairs + 1)))) return st;
-  if ((st = ensure(c, c->pval, size_t(n_pairs + 1) * 32 * sizeof(T)))) return st;
+  // one chunk's values: 4 planes (local vertex) of chunk_max pairs x 8
+  if ((st = ensure(c, c->pval, size_t(chunk_max + 1) * 32 * sizeof(T)))) return st;
+  if ((st = ensure(c, c->rowtmpcol, size_t(tmp_total + 1) * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->rowtmpval, size_t(tmp_total + 1) * sizeof(T)))) return st;
+  const size_t spill_acc_bytes = (size_t(spill_total + 1) * sizeof(double) + 255) & ~size_t(255);
+  if ((st = ensure(c, c->rowspill, spill_acc_bytes + size_t(spill_total + 1)))) return st;
+  double* spill_acc = c->rowspill.as<double>();
+  uint8_t* spill_flg = c->rowspill.as<uint8_t>() + spill_acc_bytes;
   if ((st = ensure(c, c->pmom, size_t(n_pairs + 1) * kMomPad * sizeof(T)))) return st;
   if ((st = ensure(c, c->pinfo, size_t(n_pairs + 1) * sizeof(uint64_t)))) return st;
   // the clip order of one chunk at a time, as pair descriptors
@@ -1013,18 +1116,6 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   PairDesc* desc_in = reinterpret_cast<PairDesc*>(c->pscan.as<char>() + kb);
   void* sort_scratch = c->pscan.as<char>() + kb + db;
   if ((st = side_stream(c))) return st;
-  // (IV, set-up) each row's node box: from the cell ranges alone
-  if ((st = ensure(c, c->rowbox, size_t(3 * n_v + 1) * sizeof(RowBox)))) return st;
-  if ((st = ensure(c, c->rowcap, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, c->rowtmpoff, size_t(3 * n_v + 1) * sizeof(int64_t)))) return st;
-  {
-    ProfScope ps("rows_box", s);
-    k_row_box<<<blocks_for(3 * n_v * kBoxG, 256), 256, 0, s>>>(
-        n_v, n_t, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->rng.as<CellRange>(),
-        c->rowbox.as<RowBox>(), c->rowcap.as<int64_t>());
-  }
-  if ((st = scan_i64(c, c->rowcap.as<int64_t>(), c->rowtmpoff.as<int64_t>(), 3 * n_v, s))) return st;
-  int64_t tmp_total = 0;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int64_t want = std::max<int64_t>(int64_t(3.25 * double(chunk_max)) + 1024,
                                            c->pool_needed + c->pool_needed / 32 + 1024);
@@ -1111,44 +1202,47 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
         // whose records did not fit the store read as empty)
         ProfScope ps("integrate", s);
         k_integrate<T><<<dim3(unsigned(ceil_div(nc, kWave))), kWave, 0, s>>>(
-            n_pairs, p0, p0 + nc, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(),
+            chunk_max, p0, p0 + nc, n_t, c->pinfo.as<uint64_t>(), c->pool.as<T>(),
             c->owner.as<int32_t>(), c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
             c->tetrec.as<double>(), c->lat.as<double>(), c->ld, c->keep.as<uint8_t>(),
             c->pval.as<T>(), c->pmom.as<T>(), c->dual ? 1 : 0);
       }
       if ((st = hip_check(hipGetLastError(), "integrate launch"))) return st;
+      {
+        // (IV) the rows of B^d that take pairs of this chunk: the rows of
+        // the components its items belong to (on this stream: beside the
+        // next chunk's clip they slow it by more than they take)
+        ProfScope ps("rows_gather", s);
+        const int64_t d_lo = tc_at[ch] / n_t, d_hi = (tc_at[ch + 1] - 1) / n_t;
+        const int64_t w_begin = d_lo * n_v, n_rows = (d_hi - d_lo + 1) * n_v;
+        k_rows<T><<<blocks_for(ceil_div(n_rows, kRowsPerWave) * kWave, 256), 256, 0, s>>>(
+            n_v, n_t, ch, tc_at[ch], tc_at[ch + 1], p0, chunk_max, w_begin, n_rows,
+            c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
+            c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(),
+            c->pval.as<T>(), c->ld, c->rowbox.as<RowBox>(), c->rowtmpoff.as<int64_t>(),
+            c->rowtmpcol.as<int32_t>(), c->rowtmpval.as<T>(), c->rownnz.as<int64_t>(),
+            c->rowspilloff.as<int64_t>(), spill_acc, spill_flg);
+      }
+      if ((st = hip_check(hipGetLastError(), "rows launch"))) return st;
       if (next && (st = hip_check(hipStreamWaitEvent(s, c->ev_sorted, 0), "stream wait")))
         return st;
     }
-    // read-back 2: records each chunk asked for, the row scratch size, flags
-    int64_t rb2[kMaxChunks + 1];
+
+    // read-back 2: records each chunk asked for, flags
+    int64_t rb2[kMaxChunks];
     {
-      const int64_t* src[kMaxChunks + 1];
-      src[0] = c->rowtmpoff.as<int64_t>() + 3 * n_v;
+      const int64_t* src[kMaxChunks];
       for (int k = 0; k < nchunk; ++k)
-        src[1 + k] = reinterpret_cast<const int64_t*>(counters + kCntChunkPool + k);
-      if ((st = read_counts(c, src, nchunk + 1, rb2, s))) return st;
+        src[k] = reinterpret_cast<const int64_t*>(counters + kCntChunkPool + k);
+      if ((st = read_counts(c, src, nchunk, rb2, s))) return st;
     }
     if ((st = flags_status(c->host_flags))) return st;
-    tmp_total = rb2[0];
     c->pool_needed = 0;
-    for (int k = 0; k < nchunk; ++k) c->pool_needed = std::max(c->pool_needed, rb2[1 + k]);
+    for (int k = 0; k < nchunk; ++k) c->pool_needed = std::max(c->pool_needed, rb2[k]);
     if (c->pool_needed <= c->pool_cap) break;
     if (attempt == 1) return set_error(IBVT_E_CAPACITY, "piece store could not be sized");
   }
-  // (IV) global assembly: rows of B^d
-  if ((st = ensure(c, c->rowtmpcol, size_t(tmp_total + 1) * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, c->rowtmpval, size_t(tmp_total + 1) * sizeof(T)))) return st;
-  {
-    ProfScope ps("rows_gather", s);
-    // kRowsPerWave rows per wavefront
-    k_rows<T><<<blocks_for(ceil_div(3 * n_v, kRowsPerWave) * kWave, 256), 256, 0, s>>>(
-        n_v, n_t, n_pairs, c->vt_ptr.as<int64_t>(), c->vt_tet.as<int32_t>(), c->tets.as<int32_t>(),
-        c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), c->keep.as<uint8_t>(), c->pval.as<T>(),
-        c->ld, c->rowbox.as<RowBox>(), c->rowtmpoff.as<int64_t>(), c->rowtmpcol.as<int32_t>(),
-        c->rowtmpval.as<T>(), c->rownnz.as<int64_t>());
-  }
-  if ((st = hip_check(hipGetLastError(), "rows launch"))) return st;
+  // (IV) global assembly: rows of B^d (gathered per chunk above)
   for (int d = 0; d < 3; ++d) {
     c->B[d].nrows = n_v;
     if ((st = scan_i64(c, c->rownnz.as<int64_t>() + d * n_v, c->B[d].rowptr.as<int64_t>(), n_v, s)))
@@ -1309,6 +1403,7 @@ int assemble_grid(ibvt_coupling* c, hipStream_t s);
 int assemble_all(ibvt_coupling* c, hipStream_t s) {
   c->ready = false;
   c->mom_valid = false;
+  c->tcorder_valid = false;
   const int st = c->dim == 2 ? assemble_all_2d(c, s)
                  : c->unstructured ? assemble_all_unstructured(c, s)
                                    : assemble_grid(c, s);

@@ -100,8 +100,10 @@ __global__ __launch_bounds__(kWave) void k_shape_pairs(
 // Pair terms from the stored piece moments (no clipping, no quadrature),
 // summed over the pieces of each (component, tet): one lane per (component,
 // tet) walks the tet's pairs in cell order, so the tet's geometry, vertex
-// weights and lattice are set up once per lane.  Sums in double to
-// pgt[(d, t)][12] (vertex a, axis k at a*3 + k).  With TWO, a second
+// weights and lattice are set up once per lane.  The lanes take the items
+// in the order of their pair counts (order[]), so the walks of a wave have
+// about the same length.  Sums in double to pgt[(d, t)][12] (vertex a,
+// axis k at a*3 + k).  With TWO, a second
 // contraction (solid weights z2, fluid field v, factor alpha2) is added from
 // the same moments: both adjoints' terms in one pass over the store.
 template <typename T, bool TWO>
@@ -111,9 +113,11 @@ __global__ __launch_bounds__(256) void k_shape_tet(
     const T* __restrict__ pmom, const double* __restrict__ tetrec,
     const double* __restrict__ lat, const int32_t* __restrict__ tets, LatDesc ld,
     const T* __restrict__ z, const T* u0, const T* u1, const T* u2, const T* __restrict__ z2,
-    const T* v0, const T* v1, const T* v2, double alpha2, double* __restrict__ pgt, int dual) {
-  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (w >= 3 * n_t) return;
+    const T* v0, const T* v1, const T* v2, double alpha2, const int32_t* __restrict__ order,
+    double* __restrict__ pgt, int dual) {
+  const int64_t item = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (item >= 3 * n_t) return;
+  const int64_t w = order[item];
   const int d = int(w / n_t);
   const int64_t t = w - int64_t(d) * n_t;
   double acc[12];
@@ -192,6 +196,13 @@ __global__ __launch_bounds__(256) void k_shape_tet(
     }
   }
   store_row<12>(pgt + w * 12, acc);
+}
+
+// Sort key of (component, tet) w: its pair count, clamped to 255.
+__global__ void k_tc_key(int64_t n_tc, const int64_t* __restrict__ pair_off,
+                         uint8_t* __restrict__ key) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w < n_tc) key[w] = uint8_t(min<int64_t>(pair_off[w + 1] - pair_off[w], 255));
 }
 
 // Per (component, tet) sums of the per-pair terms of k_shape_pairs.
@@ -303,13 +314,29 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
   // per (component, tet) sums (double), then the per-pair terms of the
   // re-clipping path
   const size_t tc_bytes = (size_t(3 * c->n_tet + 1) * 12 * sizeof(double) + 255) & ~size_t(255);
-  const size_t pg_bytes = c->mom_valid ? 0 : size_t(c->n_pairs + 1) * 12 * sizeof(T);
+  // (stored moments) the sort keys and scratch of the item order
+  const int64_t n_tc = 3 * c->n_tet;
+  const size_t kb = (size_t(n_tc + 1) + 255) & ~size_t(255);
+  const size_t pg_bytes = c->mom_valid ? kb + sort_pass_bytes(std::max<int64_t>(n_tc, 1), 8)
+                                       : size_t(c->n_pairs + 1) * 12 * sizeof(T);
   int st = ensure(c, c->work2, tc_bytes + pg_bytes);
   if (st) return st;
   double* pgt = c->work2.as<double>();
   T* pg = reinterpret_cast<T*>(c->work2.as<char>() + tc_bytes);
   unsigned* flags = c->flags_dev.as<unsigned>();
   if ((st = hip_check(hipMemsetAsync(flags, 0, sizeof(unsigned), s), "memset"))) return st;
+  if (c->mom_valid && !c->tcorder_valid && n_tc > 0) {
+    // once per assembly: the items ordered by their pair counts
+    ProfScope ps("shape_order", s);
+    if ((st = ensure(c, c->tcorder, size_t(n_tc) * sizeof(int32_t)))) return st;
+    uint8_t* keys = c->work2.as<uint8_t>() + tc_bytes;
+    k_tc_key<<<unsigned(ceil_div(n_tc, 256)), 256, 0, s>>>(n_tc, c->pair_off.as<int64_t>(), keys);
+    if ((st = hip_check(hipGetLastError(), "order key launch"))) return st;
+    if ((st = order_by_byte_key(c, n_tc, keys, c->tcorder.as<int32_t>(),
+                                c->work2.as<char>() + tc_bytes + kb, s)))
+      return st;
+    c->tcorder_valid = true;
+  }
   if (c->mom_valid) {
     ProfScope ps("shape_moments", s);
     const unsigned nb = unsigned(ceil_div(3 * c->n_tet, 256));
@@ -323,13 +350,13 @@ int shape_typed(ibvt_coupling* c, const void* z, const void* const u[3], const v
           c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(), c->lat.as<double>(),
           c->tets.as<int32_t>(), c->ld, zz, u0, u1, u2, static_cast<const T*>(z2),
           static_cast<const T*>(v[0]), static_cast<const T*>(v[1]), static_cast<const T*>(v[2]),
-          alpha2 / alpha, pgt, c->dual ? 1 : 0);
+          alpha2 / alpha, c->tcorder.as<int32_t>(), pgt, c->dual ? 1 : 0);
     else if (c->n_tet > 0)
       k_shape_tet<T, false><<<nb, 256, 0, s>>>(
           c->n_tet, c->n_vert, c->pair_off.as<int64_t>(), c->rng.as<CellRange>(),
           c->keep.as<uint8_t>(), c->pmom.as<T>(), c->tetrec.as<double>(), c->lat.as<double>(),
           c->tets.as<int32_t>(), c->ld, zz, u0, u1, u2, nullptr, nullptr, nullptr, nullptr, 0.0,
-          pgt, c->dual ? 1 : 0);
+          c->tcorder.as<int32_t>(), pgt, c->dual ? 1 : 0);
   } else {
     const int64_t nb = std::min<int64_t>(ceil_div(c->n_pairs, kWave), int64_t(1) << 22);
     ProfScope ps("shape_pairs", s);

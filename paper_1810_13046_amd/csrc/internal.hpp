@@ -172,12 +172,17 @@ struct ibvt_coupling {
   ibvt::DevBuf pinfo;        // uint64 n_pairs: first record << 8 | records (0: dropped)
   ibvt::DevBuf order;        // int32 n_pairs: pairs sorted by cut pattern
   ibvt::DevBuf pscan;        // sort keys and scratch
+  ibvt::DevBuf tcorder;      // int32 3*n_tet: (component, tet) items by pair count
+  bool tcorder_valid = false;  // tcorder belongs to the last assembly
   ibvt::DevBuf rownnz;       // int64 3*n_vert
   ibvt::DevBuf rowbox;       // node box per (vertex, component)
   ibvt::DevBuf rowcap;       // int64 box size per row
   ibvt::DevBuf rowtmpoff;    // int64 offsets into the row scratch
   ibvt::DevBuf rowtmpcol;    // int32 row scratch columns
   ibvt::DevBuf rowtmpval;    // T row scratch values
+  ibvt::DevBuf rowspilloff;  // int64 offsets of the rows' spill space
+  ibvt::DevBuf rowspill;     // double partial node sums + uint8 touched flags of rows that
+                             // take pairs of several chunks
   ibvt::Csr B[3], Bt[3];
   ibvt::DevBuf mark;         // int32 max n_fluid (+1)
   ibvt::DevBuf cidx;         // int64 max n_fluid + 1

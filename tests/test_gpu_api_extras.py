@@ -8,6 +8,8 @@ Per-body counters are checked against what the mesh fixes by itself
 coordinates, in numpy) and against coupling_info's totals; the transfers of
 a coupling whose buffers come from the caller's allocator against the FP64
 oracle (1e-12 relative)."""
+import gc
+
 import numpy as np
 import pytest
 
@@ -71,6 +73,9 @@ def test_caller_allocator(dev):
     T = to_dev(W.tets, torch.int32, dev)
     u_f = fluid_fields(W)
     ud = [to_dev(u, torch.float64, dev) for u in u_f]
+    # tensors of earlier tests still waiting for the cycle collector would
+    # otherwise be freed while this test counts torch's allocations
+    gc.collect()
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated(dev)
     use_torch_allocator(True)
