@@ -70,8 +70,8 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="f5b4ccb6dc162a1b1aab1776ceac0adb859f705ebe7946f6d1284a3490fe03b5",
-                    bytes_mixed=25349116805)
+CLIP_TRAFFIC = dict(sources_sha256="e88ab87cd8a0897566dc25910adae09212eeadb98a5f1ca92606585bb67be62a",
+                    bytes_mixed=25349834597)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
 # HBM traffic of one lumped velocity apply and one force apply (all three
