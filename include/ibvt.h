@@ -228,6 +228,10 @@ int ibvt_set_allocator(const ibvt_alloc* a);
  *   Limits: fewer than 2^30 tets, at most 2^21 cells along each axis,
  *   fewer than 2^31 (tet, cell) pairs and nonzeros per component
  *   (IBVT_E_UNSUPPORTED, IBVT_E_CAPACITY beyond them).
+ *   Pairs are clipped and integrated in up to 8 chunks of 3 * 2^19
+ *   (component, tet) items (the environment variable IBVT_CHUNK_ITEMS, a
+ *   positive integer read at every assembly, sets another size); the
+ *   matrices do not depend on the chunking.
  *   Errors: IBVT_E_INVALID, IBVT_E_OUT_OF_GRID, IBVT_E_CAPACITY,
  *   IBVT_E_UNSUPPORTED, IBVT_E_NOMEM, IBVT_E_HIP.
  */

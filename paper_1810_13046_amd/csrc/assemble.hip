@@ -29,6 +29,7 @@
 #include "internal.hpp"
 
 #include <climits>
+#include <cstdlib>
 
 namespace ibvt {
 
@@ -967,6 +968,19 @@ int read_counts(ibvt_coupling* c, const int64_t* const* srcs, int n, int64_t* ou
 
 namespace {
 
+// (Component, tet) items per pair chunk: 3 · 2^19 (about 10M pairs at the
+// three-body workload's density), or IBVT_CHUNK_ITEMS from the environment
+// (a positive integer; small values put small meshes through the chunked
+// path, as the tests do).  At most kMaxChunks chunks either way.
+int64_t chunk_items() {
+  if (const char* e = std::getenv("IBVT_CHUNK_ITEMS")) {
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end != e && *end == '\0' && v > 0) return int64_t(v);
+  }
+  return int64_t(3) << 19;
+}
+
 // The assembly's second stream and its events, made on first use (default
 // priority, no timing) and destroyed with the handle.
 int side_stream(ibvt_coupling* c) {
@@ -1035,7 +1049,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   // tet) ranges: the piece store holds one chunk's sub-tetrahedra, and a
   // chunk's tet records stay in the caches while its pairs are clipped.
   const int64_t n_tc = 3 * n_t;
-  const int nchunk = int(std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, n_tc / (int64_t(3) << 19))));
+  const int nchunk =
+      int(std::min<int64_t>(kMaxChunks, std::max<int64_t>(1, n_tc / chunk_items())));
   ChunkBounds cb{};
   cb.n = nchunk;
   for (int k = 0; k <= nchunk; ++k) cb.at[k] = n_tc * k / nchunk;
