@@ -567,3 +567,51 @@ def test_jacobi_scaled_mass_spectrum_bounds(oracle_mod):
     d1 = np.diag(M1)
     lam1 = np.linalg.eigvalsh(M1 / np.sqrt(np.outer(d1, d1)))
     np.testing.assert_allclose(lam1, [0.5, 0.5, 0.5, 2.5], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# exact rationals
+# ---------------------------------------------------------------------------
+
+def _exact_cases():
+    """The first tets of the 144-tet beam on its 32^3 grid, and hand-made tets
+    on a stretched dyadic grid: one random, one with every vertex on lattice
+    planes, two with a face in a lattice plane (z = 0.5 is a plane of
+    component 2's lattice, x = 0.3125 of components 1 and 2), all inside the
+    lattices' hull [0.125, 0.875]^3."""
+    W = wl.workload(1)
+    yield "beam144 first tets", W.faces, W.X, W.tets[:2]
+    f = np.array([0.0, 0.25, 0.375, 0.5, 0.75, 1.0])
+    faces = [f, f, f]
+    rng = np.random.default_rng(11)
+    X = np.concatenate([
+        rng.uniform(0.15, 0.85, size=(4, 3)),
+        [[0.25, 0.3125, 0.4375], [0.75, 0.3125, 0.5], [0.3125, 0.75, 0.4375], [0.5, 0.5, 0.75]],
+        [[0.2, 0.3, 0.5], [0.7, 0.35, 0.5], [0.4, 0.8, 0.5], [0.45, 0.5, 0.8]],
+        [[0.3125, 0.2, 0.3], [0.3125, 0.7, 0.35], [0.3125, 0.4, 0.8], [0.6, 0.45, 0.5]],
+    ])
+    yield "hand tets", faces, X, np.arange(16, dtype=np.int32).reshape(4, 4)
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_B_matches_exact_rationals(oracle_mod, case):
+    """Every entry of the oracle's FP64 B on small cases equals the exact
+    rational ∫ λ_i N_j (tests/exact_b.py: face-list clipping, monomial
+    expansion in each sub-tetrahedron's barycentric coordinates) to 1e-14
+    of the largest entry, including vertices and faces lying in lattice
+    planes."""
+    from tests.exact_b import assemble_exact
+    name, faces, X, T = list(_exact_cases())[case]
+    E = assemble_exact(faces, X, T)
+    R = oracle_mod.assemble(faces, X, T)
+    scale = max(abs(float(v)) for v in E.values())
+    worst = 0.0
+    for (d, i, j), v in E.items():
+        worst = max(worst, abs(R.B[d][i, j] - float(v)))
+    for d in range(3):
+        C = R.B[d].tocoo()
+        for i, j, v in zip(C.row, C.col, C.data):
+            if (d, int(i), int(j)) not in E:
+                worst = max(worst, abs(v))
+    assert len(E) > 0
+    assert worst <= 1e-14 * scale, (name, worst / scale)
