@@ -17,7 +17,9 @@
 //                  values ∫ λ_i N_j.
 //  k_row_box / k_rows<T> / k_rows_compact<T>
 //                  each (solid vertex, component) row gathered in an LDS
-//                  node box, pairs added in a fixed order (deterministic,
+//                  node box after each chunk's integration (rows whose
+//                  pairs span chunks keep double partial sums between
+//                  chunks), pairs added in a fixed order (deterministic,
 //                  no value atomics outside LDS), written column-sorted,
 //                  then compacted into CSR.
 //  transpose       B^dT over the touched fluid nodes (transpose.hip).

@@ -158,7 +158,8 @@ struct ibvt_coupling {
   ibvt::DevBuf pair_off;     // int64 3*n_tet + 1
   int64_t n_pairs = 0;
   ibvt::DevBuf owner;        // int32 n_pairs
-  ibvt::DevBuf pval;         // T n_pairs*32 (n_pairs*12 when dim = 2)
+  ibvt::DevBuf pval;         // T: one chunk's pairs x 32 (grid), n_pairs*12 (dim = 2),
+                             // 3*n_tet*4 per-tet sums (matrix-free)
   ibvt::DevBuf pmom;         // T n_pairs*kMomPad: per-pair piece moments (reverse mode)
   ibvt::DevBuf keep;         // uint8 n_pairs
   bool store_pieces = true;  // keep the moments of every piece (reverse mode)
