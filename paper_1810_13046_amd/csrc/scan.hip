@@ -8,8 +8,9 @@ namespace ibvt {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kSumsThreads = 1024;  // the one block that scans the block totals
 
 template <typename Tin>
 __global__ __launch_bounds__(kScanThreads) void k_block_sums(const Tin* __restrict__ in, int64_t n,
@@ -17,6 +18,7 @@ __global__ __launch_bounds__(kScanThreads) void k_block_sums(const Tin* __restri
   __shared__ int64_t red[kScanThreads / kWave];
   const int64_t base = int64_t(blockIdx.x) * kScanTile;
   int64_t s = 0;
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + int64_t(k) * kScanThreads + threadIdx.x;
     if (i < n) s += int64_t(in[i]);
@@ -32,7 +34,8 @@ __global__ __launch_bounds__(kScanThreads) void k_block_sums(const Tin* __restri
 }
 
 // Inclusive scan of one value per thread across the block; returns the
-// exclusive prefix and writes the block total to *total.
+// exclusive prefix and writes the block total to *total.  sh holds one
+// entry per wave.
 __device__ int64_t block_exclusive(int64_t v, int64_t* sh, int64_t* total) {
   // wave-level inclusive scan
   int64_t x = v;
@@ -54,40 +57,62 @@ __device__ int64_t block_exclusive(int64_t v, int64_t* sh, int64_t* total) {
   return pre + x - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t* __restrict__ bsum, int64_t nb,
+// Exclusive scan of the nb block totals in place by one block: each thread
+// takes a run of consecutive totals.
+__global__ __launch_bounds__(kSumsThreads) void k_scan_sums(int64_t* __restrict__ bsum, int64_t nb,
                                                            int64_t* __restrict__ total_out) {
-  __shared__ int64_t sh[kScanThreads / kWave];
-  int64_t carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
-    const int64_t i = b0 + threadIdx.x;
-    const int64_t v = (i < nb) ? bsum[i] : 0;
-    int64_t tot;
-    const int64_t ex = block_exclusive(v, sh, &tot);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += tot;
+  __shared__ int64_t sh[kSumsThreads / kWave];
+  const int64_t per = ceil_div(nb > 0 ? nb : 1, kSumsThreads);
+  const int64_t b0 = int64_t(threadIdx.x) * per;
+  const int64_t b1 = min<int64_t>(nb, b0 + per);
+  int64_t s = 0;
+  for (int64_t b = b0; b < b1; ++b) s += bsum[b];
+  int64_t tot;
+  int64_t pre = block_exclusive(s, sh, &tot);
+  for (int64_t b = b0; b < b1; ++b) {
+    const int64_t v = bsum[b];
+    bsum[b] = pre;
+    pre += v;
   }
-  if (threadIdx.x == 0) *total_out = carry;
+  if (threadIdx.x == 0) *total_out = tot;
 }
+
+// Per tile: the items are read with consecutive threads on consecutive
+// items into LDS, each thread scans its run of kScanItems there (rows
+// padded by one entry against bank conflicts), and the results leave the
+// same coalesced way.
+__device__ __forceinline__ int scan_slot(int i) { return (i / kScanItems) * (kScanItems + 1) + i % kScanItems; }
 
 template <typename Tin>
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const Tin* __restrict__ in, int64_t n,
                                                             const int64_t* __restrict__ bsum,
                                                             int64_t* __restrict__ out) {
+  __shared__ int64_t buf[kScanThreads * (kScanItems + 1)];
   __shared__ int64_t sh[kScanThreads / kWave];
-  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
-  int64_t v[kScanItems];
-  int64_t s = 0;
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + k;
-    v[k] = (i < n) ? int64_t(in[i]) : 0;
-    s += v[k];
+    const int i = k * kScanThreads + int(threadIdx.x);
+    buf[scan_slot(i)] = (base + i < n) ? int64_t(in[base + i]) : 0;
   }
+  __syncthreads();
+  int64_t* row = buf + threadIdx.x * (kScanItems + 1);
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) s += row[k];
   int64_t tot;
   int64_t pre = block_exclusive(s, sh, &tot) + bsum[blockIdx.x];
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + k;
-    if (i < n) out[i] = pre;
-    pre += v[k];
+    const int64_t v = row[k];
+    row[k] = pre;
+    pre += v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = k * kScanThreads + int(threadIdx.x);
+    if (base + i < n) out[base + i] = buf[scan_slot(i)];
   }
 }
 
@@ -102,7 +127,7 @@ int scan_impl(ibvt_coupling* c, const Tin* in, int64_t* out, int64_t n, hipStrea
     st = hip_check(hipMemsetAsync(bsum, 0, sizeof(int64_t), s), "memset");
     if (st) return st;
   }
-  k_scan_sums<<<1, kScanThreads, 0, s>>>(bsum, n > 0 ? nb : 0, out + n);
+  k_scan_sums<<<1, kSumsThreads, 0, s>>>(bsum, n > 0 ? nb : 0, out + n);
   if (n > 0) k_scan_tiles<Tin><<<dim3(unsigned(nb)), kScanThreads, 0, s>>>(in, n, bsum, out);
   return hip_check(hipGetLastError(), "scan launch");
 }
