@@ -5,10 +5,11 @@
 //                  rectilinear grid the overlap candidates of a tet are an
 //                  index box), volume, geometry record, validity checks.
 //  scan / k_owner  candidate (tet, component, cell) pair offsets and owners.
-//  k_pair_key      per chunk of pairs: sort key (the cell planes the tet
-//                  straddles, in classes by cut count: vertex slots 10,
-//                  12, 16) and 16-byte descriptor; a counting sort puts
-//                  the descriptors in clip order.
+//  k_order_count / k_order_scatter
+//                  per chunk: the pairs' 16-byte descriptors in clip
+//                  order (key: the cell planes the tet straddles, in
+//                  classes by cut count: vertex slots 10, 12, 16), counted
+//                  and placed per (tet, key) group from the cell ranges.
 //  k_clip<T,MAXV>  one lane per pair: clip the tet by the straddled cell
 //                  planes in double (vertex graph in LDS), fan the piece
 //                  into sub-tetrahedra and store them as records.
@@ -232,34 +233,115 @@ __global__ void k_owner(int64_t n_tc, const int64_t* __restrict__ off, int32_t* 
 // clip + integrate, one lane per (tet, component, cell) pair
 // ---------------------------------------------------------------------------
 
-// Which of the six cell planes a pair's tet straddles, from indices alone:
-// the low plane of cell ci cuts the tet iff ci > first cell of the tet's
-// range, the high plane iff ci < last.  Sort key = class · 64 + pattern,
-// class 0: <= 3 cuts, 1: 4, 2: >= 5 (classes need 10, 12, 16 vertex
-// slots); sorting by the key gives every wave the same sequence of clips.
-// Also writes the pair's descriptor (pair_desc), which the sort carries.
-// One chunk of pairs: p0 .. p0 + n - 1 (outputs indexed from 0).
-__global__ void k_pair_key(int64_t p0, int64_t n, int64_t n_t, const int32_t* __restrict__ owner,
-                           const int64_t* __restrict__ pair_off, const CellRange* __restrict__ rng,
-                           uint8_t* __restrict__ key, PairDesc* __restrict__ desc) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const PairDesc q = pair_desc(p0 + i, n_t, owner, pair_off, rng);
-    const int64_t tc = owner[p0 + i];
-    const CellRange r = rng[tc];
-    constexpr uint64_t m = (uint64_t(1) << kCellBits) - 1;
-    const int c[3] = {int(q.cell & m) - r.lo[0], int((q.cell >> kCellBits) & m) - r.lo[1],
-                      int(q.cell >> (2 * kCellBits)) - r.lo[2]};
-    int pattern = 0;
-    for (int e = 0; e < 3; ++e) {
-      if (c[e] > 0) pattern |= 1 << (2 * e);
-      if (c[e] < r.n[e] - 1) pattern |= 2 << (2 * e);
-    }
-    const int cuts = __popc(pattern);
-    const int cls = cuts <= 3 ? 0 : (cuts == 4 ? 1 : 2);
-    key[i] = uint8_t(cls * 64 + pattern);
-    desc[i] = q;
+// The clip order of a chunk, from the cell ranges alone.  Which of the six
+// cell planes a pair's tet straddles follows from indices: the low plane of
+// cell ci cuts the tet iff ci > the first cell of the tet's range along that
+// axis, the high plane iff ci < the last.  Sort key = class · 64 + pattern
+// (the straddled planes, two bits per axis), class 0: <= 3 cuts, 1: 4,
+// 2: >= 5 (classes need 10, 12, 16 vertex slots); ordering the pairs by
+// key gives every wave the same sequence of clips.  Along an axis with n
+// cells the pairs fall into at most three runs (first cell, inner cells,
+// last cell), so a (component, tet) item's pairs form at most 27 groups of
+// one key each, counted and placed per group:
+//   k_order_count    per block of kOrderItems items: pairs per key (LDS
+//                    integer atomics) → hist[key][block];
+//   scan             → the first place of each (key, block), key-major, so
+//                    entry 64·k·blocks is where class k starts;
+//   k_order_scatter  each item takes chunk-local places for its groups
+//                    from its block's running offsets (LDS atomics: the
+//                    order within a key depends on timing, which changes no
+//                    result: a pair's clip and its records depend on the
+//                    pair alone) and writes the groups' descriptors
+//                    (pair_desc's fields).
+constexpr int kOrderItems = 256;
+
+struct AxisRuns {
+  int n;          // runs along the axis (1, 2 or 3)
+  int start[3];   // first cell of each run (range-relative)
+  int count[3];   // cells in each run
+  int bits[3];    // straddled planes of the run's cells: 1 low, 2 high
+};
+
+__device__ __forceinline__ AxisRuns axis_runs(int n) {
+  AxisRuns a;
+  if (n <= 1) {
+    a.n = 1;
+    a.start[0] = 0; a.count[0] = n; a.bits[0] = 0;
+  } else {
+    a.n = n > 2 ? 3 : 2;
+    a.start[0] = 0; a.count[0] = 1; a.bits[0] = 2;
+    a.start[1] = n - 1; a.count[1] = 1; a.bits[1] = 1;
+    a.start[2] = 1; a.count[2] = n - 2; a.bits[2] = 3;
   }
+  return a;
+}
+
+__device__ __forceinline__ int order_key(int pattern) {
+  const int cuts = __popc(pattern);
+  return (cuts <= 3 ? 0 : (cuts == 4 ? 1 : 2)) * 64 + pattern;
+}
+
+__global__ __launch_bounds__(kOrderItems) void k_order_count(int64_t tc0, int64_t n_items,
+                                                             const CellRange* __restrict__ rng,
+                                                             int32_t* __restrict__ hist) {
+  __shared__ int32_t h[256];
+  const int64_t nb = gridDim.x;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t w = int64_t(blockIdx.x) * kOrderItems + threadIdx.x;
+  if (w < n_items) {
+    const CellRange r = rng[tc0 + w];
+    if (int64_t(r.n[0]) * r.n[1] * r.n[2] > 0) {
+      const AxisRuns ax = axis_runs(r.n[0]), ay = axis_runs(r.n[1]), az = axis_runs(r.n[2]);
+      for (int c = 0; c < az.n; ++c)
+        for (int b = 0; b < ay.n; ++b)
+          for (int a = 0; a < ax.n; ++a) {
+            const int cnt = ax.count[a] * ay.count[b] * az.count[c];
+            if (cnt > 0)
+              atomicAdd(&h[order_key(ax.bits[a] | (ay.bits[b] << 2) | (az.bits[c] << 4))], cnt);
+          }
+    }
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kOrderItems) void k_order_scatter(
+    int64_t tc0, int64_t n_items, int64_t n_t, const CellRange* __restrict__ rng,
+    const int64_t* __restrict__ pair_off, const int64_t* __restrict__ first,
+    PairDesc* __restrict__ order) {
+  __shared__ unsigned long long cur[256];
+  const int64_t nb = gridDim.x;
+  cur[threadIdx.x] = (unsigned long long)first[int64_t(threadIdx.x) * nb + blockIdx.x];
+  __syncthreads();
+  const int64_t w = int64_t(blockIdx.x) * kOrderItems + threadIdx.x;
+  if (w >= n_items) return;
+  const int64_t tc = tc0 + w;
+  const CellRange r = rng[tc];
+  if (int64_t(r.n[0]) * r.n[1] * r.n[2] == 0) return;
+  const int d = (tc >= n_t) + (tc >= 2 * n_t);
+  const uint32_t td = uint32_t(tc - int64_t(d) * n_t) | (uint32_t(d) << 30);
+  const int64_t pb = pair_off[tc];
+  const AxisRuns ax = axis_runs(r.n[0]), ay = axis_runs(r.n[1]), az = axis_runs(r.n[2]);
+  for (int c = 0; c < az.n; ++c)
+    for (int b = 0; b < ay.n; ++b)
+      for (int a = 0; a < ax.n; ++a) {
+        const int cnt = ax.count[a] * ay.count[b] * az.count[c];
+        if (cnt == 0) continue;
+        const int key = order_key(ax.bits[a] | (ay.bits[b] << 2) | (az.bits[c] << 4));
+        int64_t pos = int64_t(atomicAdd(&cur[key], (unsigned long long)cnt));
+        for (int z = az.start[c]; z < az.start[c] + az.count[c]; ++z)
+          for (int y = ay.start[b]; y < ay.start[b] + ay.count[b]; ++y)
+            for (int x = ax.start[a]; x < ax.start[a] + ax.count[a]; ++x) {
+              PairDesc o;
+              o.p = int32_t(pb + x + int64_t(r.n[0]) * (y + int64_t(r.n[1]) * z));
+              o.td = td;
+              o.cell = uint64_t(uint32_t(r.lo[0] + x)) |
+                       (uint64_t(uint32_t(r.lo[1] + y)) << kCellBits) |
+                       (uint64_t(uint32_t(r.lo[2] + z)) << (2 * kCellBits));
+              order[pos++] = o;  // chunk-local place
+            }
+      }
 }
 
 // Clip every (tet, component, cell) pair in double, one lane per pair, and
@@ -1121,17 +1203,16 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->order, size_t(chunk_max + 1) * sizeof(PairDesc)))) return st;
   k_owner<<<blocks_for(n_tc, 256), 256, 0, s>>>(n_tc, c->pair_off.as<int64_t>(),
                                                 c->owner.as<int32_t>());
-  // per chunk: sort keys (cut class, straddled-plane pattern) and pair
-  // descriptors, ordered by a stable counting sort (sort.hip) whose digit
-  // starts give the clip launches their class stretches on the device
-  const size_t kb = (size_t(chunk_max + 1) + 255) & ~size_t(255);
-  const size_t db = size_t(chunk_max + 1) * sizeof(PairDesc);
-  if ((st = ensure(c, c->pscan,
-                   kb + db + sort_pass_bytes(std::max<int64_t>(chunk_max, 1), 8))))
-    return st;
-  uint8_t* keys = c->pscan.as<uint8_t>();
-  PairDesc* desc_in = reinterpret_cast<PairDesc*>(c->pscan.as<char>() + kb);
-  void* sort_scratch = c->pscan.as<char>() + kb + db;
+  // per chunk: the pair descriptors in clip order (k_order_count, scan,
+  // k_order_scatter); the scanned key counts give the clip launches their
+  // class stretches on the device
+  int64_t items_max = 1;
+  for (int k = 0; k < nchunk; ++k) items_max = std::max(items_max, tc_at[k + 1] - tc_at[k]);
+  const int64_t ob_max = ceil_div(items_max, kOrderItems);
+  const size_t hb = (size_t(256 * ob_max) * sizeof(int32_t) + 255) & ~size_t(255);
+  if ((st = ensure(c, c->pscan, hb + size_t(256 * ob_max + 1) * sizeof(int64_t)))) return st;
+  int32_t* ohist = c->pscan.as<int32_t>();
+  int64_t* ofirst = reinterpret_cast<int64_t*>(c->pscan.as<char>() + hb);
   if ((st = side_stream(c))) return st;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int64_t want = std::max<int64_t>(int64_t(3.25 * double(chunk_max)) + 1024,
@@ -1160,24 +1241,26 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     for (int ch = 0; ch < nchunk; ++ch)
       if (pat[ch + 1] > pat[ch]) live[n_live++] = ch;
     auto order_chunk = [&](int ch, hipStream_t q) -> int {
-      const int64_t p0 = pat[ch], nc = pat[ch + 1] - pat[ch];
       // the next chunk's order runs beside the integration: its span is
       // shared with it
       ProfScope ps(q == s ? "pair_order" : "pair_order_beside_integrate", q);
-      k_pair_key<<<blocks_for(nc, 256), 256, 0, q>>>(p0, nc, n_t, c->owner.as<int32_t>(),
-                                                    c->pair_off.as<int64_t>(),
-                                                    c->rng.as<CellRange>(), keys, desc_in);
-      int r = hip_check(hipGetLastError(), "pair key launch");
+      const int64_t tc0 = tc_at[ch], items = tc_at[ch + 1] - tc_at[ch];
+      const int64_t ob = ceil_div(items, kOrderItems);
+      k_order_count<<<unsigned(ob), kOrderItems, 0, q>>>(tc0, items, c->rng.as<CellRange>(), ohist);
+      int r = hip_check(hipGetLastError(), "order count launch");
       if (r) return r;
-      return order_pairs_by_byte_key(c, nc, keys, desc_in, c->order.as<PairDesc>(), sort_scratch,
-                                     q);
+      if ((r = scan_i32_to_i64(c, ohist, ofirst, 256 * ob, q))) return r;
+      k_order_scatter<<<unsigned(ob), kOrderItems, 0, q>>>(
+          tc0, items, n_t, c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), ofirst,
+          c->order.as<PairDesc>());
+      return hip_check(hipGetLastError(), "order scatter launch");
     };
     if (n_live > 0 && (st = order_chunk(live[0], s))) return st;
     for (int li = 0; li < n_live; ++li) {
       const int ch = live[li];
       const int64_t p0 = pat[ch], nc = pat[ch + 1] - pat[ch];
-      const int64_t* cls_start = sort_digit_starts(sort_scratch, nc, 8);
-      const int64_t ntiles = sort_tiles(nc);
+      const int64_t* cls_start = ofirst;  // key-major: class k starts at 64 k blocks
+      const int64_t ntiles = ceil_div(tc_at[ch + 1] - tc_at[ch], kOrderItems);
       {
         // (II) clip the chunk's pairs, one launch per cut class (fewer vertex
         // slots per lane, more resident waves); each launch reads its

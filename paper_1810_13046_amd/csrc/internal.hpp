@@ -287,9 +287,6 @@ const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits, int v
 // order = the indices 0..n-1 stably sorted by their 8-bit keys
 int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
                       void* scratch, hipStream_t s);
-// out = the pair descriptors desc[0..n-1] stably sorted by their 8-bit keys
-int order_pairs_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys,
-                            const PairDesc* desc, PairDesc* out, void* scratch, hipStream_t s);
 // stable sort of (keys, vals) by keys < 2^end_bit in digit passes of at
 // most 8 bits, alternating with (keys_tmp, vals_tmp); *in_tmp tells where
 // the result is.  scratch: sort_pass_bytes(n, 8) bytes.

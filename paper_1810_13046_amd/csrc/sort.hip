@@ -216,7 +216,6 @@ size_t sort_pass_bytes(int64_t n, int bits) {
   return hist_bytes(m) + size_t(m + 1) * sizeof(int64_t) + 256;
 }
 
-// (for the pair order's 16-byte descriptors)
 const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits, int value_bytes) {
   const int64_t m = (int64_t(1) << bits) * sort_tiles(n, value_bytes);
   return reinterpret_cast<const int64_t*>(static_cast<const char*>(scratch) + hist_bytes(m));
@@ -244,14 +243,6 @@ int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t*
                       void* scratch, hipStream_t s) {
   if (n <= 0) return IBVT_OK;
   return digit_pass<uint8_t, int32_t, 8>(c, n, keys, IndexVals{}, 0, nullptr, order, scratch, s);
-}
-
-int order_pairs_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys,
-                            const PairDesc* desc, PairDesc* out, void* scratch, hipStream_t s) {
-  if (n <= 0) return IBVT_OK;
-  static_assert(sizeof(PairDesc) == 16, "16-byte pair descriptor");
-  return digit_pass<uint8_t, PairDesc, 8>(c, n, keys, ArrayVals<PairDesc>{desc}, 0, nullptr, out,
-                                          scratch, s);
 }
 
 template <typename V, int B>
