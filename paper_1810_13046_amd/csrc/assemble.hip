@@ -4,7 +4,7 @@
 //                  component's lattice (replaces the tree search: on a
 //                  rectilinear grid the overlap candidates of a tet are an
 //                  index box), volume, geometry record, validity checks.
-//  scan / k_owner  candidate (tet, component, cell) pair offsets and owners.
+//  scan            candidate (tet, component, cell) pair offsets.
 //  k_order_count / k_order_scatter
 //                  per chunk: the pairs' 16-byte descriptors in clip
 //                  order (key: the cell planes the tet straddles, in
@@ -223,12 +223,6 @@ __global__ void k_tet_prep(int64_t n_t, const double* __restrict__ X,
   if (lane_id() == 0 && zm) atomicAdd(&counters[kCntZeroTets], (unsigned long long)popc64(zm));
 }
 
-__global__ void k_owner(int64_t n_tc, const int64_t* __restrict__ off, int32_t* __restrict__ owner) {
-  const int64_t tc = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (tc >= n_tc) return;
-  for (int64_t p = off[tc]; p < off[tc + 1]; ++p) owner[p] = int32_t(tc);
-}
-
 // ---------------------------------------------------------------------------
 // clip + integrate, one lane per (tet, component, cell) pair
 // ---------------------------------------------------------------------------
@@ -252,7 +246,8 @@ __global__ void k_owner(int64_t n_tc, const int64_t* __restrict__ off, int32_t* 
 //                    order within a key depends on timing, which changes no
 //                    result: a pair's clip and its records depend on the
 //                    pair alone) and writes the groups' descriptors
-//                    (pair_desc's fields).
+//                    (pair_desc's fields), and the owner (the item's index)
+//                    of each of its pairs.
 constexpr int kOrderItems = 256;
 
 struct AxisRuns {
@@ -309,7 +304,7 @@ __global__ __launch_bounds__(kOrderItems) void k_order_count(int64_t tc0, int64_
 __global__ __launch_bounds__(kOrderItems) void k_order_scatter(
     int64_t tc0, int64_t n_items, int64_t n_t, const CellRange* __restrict__ rng,
     const int64_t* __restrict__ pair_off, const int64_t* __restrict__ first,
-    PairDesc* __restrict__ order) {
+    PairDesc* __restrict__ order, int32_t* __restrict__ owner) {
   __shared__ unsigned long long cur[256];
   const int64_t nb = gridDim.x;
   cur[threadIdx.x] = (unsigned long long)first[int64_t(threadIdx.x) * nb + blockIdx.x];
@@ -322,6 +317,8 @@ __global__ __launch_bounds__(kOrderItems) void k_order_scatter(
   const int d = (tc >= n_t) + (tc >= 2 * n_t);
   const uint32_t td = uint32_t(tc - int64_t(d) * n_t) | (uint32_t(d) << 30);
   const int64_t pb = pair_off[tc];
+  const int64_t cnt_all = int64_t(r.n[0]) * r.n[1] * r.n[2];
+  for (int64_t q = 0; q < cnt_all; ++q) owner[pb + q] = int32_t(tc);
   const AxisRuns ax = axis_runs(r.n[0]), ay = axis_runs(r.n[1]), az = axis_runs(r.n[2]);
   for (int c = 0; c < az.n; ++c)
     for (int b = 0; b < ay.n; ++b)
@@ -1201,8 +1198,6 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->pinfo, size_t(n_pairs + 1) * sizeof(uint64_t)))) return st;
   // the clip order of one chunk at a time, as pair descriptors
   if ((st = ensure(c, c->order, size_t(chunk_max + 1) * sizeof(PairDesc)))) return st;
-  k_owner<<<blocks_for(n_tc, 256), 256, 0, s>>>(n_tc, c->pair_off.as<int64_t>(),
-                                                c->owner.as<int32_t>());
   // per chunk: the pair descriptors in clip order (k_order_count, scan,
   // k_order_scatter); the scanned key counts give the clip launches their
   // class stretches on the device
@@ -1252,7 +1247,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
       if ((r = scan_i32_to_i64(c, ohist, ofirst, 256 * ob, q))) return r;
       k_order_scatter<<<unsigned(ob), kOrderItems, 0, q>>>(
           tc0, items, n_t, c->rng.as<CellRange>(), c->pair_off.as<int64_t>(), ofirst,
-          c->order.as<PairDesc>());
+          c->order.as<PairDesc>(), c->owner.as<int32_t>());
       return hip_check(hipGetLastError(), "order scatter launch");
     };
     if (n_live > 0 && (st = order_chunk(live[0], s))) return st;
