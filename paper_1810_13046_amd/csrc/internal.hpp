@@ -287,12 +287,15 @@ const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits, int v
 // order = the indices 0..n-1 stably sorted by their 8-bit keys
 int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
                       void* scratch, hipStream_t s);
-// stable sort of (keys, vals) by keys < 2^end_bit in digit passes of at
-// most 8 bits, alternating with (keys_tmp, vals_tmp); *in_tmp tells where
-// the result is.  scratch: sort_pass_bytes(n, 8) bytes.
+// stable sort of (value, row) items vals by keys < 2^end_bit in digit
+// passes of at most 8 bits (alternating with keys_tmp, vals_tmp; both pairs
+// of arrays are overwritten), the last pass writing CSR by key: col[k] =
+// row, val[k] = value, rowptr[0..n_rows] (every key 0..n_rows-1 must
+// occur).  scratch: sort_pass_bytes(n, 8) bytes.
 template <typename V>
-int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals,
-                   int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, bool* in_tmp);
+int sort_to_csr(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals, int32_t* keys_tmp,
+                V* vals_tmp, void* scratch, hipStream_t s, int32_t* col, decltype(V::v)* val,
+                int64_t* rowptr, int64_t n_rows);
 
 // apply.hip
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s);

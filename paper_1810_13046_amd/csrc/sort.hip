@@ -27,7 +27,7 @@ namespace ibvt {
 namespace {
 
 constexpr int kSortWaves = 4;  // waves (tiles) per block of the count kernel
-constexpr int kMaxPassBits = 8;  // widest digit of sort_pairs_i32 (wider measured slower)
+constexpr int kMaxPassBits = 8;  // widest digit of sort_to_csr (wider measured slower)
 
 // Rounds of 64 items per tile: every item of a tile is held in registers
 // while it is ranked (values of 16 bytes take half the rounds).
@@ -104,11 +104,47 @@ struct IndexVals {
   }
 };
 
-template <typename K, typename V, int BITS, int R, typename Src>
+// Where a pass's items go: keys and values to two arrays (the keys may be
+// left out).
+template <typename K, typename V>
+struct PlainOut {
+  K* keys_out;
+  V* vals_out;
+  template <typename W>
+  __device__ __forceinline__ void put(int64_t pos, K key, const W& w, bool, K) const {
+    if (keys_out) keys_out[pos] = key;
+    reinterpret_cast<W*>(vals_out)[pos] = w;
+  }
+};
+
+// The last pass of a sort of (value, row) items by compacted column, written
+// as CSR by that column: col[pos] = row, val[pos] = value, and rowptr[key] =
+// the first place of the key.  Every key has items; the first item of a key
+// is either inside a tile's run of its top digit (its predecessor there has
+// another key: a plain store) or first in such a run (an atomic minimum over
+// the runs' first items, which the plain store of the true first also
+// beats); rowptr starts at all ones.
+template <typename V>
+struct CsrOut {
+  int32_t* col;
+  decltype(V::v)* val;
+  unsigned long long* rowptr;
+  template <typename W>
+  __device__ __forceinline__ void put(int64_t pos, int32_t key, const W& w, bool run_first,
+                                      int32_t prev) const {
+    V x;
+    __builtin_memcpy(&x, &w, sizeof(V));
+    col[pos] = x.r;
+    val[pos] = x.v;
+    if (run_first) atomicMin(&rowptr[key], (unsigned long long)pos);
+    else if (prev != key) rowptr[key] = (unsigned long long)pos;
+  }
+};
+
+template <typename K, typename V, int BITS, int R, typename Src, typename Dst>
 __global__ __launch_bounds__(kWave) void k_digit_scatter(
     int64_t n, const K* __restrict__ keys_in, Src src, int shift, int64_t ntiles,
-    const int32_t* __restrict__ hist, const int64_t* __restrict__ off, K* __restrict__ keys_out,
-    V* __restrict__ vals_out) {
+    const int32_t* __restrict__ hist, const int64_t* __restrict__ off, Dst dst) {
   constexpr int kBins = 1 << BITS;
   constexpr int kPer = (kBins + kWave - 1) / kWave;  // bins per lane in the local scan
   constexpr int kTile = R * kWave;
@@ -116,7 +152,6 @@ __global__ __launch_bounds__(kWave) void k_digit_scatter(
   static_assert(sizeof(W) == sizeof(V), "value word size");
   __shared__ K sk[kTile];
   __shared__ W sv[kTile];
-  W* __restrict__ wout = reinterpret_cast<W*>(vals_out);
   __shared__ int32_t lstart[kBins], run[kBins];
   __shared__ int64_t gstart[kBins];
   const int lane = lane_id();
@@ -189,8 +224,8 @@ __global__ __launch_bounds__(kWave) void k_digit_scatter(
     const K key = sk[j];
     const uint32_t dg = digit_of(key, shift, kBins - 1);
     const int64_t pos = gstart[dg] + (j - lstart[dg]);
-    if (keys_out) keys_out[pos] = key;
-    wout[pos] = sv[j];
+    const bool run_first = j == lstart[dg];
+    dst.put(pos, key, sv[j], run_first, run_first ? key : sk[j - 1]);
   }
 }
 
@@ -221,9 +256,9 @@ const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits, int v
   return reinterpret_cast<const int64_t*>(static_cast<const char*>(scratch) + hist_bytes(m));
 }
 
-template <typename K, typename V, int BITS, typename Src>
-int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, Src src, int shift, K* keys_out,
-               V* vals_out, void* scratch, hipStream_t s) {
+template <typename K, typename V, int BITS, typename Src, typename Dst>
+int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, Src src, int shift, Dst dst,
+               void* scratch, hipStream_t s) {
   constexpr int R = sort_rounds<V>();
   const int64_t ntiles = tiles_for(n, R);
   const int64_t m = (int64_t(1) << BITS) * ntiles;
@@ -234,38 +269,49 @@ int digit_pass(ibvt_coupling* c, int64_t n, const K* keys_in, Src src, int shift
   int st = hip_check(hipGetLastError(), "digit count launch");
   if (st) return st;
   if ((st = scan_i32_to_i64(c, hist, off, m, s))) return st;
-  k_digit_scatter<K, V, BITS, R, Src><<<unsigned(ntiles), kWave, 0, s>>>(
-      n, keys_in, src, shift, ntiles, hist, off, keys_out, vals_out);
+  k_digit_scatter<K, V, BITS, R, Src, Dst><<<unsigned(ntiles), kWave, 0, s>>>(
+      n, keys_in, src, shift, ntiles, hist, off, dst);
   return hip_check(hipGetLastError(), "digit scatter launch");
 }
 
 int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
                       void* scratch, hipStream_t s) {
   if (n <= 0) return IBVT_OK;
-  return digit_pass<uint8_t, int32_t, 8>(c, n, keys, IndexVals{}, 0, nullptr, order, scratch, s);
+  return digit_pass<uint8_t, int32_t, 8>(c, n, keys, IndexVals{}, 0,
+                                         PlainOut<uint8_t, int32_t>{nullptr, order}, scratch, s);
 }
 
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+
 template <typename V, int B>
-int digit_passes(ibvt_coupling* c, int64_t n, int passes, int32_t* keys, V* vals,
-                 int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, bool* in_tmp) {
+int digit_passes_csr(ibvt_coupling* c, int64_t n, int passes, int32_t* keys, V* vals,
+                     int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, int32_t* col,
+                     decltype(V::v)* val, int64_t* rowptr, int64_t n_rows) {
   int32_t* kin = keys;
   V* vin = vals;
   int32_t* kout = keys_tmp;
   V* vout = vals_tmp;
-  for (int p = 0; p < passes; ++p) {
-    int st = digit_pass<int32_t, V, B>(c, n, kin, ArrayVals<V>{vin}, p * B, kout, vout, scratch, s);
-    if (st) return st;
+  int st;
+  for (int p = 0; p + 1 < passes; ++p) {
+    if ((st = digit_pass<int32_t, V, B>(c, n, kin, ArrayVals<V>{vin}, p * B,
+                                        PlainOut<int32_t, V>{kout, vout}, scratch, s)))
+      return st;
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
-  *in_tmp = (passes % 2) == 1;
-  return IBVT_OK;
+  if ((st = hip_check(hipMemsetAsync(rowptr, 0xff, size_t(n_rows) * sizeof(int64_t), s), "memset")))
+    return st;
+  k_set_i64<<<1, 1, 0, s>>>(rowptr + n_rows, n);
+  if ((st = hip_check(hipGetLastError(), "rowptr launch"))) return st;
+  return digit_pass<int32_t, V, B>(
+      c, n, kin, ArrayVals<V>{vin}, (passes - 1) * B,
+      CsrOut<V>{col, val, reinterpret_cast<unsigned long long*>(rowptr)}, scratch, s);
 }
 
 template <typename V>
-int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals,
-                   int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, bool* in_tmp) {
-  *in_tmp = false;
+int sort_to_csr(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals, int32_t* keys_tmp,
+                V* vals_tmp, void* scratch, hipStream_t s, int32_t* col, decltype(V::v)* val,
+                int64_t* rowptr, int64_t n_rows) {
   if (n <= 0) return IBVT_OK;
   // passes of at most kMaxPassBits bits, all of one width
   const int passes = std::max(1, (end_bit + kMaxPassBits - 1) / kMaxPassBits);
@@ -273,7 +319,8 @@ int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* v
   switch (bits) {
 #define IBVT_PASSES(B) \
   case B:              \
-    return digit_passes<V, B>(c, n, passes, keys, vals, keys_tmp, vals_tmp, scratch, s, in_tmp);
+    return digit_passes_csr<V, B>(c, n, passes, keys, vals, keys_tmp, vals_tmp, scratch, s, col, \
+                                  val, rowptr, n_rows);
     IBVT_PASSES(1)
     IBVT_PASSES(2)
     IBVT_PASSES(3)
@@ -288,9 +335,11 @@ int sort_pairs_i32(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* v
   }
 }
 
-template int sort_pairs_i32<SortVal32>(ibvt_coupling*, int64_t, int, int32_t*, SortVal32*,
-                                       int32_t*, SortVal32*, void*, hipStream_t, bool*);
-template int sort_pairs_i32<SortVal64>(ibvt_coupling*, int64_t, int, int32_t*, SortVal64*,
-                                       int32_t*, SortVal64*, void*, hipStream_t, bool*);
+template int sort_to_csr<SortVal32>(ibvt_coupling*, int64_t, int, int32_t*, SortVal32*, int32_t*,
+                                    SortVal32*, void*, hipStream_t, int32_t*, float*, int64_t*,
+                                    int64_t);
+template int sort_to_csr<SortVal64>(ibvt_coupling*, int64_t, int, int32_t*, SortVal64*, int32_t*,
+                                    SortVal64*, void*, hipStream_t, int32_t*, double*, int64_t*,
+                                    int64_t);
 
 }  // namespace ibvt

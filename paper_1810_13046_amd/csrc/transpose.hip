@@ -5,7 +5,8 @@
 // column), are sorted by compacted column with a stable LSD radix sort
 // (digit passes of at most 8 bits, sort.hip) that carries each nonzero's
 // (value, row) along, so each row of B^dT lists its vertices in ascending
-// order and no gather by permutation follows.  Small
+// order; the last pass writes B^dT's columns, values and row pointers
+// directly (no gather by permutation follows).  Small
 // operators take a counting sort instead (column counts, their prefix sum,
 // a scatter into slots, then each row of B^dT put in vertex order by
 // ranking).  No value is reduced and no position depends on timing: the
@@ -54,21 +55,6 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n_rows, const int64_t* __r
     x.r = int32_t(i);
     vr[k] = x;
   }
-}
-
-template <typename T>
-__global__ void k_tgather(int64_t nnz, const int32_t* __restrict__ skeys,
-                          const ValRow<T>* __restrict__ svr, int32_t* __restrict__ tcol,
-                          T* __restrict__ tval, int64_t* __restrict__ trowptr) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  const ValRow<T> x = svr[p];
-  tcol[p] = x.r;
-  tval[p] = x.v;
-  // every compacted row has at least one entry, so a row starts where the
-  // sorted key changes
-  if (p == 0 || skeys[p] != skeys[p - 1]) trowptr[skeys[p]] = p;
-  if (p == nnz - 1) trowptr[int64_t(skeys[p]) + 1] = nnz;
 }
 
 // Counting sort for small operators (below kCountingNnz nonzeros), where
@@ -220,15 +206,9 @@ int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
       c->n_vert, B.rowptr.as<int64_t>(), B.col.as<int32_t>(), B.val.as<T>(),
       c->cidx.as<int64_t>(), keys, vr);
   if ((st = hip_check(hipGetLastError(), "transpose keys launch"))) return st;
-  bool in_tmp = false;
-  if ((st = sort_pairs_i32<ValRow<T>>(c, B.nnz, end_bit, keys, vr, keys_tmp, vr_tmp, scratch, s,
-                                      &in_tmp)))
-    return st;
-  const int32_t* skeys = in_tmp ? keys_tmp : keys;
-  const ValRow<T>* svr = in_tmp ? vr_tmp : vr;
-  k_tgather<T><<<blocks_for(B.nnz, 256), 256, 0, s>>>(B.nnz, skeys, svr, Bt.col.as<int32_t>(),
-                                                      Bt.val.as<T>(), Bt.rowptr.as<int64_t>());
-  return hip_check(hipGetLastError(), "transpose launch");
+  return sort_to_csr<ValRow<T>>(c, B.nnz, end_bit, keys, vr, keys_tmp, vr_tmp, scratch, s,
+                                Bt.col.as<int32_t>(), Bt.val.as<T>(), Bt.rowptr.as<int64_t>(),
+                                touched);
 }
 
 template int transpose_one<float>(ibvt_coupling*, int, hipStream_t);

@@ -1,7 +1,8 @@
 """Full-size parity in the configuration bench.py times (three bodies,
 4.5M tets, 512x256x256 stretched grid; mixed precision and FP64): sampled
 rows of B and B^T and the transferred values there are recomputed one by one
-by the oracle from the tets that touch them; the consistent solve is checked
+by the oracle from the tets that touch them; the stored B^T of one component
+is checked to be exactly the transpose of B; the consistent solve is checked
 by its residual against the oracle's mass matrix."""
 import numpy as np
 import pytest
@@ -76,6 +77,18 @@ def test_sampled_rows_full_size(big, prec):
         say(f"  B^{d}T sampled columns rel {e:.2e}")
         assert e <= TOL[prec]
         assert rel_fro(ff[d][pick], Rc.T @ f_s[d]) <= TOL[prec]
+        if d == 0:
+            # the stored B^T (the radix-sort path at this size) is exactly the
+            # transpose of B, each row's vertices ascending
+            trp, tcol, tval, rmap = c.export_csr(d, transposed=True)
+            Tt = sp.csr_matrix((tval, tcol, trp), shape=(rmap.size, W.X.shape[0]))
+            assert np.all(np.diff(rmap) > 0) and rmap.size == np.unique(G.indices).size
+            assert abs(Tt - G.T.tocsr()[rmap]).max() == 0.0
+            starts = trp[:-1]
+            inner = np.ones(tcol.size, dtype=bool)
+            inner[starts] = False
+            assert np.all(np.diff(tcol)[inner[1:]] > 0)
+            say(f"  B^{d}T: exact transpose of {G.nnz} nonzeros")
         # consistent solve: M u_s = B u_f with the oracle's M and the GPU's B
         if d == 0:
             M = oracle.consistent_mass(W.X, W.tets)
