@@ -1259,7 +1259,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
       {
         // (II) clip the chunk's pairs, one launch per cut class (fewer vertex
         // slots per lane, more resident waves); each launch reads its
-        // class's stretch of the order from the sort's digit starts
+        // class's stretch of the order from the prefix sum of the key counts
         ProfScope ps("clip", s);
         if ((st = hip_check(hipEventRecord(c->ev_fork, s), "event")) ||
             (st = hip_check(hipStreamWaitEvent(c->side, c->ev_fork, 0), "stream wait")))
