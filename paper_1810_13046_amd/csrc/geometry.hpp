@@ -17,9 +17,11 @@
 // vertex (faces through that vertex are skipped).  The assembly integrates
 // the 35 monomial moments of degree <= 4 of each sub-tetrahedron with a
 // symmetric 11-point degree-4 rule (subtet_moments), from which every
-// integrand λ_i N_j follows; the reverse mode's re-clipping path integrates
-// its degree-4 integrands directly with a symmetric 14-point degree-5 rule
-// (subtet_integrate, subtet_grad).  Coordinates are cell-local
+// integrand λ_i N_j follows; the re-clipping paths (the reverse mode
+// without stored moments, the products without stored matrices) integrate
+// their degree-4 integrands, already contracted with the fields, directly
+// with a symmetric 14-point degree-5 rule (subtet_quad, subtet_grad).
+// Coordinates are cell-local
 // (ξ = (x − x0)/h ∈ [0, 1]^3), so the Q1 hats are ξ or 1 − ξ per axis and
 // float arithmetic keeps its relative precision in the mixed-precision path.
 //
@@ -299,31 +301,11 @@ __host__ __device__ inline bool poly_fan(const PolyView& P, uint32_t live, F&& f
   return true;
 }
 
-// Integrate λ_i N_j (i = 0..3 tet vertices, j = corner a + 2b + 4c of the
-// cell) over one sub-tetrahedron with vertices y (cell-local coordinates)
-// and weight scale wscale (its determinant).  λ_i(ξ) = LA[i] + LG[i]·ξ.
-// Adds the unscaled sums into acc[i*8 + j]; the caller multiplies by
-// (cell volume / 6) and the orientation sign.
-template <typename T>
-__host__ __device__ __forceinline__ void quad_point(T px, T py, T pz, T w, const T LA[4],
-                                                    const T LG[4][3], T acc[32]) {
-  const T hx1 = px, hx0 = T(1) - px;
-  const T hy1 = py, hy0 = T(1) - py;
-  const T hz1 = pz, hz0 = T(1) - pz;
-  const T n00 = hx0 * hy0, n10 = hx1 * hy0, n01 = hx0 * hy1, n11 = hx1 * hy1;
-  const T N[8] = {n00 * hz0, n10 * hz0, n01 * hz0, n11 * hz0,
-                  n00 * hz1, n10 * hz1, n01 * hz1, n11 * hz1};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const T wl = w * (LA[i] + LG[i][0] * px + LG[i][1] * py + LG[i][2] * pz);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i * 8 + j] += wl * N[j];
-  }
-}
-
-template <typename T>
-__host__ __device__ inline void subtet_integrate(const T y[4][3], T wscale, const T LA[4],
-                                                 const T LG[4][3], T acc[32]) {
+// The 14 points and weights of the symmetric degree-5 rule on the
+// sub-tetrahedron with vertices y (cell-local), weights scaled by wscale:
+// f(px, py, pz, w) for each point.
+template <typename T, typename F>
+__host__ __device__ __forceinline__ void subtet_quad(const T y[4][3], T wscale, F&& f) {
   T S[3];
 #pragma unroll
   for (int e = 0; e < 3; ++e) S[e] = y[0][e] + y[1][e] + y[2][e] + y[3][e];
@@ -331,19 +313,16 @@ __host__ __device__ inline void subtet_integrate(const T y[4][3], T wscale, cons
   const T a2 = T(kQA2), c2 = T(1.0 - 4.0 * kQA2), w2 = T(kQW2) * wscale;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    quad_point<T>(a1 * S[0] + c1 * y[k][0], a1 * S[1] + c1 * y[k][1], a1 * S[2] + c1 * y[k][2],
-                  w1, LA, LG, acc);
-    quad_point<T>(a2 * S[0] + c2 * y[k][0], a2 * S[1] + c2 * y[k][1], a2 * S[2] + c2 * y[k][2],
-                  w2, LA, LG, acc);
+    f(a1 * S[0] + c1 * y[k][0], a1 * S[1] + c1 * y[k][1], a1 * S[2] + c1 * y[k][2], w1);
+    f(a2 * S[0] + c2 * y[k][0], a2 * S[1] + c2 * y[k][1], a2 * S[2] + c2 * y[k][2], w2);
   }
-  // S22 orbit: b on a pair of vertices, 1/2 − b on the complementary pair
   const T pb = T(2.0 * kQB - 0.5), ps = T(0.5 - kQB), w3 = T(kQW3) * wscale;
   const int pk[6] = {0, 0, 0, 1, 1, 2}, pl[6] = {1, 2, 3, 2, 3, 3};
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int k = pk[q], l = pl[q];
-    quad_point<T>(pb * (y[k][0] + y[l][0]) + ps * S[0], pb * (y[k][1] + y[l][1]) + ps * S[1],
-                  pb * (y[k][2] + y[l][2]) + ps * S[2], w3, LA, LG, acc);
+    f(pb * (y[k][0] + y[l][0]) + ps * S[0], pb * (y[k][1] + y[l][1]) + ps * S[1],
+      pb * (y[k][2] + y[l][2]) + ps * S[2], w3);
   }
 }
 
@@ -712,44 +691,6 @@ __host__ __device__ __forceinline__ T subtet_det(const T ya[3], const T yv[3], c
          d0[2] * (d1[0] * d2[1] - d1[1] * d2[0]);
 }
 
-// Clip tet ∩ box and integrate.  Returns false on a capacity/walk failure.
-// vol6 receives 6·|piece| in cell-local units (times the cell volume gives
-// 6|piece|), acc the 32 unscaled sums (caller scales by cellvol/6·(−1)).
-// The piece must already be clipped (live = its vertex mask).
-template <typename T>
-__host__ __device__ inline bool integrate_piece(const PolyView& P, uint32_t live, const TetGeom& G,
-                                                const double lo[3], const double hi[3],
-                                                double& vol6, T acc[32], int& nsub) {
-  for (int k = 0; k < 32; ++k) acc[k] = T(0);
-  vol6 = 0.0;
-  nsub = 0;
-  if (!live) return true;
-  const double ih[3] = {1.0 / (hi[0] - lo[0]), 1.0 / (hi[1] - lo[1]), 1.0 / (hi[2] - lo[2])};
-  T LA[4], LG[4][3];
-  cell_lambda<T>(G, lo, hi, LA, LG);
-  double vsum = 0.0;
-  const bool ok = poly_fan(P, live, [&](int q0, int q1, int q2, int q3) {
-    const int qs[4] = {q0, q1, q2, q3};
-    double yd[4][3];
-    for (int v = 0; v < 4; ++v)
-      for (int e = 0; e < 3; ++e) yd[v][e] = (P.co(qs[v], e) - lo[e]) * ih[e];
-    double d[3][3];
-    for (int v = 0; v < 3; ++v)
-      for (int e = 0; e < 3; ++e) d[v][e] = yd[v + 1][e] - yd[0][e];
-    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
-                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
-                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
-    vsum += det;
-    T y[4][3];
-    for (int v = 0; v < 4; ++v)
-      for (int e = 0; e < 3; ++e) y[v][e] = T(yd[v][e]);
-    ++nsub;
-    subtet_integrate<T>(y, T(det), LA, LG, acc);
-  });
-  vol6 = -vsum;
-  return ok;
-}
-
 // Walk the three faces through the apex (the lowest live vertex) once:
 // their directed edges are marked in `seen` (they give no sub-tetrahedra),
 // and the number of sub-tetrahedra of the fan is returned:
@@ -842,19 +783,6 @@ __host__ __device__ inline bool emit_subtets(const PolyView& P, uint32_t live, u
   }
   vol6 = -vsum;
   return true;
-}
-
-template <typename T, int NS = kMaxV>
-__host__ __device__ inline bool clip_integrate(const PolyView& P, const TetGeom& G,
-                                               const double lo[3], const double hi[3],
-                                               double& vol6, T acc[32], int& nsub) {
-  uint32_t live = poly_init_tet(P, G.V, G.det < 0.0);
-  if (!poly_clip_box<NS>(P, live, lo, hi, G.mn, G.mx)) {
-    vol6 = 0.0;
-    nsub = 0;
-    return false;
-  }
-  return integrate_piece<T>(P, live, G, lo, hi, vol6, acc, nsub);
 }
 
 // Clip tet ∩ box and call sub(y, det) for every sub-tetrahedron (cell-local

@@ -5,9 +5,11 @@
 //
 // One lane per (component d, tet t) walks the tet's cells in index order
 // (the order of its pairs in the assembled coupling), clips each cell in
-// double (vertex graph in LDS), integrates λ_i N_j on the piece exactly and
-// applies the assembly's drop rule (pieces of volume <= 1e-14 |T| are left
-// out).  The (component, tet) items are ordered once per assembly by the
+// double (vertex graph in LDS), integrates the product's integrand on the
+// piece exactly, already contracted with the field (∫ λ_i U with U = Σ_j
+// x_j N_j for B x, ∫ w N_j with w = Σ_i y_i λ_i for B^T y: 4 or 8 sums per
+// piece instead of the 32 ∫ λ_i N_j), and applies the assembly's drop rule
+// (pieces of volume <= 1e-14 |T| are left out).  The (component, tet) items are ordered once per assembly by the
 // vertex slots their cells need (the most planes any of their cells cuts:
 // <= 3, 4, >= 5 → 10, 12, 16 slots, one launch each) and, within a class,
 // by their cell count, so the lanes of a wave walk similar loops; then:
@@ -49,6 +51,12 @@ __device__ __forceinline__ bool tet_cells(int64_t w, int64_t n_t, const CellRang
   return tc.count > 0;
 }
 
+// Entry (component d, axis e) of a lattice descriptor array, by selects on
+// d (a runtime index into the kernel argument would copy it to scratch).
+__device__ __forceinline__ int32_t ld_at(const int32_t a[9], int d, int e) {
+  return d == 0 ? a[e] : (d == 1 ? a[3 + e] : a[6 + e]);
+}
+
 // Cell q of the range (x fastest) and its box.
 __device__ __forceinline__ void range_cell(const CellRange& r, int64_t q, const double* lat,
                                            const LatDesc& ld, int d, int ci[3], double lo[3],
@@ -57,41 +65,35 @@ __device__ __forceinline__ void range_cell(const CellRange& r, int64_t q, const 
   ci[0] = r.lo[0] + int(q - qy * r.n[0]);
   ci[1] = r.lo[1] + int(qy - qz * r.n[1]);
   ci[2] = r.lo[2] + int(qz);
+#pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const double* L = lat + ld.off[3 * d + e];
+    const double* L = lat + ld_at(ld.off, d, e);
     lo[e] = L[ci[e]];
     hi[e] = L[ci[e] + 1];
   }
 }
 
-// b[i][j] = ∫ λ_i N_j over tet ∩ box (ψ_i = 5λ_i − Σ_k λ_k for the dual
-// basis); keep = the piece passes the drop rule.  False on a capacity or
-// walk failure.
-template <typename T, int NS>
-__device__ __forceinline__ bool piece_values(const PolyView& P, const TetGeom& G,
-                                             const double lo[3], const double hi[3], int dual,
-                                             T b[4][8], bool& keep) {
-  double vol6 = 0.0;
-  T acc[32];
-  int nsub = 0;
-  keep = false;
-  if (!clip_integrate<T, NS>(P, G, lo, hi, vol6, acc, nsub)) return false;
+// Dual multipliers: w = Σ_i z_i ψ_i = Σ_i (5 z_i − Σ_k z_k) λ_i.
+template <typename T>
+__device__ __forceinline__ void dual_weights_mf(T zl[4]) {
+  const T s = zl[0] + zl[1] + zl[2] + zl[3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) zl[k] = T(5) * zl[k] - s;
+}
+
+// Σ_j u_j N_j at cell-local point p (corner j = a + 2b + 4c).
+template <typename T>
+__device__ __forceinline__ T trilinear(const T u[8], T px, T py, T pz) {
+  const T x0 = u[0] + px * (u[1] - u[0]), x1 = u[2] + px * (u[3] - u[2]);
+  const T x2 = u[4] + px * (u[5] - u[4]), x3 = u[6] + px * (u[7] - u[6]);
+  const T y0 = x0 + py * (x1 - x0), y1 = x2 + py * (x3 - x2);
+  return y0 + pz * (y1 - y0);
+}
+
+__device__ __forceinline__ bool piece_kept(double vol6, const double lo[3], const double hi[3],
+                                           const TetGeom& G) {
   const double cv = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
-  keep = vol6 * cv / 6.0 > kDropRel * (fabs(G.det) / 6.0);
-  const T sc = T(-cv / 6.0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) b[i][j] = sc * acc[i * 8 + j];
-  if (dual) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const T s = b[0][j] + b[1][j] + b[2][j] + b[3][j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) b[i][j] = T(5) * b[i][j] - s;
-    }
-  }
-  return true;
+  return vol6 * cv / 6.0 > kDropRel * (fabs(G.det) / 6.0);
 }
 
 __device__ __forceinline__ void load_tet(const double* tetrec, int64_t t, TetGeom& G) {
@@ -115,16 +117,16 @@ struct TcList {
   const int64_t* end;
 };
 
-// Walk the class's items, one per lane, in batches of 64 over a grid sized
-// to the resident waves; body(w) handles item w.
-template <typename F>
-__device__ __forceinline__ void for_each_item(const TcList& lst, F&& body) {
-  const int64_t f = *lst.first, n = *lst.end - f;
-  for (int64_t i0 = int64_t(blockIdx.x) * kWave; i0 < n; i0 += int64_t(gridDim.x) * kWave) {
-    const int64_t i = i0 + threadIdx.x;
-    if (i < n) body(int64_t(lst.order[f + i]));
-  }
-}
+// The class's items, one per lane, in batches of 64 over a grid sized to
+// the resident waves: ITEM_LOOP(lst, w) { body for item w }.  (A plain loop:
+// a lambda capturing the kernel's parameters by reference would give them
+// addresses, and the compiler then copies them to scratch.)
+#define ITEM_LOOP(lst, w)                                                                  \
+  for (int64_t i0_ = int64_t(blockIdx.x) * kWave, f_ = *(lst).first,                        \
+               n_ = *(lst).end - *(lst).first;                                              \
+       i0_ < n_; i0_ += int64_t(gridDim.x) * kWave)                                        \
+    if (const int64_t i_ = i0_ + threadIdx.x; i_ < n_)                                      \
+      if (const int64_t w = int64_t((lst).order[f_ + i_]); true)
 
 template <typename T, int MAXV>
 __global__ __launch_bounds__(kWave) void k_mf_tet_apply(
@@ -136,40 +138,54 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_apply(
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   bool fail = false;
-  for_each_item(lst, [&](int64_t w) {
+  ITEM_LOOP(lst, w) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     TetCells tc;
     if (tet_cells(w, n_t, rng, tc)) {
       TetGeom G;
       load_tet(tetrec, tc.t, G);
       const T* x = tc.d == 0 ? x0 : (tc.d == 1 ? x1 : x2);
-      const int64_t NX = ld.n[3 * tc.d + 0], NY = ld.n[3 * tc.d + 1];
+      const int64_t NX = ld_at(ld.n, tc.d, 0), NY = ld_at(ld.n, tc.d, 1);
       for (int64_t q = 0; q < tc.count; ++q) {
         int ci[3];
         double lo[3], hi[3];
         range_cell(tc.r, q, lat, ld, tc.d, ci, lo, hi);
-        T b[4][8];
-        bool keep;
-        if (!piece_values<T, MAXV>(P, G, lo, hi, dual, b, keep)) {
-          fail = true;
-          continue;
-        }
-        if (!keep) continue;
         T xl[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) xl[j] = x[corner_node(ci, j, NX, NY)];
+        // Σ_j b_ij x_j = ∫ λ_i U with U = Σ_j x_j N_j: four sums per piece
+        T LA[4], LG[4][3], b4[4] = {T(0), T(0), T(0), T(0)};
+        double vol6 = 0.0;
+        const bool ok = clip_fan_local<T, MAXV>(
+            P, G, lo, hi, LA, LG, vol6, [&](const T (&y)[4][3], double det) {
+              subtet_quad<T>(y, T(det), [&](T px, T py, T pz, T w) {
+                const T wu = w * trilinear<T>(xl, px, py, pz);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          T s = T(0);
-#pragma unroll
-          for (int j = 0; j < 8; ++j) s += b[i][j] * xl[j];
-          acc[i] += double(s);
+                for (int i = 0; i < 4; ++i)
+                  b4[i] += wu * (LA[i] + LG[i][0] * px + LG[i][1] * py + LG[i][2] * pz);
+              });
+            });
+        if (!ok) {
+          fail = true;
+          continue;
         }
+        if (!piece_kept(vol6, lo, hi, G)) continue;
+        const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b4[i] *= sc;
+        if (dual) {
+          // ψ_i = 5 λ_i − Σ_k λ_k
+          const T sum = b4[0] + b4[1] + b4[2] + b4[3];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b4[i] = T(5) * b4[i] - sum;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += double(b4[i]);
       }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) pt[w * 4 + i] = T(acc[i]);
-  });
+  }
   const uint64_t fm = ballot64(fail);
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
@@ -211,9 +227,9 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_spread(
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   bool fail = false;
-  for_each_item(lst, [&](int64_t w) {
+  ITEM_LOOP(lst, w) {
     TetCells tc;
-    if (!tet_cells(w, n_t, rng, tc)) return;
+    if (!tet_cells(w, n_t, rng, tc)) continue;
     TetGeom G;
     load_tet(tetrec, tc.t, G);
     T zl[4];
@@ -221,36 +237,52 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_spread(
     const int32_t vv[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) zl[k] = ys[int64_t(tc.d) * n_v + vv[k]];
+    if (dual) dual_weights_mf<T>(zl);
     T* out = tc.d == 0 ? o0 : (tc.d == 1 ? o1 : o2);
-    const int64_t NX = ld.n[3 * tc.d + 0], NY = ld.n[3 * tc.d + 1];
+    const int64_t NX = ld_at(ld.n, tc.d, 0), NY = ld_at(ld.n, tc.d, 1);
     for (int64_t q = 0; q < tc.count; ++q) {
       int ci[3];
       double lo[3], hi[3];
       range_cell(tc.r, q, lat, ld, tc.d, ci, lo, hi);
-      T b[4][8];
-      bool keep;
-      if (!piece_values<T, MAXV>(P, G, lo, hi, dual, b, keep)) {
+      // Σ_i y_i b_ij = ∫ w N_j with w = Σ_i y_i λ_i (dual: the weights of
+      // ψ): eight sums per piece
+      T LA[4], LG[4][3], b8[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b8[j] = T(0);
+      double vol6 = 0.0;
+      const bool ok = clip_fan_local<T, MAXV>(
+          P, G, lo, hi, LA, LG, vol6, [&](const T (&y)[4][3], double det) {
+            subtet_quad<T>(y, T(det), [&](T px, T py, T pz, T w) {
+              T wv = T(0);
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                wv += zl[i] * (LA[i] + LG[i][0] * px + LG[i][1] * py + LG[i][2] * pz);
+              wv *= w;
+              const T hx0 = T(1) - px, hy0 = T(1) - py, hz0 = T(1) - pz;
+              const T n00 = hx0 * hy0, n10 = px * hy0, n01 = hx0 * py, n11 = px * py;
+              b8[0] += wv * n00 * hz0;
+              b8[1] += wv * n10 * hz0;
+              b8[2] += wv * n01 * hz0;
+              b8[3] += wv * n11 * hz0;
+              b8[4] += wv * n00 * pz;
+              b8[5] += wv * n10 * pz;
+              b8[6] += wv * n01 * pz;
+              b8[7] += wv * n11 * pz;
+            });
+          });
+      if (!ok) {
         fail = true;
         continue;
       }
-      if (!keep) continue;
+      if (!piece_kept(vol6, lo, hi, G)) continue;
+      const T sc = T(-(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) / 6.0);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const T s = b[0][j] * zl[0] + b[1][j] * zl[1] + b[2][j] * zl[2] + b[3][j] * zl[3];
-        unsafeAtomicAdd(out + corner_node(ci, j, NX, NY), T(alpha * double(s)));
-      }
+      for (int j = 0; j < 8; ++j)
+        unsafeAtomicAdd(out + corner_node(ci, j, NX, NY), T(alpha * double(sc * b8[j])));
     }
-  });
+  }
   const uint64_t fm = ballot64(fail);
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
-}
-
-// Dual multipliers: w = Σ_i z_i ψ_i = Σ_i (5 z_i − Σ_k z_k) λ_i.
-template <typename T>
-__device__ __forceinline__ void dual_weights_mf(T zl[4]) {
-  const T s = zl[0] + zl[1] + zl[2] + zl[3];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) zl[k] = T(5) * zl[k] - s;
 }
 
 template <typename T, int MAXV>
@@ -264,7 +296,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_shape(
   const int lane = threadIdx.x;
   const PolyView P{sx + lane, sy + lane, sz + lane, snb + lane, kWave, (1u << MAXV) - 1u};
   bool fail = false;
-  for_each_item(lst, [&](int64_t w) {
+  ITEM_LOOP(lst, w) {
     double acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = 0.0;
@@ -279,7 +311,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_shape(
       for (int k = 0; k < 4; ++k) zl[k] = z[int64_t(tc.d) * n_v + vv[k]];
       if (dual) dual_weights_mf<T>(zl);
       const T* u = tc.d == 0 ? u0 : (tc.d == 1 ? u1 : u2);
-      const int64_t NX = ld.n[3 * tc.d + 0], NY = ld.n[3 * tc.d + 1];
+      const int64_t NX = ld_at(ld.n, tc.d, 0), NY = ld_at(ld.n, tc.d, 1);
       for (int64_t q = 0; q < tc.count; ++q) {
         int ci[3];
         double lo[3], hi[3];
@@ -311,7 +343,7 @@ __global__ __launch_bounds__(kWave) void k_mf_tet_shape(
       }
     }
     store_row<12>(pgt + w * 12, acc);
-  });
+  }
   const uint64_t fm = ballot64(fail);
   if (lane == 0 && fm) atomicOr(flags, kFlagCapacity);
 }
@@ -430,6 +462,7 @@ int shape_typed_mf(ibvt_coupling* c, const void* z, const void* const u[3], cons
 }  // namespace
 
 #undef IBVT_MF_CLASSES
+#undef ITEM_LOOP
 
 // The (component, tet) order of the products (slot class, then cell
 // count); kept with the coupling until it is freed or reassembled.
