@@ -231,7 +231,11 @@ int ibvt_set_allocator(const ibvt_alloc* a);
  *   Pairs are clipped and integrated in up to 8 chunks of 3 * 2^19
  *   (component, tet) items (the environment variable IBVT_CHUNK_ITEMS, a
  *   positive integer read at every assembly, sets another size); the
- *   matrices do not depend on the chunking.
+ *   matrices do not depend on the chunking.  B^dT is built through buckets
+ *   of consecutive fluid nodes when B^d has at least 2^22 nonzeros, else by
+ *   a counting sort over the lattice (IBVT_BUCKET_NNZ, a positive integer
+ *   read at every assembly, sets another threshold); both give the same
+ *   B^dT.
  *   Errors: IBVT_E_INVALID, IBVT_E_OUT_OF_GRID, IBVT_E_CAPACITY,
  *   IBVT_E_UNSUPPORTED, IBVT_E_NOMEM, IBVT_E_HIP.
  */

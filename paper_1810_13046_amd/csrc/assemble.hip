@@ -1519,16 +1519,12 @@ int assemble_grid(ibvt_coupling* c, hipStream_t s) {
   for (int k = 0; k < 9; ++k)
     if (c->ld.n[k] > (1 << kCellBits))
       return set_error(IBVT_E_UNSUPPORTED, "more than 2^21 lattice cells along one axis");
-  int64_t nf_max = std::max(c->n_fluid[0], std::max(c->n_fluid[1], c->n_fluid[2]));
-  if (c->matrix_free) nf_max = 0;  // no transpose
   if ((st = ensure(c, c->tetvol, size_t(n_t + 1) * sizeof(double)))) return st;
   if ((st = ensure(c, c->tetrec, size_t(n_t + 1) * kTetRec * sizeof(double)))) return st;
   if ((st = ensure(c, c->tetgrad, size_t(n_t + 1) * 12 * sizeof(double)))) return st;
   if ((st = ensure(c, c->rng, size_t(3 * n_t + 1) * sizeof(CellRange)))) return st;
   if ((st = ensure(c, c->cnt, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->pair_off, size_t(3 * n_t + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, c->mark, size_t(nf_max + 1) * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, c->cidx, size_t(nf_max + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->mlump, size_t(n_v + 1) * sizeof(double)))) return st;
   for (int d = 0; d < 3; ++d)
     if ((st = ensure(c, c->B[d].rowptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;

@@ -682,15 +682,12 @@ int shape2_typed(ibvt_coupling* c, const T* z, const T* u0, const T* u1, const T
 int assemble_all_2d(ibvt_coupling* c, hipStream_t s) {
   const int64_t n_t = c->n_tet, n_v = c->n_vert;
   int st;
-  int64_t nf_max = std::max(c->n_fluid[0], c->n_fluid[1]);
   if ((st = ensure(c, c->tetvol, size_t(n_t + 1) * sizeof(double)))) return st;
   if ((st = ensure(c, c->tetrec, size_t(n_t + 1) * kTriRec * sizeof(double)))) return st;
   if ((st = ensure(c, c->tetgrad, size_t(n_t + 1) * 6 * sizeof(double)))) return st;
   if ((st = ensure(c, c->rng, size_t(2 * n_t + 1) * sizeof(CellRange)))) return st;
   if ((st = ensure(c, c->cnt, size_t(2 * n_t + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->pair_off, size_t(2 * n_t + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, c->mark, size_t(nf_max + 1) * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, c->cidx, size_t(nf_max + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->mlump, size_t(n_v + 1) * sizeof(double)))) return st;
   for (int d = 0; d < 2; ++d)
     if ((st = ensure(c, c->B[d].rowptr, size_t(n_v + 1) * sizeof(int64_t)))) return st;

@@ -185,9 +185,9 @@ struct ibvt_coupling {
   ibvt::DevBuf rowspill;     // double partial node sums + uint8 touched flags of rows that
                              // take pairs of several chunks
   ibvt::Csr B[3], Bt[3];
-  ibvt::DevBuf mark;         // int32 max n_fluid (+1)
-  ibvt::DevBuf cidx;         // int64 max n_fluid + 1
-  ibvt::DevBuf tbuf;         // transpose sort scratch
+  ibvt::DevBuf mark;         // int32 n_fluid + 1 (transposes of small operators)
+  ibvt::DevBuf cidx;         // int64 n_fluid + 1 (transposes of small operators)
+  ibvt::DevBuf tbuf;         // transpose scratch (bucket records and tables)
   ibvt::DevBuf mlump;        // double n_vert
   ibvt::DevBuf minv;         // T n_vert
   bool has_M = false;
@@ -267,7 +267,8 @@ template <typename T>
 int transpose_one(ibvt_coupling* c, int d, hipStream_t s);
 
 // sort.hip: stable sorts by small integer keys (n < 2^31).
-// A nonzero carried through the transpose's sort: its value and its row.
+// A nonzero carried through the small operators' transpose: its value and
+// its row.
 struct SortVal32 {
   float v;
   int32_t r;
@@ -287,15 +288,6 @@ const int64_t* sort_digit_starts(const void* scratch, int64_t n, int bits, int v
 // order = the indices 0..n-1 stably sorted by their 8-bit keys
 int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t* order,
                       void* scratch, hipStream_t s);
-// stable sort of (value, row) items vals by keys < 2^end_bit in digit
-// passes of at most 8 bits (alternating with keys_tmp, vals_tmp; both pairs
-// of arrays are overwritten), the last pass writing CSR by key: col[k] =
-// row, val[k] = value, rowptr[0..n_rows] (every key 0..n_rows-1 must
-// occur).  scratch: sort_pass_bytes(n, 8) bytes.
-template <typename V>
-int sort_to_csr(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals, int32_t* keys_tmp,
-                V* vals_tmp, void* scratch, hipStream_t s, int32_t* col, decltype(V::v)* val,
-                int64_t* rowptr, int64_t n_rows);
 
 // apply.hip
 int apply_B(ibvt_coupling* c, const void* const x[3], void* y, bool lumped_scale, hipStream_t s);

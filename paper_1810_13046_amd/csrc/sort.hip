@@ -1,6 +1,5 @@
-// Stable sorts by small integer keys, written for wave64: the pair order of
-// the clip (8-bit keys) and the radix passes of the transpose (int32 keys,
-// passes of at most 8 bits).
+// Stable sorts by small integer keys, written for wave64: the orders of the
+// pairs and of the (component, tet) items by 8-bit keys.
 //
 // One pass orders the items by one digit of the key, keeping the input
 // order among equal digits (LSD radix pass):
@@ -27,7 +26,6 @@ namespace ibvt {
 namespace {
 
 constexpr int kSortWaves = 4;  // waves (tiles) per block of the count kernel
-constexpr int kMaxPassBits = 8;  // widest digit of sort_to_csr (wider measured slower)
 
 // Rounds of 64 items per tile: every item of a tile is held in registers
 // while it is ranked (values of 16 bytes take half the rounds).
@@ -86,16 +84,6 @@ using RawWord = std::conditional_t<
     sizeof(V) == 16, RawWord4,
     std::conditional_t<sizeof(V) == 8, RawWord2, std::conditional_t<sizeof(V) == 4, uint32_t, V>>>;
 
-// values from an array (entry 0 stands in past the end; n >= 1)
-template <typename V>
-struct ArrayVals {
-  const V* v;
-  template <typename W>
-  __device__ __forceinline__ W load(int64_t i, bool act) const {
-    return reinterpret_cast<const W*>(v)[act ? i : 0];
-  }
-};
-
 // the item's own index as the value (an order of the items)
 struct IndexVals {
   template <typename W>
@@ -111,33 +99,9 @@ struct PlainOut {
   K* keys_out;
   V* vals_out;
   template <typename W>
-  __device__ __forceinline__ void put(int64_t pos, K key, const W& w, bool, K) const {
+  __device__ __forceinline__ void put(int64_t pos, K key, const W& w) const {
     if (keys_out) keys_out[pos] = key;
     reinterpret_cast<W*>(vals_out)[pos] = w;
-  }
-};
-
-// The last pass of a sort of (value, row) items by compacted column, written
-// as CSR by that column: col[pos] = row, val[pos] = value, and rowptr[key] =
-// the first place of the key.  Every key has items; the first item of a key
-// is either inside a tile's run of its top digit (its predecessor there has
-// another key: a plain store) or first in such a run (an atomic minimum over
-// the runs' first items, which the plain store of the true first also
-// beats); rowptr starts at all ones.
-template <typename V>
-struct CsrOut {
-  int32_t* col;
-  decltype(V::v)* val;
-  unsigned long long* rowptr;
-  template <typename W>
-  __device__ __forceinline__ void put(int64_t pos, int32_t key, const W& w, bool run_first,
-                                      int32_t prev) const {
-    V x;
-    __builtin_memcpy(&x, &w, sizeof(V));
-    col[pos] = x.r;
-    val[pos] = x.v;
-    if (run_first) atomicMin(&rowptr[key], (unsigned long long)pos);
-    else if (prev != key) rowptr[key] = (unsigned long long)pos;
   }
 };
 
@@ -223,9 +187,7 @@ __global__ __launch_bounds__(kWave) void k_digit_scatter(
   for (int j = lane; j < m; j += kWave) {
     const K key = sk[j];
     const uint32_t dg = digit_of(key, shift, kBins - 1);
-    const int64_t pos = gstart[dg] + (j - lstart[dg]);
-    const bool run_first = j == lstart[dg];
-    dst.put(pos, key, sv[j], run_first, run_first ? key : sk[j - 1]);
+    dst.put(gstart[dg] + (j - lstart[dg]), key, sv[j]);
   }
 }
 
@@ -280,66 +242,5 @@ int order_by_byte_key(ibvt_coupling* c, int64_t n, const uint8_t* keys, int32_t*
   return digit_pass<uint8_t, int32_t, 8>(c, n, keys, IndexVals{}, 0,
                                          PlainOut<uint8_t, int32_t>{nullptr, order}, scratch, s);
 }
-
-__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
-
-template <typename V, int B>
-int digit_passes_csr(ibvt_coupling* c, int64_t n, int passes, int32_t* keys, V* vals,
-                     int32_t* keys_tmp, V* vals_tmp, void* scratch, hipStream_t s, int32_t* col,
-                     decltype(V::v)* val, int64_t* rowptr, int64_t n_rows) {
-  int32_t* kin = keys;
-  V* vin = vals;
-  int32_t* kout = keys_tmp;
-  V* vout = vals_tmp;
-  int st;
-  for (int p = 0; p + 1 < passes; ++p) {
-    if ((st = digit_pass<int32_t, V, B>(c, n, kin, ArrayVals<V>{vin}, p * B,
-                                        PlainOut<int32_t, V>{kout, vout}, scratch, s)))
-      return st;
-    std::swap(kin, kout);
-    std::swap(vin, vout);
-  }
-  if ((st = hip_check(hipMemsetAsync(rowptr, 0xff, size_t(n_rows) * sizeof(int64_t), s), "memset")))
-    return st;
-  k_set_i64<<<1, 1, 0, s>>>(rowptr + n_rows, n);
-  if ((st = hip_check(hipGetLastError(), "rowptr launch"))) return st;
-  return digit_pass<int32_t, V, B>(
-      c, n, kin, ArrayVals<V>{vin}, (passes - 1) * B,
-      CsrOut<V>{col, val, reinterpret_cast<unsigned long long*>(rowptr)}, scratch, s);
-}
-
-template <typename V>
-int sort_to_csr(ibvt_coupling* c, int64_t n, int end_bit, int32_t* keys, V* vals, int32_t* keys_tmp,
-                V* vals_tmp, void* scratch, hipStream_t s, int32_t* col, decltype(V::v)* val,
-                int64_t* rowptr, int64_t n_rows) {
-  if (n <= 0) return IBVT_OK;
-  // passes of at most kMaxPassBits bits, all of one width
-  const int passes = std::max(1, (end_bit + kMaxPassBits - 1) / kMaxPassBits);
-  const int bits = (end_bit + passes - 1) / passes;
-  switch (bits) {
-#define IBVT_PASSES(B) \
-  case B:              \
-    return digit_passes_csr<V, B>(c, n, passes, keys, vals, keys_tmp, vals_tmp, scratch, s, col, \
-                                  val, rowptr, n_rows);
-    IBVT_PASSES(1)
-    IBVT_PASSES(2)
-    IBVT_PASSES(3)
-    IBVT_PASSES(4)
-    IBVT_PASSES(5)
-    IBVT_PASSES(6)
-    IBVT_PASSES(7)
-    IBVT_PASSES(8)
-#undef IBVT_PASSES
-    default:
-      return set_error(IBVT_E_CAPACITY, "sort digit width");
-  }
-}
-
-template int sort_to_csr<SortVal32>(ibvt_coupling*, int64_t, int, int32_t*, SortVal32*, int32_t*,
-                                    SortVal32*, void*, hipStream_t, int32_t*, float*, int64_t*,
-                                    int64_t);
-template int sort_to_csr<SortVal64>(ibvt_coupling*, int64_t, int, int32_t*, SortVal64*, int32_t*,
-                                    SortVal64*, void*, hipStream_t, int32_t*, double*, int64_t*,
-                                    int64_t);
 
 }  // namespace ibvt

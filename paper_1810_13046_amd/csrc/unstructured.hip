@@ -1100,8 +1100,6 @@ int assemble_all_unstructured(ibvt_coupling* c, hipStream_t s) {
   if ((st = ensure(c, c->rowbox, size_t(n_s + 1) * 8 * sizeof(double)))) return st;
   if ((st = ensure(c, c->cnt, size_t(n_s + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->pair_off, size_t(n_s + 1) * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, c->mark, size_t(c->n_fvert + 1) * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, c->cidx, size_t(c->n_fvert + 1) * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->mlump, size_t(n_v + 1) * sizeof(double)))) return st;
   if (c->precision == IBVT_FP32_MIXED) {
     if ((st = ensure(c, c->minv, size_t(n_v + 1) * sizeof(float)))) return st;
