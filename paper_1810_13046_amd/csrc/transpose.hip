@@ -6,13 +6,13 @@
 //   k_bucket_count    blocks of kBucketRows rows of B^d take their nonzeros
 //                     in rounds of kRound; within a wave the nonzeros of one
 //                     bucket come in runs (a row's columns ascend), and each
-//                     run's head adds its count and node mask into an LDS
-//                     hash table, so one global atomic per (round, bucket)
-//                     sums them.
+//                     run's head adds its count into an LDS hash table, so
+//                     one global atomic per (round, bucket) sums them; every
+//                     nonzero marks its node (a byte per lattice node).
 //   scans             bucket offsets in B^dT (from the counts), row offsets
-//                     (from the masks' popcounts) and the list of nonempty
-//                     buckets; one read-back gives the touched-node and
-//                     nonempty-bucket counts.
+//                     (from the marked nodes per bucket) and the list of
+//                     nonempty buckets; one read-back gives the touched-node
+//                     and nonempty-bucket counts.
 //   k_bucket_scatter  the same rounds reserve a range per (round, bucket);
 //                     run heads take their runs' places in it and every
 //                     nonzero writes its (value, vertex, node) record.
@@ -128,19 +128,28 @@ constexpr int kBucketBits = 5;
 constexpr int kBucketNodes = 1 << kBucketBits;  // consecutive lattice nodes per bucket
 constexpr int kBucketRows = 64;                 // rows of B^d per block (count, scatter)
 constexpr int kBucketThreads = 256;
-constexpr int kRound = 1024;                    // nonzeros per round (4 per thread)
-constexpr int kTableBits = 11;
+constexpr int kRound = 2048;                    // nonzeros per round (8 per thread)
+constexpr int kTableBits = 12;
 constexpr int kTable = 1 << kTableBits;         // hash slots per round (>= 2 x kRound)
 constexpr int kSortCap = 4096;                  // records a bucket sorts in LDS
-static_assert(kRound == 1024 && 2 * kRound <= kTable, "round and table sizes");
+static_assert(kRound % kBucketThreads == 0 && 2 * kRound <= kTable, "round and table sizes");
 
-// A nonzero of B^d on its way into B^dT: value, vertex (its row of B^d) and
-// node within the bucket.
+// A nonzero of B^d on its way into B^dT: value, and vertex (its row of B^d)
+// with the node within the bucket in one word (vertices below 2^27).
 template <typename T>
 struct BucketRec {
   T v;
-  int32_t r;
-  int32_t nl;
+  uint32_t rn;  // vertex << kBucketBits | node
+  __device__ __forceinline__ int32_t r() const { return int32_t(rn >> kBucketBits); }
+  __device__ __forceinline__ int nl() const { return int(rn & (kBucketNodes - 1)); }
+};
+constexpr int64_t kBucketMaxVert = int64_t(1) << (32 - kBucketBits);
+
+// A nonempty bucket as the sort takes it: its first record (= its first
+// place in B^dT), its first row of B^dT, the bucket and its record count.
+struct BucketSpan {
+  int64_t a, t;
+  int32_t b, n;
 };
 
 // Slot of bucket b in a round's table (open addressing; a round has at most
@@ -184,14 +193,13 @@ __device__ __forceinline__ WaveRun wave_run(int32_t bucket, bool valid) {
   return w;
 }
 
-// Per bucket: nonzero count and mask of the nodes that occur.  Only run
-// heads touch the round's table.
+// Per bucket: nonzero count (only run heads touch the round's table), and
+// a byte per node that occurs (plain stores: every writer stores 1).
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(
     int64_t n_rows, int64_t per, const int64_t* __restrict__ rowptr,
-    const int32_t* __restrict__ col, int32_t* __restrict__ bcount, uint32_t* __restrict__ bmask) {
+    const int32_t* __restrict__ col, int32_t* __restrict__ bcount, uint8_t* __restrict__ mark) {
   __shared__ int32_t key[kTable];
   __shared__ int32_t cnt[kTable];
-  __shared__ uint32_t msk[kTable];
   const int64_t r0 = xcd_row_block(per) * kBucketRows;
   if (r0 >= n_rows) return;
   const int64_t r1 = min<int64_t>(n_rows, r0 + kBucketRows);
@@ -201,7 +209,6 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(
     for (int h = threadIdx.x; h < kTable; h += kBucketThreads) {
       key[h] = -1;
       cnt[h] = 0;
-      msk[h] = 0;
     }
     __syncthreads();
     constexpr int J = kRound / kBucketThreads;
@@ -216,45 +223,44 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(
       const bool valid = kb + j * kBucketThreads + threadIdx.x < k1;
       const int32_t node = nodes[j];
       const WaveRun w = wave_run(node >> kBucketBits, valid);
-      // the run's node mask, gathered at its head
-      uint32_t bits = valid ? 1u << (node & (kBucketNodes - 1)) : 0u;
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_down(bits, o, kWave);
-        if (l + o < w.end) bits |= y;
-      }
-      if (w.is_head) {
-        const int h = table_slot(key, node >> kBucketBits);
-        atomicAdd(&cnt[h], w.end - l);
-        atomicOr(&msk[h], bits);
-      }
+      if (valid) mark[node] = 1;
+      if (w.is_head) atomicAdd(&cnt[table_slot(key, node >> kBucketBits)], w.end - l);
     }
     __syncthreads();
     for (int h = threadIdx.x; h < kTable; h += kBucketThreads) {
       const int32_t b = key[h];
-      if (b >= 0) {
-        atomicOr(&bmask[b], msk[h]);
-        atomicAdd(&bcount[b], cnt[h]);
-      }
+      if (b >= 0) atomicAdd(&bcount[b], cnt[h]);
     }
     __syncthreads();
   }
 }
 
-// Touched nodes per bucket (the popcount of its mask) and its nonempty flag.
-__global__ void k_bucket_rows(int64_t nb, const uint32_t* __restrict__ bmask,
+// Touched nodes per bucket (its marked nodes) and its nonempty flag.
+__global__ void k_bucket_rows(int64_t nb, const uint32_t* __restrict__ mark,
                               int32_t* __restrict__ tb, int32_t* __restrict__ nonempty) {
   const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (b < nb) {
-    tb[b] = __popc(bmask[b]);
-    nonempty[b] = bmask[b] != 0u;
+    int m = 0;
+#pragma unroll
+    for (int w = 0; w < kBucketNodes / 4; ++w) m += __popc(mark[b * (kBucketNodes / 4) + w]);
+    tb[b] = m;
+    nonempty[b] = m != 0;
   }
 }
 
 // The nonempty buckets in ascending order.
 __global__ void k_bucket_list(int64_t nb, const int32_t* __restrict__ nonempty,
-                              const int64_t* __restrict__ pos, int32_t* __restrict__ list) {
+                              const int64_t* __restrict__ pos, const int64_t* __restrict__ boff,
+                              const int64_t* __restrict__ toff, BucketSpan* __restrict__ list) {
   const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (b < nb && nonempty[b]) list[pos[b]] = int32_t(b);
+  if (b < nb && nonempty[b]) {
+    BucketSpan e;
+    e.a = boff[b];
+    e.t = toff[b];
+    e.b = int32_t(b);
+    e.n = int32_t(boff[b + 1] - boff[b]);
+    list[pos[b]] = e;
+  }
 }
 
 // The same rounds as k_bucket_count: each (round, bucket) reserves a range
@@ -266,8 +272,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(
     const int32_t* __restrict__ col, const T* __restrict__ val, const int64_t* __restrict__ boff,
     int32_t* __restrict__ bfill, BucketRec<T>* __restrict__ rec) {
   __shared__ int32_t key[kTable];
-  __shared__ int32_t cnt[kTable];
-  __shared__ int64_t base[kTable];
+  __shared__ int32_t cnt[kTable];  // then the slot's first position in the records
   __shared__ int64_t srp[kBucketRows + 1];
   const int64_t r0 = xcd_row_block(per) * kBucketRows;
   if (r0 >= n_rows) return;
@@ -307,7 +312,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(
     __syncthreads();
     for (int h = threadIdx.x; h < kTable; h += kBucketThreads) {
       const int32_t b = key[h];
-      if (b >= 0) base[h] = boff[b] + atomicAdd(&bfill[b], cnt[h]);
+      if (b >= 0) cnt[h] = int32_t(boff[b]) + atomicAdd(&bfill[b], cnt[h]);
     }
     __syncthreads();
 #pragma unroll
@@ -323,32 +328,30 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(
       }
       BucketRec<T> x;
       x.v = v[j];
-      x.r = int32_t(r0 + lo);
-      x.nl = node[j] & (kBucketNodes - 1);
-      rec[base[slot[j]] + rank[j]] = x;
+      x.rn = (uint32_t(r0 + lo) << kBucketBits) | uint32_t(node[j] & (kBucketNodes - 1));
+      rec[cnt[slot[j]] + rank[j]] = x;
     }
     __syncthreads();
   }
 }
 
-// One block per nonempty bucket (each bucket owns its ranges of B^dT): row pointers and row map of its nodes, then its
-// records in (node, vertex) order.  A bucket that fits the LDS is read once
-// into registers; counting a record's node also gives it a slot among that
-// node's records.
+// One block per nonempty bucket (each bucket owns its ranges of B^dT): row
+// pointers and row map of its nodes, then its records in (node, vertex)
+// order.  A bucket that fits the LDS is read once into registers; counting
+// a record's node also gives it a slot among that node's records, the LDS
+// holds the vertices grouped by node, and each record is ranked from its
+// registers.
 template <typename T>
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_sort(
-    const int32_t* __restrict__ list, const int64_t* __restrict__ boff,
-    const int64_t* __restrict__ toff, BucketRec<T>* __restrict__ rec,
+    const BucketSpan* __restrict__ list, BucketRec<T>* __restrict__ rec,
     int32_t* __restrict__ tcol, T* __restrict__ tval, int64_t* __restrict__ trowptr,
     int32_t* __restrict__ rowmap, int64_t touched, int64_t nnz) {
   constexpr int R = kSortCap / kBucketThreads;
   __shared__ int32_t ncnt[kBucketNodes], noff[kBucketNodes], nfill[kBucketNodes];
   __shared__ int32_t sr[kSortCap];
-  __shared__ T sv[kSortCap];
-  __shared__ uint8_t snl[kSortCap];
-  const int32_t b = list[blockIdx.x];
-  const int64_t a = boff[b];
-  const int n = int(boff[b + 1] - a);
+  const BucketSpan e = list[blockIdx.x];
+  const int64_t a = e.a;
+  const int n = e.n;
   const int t = threadIdx.x;
   const bool fits = n <= kSortCap;
   if (t < kBucketNodes) {
@@ -360,18 +363,16 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_sort(
   int slot[R];
   if (fits) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int j = t + i * kBucketThreads;
-      if (j < n) x[i] = rec[a + j];
-    }
+    for (int i = 0; i < R; ++i)
+      if (t + i * kBucketThreads < n) x[i] = rec[a + t + i * kBucketThreads];
   }
   __syncthreads();
   if (fits) {
 #pragma unroll
     for (int i = 0; i < R; ++i)
-      if (t + i * kBucketThreads < n) slot[i] = atomicAdd(&ncnt[x[i].nl], 1);
+      if (t + i * kBucketThreads < n) slot[i] = atomicAdd(&ncnt[x[i].nl()], 1);
   } else {
-    for (int j = t; j < n; j += kBucketThreads) atomicAdd(&ncnt[rec[a + j].nl], 1);
+    for (int j = t; j < n; j += kBucketThreads) atomicAdd(&ncnt[rec[a + j].nl()], 1);
   }
   __syncthreads();
   if (t < kWave) {  // the first wave: node offsets, and the touched nodes' rows
@@ -384,38 +385,35 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_sort(
     const uint64_t m = ballot64(cn > 0);
     if (t < kBucketNodes) noff[t] = y - cn;
     if (cn > 0) {
-      const int64_t row = toff[b] + rank_below(m);
+      const int64_t row = e.t + rank_below(m);
       trowptr[row] = a + (y - cn);
-      rowmap[row] = (b << kBucketBits) | t;
+      rowmap[row] = (e.b << kBucketBits) | t;
     }
   }
   __syncthreads();
   if (fits) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      if (t + i * kBucketThreads >= n) continue;
-      const int q = noff[x[i].nl] + slot[i];
-      sr[q] = x[i].r;
-      sv[q] = x[i].v;
-      snl[q] = uint8_t(x[i].nl);
-    }
+    for (int i = 0; i < R; ++i)
+      if (t + i * kBucketThreads < n) sr[noff[x[i].nl()] + slot[i]] = x[i].r();
     __syncthreads();
     // a record's place in its row: the row's vertices below its own
-    for (int q = t; q < n; q += kBucketThreads) {
-      const int nl = snl[q];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (t + i * kBucketThreads >= n) continue;
+      const int nl = x[i].nl();
       const int s0 = noff[nl], s1 = s0 + ncnt[nl];
-      const int32_t r = sr[q];
+      const int32_t r = x[i].r();
       int rank = 0, u = s0;
       for (; u + 8 <= s1; u += 8) {  // eight reads in flight
         int32_t y[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) y[e] = sr[u + e];
+        for (int k = 0; k < 8; ++k) y[k] = sr[u + k];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) rank += y[e] < r ? 1 : 0;
+        for (int k = 0; k < 8; ++k) rank += y[k] < r ? 1 : 0;
       }
       for (; u < s1; ++u) rank += sr[u] < r ? 1 : 0;
       tcol[a + s0 + rank] = r;
-      tval[a + s0 + rank] = sv[q];
+      tval[a + s0 + rank] = x[i].v;
     }
   } else {
     // more records than the LDS holds: group them by node in B^dT's arrays,
@@ -424,16 +422,15 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_sort(
     // vertices at a time through LDS
     for (int j = t; j < n; j += kBucketThreads) {
       const BucketRec<T> g = rec[a + j];
-      const int64_t q = a + noff[g.nl] + atomicAdd(&nfill[g.nl], 1);
-      tcol[q] = g.r;
+      const int64_t q = a + noff[g.nl()] + atomicAdd(&nfill[g.nl()], 1);
+      tcol[q] = g.r();
       tval[q] = g.v;
     }
     __syncthreads();
     for (int j = t; j < n; j += kBucketThreads) {
       BucketRec<T> g;
       g.v = tval[a + j];
-      g.r = tcol[a + j];
-      g.nl = 0;
+      g.rn = uint32_t(tcol[a + j]) << kBucketBits;
       rec[a + j] = g;
     }
     for (int nl = 0; nl < kBucketNodes; ++nl) {
@@ -443,19 +440,19 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_sort(
         const int q = q0 + t;
         BucketRec<T> g;
         g.v = T(0);
-        g.r = 0;
+        g.rn = 0;
         int rank = 0;
         for (int c0 = 0; c0 < L; c0 += kSortCap) {
           const int m = min(kSortCap, L - c0);
           __syncthreads();  // the grouped records are written; sr is free
           if (c0 == 0 && q < L) g = rec[s0 + q];
-          for (int u = t; u < m; u += kBucketThreads) sr[u] = rec[s0 + c0 + u].r;
+          for (int u = t; u < m; u += kBucketThreads) sr[u] = rec[s0 + c0 + u].r();
           __syncthreads();
           if (q < L)
-            for (int u = 0; u < m; ++u) rank += sr[u] < g.r ? 1 : 0;
+            for (int u = 0; u < m; ++u) rank += sr[u] < g.r() ? 1 : 0;
         }
         if (q < L) {
-          tcol[s0 + rank] = g.r;
+          tcol[s0 + rank] = g.r();
           tval[s0 + rank] = g.v;
         }
       }
@@ -542,35 +539,38 @@ int transpose_buckets(ibvt_coupling* c, int d, hipStream_t s) {
   const size_t rec_b = al(size_t(B.nnz) * sizeof(BucketRec<T>));
   const size_t i32_b = al(size_t(nb) * sizeof(int32_t));
   const size_t i64_b = al(size_t(nb + 1) * sizeof(int64_t));
-  const size_t zero_b = 3 * i32_b;  // counts, fill levels, node masks
-  if ((st = ensure(c, c->tbuf, rec_b + zero_b + 3 * i32_b + 3 * i64_b))) return st;
+  const size_t mark_b = al(size_t(nb) * kBucketNodes);  // a byte per lattice node
+  const size_t zero_b = 2 * i32_b + mark_b;             // counts, fill levels, marks
+  const size_t list_b = al(size_t(nb) * sizeof(BucketSpan));
+  if ((st = ensure(c, c->tbuf, rec_b + zero_b + 2 * i32_b + 3 * i64_b + list_b))) return st;
   char* p = c->tbuf.as<char>();
   BucketRec<T>* rec = reinterpret_cast<BucketRec<T>*>(p);
   p += rec_b;
   int32_t* bcount = reinterpret_cast<int32_t*>(p);
   int32_t* bfill = reinterpret_cast<int32_t*>(p + i32_b);
-  uint32_t* bmask = reinterpret_cast<uint32_t*>(p + 2 * i32_b);
+  uint8_t* mark = reinterpret_cast<uint8_t*>(p + 2 * i32_b);
   if ((st = hip_check(hipMemsetAsync(p, 0, zero_b, s), "memset"))) return st;
   p += zero_b;
   int32_t* tb = reinterpret_cast<int32_t*>(p);
   int32_t* nonempty = reinterpret_cast<int32_t*>(p + i32_b);
-  int32_t* list = reinterpret_cast<int32_t*>(p + 2 * i32_b);
-  p += 3 * i32_b;
+  p += 2 * i32_b;
   int64_t* boff = reinterpret_cast<int64_t*>(p);
   int64_t* toff = reinterpret_cast<int64_t*>(p + i64_b);
   int64_t* lpos = reinterpret_cast<int64_t*>(p + 2 * i64_b);
+  BucketSpan* list = reinterpret_cast<BucketSpan*>(p + 3 * i64_b);
 
   const int64_t n_rows = c->n_vert;
   const int64_t per = ceil_div(ceil_div(n_rows, kBucketRows), 8);
   const unsigned grid = unsigned(8 * per);
   k_bucket_count<<<grid, kBucketThreads, 0, s>>>(n_rows, per, B.rowptr.as<int64_t>(),
-                                                 B.col.as<int32_t>(), bcount, bmask);
-  k_bucket_rows<<<blocks_for(nb, 256), 256, 0, s>>>(nb, bmask, tb, nonempty);
+                                                 B.col.as<int32_t>(), bcount, mark);
+  k_bucket_rows<<<blocks_for(nb, 256), 256, 0, s>>>(nb, reinterpret_cast<const uint32_t*>(mark),
+                                                    tb, nonempty);
   if ((st = hip_check(hipGetLastError(), "transpose count launch"))) return st;
   if ((st = scan_i32_to_i64(c, bcount, boff, nb, s))) return st;
   if ((st = scan_i32_to_i64(c, tb, toff, nb, s))) return st;
   if ((st = scan_i32_to_i64(c, nonempty, lpos, nb, s))) return st;
-  k_bucket_list<<<blocks_for(nb, 256), 256, 0, s>>>(nb, nonempty, lpos, list);
+  k_bucket_list<<<blocks_for(nb, 256), 256, 0, s>>>(nb, nonempty, lpos, boff, toff, list);
   int64_t got[2] = {0, 0};
   {
     const int64_t* src[2] = {toff + nb, lpos + nb};
@@ -587,7 +587,7 @@ int transpose_buckets(ibvt_coupling* c, int d, hipStream_t s) {
                                                       B.col.as<int32_t>(), B.val.as<T>(), boff,
                                                       bfill, rec);
   k_bucket_sort<T><<<unsigned(n_nonempty), kBucketThreads, 0, s>>>(
-      list, boff, toff, rec, Bt.col.as<int32_t>(), Bt.val.as<T>(), Bt.rowptr.as<int64_t>(),
+      list, rec, Bt.col.as<int32_t>(), Bt.val.as<T>(), Bt.rowptr.as<int64_t>(),
       Bt.rowmap.as<int32_t>(), touched, B.nnz);
   return hip_check(hipGetLastError(), "transpose launch");
 }
@@ -596,8 +596,9 @@ int transpose_buckets(ibvt_coupling* c, int d, hipStream_t s) {
 
 template <typename T>
 int transpose_one(ibvt_coupling* c, int d, hipStream_t s) {
-  return c->B[d].nnz < bucket_nnz() ? transpose_counting<T>(c, d, s)
-                                     : transpose_buckets<T>(c, d, s);
+  return c->B[d].nnz >= bucket_nnz() && c->n_vert < kBucketMaxVert
+             ? transpose_buckets<T>(c, d, s)
+             : transpose_counting<T>(c, d, s);
 }
 
 template int transpose_one<float>(ibvt_coupling*, int, hipStream_t);
