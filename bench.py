@@ -59,10 +59,10 @@ CLIP_FLOPS = dict(dist=2, cut=11, subtet=47, pair=50)
 # the range beside it.
 FLOPS_PER_PLANE_CUT = (150, 225, 300)
 FLUSH_BYTES = 1 << 30   # cold-cache protocol: >= 1 GiB written between repetitions
-# flops per quadrature point of the 35 piece moments: point 6, powers 9,
-# partial products 14, 35 multiply-adds 70; 11 points (degree 4) per
+# flops per quadrature point of the 32 piece moments: point 6, powers 6,
+# partial products 12, 32 multiply-adds 64; 11 points (degree 4) per
 # sub-tetrahedron
-MOM_FLOPS_PER_POINT = 99
+MOM_FLOPS_PER_POINT = 88
 POINTS_PER_SUBTET = 11
 
 # HBM traffic of the clip step (all launches of one assembly) on
@@ -70,7 +70,7 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="4570a6f09894be6fafb9319fc0f7c12ae950d6546fa80ec78dee4b59eded8d8d",
+CLIP_TRAFFIC = dict(sources_sha256="08955eefd7833181d09dfcd20c24eeee219ade3495b4862f783b57cb272a034b",
                     bytes_mixed=25437294800)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]

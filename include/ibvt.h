@@ -219,8 +219,9 @@ int ibvt_set_allocator(const ibvt_alloc* a);
  *   in double, then quadrature exact for the degree-4 integrand), and global
  *   assembly.  Also builds B^dT (over the touched fluid nodes), the lumped
  *   mass and, with IBVT_BUILD_CONSISTENT_M, the consistent mass matrix.
- *   Unless IBVT_NO_PIECE_STORE is set, the 35 moments of every piece
- *   (monomials of degree <= 4 in cell-local coordinates) are kept, so that
+ *   Unless IBVT_NO_PIECE_STORE is set, the 32 moments of every piece
+ *   (monomials of degree <= 4 in cell-local coordinates, no exponent above
+ *   3) are kept, so that
  *   the reverse-mode calls neither clip nor integrate again.
  *   precision: IBVT_FP64 or IBVT_FP32_MIXED.
  *   out: receives a new handle owned by the library (free with

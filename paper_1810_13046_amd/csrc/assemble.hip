@@ -13,7 +13,7 @@
 //  k_clip<T,MAXV>  one lane per pair: clip the tet by the straddled cell
 //                  planes in double (vertex graph in LDS), fan the piece
 //                  into sub-tetrahedra and store them as records.
-//  k_integrate<T>  one lane per record: its 35 cell-local moments, summed
+//  k_integrate<T>  one lane per record: its 32 cell-local moments, summed
 //                  per pair; then one lane per pair turns them into the 32
 //                  values ∫ λ_i N_j.
 //  k_row_box / k_rows<T> / k_rows_compact<T>
@@ -482,7 +482,7 @@ __device__ __forceinline__ int owner_lane(int excl, int s) {
   return lo;
 }
 
-// (III) integrate every stored sub-tetrahedron: its 35 moments (cell-local,
+// (III) integrate every stored sub-tetrahedron: its 32 moments (cell-local,
 // centred) with the 11-point degree-4 rule, summed per pair in record order through
 // LDS (deterministic) into pmom[pair][m] (rows of kMomPad).  Then each lane
 // turns its pair's moments into the 4 x 8 values ∫ λ_i N_j, written to
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kWave) void k_integrate(
     const CellRange* __restrict__ rng, const double* __restrict__ tetrec,
     const double* __restrict__ lat, LatDesc ld, uint8_t* __restrict__ keep,
     T* __restrict__ pval, T* __restrict__ pmom, int dual) {
-  __shared__ __align__(16) T red[kWave][kMomPad];  // a record's moments per row, padded
+  __shared__ __align__(16) T red[kWave][kMomLds];  // a record's moments per row, padded
   const int lane = threadIdx.x;
   const int64_t g0 = p_begin + int64_t(blockIdx.x) * kWave;
   const int64_t pj = g0 + lane;
@@ -537,11 +537,12 @@ __global__ __launch_bounds__(kWave) void k_integrate(
       subtet_moments<T>(y, subtet_det<T>(y[0], y[1], y[2], y[3]), M);
     }
     {
-      T Mp[kMomPad];
+      T Mp[kMomLds];
 #pragma unroll
       for (int k = 0; k < kMom; ++k) Mp[k] = M[k];
-      Mp[kMom] = T(0);
-      store_row<kMomPad>(&red[lane][0], Mp);  // 16-byte LDS writes
+#pragma unroll
+      for (int k = kMom; k < kMomLds; ++k) Mp[k] = T(0);
+      store_row<kMomLds>(&red[lane][0], Mp);  // 16-byte LDS writes
     }
     // the record that ends each pair, and each record's pair, are uniform
     // across the wave: a ballot and lane reads (no LDS)

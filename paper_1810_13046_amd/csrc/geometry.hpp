@@ -15,9 +15,9 @@
 //
 // Integration: the piece is fanned into sub-tetrahedra from its lowest
 // vertex (faces through that vertex are skipped).  The assembly integrates
-// the 35 monomial moments of degree <= 4 of each sub-tetrahedron with a
-// symmetric 11-point degree-4 rule (subtet_moments), from which every
-// integrand λ_i N_j follows; the re-clipping paths (the reverse mode
+// the 32 monomial moments of degree <= 4 (no exponent above 3) of each
+// sub-tetrahedron with a symmetric 11-point degree-4 rule (subtet_moments),
+// from which every integrand λ_i N_j follows; the re-clipping paths (the reverse mode
 // without stored moments, the products without stored matrices) integrate
 // their degree-4 integrands, already contracted with the fields, directly
 // with a symmetric 14-point degree-5 rule (subtet_quad, subtet_grad).
@@ -391,15 +391,18 @@ __host__ __device__ inline void subtet_grad(const T y[4][3], T wscale, const T L
 // ---------------------------------------------------------------------------
 // Piece moments.  Every integrand of the transfer and of its shape
 // derivative is a polynomial of degree <= 4 on a piece (λ_i N_j, λ_a w ∂_k U,
-// w U with w, λ linear and N_j, U trilinear), so the 35 moments
-//   M_α = ∫_piece s^α,  s = ξ − (½, ½, ½),  |α| <= 4
+// w U with w, λ linear and N_j, U trilinear) in which no coordinate has an
+// exponent above 3 (a trilinear factor and its derivatives have exponents
+// <= 1, the linear or quadratic one <= 2), so the 32 moments
+//   M_α = ∫_piece s^α,  s = ξ − (½, ½, ½),  |α| <= 4, α_e <= 3
 // (cell-local coordinates centred in the cell, which keeps the
 // recombination well conditioned) determine all of them.  Moments are summed
 // per sub-tetrahedron with the 11-point degree-4 rule and per piece over its
 // fan.
 // ---------------------------------------------------------------------------
-constexpr int kMom = 35;
-constexpr int kMomPad = 36;  // per-pair stride of the moment store (16-byte rows)
+constexpr int kMom = 32;
+constexpr int kMomPad = 32;  // per-pair stride of the moment store (16-byte rows)
+constexpr int kMomLds = 36;  // row stride of LDS staging (rows apart in the banks)
 
 struct MomTable {
   int idx[5][5][5];
@@ -408,31 +411,34 @@ struct MomTable {
       for (int y = 0; y < 5; ++y)
         for (int z = 0; z < 5; ++z) idx[x][y][z] = -1;
     int n = 0;
-    for (int x = 0; x <= 4; ++x)
-      for (int y = 0; y <= 4 - x; ++y)
-        for (int z = 0; z <= 4 - x - y; ++z) idx[x][y][z] = n++;
+    for (int x = 0; x <= 3; ++x)
+      for (int y = 0; y <= 4 - x && y <= 3; ++y)
+        for (int z = 0; z <= 4 - x - y && z <= 3; ++z) idx[x][y][z] = n++;
   }
 };
 constexpr MomTable kMomTable{};
-// position of s_x^a s_y^b s_z^c (a + b + c <= 4) in the moment vector
+static_assert(kMomTable.idx[3][1][0] == kMom - 1 && kMomTable.idx[4][0][0] == -1 &&
+                  kMomTable.idx[0][0][3] == 3,
+              "moment table");
+// position of s_x^a s_y^b s_z^c (a + b + c <= 4, each <= 3) in the moment vector
 __host__ __device__ constexpr int mom_idx(int a, int b, int c) { return kMomTable.idx[a][b][c]; }
 
 // M += w · s^α for every α (the moment order is a, then b, then c ascending)
 template <typename T>
 __host__ __device__ __forceinline__ void mom_point(T sx, T sy, T sz, T w, T M[kMom]) {
   const T x2 = sx * sx, y2 = sy * sy, z2 = sz * sz;
-  const T px[5] = {T(1), sx, x2, x2 * sx, x2 * x2};
-  const T py[5] = {T(1), sy, y2, y2 * sy, y2 * y2};
-  const T pz[5] = {T(1), sz, z2, z2 * sz, z2 * z2};
+  const T px[4] = {T(1), sx, x2, x2 * sx};
+  const T py[4] = {T(1), sy, y2, y2 * sy};
+  const T pz[4] = {T(1), sz, z2, z2 * sz};
   int k = 0;
 #pragma unroll
-  for (int a = 0; a <= 4; ++a) {
+  for (int a = 0; a <= 3; ++a) {
     const T wa = w * px[a];
 #pragma unroll
-    for (int b = 0; b <= 4 - a; ++b) {
+    for (int b = 0; b <= 4 - a && b <= 3; ++b) {
       const T wab = wa * py[b];
 #pragma unroll
-      for (int c = 0; c <= 4 - a - b; ++c) M[k++] += wab * pz[c];
+      for (int c = 0; c <= 4 - a - b && c <= 3; ++c) M[k++] += wab * pz[c];
     }
   }
 }
