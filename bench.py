@@ -71,7 +71,7 @@ POINTS_PER_SUBTET = 11
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
 CLIP_TRAFFIC = dict(sources_sha256="08955eefd7833181d09dfcd20c24eeee219ade3495b4862f783b57cb272a034b",
-                    bytes_mixed=25437294800)
+                    bytes_mixed=25436929408)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]
 # HBM traffic of one lumped velocity apply and one force apply (all three
@@ -79,7 +79,7 @@ CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/
 # counter passes (profiles/hbm_traffic_three_bodies4.5M_mixed.txt);
 # reported while apply.hip is the source they were taken on.
 APPLY_TRAFFIC = dict(sources_sha256="2364d30cd6bae5f50fd603c4ed7fdc3e6a156ff37b34dcc7efd560032113be06",
-                     velocity_bytes=972427267, force_bytes=980969721)
+                     velocity_bytes=972426558, force_bytes=980883005)
 APPLY_SOURCES = ["paper_1810_13046_amd/csrc/apply.hip"]
 
 
