@@ -55,8 +55,8 @@ using ValRow = std::conditional_t<std::is_same<T, float>::value, SortVal32, Sort
 constexpr int kKeyLanes = 16;  // lanes per row of B^d in the counting sort's scatter
 
 // Counting sort for small operators, where the bucket path's fixed launches
-// dominate.  tcnt[c] = nonzeros
-// of B^d in compacted column c (integer atomics).
+// dominate.  tcnt[c] = nonzeros of B^d in compacted column c (integer
+// atomics).
 __global__ void k_tcount(int64_t nnz, const int32_t* __restrict__ col,
                          const int64_t* __restrict__ cidx, int32_t* __restrict__ tcnt) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
