@@ -70,7 +70,7 @@ POINTS_PER_SUBTET = 11
 # passes, scaled by the copy-kernel calibration (FETCH x 2, WRITE x 1): the
 # summary and its commands are in profiles/.  Reported only while the clip
 # sources are the ones the counters were taken on.
-CLIP_TRAFFIC = dict(sources_sha256="08955eefd7833181d09dfcd20c24eeee219ade3495b4862f783b57cb272a034b",
+CLIP_TRAFFIC = dict(sources_sha256="3800264d4994daa2c74c70a25de4942cd18f307be5a10b65554dee672c5342f0",
                     bytes_mixed=25436929408)
 CLIP_SOURCES = ["paper_1810_13046_amd/csrc/assemble.hip", "paper_1810_13046_amd/csrc/geometry.hpp",
                 "paper_1810_13046_amd/csrc/common.hpp"]

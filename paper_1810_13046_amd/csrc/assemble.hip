@@ -1210,6 +1210,7 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
   int32_t* ohist = c->pscan.as<int32_t>();
   int64_t* ofirst = reinterpret_cast<int64_t*>(c->pscan.as<char>() + hb);
   if ((st = side_stream(c))) return st;
+  bool masses_done = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int64_t want = std::max<int64_t>(int64_t(3.25 * double(chunk_max)) + 1024,
                                            c->pool_needed + c->pool_needed / 32 + 1024);
@@ -1265,6 +1266,13 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
         if ((st = hip_check(hipEventRecord(c->ev_fork, s), "event")) ||
             (st = hip_check(hipStreamWaitEvent(c->side, c->ev_fork, 0), "stream wait")))
           return st;
+        if (!masses_done) {
+          // the solid masses need only the tet volumes: on the second stream
+          // ahead of the first clip's classes 12 and 16, in the wave slots
+          // the LDS-bound clip leaves free (joined with the clip below)
+          if ((st = solid_masses(c, c->side))) return st;
+          masses_done = true;
+        }
         for (int k = 2; k >= 0; --k) {
           hipStream_t ks = k == 0 ? s : c->side;
           const int resident =
@@ -1373,8 +1381,8 @@ int assemble_typed(ibvt_coupling* c, hipStream_t s) {
     ProfScope ps("transpose", s);
     if ((st = transpose_one<T>(c, d, s))) return st;
   }
-  // masses
-  if ((st = solid_masses(c, s))) return st;
+  // masses, unless they ran beside the first clip (no pairs at all)
+  if (!masses_done && (st = solid_masses(c, s))) return st;
   // read-back 4: the counters of the assembly, flags
   int64_t cnt[kCntSlots];
   {
